@@ -1,0 +1,34 @@
+"""The whole solve of the parallel pseudocode table (Section 2.6), run serially.
+
+Order: validate and curve the surface, store the quadrature data (routines (2)-(4)),
+source terms (routine (1)), GMRES on A u = (S1, S2) (routine (5) inside), solvation
+energy (routine (6)).  Outputs phi and dphi/dn in kcal/(mol e) and kcal/(mol e A)
+(internal values times 4 pi C) and E_sol in kcal/mol.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import COULOMB_KCAL, FOUR_PI
+from .gmres import gmres
+from .operator import check_charges_inside, matvec, setup, solvation_energy, sources
+
+
+def solve(xyz, nrm, tri, qpos, q, eps1=1.0, eps2=80.0, kappa=0.1257,
+          rtol=1e-6, restart=200, max_iter=200, st=None, workers=1):
+    eps = eps2 / eps1
+    if st is None:
+        st = setup(xyz, nrm, tri)
+    qpos = np.asarray(qpos, dtype=np.float64).reshape(-1, 3)
+    q = np.asarray(q, dtype=np.float64).ravel()
+    check_charges_inside(st, qpos)
+    S1, S2 = sources(st.xyz, st.nrm, qpos, q, eps1)
+    b = np.concatenate([S1, S2])
+    u, its, rel, conv = gmres(lambda v: matvec(st, v, kappa, eps, workers=workers), b, rtol, restart,
+                             max_iter)
+    true_rel = float(np.linalg.norm(b - matvec(st, u, kappa, eps, workers=workers)) / np.linalg.norm(b))
+    E = solvation_energy(st, u, qpos, q, kappa, eps)
+    nv = st.nv
+    scale = FOUR_PI * COULOMB_KCAL
+    return dict(u=u, phi=scale * u[:nv], dphi=scale * u[nv:], energy=E, iterations=its,
+                est_residual=rel, true_residual=true_rel, converged=conv, setup=st, b=b)

@@ -1,0 +1,198 @@
+"""Pins of the oracle's curved-triangle construction (Section 2.2).
+
+The construction itself (tangent lengths, node normals, centroid node) is a reading of
+an underdetermined passage, so it is pinned through what any correct construction must
+satisfy: the P3 basis interpolates cubics exactly; the arcs interpolate their end data;
+curved icospheres reproduce the sphere's area and volume at high order; shared edges
+are watertight; the patch is tangent to the vertex normals; the double-layer identity
+holds to rounding once the quadrature is refined.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import FOUR_PI
+from oracle import geometry as G
+from oracle import operator as O
+from oracle import quadrature as Q
+from paper_1301_5914_amd import inputs
+
+
+def test_p3_basis_interpolates_cubics():
+    rng = np.random.default_rng(21)
+    coef = rng.standard_normal(10)
+
+    def f(r, s):
+        mons = [1, r, s, r * r, r * s, s * s, r ** 3, r * r * s, r * s * s, s ** 3]
+        return sum(c * m for c, m in zip(coef, mons))
+
+    def df(r, s):
+        dr = coef[1] + 2 * coef[3] * r + coef[4] * s + 3 * coef[6] * r * r + 2 * coef[7] * r * s + coef[8] * s * s
+        ds = coef[2] + coef[4] * r + 2 * coef[5] * s + coef[7] * r * r + 2 * coef[8] * r * s + 3 * coef[9] * s * s
+        return dr, ds
+
+    nodal = np.array([f(a[1] / 3, a[2] / 3) for a in G.ALPHA])
+    for _ in range(20):
+        r, s = rng.uniform(0, 1, 2)
+        if r + s > 1:
+            r, s = 1 - r, 1 - s
+        N, Nr, Ns = G.p3_basis(r, s)
+        assert abs(N.sum() - 1.0) < 1e-14 and abs(Nr.sum()) < 1e-13 and abs(Ns.sum()) < 1e-13
+        assert abs(N @ nodal - f(r, s)) < 1e-12
+        dr, ds = df(r, s)
+        assert abs(Nr @ nodal - dr) < 1e-11 and abs(Ns @ nodal - ds) < 1e-11
+    for k, a in enumerate(G.ALPHA):          # Kronecker property at the lattice
+        N, _, _ = G.p3_basis(a[1] / 3, a[2] / 3)
+        assert np.allclose(N, np.eye(10)[k], atol=1e-14)
+
+
+def test_arc_end_conditions_and_symmetry():
+    rng = np.random.default_rng(22)
+    for _ in range(10):
+        P, Q_ = rng.standard_normal(3), rng.standard_normal(3)
+        d = Q_ - P
+        nP = rng.standard_normal(3)
+        nP -= 0.8 * np.dot(nP, d) / np.dot(d, d) * d
+        nP /= np.linalg.norm(nP)
+        nQ = rng.standard_normal(3)
+        nQ -= 0.8 * np.dot(nQ, d) / np.dot(d, d) * d
+        nQ /= np.linalg.norm(nQ)
+        c0, c1, c2, c3 = G.arc_coefficients(P, nP, Q_, nQ)
+        assert np.allclose(c0 + c1 + c2 + c3, Q_, atol=1e-13)
+        assert abs(np.dot(c1, nP)) < 1e-13                         # tangent at P in P's plane
+        assert abs(np.dot(c1 + 2 * c2 + 3 * c3, nQ)) < 1e-12       # tangent at Q in Q's plane
+        for t in (0.25, 1 / 3, 0.5, 0.8):
+            x1, n1 = G.arc_point(P, nP, Q_, nQ, t)
+            x2, n2 = G.arc_point(Q_, nQ, P, nP, 1 - t)
+            assert np.allclose(x1, x2, atol=1e-13) and np.allclose(n1, n2, atol=1e-13)
+
+
+def test_arc_on_a_circle():
+    """On a circle the arc tangents have the 4 R tan(theta/4) length; the radial error is small."""
+    R, th = 2.0, 0.6
+    P = np.array([R, 0.0, 0.0])
+    Q_ = np.array([R * math.cos(th), R * math.sin(th), 0.0])
+    c0, c1, c2, c3 = G.arc_coefficients(P, P / R, Q_, Q_ / R)
+    assert abs(np.linalg.norm(c1) - 4 * R * math.tan(th / 4)) < 1e-13
+    for t in np.linspace(0, 1, 11):
+        x, n = G.arc_point(P, P / R, Q_, Q_ / R, t)
+        assert abs(np.linalg.norm(x) - R) < 2e-5 * R
+        assert np.allclose(n, x / np.linalg.norm(x), atol=1e-4)
+
+
+def test_normal_parallel_to_edge_is_rejected():
+    P, Q_ = np.zeros(3), np.array([1.0, 0.0, 0.0])
+    with pytest.raises(G.GeometryError):
+        G.arc_coefficients(P, np.array([1.0, 0, 0]), Q_, np.array([0, 0, 1.0]))
+
+
+@pytest.fixture(scope="module")
+def spheres():
+    out = {}
+    for lvl in (1, 2, 3):
+        xyz, nrm, tri = inputs.icosphere(lvl, 2.0)
+        out[lvl] = O.setup(xyz, nrm, tri)
+    return out
+
+
+def test_sphere_area_and_volume_converge_at_high_order(spheres):
+    R = 2.0
+    errs_a, errs_v = [], []
+    for lvl in (1, 2, 3):
+        st = spheres[lvl]
+        area = st.w.sum()
+        vol = np.sum(st.w * np.einsum("fmc,fmc->fm", st.y, st.ny)) / 3.0
+        errs_a.append(abs(area / (4 * math.pi * R * R) - 1))
+        errs_v.append(abs(vol / (4 * math.pi * R ** 3 / 3) - 1))
+    assert errs_a[2] < 1e-7 and errs_v[2] < 1e-8
+    for e in (errs_a, errs_v):          # at least 4th order in h (h halves per level)
+        assert e[1] / e[2] > 12 and e[0] / e[1] > 12
+    # radial error of the quadrature nodes
+    st = spheres[3]
+    assert np.max(np.abs(np.linalg.norm(st.y, axis=-1) - R)) < 2e-6 * R
+
+
+def test_watertight_and_tangent_to_vertex_normals(spheres):
+    st = spheres[2]
+    # edge nodes of the two triangles that share an edge coincide
+    edge_nodes = {(0, 1): (3, 4), (0, 2): (5, 6), (1, 2): (7, 8)}
+    seen = {}
+    for j, t in enumerate(st.tri):
+        for (a, b), (k1, k2) in edge_nodes.items():
+            va, vb = int(t[a]), int(t[b])
+            pts = (st.patch[j, k1], st.patch[j, k2])
+            key = (min(va, vb), max(va, vb))
+            if va > vb:
+                pts = pts[::-1]
+            if key in seen:
+                assert np.allclose(seen[key][0], pts[0], atol=1e-14 * 2) and \
+                    np.allclose(seen[key][1], pts[1], atol=1e-14 * 2)
+            else:
+                seen[key] = pts
+    # patch normal at each vertex is the vertex normal (G1 at vertices)
+    for j in range(0, st.nf, 7):
+        for k in range(3):
+            rot = G.rotate_nodes(st.patch[j], k)
+            _, _, n = G.eval_patch(rot, 0.0, 0.0)
+            assert abs(np.dot(n, st.nrm[st.tri[j, k]]) - 1.0) < 1e-13
+
+
+def test_rotation_relabels_the_same_surface(spheres):
+    st = spheres[1]
+    rng = np.random.default_rng(23)
+    for j in range(0, st.nf, 5):
+        for k in (1, 2):
+            rot = G.rotate_nodes(st.patch[j], k)
+            r, s = rng.uniform(0, 0.5, 2)
+            L = [1 - r - s, r, s]                 # barycentrics in the rotated frame
+            Ls = [0.0, 0.0, 0.0]
+            for b in range(3):
+                Ls[(k + b) % 3] = L[b]
+            x1, J1, n1 = G.eval_patch(rot, r, s)
+            x2, J2, n2 = G.eval_patch(st.patch[j], Ls[1], Ls[2])
+            assert np.allclose(x1, x2, atol=1e-14) and abs(J1 - J2) < 1e-13 and np.allclose(n1, n2, atol=1e-13)
+
+
+def _double_layer(st, x, exclude_vertex=None, fine=None):
+    """sum over the surface of w dG0/dny at x (regular rule, or a fine rule everywhere)."""
+    if fine is None:
+        d = x - st.y
+        return np.sum(st.w * np.einsum("fmc,fmc->fm", d, st.ny) / (FOUR_PI * np.linalg.norm(d, axis=-1) ** 3))
+    rd, sd, wd = Q.duffy_gauss_legendre(fine)
+    tot = 0.0
+    for j in range(st.nf):
+        k = 0
+        if exclude_vertex is not None and exclude_vertex in st.tri[j]:
+            k = int(np.nonzero(st.tri[j] == exclude_vertex)[0][0])
+        rot = G.rotate_nodes(st.patch[j], k)
+        for m in range(rd.shape[0]):
+            y, J, n = G.eval_patch(rot, rd[m], sd[m])
+            d = x - y
+            tot += wd[m] * J * np.dot(d, n) / (FOUR_PI * np.linalg.norm(d) ** 3)
+    return tot
+
+
+def test_double_layer_identity(spheres):
+    """Gauss: int dG0/dny = -1 inside, 0 outside, -1/2 on the (smooth) surface."""
+    st = spheres[3]
+    assert abs(_double_layer(st, np.array([0.3, -0.2, 0.5])) + 1.0) < 1e-6
+    assert abs(_double_layer(st, np.array([3.0, 1.0, 0.0]))) < 1e-5
+    st = spheres[2]
+    # with a fine singular-aware rule the identity holds at a vertex to rounding
+    i = 7
+    assert abs(_double_layer(st, st.xyz[i], exclude_vertex=i, fine=12) + 0.5) < 1e-9
+
+
+def test_discrete_double_layer_row_sums_converge(spheres):
+    """The operator's own rules: row sums of the double layer tend to -1/2 as h -> 0."""
+    errs = []
+    for lvl in (1, 2, 3):
+        st = spheres[lvl]
+        nv = st.nv
+        # A applied to (phi = 1, dphi = 0) at kappa = 0, eps = 2: row = 1.5 - K2-sum
+        # with K2 = (eps - 1) dG0/dny = dG0/dny, so A 1 = 1.5 - DL -> 2 as DL -> -1/2
+        rows = np.arange(0, nv, max(1, nv // 40))
+        y = O.matvec(st, np.concatenate([np.ones(nv), np.zeros(nv)]), 0.0, 2.0, rows=rows)
+        errs.append(np.max(np.abs(y[0] - 2.0)))
+    assert errs[2] < errs[1] < errs[0] and errs[2] < 3e-5

@@ -1,0 +1,264 @@
+"""Pins of the oracle's operator, GMRES, energy and analytic references.
+
+Each test checks the oracle against something it does not compute itself: Kirkwood's
+closed form and series (Section 3 validation), the value the paper prints for the 2 A
+sphere (Table 1, golden fixture), dense LAPACK solves, identities of the continuous
+problem (A = I when eps1 = eps2 and kappa = 0; Gauss's law; Green's reciprocity) and
+invariances (rigid motions, vertex relabelling).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.special
+
+from oracle import COULOMB_KCAL, FOUR_PI
+from oracle import geometry as G
+from oracle import kirkwood as KW
+from oracle import operator as O
+from oracle import quadrature as Q
+from oracle.gmres import gmres
+from oracle.kernels import kernels
+from oracle.solve import solve
+from paper_1301_5914_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+SCALE = FOUR_PI * COULOMB_KCAL
+
+
+def _solve(p, **kw):
+    return solve(p.xyz, p.nrm, p.tri, p.qpos, p.q, p.eps1, p.eps2, p.kappa, **kw)
+
+
+# ---------------------------------------------------------------- analytic references
+
+def test_bessel_log_derivative_matches_scipy():
+    for z in (0.05, 0.2514, 1.0, 4.0):
+        rho = KW.log_derivative_kn(40, z)
+        n = np.arange(41)
+        ref = z * scipy.special.spherical_kn(n, z, derivative=True) / scipy.special.spherical_kn(n, z)
+        np.testing.assert_allclose(rho, ref, rtol=1e-12)
+
+
+def test_kirkwood_series_reduces_to_closed_form_for_a_centred_charge():
+    for kappa in (0.0, 0.1257, 1.0):
+        E, phi, dphi = KW.centered_closed_form(1.0, 2.0, 1.0, 80.0, kappa)
+        pts = inputs.icosphere(1, 2.0)[0]
+        ps, ds = KW.surface_values(pts, np.zeros((1, 3)), np.ones(1), 2.0, 1.0, 80.0, kappa)
+        np.testing.assert_allclose(ps, phi, rtol=1e-14)
+        np.testing.assert_allclose(ds, dphi, rtol=1e-14)
+        Es = KW.solvation_energy(np.zeros((1, 3)), np.ones(1), 2.0, 1.0, 80.0, kappa)
+        assert abs(Es / E - 1) < 1e-14
+
+
+def test_born_energy_matches_table1():
+    """kappa = 0 closed form at 2 A against the value printed in Table 1."""
+    g = json.load(open(os.path.join(GOLDEN, "table1_hobi_sphere.json")))
+    pr = g["problem"]
+    E, _, _ = KW.centered_closed_form(pr["charge_e"], pr["radius_A"], pr["eps1"], pr["eps2"], pr["kappa"])
+    assert round(E, 2) == g["true_E_sol_kcal_per_mol"]
+
+
+def test_kirkwood_solution_satisfies_the_continuous_equations():
+    """Exact surface data, integrated with a fine rule, solve eqbim_3/eqbim_4 with
+    eps = eps2/eps1 and S carrying 1/eps1 -- and fail with the printed eps1/eps2."""
+    a, eps1, eps2, kappa = 4.0, 2.0, 80.0, 0.4
+    p = inputs.kirkwood_offcenter(2, radius=a, kappa=kappa, eps1=eps1, eps2=eps2)
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    rd, sd, wd = Q.duffy_gauss_legendre(10)
+    S1, S2 = O.sources(st.xyz, st.nrm, p.qpos, p.q, eps1)
+    for i in (0, 17, 101):
+        ys, ns, ws = [], [], []
+        for j in range(st.nf):
+            k = int(np.nonzero(st.tri[j] == i)[0][0]) if i in st.tri[j] else 0
+            rot = G.rotate_nodes(st.patch[j], k)
+            for m in range(rd.shape[0]):
+                y, J, n = G.eval_patch(rot, rd[m], sd[m])
+                ys.append(y), ns.append(n), ws.append(wd[m] * J)
+        ys, ns, ws = np.array(ys), np.array(ns), np.array(ws)
+        on_sphere = ys / np.linalg.norm(ys, axis=1, keepdims=True) * a
+        phi_y, dphi_y = KW.surface_values(on_sphere, p.qpos, p.q, a, eps1, eps2, kappa)
+        x = st.xyz[i][None]
+        phi_x, dphi_x = KW.surface_values(x, p.qpos, p.q, a, eps1, eps2, kappa)
+        for eps, ok in ((eps2 / eps1, True), (eps1 / eps2, False)):
+            K1, K2, K3, K4 = kernels(st.xyz[i], st.nrm[i], ys, ns, kappa, eps)
+            r1 = 0.5 * (1 + eps) * phi_x[0] - np.sum(ws * (K1 * dphi_y + K2 * phi_y)) - S1[i]
+            r2 = 0.5 * (1 + 1 / eps) * dphi_x[0] - np.sum(ws * (K3 * dphi_y + K4 * phi_y)) - S2[i]
+            rel1 = abs(r1) / abs(S1[i])
+            rel2 = abs(r2) / abs(S2[i])
+            if ok:
+                assert rel1 < 1e-5 and rel2 < 5e-3
+            else:
+                assert max(rel1, rel2) > 1.0
+
+
+# ---------------------------------------------------------------- the discrete solve
+
+def test_identity_operator_when_dielectrics_match():
+    """eps1 = eps2, kappa = 0: K1..K4 vanish, A = I, u = (S1, S2), E = 0."""
+    p = inputs.kirkwood_offcenter(1, eps1=2.0, eps2=2.0, kappa=0.0)
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    u = inputs.random_vector(2 * p.nv, 5)
+    np.testing.assert_array_equal(O.matvec(st, u, 0.0, 1.0), u)
+    r = _solve(p, st=st)
+    S1, S2 = O.sources(st.xyz, st.nrm, p.qpos, p.q, 2.0)
+    np.testing.assert_allclose(r["u"], np.concatenate([S1, S2]), rtol=1e-15)
+    assert r["energy"] == 0.0
+
+
+def test_gmres_matches_dense_lapack_solve():
+    p = inputs.kirkwood_offcenter(1)
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    eps = p.eps2 / p.eps1
+    A = O.dense_matrix(st, p.kappa, eps)
+    S1, S2 = O.sources(st.xyz, st.nrm, p.qpos, p.q, p.eps1)
+    b = np.concatenate([S1, S2])
+    x_ref = np.linalg.solve(A, b)
+    x, its, rel, conv = gmres(lambda v: A @ v, b, rtol=1e-13)
+    assert conv
+    assert np.max(np.abs(x - x_ref)) <= 1e-10 * np.max(np.abs(x_ref))
+    # restarted variant reaches the same solution
+    x2, _, _, conv2 = gmres(lambda v: A @ v, b, rtol=1e-13, restart=5, max_iter=500)
+    assert conv2 and np.max(np.abs(x2 - x_ref)) <= 1e-10 * np.max(np.abs(x_ref))
+
+
+def test_centred_kirkwood_config1():
+    """Icosphere L3, R = 2, q = +1 at the centre, kappa = 0.1257 (config 1)."""
+    p = inputs.kirkwood_centered(3)
+    r = _solve(p, workers=8)
+    E, phi, dphi = KW.centered_closed_form(1.0, 2.0, 1.0, 80.0, 0.1257)
+    assert abs(E - (-82.18865)) < 1e-4
+    assert abs(r["energy"] / E - 1) < 1e-5
+    assert KW.rel_max_error(r["phi"], SCALE * phi) < 5e-5
+    assert KW.rel_max_error(r["dphi"], SCALE * dphi) < 1e-4
+    assert r["converged"] and r["true_residual"] < 1e-6
+    assert 4 <= r["iterations"] <= 20
+
+
+def test_centred_kappa0_matches_table1():
+    """The kappa = 0 twin reproduces Table 1's HOBI energy; e_phi at d ~ 12.8 vertices/A^2
+    is within Table 1's figure at d = 10."""
+    g = json.load(open(os.path.join(GOLDEN, "table1_hobi_sphere.json")))
+    p = inputs.kirkwood_centered(3, kappa=0.0)
+    r = _solve(p, workers=8)
+    assert round(r["energy"], 2) == g["E_sol_kcal_per_mol"][1]
+    _, phi, _ = KW.centered_closed_form(1.0, 2.0, 1.0, 80.0, 0.0)
+    density = p.nv / (4 * math.pi * 4.0)
+    assert density > g["density_vertices_per_A2"][1]
+    assert KW.rel_max_error(r["phi"], SCALE * phi) < g["e_phi"][1]
+
+
+@pytest.fixture(scope="module")
+def offcenter_runs():
+    out = {}
+    for lvl in (1, 2, 3):
+        p = inputs.kirkwood_offcenter(lvl)
+        out[lvl] = (p, _solve(p, rtol=1e-10, workers=8))
+    return out
+
+
+def test_offcenter_converges_to_the_kirkwood_series(offcenter_runs):
+    errs_phi, errs_dphi, errs_E = [], [], []
+    for lvl in (1, 2, 3):
+        p, r = offcenter_runs[lvl]
+        a = 4.0
+        phi, dphi = KW.surface_values(p.xyz, p.qpos, p.q, a, p.eps1, p.eps2, p.kappa)
+        E = KW.solvation_energy(p.qpos, p.q, a, p.eps1, p.eps2, p.kappa)
+        errs_phi.append(KW.rel_max_error(r["phi"], SCALE * phi))
+        errs_dphi.append(KW.rel_max_error(r["dphi"], SCALE * dphi))
+        errs_E.append(abs(r["energy"] / E - 1))
+    assert errs_phi[2] < errs_phi[1] < errs_phi[0]
+    assert errs_dphi[2] < errs_dphi[1] < errs_dphi[0]
+    assert errs_E[2] < errs_E[1] < errs_E[0]
+    # second order in h (h halves per level) for the energy, better than 1.5 for phi, dphi
+    assert KW.order(2, 1, errs_E[1], errs_E[2]) > 1.8
+    assert KW.order(2, 1, errs_phi[1], errs_phi[2]) > 1.5
+    assert KW.order(2, 1, errs_dphi[1], errs_dphi[2]) > 1.5
+    assert errs_phi[2] < 2e-3 and errs_E[2] < 5e-3
+
+
+def test_consistency_residual_of_the_exact_solution(offcenter_runs):
+    """||A u* - b|| / ||b|| for the exact vertex values u* shrinks under refinement."""
+    res = []
+    for lvl in (1, 2, 3):
+        p, r = offcenter_runs[lvl]
+        st = r["setup"]
+        phi, dphi = KW.surface_values(p.xyz, p.qpos, p.q, 4.0, p.eps1, p.eps2, p.kappa)
+        ustar = np.concatenate([phi, dphi])
+        res.append(np.linalg.norm(O.matvec(st, ustar, p.kappa, p.eps2 / p.eps1, workers=8) - r["b"])
+                   / np.linalg.norm(r["b"]))
+    assert res[2] < res[1] < res[0]
+
+
+def test_gauss_law_charge_neutrality(offcenter_runs):
+    """int dphi1/dn dS = -Q_total / eps1 (Gauss's law inside the cavity)."""
+    p, r = offcenter_runs[3]
+    st = r["setup"]
+    nv = st.nv
+    dphi = r["u"][nv:]
+    flux = np.sum(st.w * (dphi[st.tri] @ st.L.T))
+    assert abs(flux - (-p.q.sum() / p.eps1)) < 1e-4 * np.abs(p.q).sum()
+    frac = O.solid_angle_fraction(st, p.qpos)
+    np.testing.assert_allclose(frac, 1.0, atol=1e-5)
+
+
+def test_reciprocity_and_linearity():
+    xyz, nrm, tri = inputs.icosphere(2, 3.0)
+    st = O.setup(xyz, nrm, tri)
+    xa, xb = np.array([[0.5, 0.2, -0.3]]), np.array([[-0.8, 0.1, 0.9]])
+    kappa, eps1, eps2 = 0.3, 2.0, 80.0
+
+    def reac(src, at, q=1.0):
+        S1, S2 = O.sources(st.xyz, st.nrm, src, np.array([q]), eps1)
+        b = np.concatenate([S1, S2])
+        u, _, _, _ = gmres(lambda v: O.matvec(st, v, kappa, eps2 / eps1), b, rtol=1e-12)
+        return O.reaction_potential(st, u, at, kappa, eps2 / eps1)[0]
+
+    ab, ba = reac(xa, xb), reac(xb, xa)
+    assert abs(ab - ba) < 2e-3 * abs(ab)
+    assert abs(reac(xa, xb, 2.0) - 2 * ab) < 1e-9 * abs(ab)
+
+
+def test_rigid_motion_and_relabelling_invariance():
+    p = inputs.kirkwood_offcenter(2)
+    base = _solve(p, rtol=1e-12)
+    # rigid rotation + translation of every input
+    rng = np.random.default_rng(7)
+    Qm, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    if np.linalg.det(Qm) < 0:
+        Qm[:, 0] *= -1
+    t = np.array([1.5, -2.0, 0.7])
+    p2 = inputs.Problem(p.xyz @ Qm.T + t, p.nrm @ Qm.T, p.tri, p.qpos @ Qm.T + t, p.q,
+                        p.eps1, p.eps2, p.kappa)
+    rot = _solve(p2, rtol=1e-12)
+    assert abs(rot["energy"] / base["energy"] - 1) < 1e-11
+    np.testing.assert_allclose(rot["phi"], base["phi"], rtol=1e-10, atol=1e-10 * np.abs(base["phi"]).max())
+    # relabel vertices, keep each triangle's vertex order
+    perm = rng.permutation(p.nv)
+    inv = np.argsort(perm)
+    p3 = inputs.Problem(p.xyz[perm], p.nrm[perm], inv[p.tri].astype(np.int32), p.qpos, p.q,
+                        p.eps1, p.eps2, p.kappa)
+    rel = _solve(p3, rtol=1e-12)
+    np.testing.assert_allclose(rel["phi"], base["phi"][perm], rtol=1e-11, atol=1e-11 * np.abs(base["phi"]).max())
+    assert abs(rel["energy"] / base["energy"] - 1) < 1e-12
+
+
+# ---------------------------------------------------------------- input validation
+
+def test_validation_rejects_bad_meshes_and_charges():
+    xyz, nrm, tri = inputs.icosphere(1, 2.0)
+    with pytest.raises(O.MeshError):            # open surface
+        O.setup(xyz, nrm, tri[1:])
+    bad = tri.copy()
+    bad[3] = bad[3][::-1]
+    with pytest.raises(O.MeshError):            # one flipped triangle
+        O.setup(xyz, nrm, bad)
+    with pytest.raises(O.MeshError):            # normals not unit
+        O.setup(xyz, 2 * nrm, tri)
+    with pytest.raises(O.MeshError):            # inward normals
+        O.setup(xyz, -nrm, tri)
+    st = O.setup(xyz, nrm, tri)
+    with pytest.raises(O.ChargeOutsideError):
+        O.check_charges_inside(st, np.array([[0.0, 0.0, 2.5]]))
