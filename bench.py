@@ -1,0 +1,168 @@
+"""Benchmark of the HOBI-PB hot path on one MI355X.
+
+One step = one pass of the whole path on resident inputs: device setup (curved elements,
+regular nodes, singular coefficients, source terms), restarted GMRES to ||r||/||b|| <= 1e-6
+(every iteration one matvec: gather, dense pair kernel, singular correction + diagonal,
+then Gram-Schmidt/Givens on the device) and the solvation energy.
+
+Workload (default): the off-centre Kirkwood sphere -- radius 4 A, 8 seeded charges in
+r < 2.5 A, eps1 = 1, eps2 = 80, kappa = 0.1257 / A -- on the level-6 icosphere (40962
+vertices, 81920 curved triangles, 327680 quadrature nodes, 1.34e10 pairs per matvec),
+mixed precision (FP32 pair kernel, FP64 everywhere else).
+
+Prints one JSON line: value = matvec (vertex, node) pairs evaluated per second over the
+timed steps (G-pairs/s), with the dominant kernel's roofline and the FP64 oracle's rate on
+the host cores beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_PAIR = {True: 58, False: 28}      # kappa > 0 / kappa = 0 (algorithmic count)
+PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}
+
+
+def workload(level: int):
+    from paper_1301_5914_amd import inputs
+    return inputs.kirkwood_offcenter(level)
+
+
+def cpu_baseline(prob, seconds: float, workers: int):
+    """The FP64 oracle's matvec on a bounded sample of rows of the same workload."""
+    from oracle import operator as O
+    from paper_1301_5914_amd import inputs
+
+    st = O.setup(prob.xyz, prob.nrm, prob.tri)
+    u = inputs.random_vector(2 * prob.nv, 1)
+    eps = prob.eps2 / prob.eps1
+    t0 = time.perf_counter()
+    O.matvec(st, u, prob.kappa, eps, rows=np.arange(8))
+    per_row = (time.perf_counter() - t0) / 8
+    nrows = int(max(workers * 8, min(prob.nv, seconds * workers / max(per_row, 1e-6))))
+    nrows = min(nrows, prob.nv)
+    rows = np.arange(nrows)
+    t0 = time.perf_counter()
+    O.matvec(st, u, prob.kappa, eps, rows=rows, workers=workers)
+    dt = time.perf_counter() - t0
+    pairs = nrows * 4 * prob.nf
+    return {"value": pairs / dt / 1e9, "unit": "G-pairs/s", "cores": workers, "kind": "oracle",
+            "sample": f"{nrows} of {prob.nv} matvec rows (x {4 * prob.nf} nodes), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--level", type=int, default=6)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    prob = workload(args.level)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before any GPU call: the oracle forks worker processes
+        workers = max(1, min(16, len(os.sched_getaffinity(0))))
+        cpu = cpu_baseline(prob, args.cpu_seconds, workers)
+
+    import torch
+    from oracle import kirkwood as KW
+    from paper_1301_5914_amd import hobi
+
+    mixed = args.precision == "mixed"
+    stream = torch.cuda.current_stream()
+    ctx = hobi.Context(0, stream=stream, profiling=True)
+    pb = hobi.Problem.from_inputs(ctx, prob, precision=hobi.HOBI_MIXED if mixed else hobi.HOBI_FP64)
+
+    def step():
+        pb.set_dielectric(prob.eps1, prob.eps2, prob.kappa)
+        return pb.solve()
+
+    for _ in range(args.warmup):
+        step()
+    pb.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kst = pb.stats()
+
+    pairs_mv = prob.nv * 4 * prob.nf
+    matvecs = sum(r["stats"]["iterations"] + 1 for r in results)   # + the true-residual matvec
+    value = matvecs * pairs_mv / wall / 1e9
+    avg_pair_ms = kst["ms_pair_kernel"] / max(1, kst["pair_launches"])
+    flops = FLOPS_PER_PAIR[prob.kappa > 0] * pairs_mv
+    achieved = flops / (avg_pair_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    E = results[-1]["energy"]
+    E_exact = KW.solvation_energy(prob.qpos, prob.q, 4.0, prob.eps1, prob.eps2, prob.kappa)
+    out = {
+        "metric": "matvec G-pairs/s + GMRES solve time to 1e-6; serving p50/p99 latency",
+        "value": value,
+        "unit": "G-pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-pairs/f64-accumulate" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"off-centre Kirkwood sphere R=4 A, 8 charges, icosphere L{args.level}",
+                   "nv": prob.nv, "nf": prob.nf, "nodes": 4 * prob.nf, "pairs_per_matvec": pairs_mv,
+                   "kappa": prob.kappa, "eps1": prob.eps1, "eps2": prob.eps2, "rtol": 1e-6,
+                   "precision": args.precision},
+        "gmres_iterations": results[-1]["stats"]["iterations"],
+        "solve_ms": float(np.mean([r["stats"]["ms_solve"] for r in results])),
+        "setup_ms": results[-1]["stats"]["ms_setup"],
+        "energy_ms": results[-1]["stats"]["ms_energy"],
+        "pair_kernel_ms": avg_pair_ms,
+        "pair_kernel_gpairs_per_s": pairs_mv / (avg_pair_ms * 1e-3) / 1e9,
+        "energy_kcal_mol": E,
+        "energy_rel_err_vs_kirkwood": abs(E / E_exact - 1),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "pair_f32_kernel" if mixed else "pair_f64_kernel",
+                     "flops_per_pair": FLOPS_PER_PAIR[prob.kappa > 0]},
+    }
+    if not args.no_compare:
+        # the other precision on the same problem (outside the timed region)
+        pb.set_precision(hobi.HOBI_FP64 if mixed else hobi.HOBI_MIXED)
+        pb.reset_stats()
+        other = pb.solve()
+        ost = pb.stats()
+        o_pair = ost["ms_pair_kernel"] / max(1, ost["pair_launches"])
+        fp64_E = other["energy"] if mixed else E
+        mixed_E = E if mixed else other["energy"]
+        out["compare"] = {
+            "other_precision": "fp64" if mixed else "mixed",
+            "other_solve_ms": other["stats"]["ms_solve"],
+            "other_iterations": other["stats"]["iterations"],
+            "other_pair_kernel_ms": o_pair,
+            "mixed_vs_fp64_energy_rel": abs(mixed_E / fp64_E - 1),
+            "speedup_mixed_over_fp64_pair_kernel": (o_pair / avg_pair_ms) if mixed else (avg_pair_ms / o_pair),
+        }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,167 @@
+/*
+ * hobi.h -- C ABI of the MI355X implementation of the higher-order boundary-integral
+ * Poisson-Boltzmann method (HOBI-PB, arXiv 1301.5914).
+ *
+ * Problem (Section 2, eqs. eq1-radiation with the linearised eq2): a closed molecular
+ * surface Gamma given as a triangulation with unit outward vertex normals; Nc point
+ * charges q_k at x_k inside it; dielectric eps1 inside, eps2 and inverse Debye length
+ * kappa outside.  Results: the surface potential phi and its normal derivative
+ * dphi/dn at the vertices (the unknowns of Section 2.2) and the electrostatic
+ * solvation energy E_sol (eq. solvation_energy, Section 2.5).
+ *
+ * Conventions shared by every entry point:
+ *  - Lengths in Angstrom, charges in units of e.  phi is returned in kcal/(mol e),
+ *    dphi/dn in kcal/(mol e A), E_sol in kcal/mol (Coulomb constant 332.0716).
+ *  - Internal vectors u = (phi_1..phi_Nv, dphi_1..dphi_Nv) used by hobi_matvec and
+ *    hobi_energy are in internal units: Green's functions G0 = 1/(4 pi r) and
+ *    Gk = exp(-kappa r)/(4 pi r) (eq. eq_potential) with charges in e, i.e. phi in e/A.
+ *    Output phi = 4 pi * 332.0716 * internal phi.
+ *  - eps = eps2 / eps1 in the kernels K1..K4 (eq. Eq_Ls; the printed eps1/eps2 is read
+ *    as inverted) and the source terms S1, S2 (eq. Eq_Ss) carry a factor 1/eps1.
+ *  - Arrays are row-major and contiguous.  The library copies every input during the
+ *    call and never keeps a caller pointer after returning.  The caller owns every
+ *    input and output buffer; handles own all device memory and free it on destroy.
+ *  - Every call returns a hobi_status; on failure the message is available from
+ *    hobi_last_error() on the context.  Inputs are never repaired silently, except
+ *    that normals within 1e-6 of unit length are renormalised.
+ *  - One context per host thread.  Calls on one context are serialised on its stream.
+ */
+#ifndef HOBI_H
+#define HOBI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hobi_status {
+    HOBI_OK = 0,
+    HOBI_E_ARG = 1,             /* bad argument (null pointer, size, parameter range)      */
+    HOBI_E_MESH = 2,            /* not a closed oriented 2-manifold, degenerate triangle,   */
+                                /* normal disagreeing with orientation or along an edge   */
+    HOBI_E_CHARGE_OUTSIDE = 3,  /* a charge is not enclosed by the surface                  */
+    HOBI_E_NOCONV = 4,          /* GMRES hit max_iter; outputs hold the last iterate        */
+    HOBI_E_OOM = 5,             /* device allocation failed / over the serving budget      */
+    HOBI_E_HIP = 6,             /* a HIP runtime call failed                                */
+    HOBI_E_NUMERIC = 7,         /* NaN or Inf in the inputs or in a result                 */
+    HOBI_E_BUSY = 8             /* serving: the request is not finished yet                */
+} hobi_status;
+
+/* Arithmetic of the dense pair sum (the regular far field, eqdbef3/eqdbef4). */
+enum {
+    HOBI_FP64 = 0,   /* every step in FP64                                              */
+    HOBI_MIXED = 1   /* pair kernel in FP32, tile sums folded into FP64 accumulators;   */
+                     /* singular correction, GMRES, sources and energy stay FP64        */
+};
+
+typedef struct hobi_ctx_s* hobi_ctx;
+typedef struct hobi_problem_s* hobi_problem;
+typedef struct hobi_server_s* hobi_server;
+
+typedef struct hobi_params {
+    double eps1;        /* solute dielectric (> 0), default 1                               */
+    double eps2;        /* solvent dielectric (> 0), default 80                             */
+    double kappa;       /* inverse Debye length in 1/A (>= 0), default 0.1257               */
+    double rtol;        /* GMRES stop: ||b - A u|| / ||b|| <= rtol (estimated), default 1e-6*/
+    int32_t max_iter;   /* total matvecs allowed, default 200                               */
+    int32_t restart;    /* GMRES(m) restart length, default 200                             */
+    int32_t precision;  /* HOBI_FP64 or HOBI_MIXED, default HOBI_FP64                       */
+    int32_t reserved;   /* must be 0                                                        */
+} hobi_params;
+
+typedef struct hobi_stats {
+    int32_t iterations;        /* matvecs inside GMRES                                      */
+    int32_t converged;         /* 1 if the estimated residual reached rtol                  */
+    double est_residual;       /* GMRES estimate of ||b - A u|| / ||b||                     */
+    double true_residual;      /* recomputed ||b - A u|| / ||b|| (one extra matvec)         */
+    double ms_setup;           /* geometry + quadrature + singular coefficients + sources   */
+    double ms_solve;           /* GMRES wall time on the stream                             */
+    double ms_energy;          /* solvation energy                                          */
+    int64_t pairs_per_matvec;  /* Nv * 4 Nf (target vertex, regular node) pairs             */
+    /* Per-kernel device time, accumulated over the calls since the last reset when the
+     * context has profiling enabled (HIP events on the context's stream), else 0.        */
+    double ms_pair_kernel;
+    int64_t pair_launches;
+    double ms_gather, ms_combine, ms_krylov;
+} hobi_stats;
+
+/* Fills p with the defaults listed in hobi_params. */
+void hobi_params_default(hobi_params* p);
+
+/* ---- context ---------------------------------------------------------------------
+ * device: HIP device ordinal.  stream: a hipStream_t to run on, or NULL for a stream
+ * owned by the context.  Fails with HOBI_E_ARG / HOBI_E_HIP. */
+hobi_status hobi_ctx_create(int device, void* stream, hobi_ctx* out);
+void hobi_ctx_destroy(hobi_ctx ctx);
+/* Message of the last failure on this context (valid until the next call). */
+const char* hobi_last_error(hobi_ctx ctx);
+/* Enables (1) or disables (0) per-kernel HIP-event timing into hobi_stats. */
+hobi_status hobi_ctx_set_profiling(hobi_ctx ctx, int32_t enable);
+/* The hipStream_t the context runs on. */
+void* hobi_ctx_stream(hobi_ctx ctx);
+
+/* ---- problem ---------------------------------------------------------------------
+ * Copies and validates the inputs and runs the per-molecule setup on the context's
+ * stream (routines (1)-(4) of Section 2.6): curved 10-node elements (Section 2.2),
+ * 4-point Gauss-Radau nodes, the singular 16-point Duffy/Gauss-Legendre
+ * coefficients (Section 2.3), source terms S1/S2 (eq. Eq_Ss) and the check that every
+ * charge is enclosed.
+ *   xyz [nv][3], nrm [nv][3]: vertex positions and unit outward normals (host).
+ *   tri [nf][3]: 0-based vertex ids, counter-clockwise seen from outside (host).  The
+ *        first vertex of each triangle is significant: the 4-point rule is anchored at
+ *        it.
+ *   qpos [nc][3], q [nc]: charges (host); nc >= 1.
+ *   params: NULL for the defaults.
+ * Errors: HOBI_E_ARG, HOBI_E_MESH, HOBI_E_CHARGE_OUTSIDE, HOBI_E_NUMERIC, HOBI_E_OOM,
+ * HOBI_E_HIP. */
+hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz,
+                                const double* nrm, int32_t nf, const int32_t* tri,
+                                int32_t nc, const double* qpos, const double* q,
+                                const hobi_params* params, hobi_problem* out);
+void hobi_problem_destroy(hobi_problem pb);
+/* Switches the pair-kernel arithmetic (HOBI_FP64 / HOBI_MIXED) of an existing problem. */
+hobi_status hobi_problem_set_precision(hobi_problem pb, int32_t precision);
+/* Replaces eps1, eps2 and kappa and re-runs the whole device part of the setup (curved
+ * elements, regular nodes, singular coefficients, source terms) on the resident surface
+ * and charges, e.g. the same molecule in another solvent.  Synchronous.
+ * Errors: HOBI_E_ARG, HOBI_E_HIP. */
+hobi_status hobi_problem_set_dielectric(hobi_problem pb, double eps1, double eps2, double kappa);
+/* Replaces rtol / max_iter / restart. */
+hobi_status hobi_problem_set_solver(hobi_problem pb, double rtol, int32_t max_iter,
+                                    int32_t restart);
+
+/* ---- solve: GMRES on A u = (S1, S2), then the energy (Sections 2.2-2.5) ------------
+ * phi, dphi: [nv] host outputs (nullable); e_sol: host output (nullable);
+ * st: nullable.  Returns HOBI_E_NOCONV (outputs hold the last iterate) when the
+ * estimated residual did not reach rtol within max_iter matvecs. */
+hobi_status hobi_solve(hobi_problem pb, double* phi, double* dphi, double* e_sol,
+                       hobi_stats* st);
+
+/* ---- the hot path: y = A u (eqdbef3 + eqdbef4 + eqdbef5 + eqdbef6) ----------------
+ * u, y: [2 nv] FP64 in internal units and the caller's vertex order.
+ * on_device = 0: host pointers; 1: device pointers valid on the context's stream (the
+ * call is asynchronous with respect to the host in that case). */
+hobi_status hobi_matvec(hobi_problem pb, const double* u, double* y, int32_t on_device);
+
+/* ---- solvation energy of a given u (eq. solvation_energy, 4-point rule on every
+ * triangle; Section 2.6 routine (6)).  u: [2 nv] internal units; e_sol: kcal/mol. */
+hobi_status hobi_energy(hobi_problem pb, const double* u, int32_t on_device,
+                        double* e_sol);
+
+/* ---- inspection of the setup (for verification), caller's vertex/triangle order ---
+ * y, ny: [nf][4][3] regular quadrature nodes and unit normals; w: [nf][4] weight times
+ * Jacobian (Section 2.2).  Any pointer may be NULL. */
+hobi_status hobi_get_nodes(hobi_problem pb, double* y, double* ny, double* w);
+/* b: [2 nv] right-hand side (S1, S2) in internal units. */
+hobi_status hobi_get_rhs(hobi_problem pb, double* b);
+/* Zeroes the per-kernel timers reported in hobi_stats; hobi_get_stats reads them. */
+hobi_status hobi_reset_stats(hobi_problem pb);
+hobi_status hobi_get_stats(hobi_problem pb, hobi_stats* st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOBI_H */

@@ -1,0 +1,166 @@
+// FP64 building blocks of restarted GMRES on the device: multi-vector dot products with
+// a fixed two-stage reduction (deterministic), multi-vector updates for classical
+// Gram-Schmidt with one re-orthogonalisation pass, and the small Hessenberg work
+// (Givens rotations, back substitution) in single-lane kernels.
+#include "hobi_internal.h"
+
+namespace hobi {
+
+namespace {
+
+constexpr int kT = 256;
+
+// partial[j * kDotBlocks + b] = sum over block b's slice of V[j] . w
+__global__ __launch_bounds__(kT) void dots_kernel(const double* __restrict__ V, size_t ld,
+                                                 const double* __restrict__ w, int n,
+                                                 double* __restrict__ partial) {
+    __shared__ double red[kT];
+    const int j = blockIdx.y;
+    const double* v = V + ld * j;
+    double acc = 0.0;
+    for (int i = blockIdx.x * kT + threadIdx.x; i < n; i += kT * kDotBlocks) acc += v[i] * w[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = kT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)j * kDotBlocks + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kDotBlocks) void reduce_kernel(const double* __restrict__ partial,
+                                                           double* __restrict__ out, int sqrt_out) {
+    __shared__ double red[kDotBlocks];
+    const int j = blockIdx.x;
+    red[threadIdx.x] = partial[(size_t)j * kDotBlocks + threadIdx.x];
+    __syncthreads();
+    for (int off = kDotBlocks / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = sqrt_out ? sqrt(red[0]) : red[0];
+}
+
+// w[i] += sign * sum_j coef[j] V[j][i]
+__global__ void multi_axpy_kernel(const double* __restrict__ V, size_t ld, int nvec,
+                                  const double* __restrict__ coef, double sign, double* __restrict__ w,
+                                  int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int j = 0; j < nvec; ++j) acc += coef[j] * V[ld * j + i];
+    w[i] += sign * acc;
+}
+
+__global__ void scale_copy_kernel(const double* __restrict__ in, const double* __restrict__ denom,
+                                  double* __restrict__ out, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double d = denom[0];
+    out[i] = d != 0.0 ? in[i] / d : 0.0;
+}
+
+__global__ void sub_kernel(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out,
+                           int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] - b[i];
+}
+
+// Column k of the Hessenberg matrix (column-major, leading dimension ldh = m + 1):
+// H[0..k][k] = h1 + h2 (two Gram-Schmidt passes), H[k+1][k] = hnext.  Applies the k
+// previous rotations, forms rotation k, updates g and writes |g[k+1]| / bnorm.
+__global__ void givens_kernel(double* __restrict__ H, int ldh, int k, const double* __restrict__ h1,
+                              const double* __restrict__ h2, const double* __restrict__ hnext,
+                              double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                              double bnorm, double* __restrict__ res) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double* col = H + (size_t)k * ldh;
+    for (int i = 0; i <= k; ++i) col[i] = h1[i] + h2[i];
+    col[k + 1] = hnext[0];
+    for (int i = 0; i < k; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[k], b = col[k + 1];
+    const double den = hypot(a, b);
+    double c = 1.0, s = 0.0;
+    if (den > 0.0) {
+        c = a / den;
+        s = b / den;
+    }
+    cs[k] = c;
+    sn[k] = s;
+    col[k] = den;
+    col[k + 1] = 0.0;
+    const double gk = g[k];
+    g[k + 1] = -s * gk;
+    g[k] = c * gk;
+    res[0] = fabs(g[k + 1]) / bnorm;
+}
+
+__global__ void init_g_kernel(const double* __restrict__ beta, double* __restrict__ g, int m) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= m) g[i] = (i == 0) ? beta[0] : 0.0;
+}
+
+// Solves the k x k upper-triangular system H y = g (column-major H).
+__global__ void trisolve_kernel(const double* __restrict__ H, int ldh, int k, const double* __restrict__ g,
+                                double* __restrict__ y) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = k - 1; i >= 0; --i) {
+        double acc = g[i];
+        for (int l = i + 1; l < k; ++l) acc -= H[(size_t)l * ldh + i] * y[l];
+        const double d = H[(size_t)i * ldh + i];
+        y[i] = d != 0.0 ? acc / d : 0.0;
+    }
+}
+
+inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_dots(const double* V, size_t ld, int nvec, const double* w, int n, double* partial,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(dots_kernel, dim3(kDotBlocks, nvec), dim3(kT), 0, s, V, ld, w, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partial, int nvec, double* out, int sqrt_out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(nvec), dim3(kDotBlocks), 0, s, partial, out, sqrt_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy(const double* V, size_t ld, int nvec, const double* coef, double sign,
+                             double* w, int n, hipStream_t s) {
+    hipLaunchKernelGGL(multi_axpy_kernel, dim3(nblk(n, kT)), dim3(kT), 0, s, V, ld, nvec, coef, sign, w, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(const double* in, const double* denom, double* out, int n, hipStream_t s) {
+    hipLaunchKernelGGL(scale_copy_kernel, dim3(nblk(n, kT)), dim3(kT), 0, s, in, denom, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub(const double* a, const double* b, double* out, int n, hipStream_t s) {
+    hipLaunchKernelGGL(sub_kernel, dim3(nblk(n, kT)), dim3(kT), 0, s, a, b, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_givens(double* H, int ldh, int k, const double* h1, const double* h2, const double* hnext,
+                         double* cs, double* sn, double* g, double bnorm, double* res, hipStream_t s) {
+    hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, s, H, ldh, k, h1, h2, hnext, cs, sn, g, bnorm, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_g(const double* beta, double* g, int m, hipStream_t s) {
+    hipLaunchKernelGGL(init_g_kernel, dim3(nblk(m + 1, kT)), dim3(kT), 0, s, beta, g, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_trisolve(const double* H, int ldh, int k, const double* g, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(trisolve_kernel, dim3(1), dim3(64), 0, s, H, ldh, k, g, y);
+    return hipGetLastError();
+}
+
+}  // namespace hobi

@@ -1,0 +1,853 @@
+// Host side of the HOBI-PB library: the C ABI declared in hobi.h.
+//
+// Owns device memory and the stream, validates inputs, orders the surface spatially
+// (Morton order of vertices and of triangle centroids, so that a wavefront's targets and
+// a chunk's source nodes are compact in space), runs the per-molecule setup kernels,
+// and drives the matvec, restarted GMRES and the energy on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hobi.h"
+#include "hobi_internal.h"
+
+using namespace hobi;
+
+struct hobi_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool profile = false;
+    std::string err;
+};
+
+namespace {
+
+enum TimerKind { T_GATHER = 0, T_PAIR, T_COMBINE, T_KRYLOV, T_NKINDS };
+
+struct Timer {
+    hipEvent_t a, b;
+    int kind;
+};
+
+struct Krylov {
+    int n = 0, m = 0;
+    double *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
+    double *h1 = nullptr, *h2 = nullptr, *hn = nullptr, *yk = nullptr, *res = nullptr;
+    double *dpart = nullptr, *x = nullptr, *tmp = nullptr, *scal = nullptr;
+};
+
+}  // namespace
+
+struct hobi_problem_s {
+    hobi_ctx ctx = nullptr;
+    DeviceProblem d;
+    hobi_params prm{};
+    std::vector<int> vperm, tperm;   // internal -> caller ids
+    int* d_vperm = nullptr;          // [nv] internal -> caller vertex
+    double* u_in = nullptr;          // [2 nv] internal-order work vectors
+    double* y_out = nullptr;
+    double* phi_reac = nullptr;      // [nc]
+    double* e_dev = nullptr;         // [1]
+    double* host_pinned = nullptr;   // small pinned buffer for scalar read-backs
+    int* d_err = nullptr;            // [nf] per-triangle flags of the curved-edge construction
+    Krylov kr;
+    std::vector<Timer> pending;
+    std::vector<hipEvent_t> event_pool;
+    double ms[T_NKINDS] = {0, 0, 0, 0};
+    int64_t cnt[T_NKINDS] = {0, 0, 0, 0};
+    hobi_stats last{};
+};
+
+namespace {
+
+hobi_status fail(hobi_ctx ctx, hobi_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? HOBI_E_OOM : HOBI_E_HIP, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                     \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t n) {
+    return hipMalloc((void**)p, (n ? n : 1) * sizeof(T));
+}
+
+uint64_t spread3(uint64_t v) {   // 21 bits -> every third bit
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+
+std::vector<int> morton_order(const std::vector<double>& pts, int n, const double lo[3], const double hi[3]) {
+    std::vector<uint64_t> code(n);
+    for (int i = 0; i < n; ++i) {
+        uint64_t c = 0;
+        for (int d = 0; d < 3; ++d) {
+            const double ext = hi[d] - lo[d] > 0 ? hi[d] - lo[d] : 1.0;
+            double f = (pts[3 * i + d] - lo[d]) / ext;
+            f = std::min(std::max(f, 0.0), 1.0);
+            c |= spread3((uint64_t)(f * 2097151.0)) << d;
+        }
+        code[i] = c;
+    }
+    std::vector<int> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return code[a] < code[b]; });
+    return ord;
+}
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+hipEvent_t take_event(hobi_problem pb) {
+    if (!pb->event_pool.empty()) {
+        hipEvent_t e = pb->event_pool.back();
+        pb->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct ScopedTimer {
+    hobi_problem pb;
+    Timer t{};
+    bool on;
+    ScopedTimer(hobi_problem p, int kind) : pb(p), on(p->ctx->profile) {
+        if (!on) return;
+        t.a = take_event(pb);
+        t.b = take_event(pb);
+        t.kind = kind;
+        if (!t.a || !t.b) { on = false; return; }
+        (void)hipEventRecord(t.a, pb->ctx->stream);
+    }
+    ~ScopedTimer() {
+        if (!on) return;
+        (void)hipEventRecord(t.b, pb->ctx->stream);
+        pb->pending.push_back(t);
+    }
+};
+
+hobi_status resolve_timers(hobi_problem pb) {
+    if (pb->pending.empty()) return HOBI_OK;
+    HIPCHK(pb->ctx, hipStreamSynchronize(pb->ctx->stream));
+    for (const Timer& t : pb->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            pb->ms[t.kind] += ms;
+            pb->cnt[t.kind] += 1;
+        }
+        pb->event_pool.push_back(t.a);
+        pb->event_pool.push_back(t.b);
+    }
+    pb->pending.clear();
+    return HOBI_OK;
+}
+
+// y = A u, both in internal order on the device.
+hobi_status matvec_internal(hobi_problem pb, const double* u, double* y) {
+    hipStream_t s = pb->ctx->stream;
+    const bool mixed = pb->prm.precision == HOBI_MIXED;
+    {
+        ScopedTimer t(pb, T_GATHER);
+        HIPCHK(pb->ctx, launch_gather(pb->d, u, mixed, s));
+    }
+    {
+        ScopedTimer t(pb, T_PAIR);
+        HIPCHK(pb->ctx, launch_pair(pb->d, mixed, s));
+    }
+    {
+        ScopedTimer t(pb, T_COMBINE);
+        HIPCHK(pb->ctx, launch_combine(pb->d, u, y, mixed, s));
+    }
+    return HOBI_OK;
+}
+
+void free_krylov(Krylov& k) {
+    double* ptrs[] = {k.V, k.H, k.cs, k.sn, k.g, k.h1, k.h2, k.hn, k.yk, k.res, k.dpart, k.x, k.tmp, k.scal};
+    for (double* p : ptrs)
+        if (p) (void)hipFree(p);
+    k = Krylov{};
+}
+
+hobi_status ensure_krylov(hobi_problem pb, int n, int m) {
+    Krylov& k = pb->kr;
+    if (k.n == n && k.m == m) return HOBI_OK;
+    free_krylov(k);
+    hobi_ctx c = pb->ctx;
+    HIPCHK(c, dalloc(&k.V, (size_t)(m + 1) * n));
+    HIPCHK(c, dalloc(&k.H, (size_t)(m + 1) * m));
+    HIPCHK(c, dalloc(&k.cs, m));
+    HIPCHK(c, dalloc(&k.sn, m));
+    HIPCHK(c, dalloc(&k.g, m + 1));
+    HIPCHK(c, dalloc(&k.h1, m + 1));
+    HIPCHK(c, dalloc(&k.h2, m + 1));
+    HIPCHK(c, dalloc(&k.hn, 1));
+    HIPCHK(c, dalloc(&k.yk, m));
+    HIPCHK(c, dalloc(&k.res, 1));
+    HIPCHK(c, dalloc(&k.dpart, (size_t)kDotBlocks * (m + 1)));
+    HIPCHK(c, dalloc(&k.x, n));
+    HIPCHK(c, dalloc(&k.tmp, n));
+    HIPCHK(c, dalloc(&k.scal, 4));
+    k.n = n;
+    k.m = m;
+    return HOBI_OK;
+}
+
+hobi_status read_scalar(hobi_problem pb, const double* dev, double* out) {
+    HIPCHK(pb->ctx, hipMemcpyAsync(pb->host_pinned, dev, sizeof(double), hipMemcpyDeviceToHost,
+                                   pb->ctx->stream));
+    HIPCHK(pb->ctx, hipStreamSynchronize(pb->ctx->stream));
+    *out = pb->host_pinned[0];
+    return HOBI_OK;
+}
+
+hobi_status norm2(hobi_problem pb, const double* v, int n, double* dev_out) {
+    hipStream_t s = pb->ctx->stream;
+    HIPCHK(pb->ctx, launch_dots(v, 0, 1, v, n, pb->kr.dpart, s));
+    HIPCHK(pb->ctx, launch_reduce(pb->kr.dpart, 1, dev_out, 1, s));
+    return HOBI_OK;
+}
+
+// Restarted GMRES(m) from x0 = 0 on A x = rhs (internal order).  Classical Gram-Schmidt
+// with a second pass, Givens rotations, stop when the estimate |g_{k+1}| / ||b|| <= rtol.
+hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
+    const int n = 2 * pb->d.nv;
+    const int m = std::max(1, std::min(pb->prm.restart, pb->prm.max_iter));
+    hobi_status st = ensure_krylov(pb, n, m);
+    if (st != HOBI_OK) return st;
+    Krylov& k = pb->kr;
+    hipStream_t s = pb->ctx->stream;
+    hobi_ctx c = pb->ctx;
+    const double* b = pb->d.rhs;
+    HIPCHK(c, hipMemsetAsync(k.x, 0, sizeof(double) * n, s));
+    if ((st = norm2(pb, b, n, k.scal)) != HOBI_OK) return st;
+    double bnorm = 0;
+    if ((st = read_scalar(pb, k.scal, &bnorm)) != HOBI_OK) return st;
+    *iters = 0;
+    *est = 0.0;
+    *converged = true;
+    if (!(bnorm > 0.0)) return std::isfinite(bnorm) ? HOBI_OK : fail(c, HOBI_E_NUMERIC, "non-finite rhs");
+    int total = 0;
+    const double rtol = pb->prm.rtol;
+    while (true) {
+        // r = b - A x
+        const double* r = b;
+        if (total > 0) {
+            if ((st = matvec_internal(pb, k.x, k.tmp)) != HOBI_OK) return st;
+            HIPCHK(c, launch_sub(b, k.tmp, k.tmp, n, s));
+            r = k.tmp;
+        }
+        if ((st = norm2(pb, r, n, k.scal + 1)) != HOBI_OK) return st;
+        double beta = 0;
+        if ((st = read_scalar(pb, k.scal + 1, &beta)) != HOBI_OK) return st;
+        if (!std::isfinite(beta)) return fail(c, HOBI_E_NUMERIC, "GMRES residual is not finite");
+        *est = beta / bnorm;
+        if (*est <= rtol || total >= pb->prm.max_iter) break;
+        HIPCHK(c, launch_scale_copy(r, k.scal + 1, k.V, n, s));
+        HIPCHK(c, launch_init_g(k.scal + 1, k.g, m, s));
+        int kk = 0;
+        bool stop = false;
+        for (int j = 0; j < m; ++j) {
+            double* w = k.V + (size_t)(j + 1) * n;
+            if ((st = matvec_internal(pb, k.V + (size_t)j * n, w)) != HOBI_OK) return st;
+            ++total;
+            {
+                ScopedTimer t(pb, T_KRYLOV);
+                for (int pass = 0; pass < 2; ++pass) {
+                    double* h = pass == 0 ? k.h1 : k.h2;
+                    HIPCHK(c, launch_dots(k.V, n, j + 1, w, n, k.dpart, s));
+                    HIPCHK(c, launch_reduce(k.dpart, j + 1, h, 0, s));
+                    HIPCHK(c, launch_multi_axpy(k.V, n, j + 1, h, -1.0, w, n, s));
+                }
+                if ((st = norm2(pb, w, n, k.hn)) != HOBI_OK) return st;
+                HIPCHK(c, launch_scale_copy(w, k.hn, w, n, s));
+                HIPCHK(c, launch_givens(k.H, m + 1, j, k.h1, k.h2, k.hn, k.cs, k.sn, k.g, bnorm, k.res, s));
+            }
+            double res = 0;
+            if ((st = read_scalar(pb, k.res, &res)) != HOBI_OK) return st;
+            if (!std::isfinite(res)) return fail(c, HOBI_E_NUMERIC, "GMRES residual is not finite");
+            *est = res;
+            kk = j + 1;
+            if (res <= rtol || total >= pb->prm.max_iter) {
+                stop = true;
+                break;
+            }
+        }
+        HIPCHK(c, launch_trisolve(k.H, m + 1, kk, k.g, k.yk, s));
+        HIPCHK(c, launch_multi_axpy(k.V, n, kk, k.yk, 1.0, k.x, n, s));
+        if (stop) break;
+    }
+    *iters = total;
+    *converged = *est <= rtol;
+    return HOBI_OK;
+}
+
+hobi_status to_internal(hobi_problem pb, const double* u, int on_device, double* dst) {
+    const int nv = pb->d.nv;
+    hipStream_t s = pb->ctx->stream;
+    if (on_device) {
+        HIPCHK(pb->ctx, launch_permute(u, dst, pb->d_vperm, nv, true, s));
+    } else {
+        std::vector<double> h(2 * (size_t)nv);
+        for (int i = 0; i < nv; ++i) {
+            h[i] = u[pb->vperm[i]];
+            h[nv + i] = u[nv + pb->vperm[i]];
+        }
+        HIPCHK(pb->ctx, hipMemcpyAsync(dst, h.data(), sizeof(double) * 2 * nv, hipMemcpyHostToDevice, s));
+        HIPCHK(pb->ctx, hipStreamSynchronize(s));
+    }
+    return HOBI_OK;
+}
+
+hobi_status from_internal(hobi_problem pb, const double* src, int on_device, double* y) {
+    const int nv = pb->d.nv;
+    hipStream_t s = pb->ctx->stream;
+    if (on_device) {
+        HIPCHK(pb->ctx, launch_permute(src, y, pb->d_vperm, nv, false, s));
+    } else {
+        std::vector<double> h(2 * (size_t)nv);
+        HIPCHK(pb->ctx, hipMemcpyAsync(h.data(), src, sizeof(double) * 2 * nv, hipMemcpyDeviceToHost, s));
+        HIPCHK(pb->ctx, hipStreamSynchronize(s));
+        for (int i = 0; i < nv; ++i) {
+            y[pb->vperm[i]] = h[i];
+            y[nv + pb->vperm[i]] = h[nv + i];
+        }
+    }
+    return HOBI_OK;
+}
+
+void free_problem(hobi_problem pb) {
+    DeviceProblem& d = pb->d;
+    void* ptrs[] = {d.xyz, d.nrm, d.tri, d.qpos, d.q, d.qsoa, d.patch, d.node64, d.node32, d.w,
+                    d.tgt64, d.tgt32, d.inc_off, d.inc_ent, d.coef, d.rhs, d.partial,
+                    pb->d_vperm, pb->u_in, pb->y_out, pb->phi_reac, pb->e_dev, pb->d_err};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    free_krylov(pb->kr);
+    if (pb->host_pinned) (void)hipHostFree(pb->host_pinned);
+    for (const Timer& t : pb->pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (hipEvent_t e : pb->event_pool) (void)hipEventDestroy(e);
+}
+
+// Device part of the per-molecule setup on the resident inputs; returns the elapsed ms.
+hobi_status run_device_setup(hobi_problem pb, float* ms_out) {
+    hipStream_t s = pb->ctx->stream;
+    DeviceProblem& d = pb->d;
+    hipEvent_t e0 = take_event(pb), e1 = take_event(pb);
+    if (e0) (void)hipEventRecord(e0, s);
+    HIPCHK(pb->ctx, launch_patch(d, pb->d_err, s));
+    HIPCHK(pb->ctx, launch_regular_nodes(d, s));
+    HIPCHK(pb->ctx, launch_targets(d, s));
+    HIPCHK(pb->ctx, launch_singular(d, s));
+    HIPCHK(pb->ctx, launch_sources(d, s));
+    if (e1) (void)hipEventRecord(e1, s);
+    HIPCHK(pb->ctx, hipStreamSynchronize(s));
+    float ms = 0.f;
+    if (e0 && e1) (void)hipEventElapsedTime(&ms, e0, e1);
+    if (e0) pb->event_pool.push_back(e0);
+    if (e1) pb->event_pool.push_back(e1);
+    *ms_out = ms;
+    return HOBI_OK;
+}
+
+bool finite_all(const double* a, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+hobi_status validate_params(hobi_ctx ctx, const hobi_params& p) {
+    if (!(p.eps1 > 0) || !(p.eps2 > 0) || !std::isfinite(p.eps1) || !std::isfinite(p.eps2))
+        return fail(ctx, HOBI_E_ARG, "eps1 and eps2 must be positive and finite");
+    if (!(p.kappa >= 0) || !std::isfinite(p.kappa)) return fail(ctx, HOBI_E_ARG, "kappa must be >= 0");
+    if (!(p.rtol >= 0) || !std::isfinite(p.rtol)) return fail(ctx, HOBI_E_ARG, "rtol must be >= 0");
+    if (p.max_iter < 1 || p.restart < 1) return fail(ctx, HOBI_E_ARG, "max_iter and restart must be >= 1");
+    if (p.precision != HOBI_FP64 && p.precision != HOBI_MIXED)
+        return fail(ctx, HOBI_E_ARG, "precision must be HOBI_FP64 or HOBI_MIXED");
+    return HOBI_OK;
+}
+
+// Closed, consistently oriented 2-manifold, non-degenerate, counter-clockwise w.r.t. normals.
+hobi_status validate_mesh(hobi_ctx ctx, int nv, const double* xyz, std::vector<double>& nrm, int nf,
+                          const int32_t* tri) {
+    for (int i = 0; i < nv; ++i) {
+        double* n = &nrm[3 * i];
+        const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        if (std::fabs(l - 1.0) > 1e-6) return fail(ctx, HOBI_E_MESH, "normal %d is not unit length", i);
+        n[0] /= l, n[1] /= l, n[2] /= l;
+    }
+    std::vector<uint64_t> keys;
+    keys.reserve(3 * (size_t)nf);
+    std::vector<char> used(nv, 0);
+    for (int t = 0; t < nf; ++t) {
+        const int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+        if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv)
+            return fail(ctx, HOBI_E_MESH, "triangle %d: vertex id out of range", t);
+        if (a == b || b == c || a == c) return fail(ctx, HOBI_E_MESH, "triangle %d repeats a vertex", t);
+        used[a] = used[b] = used[c] = 1;
+        keys.push_back((uint64_t)a * nv + b);
+        keys.push_back((uint64_t)b * nv + c);
+        keys.push_back((uint64_t)c * nv + a);
+        double e1[3], e2[3], cr[3], ns[3];
+        for (int d = 0; d < 3; ++d) {
+            e1[d] = xyz[3 * b + d] - xyz[3 * a + d];
+            e2[d] = xyz[3 * c + d] - xyz[3 * a + d];
+            ns[d] = nrm[3 * a + d] + nrm[3 * b + d] + nrm[3 * c + d];
+        }
+        cr[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        cr[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        const double area2 = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        const double l1 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+        const double l2 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+        if (!(area2 > 1e-12 * std::max(l1, l2))) return fail(ctx, HOBI_E_MESH, "triangle %d is degenerate", t);
+        if (!(cr[0] * ns[0] + cr[1] * ns[1] + cr[2] * ns[2] > 0.0))
+            return fail(ctx, HOBI_E_MESH, "triangle %d: orientation disagrees with vertex normals", t);
+    }
+    for (int i = 0; i < nv; ++i)
+        if (!used[i]) return fail(ctx, HOBI_E_MESH, "vertex %d is not used by any triangle", i);
+    std::vector<uint64_t> sorted(keys);
+    std::sort(sorted.begin(), sorted.end());
+    for (size_t i = 1; i < sorted.size(); ++i)
+        if (sorted[i] == sorted[i - 1])
+            return fail(ctx, HOBI_E_MESH, "directed edge used twice (non-manifold or misoriented)");
+    for (uint64_t k : sorted) {
+        const uint64_t a = k / nv, b = k % nv;
+        if (!std::binary_search(sorted.begin(), sorted.end(), b * nv + a))
+            return fail(ctx, HOBI_E_MESH, "open edge (%d, %d)", (int)a, (int)b);
+    }
+    return HOBI_OK;
+}
+
+}  // namespace
+
+// ======================================================================= C ABI ======
+
+extern "C" {
+
+void hobi_params_default(hobi_params* p) {
+    if (!p) return;
+    p->eps1 = 1.0;
+    p->eps2 = 80.0;
+    p->kappa = 0.1257;
+    p->rtol = 1e-6;
+    p->max_iter = 200;
+    p->restart = 200;
+    p->precision = HOBI_FP64;
+    p->reserved = 0;
+}
+
+hobi_status hobi_ctx_create(int device, void* stream, hobi_ctx* out) {
+    if (!out) return HOBI_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return HOBI_E_HIP;
+    if (device < 0 || device >= ndev) return HOBI_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return HOBI_E_HIP;
+    hobi_ctx c = new hobi_ctx_s();
+    c->device = device;
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return HOBI_E_HIP;
+        }
+        c->own_stream = true;
+    }
+    *out = c;
+    return HOBI_OK;
+}
+
+void hobi_ctx_destroy(hobi_ctx ctx) {
+    if (!ctx) return;
+    if (ctx->own_stream && ctx->stream) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipStreamDestroy(ctx->stream);
+    }
+    delete ctx;
+}
+
+const char* hobi_last_error(hobi_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+hobi_status hobi_ctx_set_profiling(hobi_ctx ctx, int32_t enable) {
+    if (!ctx) return HOBI_E_ARG;
+    ctx->profile = enable != 0;
+    return HOBI_OK;
+}
+
+void* hobi_ctx_stream(hobi_ctx ctx) { return ctx ? (void*)ctx->stream : nullptr; }
+
+hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, const double* nrm_in,
+                                int32_t nf, const int32_t* tri_in, int32_t nc, const double* qpos,
+                                const double* q, const hobi_params* params, hobi_problem* out) {
+    if (!ctx) return HOBI_E_ARG;
+    if (!out) return fail(ctx, HOBI_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!xyz || !nrm_in || !tri_in || !qpos || !q) return fail(ctx, HOBI_E_ARG, "NULL input array");
+    if (nv < 4 || nf < 4 || nc < 1) return fail(ctx, HOBI_E_ARG, "need nv >= 4, nf >= 4, nc >= 1");
+    if ((int64_t)nf * 4 > (int64_t)0x7fffffff / 4) return fail(ctx, HOBI_E_ARG, "nf too large");
+    hobi_params prm;
+    hobi_params_default(&prm);
+    if (params) prm = *params;
+    hobi_status st = validate_params(ctx, prm);
+    if (st != HOBI_OK) return st;
+    if (!finite_all(xyz, 3 * (size_t)nv) || !finite_all(nrm_in, 3 * (size_t)nv) ||
+        !finite_all(qpos, 3 * (size_t)nc) || !finite_all(q, nc))
+        return fail(ctx, HOBI_E_NUMERIC, "non-finite input");
+    std::vector<double> nrm(nrm_in, nrm_in + 3 * (size_t)nv);
+    if ((st = validate_mesh(ctx, nv, xyz, nrm, nf, tri_in)) != HOBI_OK) return st;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+
+    // ---- spatial order ----
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int i = 0; i < nv; ++i)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], xyz[3 * i + d]);
+            hi[d] = std::max(hi[d], xyz[3 * i + d]);
+        }
+    std::vector<double> xv(xyz, xyz + 3 * (size_t)nv);
+    std::vector<int> vperm = morton_order(xv, nv, lo, hi);
+    std::vector<int> vinv(nv);
+    for (int i = 0; i < nv; ++i) vinv[vperm[i]] = i;
+    std::vector<double> cen(3 * (size_t)nf);
+    for (int t = 0; t < nf; ++t)
+        for (int d = 0; d < 3; ++d)
+            cen[3 * t + d] = (xyz[3 * tri_in[3 * t] + d] + xyz[3 * tri_in[3 * t + 1] + d] +
+                              xyz[3 * tri_in[3 * t + 2] + d]) / 3.0;
+    std::vector<int> tperm = morton_order(cen, nf, lo, hi);
+    std::vector<double> hx(3 * (size_t)nv), hn(3 * (size_t)nv);
+    for (int i = 0; i < nv; ++i)
+        for (int d = 0; d < 3; ++d) {
+            hx[3 * i + d] = xyz[3 * vperm[i] + d];
+            hn[3 * i + d] = nrm[3 * vperm[i] + d];
+        }
+    std::vector<int> ht(3 * (size_t)nf);
+    for (int t = 0; t < nf; ++t)
+        for (int k = 0; k < 3; ++k) ht[3 * t + k] = vinv[tri_in[3 * tperm[t] + k]];
+    // incidence lists: entries t*3+k with ht[t][k] == i, in increasing entry order
+    std::vector<int> off(nv + 1, 0), ent(3 * (size_t)nf);
+    for (int e = 0; e < 3 * nf; ++e) off[ht[e] + 1]++;
+    for (int i = 0; i < nv; ++i) off[i + 1] += off[i];
+    {
+        std::vector<int> fill(off.begin(), off.end() - 1);
+        for (int e = 0; e < 3 * nf; ++e) ent[fill[ht[e]]++] = e;
+    }
+
+    hobi_problem pb = new hobi_problem_s();
+    pb->ctx = ctx;
+    pb->prm = prm;
+    pb->vperm = vperm;
+    pb->tperm = tperm;
+    DeviceProblem& d = pb->d;
+    d.nv = nv;
+    d.nf = nf;
+    d.nc = nc;
+    d.nn = 4 * nf;
+    d.eps1 = prm.eps1;
+    d.eps2 = prm.eps2;
+    d.kappa = prm.kappa;
+    d.eps = prm.eps2 / prm.eps1;
+    for (int k = 0; k < 3; ++k) d.center[k] = 0.5 * (lo[k] + hi[k]);
+    d.nv_pad = round_up(nv, 1024);
+    d.nc_pad = round_up(nc, 256);
+    d.plan64 = make_plan(d.nv_pad, d.nn, 2);
+    d.plan32 = make_plan(d.nv_pad, d.nn, 4);
+    d.plan_pts = make_plan(d.nc_pad, d.nn, 1);
+    d.partial_elems = std::max((size_t)2 * d.nv_pad * std::max(d.plan64.chunks, d.plan32.chunks),
+                               (size_t)d.nc_pad * d.plan_pts.chunks);
+
+    auto cleanup_fail = [&](hobi_status code) {
+        free_problem(pb);
+        delete pb;
+        return code;
+    };
+#define PCHK(expr)                                                                              \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return cleanup_fail(fail(ctx, e_ == hipErrorOutOfMemory ? HOBI_E_OOM : HOBI_E_HIP,  \
+                                     "%s: %s", #expr, hipGetErrorString(e_)));                  \
+    } while (0)
+
+    hipStream_t s = ctx->stream;
+    PCHK(dalloc(&d.xyz, 3 * (size_t)nv));
+    PCHK(dalloc(&d.nrm, 3 * (size_t)nv));
+    PCHK(dalloc(&d.tri, 3 * (size_t)nf));
+    PCHK(dalloc(&d.qpos, 3 * (size_t)nc));
+    PCHK(dalloc(&d.q, nc));
+    PCHK(dalloc(&d.qsoa, 3 * (size_t)d.nc_pad));
+    PCHK(dalloc(&d.patch, 30 * (size_t)nf));
+    PCHK(dalloc(&d.node64, d.nn));
+    PCHK(dalloc(&d.node32, d.nn));
+    PCHK(dalloc(&d.w, d.nn));
+    PCHK(dalloc(&d.tgt64, 6 * (size_t)d.nv_pad));
+    PCHK(dalloc(&d.tgt32, 6 * (size_t)d.nv_pad));
+    PCHK(dalloc(&d.inc_off, nv + 1));
+    PCHK(dalloc(&d.inc_ent, 3 * (size_t)nf));
+    PCHK(dalloc(&d.coef, 36 * (size_t)nf));
+    PCHK(dalloc(&d.rhs, 2 * (size_t)nv));
+    PCHK(dalloc(&d.partial, d.partial_elems));
+    PCHK(dalloc(&pb->d_vperm, nv));
+    PCHK(dalloc(&pb->u_in, 2 * (size_t)nv));
+    PCHK(dalloc(&pb->y_out, 2 * (size_t)nv));
+    PCHK(dalloc(&pb->phi_reac, nc));
+    PCHK(dalloc(&pb->e_dev, 4));
+    PCHK(hipHostMalloc((void**)&pb->host_pinned, 64));
+    PCHK(dalloc(&pb->d_err, nf));
+
+    std::vector<double> qs(3 * (size_t)d.nc_pad);
+    for (int k = 0; k < d.nc_pad; ++k)
+        for (int c = 0; c < 3; ++c) qs[(size_t)c * d.nc_pad + k] = qpos[3 * std::min(k, nc - 1) + c];
+
+    PCHK(hipMemcpyAsync(d.xyz, hx.data(), sizeof(double) * hx.size(), hipMemcpyHostToDevice, s));
+    PCHK(hipMemcpyAsync(d.nrm, hn.data(), sizeof(double) * hn.size(), hipMemcpyHostToDevice, s));
+    PCHK(hipMemcpyAsync(d.tri, ht.data(), sizeof(int) * ht.size(), hipMemcpyHostToDevice, s));
+    PCHK(hipMemcpyAsync(d.qpos, qpos, sizeof(double) * 3 * nc, hipMemcpyHostToDevice, s));
+    PCHK(hipMemcpyAsync(d.q, q, sizeof(double) * nc, hipMemcpyHostToDevice, s));
+    PCHK(hipMemcpyAsync(d.qsoa, qs.data(), sizeof(double) * qs.size(), hipMemcpyHostToDevice, s));
+    PCHK(hipMemcpyAsync(d.inc_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
+    PCHK(hipMemcpyAsync(d.inc_ent, ent.data(), sizeof(int) * ent.size(), hipMemcpyHostToDevice, s));
+    PCHK(hipMemcpyAsync(pb->d_vperm, vperm.data(), sizeof(int) * nv, hipMemcpyHostToDevice, s));
+    PCHK(hipMemsetAsync(d.node64, 0, sizeof(NodeD) * d.nn, s));
+    PCHK(hipMemsetAsync(d.node32, 0, sizeof(NodeF) * d.nn, s));
+    PCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    if ((st = run_device_setup(pb, &ms)) != HOBI_OK) return cleanup_fail(st);
+    std::vector<int> herr(nf);
+    PCHK(hipMemcpyAsync(herr.data(), pb->d_err, sizeof(int) * nf, hipMemcpyDeviceToHost, s));
+    PCHK(hipStreamSynchronize(s));
+    for (int t = 0; t < nf; ++t)
+        if (herr[t])
+            return cleanup_fail(fail(ctx, HOBI_E_MESH, "triangle %d: a vertex normal is parallel to an edge",
+                                     tperm[t]));
+    pb->last.ms_setup = ms;
+
+    // every charge must be enclosed: solid-angle fraction ~ 1 inside, ~ 0 outside
+    double* frac = pb->phi_reac;
+    PCHK(launch_solid_angle(d, frac, s));
+    std::vector<double> hf(nc);
+    PCHK(hipMemcpyAsync(hf.data(), frac, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+    PCHK(hipStreamSynchronize(s));
+    for (int k = 0; k < nc; ++k) {
+        if (!std::isfinite(hf[k])) return cleanup_fail(fail(ctx, HOBI_E_NUMERIC, "charge %d: non-finite", k));
+        if (hf[k] < 0.5)
+            return cleanup_fail(fail(ctx, HOBI_E_CHARGE_OUTSIDE, "charge %d is outside the surface", k));
+    }
+#undef PCHK
+    pb->last.pairs_per_matvec = (int64_t)nv * d.nn;
+    *out = pb;
+    return HOBI_OK;
+}
+
+void hobi_problem_destroy(hobi_problem pb) {
+    if (!pb) return;
+    if (pb->ctx && pb->ctx->stream) (void)hipStreamSynchronize(pb->ctx->stream);
+    free_problem(pb);
+    delete pb;
+}
+
+hobi_status hobi_problem_set_precision(hobi_problem pb, int32_t precision) {
+    if (!pb) return HOBI_E_ARG;
+    if (precision != HOBI_FP64 && precision != HOBI_MIXED)
+        return fail(pb->ctx, HOBI_E_ARG, "precision must be HOBI_FP64 or HOBI_MIXED");
+    pb->prm.precision = precision;
+    return HOBI_OK;
+}
+
+hobi_status hobi_problem_set_dielectric(hobi_problem pb, double eps1, double eps2, double kappa) {
+    if (!pb) return HOBI_E_ARG;
+    hobi_params p = pb->prm;
+    p.eps1 = eps1;
+    p.eps2 = eps2;
+    p.kappa = kappa;
+    hobi_status st = validate_params(pb->ctx, p);
+    if (st != HOBI_OK) return st;
+    HIPCHK(pb->ctx, hipSetDevice(pb->ctx->device));
+    pb->prm = p;
+    DeviceProblem& d = pb->d;
+    d.eps1 = eps1;
+    d.eps2 = eps2;
+    d.kappa = kappa;
+    d.eps = eps2 / eps1;
+    float ms = 0.f;
+    if ((st = run_device_setup(pb, &ms)) != HOBI_OK) return st;
+    pb->last.ms_setup = ms;
+    return HOBI_OK;
+}
+
+hobi_status hobi_problem_set_solver(hobi_problem pb, double rtol, int32_t max_iter, int32_t restart) {
+    if (!pb) return HOBI_E_ARG;
+    hobi_params p = pb->prm;
+    p.rtol = rtol;
+    p.max_iter = max_iter;
+    p.restart = restart;
+    hobi_status st = validate_params(pb->ctx, p);
+    if (st != HOBI_OK) return st;
+    pb->prm = p;
+    return HOBI_OK;
+}
+
+hobi_status hobi_matvec(hobi_problem pb, const double* u, double* y, int32_t on_device) {
+    if (!pb) return HOBI_E_ARG;
+    if (!u || !y) return fail(pb->ctx, HOBI_E_ARG, "NULL vector");
+    HIPCHK(pb->ctx, hipSetDevice(pb->ctx->device));
+    hobi_status st = to_internal(pb, u, on_device, pb->u_in);
+    if (st != HOBI_OK) return st;
+    if ((st = matvec_internal(pb, pb->u_in, pb->y_out)) != HOBI_OK) return st;
+    return from_internal(pb, pb->y_out, on_device, y);
+}
+
+hobi_status hobi_energy(hobi_problem pb, const double* u, int32_t on_device, double* e_sol) {
+    if (!pb) return HOBI_E_ARG;
+    if (!u || !e_sol) return fail(pb->ctx, HOBI_E_ARG, "NULL argument");
+    HIPCHK(pb->ctx, hipSetDevice(pb->ctx->device));
+    hipStream_t s = pb->ctx->stream;
+    hobi_status st = to_internal(pb, u, on_device, pb->u_in);
+    if (st != HOBI_OK) return st;
+    HIPCHK(pb->ctx, launch_gather(pb->d, pb->u_in, false, s));
+    HIPCHK(pb->ctx, launch_reaction_energy(pb->d, pb->phi_reac, pb->e_dev, s));
+    return read_scalar(pb, pb->e_dev, e_sol);
+}
+
+hobi_status hobi_solve(hobi_problem pb, double* phi, double* dphi, double* e_sol, hobi_stats* stats) {
+    if (!pb) return HOBI_E_ARG;
+    hobi_ctx c = pb->ctx;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const int nv = pb->d.nv, n = 2 * nv;
+    hipEvent_t ev[4];
+    for (auto& e : ev) e = take_event(pb);
+    for (auto& e : ev)
+        if (!e) return fail(c, HOBI_E_HIP, "hipEventCreate failed");
+    HIPCHK(c, hipEventRecord(ev[0], s));
+    int iters = 0;
+    double est = 0;
+    bool conv = false;
+    hobi_status st = gmres(pb, &iters, &est, &conv);
+    if (st != HOBI_OK) return st;
+    HIPCHK(c, hipEventRecord(ev[1], s));
+    Krylov& k = pb->kr;
+    // true residual
+    if ((st = matvec_internal(pb, k.x, k.tmp)) != HOBI_OK) return st;
+    HIPCHK(c, launch_sub(pb->d.rhs, k.tmp, k.tmp, n, s));
+    if ((st = norm2(pb, k.tmp, n, k.scal + 2)) != HOBI_OK) return st;
+    if ((st = norm2(pb, pb->d.rhs, n, k.scal + 3)) != HOBI_OK) return st;
+    // energy (FP64 nodes, FP64 reduction)
+    HIPCHK(c, hipEventRecord(ev[2], s));
+    HIPCHK(c, launch_gather(pb->d, k.x, false, s));
+    HIPCHK(c, launch_reaction_energy(pb->d, pb->phi_reac, pb->e_dev, s));
+    HIPCHK(c, hipEventRecord(ev[3], s));
+    double hs[2];
+    HIPCHK(c, hipMemcpyAsync(hs, k.scal + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    double E = 0;
+    if ((st = read_scalar(pb, pb->e_dev, &E)) != HOBI_OK) return st;
+    std::vector<double> hu(n);
+    if ((st = from_internal(pb, k.x, 0, hu.data())) != HOBI_OK) return st;
+    const double scale = 4.0 * kPi * 332.0716;
+    if (phi)
+        for (int i = 0; i < nv; ++i) phi[i] = scale * hu[i];
+    if (dphi)
+        for (int i = 0; i < nv; ++i) dphi[i] = scale * hu[nv + i];
+    if (e_sol) *e_sol = E;
+    float t_solve = 0, t_energy = 0;
+    (void)hipEventElapsedTime(&t_solve, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&t_energy, ev[2], ev[3]);
+    for (auto& e : ev) pb->event_pool.push_back(e);
+    if ((st = resolve_timers(pb)) != HOBI_OK) return st;
+    hobi_stats& L = pb->last;
+    L.iterations = iters;
+    L.converged = conv ? 1 : 0;
+    L.est_residual = est;
+    L.true_residual = hs[1] > 0 ? hs[0] / hs[1] : 0.0;
+    L.ms_solve = t_solve;
+    L.ms_energy = t_energy;
+    L.ms_pair_kernel = pb->ms[T_PAIR];
+    L.pair_launches = pb->cnt[T_PAIR];
+    L.ms_gather = pb->ms[T_GATHER];
+    L.ms_combine = pb->ms[T_COMBINE];
+    L.ms_krylov = pb->ms[T_KRYLOV];
+    if (stats) *stats = L;
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(hu[i])) return fail(c, HOBI_E_NUMERIC, "non-finite solution");
+    if (!std::isfinite(E)) return fail(c, HOBI_E_NUMERIC, "non-finite energy");
+    if (!conv) return fail(c, HOBI_E_NOCONV, "GMRES stopped at %d matvecs, residual %.3e", iters, est);
+    return HOBI_OK;
+}
+
+hobi_status hobi_get_nodes(hobi_problem pb, double* y, double* ny, double* w) {
+    if (!pb) return HOBI_E_ARG;
+    HIPCHK(pb->ctx, hipSetDevice(pb->ctx->device));
+    const int nf = pb->d.nf, nn = pb->d.nn;
+    std::vector<NodeD> nd(nn);
+    std::vector<double> hw(nn);
+    hipStream_t s = pb->ctx->stream;
+    HIPCHK(pb->ctx, hipMemcpyAsync(nd.data(), pb->d.node64, sizeof(NodeD) * nn, hipMemcpyDeviceToHost, s));
+    HIPCHK(pb->ctx, hipMemcpyAsync(hw.data(), pb->d.w, sizeof(double) * nn, hipMemcpyDeviceToHost, s));
+    HIPCHK(pb->ctx, hipStreamSynchronize(s));
+    for (int t = 0; t < nf; ++t) {
+        const int o = pb->tperm[t];
+        for (int m = 0; m < 4; ++m) {
+            const NodeD& a = nd[4 * t + m];
+            const size_t b = 4 * (size_t)o + m;
+            if (y) y[3 * b] = a.x, y[3 * b + 1] = a.y, y[3 * b + 2] = a.z;
+            if (ny) ny[3 * b] = a.nx, ny[3 * b + 1] = a.ny, ny[3 * b + 2] = a.nz;
+            if (w) w[b] = hw[4 * t + m];
+        }
+    }
+    return HOBI_OK;
+}
+
+hobi_status hobi_get_rhs(hobi_problem pb, double* b) {
+    if (!pb || !b) return HOBI_E_ARG;
+    HIPCHK(pb->ctx, hipSetDevice(pb->ctx->device));
+    return from_internal(pb, pb->d.rhs, 0, b);
+}
+
+hobi_status hobi_reset_stats(hobi_problem pb) {
+    if (!pb) return HOBI_E_ARG;
+    hobi_status st = resolve_timers(pb);
+    for (int k = 0; k < T_NKINDS; ++k) pb->ms[k] = 0, pb->cnt[k] = 0;
+    return st;
+}
+
+hobi_status hobi_get_stats(hobi_problem pb, hobi_stats* out) {
+    if (!pb || !out) return HOBI_E_ARG;
+    hobi_status st = resolve_timers(pb);
+    pb->last.ms_pair_kernel = pb->ms[T_PAIR];
+    pb->last.pair_launches = pb->cnt[T_PAIR];
+    pb->last.ms_gather = pb->ms[T_GATHER];
+    pb->last.ms_combine = pb->ms[T_COMBINE];
+    pb->last.ms_krylov = pb->ms[T_KRYLOV];
+    *out = pb->last;
+    return st;
+}
+
+}  // extern "C"
