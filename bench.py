@@ -85,7 +85,7 @@ def main():
     from paper_1301_5914_amd import hobi
 
     mixed = args.precision == "mixed"
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()          # kernels and their timing events share this stream
     ctx = hobi.Context(0, stream=stream, profiling=True)
     pb = hobi.Problem.from_inputs(ctx, prob, precision=hobi.HOBI_MIXED if mixed else hobi.HOBI_FP64)
 

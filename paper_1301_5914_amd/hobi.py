@@ -88,6 +88,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1301_5914_amd.build`")
+        # torch ships its own HIP runtime under the same soname; loading torch first makes
+        # the library bind to that one, so that a process holds a single HIP runtime and
+        # torch's device pointers and streams are valid in the library.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
@@ -145,6 +149,9 @@ class Context:
 
     def __init__(self, device: int = 0, stream=None, profiling: bool = False):
         raw = getattr(stream, "cuda_stream", stream)
+        if stream is not None and not raw:
+            raise ValueError("the legacy default stream (handle 0) cannot be shared; pass a "
+                             "non-default stream, or None for a stream owned by the context")
         self.handle = hobi_ctx_create(device, raw)
         self.device = device
         if profiling:

@@ -177,13 +177,15 @@ def test_deterministic(ctx):
 def test_device_pointer_matvec(ctx):
     torch = pytest.importorskip("torch")
     p = inputs.kirkwood_offcenter(2)
-    tctx = hobi.Context(0, stream=torch.cuda.current_stream())
+    s = torch.cuda.Stream()
+    tctx = hobi.Context(0, stream=s)
     g = hobi.Problem.from_inputs(tctx, p)
     u = inputs.random_vector(2 * p.nv, 5)
-    ud = torch.tensor(u, dtype=torch.float64, device="cuda")
-    yd = torch.empty_like(ud)
-    g.matvec(ud, out=yd)
-    y_dev = yd.cpu().numpy()            # same stream: ordered after the matvec
+    with torch.cuda.stream(s):
+        ud = torch.tensor(u, dtype=torch.float64, device="cuda")
+        yd = torch.empty_like(ud)
+        g.matvec(ud, out=yd)            # enqueued on s, after the tensors' creation
+        y_dev = yd.cpu().numpy()        # ordered after the matvec on the same stream
     np.testing.assert_array_equal(y_dev, g.matvec(u))
 
 
