@@ -28,7 +28,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOPS_PER_PAIR = {True: 58, False: 28}      # kappa > 0 / kappa = 0 (algorithmic count)
-PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}
+PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}  # published FP32 (packed) and FP64 vector peaks
+PEAK_NONPACKED_FP32 = 78.6                    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+# HBM bytes per launch of the FP32 pair kernel on the default workload (icosphere L6):
+# rocprofv3 FETCH_SIZE (x2.000) + WRITE_SIZE (x1.000), each scaled by a 256 MiB copy.
+# Only valid for the kernel build it was measured on; null for any other configuration.
+PAIR_F32_L6_TRAFFIC_BYTES = (26043.9 * 2.000 + 65856.0 * 1.000) * 1024
 
 
 def workload(level: int):
@@ -44,11 +49,12 @@ def cpu_baseline(prob, seconds: float, workers: int):
     st = O.setup(prob.xyz, prob.nrm, prob.tri)
     u = inputs.random_vector(2 * prob.nv, 1)
     eps = prob.eps2 / prob.eps1
+    # per-row cost measured with all workers busy, then a sample sized to ~`seconds`
+    probe = np.arange(4 * workers)
     t0 = time.perf_counter()
-    O.matvec(st, u, prob.kappa, eps, rows=np.arange(8))
-    per_row = (time.perf_counter() - t0) / 8
-    nrows = int(max(workers * 8, min(prob.nv, seconds * workers / max(per_row, 1e-6))))
-    nrows = min(nrows, prob.nv)
+    O.matvec(st, u, prob.kappa, eps, rows=probe, workers=workers)
+    per_row = (time.perf_counter() - t0) / probe.size
+    nrows = int(min(prob.nv, max(probe.size, seconds / max(per_row, 1e-9))))
     rows = np.arange(nrows)
     t0 = time.perf_counter()
     O.matvec(st, u, prob.kappa, eps, rows=rows, workers=workers)
@@ -68,6 +74,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -138,7 +146,9 @@ def main():
         "energy_kcal_mol": E,
         "energy_rel_err_vs_kirkwood": abs(E / E_exact - 1),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": PAIR_F32_L6_TRAFFIC_BYTES if (mixed and args.level == 6) else None,
+                     "frac_nonpacked_fp32": achieved / PEAK_NONPACKED_FP32 if mixed else None,
                      "kernel": "pair_f32_kernel" if mixed else "pair_f64_kernel",
                      "flops_per_pair": FLOPS_PER_PAIR[prob.kappa > 0]},
     }
@@ -159,6 +169,12 @@ def main():
             "mixed_vs_fp64_energy_rel": abs(mixed_E / fp64_E - 1),
             "speedup_mixed_over_fp64_pair_kernel": (o_pair / avg_pair_ms) if mixed else (avg_pair_ms / o_pair),
         }
+    if args.calibrate_copy:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = src.numel() * 4
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -8,13 +8,15 @@
 
 namespace hobi {
 
-// Source node as the pair kernel reads it: position, Gamma (interpolated dphi times
-// quadrature weight, Jacobian and 1/(4 pi)), node normal, Phi (same with phi).
-// One node is one 32-byte (FP32) or 64-byte (FP64) record so that a whole wavefront
-// receives it through a single scalar load.
-struct alignas(32) NodeF {
-    float x, y, z, g;
-    float nx, ny, nz, p;
+// Source node as the pair kernels read it: position, node normal, Gamma (interpolated
+// dphi times quadrature weight, Jacobian and 1/(4 pi)) and Phi (same with phi).  The
+// FP32 record also carries the strengths pre-scaled by the dielectric constants,
+//   ga = -(1 - 1/eps) Gamma, gb = -Gamma / eps, pa = (eps - 1) Phi, pb = -eps Phi,
+// so that K2 Phi = (d.ny)/r^3 (pa + pb f1) and K3 Gamma = (d.nx)/r^3 (ga + gb f1).
+// One node is one 64-byte record, i.e. one wave-uniform scalar load.
+struct alignas(64) NodeF {
+    float x, y, z, nx, ny, nz, g, p;
+    float ga, gb, pa, pb, pad0, pad1, pad2, pad3;
 };
 struct alignas(64) NodeD {
     double x, y, z, g;

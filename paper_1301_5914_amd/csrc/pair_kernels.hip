@@ -23,9 +23,22 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kFold = 64;   // FP32 running sums are folded into FP64 every kFold nodes
 
+// Workgroups are dispatched round-robin over the 8 XCDs by linear id.  Give each XCD a
+// contiguous range of logical blocks (target block fastest) so that the blocks sharing a
+// source chunk run on the same XCD and re-read the chunk from that XCD's L2.
+__device__ __forceinline__ void xcd_block(int* tb, int* ch) {
+    const int nx = gridDim.x, nb = gridDim.x * gridDim.y;
+    const int lin = blockIdx.x + nx * blockIdx.y;
+    const int x = lin & 7, slot = lin >> 3;
+    const int q = nb >> 3, rm = nb & 7;
+    const int logical = x * q + min(x, rm) + slot;
+    *tb = logical % nx;
+    *ch = logical / nx;
+}
+
 __global__ void gather_kernel(const double* __restrict__ u, int nv, const int* __restrict__ tri,
                               const double* __restrict__ w, int nn, NodeD* __restrict__ node64,
-                              NodeF* __restrict__ node32, int mixed) {
+                              NodeF* __restrict__ node32, int mixed, double eps) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nn) return;
     const int j = idx >> 2, m = idx & 3;
@@ -40,8 +53,13 @@ __global__ void gather_kernel(const double* __restrict__ u, int nv, const int* _
     node64[idx].g = g;
     node64[idx].p = p;
     if (mixed) {
-        node32[idx].g = (float)g;
-        node32[idx].p = (float)p;
+        NodeF& n = node32[idx];
+        n.g = (float)g;
+        n.p = (float)p;
+        n.ga = (float)(-(1.0 - 1.0 / eps) * g);
+        n.gb = (float)(-g / eps);
+        n.pa = (float)((eps - 1.0) * p);
+        n.pb = (float)(-eps * p);
     }
 }
 
@@ -49,7 +67,9 @@ template <int TPL, bool KAPPA0>
 __global__ __launch_bounds__(kBlock) void pair_f64_kernel(
     const double* __restrict__ tgt, int nv_pad, const NodeD* __restrict__ nodes, int nn, int chunk,
     double kappa, double eps, double* __restrict__ partial) {
-    const int t0 = blockIdx.x * (kBlock * TPL) + threadIdx.x;
+    int tb, ch;
+    xcd_block(&tb, &ch);
+    const int t0 = tb * (kBlock * TPL) + threadIdx.x;
     double tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL], a1[TPL], a2[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -64,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void pair_f64_kernel(
         a2[k] = 0.0;
     }
     const double em1 = eps - 1.0, ce3 = 1.0 - 1.0 / eps, ie = 1.0 / eps;
-    const int s0 = blockIdx.y * chunk;
+    const int s0 = ch * chunk;
     const int s1 = min(s0 + chunk, nn);
     for (int s = s0; s < s1; ++s) {
         const NodeD nd = nodes[s];
@@ -95,16 +115,21 @@ __global__ __launch_bounds__(kBlock) void pair_f64_kernel(
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
         const int t = t0 + k * kBlock;
-        partial[(size_t)(2 * blockIdx.y) * nv_pad + t] = a1[k];
-        partial[(size_t)(2 * blockIdx.y + 1) * nv_pad + t] = a2[k];
+        partial[(size_t)(2 * ch) * nv_pad + t] = a1[k];
+        partial[(size_t)(2 * ch + 1) * nv_pad + t] = a2[k];
     }
 }
 
+// FP32 pairs, FP64 accumulation: running FP32 sums over kFold nodes are added into
+// FP64 per-target accumulators.  Per pair (kappa > 0): 38 VALU operations plus one
+// rsqrt and one exp2 on the transcendental unit.
 template <int TPL, bool KAPPA0>
 __global__ __launch_bounds__(kBlock) void pair_f32_kernel(
     const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes, int nn, int chunk,
-    float kappa, float kl2, float eps, double* __restrict__ partial) {
-    const int t0 = blockIdx.x * (kBlock * TPL) + threadIdx.x;
+    float kappa, float kl2n, double* __restrict__ partial) {
+    int tb, ch;
+    xcd_block(&tb, &ch);
+    const int t0 = tb * (kBlock * TPL) + threadIdx.x;
     float tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL];
     double d1[TPL], d2[TPL];
 #pragma unroll
@@ -119,8 +144,7 @@ __global__ __launch_bounds__(kBlock) void pair_f32_kernel(
         d1[k] = 0.0;
         d2[k] = 0.0;
     }
-    const float em1 = eps - 1.0f, ce3 = 1.0f - 1.0f / eps, ie = 1.0f / eps;
-    const int s0 = blockIdx.y * chunk;
+    const int s0 = ch * chunk;
     const int s1 = min(s0 + chunk, nn);
     for (int sb = s0; sb < s1; sb += kFold) {
         const int se = min(sb + kFold, s1);
@@ -128,32 +152,32 @@ __global__ __launch_bounds__(kBlock) void pair_f32_kernel(
 #pragma unroll
         for (int k = 0; k < TPL; ++k) a1[k] = a2[k] = 0.0f;
         for (int s = sb; s < se; ++s) {
-            const NodeF nd = nodes[s];
+            const NodeF n = nodes[s];
 #pragma unroll
             for (int k = 0; k < TPL; ++k) {
-                const float dx = tx[k] - nd.x, dy = ty[k] - nd.y, dz = tz[k] - nd.z;
+                const float dx = tx[k] - n.x, dy = ty[k] - n.y, dz = tz[k] - n.z;
                 const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                 const float rinv = __builtin_amdgcn_rsqf(r2);
-                const float rinv3 = rinv * rinv * rinv;
-                const float dny = fmaf(dx, nd.nx, fmaf(dy, nd.ny, dz * nd.nz));
+                const float rinv2 = rinv * rinv;
+                const float rinv3 = rinv2 * rinv;
+                const float dny = fmaf(dx, n.nx, fmaf(dy, n.ny, dz * n.nz));
                 const float dnx = fmaf(dx, tnx[k], fmaf(dy, tny[k], dz * tnz[k]));
                 if (KAPPA0) {
-                    a1[k] = fmaf(em1 * dny * rinv3, nd.p, a1[k]);
-                    a2[k] = fmaf(-ce3 * dnx * rinv3, nd.g, a2[k]);
+                    a1[k] = fmaf(dny * rinv3, n.pa, a1[k]);
+                    a2[k] = fmaf(dnx * rinv3, n.ga, a2[k]);
                 } else {
-                    const float nxy = fmaf(tnx[k], nd.nx, fmaf(tny[k], nd.ny, tnz[k] * nd.nz));
+                    const float nxy = fmaf(tnx[k], n.nx, fmaf(tny[k], n.ny, tnz[k] * n.nz));
                     const float r = r2 * rinv;
-                    const float z = kappa * r;
-                    const float e = __builtin_amdgcn_exp2f(-kl2 * r);
-                    const float f0 = 1.0f - e;
-                    const float f1 = fmaf(-e, 1.0f + z, 1.0f);
-                    const float f2 = fmaf(-e, fmaf(z, 3.0f + z, 3.0f), 3.0f);
-                    const float K1 = f0 * rinv;
-                    const float K2 = dny * rinv3 * fmaf(-eps, f1, em1);
-                    const float K3 = -dnx * rinv3 * fmaf(ie, f1, ce3);
-                    const float K4 = fmaf(dnx * dny * f2, rinv * rinv, -nxy * f1) * rinv3;
-                    a1[k] = fmaf(K1, nd.g, fmaf(K2, nd.p, a1[k]));
-                    a2[k] = fmaf(K3, nd.g, fmaf(K4, nd.p, a2[k]));
+                    const float e = __builtin_amdgcn_exp2f(kl2n * r);         // exp(-kappa r)
+                    const float zp1 = fmaf(kappa, r, 1.0f);                  // 1 + z
+                    const float f1 = fmaf(-e, zp1, 1.0f);                    // 1 - e (1 + z)
+                    const float f2 = fmaf(-e, fmaf(zp1, zp1 + 1.0f, 1.0f), 3.0f);   // 3 - e (3 + 3z + z^2)
+                    // row 1: K1 Gamma + K2 Phi = (Gamma - e Gamma)/r + (d.ny)/r^3 (pa + pb f1)
+                    a1[k] = fmaf(dny * rinv3, fmaf(n.pb, f1, n.pa), a1[k]);
+                    a1[k] = fmaf(fmaf(-e, n.g, n.g), rinv, a1[k]);
+                    // row 2: K3 Gamma + K4 Phi = [(d.nx)(ga + gb f1) + Phi ((d.nx)(d.ny) f2 / r^2 - (nx.ny) f1)] / r^3
+                    const float w = fmaf(dnx * dny * f2, rinv2, -nxy * f1);
+                    a2[k] = fmaf(rinv3, fmaf(w, n.p, dnx * fmaf(n.gb, f1, n.ga)), a2[k]);
                 }
             }
         }
@@ -166,8 +190,8 @@ __global__ __launch_bounds__(kBlock) void pair_f32_kernel(
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
         const int t = t0 + k * kBlock;
-        partial[(size_t)(2 * blockIdx.y) * nv_pad + t] = d1[k];
-        partial[(size_t)(2 * blockIdx.y + 1) * nv_pad + t] = d2[k];
+        partial[(size_t)(2 * ch) * nv_pad + t] = d1[k];
+        partial[(size_t)(2 * ch + 1) * nv_pad + t] = d2[k];
     }
 }
 
@@ -298,7 +322,7 @@ PairPlan make_plan(int n_pad, int nn, int tpl) {
 
 hipError_t launch_gather(const DeviceProblem& p, const double* u, bool mixed, hipStream_t s) {
     hipLaunchKernelGGL(gather_kernel, dim3(nblk(p.nn, 256)), dim3(256), 0, s, u, p.nv, p.tri, p.w, p.nn,
-                       p.node64, p.node32, mixed ? 1 : 0);
+                       p.node64, p.node32, mixed ? 1 : 0, p.eps);
     return hipGetLastError();
 }
 
@@ -307,13 +331,16 @@ hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s) {
     if (mixed) {
         const PairPlan& pl = p.plan32;
         dim3 grid(pl.target_blocks, pl.chunks);
-        const float kappa = (float)p.kappa, kl2 = (float)(p.kappa * 1.4426950408889634074);
-        if (k0)
-            hipLaunchKernelGGL((pair_f32_kernel<4, true>), grid, dim3(kBlock), 0, s, p.tgt32, p.nv_pad,
-                               p.node32, p.nn, pl.chunk, kappa, kl2, (float)p.eps, p.partial);
-        else
-            hipLaunchKernelGGL((pair_f32_kernel<4, false>), grid, dim3(kBlock), 0, s, p.tgt32, p.nv_pad,
-                               p.node32, p.nn, pl.chunk, kappa, kl2, (float)p.eps, p.partial);
+        const float kappa = (float)p.kappa, kl2n = (float)(-p.kappa * 1.4426950408889634074);
+#define HOBI_PAIR32(T, K0)                                                                        \
+    hipLaunchKernelGGL((pair_f32_kernel<T, K0>), grid, dim3(kBlock), 0, s, p.tgt32, p.nv_pad, p.node32, \
+                       p.nn, pl.chunk, kappa, kl2n, p.partial)
+        if (pl.tpl == 8) {
+            if (k0) HOBI_PAIR32(8, true); else HOBI_PAIR32(8, false);
+        } else {
+            if (k0) HOBI_PAIR32(4, true); else HOBI_PAIR32(4, false);
+        }
+#undef HOBI_PAIR32
     } else {
         const PairPlan& pl = p.plan64;
         dim3 grid(pl.target_blocks, pl.chunks);

@@ -60,9 +60,22 @@ __global__ void regular_kernel(const double* __restrict__ patch, int nf, NodeD* 
     gauss_radau4(m, &r, &s, &wm);
     Vec3 x, n;
     patch_eval(patch + 30 * (size_t)j, kRotPerm[0], r, s, &x, &J, &n);
-    node64[idx] = NodeD{x.x, x.y, x.z, 0.0, n.x, n.y, n.z, 0.0};
-    node32[idx] = NodeF{(float)(x.x - cx), (float)(x.y - cy), (float)(x.z - cz), 0.0f,
-                        (float)n.x, (float)n.y, (float)n.z, 0.0f};
+    NodeD d{};
+    d.x = x.x;
+    d.y = x.y;
+    d.z = x.z;
+    d.nx = n.x;
+    d.ny = n.y;
+    d.nz = n.z;
+    node64[idx] = d;
+    NodeF f{};
+    f.x = (float)(x.x - cx);
+    f.y = (float)(x.y - cy);
+    f.z = (float)(x.z - cz);
+    f.nx = (float)n.x;
+    f.ny = (float)n.y;
+    f.nz = (float)n.z;
+    node32[idx] = f;
     w[idx] = wm * J;
 }
 
