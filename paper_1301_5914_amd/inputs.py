@@ -148,3 +148,416 @@ def kirkwood_offcenter(level: int = 3, radius: float = 4.0, kappa: float = 0.125
 def random_vector(n: int, seed: int) -> np.ndarray:
     """Seeded random FP64 vector (e.g. a matvec input)."""
     return np.random.default_rng(seed).standard_normal(n)
+
+
+# --------------------------------------------------------------------------------------
+# Protein-like synthetic molecules: packed atoms, Gaussian density, marching tetrahedra
+# --------------------------------------------------------------------------------------
+
+DENSITY_DECAY = 2.3
+
+
+def pack_atoms(n: int, ball_radius: float, seed: int, min_spacing: float = 1.4,
+               radius_range=(1.2, 2.0), charge_sigma: float = 0.4, max_tries: int = 10_000_000):
+    """Random sequential addition of n atom centres in a ball (rejecting candidates closer
+    than ``min_spacing`` to an accepted centre), radii ~ U(radius_range), partial charges
+    ~ N(0, charge_sigma) shifted so that the net charge is an integer."""
+    rng = np.random.default_rng(seed)
+    cell = min_spacing
+    grid: dict = {}
+    centers = []
+    tries = 0
+    R2 = ball_radius * ball_radius
+    while len(centers) < n:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("packing did not finish")
+        c = rng.uniform(-ball_radius, ball_radius, size=3)
+        if np.dot(c, c) > R2:
+            continue
+        key = tuple(np.floor(c / cell).astype(int))
+        ok = True
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    for j in grid.get((key[0] + dx, key[1] + dy, key[2] + dz), ()):
+                        d = c - centers[j]
+                        if np.dot(d, d) < min_spacing * min_spacing:
+                            ok = False
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if not ok:
+                break
+        if ok:
+            grid.setdefault(key, []).append(len(centers))
+            centers.append(c)
+    centers = np.array(centers)
+    radii = rng.uniform(radius_range[0], radius_range[1], size=n)
+    q = rng.normal(0.0, charge_sigma, size=n)
+    q -= (q.sum() - np.round(q.sum())) / n
+    return centers, radii, q
+
+
+class _AtomGrid:
+    """Cell list of atoms for evaluating the density and its gradient at points."""
+
+    def __init__(self, centers, radii, decay=DENSITY_DECAY, tol=1e-10):
+        self.c = centers
+        self.r = radii
+        self.decay = decay
+        # exp(-decay (d^2/r^2 - 1)) < tol beyond d = r sqrt(1 + ln(1/tol)/decay)
+        self.cut = float(np.max(radii) * np.sqrt(1.0 + np.log(1.0 / tol) / decay))
+        self.cell = self.cut
+        self.lo = centers.min(axis=0) - self.cut
+        keys = np.floor((centers - self.lo) / self.cell).astype(np.int64)
+        self.cells: dict = {}
+        for i, k in enumerate(map(tuple, keys)):
+            self.cells.setdefault(k, []).append(i)
+
+    def eval(self, pts, grad=False):
+        pts = np.asarray(pts, dtype=np.float64)
+        rho = np.zeros(pts.shape[0])
+        g = np.zeros_like(pts) if grad else None
+        keys = np.floor((pts - self.lo) / self.cell).astype(np.int64)
+        order = np.lexsort(keys.T[::-1])
+        ks = keys[order]
+        bounds = np.flatnonzero(np.any(np.diff(ks, axis=0) != 0, axis=1)) + 1
+        starts = np.r_[0, bounds]
+        ends = np.r_[bounds, len(order)]
+        for s, e in zip(starts, ends):
+            k = ks[s]
+            idx = order[s:e]
+            atoms = []
+            for dx in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dz in (-1, 0, 1):
+                        atoms += self.cells.get((k[0] + dx, k[1] + dy, k[2] + dz), [])
+            if not atoms:
+                continue
+            atoms = np.array(atoms)
+            d = pts[idx, None, :] - self.c[None, atoms, :]
+            r2 = self.r[atoms] ** 2
+            w = np.exp(-self.decay * (np.sum(d * d, axis=-1) / r2 - 1.0))
+            rho[idx] = w.sum(axis=1)
+            if grad:
+                g[idx] = np.einsum("pa,pac->pc", -2.0 * self.decay * w / r2, d)
+        return (rho, g) if grad else rho
+
+
+# the six tetrahedra of a cube along its main diagonal (one per axis permutation): a
+# consistent split, so neighbouring cubes cut their shared faces the same way
+_KUHN = []
+for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+    p = [np.zeros(3, dtype=np.int64)]
+    for ax in perm:
+        q_ = p[-1].copy()
+        q_[ax] += 1
+        p.append(q_)
+    _KUHN.append(np.array(p))
+
+
+def _tet_table():
+    """Per sign pattern (bit a set = local vertex a inside): list of triangles as triples
+    of tet edges (pairs of local vertices), and one (inside, outside) vertex pair used to
+    orient them."""
+    table = {}
+    for mask in range(16):
+        inside = [a for a in range(4) if mask >> a & 1]
+        outside = [a for a in range(4) if not mask >> a & 1]
+        if len(inside) in (0, 4):
+            table[mask] = ([], None)
+        elif len(inside) in (1, 3):
+            lone = inside[0] if len(inside) == 1 else outside[0]
+            others = [a for a in range(4) if a != lone]
+            tris = [[(lone, others[0]), (lone, others[1]), (lone, others[2])]]
+            ref = (inside[0], outside[0])
+            table[mask] = (tris, ref)
+        else:
+            a, b = inside
+            c, d = outside
+            tris = [[(a, c), (a, d), (b, d)], [(a, c), (b, d), (b, c)]]
+            table[mask] = (tris, (a, c))
+    return table
+
+
+_TET_TABLE = _tet_table()
+
+
+def marching_tetrahedra(func, lo, h, shape, iso_shift=1e-9):
+    """Watertight triangulation of {func > 0} on the grid lo + h * (i, j, k).
+
+    func: callable on [n, 3] points -> values (positive inside).  Returns (verts, tris,
+    edge_keys) with triangles oriented so that their normals point outside.
+    """
+    nx, ny, nz = shape
+    gx = lo[0] + h * np.arange(nx)
+    gy = lo[1] + h * np.arange(ny)
+    gz = lo[2] + h * np.arange(nz)
+    vals = np.empty(shape)
+    for i in range(nx):
+        P = np.stack(np.meshgrid(np.full(1, gx[i]), gy, gz, indexing="ij"), axis=-1).reshape(-1, 3)
+        vals[i] = func(P).reshape(ny, nz)
+    # keep grid values off the iso level so that no crossing sits exactly on a grid point
+    vals = np.where(np.abs(vals) < iso_shift, np.where(vals < 0, -iso_shift, iso_shift), vals)
+    gid = lambda i, j, k: (i * ny + j) * nz + k
+    I, J, K = np.meshgrid(np.arange(nx - 1), np.arange(ny - 1), np.arange(nz - 1), indexing="ij")
+    I, J, K = I.ravel(), J.ravel(), K.ravel()
+    edge_a, edge_b, tri_edges_all = [], [], []
+    n_edges_total = 0
+    tri_list = []
+    for tet in _KUHN:
+        cid = [gid(I + t[0], J + t[1], K + t[2]) for t in tet]              # 4 x ncube
+        fv = [vals.ravel()[c] for c in cid]
+        mask = sum((fv[a] > 0).astype(np.int64) << a for a in range(4))
+        for m in range(1, 15):
+            tris, ref = _TET_TABLE[m]
+            sel = np.flatnonzero(mask == m)
+            if sel.size == 0:
+                continue
+            for tri in tris:
+                ids = []
+                for (a, b) in tri:
+                    ga, gb = cid[a][sel], cid[b][sel]
+                    ids.append(np.stack([np.minimum(ga, gb), np.maximum(ga, gb)], axis=1))
+                ia, ib = ref
+                tri_list.append((np.stack(ids, axis=1), cid[ia][sel], cid[ib][sel]))
+    edges = np.concatenate([t[0].reshape(-1, 2) for t in tri_list])
+    uniq, inv = np.unique(edges, axis=0, return_inverse=True)
+    inv = inv.ravel()
+    fa = vals.ravel()[uniq[:, 0]]
+    fb = vals.ravel()[uniq[:, 1]]
+    t = fa / (fa - fb)
+
+    def coords(g):
+        k = g % nz
+        j = (g // nz) % ny
+        i = g // (ny * nz)
+        return np.stack([gx[i], gy[j], gz[k]], axis=1)
+
+    pa, pb = coords(uniq[:, 0]), coords(uniq[:, 1])
+    verts = pa + t[:, None] * (pb - pa)
+    tris = inv.reshape(-1, 3)
+    refin = np.concatenate([t_[1] for t_ in tri_list])
+    refout = np.concatenate([t_[2] for t_ in tri_list])
+    nrm = np.cross(verts[tris[:, 1]] - verts[tris[:, 0]], verts[tris[:, 2]] - verts[tris[:, 0]])
+    flip = np.einsum("ij,ij->i", nrm, coords(refout) - coords(refin)) < 0
+    tris[flip] = tris[flip][:, ::-1]
+    return verts, tris, (uniq, pa, pb, fa, fb)
+
+
+def collapse_short_edges(xyz, tri, min_len, normal_of=None):
+    """Removes edges shorter than ``min_len`` by merging their end points, keeping the mesh
+    a closed oriented 2-manifold: an edge is collapsed only when its end points share
+    exactly the two vertices opposite to it (the link condition) and no surviving triangle
+    around it turns over.  Returns (xyz, tri) with unused vertices dropped."""
+    xyz = np.array(xyz, dtype=np.float64)
+    tri = [list(t) for t in np.asarray(tri)]
+    nv = xyz.shape[0]
+    vt = [set() for _ in range(nv)]
+    for t, (a, b, c) in enumerate(tri):
+        vt[a].add(t), vt[b].add(t), vt[c].add(t)
+    alive_t = np.ones(len(tri), dtype=bool)
+
+    def neigh(v):
+        out = set()
+        for t in vt[v]:
+            out.update(tri[t])
+        out.discard(v)
+        return out
+
+    def tnormal(t, pos):
+        a, b, c = tri[t]
+        pa, pb, pc = pos(a), pos(b), pos(c)
+        return np.cross(pb - pa, pc - pa)
+
+    changed = True
+    while changed:
+        changed = False
+        E = np.concatenate([np.asarray([t for t, ok in zip(tri, alive_t) if ok])[:, [i, (i + 1) % 3]]
+                            for i in range(3)])
+        E = np.unique(np.sort(E, axis=1), axis=0)
+        L = np.linalg.norm(xyz[E[:, 0]] - xyz[E[:, 1]], axis=1)
+        order = np.argsort(L)
+        order = order[L[order] < min_len]
+        touched = set()
+        for e in order:
+            u, v = int(E[e, 0]), int(E[e, 1])
+            if u in touched or v in touched:
+                continue
+            shared = vt[u] & vt[v]
+            if len(shared) != 2:
+                continue
+            opp = set()
+            for t in shared:
+                opp.update(tri[t])
+            opp -= {u, v}
+            if neigh(u) & neigh(v) != opp or len(opp) != 2:
+                continue
+            p = 0.5 * (xyz[u] + xyz[v])
+            ok = True
+            for t in (vt[u] | vt[v]) - shared:
+                before = tnormal(t, lambda w: xyz[w])
+                after = tnormal(t, lambda w: p if w in (u, v) else xyz[w])
+                if np.dot(before, after) <= 0.0 or np.linalg.norm(after) <= 1e-12 * np.dot(before, before) ** 0.5:
+                    ok = False
+                    break
+            if not ok:
+                continue
+            for t in shared:
+                alive_t[t] = False
+                for w in tri[t]:
+                    vt[w].discard(t)
+            for t in list(vt[v]):
+                tri[t] = [u if w == v else w for w in tri[t]]
+                vt[u].add(t)
+            vt[v] = set()
+            xyz[u] = p
+            touched.update((u, v))
+            touched.update(neigh(u))
+            changed = True
+    tri = np.asarray([t for t, ok in zip(tri, alive_t) if ok], dtype=np.int64)
+    used = np.unique(tri)
+    remap = -np.ones(nv, dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    return xyz[used], remap[tri]
+
+
+def delaunay_flips(xyz, tri, nrm, max_passes: int = 20):
+    """Flips interior edges whose two opposite angles sum to more than pi (the Delaunay
+    criterion on the surface), when the flipped pair stays counter-clockwise with respect
+    to the vertex normals and the new edge does not exist yet.  Removes the obtuse
+    'cap' triangles marching tetrahedra produces."""
+    tri = np.array(tri, dtype=np.int64)
+    edge_of = {}
+    for t, (a, b, c) in enumerate(tri):
+        edge_of[(a, b)] = t
+        edge_of[(b, c)] = t
+        edge_of[(c, a)] = t
+
+    def angle(p, q, r):   # angle at p
+        u, v = q - p, r - p
+        return np.arctan2(np.linalg.norm(np.cross(u, v)), np.dot(u, v))
+
+    def ok_tri(a, b, c):
+        n = np.cross(xyz[b] - xyz[a], xyz[c] - xyz[a])
+        return np.dot(n, nrm[a] + nrm[b] + nrm[c]) > 0.0
+
+    for _ in range(max_passes):
+        flipped = 0
+        for (a, b), t1 in list(edge_of.items()):
+            if a > b or edge_of.get((a, b)) != t1:
+                continue
+            t2 = edge_of.get((b, a))
+            if t2 is None:
+                continue
+            c = [w for w in tri[t1] if w != a and w != b][0]
+            d = [w for w in tri[t2] if w != a and w != b][0]
+            if c == d or (c, d) in edge_of or (d, c) in edge_of:
+                continue
+            if angle(xyz[c], xyz[a], xyz[b]) + angle(xyz[d], xyz[a], xyz[b]) <= np.pi + 1e-9:
+                continue
+            if not (ok_tri(a, d, c) and ok_tri(d, b, c)):
+                continue
+            for e in ((a, b), (b, c), (c, a), (b, a), (a, d), (d, b)):
+                edge_of.pop(e, None)
+            tri[t1] = (a, d, c)
+            tri[t2] = (d, b, c)
+            for t in (t1, t2):
+                x, y, z = tri[t]
+                edge_of[(x, y)] = t
+                edge_of[(y, z)] = t
+                edge_of[(z, x)] = t
+            flipped += 1
+        if flipped == 0:
+            break
+    return tri
+
+
+def molecule_surface(centers, radii, grid: float = 0.5, pad: float = 3.0, decay=DENSITY_DECAY,
+                     refine_steps: int = 30, collapse: float = 0.25, flips: bool = True):
+    """Iso-surface rho = 1 of rho(x) = sum_i exp(-decay (|x - c_i|^2 / r_i^2 - 1)), by
+    marching tetrahedra on a grid of spacing ``grid`` over the bounding box padded by
+    ``pad``.  Vertices are moved onto the iso-surface along their grid edge (bisection
+    on the exact density); edges shorter than ``collapse * grid`` are collapsed (the
+    slivers marching tetrahedra leaves near grid points) and the merged points projected
+    back onto the surface; normals are -grad rho / |grad rho|."""
+    ag = _AtomGrid(centers, radii, decay)
+    lo = centers.min(axis=0) - radii.max() - pad
+    hi = centers.max(axis=0) + radii.max() + pad
+    shape = tuple(int(np.ceil((hi[d] - lo[d]) / grid)) + 1 for d in range(3))
+    verts, tris, (uniq, pa, pb, fa, fb) = marching_tetrahedra(lambda P: ag.eval(P) - 1.0, lo, grid, shape)
+    # bisection along each grid edge on the exact density (fa > 0 inside or fb > 0 inside)
+    a_in = fa > 0
+    pin = np.where(a_in[:, None], pa, pb)
+    pout = np.where(a_in[:, None], pb, pa)
+    lo_t = np.zeros(len(pin))
+    hi_t = np.ones(len(pin))
+    for _ in range(refine_steps):
+        mid = 0.5 * (lo_t + hi_t)
+        inside = ag.eval(pin + mid[:, None] * (pout - pin)) > 1.0
+        lo_t = np.where(inside, mid, lo_t)
+        hi_t = np.where(inside, hi_t, mid)
+    tm = 0.5 * (lo_t + hi_t)
+    verts = pin + tm[:, None] * (pout - pin)
+    if collapse > 0:
+        verts, tris = collapse_short_edges(verts, tris, collapse * grid)
+        # merged points back onto rho = 1 along the gradient (Newton steps)
+        for _ in range(8):
+            rho, g = ag.eval(verts, grad=True)
+            verts = verts - ((rho - 1.0) / np.sum(g * g, axis=1))[:, None] * g
+    _, g = ag.eval(verts, grad=True)
+    nrm = -g / np.linalg.norm(g, axis=1, keepdims=True)
+    if flips:
+        tris = delaunay_flips(verts, tris, nrm)
+    return verts, nrm, tris.astype(np.int32)
+
+
+ATOM_VOLUME = 8.5   # A^3 per atom (hydrogens included) at protein density
+
+
+def protein_ball_radius(n_atoms: int) -> float:
+    """Radius of the ball holding n atoms at protein density (about 10 A for 500 atoms)."""
+    return float((3.0 * n_atoms * ATOM_VOLUME / (4.0 * math.pi)) ** (1.0 / 3.0))
+
+
+def molecule(n_atoms: int = 500, seed: int = 3, grid: float = 0.5, ball_radius=None,
+             eps1: float = 1.0, eps2: float = 80.0, kappa: float = 0.1257) -> Problem:
+    """Protein-like test molecule: atoms packed at protein density (unless ``ball_radius``
+    is given), the Gaussian-density surface marched on ``grid``, one partial charge at
+    every atom centre."""
+    R = protein_ball_radius(n_atoms) if ball_radius is None else ball_radius
+    c, r, q = pack_atoms(n_atoms, R, seed)
+    xyz, nrm, tri = molecule_surface(c, r, grid=grid)
+    return Problem(xyz, nrm, tri, c, q, eps1, eps2, kappa, name=f"molecule_{n_atoms}_s{seed}")
+
+
+def mesh_quality(xyz, tri):
+    """(min angle in degrees, number of connected components, Euler characteristic)."""
+    A, B, C = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
+
+    def ang(u, v):
+        c = np.einsum("ij,ij->i", u, v) / (np.linalg.norm(u, axis=1) * np.linalg.norm(v, axis=1))
+        return np.degrees(np.arccos(np.clip(c, -1, 1)))
+
+    amin = np.minimum(np.minimum(ang(B - A, C - A), ang(A - B, C - B)), ang(A - C, B - C))
+    nv = xyz.shape[0]
+    parent = np.arange(nv)
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for a, b, c in tri:
+        for u, v in ((a, b), (b, c)):
+            ru, rv = find(u), find(v)
+            if ru != rv:
+                parent[ru] = rv
+    comps = len({find(i) for i in range(nv)})
+    edges = np.unique(np.sort(np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]]), axis=1), axis=0)
+    euler = nv - edges.shape[0] + tri.shape[0]
+    return float(amin.min()), comps, int(euler)

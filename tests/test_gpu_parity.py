@@ -215,3 +215,39 @@ def test_error_statuses(ctx):
     with pytest.raises(hobi.HobiError) as e:
         g.solve()
     assert e.value.name == "HOBI_E_NOCONV"
+
+
+@pytest.fixture(scope="module")
+def mol30():
+    return inputs.molecule(30, seed=7)
+
+
+def test_molecule_matvec_matches_oracle(ctx, mol30):
+    """Protein-like marched surface (30 atoms): FP64 to 1e-12 on sampled rows.  The mixed
+    matvec on a random (sign-alternating) vector is held to 1e-4: near pairs of sliver-like
+    marched triangles carry terms ~50x the row value, each rounded in FP32; the 1e-5 bar of
+    the mixed mode is on the solvation energy (next test)."""
+    p = mol30
+    print(f"molecule nv={p.nv} nf={p.nf}", flush=True)
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    u = inputs.random_vector(2 * p.nv, 21)
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.r_[0:30, p.nv - 30:p.nv, rng.integers(0, p.nv, 60)])
+    y_or = O.matvec(st, u, p.kappa, p.eps2 / p.eps1, rows=rows)
+    for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-4)):
+        g = hobi.Problem.from_inputs(ctx, p, precision=prec)
+        y = g.matvec(u)
+        got = np.stack([y[rows], y[p.nv + rows]])
+        err = _rel_inf(got, y_or)
+        print("precision", prec, "rel err", err)
+        assert err <= tol
+
+
+def test_molecule_solve_mixed_matches_fp64(ctx, mol30):
+    p = mol30
+    r64 = hobi.Problem.from_inputs(ctx, p).solve()
+    r32 = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED).solve()
+    print("E fp64", r64["energy"], "its", r64["stats"]["iterations"], "E mixed", r32["energy"],
+          "its", r32["stats"]["iterations"])
+    assert abs(r32["energy"] / r64["energy"] - 1) <= 1e-5
+    assert r64["stats"]["converged"] == 1 and r32["stats"]["converged"] == 1
