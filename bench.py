@@ -73,6 +73,102 @@ def cpu_baseline(prob, seconds: float, workers: int):
             "sample": f"{nrows} of {prob.nv} matvec rows (x {4 * prob.nf} nodes), {dt:.1f} s"}
 
 
+def _make_molecule(n_atoms, seed):
+    from paper_1301_5914_amd import inputs
+    return inputs.molecule(int(n_atoms), seed=int(seed))
+
+
+def build_pool(n_mol, min_atoms, max_atoms, seed, workers):
+    """Seeded pool of protein-like molecules, atom counts log-uniform in [min, max]."""
+    import multiprocessing as mp
+    rng = np.random.default_rng(seed)
+    atoms = np.round(np.exp(rng.uniform(np.log(min_atoms), np.log(max_atoms), n_mol))).astype(int)
+    jobs = [(int(a), 1000 + i) for i, a in enumerate(atoms)]
+    with mp.get_context("fork").Pool(max(1, min(workers, n_mol))) as pool:
+        return pool.starmap(_make_molecule, jobs)
+
+
+def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slots, n_check):
+    """Poisson request stream through the continuous-batching server (mixed precision)."""
+    from paper_1301_5914_amd import hobi
+
+    rng = np.random.default_rng(seed)
+
+    def draw(k):
+        out = []
+        for _ in range(k):
+            m = pool_mols[int(rng.integers(len(pool_mols)))]
+            out.append((m, float(rng.choice([1.0, 2.0, 4.0])), float(rng.choice([0.0, 0.1257]))))
+        return out
+
+    ctx = hobi.Context(0)
+    sv = hobi.Server(ctx, hbm_budget_bytes=budget_bytes, max_slots=max_slots)
+
+    def submit(req):
+        m, e1, kap = req
+        return sv.submit(m, precision=hobi.HOBI_MIXED, eps1=e1, kappa=kap, max_iter=400)
+
+    # saturated throughput: a burst submitted at once
+    burst = draw(min(16, n_requests))
+    t0 = time.perf_counter()
+    ts = [submit(r) for r in burst]
+    left = set(ts)
+    while left:
+        for t in list(left):
+            if sv.poll(t, raise_errors=False) is not None:
+                left.discard(t)
+        time.sleep(0.0005)
+    sat = len(burst) / (time.perf_counter() - t0)
+    rate = rate_factor * sat
+    reqs = draw(n_requests)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+    sub_time, lat, results = {}, [], {}
+    i = 0
+    start = time.perf_counter()
+    while len(results) < n_requests:
+        now = time.perf_counter() - start
+        while i < n_requests and arrivals[i] <= now:
+            t = submit(reqs[i])
+            sub_time[t] = (time.perf_counter(), i)
+            i += 1
+        for t in [t for t in sub_time if t not in results]:
+            r = sv.poll(t, raise_errors=False)
+            if r is not None:
+                results[t] = r
+                lat.append(time.perf_counter() - sub_time[t][0])
+        time.sleep(0.0002)
+    wall = time.perf_counter() - start
+    st = sv.stats()
+    sv.close()
+    pairs = sum(r["stats"]["pairs_per_matvec"] * r["stats"]["iterations"] for r in results.values())
+    ok = sum(1 for r in results.values() if r["status"] == "HOBI_OK")
+    # per-request energy error against the single-problem FP64 path (oracle-validated)
+    errs, checks = [], []
+    for t in list(results)[:n_check]:
+        m, e1, kap = reqs[sub_time[t][1]]
+        ref = hobi.Problem(ctx, m.xyz, m.nrm, m.tri, m.qpos, m.q, eps1=e1, eps2=m.eps2, kappa=kap,
+                           max_iter=400, restart=400).solve(allow_noconv=True)
+        errs.append(abs(results[t]["energy"] / ref["energy"] - 1))
+        checks.append({"nf": m.nf, "eps1": e1, "kappa": kap, "err": errs[-1],
+                       "its": results[t]["stats"]["iterations"], "its_fp64": ref["stats"]["iterations"],
+                       "status": results[t]["status"], "status_fp64": ref["status"],
+                       "E": results[t]["energy"], "E_fp64": ref["energy"]})
+    lat_ms = np.array(lat) * 1e3
+    sizes = [m.nf for m in pool_mols]
+    return {
+        "requests": n_requests, "converged": ok, "arrival_rate_per_s": rate,
+        "saturated_rate_per_s": sat, "rate_factor": rate_factor,
+        "throughput_requests_per_s": n_requests / wall, "throughput_gpairs_per_s": pairs / wall / 1e9,
+        "latency_ms_p50": float(np.percentile(lat_ms, 50)), "latency_ms_p99": float(np.percentile(lat_ms, 99)),
+        "latency_ms_mean": float(lat_ms.mean()),
+        "mean_active_per_tick": st["mean_batch"], "ticks": st["ticks"], "peak_hbm_bytes": st["peak_bytes"],
+        "budget_bytes": budget_bytes,
+        "pool": {"molecules": len(pool_mols), "triangles_min": int(min(sizes)), "triangles_max": int(max(sizes))},
+        "energy_rel_err_vs_fp64_max": float(max(errs)) if errs else None, "energy_checked": len(errs),
+        "checks": checks,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +182,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests in the served stream (0: skip the serving measurement)")
+    ap.add_argument("--serve-pool", type=int, default=8, help="distinct molecules the stream draws from")
+    ap.add_argument("--serve-min-atoms", type=int, default=50)
+    ap.add_argument("--serve-max-atoms", type=int, default=1000)
+    ap.add_argument("--serve-rate", type=float, default=0.7, help="arrival rate / saturated throughput")
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -94,6 +198,10 @@ def main():
         sys.exit(2)
 
     prob = workload(args)
+    pool_mols = None
+    if args.serve_requests > 0:
+        pool_mols = build_pool(args.serve_pool, args.serve_min_atoms, args.serve_max_atoms, 5,
+                               max(1, min(16, len(os.sched_getaffinity(0)))))
     cpu = None
     if not args.no_cpu_baseline:
         # before any GPU call: the oracle forks worker processes
@@ -190,6 +298,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = src.numel() * 4
+    if pool_mols is not None:
+        out["serving"] = serve_bench(pool_mols, args.serve_requests, 5, args.serve_rate,
+                                     int(args.serve_budget_gb * (1 << 30)), args.serve_slots, n_check=8)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

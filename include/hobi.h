@@ -161,6 +161,50 @@ hobi_status hobi_get_rhs(hobi_problem pb, double* b);
 hobi_status hobi_reset_stats(hobi_problem pb);
 hobi_status hobi_get_stats(hobi_problem pb, hobi_stats* st);
 
+/* ---- request server: continuous batching of many solves on one device -------------
+ * A worker thread owns a stream of its own.  Submitted requests wait in FIFO order until
+ * a slot is free and their device footprint (surface, quadrature data, Krylov basis of
+ * max_iter + 1 vectors) fits in hbm_budget_bytes next to the active ones; admitted
+ * requests run their setup and then advance one GMRES iteration per scheduler tick, all
+ * active requests together: each tick does one batched gather, one batched pair-sum and
+ * one batched combine launch for every request (captured once in a HIP graph when
+ * use_graph is 1), then each request's Gram-Schmidt and Givens update.  Requests
+ * arriving during a tick join at the next one; finished requests leave at the end of the
+ * tick that finished them.  A request's arithmetic depends only on that request (its
+ * chunking is fixed by its own size), so its results are bit-for-bit the same alone and
+ * in any mix.  Served solves do not restart: max_iter bounds the Krylov basis.
+ * Thread safety: submit, poll and get_stats may be called from any thread. */
+typedef struct hobi_server_stats {
+    int64_t submitted, completed, failed;  /* requests                                      */
+    int64_t ticks;                         /* scheduler ticks so far                          */
+    int32_t active, pending;               /* requests on the device / waiting               */
+    double mean_batch;                     /* mean active requests per tick                   */
+    int64_t bytes_in_use, peak_bytes;      /* admitted footprint, now and at its maximum      */
+    double busy_ms;                        /* wall time the worker spent with work in hand    */
+} hobi_server_stats;
+
+/* device: from ctx (the server creates its own stream and worker thread).
+ * hbm_budget_bytes > 0; max_slots >= 1.  Errors: HOBI_E_ARG, HOBI_E_HIP. */
+hobi_status hobi_server_create(hobi_ctx ctx, int64_t hbm_budget_bytes, int32_t max_slots,
+                               int32_t use_graph, hobi_server* out);
+/* Inputs as hobi_problem_create (copied during the call); params NULL for the defaults.
+ * Returns a ticket.  HOBI_E_OOM if the request alone exceeds the budget, HOBI_E_ARG for
+ * bad sizes/pointers; mesh and charge errors are reported by hobi_server_poll. */
+hobi_status hobi_server_submit(hobi_server sv, int32_t nv, const double* xyz, const double* nrm,
+                               int32_t nf, const int32_t* tri, int32_t nc, const double* qpos,
+                               const double* q, const hobi_params* params, uint64_t* ticket);
+/* HOBI_E_BUSY while the request waits or runs.  Once it has finished: copies phi, dphi
+ * ([nv], kcal/(mol e) and kcal/(mol e A), nullable), e_sol (kcal/mol, nullable) and st
+ * (nullable), forgets the ticket and returns the request's status (HOBI_OK,
+ * HOBI_E_NOCONV with the last iterate, or the error that stopped it; the message is then
+ * in hobi_server_last_error).  Unknown ticket: HOBI_E_ARG. */
+hobi_status hobi_server_poll(hobi_server sv, uint64_t ticket, double* phi, double* dphi,
+                             double* e_sol, hobi_stats* st);
+hobi_status hobi_server_get_stats(hobi_server sv, hobi_server_stats* out);
+const char* hobi_server_last_error(hobi_server sv);
+/* Stops the worker (requests still waiting or running are dropped) and frees everything. */
+void hobi_server_destroy(hobi_server sv);
+
 #ifdef __cplusplus
 }
 #endif

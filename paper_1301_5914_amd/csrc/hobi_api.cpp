@@ -16,55 +16,10 @@
 #include <vector>
 
 #include "hobi.h"
+#include "hobi_host.h"
 #include "hobi_internal.h"
 
 using namespace hobi;
-
-struct hobi_ctx_s {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    bool profile = false;
-    std::string err;
-};
-
-namespace {
-
-enum TimerKind { T_GATHER = 0, T_PAIR, T_COMBINE, T_KRYLOV, T_NKINDS };
-
-struct Timer {
-    hipEvent_t a, b;
-    int kind;
-};
-
-struct Krylov {
-    int n = 0, m = 0;
-    double *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
-    double *h1 = nullptr, *h2 = nullptr, *hn = nullptr, *yk = nullptr, *res = nullptr;
-    double *dpart = nullptr, *x = nullptr, *tmp = nullptr, *scal = nullptr;
-};
-
-}  // namespace
-
-struct hobi_problem_s {
-    hobi_ctx ctx = nullptr;
-    DeviceProblem d;
-    hobi_params prm{};
-    std::vector<int> vperm, tperm;   // internal -> caller ids
-    int* d_vperm = nullptr;          // [nv] internal -> caller vertex
-    double* u_in = nullptr;          // [2 nv] internal-order work vectors
-    double* y_out = nullptr;
-    double* phi_reac = nullptr;      // [nc]
-    double* e_dev = nullptr;         // [1]
-    double* host_pinned = nullptr;   // small pinned buffer for scalar read-backs
-    int* d_err = nullptr;            // [nf] per-triangle flags of the curved-edge construction
-    Krylov kr;
-    std::vector<Timer> pending;
-    std::vector<hipEvent_t> event_pool;
-    double ms[T_NKINDS] = {0, 0, 0, 0};
-    int64_t cnt[T_NKINDS] = {0, 0, 0, 0};
-    hobi_stats last{};
-};
 
 namespace {
 
@@ -342,7 +297,7 @@ hobi_status from_internal(hobi_problem pb, const double* src, int on_device, dou
 
 void free_problem(hobi_problem pb) {
     DeviceProblem& d = pb->d;
-    void* ptrs[] = {d.xyz, d.nrm, d.tri, d.qpos, d.q, d.qsoa, d.patch, d.node64, d.node32, d.w,
+    void* ptrs[] = {d.xyz, d.nrm, d.tri, d.qpos, d.q, d.qsoa, d.patch, d.node64, d.node32, d.node_vid, d.w,
                     d.tgt64, d.tgt32, d.inc_off, d.inc_ent, d.coef, d.rhs, d.partial,
                     pb->d_vperm, pb->u_in, pb->y_out, pb->phi_reac, pb->e_dev, pb->d_err};
     for (void* p : ptrs)
@@ -453,6 +408,16 @@ hobi_status validate_mesh(hobi_ctx ctx, int nv, const double* xyz, std::vector<d
 }
 
 }  // namespace
+
+namespace hobi {
+
+hobi_status host_from_internal(hobi_problem pb, const double* src, int on_device, double* y) {
+    return from_internal(pb, src, on_device, y);
+}
+
+hobi_status host_fail(hobi_ctx ctx, hobi_status code, const char* msg) { return fail(ctx, code, "%s", msg); }
+
+}  // namespace hobi
 
 // ======================================================================= C ABI ======
 
@@ -613,6 +578,7 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
     PCHK(dalloc(&d.patch, 30 * (size_t)nf));
     PCHK(dalloc(&d.node64, d.nn));
     PCHK(dalloc(&d.node32, d.nn));
+    PCHK(dalloc(&d.node_vid, d.nn));
     PCHK(dalloc(&d.w, d.nn));
     PCHK(dalloc(&d.tgt64, 6 * (size_t)d.nv_pad));
     PCHK(dalloc(&d.tgt32, 6 * (size_t)d.nv_pad));

@@ -12,11 +12,14 @@ namespace hobi {
 // dphi times quadrature weight, Jacobian and 1/(4 pi)) and Phi (same with phi).  The
 // FP32 record also carries the strengths pre-scaled by the dielectric constants,
 //   ga = -(1 - 1/eps) Gamma, gb = -Gamma / eps, pa = (eps - 1) Phi, pb = -eps Phi,
-// so that K2 Phi = (d.ny)/r^3 (pa + pb f1) and K3 Gamma = (d.nx)/r^3 (ga + gb f1).
+// so that K2 Phi = (d.ny)/r^3 (pa + pb f1) and K3 Gamma = (d.nx)/r^3 (ga + gb f1),
+// and the three vertex ids of the node's triangle (its pairs with those vertices belong
+// to the singular rule and are skipped by the dense sum).
 // One node is one 64-byte record, i.e. one wave-uniform scalar load.
 struct alignas(64) NodeF {
     float x, y, z, nx, ny, nz, g, p;
-    float ga, gb, pa, pb, pad0, pad1, pad2, pad3;
+    float ga, gb, pa, pb;
+    int v0, v1, v2, pad;
 };
 struct alignas(64) NodeD {
     double x, y, z, g;

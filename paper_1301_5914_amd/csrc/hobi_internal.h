@@ -39,12 +39,13 @@ struct DeviceProblem {
     double* patch = nullptr;                // [nf][10][3]
     NodeD* node64 = nullptr;                // [nn] positions, normals, Gamma, Phi
     NodeF* node32 = nullptr;                // [nn] FP32 copy (positions shifted by center)
+    int4* node_vid = nullptr;               // [nn] vertex ids of each node's triangle (FP64 path)
     double* w = nullptr;                    // [nn] quadrature weight * Jacobian
     double* tgt64 = nullptr;                // [6][nv_pad] SoA targets x,y,z,nx,ny,nz
     float* tgt32 = nullptr;                 // [6][nv_pad] FP32 SoA (shifted)
     int* inc_off = nullptr;                 // [nv+1] incidence CSR (vertex -> entries)
     int* inc_ent = nullptr;                 // [3 nf] entry = tri * 3 + local vertex
-    double* coef = nullptr;                 // [3 nf][12] singular minus incident-regular
+    double* coef = nullptr;                 // [3 nf][12] singular (Duffy) coefficients
     double* rhs = nullptr;                  // [2 nv] (S1, S2)
     // per-matvec work space
     double* partial = nullptr;              // [chunks][2][nv_pad]

@@ -1,0 +1,580 @@
+// Request server: continuous batching of HOBI-PB solves on one device (hobi_server_* in
+// hobi.h).  One worker thread owns a stream; requests are admitted by device footprint,
+// advance one GMRES iteration per tick with their matvecs batched into three launches,
+// and retire as soon as they converge.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "hobi.h"
+#include "hobi_host.h"
+#include "hobi_internal.h"
+#include "serve_internal.h"
+
+using namespace hobi;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+struct Request {
+    uint64_t ticket = 0;
+    int nv = 0, nf = 0, nc = 0;
+    std::vector<double> xyz, nrm, qpos, q;
+    std::vector<int32_t> tri;
+    hobi_params prm{};
+    int64_t footprint = 0;
+    // device state while active
+    hobi_problem pb = nullptr;
+    PairPlan plan{};
+    double* partial = nullptr;
+    double *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
+    double *h1 = nullptr, *h2 = nullptr, *hn = nullptr, *yk = nullptr, *dpart = nullptr;
+    double *x = nullptr, *scal = nullptr;
+    int m = 0, k = 0;
+    double bnorm = 0, est = 1;
+    Clock::time_point t_admit;
+    // outcome
+    hobi_status status = HOBI_OK;
+    std::string message;
+    std::vector<double> phi, dphi;
+    double energy = 0;
+    hobi_stats stats{};
+};
+
+template <class T>
+hipError_t dalloc(T** p, size_t n) {
+    return hipMalloc((void**)p, (n ? n : 1) * sizeof(T));
+}
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Device bytes of one admitted request (the allocations of hobi_problem_create plus the
+// server's partial sums and Krylov basis), from its sizes alone.
+int64_t footprint_bytes(int nv, int nf, int nc, int m, bool mixed) {
+    const int64_t nv_pad = round_up(nv, 2048), nc_pad = round_up(nc, 256), nn = 4LL * nf;
+    const PairPlan p64 = make_plan((int)nv_pad, (int)nn, 2), p32 = make_plan((int)nv_pad, (int)nn, nv_pad >= 16384 ? 8 : 4);
+    const PairPlan pp = make_plan((int)nc_pad, (int)nn, 1);
+    const PairPlan ps = make_plan((int)nv_pad, (int)nn, mixed ? kServeTpl32 : kServeTpl64);
+    int64_t b = 0;
+    b += 8 * (6LL * nv + 4LL * nc + 3 * nc_pad + 30LL * nf + 4 * nn + 12 * nv_pad + 36LL * nf + 2LL * nv + 4LL * nv);
+    b += (int64_t)sizeof(NodeD) * nn + (int64_t)sizeof(NodeF) * nn + 16 * nn;
+    b += 4 * (3LL * nf + nv + 1 + 3LL * nf + nv + nf) + 2LL * 4 * nv_pad;
+    b += 8 * std::max<int64_t>(2 * nv_pad * std::max(p64.chunks, p32.chunks), nc_pad * pp.chunks);
+    b += 8 * 2 * nv_pad * (int64_t)ps.chunks;
+    const int64_t n = 2LL * nv;
+    b += 8 * ((int64_t)(m + 1) * n + (int64_t)(m + 1) * m + 6LL * (m + 1) + kDotBlocks * (int64_t)(m + 1) + n + 8);
+    return b;
+}
+
+void free_request_device(Request& r) {
+    double* ptrs[] = {r.partial, r.V, r.H, r.cs, r.sn, r.g, r.h1, r.h2, r.hn, r.yk, r.dpart, r.x, r.scal};
+    for (double* p : ptrs)
+        if (p) (void)hipFree(p);
+    r.partial = r.V = r.H = r.cs = r.sn = r.g = r.h1 = r.h2 = r.hn = r.yk = r.dpart = r.x = r.scal = nullptr;
+    if (r.pb) hobi_problem_destroy(r.pb);
+    r.pb = nullptr;
+}
+
+}  // namespace
+
+struct hobi_server_s {
+    int device = 0;
+    hobi_ctx ctx = nullptr;           // the worker's context (own stream)
+    int64_t budget = 0;
+    int max_slots = 1;
+    bool use_graph = true;
+
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    std::deque<std::unique_ptr<Request>> pending;
+    std::map<uint64_t, std::unique_ptr<Request>> done;
+    std::set<uint64_t> in_flight;     // submitted, not finished yet
+    std::string last_error;
+    hobi_server_stats st{};
+
+    // worker-only state
+    std::vector<std::unique_ptr<Request>> active;
+    int64_t in_use = 0;
+    double batch_sum = 0;
+    ServeDesc* d_desc = nullptr;
+    ServeItem* d_items = nullptr;     // gather | pair | combine item arrays
+    int* d_counts = nullptr;
+    ServeDesc* h_desc = nullptr;      // pinned staging
+    ServeItem* h_items = nullptr;
+    int* h_counts = nullptr;
+    double* d_res = nullptr;          // one residual per active request
+    double* h_res = nullptr;
+    size_t cap_desc = 0, cap_items = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    bool graph_dirty = true;
+    std::thread worker;
+};
+
+namespace {
+
+void fail_request(Request& r, hobi_status code, const std::string& msg) {
+    r.status = code;
+    r.message = msg;
+}
+
+// Allocates the device state of a request and starts its GMRES (x0 = 0, v0 = b / |b|).
+hobi_status admit(hobi_server sv, Request& r) {
+    hobi_ctx c = sv->ctx;
+    hipStream_t s = c->stream;
+    r.t_admit = Clock::now();
+    hobi_status st = hobi_problem_create(c, r.nv, r.xyz.data(), r.nrm.data(), r.nf, r.tri.data(), r.nc,
+                                         r.qpos.data(), r.q.data(), &r.prm, &r.pb);
+    if (st != HOBI_OK) {
+        fail_request(r, st, c->err);
+        return st;
+    }
+    const bool mixed = r.prm.precision == HOBI_MIXED;
+    const DeviceProblem& d = r.pb->d;
+    r.plan = make_plan(d.nv_pad, d.nn, mixed ? kServeTpl32 : kServeTpl64);
+    r.m = std::max(1, r.prm.max_iter);
+    const int n = 2 * r.nv, m = r.m;
+    hipError_t e = hipSuccess;
+#define SA(expr)                                                                   \
+    if ((e = (expr)) != hipSuccess) {                                              \
+        fail_request(r, e == hipErrorOutOfMemory ? HOBI_E_OOM : HOBI_E_HIP, #expr); \
+        return r.status;                                                           \
+    }
+    SA(dalloc(&r.partial, 2 * (size_t)d.nv_pad * r.plan.chunks));
+    SA(dalloc(&r.V, (size_t)(m + 1) * n));
+    SA(dalloc(&r.H, (size_t)(m + 1) * m));
+    SA(dalloc(&r.cs, m));
+    SA(dalloc(&r.sn, m));
+    SA(dalloc(&r.g, m + 1));
+    SA(dalloc(&r.h1, m + 1));
+    SA(dalloc(&r.h2, m + 1));
+    SA(dalloc(&r.hn, 1));
+    SA(dalloc(&r.yk, m));
+    SA(dalloc(&r.dpart, (size_t)kDotBlocks * (m + 1)));
+    SA(dalloc(&r.x, n));
+    SA(dalloc(&r.scal, 4));
+    SA(hipMemsetAsync(r.x, 0, sizeof(double) * n, s));
+    SA(launch_dots(d.rhs, 0, 1, d.rhs, n, r.dpart, s));
+    SA(launch_reduce(r.dpart, 1, r.scal, 1, s));
+    SA(hipMemcpyAsync(sv->h_res, r.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    SA(hipStreamSynchronize(s));
+    r.bnorm = sv->h_res[0];
+    if (!std::isfinite(r.bnorm)) {
+        fail_request(r, HOBI_E_NUMERIC, "non-finite right-hand side");
+        return r.status;
+    }
+    SA(launch_scale_copy(d.rhs, r.scal, r.V, n, s));
+    SA(launch_init_g(r.scal, r.g, m, s));
+#undef SA
+    r.k = 0;
+    r.est = r.bnorm > 0 ? 1.0 : 0.0;
+    r.stats.ms_setup = r.pb->last.ms_setup;
+    r.stats.pairs_per_matvec = (int64_t)r.nv * d.nn;
+    return HOBI_OK;
+}
+
+// Forms x = V y, the energy and the caller-order outputs; frees the device state.
+void finish(hobi_server sv, Request& r, bool converged) {
+    hobi_ctx c = sv->ctx;
+    hipStream_t s = c->stream;
+    const int n = 2 * r.nv;
+    hipError_t e = hipSuccess;
+    if (r.k > 0) {
+        if ((e = launch_trisolve(r.H, r.m + 1, r.k, r.g, r.yk, s)) == hipSuccess)
+            e = launch_multi_axpy(r.V, n, r.k, r.yk, 1.0, r.x, n, s);
+    }
+    if (e == hipSuccess) e = launch_gather(r.pb->d, r.x, false, s);
+    if (e == hipSuccess) e = launch_reaction_energy(r.pb->d, r.pb->phi_reac, r.pb->e_dev, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(sv->h_res, r.pb->e_dev, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        fail_request(r, HOBI_E_HIP, hipGetErrorString(e));
+    } else {
+        r.energy = sv->h_res[0];
+        std::vector<double> hu(n);
+        hobi_status st = host_from_internal(r.pb, r.x, 0, hu.data());
+        if (st != HOBI_OK) {
+            fail_request(r, st, c->err);
+        } else {
+            const double scale = 4.0 * kPi * 332.0716;
+            r.phi.assign(hu.begin(), hu.begin() + r.nv);
+            r.dphi.assign(hu.begin() + r.nv, hu.end());
+            for (double& v : r.phi) v *= scale;
+            for (double& v : r.dphi) v *= scale;
+            bool finite = std::isfinite(r.energy);
+            for (double v : hu) finite = finite && std::isfinite(v);
+            if (!finite)
+                fail_request(r, HOBI_E_NUMERIC, "non-finite solution");
+            else if (!converged)
+                fail_request(r, HOBI_E_NOCONV, "GMRES reached max_iter");
+        }
+    }
+    r.stats.iterations = r.k;
+    r.stats.converged = converged ? 1 : 0;
+    r.stats.est_residual = r.est;
+    r.stats.ms_solve = std::chrono::duration<double, std::milli>(Clock::now() - r.t_admit).count();
+    free_request_device(r);
+}
+
+hipError_t ensure_capacity(hobi_server sv, size_t ndesc, size_t nitems) {
+    hipError_t e = hipSuccess;
+    if (ndesc > sv->cap_desc) {
+        size_t cap = std::max<size_t>(ndesc, 2 * sv->cap_desc);
+        if (sv->d_desc) (void)hipFree(sv->d_desc);
+        if (sv->h_desc) (void)hipHostFree(sv->h_desc);
+        if (sv->d_res) (void)hipFree(sv->d_res);
+        if (sv->h_res) (void)hipHostFree(sv->h_res);
+        if ((e = hipMalloc((void**)&sv->d_desc, cap * sizeof(ServeDesc))) != hipSuccess) return e;
+        if ((e = hipHostMalloc((void**)&sv->h_desc, cap * sizeof(ServeDesc))) != hipSuccess) return e;
+        if ((e = hipMalloc((void**)&sv->d_res, (cap + 1) * sizeof(double))) != hipSuccess) return e;
+        if ((e = hipHostMalloc((void**)&sv->h_res, (cap + 1) * sizeof(double))) != hipSuccess) return e;
+        sv->cap_desc = cap;
+        sv->graph_dirty = true;
+    }
+    if (nitems > sv->cap_items) {
+        size_t cap = std::max<size_t>(nitems, 2 * sv->cap_items);
+        if (sv->d_items) (void)hipFree(sv->d_items);
+        if (sv->h_items) (void)hipHostFree(sv->h_items);
+        if ((e = hipMalloc((void**)&sv->d_items, cap * sizeof(ServeItem))) != hipSuccess) return e;
+        if ((e = hipHostMalloc((void**)&sv->h_items, cap * sizeof(ServeItem))) != hipSuccess) return e;
+        sv->cap_items = cap;
+        sv->graph_dirty = true;
+    }
+    return e;
+}
+
+// One tick: every active request advances one Arnoldi step.
+hobi_status tick(hobi_server sv) {
+    hipStream_t s = sv->ctx->stream;
+    const size_t na = sv->active.size();
+    // work lists: gather items, then pair items, then combine items
+    size_t ng = 0, np = 0, nc = 0;
+    for (auto& rp : sv->active) {
+        const DeviceProblem& d = rp->pb->d;
+        ng += (d.nn + kServeBlock - 1) / kServeBlock;
+        np += (size_t)rp->plan.target_blocks * rp->plan.chunks;
+        nc += (d.nv + kServeBlock - 1) / kServeBlock;
+    }
+    // the three lists live at fixed offsets (thirds of the item buffer), so that the
+    // captured launches stay valid until the buffer has to grow
+    hipError_t e = ensure_capacity(sv, na, 3 * std::max(std::max(ng, np), nc));
+    if (e != hipSuccess) return host_fail(sv->ctx, HOBI_E_OOM, "server work-list allocation failed");
+    const size_t t3 = sv->cap_items / 3;
+    ServeItem* gi = sv->h_items;
+    ServeItem* pi = sv->h_items + t3;
+    ServeItem* ci = sv->h_items + 2 * t3;
+    size_t a = 0, b = 0, cc = 0;
+    for (size_t q = 0; q < na; ++q) {
+        Request& r = *sv->active[q];
+        const DeviceProblem& d = r.pb->d;
+        const int n = 2 * r.nv;
+        ServeDesc& sd = sv->h_desc[q];
+        sd.u = r.V + (size_t)r.k * n;
+        sd.y = r.V + (size_t)(r.k + 1) * n;
+        sd.tri = d.tri;
+        sd.w = d.w;
+        sd.node64 = d.node64;
+        sd.node32 = d.node32;
+        sd.node_vid = d.node_vid;
+        sd.tgt32 = d.tgt32;
+        sd.tgt64 = d.tgt64;
+        sd.partial = r.partial;
+        sd.inc_off = d.inc_off;
+        sd.inc_ent = d.inc_ent;
+        sd.coef = d.coef;
+        sd.kappa = d.kappa;
+        sd.eps = d.eps;
+        sd.kl2n = (float)(-d.kappa * 1.4426950408889634074);
+        sd.nv = d.nv;
+        sd.nv_pad = d.nv_pad;
+        sd.nn = d.nn;
+        sd.chunk = r.plan.chunk;
+        sd.chunks = r.plan.chunks;
+        sd.mixed = r.prm.precision == HOBI_MIXED ? 1 : 0;
+        sd.pad = 0;
+        for (int blk = 0; blk < (d.nn + kServeBlock - 1) / kServeBlock; ++blk) gi[a++] = ServeItem{(int)q, blk, 0, 0};
+        for (int ch = 0; ch < r.plan.chunks; ++ch)
+            for (int tb = 0; tb < r.plan.target_blocks; ++tb) pi[b++] = ServeItem{(int)q, tb, ch, 0};
+        for (int blk = 0; blk < (d.nv + kServeBlock - 1) / kServeBlock; ++blk) ci[cc++] = ServeItem{(int)q, blk, 0, 0};
+    }
+    sv->h_counts[0] = (int)ng;
+    sv->h_counts[1] = (int)np;
+    sv->h_counts[2] = (int)nc;
+    if ((e = hipMemcpyAsync(sv->d_desc, sv->h_desc, na * sizeof(ServeDesc), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(sv->d_items, gi, ng * sizeof(ServeItem), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(sv->d_items + t3, pi, np * sizeof(ServeItem), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(sv->d_items + 2 * t3, ci, nc * sizeof(ServeItem), hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(sv->d_counts, sv->h_counts, 3 * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
+    const ServeItem* dg = sv->d_items;
+    const ServeItem* dp = sv->d_items + t3;
+    const ServeItem* dc = sv->d_items + 2 * t3;
+    if (sv->use_graph) {
+        if (sv->graph_dirty || !sv->graph_exec) {
+            if (sv->graph_exec) (void)hipGraphExecDestroy(sv->graph_exec);
+            if (sv->graph) (void)hipGraphDestroy(sv->graph);
+            sv->graph_exec = nullptr;
+            sv->graph = nullptr;
+            if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
+            const hipError_t le =
+                launch_batched_matvec(sv->d_desc, dg, sv->d_counts, dp, sv->d_counts + 1, dc, sv->d_counts + 2, s);
+            e = hipStreamEndCapture(s, &sv->graph);
+            if (le != hipSuccess || e != hipSuccess)
+                return host_fail(sv->ctx, HOBI_E_HIP, "graph capture of the batched matvec failed");
+            if ((e = hipGraphInstantiate(&sv->graph_exec, sv->graph, nullptr, nullptr, 0)) != hipSuccess)
+                return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
+            sv->graph_dirty = false;
+        }
+        if ((e = hipGraphLaunch(sv->graph_exec, s)) != hipSuccess)
+            return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
+    } else if ((e = launch_batched_matvec(sv->d_desc, dg, sv->d_counts, dp, sv->d_counts + 1, dc, sv->d_counts + 2,
+                                          s)) != hipSuccess) {
+        return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
+    }
+    // per-request Gram-Schmidt (two passes), normalisation and Givens update
+    for (size_t q = 0; q < na; ++q) {
+        Request& r = *sv->active[q];
+        const int n = 2 * r.nv, j = r.k;
+        double* w = r.V + (size_t)(j + 1) * n;
+        for (int pass = 0; pass < 2; ++pass) {
+            double* h = pass == 0 ? r.h1 : r.h2;
+            if ((e = launch_dots(r.V, n, j + 1, w, n, r.dpart, s)) != hipSuccess ||
+                (e = launch_reduce(r.dpart, j + 1, h, 0, s)) != hipSuccess ||
+                (e = launch_multi_axpy(r.V, n, j + 1, h, -1.0, w, n, s)) != hipSuccess)
+                return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
+        }
+        if ((e = launch_dots(w, 0, 1, w, n, r.dpart, s)) != hipSuccess ||
+            (e = launch_reduce(r.dpart, 1, r.hn, 1, s)) != hipSuccess ||
+            (e = launch_scale_copy(w, r.hn, w, n, s)) != hipSuccess ||
+            (e = launch_givens(r.H, r.m + 1, j, r.h1, r.h2, r.hn, r.cs, r.sn, r.g, r.bnorm, sv->d_res + q, s)) !=
+                hipSuccess)
+            return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
+    }
+    if ((e = hipMemcpyAsync(sv->h_res, sv->d_res, na * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
+    return HOBI_OK;
+}
+
+void worker_main(hobi_server sv) {
+    (void)hipSetDevice(sv->device);
+    while (true) {
+        std::vector<std::unique_ptr<Request>> admitted;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            if (sv->active.empty())
+                sv->cv.wait(lk, [&] { return sv->stop || !sv->pending.empty(); });
+            if (sv->stop) break;
+            // FIFO admission while a slot is free and the head fits in the budget
+            while (!sv->pending.empty() && (int)(sv->active.size() + admitted.size()) < sv->max_slots &&
+                   sv->in_use + sv->pending.front()->footprint <= sv->budget) {
+                sv->in_use += sv->pending.front()->footprint;
+                admitted.push_back(std::move(sv->pending.front()));
+                sv->pending.pop_front();
+            }
+            sv->st.pending = (int32_t)sv->pending.size();
+            sv->st.bytes_in_use = sv->in_use;
+            sv->st.peak_bytes = std::max(sv->st.peak_bytes, sv->in_use);
+        }
+        const auto t0 = Clock::now();
+        std::vector<std::unique_ptr<Request>> finished;
+        for (auto& r : admitted) {
+            if (admit(sv, *r) != HOBI_OK || r->bnorm == 0.0) {
+                if (r->status == HOBI_OK) finish(sv, *r, true);   // b = 0: u = 0
+                else free_request_device(*r);
+                finished.push_back(std::move(r));
+            } else {
+                sv->active.push_back(std::move(r));
+            }
+        }
+        if (!sv->active.empty()) {
+            hobi_status ts = tick(sv);
+            sv->batch_sum += (double)sv->active.size();
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                sv->st.ticks += 1;
+            }
+            std::vector<std::unique_ptr<Request>> still;
+            for (size_t q = 0; q < sv->active.size(); ++q) {
+                auto& r = sv->active[q];
+                if (ts != HOBI_OK) {
+                    fail_request(*r, ts, sv->ctx->err);
+                    free_request_device(*r);
+                    finished.push_back(std::move(r));
+                    continue;
+                }
+                const double res = sv->h_res[q];
+                r->k += 1;
+                r->est = res;
+                if (!std::isfinite(res)) {
+                    fail_request(*r, HOBI_E_NUMERIC, "GMRES residual is not finite");
+                    free_request_device(*r);
+                    finished.push_back(std::move(r));
+                } else if (res <= r->prm.rtol || r->k >= r->m) {
+                    finish(sv, *r, res <= r->prm.rtol);
+                    finished.push_back(std::move(r));
+                } else {
+                    still.push_back(std::move(r));
+                }
+            }
+            sv->active = std::move(still);
+        }
+        const double busy = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->st.busy_ms += busy;
+            for (auto& r : finished) {
+                sv->in_use -= r->footprint;
+                if (r->status == HOBI_OK || r->status == HOBI_E_NOCONV) sv->st.completed += 1;
+                else sv->st.failed += 1;
+                sv->in_flight.erase(r->ticket);
+                sv->done[r->ticket] = std::move(r);
+            }
+            sv->st.active = (int32_t)sv->active.size();
+            sv->st.bytes_in_use = sv->in_use;
+            sv->st.mean_batch = sv->st.ticks ? sv->batch_sum / (double)sv->st.ticks : 0.0;
+        }
+    }
+    for (auto& r : sv->active) free_request_device(*r);
+    sv->active.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+hobi_status hobi_server_create(hobi_ctx ctx, int64_t hbm_budget_bytes, int32_t max_slots, int32_t use_graph,
+                               hobi_server* out) {
+    if (!ctx || !out) return HOBI_E_ARG;
+    *out = nullptr;
+    if (hbm_budget_bytes <= 0 || max_slots < 1) return host_fail(ctx, HOBI_E_ARG, "budget and slots must be positive");
+    hobi_server sv = new hobi_server_s();
+    sv->device = ctx->device;
+    sv->budget = hbm_budget_bytes;
+    sv->max_slots = max_slots;
+    sv->use_graph = use_graph != 0;
+    if (hobi_ctx_create(ctx->device, nullptr, &sv->ctx) != HOBI_OK) {
+        delete sv;
+        return host_fail(ctx, HOBI_E_HIP, "could not create the server stream");
+    }
+    if (hipMalloc((void**)&sv->d_counts, 4 * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void**)&sv->h_counts, 4 * sizeof(int)) != hipSuccess ||
+        ensure_capacity(sv, 16, 3 * 4096) != hipSuccess) {
+        hobi_server_destroy(sv);
+        return host_fail(ctx, HOBI_E_OOM, "server buffers");
+    }
+    sv->worker = std::thread(worker_main, sv);
+    *out = sv;
+    return HOBI_OK;
+}
+
+hobi_status hobi_server_submit(hobi_server sv, int32_t nv, const double* xyz, const double* nrm, int32_t nf,
+                               const int32_t* tri, int32_t nc, const double* qpos, const double* q,
+                               const hobi_params* params, uint64_t* ticket) {
+    if (!sv || !ticket) return HOBI_E_ARG;
+    if (!xyz || !nrm || !tri || !qpos || !q || nv < 4 || nf < 4 || nc < 1) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->last_error = "bad sizes or NULL inputs";
+        return HOBI_E_ARG;
+    }
+    auto r = std::make_unique<Request>();
+    r->nv = nv;
+    r->nf = nf;
+    r->nc = nc;
+    r->xyz.assign(xyz, xyz + 3 * (size_t)nv);
+    r->nrm.assign(nrm, nrm + 3 * (size_t)nv);
+    r->tri.assign(tri, tri + 3 * (size_t)nf);
+    r->qpos.assign(qpos, qpos + 3 * (size_t)nc);
+    r->q.assign(q, q + nc);
+    hobi_params_default(&r->prm);
+    if (params) r->prm = *params;
+    r->prm.restart = r->prm.max_iter;
+    r->footprint = footprint_bytes(nv, nf, nc, std::max(1, r->prm.max_iter), r->prm.precision == HOBI_MIXED);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (r->footprint > sv->budget) {
+        sv->last_error = "request footprint exceeds the server budget";
+        return HOBI_E_OOM;
+    }
+    r->ticket = sv->next_ticket++;
+    *ticket = r->ticket;
+    sv->in_flight.insert(r->ticket);
+    sv->pending.push_back(std::move(r));
+    sv->st.submitted += 1;
+    sv->st.pending = (int32_t)sv->pending.size();
+    sv->cv.notify_one();
+    return HOBI_OK;
+}
+
+hobi_status hobi_server_poll(hobi_server sv, uint64_t ticket, double* phi, double* dphi, double* e_sol,
+                             hobi_stats* st) {
+    if (!sv) return HOBI_E_ARG;
+    std::unique_ptr<Request> r;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        auto it = sv->done.find(ticket);
+        if (it == sv->done.end()) {
+            if (sv->in_flight.count(ticket)) return HOBI_E_BUSY;
+            sv->last_error = "unknown ticket";
+            return HOBI_E_ARG;
+        }
+        r = std::move(it->second);
+        sv->done.erase(it);
+        if (r->status != HOBI_OK) sv->last_error = r->message;
+    }
+    if (phi && !r->phi.empty()) std::memcpy(phi, r->phi.data(), sizeof(double) * r->nv);
+    if (dphi && !r->dphi.empty()) std::memcpy(dphi, r->dphi.data(), sizeof(double) * r->nv);
+    if (e_sol) *e_sol = r->energy;
+    if (st) *st = r->stats;
+    return r->status;
+}
+
+hobi_status hobi_server_get_stats(hobi_server sv, hobi_server_stats* out) {
+    if (!sv || !out) return HOBI_E_ARG;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    *out = sv->st;
+    return HOBI_OK;
+}
+
+const char* hobi_server_last_error(hobi_server sv) { return sv ? sv->last_error.c_str() : "null server"; }
+
+void hobi_server_destroy(hobi_server sv) {
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv.notify_all();
+    if (sv->worker.joinable()) sv->worker.join();
+    if (sv->ctx) (void)hipStreamSynchronize(sv->ctx->stream);
+    if (sv->graph_exec) (void)hipGraphExecDestroy(sv->graph_exec);
+    if (sv->graph) (void)hipGraphDestroy(sv->graph);
+    if (sv->d_desc) (void)hipFree(sv->d_desc);
+    if (sv->d_items) (void)hipFree(sv->d_items);
+    if (sv->d_counts) (void)hipFree(sv->d_counts);
+    if (sv->d_res) (void)hipFree(sv->d_res);
+    if (sv->h_desc) (void)hipHostFree(sv->h_desc);
+    if (sv->h_items) (void)hipHostFree(sv->h_items);
+    if (sv->h_counts) (void)hipHostFree(sv->h_counts);
+    if (sv->h_res) (void)hipHostFree(sv->h_res);
+    if (sv->ctx) hobi_ctx_destroy(sv->ctx);
+    delete sv;
+}
+
+}  // extern "C"

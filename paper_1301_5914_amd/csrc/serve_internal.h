@@ -1,0 +1,50 @@
+// Device-side descriptors of the request server's batched matvec.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hobi_device.h"
+
+namespace hobi {
+
+constexpr int kServeBlock = 256;       // threads per block of the batched kernels
+constexpr int kServeTpl32 = 4;        // targets per lane of served FP32 tiles
+constexpr int kServeTpl64 = 2;        // targets per lane of served FP64 tiles
+constexpr int kServeGridPair = 2048;  // fixed grids: the kernels walk the item lists
+constexpr int kServeGridSmall = 1024;
+
+// One active request as the batched kernels see it during one tick.
+struct ServeDesc {
+    const double* u;        // Krylov vector v_k (internal order)
+    double* y;              // output A v_k (the next Krylov slot)
+    const int* tri;
+    const double* w;
+    NodeD* node64;
+    NodeF* node32;
+    const int4* node_vid;
+    const float* tgt32;
+    const double* tgt64;
+    double* partial;        // [chunks][2][nv_pad]
+    const int* inc_off;
+    const int* inc_ent;
+    const double* coef;
+    double kappa;
+    double eps;
+    float kl2n;             // -kappa * log2(e)
+    int nv, nv_pad, nn;
+    int chunk, chunks;
+    int mixed;
+    int pad;
+};
+
+// One unit of work: request `req`; (a, b) = (target block, chunk) for the pair kernel,
+// (node or vertex block, 0) for gather and combine.
+struct ServeItem {
+    int req, a, b, pad;
+};
+
+hipError_t launch_batched_matvec(const ServeDesc* desc, const ServeItem* gather_items, const int* n_gather,
+                                 const ServeItem* pair_items, const int* n_pair, const ServeItem* comb_items,
+                                 const int* n_comb, hipStream_t s);
+
+}  // namespace hobi

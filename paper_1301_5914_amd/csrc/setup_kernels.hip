@@ -3,9 +3,8 @@
 //   regular_kernel    -- 4-point Gauss-Radau nodes, normals and weight*Jacobian
 //   targets_kernel    -- SoA target arrays (vertex positions and normals)
 //   singular_kernel   -- 16-point Duffy/Gauss-Legendre coefficients of the triangles
-//                        incident to each vertex (Section 2.3, eqdbef5/eqdbef6), minus
-//                        the 4-point terms of the same triangles, which the dense pair
-//                        sum includes
+//                        incident to each vertex (Section 2.3, eqdbef5/eqdbef6); the
+//                        dense pair sum skips those triangles' regular nodes
 //   sources_kernel    -- S1, S2 at every vertex (eq. Eq_Ss)
 #include "hobi_internal.h"
 
@@ -50,8 +49,9 @@ __global__ void patch_kernel(const double* __restrict__ xyz, const double* __res
     err[j] = ok ? 0 : 1;   // per-triangle flag, checked on the host
 }
 
-__global__ void regular_kernel(const double* __restrict__ patch, int nf, NodeD* __restrict__ node64,
-                               NodeF* __restrict__ node32, double* __restrict__ w, double cx,
+__global__ void regular_kernel(const double* __restrict__ patch, const int* __restrict__ tri, int nf,
+                               NodeD* __restrict__ node64, NodeF* __restrict__ node32,
+                               int4* __restrict__ node_vid, double* __restrict__ w, double cx,
                                double cy, double cz) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= 4 * nf) return;
@@ -75,7 +75,11 @@ __global__ void regular_kernel(const double* __restrict__ patch, int nf, NodeD* 
     f.nx = (float)n.x;
     f.ny = (float)n.y;
     f.nz = (float)n.z;
+    f.v0 = tri[3 * j];
+    f.v1 = tri[3 * j + 1];
+    f.v2 = tri[3 * j + 2];
     node32[idx] = f;
+    node_vid[idx] = make_int4(tri[3 * j], tri[3 * j + 1], tri[3 * j + 2], 0);
     w[idx] = wm * J;
 }
 
@@ -116,7 +120,6 @@ __device__ inline void kernels4(Vec3 x, Vec3 nx, Vec3 y, Vec3 ny, double kappa, 
 // row 1 -> K3 / K4; b = slot of the relabelled triangle (vertex tri[j][(k+b)%3]).
 __global__ void singular_kernel(const double* __restrict__ xyz, const double* __restrict__ nrm,
                                 const int* __restrict__ tri, const double* __restrict__ patch,
-                                const NodeD* __restrict__ node64, const double* __restrict__ w,
                                 int nf, double kappa, double eps, double* __restrict__ coef) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= 3 * nf) return;
@@ -148,24 +151,6 @@ __global__ void singular_kernel(const double* __restrict__ xyz, const double* __
                 c[6 + q] += WL * K[2];
                 c[9 + q] += WL * K[3];
             }
-        }
-    }
-    // remove the 4-point terms of this triangle that the dense pair sum adds
-    for (int m = 0; m < 4; ++m) {
-        double r, s, wm;
-        gauss_radau4(m, &r, &s, &wm);
-        const NodeD nd = node64[4 * j + m];
-        double K[4];
-        kernels4(x, nx, v3(nd.x, nd.y, nd.z), v3(nd.nx, nd.ny, nd.nz), kappa, eps, K);
-        const double om = w[4 * j + m];
-        const double Ls[3] = {1.0 - r - s, r, s};   // stored vertex order
-        for (int sb = 0; sb < 3; ++sb) {
-            const int q = (sb - k + 3) % 3;           // slot in the relabelled order
-            const double WL = om * Ls[sb];
-            c[0 + q] -= WL * K[0];
-            c[3 + q] -= WL * K[1];
-            c[6 + q] -= WL * K[2];
-            c[9 + q] -= WL * K[3];
         }
     }
     double* out = coef + 12 * (size_t)e;
@@ -201,8 +186,8 @@ hipError_t launch_patch(const DeviceProblem& p, int* d_err, hipStream_t s) {
 }
 
 hipError_t launch_regular_nodes(const DeviceProblem& p, hipStream_t s) {
-    hipLaunchKernelGGL(regular_kernel, dim3(nblk(4L * p.nf, 128)), dim3(128), 0, s, p.patch, p.nf,
-                       p.node64, p.node32, p.w, p.center[0], p.center[1], p.center[2]);
+    hipLaunchKernelGGL(regular_kernel, dim3(nblk(4L * p.nf, 128)), dim3(128), 0, s, p.patch, p.tri, p.nf,
+                       p.node64, p.node32, p.node_vid, p.w, p.center[0], p.center[1], p.center[2]);
     return hipGetLastError();
 }
 
@@ -214,7 +199,7 @@ hipError_t launch_targets(const DeviceProblem& p, hipStream_t s) {
 
 hipError_t launch_singular(const DeviceProblem& p, hipStream_t s) {
     hipLaunchKernelGGL(singular_kernel, dim3(nblk(3L * p.nf, 64)), dim3(64), 0, s, p.xyz, p.nrm, p.tri,
-                       p.patch, p.node64, p.w, p.nf, p.kappa, p.eps, p.coef);
+                       p.patch, p.nf, p.kappa, p.eps, p.coef);
     return hipGetLastError();
 }
 

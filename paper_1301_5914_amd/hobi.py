@@ -280,3 +280,96 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- request server
+
+class hobi_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("ticks", ctypes.c_int64), ("active", ctypes.c_int32), ("pending", ctypes.c_int32),
+                ("mean_batch", ctypes.c_double), ("bytes_in_use", ctypes.c_int64),
+                ("peak_bytes", ctypes.c_int64), ("busy_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_SIGS.update({
+    "hobi_server_create": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "hobi_server_submit": (ctypes.c_int, [_P, ctypes.c_int32, _D, _D, ctypes.c_int32, _I, ctypes.c_int32, _D, _D,
+                                          ctypes.POINTER(hobi_params), ctypes.POINTER(ctypes.c_uint64)]),
+    "hobi_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, _D, _D, _D, ctypes.POINTER(hobi_stats)]),
+    "hobi_server_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(hobi_server_stats)]),
+    "hobi_server_last_error": (ctypes.c_char_p, [_P]),
+    "hobi_server_destroy": (None, [_P]),
+})
+
+
+class Server:
+    """Continuous-batching request server on one device (hobi_server_* in the C ABI)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 8 << 30, max_slots: int = 64,
+                 use_graph: bool = True):
+        h = _P()
+        _check(ctx.handle, lib().hobi_server_create(ctx.handle, int(hbm_budget_bytes), int(max_slots),
+                                                    1 if use_graph else 0, ctypes.byref(h)))
+        self.ctx = ctx
+        self.handle = h
+        self._nv = {}
+
+    def _err(self, st):
+        msg = lib().hobi_server_last_error(self.handle)
+        raise HobiError(st, msg.decode() if msg else "")
+
+    def submit(self, prob, rtol=1e-6, max_iter=300, precision=HOBI_MIXED, eps1=None, eps2=None,
+               kappa=None) -> int:
+        xyz = _f64(prob.xyz).reshape(-1, 3)
+        nrm = _f64(prob.nrm).reshape(-1, 3)
+        tri = np.ascontiguousarray(np.asarray(prob.tri, dtype=np.int32).reshape(-1, 3))
+        qpos = _f64(prob.qpos).reshape(-1, 3)
+        q = _f64(prob.q).ravel()
+        p = hobi_params_default()
+        p.eps1 = prob.eps1 if eps1 is None else eps1
+        p.eps2 = prob.eps2 if eps2 is None else eps2
+        p.kappa = prob.kappa if kappa is None else kappa
+        p.rtol, p.max_iter, p.restart, p.precision = rtol, max_iter, max_iter, precision
+        t = ctypes.c_uint64()
+        st = lib().hobi_server_submit(self.handle, xyz.shape[0], _dptr(xyz), _dptr(nrm), tri.shape[0],
+                                      tri.ctypes.data_as(_I), q.shape[0], _dptr(qpos), _dptr(q),
+                                      ctypes.byref(p), ctypes.byref(t))
+        if st != 0:
+            self._err(st)
+        self._nv[t.value] = xyz.shape[0]
+        return t.value
+
+    def poll(self, ticket: int, raise_errors: bool = True):
+        """None while the request is waiting or running, else its result dict."""
+        nv = self._nv.get(ticket)
+        phi = np.empty(nv) if nv else None
+        dphi = np.empty(nv) if nv else None
+        e = ctypes.c_double()
+        st = hobi_stats()
+        code = lib().hobi_server_poll(self.handle, ticket, _dptr(phi), _dptr(dphi), ctypes.byref(e),
+                                      ctypes.byref(st))
+        if code == 8:
+            return None
+        self._nv.pop(ticket, None)
+        if code not in (0, 4) and raise_errors:
+            self._err(code)
+        return dict(phi=phi, dphi=dphi, energy=e.value, stats=st.as_dict(), status=STATUS[code])
+
+    def stats(self):
+        s = hobi_server_stats()
+        lib().hobi_server_get_stats(self.handle, ctypes.byref(s))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().hobi_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,136 @@
+"""The request server (continuous batching) through the C ABI: served results equal the
+single-problem path, every request's result is bit-for-bit the same alone and in a mix,
+admission respects the memory budget, graph replays equal eager launches, errors surface
+per request."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1301_5914_amd import hobi, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return hobi.Context(0)
+
+
+def _wait(sv, tickets, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t not in out:
+                r = sv.poll(t, raise_errors=False)
+                if r is not None:
+                    out[t] = r
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"{len(out)} of {len(tickets)} requests finished")
+        time.sleep(0.002)
+    return out
+
+
+def _mix():
+    return [
+        (inputs.kirkwood_offcenter(2), dict(precision=hobi.HOBI_MIXED)),
+        (inputs.kirkwood_centered(3), dict(precision=hobi.HOBI_FP64)),
+        (inputs.kirkwood_offcenter(3, kappa=0.0, eps1=2.0), dict(precision=hobi.HOBI_MIXED)),
+        (inputs.molecule(20, seed=4), dict(precision=hobi.HOBI_MIXED, eps1=4.0)),
+        (inputs.kirkwood_offcenter(1, kappa=0.1257), dict(precision=hobi.HOBI_FP64, kappa=0.0)),
+    ]
+
+
+def test_served_equals_single_problem_path(ctx):
+    """Alone in the server, a small request (same tile shape as the single-problem path)
+    gives the single-problem solve's bits."""
+    sv = hobi.Server(ctx, hbm_budget_bytes=2 << 30, max_slots=8)
+    for prec in (hobi.HOBI_FP64, hobi.HOBI_MIXED):
+        p = inputs.kirkwood_offcenter(2)
+        t = sv.submit(p, precision=prec, max_iter=200)
+        r = _wait(sv, [t])[t]
+        ref = hobi.Problem.from_inputs(ctx, p, precision=prec, max_iter=200, restart=200).solve()
+        assert r["status"] == "HOBI_OK"
+        assert r["stats"]["iterations"] == ref["stats"]["iterations"]
+        np.testing.assert_array_equal(r["phi"], ref["phi"])
+        np.testing.assert_array_equal(r["dphi"], ref["dphi"])
+        assert r["energy"] == ref["energy"]
+    sv.close()
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_alone_equals_in_the_mix(ctx, use_graph):
+    mix = _mix()
+    sv = hobi.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=16, use_graph=use_graph)
+    alone = []
+    for p, kw in mix:
+        t = sv.submit(p, **kw)
+        alone.append(_wait(sv, [t])[t])
+    # all together, with staggered arrivals while others are running
+    tickets = []
+    for i, (p, kw) in enumerate(mix):
+        tickets.append(sv.submit(p, **kw))
+        if i % 2 == 1:
+            time.sleep(0.01)
+    mixed = _wait(sv, tickets)
+    st = sv.stats()
+    print("server stats", st)
+    assert st["mean_batch"] > 1.0
+    for a, t in zip(alone, tickets):
+        b = mixed[t]
+        assert a["status"] == b["status"] == "HOBI_OK"
+        np.testing.assert_array_equal(a["phi"], b["phi"])
+        np.testing.assert_array_equal(a["dphi"], b["dphi"])
+        assert a["energy"] == b["energy"]
+    sv.close()
+
+
+def test_graph_replays_equal_eager_launches(ctx):
+    mix = _mix()
+    res = {}
+    for use_graph in (True, False):
+        sv = hobi.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=16, use_graph=use_graph)
+        ts = [sv.submit(p, **kw) for p, kw in mix]
+        out = _wait(sv, ts)
+        res[use_graph] = [out[t] for t in ts]
+        sv.close()
+    for a, b in zip(res[True], res[False]):
+        np.testing.assert_array_equal(a["phi"], b["phi"])
+        assert a["energy"] == b["energy"]
+
+
+def test_admission_respects_the_budget(ctx):
+    p = inputs.kirkwood_offcenter(3)
+    probe = hobi.Server(ctx, hbm_budget_bytes=1 << 40, max_slots=1)
+    t = probe.submit(p)
+    _wait(probe, [t])
+    one = probe.stats()["peak_bytes"]
+    probe.close()
+    sv = hobi.Server(ctx, hbm_budget_bytes=int(1.5 * one), max_slots=8)
+    ts = [sv.submit(p) for _ in range(4)]
+    out = _wait(sv, ts)
+    st = sv.stats()
+    assert st["peak_bytes"] <= 1.5 * one and st["completed"] == 4
+    assert all(r["status"] == "HOBI_OK" for r in out.values())
+    with pytest.raises(hobi.HobiError) as e:
+        hobi.Server(ctx, hbm_budget_bytes=one // 2, max_slots=2).submit(p)
+    assert e.value.name == "HOBI_E_OOM"
+    sv.close()
+
+
+def test_errors_are_reported_per_request(ctx):
+    sv = hobi.Server(ctx, hbm_budget_bytes=2 << 30, max_slots=4)
+    good = inputs.kirkwood_offcenter(2)
+    bad = inputs.kirkwood_offcenter(2)
+    bad.tri = bad.tri.copy()
+    bad.tri[3] = bad.tri[3][::-1]
+    outside = inputs.kirkwood_offcenter(2)
+    outside.qpos = outside.qpos.copy()
+    outside.qpos[0] = [0.0, 0.0, 9.0]
+    ts = [sv.submit(good), sv.submit(bad), sv.submit(outside), sv.submit(good, max_iter=1, rtol=1e-14)]
+    out = _wait(sv, ts)
+    assert [out[t]["status"] for t in ts] == ["HOBI_OK", "HOBI_E_MESH", "HOBI_E_CHARGE_OUTSIDE", "HOBI_E_NOCONV"]
+    with pytest.raises(hobi.HobiError):
+        sv.poll(ts[0])   # already collected
+    sv.close()
