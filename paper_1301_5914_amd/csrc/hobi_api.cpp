@@ -297,7 +297,7 @@ hobi_status from_internal(hobi_problem pb, const double* src, int on_device, dou
 
 void free_problem(hobi_problem pb) {
     DeviceProblem& d = pb->d;
-    void* ptrs[] = {d.xyz, d.nrm, d.tri, d.qpos, d.q, d.qsoa, d.patch, d.node64, d.node32, d.node_vid, d.w,
+    void* ptrs[] = {d.xyz, d.nrm, d.tri, d.qpos, d.q, d.qsoa, d.patch, d.node64, d.node32, d.node_vid, d.blk_range, d.w,
                     d.tgt64, d.tgt32, d.inc_off, d.inc_ent, d.coef, d.rhs, d.partial,
                     pb->d_vperm, pb->u_in, pb->y_out, pb->phi_reac, pb->e_dev, pb->d_err};
     for (void* p : ptrs)
@@ -579,6 +579,7 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
     PCHK(dalloc(&d.node64, d.nn));
     PCHK(dalloc(&d.node32, d.nn));
     PCHK(dalloc(&d.node_vid, d.nn));
+    PCHK(dalloc(&d.blk_range, (d.nn + 63) / 64));
     PCHK(dalloc(&d.w, d.nn));
     PCHK(dalloc(&d.tgt64, 6 * (size_t)d.nv_pad));
     PCHK(dalloc(&d.tgt32, 6 * (size_t)d.nv_pad));
@@ -608,6 +609,18 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
     PCHK(hipMemcpyAsync(d.inc_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
     PCHK(hipMemcpyAsync(d.inc_ent, ent.data(), sizeof(int) * ent.size(), hipMemcpyHostToDevice, s));
     PCHK(hipMemcpyAsync(pb->d_vperm, vperm.data(), sizeof(int) * nv, hipMemcpyHostToDevice, s));
+    // vertex-id range of every 64-node block (16 consecutive triangles)
+    std::vector<int2> brange((d.nn + 63) / 64);
+    for (size_t b = 0; b < brange.size(); ++b) {
+        int lo = nv, hi = -1;
+        for (int t = (int)(16 * b); t < std::min(nf, (int)(16 * b + 16)); ++t)
+            for (int k = 0; k < 3; ++k) {
+                lo = std::min(lo, ht[3 * t + k]);
+                hi = std::max(hi, ht[3 * t + k]);
+            }
+        brange[b] = make_int2(lo, hi);
+    }
+    PCHK(hipMemcpyAsync(d.blk_range, brange.data(), sizeof(int2) * brange.size(), hipMemcpyHostToDevice, s));
     PCHK(hipMemsetAsync(d.node64, 0, sizeof(NodeD) * d.nn, s));
     PCHK(hipMemsetAsync(d.node32, 0, sizeof(NodeF) * d.nn, s));
     PCHK(hipStreamSynchronize(s));

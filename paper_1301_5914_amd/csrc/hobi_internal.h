@@ -40,6 +40,7 @@ struct DeviceProblem {
     NodeD* node64 = nullptr;                // [nn] positions, normals, Gamma, Phi
     NodeF* node32 = nullptr;                // [nn] FP32 copy (positions shifted by center)
     int4* node_vid = nullptr;               // [nn] vertex ids of each node's triangle (FP64 path)
+    int2* blk_range = nullptr;              // [nn/64] min, max vertex id per 64-node block
     double* w = nullptr;                    // [nn] quadrature weight * Jacobian
     double* tgt64 = nullptr;                // [6][nv_pad] SoA targets x,y,z,nx,ny,nz
     float* tgt32 = nullptr;                 // [6][nv_pad] FP32 SoA (shifted)

@@ -57,11 +57,12 @@ __global__ __launch_bounds__(kBlock) void pair_f64_kernel(
 
 template <int TPL, bool KAPPA0>
 __global__ __launch_bounds__(kBlock) void pair_f32_kernel(
-    const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes, int nn, int chunk,
-    float kappa, float kl2n, double* __restrict__ partial) {
+    const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes,
+    const int2* __restrict__ blk_range, int nn, int chunk, float kappa, float kl2n,
+    double* __restrict__ partial) {
     int tb, ch;
     xcd_block(&tb, &ch);
-    pair_f32_tile<TPL, KAPPA0>(tgt, nv_pad, nodes, nn, chunk, kappa, kl2n, partial, tb, ch);
+    pair_f32_tile<TPL, KAPPA0>(tgt, nv_pad, nodes, blk_range, nn, chunk, kappa, kl2n, partial, tb, ch);
 }
 
 __global__ void combine_kernel(const double* __restrict__ u, double* __restrict__ y, int nv, int nv_pad,
@@ -166,6 +167,7 @@ PairPlan make_plan(int n_pad, int nn, int tpl) {
     if (chunks > max_chunks) chunks = max_chunks;
     if (chunks < 1) chunks = 1;
     pl.chunk = (nn + chunks - 1) / chunks;
+    pl.chunk = (pl.chunk + kFold - 1) / kFold * kFold;   // node sub-blocks start on kFold
     pl.chunks = (nn + pl.chunk - 1) / pl.chunk;
     return pl;
 }
@@ -184,7 +186,7 @@ hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s) {
         const float kappa = (float)p.kappa, kl2n = (float)(-p.kappa * 1.4426950408889634074);
 #define HOBI_PAIR32(T, K0)                                                                        \
     hipLaunchKernelGGL((pair_f32_kernel<T, K0>), grid, dim3(kBlock), 0, s, p.tgt32, p.nv_pad, p.node32, \
-                       p.nn, pl.chunk, kappa, kl2n, p.partial)
+                       p.blk_range, p.nn, pl.chunk, kappa, kl2n, p.partial)
         if (pl.tpl == 8) {
             if (k0) HOBI_PAIR32(8, true); else HOBI_PAIR32(8, false);
         } else {

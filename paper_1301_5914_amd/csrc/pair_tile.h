@@ -43,14 +43,62 @@ __device__ __forceinline__ NodeD load_node(const const_as<NodeD>* p, int s) {
     return n;
 }
 
-// FP32 pairs, FP64 accumulation: running FP32 sums over kFold nodes are added into
-// FP64 per-target accumulators.  Per pair (kappa > 0): 38 VALU operations plus one
-// rsqrt and one exp2 on the transcendental unit.
+// FP32 pairs of nodes [sb, se) with the lane's TPL targets, added to FP32 running sums.
+// Per pair (kappa > 0): 38 VALU operations plus one rsqrt and one exp2 on the
+// transcendental unit; with MASK, pairs of a vertex with its own triangles' nodes (they
+// belong to the singular rule) are skipped, at 4 more operations per pair.
+template <int TPL, bool KAPPA0, bool MASK>
+__device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, int sb, int se, int t0,
+                                             const float (&tx)[TPL], const float (&ty)[TPL],
+                                             const float (&tz)[TPL], const float (&tnx)[TPL],
+                                             const float (&tny)[TPL], const float (&tnz)[TPL],
+                                             float kappa, float kl2n, float (&a1)[TPL], float (&a2)[TPL]) {
+    for (int s = sb; s < se; ++s) {
+        const NodeF n = load_node(cnodes, s);
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+            const float dx = tx[k] - n.x, dy = ty[k] - n.y, dz = tz[k] - n.z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            float rinv = __builtin_amdgcn_rsqf(r2);
+            if (MASK) {
+                const int t = t0 + k * kPairBlock;
+                if ((t == n.v0) | (t == n.v1) | (t == n.v2)) rinv = 0.0f;
+            }
+            const float rinv2 = rinv * rinv;
+            const float rinv3 = rinv2 * rinv;
+            const float dny = fmaf(dx, n.nx, fmaf(dy, n.ny, dz * n.nz));
+            const float dnx = fmaf(dx, tnx[k], fmaf(dy, tny[k], dz * tnz[k]));
+            if (KAPPA0) {
+                a1[k] = fmaf(dny * rinv3, n.pa, a1[k]);
+                a2[k] = fmaf(dnx * rinv3, n.ga, a2[k]);
+            } else {
+                const float nxy = fmaf(tnx[k], n.nx, fmaf(tny[k], n.ny, tnz[k] * n.nz));
+                const float r = r2 * rinv;
+                const float e = __builtin_amdgcn_exp2f(kl2n * r);         // exp(-kappa r)
+                const float zp1 = fmaf(kappa, r, 1.0f);                  // 1 + z
+                const float f1 = fmaf(-e, zp1, 1.0f);                    // 1 - e (1 + z)
+                const float f2 = fmaf(-e, fmaf(zp1, zp1 + 1.0f, 1.0f), 3.0f);   // 3 - e (3 + 3z + z^2)
+                // row 1: K1 Gamma + K2 Phi = (Gamma - e Gamma)/r + (d.ny)/r^3 (pa + pb f1)
+                a1[k] = fmaf(dny * rinv3, fmaf(n.pb, f1, n.pa), a1[k]);
+                a1[k] = fmaf(fmaf(-e, n.g, n.g), rinv, a1[k]);
+                // row 2: K3 Gamma + K4 Phi = [(d.nx)(ga + gb f1) + Phi ((d.nx)(d.ny) f2 / r^2 - (nx.ny) f1)] / r^3
+                const float w = fmaf(dnx * dny * f2, rinv2, -nxy * f1);
+                a2[k] = fmaf(rinv3, fmaf(w, n.p, dnx * fmaf(n.gb, f1, n.ga)), a2[k]);
+            }
+        }
+    }
+}
+
+// FP32 pairs, FP64 accumulation: running FP32 sums over kFold nodes are added into FP64
+// per-target accumulators.  blk_range[b] = (min, max) vertex id of the triangles of nodes
+// [64 b, 64 b + 64); a wave whose target ranges miss it runs the unmasked loop.
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void pair_f32_tile(
-    const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes, int nn, int chunk,
-    float kappa, float kl2n, double* __restrict__ partial, int tb, int ch) {
+    const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes,
+    const int2* __restrict__ blk_range, int nn, int chunk, float kappa, float kl2n,
+    double* __restrict__ partial, int tb, int ch) {
     const int t0 = tb * (kPairBlock * TPL) + threadIdx.x;
+    const int wave0 = tb * (kPairBlock * TPL) + (__builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63);
     float tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL];
     double d1[TPL], d2[TPL];
 #pragma unroll
@@ -65,47 +113,26 @@ __device__ __forceinline__ void pair_f32_tile(
         d1[k] = 0.0;
         d2[k] = 0.0;
     }
-    const int s0 = ch * chunk;
+    const int s0 = ch * chunk;                 // chunk is a multiple of kFold
     const int s1 = min(s0 + chunk, nn);
     const const_as<NodeF>* cnodes = as_constant(nodes);
+    const const_as<int2>* crange = as_constant(blk_range);
     for (int sb = s0; sb < s1; sb += kFold) {
         const int se = min(sb + kFold, s1);
+        const int vlo = crange[sb / kFold].x, vhi = crange[sb / kFold].y;
+        bool near = false;
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+            const int lo = wave0 + k * kPairBlock;
+            near |= (vhi >= lo) & (vlo <= lo + 63);
+        }
         float a1[TPL], a2[TPL];
 #pragma unroll
         for (int k = 0; k < TPL; ++k) a1[k] = a2[k] = 0.0f;
-        for (int s = sb; s < se; ++s) {
-            const NodeF n = load_node(cnodes, s);
-#pragma unroll
-            for (int k = 0; k < TPL; ++k) {
-                const float dx = tx[k] - n.x, dy = ty[k] - n.y, dz = tz[k] - n.z;
-                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                // pairs of a vertex with its own triangles' nodes belong to the singular rule
-                const int t = t0 + k * kPairBlock;
-                const bool own = (t == n.v0) | (t == n.v1) | (t == n.v2);
-                const float rinv = own ? 0.0f : __builtin_amdgcn_rsqf(r2);
-                const float rinv2 = rinv * rinv;
-                const float rinv3 = rinv2 * rinv;
-                const float dny = fmaf(dx, n.nx, fmaf(dy, n.ny, dz * n.nz));
-                const float dnx = fmaf(dx, tnx[k], fmaf(dy, tny[k], dz * tnz[k]));
-                if (KAPPA0) {
-                    a1[k] = fmaf(dny * rinv3, n.pa, a1[k]);
-                    a2[k] = fmaf(dnx * rinv3, n.ga, a2[k]);
-                } else {
-                    const float nxy = fmaf(tnx[k], n.nx, fmaf(tny[k], n.ny, tnz[k] * n.nz));
-                    const float r = r2 * rinv;
-                    const float e = __builtin_amdgcn_exp2f(kl2n * r);         // exp(-kappa r)
-                    const float zp1 = fmaf(kappa, r, 1.0f);                  // 1 + z
-                    const float f1 = fmaf(-e, zp1, 1.0f);                    // 1 - e (1 + z)
-                    const float f2 = fmaf(-e, fmaf(zp1, zp1 + 1.0f, 1.0f), 3.0f);   // 3 - e (3 + 3z + z^2)
-                    // row 1: K1 Gamma + K2 Phi = (Gamma - e Gamma)/r + (d.ny)/r^3 (pa + pb f1)
-                    a1[k] = fmaf(dny * rinv3, fmaf(n.pb, f1, n.pa), a1[k]);
-                    a1[k] = fmaf(fmaf(-e, n.g, n.g), rinv, a1[k]);
-                    // row 2: K3 Gamma + K4 Phi = [(d.nx)(ga + gb f1) + Phi ((d.nx)(d.ny) f2 / r^2 - (nx.ny) f1)] / r^3
-                    const float w = fmaf(dnx * dny * f2, rinv2, -nxy * f1);
-                    a2[k] = fmaf(rinv3, fmaf(w, n.p, dnx * fmaf(n.gb, f1, n.ga)), a2[k]);
-                }
-            }
-        }
+        if (near)
+            pair_f32_run<TPL, KAPPA0, true>(cnodes, sb, se, t0, tx, ty, tz, tnx, tny, tnz, kappa, kl2n, a1, a2);
+        else
+            pair_f32_run<TPL, KAPPA0, false>(cnodes, sb, se, t0, tx, ty, tz, tnx, tny, tnz, kappa, kl2n, a1, a2);
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
             d1[k] += (double)a1[k];

@@ -70,7 +70,7 @@ int64_t footprint_bytes(int nv, int nf, int nc, int m, bool mixed) {
     const PairPlan ps = make_plan((int)nv_pad, (int)nn, mixed ? kServeTpl32 : kServeTpl64);
     int64_t b = 0;
     b += 8 * (6LL * nv + 4LL * nc + 3 * nc_pad + 30LL * nf + 4 * nn + 12 * nv_pad + 36LL * nf + 2LL * nv + 4LL * nv);
-    b += (int64_t)sizeof(NodeD) * nn + (int64_t)sizeof(NodeF) * nn + 16 * nn;
+    b += (int64_t)sizeof(NodeD) * nn + (int64_t)sizeof(NodeF) * nn + 16 * nn + 8 * (nn / 64 + 1);
     b += 4 * (3LL * nf + nv + 1 + 3LL * nf + nv + nf) + 2LL * 4 * nv_pad;
     b += 8 * std::max<int64_t>(2 * nv_pad * std::max(p64.chunks, p32.chunks), nc_pad * pp.chunks);
     b += 8 * 2 * nv_pad * (int64_t)ps.chunks;
@@ -291,6 +291,7 @@ hobi_status tick(hobi_server sv) {
         sd.node64 = d.node64;
         sd.node32 = d.node32;
         sd.node_vid = d.node_vid;
+        sd.blk_range = d.blk_range;
         sd.tgt32 = d.tgt32;
         sd.tgt64 = d.tgt64;
         sd.partial = r.partial;

@@ -22,6 +22,7 @@ struct ServeDesc {
     NodeD* node64;
     NodeF* node32;
     const int4* node_vid;
+    const int2* blk_range;
     const float* tgt32;
     const double* tgt64;
     double* partial;        // [chunks][2][nv_pad]
