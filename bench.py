@@ -33,7 +33,7 @@ PEAK_NONPACKED_FP32 = 78.6                    # 256 CU x 4 SIMD x 16 lanes x 2 f
 # HBM bytes per launch of the FP32 pair kernel on the default workload (icosphere L6):
 # rocprofv3 FETCH_SIZE (x2.000) + WRITE_SIZE (x1.000), each scaled by a 256 MiB copy.
 # Only valid for the kernel build it was measured on; null for any other configuration.
-PAIR_F32_L6_TRAFFIC_BYTES = (26043.9 * 2.000 + 65856.0 * 1.000) * 1024
+PAIR_F32_L6_TRAFFIC_BYTES = (26101.5 * 2.000 + 65184.0 * 1.000) * 1024
 
 
 def workload(args):
@@ -179,6 +179,7 @@ def main():
     ap.add_argument("--atoms", type=int, default=500, help="atom count (molecule)")
     ap.add_argument("--seed", type=int, default=3, help="packing seed (molecule)")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--max-iter", type=int, default=400, help="GMRES iteration cap (unrestarted)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
@@ -215,7 +216,8 @@ def main():
     mixed = args.precision == "mixed"
     stream = torch.cuda.Stream()          # kernels and their timing events share this stream
     ctx = hobi.Context(0, stream=stream, profiling=True)
-    pb = hobi.Problem.from_inputs(ctx, prob, precision=hobi.HOBI_MIXED if mixed else hobi.HOBI_FP64)
+    pb = hobi.Problem.from_inputs(ctx, prob, precision=hobi.HOBI_MIXED if mixed else hobi.HOBI_FP64,
+                                  max_iter=args.max_iter, restart=args.max_iter)
 
     def step():
         pb.set_dielectric(prob.eps1, prob.eps2, prob.kappa)
