@@ -549,7 +549,7 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
     for (int k = 0; k < 3; ++k) d.center[k] = 0.5 * (lo[k] + hi[k]);
     d.nv_pad = round_up(nv, 2048);
     d.nc_pad = round_up(nc, 256);
-    d.plan64 = make_plan(d.nv_pad, d.nn, 2);
+    d.plan64 = make_plan(d.nv_pad, d.nn, kTpl64);
     d.plan32 = make_plan(d.nv_pad, d.nn, d.nv_pad >= 16384 ? 8 : 4);
     d.plan_pts = make_plan(d.nc_pad, d.nn, 1);
     d.partial_elems = std::max((size_t)2 * d.nv_pad * std::max(d.plan64.chunks, d.plan32.chunks),

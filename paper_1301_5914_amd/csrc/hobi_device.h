@@ -219,4 +219,38 @@ __device__ __forceinline__ void f012_f64(double z, double* f0, double* f1, doubl
     }
 }
 
+// exp(-z) for z >= 0 in FP64, without the special-case handling of the library routine
+// (the argument is finite and non-negative; it is clamped where exp(-z) would underflow).
+// Cody-Waite reduction z = n ln2 - t with |t| <= ln2 / 2 (ln2 split into a 21-bit head, so
+// n * head is exact, and a tail), then the Taylor polynomial of exp(t) to degree 12
+// (truncation below 2e-16 relative) and a scaling by 2^-n.
+__device__ __forceinline__ double exp_neg_f64(double z) {
+    constexpr double kLog2e = 1.4426950408889634;
+    constexpr double kLn2Hi = 0x1.62e42p-1;
+    constexpr double kLn2Lo = 0x1.fdf473de6af28p-22;
+    z = fmin(z, 708.0);
+    const double n = __builtin_rint(z * kLog2e);
+    double t = fma(n, kLn2Hi, -z);
+    t = fma(n, kLn2Lo, t);
+    // Estrin's scheme: pairs of terms, then powers t^2, t^4, t^8
+    constexpr double c2 = 1.0 / 2, c3 = 1.0 / 6, c4 = 1.0 / 24, c5 = 1.0 / 120, c6 = 1.0 / 720,
+                     c7 = 1.0 / 5040, c8 = 1.0 / 40320, c9 = 1.0 / 362880, c10 = 1.0 / 3628800,
+                     c11 = 1.0 / 39916800, c12 = 1.0 / 479001600;
+    const double t2 = t * t, t4 = t2 * t2, t8 = t4 * t4;
+    const double p01 = fma(t, 1.0, 1.0), p23 = fma(t, c3, c2), p45 = fma(t, c5, c4), p67 = fma(t, c7, c6),
+                 p89 = fma(t, c9, c8), p1011 = fma(t, c11, c10);
+    const double q03 = fma(t2, p23, p01), q47 = fma(t2, p67, p45), q811 = fma(t2, p1011, p89);
+    const double r07 = fma(t4, q47, q03), r812 = fma(t4, c12, q811);
+    const double p = fma(t8, r812, r07);
+    return __builtin_amdgcn_ldexp(p, -(int)n);
+}
+
+// 1 / sqrt(x) for finite x > 0 in FP64: hardware estimate, then one third-order
+// correction y (1 + h/2 + 3 h^2 / 8) with h = 1 - x y^2.
+__device__ __forceinline__ double rsqrt_f64(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double h = fma(-x * y, y, 1.0);
+    return fma(y * h, fma(h, 0.375, 0.5), y);
+}
+
 }  // namespace hobi

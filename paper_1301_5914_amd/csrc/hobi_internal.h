@@ -64,6 +64,7 @@ hipError_t launch_sources(const DeviceProblem& p, hipStream_t s);
 
 // ---- matvec kernels (pair_kernels.hip) ----
 PairPlan make_plan(int n_pad, int nn, int tpl);
+constexpr int kTpl64 = 2;   // targets per lane of the FP64 pair kernel
 hipError_t launch_gather(const DeviceProblem& p, const double* u, bool mixed, hipStream_t s);
 hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s);
 hipError_t launch_combine(const DeviceProblem& p, const double* u, double* y, bool mixed,

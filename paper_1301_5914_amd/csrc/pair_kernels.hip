@@ -48,11 +48,11 @@ __global__ void gather_kernel(const double* __restrict__ u, int nv, const int* _
 template <int TPL, bool KAPPA0>
 __global__ __launch_bounds__(kBlock) void pair_f64_kernel(
     const double* __restrict__ tgt, int nv_pad, const NodeD* __restrict__ nodes,
-    const int4* __restrict__ node_vid, int nn, int chunk, double kappa, double eps,
-    double* __restrict__ partial) {
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int nn, int chunk, double kappa,
+    double eps, double* __restrict__ partial) {
     int tb, ch;
     xcd_block(&tb, &ch);
-    pair_f64_tile<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, nn, chunk, kappa, eps, partial, tb, ch);
+    pair_f64_tile<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, nn, chunk, kappa, eps, partial, tb, ch);
 }
 
 template <int TPL, bool KAPPA0>
@@ -197,11 +197,11 @@ hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s) {
         const PairPlan& pl = p.plan64;
         dim3 grid(pl.target_blocks, pl.chunks);
         if (k0)
-            hipLaunchKernelGGL((pair_f64_kernel<2, true>), grid, dim3(kBlock), 0, s, p.tgt64, p.nv_pad,
-                               p.node64, p.node_vid, p.nn, pl.chunk, p.kappa, p.eps, p.partial);
+            hipLaunchKernelGGL((pair_f64_kernel<kTpl64, true>), grid, dim3(kBlock), 0, s, p.tgt64, p.nv_pad,
+                               p.node64, p.node_vid, p.blk_range, p.nn, pl.chunk, p.kappa, p.eps, p.partial);
         else
-            hipLaunchKernelGGL((pair_f64_kernel<2, false>), grid, dim3(kBlock), 0, s, p.tgt64, p.nv_pad,
-                               p.node64, p.node_vid, p.nn, pl.chunk, p.kappa, p.eps, p.partial);
+            hipLaunchKernelGGL((pair_f64_kernel<kTpl64, false>), grid, dim3(kBlock), 0, s, p.tgt64, p.nv_pad,
+                               p.node64, p.node_vid, p.blk_range, p.nn, pl.chunk, p.kappa, p.eps, p.partial);
     }
     return hipGetLastError();
 }

@@ -174,13 +174,79 @@ __device__ __forceinline__ void gather_node(int idx, const double* __restrict__ 
     }
 }
 
-// One tile of the FP64 dense pair sum (same layout as the FP32 tile).
+// FP64 pairs of nodes [sb, se) with the lane's TPL targets.  Per pair (kappa > 0) about 70
+// VALU operations: the exponential and reciprocal square root of hobi_device.h, the closed
+// forms of f0, f1, f2, and their power series where kappa r < kSeriesZ64 (rare: only nodes
+// near the wave's targets).  With MASK, pairs of a vertex with its own triangles' nodes are
+// skipped.
+template <int TPL, bool KAPPA0, bool MASK>
+__device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, const const_as<int4>* cvid, int sb,
+                                             int se, int t0, const double (&tx)[TPL], const double (&ty)[TPL],
+                                             const double (&tz)[TPL], const double (&tnx)[TPL],
+                                             const double (&tny)[TPL], const double (&tnz)[TPL], double kappa,
+                                             double eps, double (&a1)[TPL], double (&a2)[TPL]) {
+    const double em1 = eps - 1.0, ce3 = 1.0 - 1.0 / eps, ie = 1.0 / eps;
+    for (int s = sb; s < se; ++s) {
+        const NodeD nd = load_node(cnodes, s);
+        int4 vid = make_int4(-1, -1, -1, 0);
+        if (MASK) vid = load_vid(cvid, s);
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+            const double dx = tx[k] - nd.x, dy = ty[k] - nd.y, dz = tz[k] - nd.z;
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            double rinv = rsqrt_f64(r2);
+            if (MASK) {
+                const int t = t0 + k * kPairBlock;
+                if ((t == vid.x) | (t == vid.y) | (t == vid.z)) rinv = 0.0;
+            }
+            const double rinv2 = rinv * rinv;
+            const double rinv3 = rinv2 * rinv;
+            const double dny = fma(dx, nd.nx, fma(dy, nd.ny, dz * nd.nz));
+            const double dnx = fma(dx, tnx[k], fma(dy, tny[k], dz * tnz[k]));
+            if (KAPPA0) {
+                a1[k] = fma(em1 * dny * rinv3, nd.p, a1[k]);
+                a2[k] = fma(-ce3 * dnx * rinv3, nd.g, a2[k]);
+            } else {
+                const double nxy = fma(tnx[k], nd.nx, fma(tny[k], nd.ny, tnz[k] * nd.nz));
+                const double z = kappa * (r2 * rinv);
+                const double e = exp_neg_f64(z);
+                double f0 = 1.0 - e;
+                double f1 = fma(-e, 1.0 + z, 1.0);
+                double f2 = fma(-e, fma(z, z + 3.0, 3.0), 3.0);
+                if (z < kSeriesZ64) {
+                    // Horner in z, terms k = 1..12 (f0) and k = 2..12 (f1, f2); truncation < 1e-17 rel.
+                    constexpr SeriesTable T = series_table();
+                    double s0 = T.f0[12], s1 = T.f1[12], s2 = T.f2[12];
+#pragma unroll
+                    for (int j = 11; j >= 2; --j) {
+                        s0 = fma(s0, z, T.f0[j]);
+                        s1 = fma(s1, z, T.f1[j]);
+                        s2 = fma(s2, z, T.f2[j]);
+                    }
+                    f0 = fma(s0, z, T.f0[1]) * z;
+                    f1 = s1 * z * z;
+                    f2 = s2 * z * z;
+                }
+                const double K1 = f0 * rinv;
+                const double K2 = dny * rinv3 * fma(-eps, f1, em1);
+                const double K3 = -dnx * rinv3 * fma(f1, ie, ce3);
+                const double K4 = fma(dnx * dny * f2, rinv2, -nxy * f1) * rinv3;
+                a1[k] = fma(K1, nd.g, fma(K2, nd.p, a1[k]));
+                a2[k] = fma(K3, nd.g, fma(K4, nd.p, a2[k]));
+            }
+        }
+    }
+}
+
+// FP64 pairs of target block tb with the nodes of chunk ch (same block-range test as the
+// FP32 tile).
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void pair_f64_tile(
     const double* __restrict__ tgt, int nv_pad, const NodeD* __restrict__ nodes,
-    const int4* __restrict__ node_vid, int nn, int chunk, double kappa, double eps,
-    double* __restrict__ partial, int tb, int ch) {
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int nn, int chunk, double kappa,
+    double eps, double* __restrict__ partial, int tb, int ch) {
     const int t0 = tb * (kPairBlock * TPL) + threadIdx.x;
+    const int wave0 = tb * (kPairBlock * TPL) + (__builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63);
     double tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL], a1[TPL], a2[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -194,39 +260,24 @@ __device__ __forceinline__ void pair_f64_tile(
         a1[k] = 0.0;
         a2[k] = 0.0;
     }
-    const double em1 = eps - 1.0, ce3 = 1.0 - 1.0 / eps, ie = 1.0 / eps;
-    const int s0 = ch * chunk;
+    const int s0 = ch * chunk;                 // chunk is a multiple of kFold
     const int s1 = min(s0 + chunk, nn);
     const const_as<NodeD>* cnodes = as_constant(nodes);
     const const_as<int4>* cvid = as_constant(node_vid);
-    for (int s = s0; s < s1; ++s) {
-        const NodeD nd = load_node(cnodes, s);
-        const int4 vid = load_vid(cvid, s);
+    const const_as<int2>* crange = as_constant(blk_range);
+    for (int sb = s0; sb < s1; sb += kFold) {
+        const int se = min(sb + kFold, s1);
+        const int vlo = crange[sb / kFold].x, vhi = crange[sb / kFold].y;
+        bool near = false;
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
-            const double dx = tx[k] - nd.x, dy = ty[k] - nd.y, dz = tz[k] - nd.z;
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const int t = t0 + k * kPairBlock;
-            const bool own = (t == vid.x) | (t == vid.y) | (t == vid.z);
-            const double rinv = own ? 0.0 : rsqrt(r2);
-            const double rinv3 = rinv * rinv * rinv;
-            const double dny = dx * nd.nx + dy * nd.ny + dz * nd.nz;
-            const double dnx = dx * tnx[k] + dy * tny[k] + dz * tnz[k];
-            if (KAPPA0) {
-                a1[k] += em1 * dny * rinv3 * nd.p;
-                a2[k] -= ce3 * dnx * rinv3 * nd.g;
-            } else {
-                const double nxy = tnx[k] * nd.nx + tny[k] * nd.ny + tnz[k] * nd.nz;
-                double f0, f1, f2;
-                f012_f64(kappa * (r2 * rinv), &f0, &f1, &f2);
-                const double K1 = f0 * rinv;
-                const double K2 = dny * rinv3 * (em1 - eps * f1);
-                const double K3 = -dnx * rinv3 * (ce3 + f1 * ie);
-                const double K4 = (dnx * dny * f2 * (rinv * rinv) - nxy * f1) * rinv3;
-                a1[k] += K1 * nd.g + K2 * nd.p;
-                a2[k] += K3 * nd.g + K4 * nd.p;
-            }
+            const int lo = wave0 + k * kPairBlock;
+            near |= (vhi >= lo) & (vlo <= lo + 63);
         }
+        if (near)
+            pair_f64_run<TPL, KAPPA0, true>(cnodes, cvid, sb, se, t0, tx, ty, tz, tnx, tny, tnz, kappa, eps, a1, a2);
+        else
+            pair_f64_run<TPL, KAPPA0, false>(cnodes, cvid, sb, se, t0, tx, ty, tz, tnx, tny, tnz, kappa, eps, a1, a2);
     }
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {

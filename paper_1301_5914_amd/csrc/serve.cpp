@@ -65,7 +65,7 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 // server's partial sums and Krylov basis), from its sizes alone.
 int64_t footprint_bytes(int nv, int nf, int nc, int m, bool mixed) {
     const int64_t nv_pad = round_up(nv, 2048), nc_pad = round_up(nc, 256), nn = 4LL * nf;
-    const PairPlan p64 = make_plan((int)nv_pad, (int)nn, 2), p32 = make_plan((int)nv_pad, (int)nn, nv_pad >= 16384 ? 8 : 4);
+    const PairPlan p64 = make_plan((int)nv_pad, (int)nn, kTpl64), p32 = make_plan((int)nv_pad, (int)nn, nv_pad >= 16384 ? 8 : 4);
     const PairPlan pp = make_plan((int)nc_pad, (int)nn, 1);
     const PairPlan ps = make_plan((int)nv_pad, (int)nn, mixed ? kServeTpl32 : kServeTpl64);
     int64_t b = 0;

@@ -45,10 +45,10 @@ __global__ __launch_bounds__(kPairBlock) void batched_pair_kernel(const ServeDes
                                                   d.kl2n, d.partial, item.a, item.b);
         } else {
             if (d.kappa == 0.0)
-                pair_f64_tile<kServeTpl64, true>(d.tgt64, d.nv_pad, d.node64, d.node_vid, d.nn, d.chunk, d.kappa, d.eps,
+                pair_f64_tile<kServeTpl64, true>(d.tgt64, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.nn, d.chunk, d.kappa, d.eps,
                                                  d.partial, item.a, item.b);
             else
-                pair_f64_tile<kServeTpl64, false>(d.tgt64, d.nv_pad, d.node64, d.node_vid, d.nn, d.chunk, d.kappa, d.eps,
+                pair_f64_tile<kServeTpl64, false>(d.tgt64, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.nn, d.chunk, d.kappa, d.eps,
                                                   d.partial, item.a, item.b);
         }
     }
