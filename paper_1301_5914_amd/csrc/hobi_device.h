@@ -19,7 +19,7 @@ namespace hobi {
 struct alignas(64) NodeF {
     float x, y, z, nx, ny, nz, g, p;
     float ga, gb, pa, pb;
-    int v0, v1, v2, pad;
+    float qx, qy, qz, pad;   // p * (nx, ny, nz)
 };
 struct alignas(64) NodeD {
     double x, y, z, g;

@@ -58,11 +58,11 @@ __global__ __launch_bounds__(kBlock) void pair_f64_kernel(
 template <int TPL, bool KAPPA0>
 __global__ __launch_bounds__(kBlock) void pair_f32_kernel(
     const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes,
-    const int2* __restrict__ blk_range, int nn, int chunk, float kappa, float kl2n,
-    double* __restrict__ partial) {
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int nn, int chunk, float kappa,
+    float kl2n, double* __restrict__ partial) {
     int tb, ch;
     xcd_block(&tb, &ch);
-    pair_f32_tile<TPL, KAPPA0>(tgt, nv_pad, nodes, blk_range, nn, chunk, kappa, kl2n, partial, tb, ch);
+    pair_f32_tile<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, nn, chunk, kappa, kl2n, partial, tb, ch);
 }
 
 __global__ void combine_kernel(const double* __restrict__ u, double* __restrict__ y, int nv, int nv_pad,
@@ -160,8 +160,9 @@ PairPlan make_plan(int n_pad, int nn, int tpl) {
     pl.block = kBlock;
     pl.target_blocks = n_pad / (kBlock * tpl);
     if (pl.target_blocks < 1) pl.target_blocks = 1;
-    // about 8 resident blocks per compute unit on 256 CUs; at least 256 nodes per chunk
-    const int want = 2048;
+    // about 16 blocks per compute unit on 256 CUs (a short tail when the last wave of blocks
+    // drains); at least 256 nodes per chunk
+    const int want = 4096;
     int chunks = (want + pl.target_blocks - 1) / pl.target_blocks;
     const int max_chunks = nn / 256 > 1 ? nn / 256 : 1;
     if (chunks > max_chunks) chunks = max_chunks;
@@ -186,7 +187,7 @@ hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s) {
         const float kappa = (float)p.kappa, kl2n = (float)(-p.kappa * 1.4426950408889634074);
 #define HOBI_PAIR32(T, K0)                                                                        \
     hipLaunchKernelGGL((pair_f32_kernel<T, K0>), grid, dim3(kBlock), 0, s, p.tgt32, p.nv_pad, p.node32, \
-                       p.blk_range, p.nn, pl.chunk, kappa, kl2n, p.partial)
+                       p.node_vid, p.blk_range, p.nn, pl.chunk, kappa, kl2n, p.partial)
         if (pl.tpl == 8) {
             if (k0) HOBI_PAIR32(8, true); else HOBI_PAIR32(8, false);
         } else {

@@ -28,7 +28,7 @@ __device__ __forceinline__ NodeF load_node(const const_as<NodeF>* p, int s) {
     n.x = p[s].x, n.y = p[s].y, n.z = p[s].z;
     n.nx = p[s].nx, n.ny = p[s].ny, n.nz = p[s].nz;
     n.g = p[s].g, n.p = p[s].p, n.ga = p[s].ga, n.gb = p[s].gb, n.pa = p[s].pa, n.pb = p[s].pb;
-    n.v0 = p[s].v0, n.v1 = p[s].v1, n.v2 = p[s].v2, n.pad = 0;
+    n.qx = p[s].qx, n.qy = p[s].qy, n.qz = p[s].qz, n.pad = 0.0f;
     return n;
 }
 
@@ -44,17 +44,22 @@ __device__ __forceinline__ NodeD load_node(const const_as<NodeD>* p, int s) {
 }
 
 // FP32 pairs of nodes [sb, se) with the lane's TPL targets, added to FP32 running sums.
-// Per pair (kappa > 0): 38 VALU operations plus one rsqrt and one exp2 on the
-// transcendental unit; with MASK, pairs of a vertex with its own triangles' nodes (they
-// belong to the singular rule) are skipped, at 4 more operations per pair.
+// Per pair (kappa > 0): 35 VALU operations plus one rsqrt and one exp2.  With
+// q = (d.ny)/r^2, the two rows are
+//   row 1: K1 Gamma + K2 Phi = [Gamma (1 - e) + q (pa + pb f1)] / r
+//   row 2: K3 Gamma + K4 Phi = [(d.nx)(ga + gb f1 + p q f2) - (nx.P) f1] / r^3,  P = p ny,
+// which is the kernel algebra with the node strengths folded in.  With MASK, pairs of a
+// vertex with its own triangles' nodes (they belong to the singular rule) are skipped.
 template <int TPL, bool KAPPA0, bool MASK>
-__device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, int sb, int se, int t0,
-                                             const float (&tx)[TPL], const float (&ty)[TPL],
+__device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, const const_as<int4>* cvid, int sb,
+                                             int se, int t0, const float (&tx)[TPL], const float (&ty)[TPL],
                                              const float (&tz)[TPL], const float (&tnx)[TPL],
                                              const float (&tny)[TPL], const float (&tnz)[TPL],
                                              float kappa, float kl2n, float (&a1)[TPL], float (&a2)[TPL]) {
     for (int s = sb; s < se; ++s) {
         const NodeF n = load_node(cnodes, s);
+        int4 vid = make_int4(-1, -1, -1, 0);
+        if (MASK) vid = load_vid(cvid, s);
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
             const float dx = tx[k] - n.x, dy = ty[k] - n.y, dz = tz[k] - n.z;
@@ -62,28 +67,26 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, int 
             float rinv = __builtin_amdgcn_rsqf(r2);
             if (MASK) {
                 const int t = t0 + k * kPairBlock;
-                if ((t == n.v0) | (t == n.v1) | (t == n.v2)) rinv = 0.0f;
+                if ((t == vid.x) | (t == vid.y) | (t == vid.z)) rinv = 0.0f;
             }
             const float rinv2 = rinv * rinv;
-            const float rinv3 = rinv2 * rinv;
             const float dny = fmaf(dx, n.nx, fmaf(dy, n.ny, dz * n.nz));
             const float dnx = fmaf(dx, tnx[k], fmaf(dy, tny[k], dz * tnz[k]));
             if (KAPPA0) {
+                const float rinv3 = rinv2 * rinv;
                 a1[k] = fmaf(dny * rinv3, n.pa, a1[k]);
                 a2[k] = fmaf(dnx * rinv3, n.ga, a2[k]);
             } else {
-                const float nxy = fmaf(tnx[k], n.nx, fmaf(tny[k], n.ny, tnz[k] * n.nz));
+                const float pnxy = fmaf(tnx[k], n.qx, fmaf(tny[k], n.qy, tnz[k] * n.qz));
                 const float r = r2 * rinv;
                 const float e = __builtin_amdgcn_exp2f(kl2n * r);         // exp(-kappa r)
                 const float zp1 = fmaf(kappa, r, 1.0f);                  // 1 + z
                 const float f1 = fmaf(-e, zp1, 1.0f);                    // 1 - e (1 + z)
                 const float f2 = fmaf(-e, fmaf(zp1, zp1 + 1.0f, 1.0f), 3.0f);   // 3 - e (3 + 3z + z^2)
-                // row 1: K1 Gamma + K2 Phi = (Gamma - e Gamma)/r + (d.ny)/r^3 (pa + pb f1)
-                a1[k] = fmaf(dny * rinv3, fmaf(n.pb, f1, n.pa), a1[k]);
-                a1[k] = fmaf(fmaf(-e, n.g, n.g), rinv, a1[k]);
-                // row 2: K3 Gamma + K4 Phi = [(d.nx)(ga + gb f1) + Phi ((d.nx)(d.ny) f2 / r^2 - (nx.ny) f1)] / r^3
-                const float w = fmaf(dnx * dny * f2, rinv2, -nxy * f1);
-                a2[k] = fmaf(rinv3, fmaf(w, n.p, dnx * fmaf(n.gb, f1, n.ga)), a2[k]);
+                const float q = dny * rinv2;
+                a1[k] = fmaf(rinv, fmaf(q, fmaf(n.pb, f1, n.pa), fmaf(-e, n.g, n.g)), a1[k]);
+                const float t = fmaf(n.p, q * f2, fmaf(n.gb, f1, n.ga));
+                a2[k] = fmaf(rinv2 * rinv, fmaf(-pnxy, f1, dnx * t), a2[k]);
             }
         }
     }
@@ -95,8 +98,8 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, int 
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void pair_f32_tile(
     const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes,
-    const int2* __restrict__ blk_range, int nn, int chunk, float kappa, float kl2n,
-    double* __restrict__ partial, int tb, int ch) {
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int nn, int chunk, float kappa,
+    float kl2n, double* __restrict__ partial, int tb, int ch) {
     const int t0 = tb * (kPairBlock * TPL) + threadIdx.x;
     const int wave0 = tb * (kPairBlock * TPL) + (__builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63);
     float tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL];
@@ -116,6 +119,7 @@ __device__ __forceinline__ void pair_f32_tile(
     const int s0 = ch * chunk;                 // chunk is a multiple of kFold
     const int s1 = min(s0 + chunk, nn);
     const const_as<NodeF>* cnodes = as_constant(nodes);
+    const const_as<int4>* cvid = as_constant(node_vid);
     const const_as<int2>* crange = as_constant(blk_range);
     for (int sb = s0; sb < s1; sb += kFold) {
         const int se = min(sb + kFold, s1);
@@ -130,9 +134,11 @@ __device__ __forceinline__ void pair_f32_tile(
 #pragma unroll
         for (int k = 0; k < TPL; ++k) a1[k] = a2[k] = 0.0f;
         if (near)
-            pair_f32_run<TPL, KAPPA0, true>(cnodes, sb, se, t0, tx, ty, tz, tnx, tny, tnz, kappa, kl2n, a1, a2);
+            pair_f32_run<TPL, KAPPA0, true>(cnodes, cvid, sb, se, t0, tx, ty, tz, tnx, tny, tnz, kappa, kl2n, a1,
+                                            a2);
         else
-            pair_f32_run<TPL, KAPPA0, false>(cnodes, sb, se, t0, tx, ty, tz, tnx, tny, tnz, kappa, kl2n, a1, a2);
+            pair_f32_run<TPL, KAPPA0, false>(cnodes, cvid, sb, se, t0, tx, ty, tz, tnx, tny, tnz, kappa, kl2n, a1,
+                                             a2);
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
             d1[k] += (double)a1[k];
@@ -171,6 +177,9 @@ __device__ __forceinline__ void gather_node(int idx, const double* __restrict__ 
         n.gb = (float)(-g / eps);
         n.pa = (float)((eps - 1.0) * p);
         n.pb = (float)(-eps * p);
+        n.qx = (float)(p * node64[idx].nx);
+        n.qy = (float)(p * node64[idx].ny);
+        n.qz = (float)(p * node64[idx].nz);
     }
 }
 

@@ -38,10 +38,10 @@ __global__ __launch_bounds__(kPairBlock) void batched_pair_kernel(const ServeDes
         const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
         if (d.mixed) {
             if (d.kappa == 0.0)
-                pair_f32_tile<kServeTpl32, true>(d.tgt32, d.nv_pad, d.node32, d.blk_range, d.nn, d.chunk, (float)d.kappa,
+                pair_f32_tile<kServeTpl32, true>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk, (float)d.kappa,
                                                  d.kl2n, d.partial, item.a, item.b);
             else
-                pair_f32_tile<kServeTpl32, false>(d.tgt32, d.nv_pad, d.node32, d.blk_range, d.nn, d.chunk, (float)d.kappa,
+                pair_f32_tile<kServeTpl32, false>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk, (float)d.kappa,
                                                   d.kl2n, d.partial, item.a, item.b);
         } else {
             if (d.kappa == 0.0)

@@ -75,9 +75,6 @@ __global__ void regular_kernel(const double* __restrict__ patch, const int* __re
     f.nx = (float)n.x;
     f.ny = (float)n.y;
     f.nz = (float)n.z;
-    f.v0 = tri[3 * j];
-    f.v1 = tri[3 * j + 1];
-    f.v2 = tri[3 * j + 2];
     node32[idx] = f;
     node_vid[idx] = make_int4(tri[3 * j], tri[3 * j + 1], tri[3 * j + 2], 0);
     w[idx] = wm * J;
