@@ -27,6 +27,7 @@ struct DeviceProblem {
     int nv = 0, nf = 0, nc = 0, nn = 0;     // vertices, triangles, charges, regular nodes
     double eps1 = 1, eps2 = 80, kappa = 0, eps = 80;
     double center[3] = {0, 0, 0};          // shift applied to the FP32 copies
+    double s32 = 1;                         // scale of the FP32 positions: kappa log2(e) (1 if kappa = 0)
     // inputs in internal (spatially sorted) order
     double* xyz = nullptr;                  // [nv][3]
     double* nrm = nullptr;                  // [nv][3]

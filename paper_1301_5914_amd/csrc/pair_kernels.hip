@@ -39,10 +39,10 @@ __device__ __forceinline__ void xcd_block(int* tb, int* ch) {
 
 __global__ void gather_kernel(const double* __restrict__ u, int nv, const int* __restrict__ tri,
                               const double* __restrict__ w, int nn, NodeD* __restrict__ node64,
-                              NodeF* __restrict__ node32, int mixed, double eps) {
+                              NodeF* __restrict__ node32, int mixed, double eps, double s32) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nn) return;
-    gather_node(idx, u, nv, tri, w, node64, node32, mixed, eps);
+    gather_node(idx, u, nv, tri, w, node64, node32, mixed, eps, s32);
 }
 
 template <int TPL, bool KAPPA0>
@@ -58,11 +58,11 @@ __global__ __launch_bounds__(kBlock) void pair_f64_kernel(
 template <int TPL, bool KAPPA0>
 __global__ __launch_bounds__(kBlock) void pair_f32_kernel(
     const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes,
-    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int nn, int chunk, float kappa,
-    float kl2n, double* __restrict__ partial) {
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int nn, int chunk,
+    double* __restrict__ partial) {
     int tb, ch;
     xcd_block(&tb, &ch);
-    pair_f32_tile<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, nn, chunk, kappa, kl2n, partial, tb, ch);
+    pair_f32_tile<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, nn, chunk, partial, tb, ch);
 }
 
 __global__ void combine_kernel(const double* __restrict__ u, double* __restrict__ y, int nv, int nv_pad,
@@ -175,7 +175,7 @@ PairPlan make_plan(int n_pad, int nn, int tpl) {
 
 hipError_t launch_gather(const DeviceProblem& p, const double* u, bool mixed, hipStream_t s) {
     hipLaunchKernelGGL(gather_kernel, dim3(nblk(p.nn, 256)), dim3(256), 0, s, u, p.nv, p.tri, p.w, p.nn,
-                       p.node64, p.node32, mixed ? 1 : 0, p.eps);
+                       p.node64, p.node32, mixed ? 1 : 0, p.eps, p.s32);
     return hipGetLastError();
 }
 
@@ -184,10 +184,9 @@ hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s) {
     if (mixed) {
         const PairPlan& pl = p.plan32;
         dim3 grid(pl.target_blocks, pl.chunks);
-        const float kappa = (float)p.kappa, kl2n = (float)(-p.kappa * 1.4426950408889634074);
 #define HOBI_PAIR32(T, K0)                                                                        \
     hipLaunchKernelGGL((pair_f32_kernel<T, K0>), grid, dim3(kBlock), 0, s, p.tgt32, p.nv_pad, p.node32, \
-                       p.node_vid, p.blk_range, p.nn, pl.chunk, kappa, kl2n, p.partial)
+                       p.node_vid, p.blk_range, p.nn, pl.chunk, p.partial)
         if (pl.tpl == 8) {
             if (k0) HOBI_PAIR32(8, true); else HOBI_PAIR32(8, false);
         } else {

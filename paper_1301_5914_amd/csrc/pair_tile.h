@@ -44,7 +44,9 @@ __device__ __forceinline__ NodeD load_node(const const_as<NodeD>* p, int s) {
 }
 
 // FP32 pairs of nodes [sb, se) with the lane's TPL targets, added to FP32 running sums.
-// Per pair (kappa > 0): 35 VALU operations plus one rsqrt and one exp2.  With
+// Positions are in units of 1 / (kappa log2 e) when kappa > 0, so that exp(-kappa r) is
+// exp2(-r) and kappa r = r ln 2 (the strengths carry the matching powers of the unit).
+// Per pair (kappa > 0): 34 VALU operations plus one rsqrt and one exp2.  With
 // q = (d.ny)/r^2, the two rows are
 //   row 1: K1 Gamma + K2 Phi = [Gamma (1 - e) + q (pa + pb f1)] / r
 //   row 2: K3 Gamma + K4 Phi = [(d.nx)(ga + gb f1 + p q f2) - (nx.P) f1] / r^3,  P = p ny,
@@ -55,7 +57,8 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, cons
                                              int se, int t0, const float (&tx)[TPL], const float (&ty)[TPL],
                                              const float (&tz)[TPL], const float (&tnx)[TPL],
                                              const float (&tny)[TPL], const float (&tnz)[TPL],
-                                             float kappa, float kl2n, float (&a1)[TPL], float (&a2)[TPL]) {
+                                             float (&a1)[TPL], float (&a2)[TPL]) {
+    constexpr float kLn2 = 0.693147180559945309f;
     for (int s = sb; s < se; ++s) {
         const NodeF n = load_node(cnodes, s);
         int4 vid = make_int4(-1, -1, -1, 0);
@@ -79,8 +82,8 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, cons
             } else {
                 const float pnxy = fmaf(tnx[k], n.qx, fmaf(tny[k], n.qy, tnz[k] * n.qz));
                 const float r = r2 * rinv;
-                const float e = __builtin_amdgcn_exp2f(kl2n * r);         // exp(-kappa r)
-                const float zp1 = fmaf(kappa, r, 1.0f);                  // 1 + z
+                const float e = __builtin_amdgcn_exp2f(-r);               // exp(-kappa r)
+                const float zp1 = fmaf(r, kLn2, 1.0f);                   // 1 + z
                 const float f1 = fmaf(-e, zp1, 1.0f);                    // 1 - e (1 + z)
                 const float f2 = fmaf(-e, fmaf(zp1, zp1 + 1.0f, 1.0f), 3.0f);   // 3 - e (3 + 3z + z^2)
                 const float q = dny * rinv2;
@@ -98,8 +101,8 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, cons
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void pair_f32_tile(
     const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes,
-    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int nn, int chunk, float kappa,
-    float kl2n, double* __restrict__ partial, int tb, int ch) {
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int nn, int chunk,
+    double* __restrict__ partial, int tb, int ch) {
     const int t0 = tb * (kPairBlock * TPL) + threadIdx.x;
     const int wave0 = tb * (kPairBlock * TPL) + (__builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63);
     float tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL];
@@ -134,11 +137,9 @@ __device__ __forceinline__ void pair_f32_tile(
 #pragma unroll
         for (int k = 0; k < TPL; ++k) a1[k] = a2[k] = 0.0f;
         if (near)
-            pair_f32_run<TPL, KAPPA0, true>(cnodes, cvid, sb, se, t0, tx, ty, tz, tnx, tny, tnz, kappa, kl2n, a1,
-                                            a2);
+            pair_f32_run<TPL, KAPPA0, true>(cnodes, cvid, sb, se, t0, tx, ty, tz, tnx, tny, tnz, a1, a2);
         else
-            pair_f32_run<TPL, KAPPA0, false>(cnodes, cvid, sb, se, t0, tx, ty, tz, tnx, tny, tnz, kappa, kl2n, a1,
-                                             a2);
+            pair_f32_run<TPL, KAPPA0, false>(cnodes, cvid, sb, se, t0, tx, ty, tz, tnx, tny, tnz, a1, a2);
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
             d1[k] += (double)a1[k];
@@ -154,10 +155,12 @@ __device__ __forceinline__ void pair_f32_tile(
 }
 
 // Strengths of regular node idx = 4 j + m from u (1/(4 pi) folded in), FP64 and FP32 records.
+// The FP32 record's positions are in units of 1/s32; its strengths carry the matching powers
+// of s32 (Gamma terms over r and (d.ny)/r^3 terms: s32, s32^2; the Phi term of K4: s32^3).
 __device__ __forceinline__ void gather_node(int idx, const double* __restrict__ u, int nv,
                                             const int* __restrict__ tri, const double* __restrict__ w,
                                             NodeD* __restrict__ node64, NodeF* __restrict__ node32,
-                                            int mixed, double eps) {
+                                            int mixed, double eps, double s32) {
     const int j = idx >> 2, m = idx & 3;
     double r, s, wm;
     gauss_radau4(m, &r, &s, &wm);
@@ -171,15 +174,16 @@ __device__ __forceinline__ void gather_node(int idx, const double* __restrict__ 
     node64[idx].p = p;
     if (mixed) {
         NodeF& n = node32[idx];
-        n.g = (float)g;
-        n.p = (float)p;
-        n.ga = (float)(-(1.0 - 1.0 / eps) * g);
-        n.gb = (float)(-g / eps);
-        n.pa = (float)((eps - 1.0) * p);
-        n.pb = (float)(-eps * p);
-        n.qx = (float)(p * node64[idx].nx);
-        n.qy = (float)(p * node64[idx].ny);
-        n.qz = (float)(p * node64[idx].nz);
+        const double s2 = s32 * s32, s3 = s2 * s32;
+        n.g = (float)(s32 * g);
+        n.p = (float)(s3 * p);
+        n.ga = (float)(-(1.0 - 1.0 / eps) * s2 * g);
+        n.gb = (float)(-s2 * g / eps);
+        n.pa = (float)((eps - 1.0) * s2 * p);
+        n.pb = (float)(-eps * s2 * p);
+        n.qx = (float)(s3 * p * node64[idx].nx);
+        n.qy = (float)(s3 * p * node64[idx].ny);
+        n.qz = (float)(s3 * p * node64[idx].nz);
     }
 }
 

@@ -300,7 +300,7 @@ hobi_status tick(hobi_server sv) {
         sd.coef = d.coef;
         sd.kappa = d.kappa;
         sd.eps = d.eps;
-        sd.kl2n = (float)(-d.kappa * 1.4426950408889634074);
+        sd.s32 = d.s32;
         sd.nv = d.nv;
         sd.nv_pad = d.nv_pad;
         sd.nn = d.nn;

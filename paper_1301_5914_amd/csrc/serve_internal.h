@@ -31,7 +31,7 @@ struct ServeDesc {
     const double* coef;
     double kappa;
     double eps;
-    float kl2n;             // -kappa * log2(e)
+    double s32;             // scale of the FP32 positions
     int nv, nv_pad, nn;
     int chunk, chunks;
     int mixed;

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kPairBlock) void batched_gather_kernel(const ServeD
         const const_as<ServeItem>& item = as_constant(items)[uniform(it)];
         const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
         const int idx = item.a * kPairBlock + (int)threadIdx.x;
-        if (idx < d.nn) gather_node(idx, d.u, d.nv, d.tri, d.w, d.node64, d.node32, d.mixed, d.eps);
+        if (idx < d.nn) gather_node(idx, d.u, d.nv, d.tri, d.w, d.node64, d.node32, d.mixed, d.eps, d.s32);
     }
 }
 
@@ -38,11 +38,11 @@ __global__ __launch_bounds__(kPairBlock) void batched_pair_kernel(const ServeDes
         const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
         if (d.mixed) {
             if (d.kappa == 0.0)
-                pair_f32_tile<kServeTpl32, true>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk, (float)d.kappa,
-                                                 d.kl2n, d.partial, item.a, item.b);
+                pair_f32_tile<kServeTpl32, true>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk,
+                                                 d.partial, item.a, item.b);
             else
-                pair_f32_tile<kServeTpl32, false>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk, (float)d.kappa,
-                                                  d.kl2n, d.partial, item.a, item.b);
+                pair_f32_tile<kServeTpl32, false>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk,
+                                                  d.partial, item.a, item.b);
         } else {
             if (d.kappa == 0.0)
                 pair_f64_tile<kServeTpl64, true>(d.tgt64, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.nn, d.chunk, d.kappa, d.eps,

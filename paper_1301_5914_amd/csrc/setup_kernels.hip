@@ -52,7 +52,7 @@ __global__ void patch_kernel(const double* __restrict__ xyz, const double* __res
 __global__ void regular_kernel(const double* __restrict__ patch, const int* __restrict__ tri, int nf,
                                NodeD* __restrict__ node64, NodeF* __restrict__ node32,
                                int4* __restrict__ node_vid, double* __restrict__ w, double cx,
-                               double cy, double cz) {
+                               double cy, double cz, double s32) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= 4 * nf) return;
     const int j = idx >> 2, m = idx & 3;
@@ -69,9 +69,9 @@ __global__ void regular_kernel(const double* __restrict__ patch, const int* __re
     d.nz = n.z;
     node64[idx] = d;
     NodeF f{};
-    f.x = (float)(x.x - cx);
-    f.y = (float)(x.y - cy);
-    f.z = (float)(x.z - cz);
+    f.x = (float)((x.x - cx) * s32);
+    f.y = (float)((x.y - cy) * s32);
+    f.z = (float)((x.z - cz) * s32);
     f.nx = (float)n.x;
     f.ny = (float)n.y;
     f.nz = (float)n.z;
@@ -82,7 +82,7 @@ __global__ void regular_kernel(const double* __restrict__ patch, const int* __re
 
 __global__ void targets_kernel(const double* __restrict__ xyz, const double* __restrict__ nrm, int nv,
                                int nv_pad, double* __restrict__ t64, float* __restrict__ t32,
-                               double cx, double cy, double cz) {
+                               double cx, double cy, double cz, double s32) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nv_pad) return;
     const int src = i < nv ? i : nv - 1;   // padding lanes repeat the last vertex
@@ -91,7 +91,7 @@ __global__ void targets_kernel(const double* __restrict__ xyz, const double* __r
         const double x = xyz[3 * src + d], n = nrm[3 * src + d];
         t64[(size_t)d * nv_pad + i] = x;
         t64[(size_t)(3 + d) * nv_pad + i] = n;
-        t32[(size_t)d * nv_pad + i] = (float)(x - c[d]);
+        t32[(size_t)d * nv_pad + i] = (float)((x - c[d]) * s32);
         t32[(size_t)(3 + d) * nv_pad + i] = (float)n;
     }
 }
@@ -184,13 +184,13 @@ hipError_t launch_patch(const DeviceProblem& p, int* d_err, hipStream_t s) {
 
 hipError_t launch_regular_nodes(const DeviceProblem& p, hipStream_t s) {
     hipLaunchKernelGGL(regular_kernel, dim3(nblk(4L * p.nf, 128)), dim3(128), 0, s, p.patch, p.tri, p.nf,
-                       p.node64, p.node32, p.node_vid, p.w, p.center[0], p.center[1], p.center[2]);
+                       p.node64, p.node32, p.node_vid, p.w, p.center[0], p.center[1], p.center[2], p.s32);
     return hipGetLastError();
 }
 
 hipError_t launch_targets(const DeviceProblem& p, hipStream_t s) {
     hipLaunchKernelGGL(targets_kernel, dim3(nblk(p.nv_pad, 256)), dim3(256), 0, s, p.xyz, p.nrm, p.nv,
-                       p.nv_pad, p.tgt64, p.tgt32, p.center[0], p.center[1], p.center[2]);
+                       p.nv_pad, p.tgt64, p.tgt32, p.center[0], p.center[1], p.center[2], p.s32);
     return hipGetLastError();
 }
 

@@ -348,81 +348,203 @@ def marching_tetrahedra(func, lo, h, shape, iso_shift=1e-9):
     return verts, tris, (uniq, pa, pb, fa, fb)
 
 
-def collapse_short_edges(xyz, tri, min_len, normal_of=None):
-    """Removes edges shorter than ``min_len`` by merging their end points, keeping the mesh
-    a closed oriented 2-manifold: an edge is collapsed only when its end points share
-    exactly the two vertices opposite to it (the link condition) and no surviving triangle
-    around it turns over.  Returns (xyz, tri) with unused vertices dropped."""
-    xyz = np.array(xyz, dtype=np.float64)
-    tri = [list(t) for t in np.asarray(tri)]
-    nv = xyz.shape[0]
-    vt = [set() for _ in range(nv)]
-    for t, (a, b, c) in enumerate(tri):
-        vt[a].add(t), vt[b].add(t), vt[c].add(t)
-    alive_t = np.ones(len(tri), dtype=bool)
+class _EdgeCollapser:
+    """Edge collapses on a closed oriented triangle mesh.  An edge (u, v) may be merged into
+    one point only when its end points share exactly the two vertices opposite to it (the
+    link condition), so the mesh stays a closed 2-manifold."""
 
-    def neigh(v):
+    def __init__(self, xyz, tri):
+        self.xyz = np.array(xyz, dtype=np.float64)
+        self.tri = [list(t) for t in np.asarray(tri)]
+        self.vt = [set() for _ in range(self.xyz.shape[0])]
+        for t, (a, b, c) in enumerate(self.tri):
+            self.vt[a].add(t), self.vt[b].add(t), self.vt[c].add(t)
+        self.alive = np.ones(len(self.tri), dtype=bool)
+
+    def neigh(self, v):
         out = set()
-        for t in vt[v]:
-            out.update(tri[t])
+        for t in self.vt[v]:
+            out.update(self.tri[t])
         out.discard(v)
         return out
 
-    def tnormal(t, pos):
-        a, b, c = tri[t]
-        pa, pb, pc = pos(a), pos(b), pos(c)
-        return np.cross(pb - pa, pc - pa)
+    def edges(self):
+        live = np.asarray([t for t, ok in zip(self.tri, self.alive) if ok])
+        E = np.concatenate([live[:, [i, (i + 1) % 3]] for i in range(3)])
+        return np.unique(np.sort(E, axis=1), axis=0)
+
+    def link_ok(self, u, v):
+        shared = self.vt[u] & self.vt[v]
+        if len(shared) != 2:
+            return False
+        opp = set()
+        for t in shared:
+            opp.update(self.tri[t])
+        opp -= {u, v}
+        return len(opp) == 2 and self.neigh(u) & self.neigh(v) == opp
+
+    def ring(self, u, v):
+        """Triangles that survive the collapse of (u, v) and change shape."""
+        return (self.vt[u] | self.vt[v]) - (self.vt[u] & self.vt[v])
+
+    def corners(self, t, u, v, p):
+        return [p if w in (u, v) else self.xyz[w] for w in self.tri[t]]
+
+    def collapse(self, u, v, p):
+        for t in self.vt[u] & self.vt[v]:
+            self.alive[t] = False
+            for w in self.tri[t]:
+                self.vt[w].discard(t)
+        for t in list(self.vt[v]):
+            self.tri[t] = [u if w == v else w for w in self.tri[t]]
+            self.vt[u].add(t)
+        self.vt[v] = set()
+        self.xyz[u] = p
+
+    def result(self):
+        tri = np.asarray([t for t, ok in zip(self.tri, self.alive) if ok], dtype=np.int64)
+        used = np.unique(tri)
+        remap = -np.ones(self.xyz.shape[0], dtype=np.int64)
+        remap[used] = np.arange(used.size)
+        return self.xyz[used], remap[tri]
+
+
+def collapse_short_edges(xyz, tri, min_len):
+    """Removes edges shorter than ``min_len`` by merging their end points at the midpoint,
+    when the link condition holds and no surviving triangle around the edge turns over.
+    Returns (xyz, tri) with unused vertices dropped."""
+    m = _EdgeCollapser(xyz, tri)
+
+    def tnormal(P):
+        return np.cross(P[1] - P[0], P[2] - P[0])
 
     changed = True
     while changed:
         changed = False
-        E = np.concatenate([np.asarray([t for t, ok in zip(tri, alive_t) if ok])[:, [i, (i + 1) % 3]]
-                            for i in range(3)])
-        E = np.unique(np.sort(E, axis=1), axis=0)
-        L = np.linalg.norm(xyz[E[:, 0]] - xyz[E[:, 1]], axis=1)
+        E = m.edges()
+        L = np.linalg.norm(m.xyz[E[:, 0]] - m.xyz[E[:, 1]], axis=1)
         order = np.argsort(L)
         order = order[L[order] < min_len]
         touched = set()
         for e in order:
             u, v = int(E[e, 0]), int(E[e, 1])
-            if u in touched or v in touched:
+            if u in touched or v in touched or not m.link_ok(u, v):
                 continue
-            shared = vt[u] & vt[v]
-            if len(shared) != 2:
-                continue
-            opp = set()
-            for t in shared:
-                opp.update(tri[t])
-            opp -= {u, v}
-            if neigh(u) & neigh(v) != opp or len(opp) != 2:
-                continue
-            p = 0.5 * (xyz[u] + xyz[v])
+            p = 0.5 * (m.xyz[u] + m.xyz[v])
             ok = True
-            for t in (vt[u] | vt[v]) - shared:
-                before = tnormal(t, lambda w: xyz[w])
-                after = tnormal(t, lambda w: p if w in (u, v) else xyz[w])
+            for t in m.ring(u, v):
+                before = tnormal([m.xyz[w] for w in m.tri[t]])
+                after = tnormal(m.corners(t, u, v, p))
                 if np.dot(before, after) <= 0.0 or np.linalg.norm(after) <= 1e-12 * np.dot(before, before) ** 0.5:
                     ok = False
                     break
             if not ok:
                 continue
-            for t in shared:
-                alive_t[t] = False
-                for w in tri[t]:
-                    vt[w].discard(t)
-            for t in list(vt[v]):
-                tri[t] = [u if w == v else w for w in tri[t]]
-                vt[u].add(t)
-            vt[v] = set()
-            xyz[u] = p
+            m.collapse(u, v, p)
             touched.update((u, v))
-            touched.update(neigh(u))
+            touched.update(m.neigh(u))
             changed = True
-    tri = np.asarray([t for t, ok in zip(tri, alive_t) if ok], dtype=np.int64)
-    used = np.unique(tri)
-    remap = -np.ones(nv, dtype=np.int64)
-    remap[used] = np.arange(used.size)
-    return xyz[used], remap[tri]
+    return m.result()
+
+
+def _fold_cosine(verts, tri, nrm):
+    """Smallest cosine between a triangle's face normal and its three vertex normals."""
+    A, B, C = verts[tri[:, 0]], verts[tri[:, 1]], verts[tri[:, 2]]
+    fn = np.cross(B - A, C - A)
+    fn /= np.maximum(np.linalg.norm(fn, axis=1, keepdims=True), 1e-300)
+    return np.min(np.stack([np.einsum("ij,ij->i", fn, nrm[tri[:, k]]) for k in range(3)], axis=1), axis=1)
+
+
+def _surface_normals(ag, verts):
+    _, g = ag.eval(verts, grad=True)
+    return -g / np.linalg.norm(g, axis=1, keepdims=True)
+
+
+def remove_folds(ag, verts, tri, cos_min: float = 0.3, passes: int = 6):
+    """Removes folded triangles (face normal against a vertex normal, cosine below
+    ``cos_min``: creases of the density narrower than the marching grid resolves).  Each
+    pass first flips the edges of folded triangles where the flip raises the smaller fold
+    cosine of the pair, then collapses the shortest edge of the folds left, at its midpoint
+    moved onto rho = 1, when no triangle around it ends up below both ``cos_min`` and its
+    old fold cosine."""
+    verts = np.array(verts, dtype=np.float64)
+    tri = np.asarray(tri, dtype=np.int64).copy()
+    for _ in range(passes):
+        nrm = _surface_normals(ag, verts)
+        fc = _fold_cosine(verts, tri, nrm)
+        if fc.min() >= cos_min:
+            break
+
+        def fcos(a, b, c, P=None, N=None):
+            return float(_fold_cosine(verts, np.array([[a, b, c]]), nrm)[0])
+
+        # flips
+        edge_of = {}
+        for t, (a, b, c) in enumerate(tri):
+            edge_of[(a, b)] = t
+            edge_of[(b, c)] = t
+            edge_of[(c, a)] = t
+        for t1 in np.nonzero(fc < cos_min)[0]:
+            best = None
+            for k in range(3):
+                a, b, c = tri[t1][k], tri[t1][(k + 1) % 3], tri[t1][(k + 2) % 3]
+                t2 = edge_of.get((b, a))
+                if t2 is None:
+                    continue
+                d = [w for w in tri[t2] if w != a and w != b][0]
+                if c == d or (c, d) in edge_of or (d, c) in edge_of:
+                    continue
+                old = min(fcos(*tri[t1]), fcos(*tri[t2]))
+                new = min(fcos(a, d, c), fcos(d, b, c))
+                if new > old + 1e-3 and (best is None or new > best[0]):
+                    best = (new, a, b, c, d, t2)
+            if best is None:
+                continue
+            _, a, b, c, d, t2 = best
+            for e in ((a, b), (b, c), (c, a), (b, a), (a, d), (d, b)):
+                edge_of.pop(e, None)
+            tri[t1] = (a, d, c)
+            tri[t2] = (d, b, c)
+            for t in (t1, t2):
+                x, y, z = tri[t]
+                edge_of[(x, y)] = t
+                edge_of[(y, z)] = t
+                edge_of[(z, x)] = t
+        # collapses
+        fc = _fold_cosine(verts, tri, nrm)
+        m = _EdgeCollapser(verts, tri)
+        touched = set()
+        for t in np.argsort(fc):
+            if fc[t] >= cos_min:
+                break
+            if not m.alive[t]:
+                continue
+            es = [(m.tri[t][k], m.tri[t][(k + 1) % 3]) for k in range(3)]
+            es.sort(key=lambda e: float(np.sum((m.xyz[e[0]] - m.xyz[e[1]]) ** 2)))
+            for u, v in es:
+                if u in touched or v in touched or not m.link_ok(u, v):
+                    continue
+                p = _project_to_iso(ag, (0.5 * (m.xyz[u] + m.xyz[v]))[None, :])[0]
+                pn = _surface_normals(ag, p[None, :])[0]
+                ok = True
+                for s_ in m.ring(u, v):
+                    P = m.corners(s_, u, v, p)
+                    fn = np.cross(P[1] - P[0], P[2] - P[0])
+                    ln = np.linalg.norm(fn)
+                    if ln <= 0.0:
+                        ok = False
+                        break
+                    new = min(np.dot(fn, pn if w in (u, v) else nrm[w]) for w in m.tri[s_]) / ln
+                    if new < min(cos_min, fcos(*m.tri[s_])):
+                        ok = False
+                        break
+                if ok:
+                    m.collapse(u, v, p)
+                    touched.update((u, v))
+                    touched.update(m.neigh(u))
+                    break
+        verts, tri = m.result()
+    return verts, tri
 
 
 def delaunay_flips(xyz, tri, nrm, max_passes: int = 20):
@@ -476,14 +598,101 @@ def delaunay_flips(xyz, tri, nrm, max_passes: int = 20):
     return tri
 
 
+def _project_to_iso(ag, verts, steps: int = 8):
+    """Newton steps along the gradient onto rho = 1."""
+    for _ in range(steps):
+        rho, g = ag.eval(verts, grad=True)
+        verts = verts - ((rho - 1.0) / np.sum(g * g, axis=1))[:, None] * g
+    return verts
+
+
+def tangential_smooth(ag, verts, tri, iters: int = 2, lam: float = 0.5):
+    """Moves every vertex a fraction ``lam`` of the way to the centroid of its neighbours,
+    within the tangent plane of the iso-surface, then back onto rho = 1; evens out the
+    short edges and thin triangles that survive edge collapse."""
+    nv = verts.shape[0]
+    E = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+    E = np.unique(np.concatenate([E, E[:, ::-1]]), axis=0)
+    deg = np.bincount(E[:, 0], minlength=nv).astype(np.float64)
+    for _ in range(iters):
+        acc = np.zeros_like(verts)
+        np.add.at(acc, E[:, 0], verts[E[:, 1]])
+        d = acc / deg[:, None] - verts
+        _, g = ag.eval(verts, grad=True)
+        n = g / np.linalg.norm(g, axis=1, keepdims=True)
+        d -= np.einsum("ij,ij->i", d, n)[:, None] * n
+        verts = _project_to_iso(ag, verts + lam * d, steps=6)
+    return verts
+
+
+def fill_cavities(verts, tri):
+    """Drops the closed components whose enclosed signed volume (outward normals) is not
+    positive: buried cavities of the density, which become part of the solute.  Outer
+    surfaces, also of separate blobs, enclose positive volume and are kept."""
+    tri = np.asarray(tri)
+    nv = verts.shape[0]
+    parent = np.arange(nv)
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for a, b, c in tri:
+        for u, v in ((a, b), (b, c)):
+            ru, rv = find(u), find(v)
+            if ru != rv:
+                parent[ru] = rv
+    root = np.array([find(i) for i in range(nv)])[tri[:, 0]]
+    A, B, C = verts[tri[:, 0]], verts[tri[:, 1]], verts[tri[:, 2]]
+    vol6 = np.einsum("ij,ij->i", A, np.cross(B, C))
+    keep_root = {r for r in np.unique(root) if vol6[root == r].sum() > 0.0}
+    keep = np.array([r in keep_root for r in root])
+    tri = tri[keep]
+    used = np.unique(tri)
+    remap = -np.ones(nv, dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    return verts[used], remap[tri]
+
+
+def crease_normals(verts, tri, nrm, cos_min: float = 0.3, passes: int = 3):
+    """At the vertices of triangles still folded against their vertex normals (fold cosine
+    below ``cos_min``), replaces the density-gradient normal by the area-weighted mean of
+    the incident face normals: in a crease narrower than the triangles, the gradient
+    describes the crease wall, not the triangulated surface the patches are built on."""
+    nrm = np.array(nrm, dtype=np.float64)
+    A, B, C = verts[tri[:, 0]], verts[tri[:, 1]], verts[tri[:, 2]]
+    fnw = np.cross(B - A, C - A)
+    vn = np.zeros_like(verts)
+    for k in range(3):
+        np.add.at(vn, tri[:, k], fnw)
+    vn /= np.linalg.norm(vn, axis=1, keepdims=True)
+    done = np.zeros(verts.shape[0], dtype=bool)
+    for _ in range(passes):
+        bad = _fold_cosine(verts, tri, nrm) < cos_min
+        vs = np.unique(tri[bad])
+        vs = vs[~done[vs]]
+        if vs.size == 0:
+            break
+        nrm[vs] = vn[vs]
+        done[vs] = True
+    return nrm
+
+
 def molecule_surface(centers, radii, grid: float = 0.5, pad: float = 3.0, decay=DENSITY_DECAY,
-                     refine_steps: int = 30, collapse: float = 0.25, flips: bool = True):
+                     refine_steps: int = 30, collapse: float = 0.25, smooth: int = 2, flips: bool = True,
+                     folds: bool = True, cavities: bool = False):
     """Iso-surface rho = 1 of rho(x) = sum_i exp(-decay (|x - c_i|^2 / r_i^2 - 1)), by
     marching tetrahedra on a grid of spacing ``grid`` over the bounding box padded by
     ``pad``.  Vertices are moved onto the iso-surface along their grid edge (bisection
     on the exact density); edges shorter than ``collapse * grid`` are collapsed (the
     slivers marching tetrahedra leaves near grid points) and the merged points projected
-    back onto the surface; normals are -grad rho / |grad rho|."""
+    back onto the surface; ``smooth`` rounds of tangential smoothing and Delaunay flips
+    then remove the thin triangles left over, and ``folds`` removes triangles folded across
+    creases; normals are -grad rho / |grad rho|, except at the vertices of folds that
+    remain (face-averaged there).  Buried cavities (closed components enclosing negative
+    volume) are filled unless ``cavities``."""
     ag = _AtomGrid(centers, radii, decay)
     lo = centers.min(axis=0) - radii.max() - pad
     hi = centers.max(axis=0) + radii.max() + pad
@@ -502,16 +711,21 @@ def molecule_surface(centers, radii, grid: float = 0.5, pad: float = 3.0, decay=
         hi_t = np.where(inside, hi_t, mid)
     tm = 0.5 * (lo_t + hi_t)
     verts = pin + tm[:, None] * (pout - pin)
+    if not cavities:
+        verts, tris = fill_cavities(verts, tris)
     if collapse > 0:
         verts, tris = collapse_short_edges(verts, tris, collapse * grid)
-        # merged points back onto rho = 1 along the gradient (Newton steps)
-        for _ in range(8):
-            rho, g = ag.eval(verts, grad=True)
-            verts = verts - ((rho - 1.0) / np.sum(g * g, axis=1))[:, None] * g
+        verts = _project_to_iso(ag, verts)     # merged points back onto rho = 1
+    if smooth > 0:
+        verts = tangential_smooth(ag, verts, np.asarray(tris), iters=smooth)
+    if folds:
+        verts, tris = remove_folds(ag, verts, tris)
     _, g = ag.eval(verts, grad=True)
     nrm = -g / np.linalg.norm(g, axis=1, keepdims=True)
     if flips:
         tris = delaunay_flips(verts, tris, nrm)
+    if folds:
+        nrm = crease_normals(verts, np.asarray(tris), nrm)
     return verts, nrm, tris.astype(np.int32)
 
 

@@ -29,12 +29,50 @@ def test_molecule_is_seeded():
 
 
 def test_vertices_lie_on_the_density_isosurface():
-    c, r, q = inputs.pack_atoms(12, inputs.protein_ball_radius(12), 3)
+    c, r, q = inputs.pack_atoms(20, inputs.protein_ball_radius(20), 11)
     xyz, nrm, tri = inputs.molecule_surface(c, r)
     ag = inputs._AtomGrid(c, r)
     rho, g = ag.eval(xyz, grad=True)
     np.testing.assert_allclose(rho, 1.0, atol=1e-8)
-    np.testing.assert_allclose(nrm, -g / np.linalg.norm(g, axis=1, keepdims=True), atol=1e-12)
+    grad_n = -g / np.linalg.norm(g, axis=1, keepdims=True)
+    same = np.all(np.abs(nrm - grad_n) < 1e-12, axis=1)
+    # the density-gradient normal everywhere but at a few crease vertices, where the
+    # normal is the area-weighted mean of the incident face normals
+    assert same.mean() > 0.99
+    A, B, C = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
+    fn = np.cross(B - A, C - A)
+    mean_fn = np.zeros_like(xyz)
+    for k in range(3):
+        np.add.at(mean_fn, tri[:, k], fn)
+    mean_fn /= np.linalg.norm(mean_fn, axis=1, keepdims=True)
+    np.testing.assert_allclose(nrm[~same], mean_fn[~same], atol=1e-12)
+
+
+def test_surface_has_no_folds_or_slivers():
+    """Every triangle agrees with its vertex normals (the curved patches are built from
+    them) and no angle is thinner than 5 degrees."""
+    for n, seed in ((30, 7), (60, 2)):
+        c, r, q = inputs.pack_atoms(n, inputs.protein_ball_radius(n), seed)
+        xyz, nrm, tri = inputs.molecule_surface(c, r)
+        assert inputs._fold_cosine(xyz, tri, nrm).min() > 0.0
+        assert inputs.mesh_quality(xyz, tri)[0] > 5.0
+
+
+def test_buried_cavities_are_filled_and_blobs_kept():
+    outer_x, outer_n, outer_t = inputs.icosphere(2, radius=4.0)
+    inner_x, inner_n, inner_t = inputs.icosphere(1, radius=1.0)
+    # a cavity: the inner sphere with its triangles turned inward (normals out of the solute)
+    x = np.vstack([outer_x, inner_x])
+    t = np.vstack([outer_t, inner_t[:, ::-1] + len(outer_x)])
+    xk, tk = inputs.fill_cavities(x, t)
+    assert len(tk) == len(outer_t) and len(xk) == len(outer_x)
+    np.testing.assert_array_equal(xk, outer_x)
+    # two separate blobs, both enclosing positive volume: both kept
+    far_x = inner_x + np.array([10.0, 0.0, 0.0])
+    x2 = np.vstack([outer_x, far_x])
+    t2 = np.vstack([outer_t, inner_t + len(outer_x)])
+    xk2, tk2 = inputs.fill_cavities(x2, t2)
+    assert len(tk2) == len(t2) and len(xk2) == len(x2)
 
 
 def test_atom_packing_respects_spacing():
