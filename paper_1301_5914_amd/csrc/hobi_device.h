@@ -26,6 +26,8 @@ struct alignas(64) NodeD {
     double nx, ny, nz, p;
 };
 
+constexpr int kCombineVerts = 64;   // vertices per tile of the combine step
+
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kInv4Pi = 1.0 / (4.0 * kPi);
 

@@ -70,9 +70,7 @@ __global__ void combine_kernel(const double* __restrict__ u, double* __restrict_
                                const int* __restrict__ inc_off, const int* __restrict__ inc_ent,
                                const int* __restrict__ tri, const double* __restrict__ coef,
                                double eps) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nv) return;
-    combine_vertex(i, u, y, nv, nv_pad, partial, chunks, inc_off, inc_ent, tri, coef, eps);
+    combine_tile(blockIdx.x, u, y, nv, nv_pad, partial, chunks, inc_off, inc_ent, tri, coef, eps);
 }
 
 // Sums over every regular node at interior points (the charges):
@@ -208,7 +206,7 @@ hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s) {
 
 hipError_t launch_combine(const DeviceProblem& p, const double* u, double* y, bool mixed, hipStream_t s) {
     const int chunks = mixed ? p.plan32.chunks : p.plan64.chunks;
-    hipLaunchKernelGGL(combine_kernel, dim3(nblk(p.nv, 256)), dim3(256), 0, s, u, y, p.nv, p.nv_pad,
+    hipLaunchKernelGGL(combine_kernel, dim3(nblk(p.nv, kCombineVerts)), dim3(kPairBlock), 0, s, u, y, p.nv, p.nv_pad,
                        p.partial, chunks, p.inc_off, p.inc_ent, p.tri, p.coef, p.eps);
     return hipGetLastError();
 }

@@ -300,17 +300,35 @@ __device__ __forceinline__ void pair_f64_tile(
     }
 }
 
-// Row pair (i, i + nv) of y = A u: chunk partials in order, singular correction, diagonal.
-__device__ __forceinline__ void combine_vertex(int i, const double* __restrict__ u, double* __restrict__ y, int nv,
-                                               int nv_pad, const double* __restrict__ partial, int chunks,
-                                               const int* __restrict__ inc_off, const int* __restrict__ inc_ent,
-                                               const int* __restrict__ tri, const double* __restrict__ coef,
-                                               double eps) {
+constexpr int kCombineWays = kPairBlock / kCombineVerts;  // waves splitting the chunk sum
+
+// Rows (i, i + nv) of y = A u for the kCombineVerts vertices of tile vb: the chunk partials
+// (wave s sums chunks s, s + 4, ...; the four sums are then added in a fixed order), the
+// singular correction and the diagonal.  Must be called by all kPairBlock threads of the
+// block (it synchronises them).
+__device__ __forceinline__ void combine_tile(int vb, const double* __restrict__ u, double* __restrict__ y, int nv,
+                                             int nv_pad, const double* __restrict__ partial, int chunks,
+                                             const int* __restrict__ inc_off, const int* __restrict__ inc_ent,
+                                             const int* __restrict__ tri, const double* __restrict__ coef,
+                                             double eps) {
+    static_assert(kCombineWays == 4, "four partial sums per vertex");
+    __shared__ double red[2][kCombineWays][kCombineVerts];
+    const int lane = threadIdx.x % kCombineVerts, way = threadIdx.x / kCombineVerts;
+    const int i = vb * kCombineVerts + lane;
     double r1 = 0.0, r2 = 0.0;
-    for (int c = 0; c < chunks; ++c) {
-        r1 += partial[(size_t)(2 * c) * nv_pad + i];
-        r2 += partial[(size_t)(2 * c + 1) * nv_pad + i];
+    if (i < nv) {
+        for (int c = way; c < chunks; c += kCombineWays) {
+            r1 += partial[(size_t)(2 * c) * nv_pad + i];
+            r2 += partial[(size_t)(2 * c + 1) * nv_pad + i];
+        }
     }
+    __syncthreads();                           // the previous tile's sums have been read
+    red[0][way][lane] = r1;
+    red[1][way][lane] = r2;
+    __syncthreads();
+    if (way != 0 || i >= nv) return;
+    r1 = (red[0][0][lane] + red[0][1][lane]) + (red[0][2][lane] + red[0][3][lane]);
+    r2 = (red[1][0][lane] + red[1][1][lane]) + (red[1][2][lane] + red[1][3][lane]);
     double c1 = 0.0, c2 = 0.0;
     for (int e = inc_off[i]; e < inc_off[i + 1]; ++e) {
         const int ent = inc_ent[e];

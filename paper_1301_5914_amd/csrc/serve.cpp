@@ -268,7 +268,7 @@ hobi_status tick(hobi_server sv) {
         const DeviceProblem& d = rp->pb->d;
         ng += (d.nn + kServeBlock - 1) / kServeBlock;
         np += (size_t)rp->plan.target_blocks * rp->plan.chunks;
-        nc += (d.nv + kServeBlock - 1) / kServeBlock;
+        nc += (d.nv + kCombineVerts - 1) / kCombineVerts;
     }
     // the three lists live at fixed offsets (thirds of the item buffer), so that the
     // captured launches stay valid until the buffer has to grow
@@ -311,7 +311,7 @@ hobi_status tick(hobi_server sv) {
         for (int blk = 0; blk < (d.nn + kServeBlock - 1) / kServeBlock; ++blk) gi[a++] = ServeItem{(int)q, blk, 0, 0};
         for (int ch = 0; ch < r.plan.chunks; ++ch)
             for (int tb = 0; tb < r.plan.target_blocks; ++tb) pi[b++] = ServeItem{(int)q, tb, ch, 0};
-        for (int blk = 0; blk < (d.nv + kServeBlock - 1) / kServeBlock; ++blk) ci[cc++] = ServeItem{(int)q, blk, 0, 0};
+        for (int blk = 0; blk < (d.nv + kCombineVerts - 1) / kCombineVerts; ++blk) ci[cc++] = ServeItem{(int)q, blk, 0, 0};
     }
     sv->h_counts[0] = (int)ng;
     sv->h_counts[1] = (int)np;

@@ -61,10 +61,8 @@ __global__ __launch_bounds__(kPairBlock) void batched_combine_kernel(const Serve
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const const_as<ServeItem>& item = as_constant(items)[uniform(it)];
         const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
-        const int i = item.a * kPairBlock + (int)threadIdx.x;
-        if (i < d.nv)
-            combine_vertex(i, d.u, d.y, d.nv, d.nv_pad, d.partial, d.chunks, d.inc_off, d.inc_ent, d.tri,
-                           d.coef, d.eps);
+        combine_tile(item.a, d.u, d.y, d.nv, d.nv_pad, d.partial, d.chunks, d.inc_off, d.inc_ent, d.tri, d.coef,
+                     d.eps);
     }
 }
 
