@@ -38,12 +38,19 @@ PAIR_F32_L6_TRAFFIC_BYTES = (30514.5 * 2.000 + 127680.0 * 1.000) * 1024
 
 def workload(args):
     from paper_1301_5914_amd import inputs
+    if args.mesh:
+        # a surface saved by a previous run of the same generator (xyz, nrm, tri, qpos, q)
+        d = np.load(args.mesh)
+        return inputs.Problem(d["xyz"], d["nrm"], d["tri"].astype(np.int32), d["qpos"], d["q"],
+                              name=os.path.basename(args.mesh))
     if args.workload == "molecule":
         return inputs.molecule(args.atoms, seed=args.seed)
     return inputs.kirkwood_offcenter(args.level)
 
 
 def workload_name(args, prob):
+    if args.mesh:
+        return f"surface loaded from {prob.name} ({args.mesh_label or 'saved surface'}), {prob.nf} triangles"
     if args.workload == "molecule":
         return (f"protein-like surface, {args.atoms} atoms (seed {args.seed}) at protein density, "
                 f"Gaussian density marched at 0.5 A, {prob.nf} triangles")
@@ -84,8 +91,17 @@ def build_pool(n_mol, min_atoms, max_atoms, seed, workers):
     rng = np.random.default_rng(seed)
     atoms = np.round(np.exp(rng.uniform(np.log(min_atoms), np.log(max_atoms), n_mol))).astype(int)
     jobs = [(int(a), 1000 + i) for i, a in enumerate(atoms)]
+    out = [None] * n_mol
     with mp.get_context("fork").Pool(max(1, min(workers, n_mol))) as pool:
-        return pool.starmap(_make_molecule, jobs)
+        for done, (k, m) in enumerate(pool.imap_unordered(_make_molecule_job, list(enumerate(jobs)))):
+            out[k] = m
+            print(f"[bench] pool molecule {done + 1}/{n_mol}: {m.nf} triangles", file=sys.stderr, flush=True)
+    return out
+
+
+def _make_molecule_job(indexed_job):
+    k, job = indexed_job
+    return k, _make_molecule(*job)
 
 
 def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slots, n_check):
@@ -136,6 +152,8 @@ def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slot
             if r is not None:
                 results[t] = r
                 lat.append(time.perf_counter() - sub_time[t][0])
+                if len(results) % 32 == 0:
+                    print(f"[bench] served {len(results)}/{n_requests}", file=sys.stderr, flush=True)
         time.sleep(0.0002)
     wall = time.perf_counter() - start
     st = sv.stats()
@@ -149,6 +167,8 @@ def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slot
         ref = hobi.Problem(ctx, m.xyz, m.nrm, m.tri, m.qpos, m.q, eps1=e1, eps2=m.eps2, kappa=kap,
                            max_iter=400, restart=400).solve(allow_noconv=True)
         errs.append(abs(results[t]["energy"] / ref["energy"] - 1))
+        print(f"[bench] check {len(errs)}/{n_check}: {m.nf} triangles, energy error {errs[-1]:.2e}",
+              file=sys.stderr, flush=True)
         checks.append({"nf": m.nf, "eps1": e1, "kappa": kap, "err": errs[-1],
                        "its": results[t]["stats"]["iterations"], "its_fp64": ref["stats"]["iterations"],
                        "status": results[t]["status"], "status_fp64": ref["status"],
@@ -180,6 +200,9 @@ def main():
     ap.add_argument("--seed", type=int, default=3, help="packing seed (molecule)")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--max-iter", type=int, default=400, help="GMRES iteration cap (unrestarted)")
+    ap.add_argument("--mesh", default=None,
+                    help="load the surface and charges from an .npz (xyz, nrm, tri, qpos, q) instead of generating")
+    ap.add_argument("--mesh-label", default=None, help="description of the loaded surface for the JSON line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
@@ -242,7 +265,7 @@ def main():
     peak = PEAK_TFLOPS[args.precision]
     E = results[-1]["energy"]
     E_exact = None
-    if args.workload == "kirkwood":
+    if args.workload == "kirkwood" and not args.mesh:
         E_exact = KW.solvation_energy(prob.qpos, prob.q, 4.0, prob.eps1, prob.eps2, prob.kappa)
     out = {
         "metric": "matvec G-pairs/s + GMRES solve time to 1e-6; serving p50/p99 latency",
@@ -272,7 +295,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": (PAIR_F32_L6_TRAFFIC_BYTES
-                                 if (mixed and args.workload == "kirkwood" and args.level == 6) else None),
+                                 if (mixed and args.workload == "kirkwood" and args.level == 6 and not args.mesh)
+                                 else None),
                      "frac_nonpacked_fp32": achieved / PEAK_NONPACKED_FP32 if mixed else None,
                      "kernel": "pair_f32_kernel" if mixed else "pair_f64_kernel",
                      "flops_per_pair": FLOPS_PER_PAIR[prob.kappa > 0]},

@@ -38,8 +38,7 @@ struct Request {
     int64_t footprint = 0;
     // device state while active
     hobi_problem pb = nullptr;
-    PairPlan plan{};
-    double* partial = nullptr;
+    PairPlan plan{};        // the problem's own pair plan (its partial-sum buffer is reused)
     double *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
     double *h1 = nullptr, *h2 = nullptr, *hn = nullptr, *yk = nullptr, *dpart = nullptr;
     double *x = nullptr, *scal = nullptr;
@@ -62,28 +61,26 @@ hipError_t dalloc(T** p, size_t n) {
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 // Device bytes of one admitted request (the allocations of hobi_problem_create plus the
-// server's partial sums and Krylov basis), from its sizes alone.
-int64_t footprint_bytes(int nv, int nf, int nc, int m, bool mixed) {
+// server's Krylov basis), from its sizes alone.
+int64_t footprint_bytes(int nv, int nf, int nc, int m) {
     const int64_t nv_pad = round_up(nv, 2048), nc_pad = round_up(nc, 256), nn = 4LL * nf;
     const PairPlan p64 = make_plan((int)nv_pad, (int)nn, kTpl64), p32 = make_plan((int)nv_pad, (int)nn, nv_pad >= 16384 ? 8 : 4);
     const PairPlan pp = make_plan((int)nc_pad, (int)nn, 1);
-    const PairPlan ps = make_plan((int)nv_pad, (int)nn, mixed ? kServeTpl32 : kServeTpl64);
     int64_t b = 0;
     b += 8 * (6LL * nv + 4LL * nc + 3 * nc_pad + 30LL * nf + 4 * nn + 12 * nv_pad + 36LL * nf + 2LL * nv + 4LL * nv);
     b += (int64_t)sizeof(NodeD) * nn + (int64_t)sizeof(NodeF) * nn + 16 * nn + 8 * (nn / 64 + 1);
     b += 4 * (3LL * nf + nv + 1 + 3LL * nf + nv + nf) + 2LL * 4 * nv_pad;
     b += 8 * std::max<int64_t>(2 * nv_pad * std::max(p64.chunks, p32.chunks), nc_pad * pp.chunks);
-    b += 8 * 2 * nv_pad * (int64_t)ps.chunks;
     const int64_t n = 2LL * nv;
     b += 8 * ((int64_t)(m + 1) * n + (int64_t)(m + 1) * m + 6LL * (m + 1) + kDotBlocks * (int64_t)(m + 1) + n + 8);
     return b;
 }
 
 void free_request_device(Request& r) {
-    double* ptrs[] = {r.partial, r.V, r.H, r.cs, r.sn, r.g, r.h1, r.h2, r.hn, r.yk, r.dpart, r.x, r.scal};
+    double* ptrs[] = {r.V, r.H, r.cs, r.sn, r.g, r.h1, r.h2, r.hn, r.yk, r.dpart, r.x, r.scal};
     for (double* p : ptrs)
         if (p) (void)hipFree(p);
-    r.partial = r.V = r.H = r.cs = r.sn = r.g = r.h1 = r.h2 = r.hn = r.yk = r.dpart = r.x = r.scal = nullptr;
+    r.V = r.H = r.cs = r.sn = r.g = r.h1 = r.h2 = r.hn = r.yk = r.dpart = r.x = r.scal = nullptr;
     if (r.pb) hobi_problem_destroy(r.pb);
     r.pb = nullptr;
 }
@@ -146,7 +143,7 @@ hobi_status admit(hobi_server sv, Request& r) {
     }
     const bool mixed = r.prm.precision == HOBI_MIXED;
     const DeviceProblem& d = r.pb->d;
-    r.plan = make_plan(d.nv_pad, d.nn, mixed ? kServeTpl32 : kServeTpl64);
+    r.plan = mixed ? d.plan32 : d.plan64;
     r.m = std::max(1, r.prm.max_iter);
     const int n = 2 * r.nv, m = r.m;
     hipError_t e = hipSuccess;
@@ -155,7 +152,6 @@ hobi_status admit(hobi_server sv, Request& r) {
         fail_request(r, e == hipErrorOutOfMemory ? HOBI_E_OOM : HOBI_E_HIP, #expr); \
         return r.status;                                                           \
     }
-    SA(dalloc(&r.partial, 2 * (size_t)d.nv_pad * r.plan.chunks));
     SA(dalloc(&r.V, (size_t)(m + 1) * n));
     SA(dalloc(&r.H, (size_t)(m + 1) * m));
     SA(dalloc(&r.cs, m));
@@ -262,23 +258,26 @@ hipError_t ensure_capacity(hobi_server sv, size_t ndesc, size_t nitems) {
 hobi_status tick(hobi_server sv) {
     hipStream_t s = sv->ctx->stream;
     const size_t na = sv->active.size();
-    // work lists: gather items, then pair items, then combine items
-    size_t ng = 0, np = 0, nc = 0;
+    // work lists: gather items, FP32 pair items, FP64 pair items, combine items
+    size_t cnt[4] = {0, 0, 0, 0};
     for (auto& rp : sv->active) {
         const DeviceProblem& d = rp->pb->d;
-        ng += (d.nn + kServeBlock - 1) / kServeBlock;
-        np += (size_t)rp->plan.target_blocks * rp->plan.chunks;
-        nc += (d.nv + kCombineVerts - 1) / kCombineVerts;
+        cnt[0] += (d.nn + kServeBlock - 1) / kServeBlock;
+        cnt[rp->prm.precision == HOBI_MIXED ? 1 : 2] += (size_t)rp->plan.target_blocks * rp->plan.chunks;
+        cnt[3] += (d.nv + kCombineVerts - 1) / kCombineVerts;
     }
-    // the three lists live at fixed offsets (thirds of the item buffer), so that the
+    // the four lists live at fixed offsets (quarters of the item buffer), so that the
     // captured launches stay valid until the buffer has to grow
-    hipError_t e = ensure_capacity(sv, na, 3 * std::max(std::max(ng, np), nc));
+    hipError_t e = ensure_capacity(sv, na, 4 * std::max(std::max(cnt[0], cnt[1]), std::max(cnt[2], cnt[3])));
     if (e != hipSuccess) return host_fail(sv->ctx, HOBI_E_OOM, "server work-list allocation failed");
-    const size_t t3 = sv->cap_items / 3;
-    ServeItem* gi = sv->h_items;
-    ServeItem* pi = sv->h_items + t3;
-    ServeItem* ci = sv->h_items + 2 * t3;
-    size_t a = 0, b = 0, cc = 0;
+    const size_t t4 = sv->cap_items / 4;
+    ServeItem* hl[4];
+    const ServeItem* dl[4];
+    for (int l = 0; l < 4; ++l) {
+        hl[l] = sv->h_items + l * t4;
+        dl[l] = sv->d_items + l * t4;
+    }
+    size_t fill[4] = {0, 0, 0, 0};
     for (size_t q = 0; q < na; ++q) {
         Request& r = *sv->active[q];
         const DeviceProblem& d = r.pb->d;
@@ -294,7 +293,7 @@ hobi_status tick(hobi_server sv) {
         sd.blk_range = d.blk_range;
         sd.tgt32 = d.tgt32;
         sd.tgt64 = d.tgt64;
-        sd.partial = r.partial;
+        sd.partial = d.partial;
         sd.inc_off = d.inc_off;
         sd.inc_ent = d.inc_ent;
         sd.coef = d.coef;
@@ -307,25 +306,24 @@ hobi_status tick(hobi_server sv) {
         sd.chunk = r.plan.chunk;
         sd.chunks = r.plan.chunks;
         sd.mixed = r.prm.precision == HOBI_MIXED ? 1 : 0;
-        sd.pad = 0;
-        for (int blk = 0; blk < (d.nn + kServeBlock - 1) / kServeBlock; ++blk) gi[a++] = ServeItem{(int)q, blk, 0, 0};
+        sd.tpl = r.plan.tpl;
+        for (int blk = 0; blk < (d.nn + kServeBlock - 1) / kServeBlock; ++blk)
+            hl[0][fill[0]++] = ServeItem{(int)q, blk, 0, 0};
+        const int pl = sd.mixed ? 1 : 2;
         for (int ch = 0; ch < r.plan.chunks; ++ch)
-            for (int tb = 0; tb < r.plan.target_blocks; ++tb) pi[b++] = ServeItem{(int)q, tb, ch, 0};
-        for (int blk = 0; blk < (d.nv + kCombineVerts - 1) / kCombineVerts; ++blk) ci[cc++] = ServeItem{(int)q, blk, 0, 0};
+            for (int tb = 0; tb < r.plan.target_blocks; ++tb) hl[pl][fill[pl]++] = ServeItem{(int)q, tb, ch, 0};
+        for (int blk = 0; blk < (d.nv + kCombineVerts - 1) / kCombineVerts; ++blk)
+            hl[3][fill[3]++] = ServeItem{(int)q, blk, 0, 0};
     }
-    sv->h_counts[0] = (int)ng;
-    sv->h_counts[1] = (int)np;
-    sv->h_counts[2] = (int)nc;
-    if ((e = hipMemcpyAsync(sv->d_desc, sv->h_desc, na * sizeof(ServeDesc), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(sv->d_items, gi, ng * sizeof(ServeItem), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(sv->d_items + t3, pi, np * sizeof(ServeItem), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(sv->d_items + 2 * t3, ci, nc * sizeof(ServeItem), hipMemcpyHostToDevice, s)) !=
-            hipSuccess ||
-        (e = hipMemcpyAsync(sv->d_counts, sv->h_counts, 3 * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess)
+    for (int l = 0; l < 4; ++l) sv->h_counts[l] = (int)cnt[l];
+    if ((e = hipMemcpyAsync(sv->d_desc, sv->h_desc, na * sizeof(ServeDesc), hipMemcpyHostToDevice, s)) != hipSuccess)
         return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
-    const ServeItem* dg = sv->d_items;
-    const ServeItem* dp = sv->d_items + t3;
-    const ServeItem* dc = sv->d_items + 2 * t3;
+    for (int l = 0; l < 4; ++l)
+        if (cnt[l] && (e = hipMemcpyAsync((void*)dl[l], hl[l], cnt[l] * sizeof(ServeItem), hipMemcpyHostToDevice,
+                                          s)) != hipSuccess)
+            return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
+    if ((e = hipMemcpyAsync(sv->d_counts, sv->h_counts, 4 * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
     if (sv->use_graph) {
         if (sv->graph_dirty || !sv->graph_exec) {
             if (sv->graph_exec) (void)hipGraphExecDestroy(sv->graph_exec);
@@ -334,8 +332,7 @@ hobi_status tick(hobi_server sv) {
             sv->graph = nullptr;
             if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                 return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
-            const hipError_t le =
-                launch_batched_matvec(sv->d_desc, dg, sv->d_counts, dp, sv->d_counts + 1, dc, sv->d_counts + 2, s);
+            const hipError_t le = launch_batched_matvec(sv->d_desc, dl, sv->d_counts, s);
             e = hipStreamEndCapture(s, &sv->graph);
             if (le != hipSuccess || e != hipSuccess)
                 return host_fail(sv->ctx, HOBI_E_HIP, "graph capture of the batched matvec failed");
@@ -345,8 +342,7 @@ hobi_status tick(hobi_server sv) {
         }
         if ((e = hipGraphLaunch(sv->graph_exec, s)) != hipSuccess)
             return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
-    } else if ((e = launch_batched_matvec(sv->d_desc, dg, sv->d_counts, dp, sv->d_counts + 1, dc, sv->d_counts + 2,
-                                          s)) != hipSuccess) {
+    } else if ((e = launch_batched_matvec(sv->d_desc, dl, sv->d_counts, s)) != hipSuccess) {
         return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
     }
     // per-request Gram-Schmidt (two passes), normalisation and Givens update
@@ -507,7 +503,7 @@ hobi_status hobi_server_submit(hobi_server sv, int32_t nv, const double* xyz, co
     hobi_params_default(&r->prm);
     if (params) r->prm = *params;
     r->prm.restart = r->prm.max_iter;
-    r->footprint = footprint_bytes(nv, nf, nc, std::max(1, r->prm.max_iter), r->prm.precision == HOBI_MIXED);
+    r->footprint = footprint_bytes(nv, nf, nc, std::max(1, r->prm.max_iter));
     std::lock_guard<std::mutex> lk(sv->mu);
     if (r->footprint > sv->budget) {
         sv->last_error = "request footprint exceeds the server budget";

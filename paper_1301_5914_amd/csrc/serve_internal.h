@@ -8,8 +8,6 @@
 namespace hobi {
 
 constexpr int kServeBlock = 256;       // threads per block of the batched kernels
-constexpr int kServeTpl32 = 4;        // targets per lane of served FP32 tiles
-constexpr int kServeTpl64 = 2;        // targets per lane of served FP64 tiles
 constexpr int kServeGridPair = 2048;  // fixed grids: the kernels walk the item lists
 constexpr int kServeGridSmall = 1024;
 
@@ -35,7 +33,7 @@ struct ServeDesc {
     int nv, nv_pad, nn;
     int chunk, chunks;
     int mixed;
-    int pad;
+    int tpl;                // targets per lane of the request's pair plan (the single-problem plan)
 };
 
 // One unit of work: request `req`; (a, b) = (target block, chunk) for the pair kernel,
@@ -44,8 +42,8 @@ struct ServeItem {
     int req, a, b, pad;
 };
 
-hipError_t launch_batched_matvec(const ServeDesc* desc, const ServeItem* gather_items, const int* n_gather,
-                                 const ServeItem* pair_items, const int* n_pair, const ServeItem* comb_items,
-                                 const int* n_comb, hipStream_t s);
+// Item lists and their counts, in launch order: gather, FP32 pair, FP64 pair, combine.
+hipError_t launch_batched_matvec(const ServeDesc* desc, const ServeItem* const items[4], const int* counts,
+                                 hipStream_t s);
 
 }  // namespace hobi

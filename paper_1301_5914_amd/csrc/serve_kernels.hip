@@ -12,6 +12,7 @@
 namespace hobi {
 
 static_assert(kServeBlock == kPairBlock, "served work items are pair-kernel blocks");
+static_assert(kTpl64 == 2, "served FP64 tiles use the single-problem plan");
 
 namespace {
 
@@ -29,28 +30,47 @@ __global__ __launch_bounds__(kPairBlock) void batched_gather_kernel(const ServeD
     }
 }
 
-__global__ __launch_bounds__(kPairBlock) void batched_pair_kernel(const ServeDesc* __restrict__ desc,
-                                                                const ServeItem* __restrict__ items,
-                                                                const int* __restrict__ count) {
+// FP32 and FP64 items go to separate launches, so that each kernel's register budget is
+// that of its own tile (the FP32 one then keeps the occupancy of the single-problem kernel).
+// At most 128 registers: the four tile shapes share one kernel, which would otherwise take
+// more registers than the largest of them and lose a wave per SIMD.
+__global__ __launch_bounds__(kPairBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void batched_pair32_kernel(
+    const ServeDesc* __restrict__ desc, const ServeItem* __restrict__ items, const int* __restrict__ count) {
     const int n = as_constant(count)[0];
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const const_as<ServeItem>& item = as_constant(items)[uniform(it)];
         const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
-        if (d.mixed) {
+        if (d.tpl == 8) {
             if (d.kappa == 0.0)
-                pair_f32_tile<kServeTpl32, true>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk,
-                                                 d.partial, item.a, item.b);
+                pair_f32_tile<8, true>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk, d.partial,
+                                       item.a, item.b);
             else
-                pair_f32_tile<kServeTpl32, false>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk,
-                                                  d.partial, item.a, item.b);
+                pair_f32_tile<8, false>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk,
+                                        d.partial, item.a, item.b);
         } else {
             if (d.kappa == 0.0)
-                pair_f64_tile<kServeTpl64, true>(d.tgt64, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.nn, d.chunk, d.kappa, d.eps,
-                                                 d.partial, item.a, item.b);
+                pair_f32_tile<4, true>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk, d.partial,
+                                       item.a, item.b);
             else
-                pair_f64_tile<kServeTpl64, false>(d.tgt64, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.nn, d.chunk, d.kappa, d.eps,
-                                                  d.partial, item.a, item.b);
+                pair_f32_tile<4, false>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk,
+                                        d.partial, item.a, item.b);
         }
+    }
+}
+
+__global__ __launch_bounds__(kPairBlock) void batched_pair64_kernel(const ServeDesc* __restrict__ desc,
+                                                                  const ServeItem* __restrict__ items,
+                                                                  const int* __restrict__ count) {
+    const int n = as_constant(count)[0];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const const_as<ServeItem>& item = as_constant(items)[uniform(it)];
+        const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
+        if (d.kappa == 0.0)
+            pair_f64_tile<kTpl64, true>(d.tgt64, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.nn, d.chunk, d.kappa,
+                                        d.eps, d.partial, item.a, item.b);
+        else
+            pair_f64_tile<kTpl64, false>(d.tgt64, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.nn, d.chunk,
+                                         d.kappa, d.eps, d.partial, item.a, item.b);
     }
 }
 
@@ -68,18 +88,19 @@ __global__ __launch_bounds__(kPairBlock) void batched_combine_kernel(const Serve
 
 }  // namespace
 
-hipError_t launch_batched_matvec(const ServeDesc* desc, const ServeItem* gather_items, const int* n_gather,
-                                 const ServeItem* pair_items, const int* n_pair, const ServeItem* comb_items,
-                                 const int* n_comb, hipStream_t s) {
-    hipLaunchKernelGGL(batched_gather_kernel, dim3(kServeGridSmall), dim3(kPairBlock), 0, s, desc, gather_items,
-                       n_gather);
+hipError_t launch_batched_matvec(const ServeDesc* desc, const ServeItem* const items[4], const int* counts,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(batched_gather_kernel, dim3(kServeGridSmall), dim3(kPairBlock), 0, s, desc, items[0], counts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batched_pair_kernel, dim3(kServeGridPair), dim3(kPairBlock), 0, s, desc, pair_items,
-                       n_pair);
+    hipLaunchKernelGGL(batched_pair32_kernel, dim3(kServeGridPair), dim3(kPairBlock), 0, s, desc, items[1],
+                       counts + 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(batched_combine_kernel, dim3(kServeGridSmall), dim3(kPairBlock), 0, s, desc, comb_items,
-                       n_comb);
+    hipLaunchKernelGGL(batched_pair64_kernel, dim3(kServeGridPair), dim3(kPairBlock), 0, s, desc, items[2],
+                       counts + 2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(batched_combine_kernel, dim3(kServeGridSmall), dim3(kPairBlock), 0, s, desc, items[3],
+                       counts + 3);
     return hipGetLastError();
 }
 
