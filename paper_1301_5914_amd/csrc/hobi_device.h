@@ -21,9 +21,11 @@ struct alignas(64) NodeF {
     float ga, gb, pa, pb;
     float qx, qy, qz, pad;   // p * (nx, ny, nz)
 };
-struct alignas(64) NodeD {
+struct alignas(128) NodeD {
     double x, y, z, g;
     double nx, ny, nz, p;
+    double ga, gb, pa, pb;   // Gamma, Phi times the epsilon factors of K3, K2
+    double qx, qy, qz, pad;  // Phi * (nx, ny, nz)
 };
 
 constexpr int kCombineVerts = 64;   // vertices per tile of the combine step
@@ -234,16 +236,20 @@ __device__ __forceinline__ double exp_neg_f64(double z) {
     const double n = __builtin_rint(z * kLog2e);
     double t = fma(n, kLn2Hi, -z);
     t = fma(n, kLn2Lo, t);
-    // Estrin's scheme: pairs of terms, then powers t^2, t^4, t^8
-    constexpr double c2 = 1.0 / 2, c3 = 1.0 / 6, c4 = 1.0 / 24, c5 = 1.0 / 120, c6 = 1.0 / 720,
-                     c7 = 1.0 / 5040, c8 = 1.0 / 40320, c9 = 1.0 / 362880, c10 = 1.0 / 3628800,
-                     c11 = 1.0 / 39916800, c12 = 1.0 / 479001600;
-    const double t2 = t * t, t4 = t2 * t2, t8 = t4 * t4;
-    const double p01 = fma(t, 1.0, 1.0), p23 = fma(t, c3, c2), p45 = fma(t, c5, c4), p67 = fma(t, c7, c6),
-                 p89 = fma(t, c9, c8), p1011 = fma(t, c11, c10);
-    const double q03 = fma(t2, p23, p01), q47 = fma(t2, p67, p45), q811 = fma(t2, p1011, p89);
-    const double r07 = fma(t4, q47, q03), r812 = fma(t4, c12, q811);
-    const double p = fma(t8, r812, r07);
+    // Horner's scheme (fewest operations; callers have independent work to hide its latency)
+    double p = 1.0 / 479001600.0;
+    p = fma(p, t, 1.0 / 39916800.0);
+    p = fma(p, t, 1.0 / 3628800.0);
+    p = fma(p, t, 1.0 / 362880.0);
+    p = fma(p, t, 1.0 / 40320.0);
+    p = fma(p, t, 1.0 / 5040.0);
+    p = fma(p, t, 1.0 / 720.0);
+    p = fma(p, t, 1.0 / 120.0);
+    p = fma(p, t, 1.0 / 24.0);
+    p = fma(p, t, 1.0 / 6.0);
+    p = fma(p, t, 0.5);
+    p = fma(p, t, 1.0);
+    p = fma(p, t, 1.0);
     return __builtin_amdgcn_ldexp(p, -(int)n);
 }
 

@@ -40,6 +40,8 @@ __device__ __forceinline__ NodeD load_node(const const_as<NodeD>* p, int s) {
     NodeD n;
     n.x = p[s].x, n.y = p[s].y, n.z = p[s].z, n.g = p[s].g;
     n.nx = p[s].nx, n.ny = p[s].ny, n.nz = p[s].nz, n.p = p[s].p;
+    n.ga = p[s].ga, n.gb = p[s].gb, n.pa = p[s].pa, n.pb = p[s].pb;
+    n.qx = p[s].qx, n.qy = p[s].qy, n.qz = p[s].qz, n.pad = 0.0;
     return n;
 }
 
@@ -59,8 +61,10 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, cons
                                              const float (&tny)[TPL], const float (&tnz)[TPL],
                                              float (&a1)[TPL], float (&a2)[TPL]) {
     constexpr float kLn2 = 0.693147180559945309f;
+    NodeF n = load_node(cnodes, sb);
     for (int s = sb; s < se; ++s) {
-        const NodeF n = load_node(cnodes, s);
+        // the next record's scalar load is in flight while this one is used
+        const NodeF next = load_node(cnodes, min(s + 1, se - 1));
         int4 vid = make_int4(-1, -1, -1, 0);
         if (MASK) vid = load_vid(cvid, s);
 #pragma unroll
@@ -92,6 +96,7 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, cons
                 a2[k] = fmaf(rinv2 * rinv, fmaf(-pnxy, f1, dnx * t), a2[k]);
             }
         }
+        n = next;
     }
 }
 
@@ -170,8 +175,18 @@ __device__ __forceinline__ void gather_node(int idx, const double* __restrict__ 
     const double pp = L0 * u[v0] + L1 * u[v1] + L2 * u[v2];
     const double sc = w[idx] * kInv4Pi;
     const double g = sc * dp, p = sc * pp;
-    node64[idx].g = g;
-    node64[idx].p = p;
+    {
+        NodeD& n = node64[idx];
+        n.g = g;
+        n.p = p;
+        n.ga = -(1.0 - 1.0 / eps) * g;
+        n.gb = -g / eps;
+        n.pa = (eps - 1.0) * p;
+        n.pb = -eps * p;
+        n.qx = p * n.nx;
+        n.qy = p * n.ny;
+        n.qz = p * n.nz;
+    }
     if (mixed) {
         NodeF& n = node32[idx];
         const double s2 = s32 * s32, s3 = s2 * s32;
@@ -187,10 +202,11 @@ __device__ __forceinline__ void gather_node(int idx, const double* __restrict__ 
     }
 }
 
-// FP64 pairs of nodes [sb, se) with the lane's TPL targets.  Per pair (kappa > 0) about 70
+// FP64 pairs of nodes [sb, se) with the lane's TPL targets.  Per pair (kappa > 0) about 62
 // VALU operations: the exponential and reciprocal square root of hobi_device.h, the closed
 // forms of f0, f1, f2, and their power series where kappa r < kSeriesZ64 (rare: only nodes
-// near the wave's targets).  With MASK, pairs of a vertex with its own triangles' nodes are
+// near the wave's targets); the rows as in the FP32 tile, with the strengths pre-multiplied
+// by the epsilon factors.  With MASK, pairs of a vertex with its own triangles' nodes are
 // skipped.
 template <int TPL, bool KAPPA0, bool MASK>
 __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, const const_as<int4>* cvid, int sb,
@@ -198,9 +214,8 @@ __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, cons
                                              const double (&tz)[TPL], const double (&tnx)[TPL],
                                              const double (&tny)[TPL], const double (&tnz)[TPL], double kappa,
                                              double eps, double (&a1)[TPL], double (&a2)[TPL]) {
-    const double em1 = eps - 1.0, ce3 = 1.0 - 1.0 / eps, ie = 1.0 / eps;
     for (int s = sb; s < se; ++s) {
-        const NodeD nd = load_node(cnodes, s);
+        const NodeD nd = load_node(cnodes, s);   // (a prefetched FP64 record would not fit the scalar registers)
         int4 vid = make_int4(-1, -1, -1, 0);
         if (MASK) vid = load_vid(cvid, s);
 #pragma unroll
@@ -213,14 +228,14 @@ __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, cons
                 if ((t == vid.x) | (t == vid.y) | (t == vid.z)) rinv = 0.0;
             }
             const double rinv2 = rinv * rinv;
-            const double rinv3 = rinv2 * rinv;
             const double dny = fma(dx, nd.nx, fma(dy, nd.ny, dz * nd.nz));
             const double dnx = fma(dx, tnx[k], fma(dy, tny[k], dz * tnz[k]));
             if (KAPPA0) {
-                a1[k] = fma(em1 * dny * rinv3, nd.p, a1[k]);
-                a2[k] = fma(-ce3 * dnx * rinv3, nd.g, a2[k]);
+                const double rinv3 = rinv2 * rinv;
+                a1[k] = fma(dny * rinv3, nd.pa, a1[k]);
+                a2[k] = fma(dnx * rinv3, nd.ga, a2[k]);
             } else {
-                const double nxy = fma(tnx[k], nd.nx, fma(tny[k], nd.ny, tnz[k] * nd.nz));
+                const double pnxy = fma(tnx[k], nd.qx, fma(tny[k], nd.qy, tnz[k] * nd.qz));
                 const double z = kappa * (r2 * rinv);
                 const double e = exp_neg_f64(z);
                 double f0 = 1.0 - e;
@@ -240,12 +255,11 @@ __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, cons
                     f1 = s1 * z * z;
                     f2 = s2 * z * z;
                 }
-                const double K1 = f0 * rinv;
-                const double K2 = dny * rinv3 * fma(-eps, f1, em1);
-                const double K3 = -dnx * rinv3 * fma(f1, ie, ce3);
-                const double K4 = fma(dnx * dny * f2, rinv2, -nxy * f1) * rinv3;
-                a1[k] = fma(K1, nd.g, fma(K2, nd.p, a1[k]));
-                a2[k] = fma(K3, nd.g, fma(K4, nd.p, a2[k]));
+                // the FP32 tile's row algebra: q = (d.ny)/r^2, P = Phi ny
+                const double q = dny * rinv2;
+                a1[k] = fma(rinv, fma(q, fma(nd.pb, f1, nd.pa), nd.g * f0), a1[k]);
+                const double t = fma(nd.p, q * f2, fma(nd.gb, f1, nd.ga));
+                a2[k] = fma(rinv2 * rinv, fma(-pnxy, f1, dnx * t), a2[k]);
             }
         }
     }

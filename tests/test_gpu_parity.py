@@ -223,10 +223,8 @@ def mol30():
 
 
 def test_molecule_matvec_matches_oracle(ctx, mol30):
-    """Protein-like marched surface (30 atoms): FP64 to 1e-12 on sampled rows.  The mixed
-    matvec on a random (sign-alternating) vector is held to 1e-4: near pairs of sliver-like
-    marched triangles carry terms ~50x the row value, each rounded in FP32; the 1e-5 bar of
-    the mixed mode is on the solvation energy (next test)."""
+    """Protein-like marched surface (30 atoms): FP64 to 1e-12 and mixed to 1e-5 on sampled
+    rows of a random (sign-alternating) vector."""
     p = mol30
     print(f"molecule nv={p.nv} nf={p.nf}", flush=True)
     st = O.setup(p.xyz, p.nrm, p.tri)
@@ -234,7 +232,7 @@ def test_molecule_matvec_matches_oracle(ctx, mol30):
     rng = np.random.default_rng(0)
     rows = np.unique(np.r_[0:30, p.nv - 30:p.nv, rng.integers(0, p.nv, 60)])
     y_or = O.matvec(st, u, p.kappa, p.eps2 / p.eps1, rows=rows)
-    for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-4)):
+    for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
         g = hobi.Problem.from_inputs(ctx, p, precision=prec)
         y = g.matvec(u)
         got = np.stack([y[rows], y[p.nv + rows]])
@@ -251,3 +249,73 @@ def test_molecule_solve_mixed_matches_fp64(ctx, mol30):
           "its", r32["stats"]["iterations"])
     assert abs(r32["energy"] / r64["energy"] - 1) <= 1e-5
     assert r64["stats"]["converged"] == 1 and r32["stats"]["converged"] == 1
+
+
+# ---- the bench workloads at their full sizes, in the launch configuration bench.py times
+
+@pytest.fixture(scope="module")
+def l6():
+    return inputs.kirkwood_offcenter(6)
+
+
+def test_bench_workload_L6_sampled_rows(ctx, l6):
+    """Default bench workload at full size (40962 vertices, 327680 nodes; 8 targets per lane,
+    ~4096 XCD-remapped blocks): rows spread over the first and last target blocks, tile
+    boundaries and random positions, against the oracle computed row by row."""
+    p = l6
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    u = inputs.random_vector(2 * p.nv, 31)
+    rng = np.random.default_rng(1)
+    rows = np.unique(np.r_[0:4, p.nv - 4:p.nv, 2046:2050, 16382:16386, rng.integers(0, p.nv, 16)])
+    y_or = O.matvec(st, u, p.kappa, p.eps2 / p.eps1, rows=rows)
+    for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
+        g = hobi.Problem.from_inputs(ctx, p, precision=prec)
+        y = g.matvec(u)
+        got = np.stack([y[rows], y[p.nv + rows]])
+        err = _rel_inf(got, y_or)
+        print(f"L6 precision {prec} rel err {err:.3e}", flush=True)
+        assert err <= tol
+
+
+def test_bench_workload_L6_energy(ctx, l6):
+    """Full L6 solves: mixed within 1e-5 of FP64 (the mixed-mode bar), FP64 within the
+    discretisation error of the Kirkwood series (6e-5 measured at L6; O(h^2) from L1-L4)."""
+    p = l6
+    r64 = hobi.Problem.from_inputs(ctx, p, max_iter=400, restart=400).solve()
+    r32 = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED, max_iter=400, restart=400).solve()
+    E = KW.solvation_energy(p.qpos, p.q, 4.0, p.eps1, p.eps2, p.kappa)
+    print("L6 E fp64", r64["energy"], "E mixed", r32["energy"], "Kirkwood", E, flush=True)
+    assert abs(r32["energy"] / r64["energy"] - 1) <= 1e-5
+    assert abs(r64["energy"] / E - 1) <= 2e-4
+
+
+@pytest.fixture(scope="module")
+def mol500():
+    print("generating the 500-atom surface", flush=True)
+    return inputs.molecule(500, seed=3)
+
+
+def test_molecule500_sampled_rows_and_energy(ctx, mol500):
+    """The 500-atom protein-like workload of `bench.py --workload molecule` at full size:
+    FP64 rows to 1e-12 and mixed rows to 1e-5 against the oracle, and the mixed solve's
+    energy within 1e-5 of FP64."""
+    p = mol500
+    print(f"molecule nv={p.nv} nf={p.nf}", flush=True)
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    u = inputs.random_vector(2 * p.nv, 41)
+    rng = np.random.default_rng(2)
+    rows = np.unique(np.r_[0:4, p.nv - 4:p.nv, rng.integers(0, p.nv, 24)])
+    y_or = O.matvec(st, u, p.kappa, p.eps2 / p.eps1, rows=rows)
+    for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
+        g = hobi.Problem.from_inputs(ctx, p, precision=prec)
+        y = g.matvec(u)
+        got = np.stack([y[rows], y[p.nv + rows]])
+        err = _rel_inf(got, y_or)
+        print(f"molecule500 precision {prec} rel err {err:.3e}", flush=True)
+        assert err <= tol
+    r64 = hobi.Problem.from_inputs(ctx, p, max_iter=400, restart=400).solve()
+    r32 = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED, max_iter=400, restart=400).solve()
+    print("molecule500 E fp64", r64["energy"], "its", r64["stats"]["iterations"], "E mixed", r32["energy"],
+          flush=True)
+    assert r64["stats"]["converged"] == 1 and r32["stats"]["converged"] == 1
+    assert abs(r32["energy"] / r64["energy"] - 1) <= 1e-5
