@@ -301,6 +301,23 @@ def main():
                      "kernel": "pair_f32_kernel" if mixed else "pair_f64_kernel",
                      "flops_per_pair": FLOPS_PER_PAIR[prob.kappa > 0]},
     }
+    # matvec alone (rows a1-a4, device vectors): median of 20 after 3 warm-ups, HIP events
+    # on the library's stream around each call
+    uvec = torch.randn(2 * prob.nv, dtype=torch.float64, device="cuda")
+    yvec = torch.empty_like(uvec)
+    torch.cuda.synchronize()
+    mv_ms = []
+    for i in range(23):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        pb.matvec(uvec, out=yvec)
+        ev1.record(stream)
+        ev1.synchronize()
+        if i >= 3:
+            mv_ms.append(ev0.elapsed_time(ev1))
+    out["matvec_ms_median"] = float(np.median(mv_ms))
+    out["matvec_gpairs_per_s"] = pairs_mv / (out["matvec_ms_median"] * 1e-3) / 1e9
     if not args.no_compare:
         # the other precision on the same problem (outside the timed region)
         pb.set_precision(hobi.HOBI_FP64 if mixed else hobi.HOBI_MIXED)
