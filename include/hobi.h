@@ -57,6 +57,15 @@ enum {
                      /* singular correction, GMRES, sources and energy stay FP64        */
 };
 
+/* Discretisation of the integral equations. */
+enum {
+    HOBI_HIGHER_ORDER = 0,  /* curved 10-node triangles, unknowns at the vertices, 4-point    */
+                            /* regular and 16-point singular rules (Sections 2.2-2.3)         */
+    HOBI_LOWER_ORDER = 1    /* flat triangles, centroid collocation: one unknown pair and one */
+                            /* quadrature point per triangle, the self term dropped           */
+                            /* (the low-order scheme, eqdbef1/eqdbef2)                        */
+};
+
 typedef struct hobi_ctx_s* hobi_ctx;
 typedef struct hobi_problem_s* hobi_problem;
 typedef struct hobi_server_s* hobi_server;
@@ -69,7 +78,7 @@ typedef struct hobi_params {
     int32_t max_iter;   /* total matvecs allowed, default 200                               */
     int32_t restart;    /* GMRES(m) restart length, default 200                             */
     int32_t precision;  /* HOBI_FP64 or HOBI_MIXED, default HOBI_FP64                       */
-    int32_t reserved;   /* must be 0                                                        */
+    int32_t method;     /* HOBI_HIGHER_ORDER (default) or HOBI_LOWER_ORDER                  */
 } hobi_params;
 
 typedef struct hobi_stats {
@@ -80,7 +89,8 @@ typedef struct hobi_stats {
     double ms_setup;           /* geometry + quadrature + singular coefficients + sources   */
     double ms_solve;           /* GMRES wall time on the stream                             */
     double ms_energy;          /* solvation energy                                          */
-    int64_t pairs_per_matvec;  /* Nv * 4 Nf (target vertex, regular node) pairs             */
+    int64_t pairs_per_matvec;  /* Nv * 4 Nf (target vertex, regular node) pairs; Nf * Nf for  */
+                               /* the lower-order method                                    */
     /* Per-kernel device time, accumulated over the calls since the last reset when the
      * context has profiling enabled (HIP events on the context's stream), else 0.        */
     double ms_pair_kernel;
@@ -108,7 +118,10 @@ void* hobi_ctx_stream(hobi_ctx ctx);
  * stream (routines (1)-(4) of Section 2.6): curved 10-node elements (Section 2.2),
  * 4-point Gauss-Radau nodes, the singular 16-point Duffy/Gauss-Legendre
  * coefficients (Section 2.3), source terms S1/S2 (eq. Eq_Ss) and the check that every
- * charge is enclosed.
+ * charge is enclosed.  With params->method = HOBI_LOWER_ORDER the setup is that of the
+ * low-order scheme instead (flat triangles: centroids, face normals, areas), and every
+ * per-unknown array below ("[nv]", "[2 nv]") has one entry per triangle ([nf], [2 nf], in
+ * the caller's triangle order) instead of one per vertex.
  *   xyz [nv][3], nrm [nv][3]: vertex positions and unit outward normals (host).
  *   tri [nf][3]: 0-based vertex ids, counter-clockwise seen from outside (host).  The
  *        first vertex of each triangle is significant: the 4-point rule is anchored at
@@ -153,7 +166,8 @@ hobi_status hobi_energy(hobi_problem pb, const double* u, int32_t on_device,
 
 /* ---- inspection of the setup (for verification), caller's vertex/triangle order ---
  * y, ny: [nf][4][3] regular quadrature nodes and unit normals; w: [nf][4] weight times
- * Jacobian (Section 2.2).  Any pointer may be NULL. */
+ * Jacobian (Section 2.2); lower-order method: [nf][3], [nf][3], [nf] (centroid, face
+ * normal, area).  Any pointer may be NULL. */
 hobi_status hobi_get_nodes(hobi_problem pb, double* y, double* ny, double* w);
 /* b: [2 nv] right-hand side (S1, S2) in internal units. */
 hobi_status hobi_get_rhs(hobi_problem pb, double* b);

@@ -297,7 +297,8 @@ hobi_status from_internal(hobi_problem pb, const double* src, int on_device, dou
 
 void free_problem(hobi_problem pb) {
     DeviceProblem& d = pb->d;
-    void* ptrs[] = {d.xyz, d.nrm, d.tri, d.qpos, d.q, d.qsoa, d.patch, d.node64, d.node32, d.node_vid, d.blk_range, d.w,
+    void* ptrs[] = {d.xyz, d.nrm, d.vxyz, d.tri, d.qpos, d.q, d.qsoa, d.patch, d.node64, d.node32, d.node_vid,
+                    d.blk_range, d.w,
                     d.tgt64, d.tgt32, d.inc_off, d.inc_ent, d.coef, d.rhs, d.partial,
                     pb->d_vperm, pb->u_in, pb->y_out, pb->phi_reac, pb->e_dev, pb->d_err};
     for (void* p : ptrs)
@@ -318,11 +319,17 @@ hobi_status run_device_setup(hobi_problem pb, float* ms_out) {
     hipEvent_t e0 = take_event(pb), e1 = take_event(pb);
     d.s32 = d.kappa > 0 ? d.kappa * 1.4426950408889634074 : 1.0;
     if (e0) (void)hipEventRecord(e0, s);
-    HIPCHK(pb->ctx, launch_patch(d, pb->d_err, s));
-    HIPCHK(pb->ctx, launch_regular_nodes(d, s));
-    HIPCHK(pb->ctx, launch_targets(d, s));
-    HIPCHK(pb->ctx, launch_singular(d, s));
-    HIPCHK(pb->ctx, launch_sources(d, s));
+    if (d.method == HOBI_LOWER_ORDER) {
+        HIPCHK(pb->ctx, launch_lobi_nodes(d, s));
+        HIPCHK(pb->ctx, launch_targets(d, s));
+        HIPCHK(pb->ctx, launch_sources(d, s));
+    } else {
+        HIPCHK(pb->ctx, launch_patch(d, pb->d_err, s));
+        HIPCHK(pb->ctx, launch_regular_nodes(d, s));
+        HIPCHK(pb->ctx, launch_targets(d, s));
+        HIPCHK(pb->ctx, launch_singular(d, s));
+        HIPCHK(pb->ctx, launch_sources(d, s));
+    }
     if (e1) (void)hipEventRecord(e1, s);
     HIPCHK(pb->ctx, hipStreamSynchronize(s));
     float ms = 0.f;
@@ -347,6 +354,8 @@ hobi_status validate_params(hobi_ctx ctx, const hobi_params& p) {
     if (p.max_iter < 1 || p.restart < 1) return fail(ctx, HOBI_E_ARG, "max_iter and restart must be >= 1");
     if (p.precision != HOBI_FP64 && p.precision != HOBI_MIXED)
         return fail(ctx, HOBI_E_ARG, "precision must be HOBI_FP64 or HOBI_MIXED");
+    if (p.method != HOBI_HIGHER_ORDER && p.method != HOBI_LOWER_ORDER)
+        return fail(ctx, HOBI_E_ARG, "method must be HOBI_HIGHER_ORDER or HOBI_LOWER_ORDER");
     return HOBI_OK;
 }
 
@@ -433,7 +442,7 @@ void hobi_params_default(hobi_params* p) {
     p->max_iter = 200;
     p->restart = 200;
     p->precision = HOBI_FP64;
-    p->reserved = 0;
+    p->method = HOBI_HIGHER_ORDER;
 }
 
 hobi_status hobi_ctx_create(int device, void* stream, hobi_ctx* out) {
@@ -533,22 +542,25 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
         for (int e = 0; e < 3 * nf; ++e) ent[fill[ht[e]]++] = e;
     }
 
+    const bool lower = prm.method == HOBI_LOWER_ORDER;
     hobi_problem pb = new hobi_problem_s();
     pb->ctx = ctx;
     pb->prm = prm;
-    pb->vperm = vperm;
+    pb->vperm = lower ? tperm : vperm;   // internal site -> caller's vertex (triangle) index
     pb->tperm = tperm;
     DeviceProblem& d = pb->d;
-    d.nv = nv;
+    d.method = prm.method;
+    d.nverts = nv;
+    d.nv = lower ? nf : nv;
     d.nf = nf;
     d.nc = nc;
-    d.nn = 4 * nf;
+    d.nn = lower ? nf : 4 * nf;
     d.eps1 = prm.eps1;
     d.eps2 = prm.eps2;
     d.kappa = prm.kappa;
     d.eps = prm.eps2 / prm.eps1;
     for (int k = 0; k < 3; ++k) d.center[k] = 0.5 * (lo[k] + hi[k]);
-    d.nv_pad = round_up(nv, 2048);
+    d.nv_pad = round_up(d.nv, 2048);
     d.nc_pad = round_up(nc, 256);
     d.plan64 = make_plan(d.nv_pad, d.nn, kTpl64);
     d.plan32 = make_plan(d.nv_pad, d.nn, d.nv_pad >= 16384 ? 8 : 4);
@@ -570,13 +582,15 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
     } while (0)
 
     hipStream_t s = ctx->stream;
-    PCHK(dalloc(&d.xyz, 3 * (size_t)nv));
-    PCHK(dalloc(&d.nrm, 3 * (size_t)nv));
+    const int ns = d.nv;   // sites
+    PCHK(dalloc(&d.xyz, 3 * (size_t)ns));
+    PCHK(dalloc(&d.nrm, 3 * (size_t)ns));
+    if (lower) PCHK(dalloc(&d.vxyz, 3 * (size_t)nv));
     PCHK(dalloc(&d.tri, 3 * (size_t)nf));
     PCHK(dalloc(&d.qpos, 3 * (size_t)nc));
     PCHK(dalloc(&d.q, nc));
     PCHK(dalloc(&d.qsoa, 3 * (size_t)d.nc_pad));
-    PCHK(dalloc(&d.patch, 30 * (size_t)nf));
+    if (!lower) PCHK(dalloc(&d.patch, 30 * (size_t)nf));
     PCHK(dalloc(&d.node64, d.nn));
     PCHK(dalloc(&d.node32, d.nn));
     PCHK(dalloc(&d.node_vid, d.nn));
@@ -584,14 +598,14 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
     PCHK(dalloc(&d.w, d.nn));
     PCHK(dalloc(&d.tgt64, 6 * (size_t)d.nv_pad));
     PCHK(dalloc(&d.tgt32, 6 * (size_t)d.nv_pad));
-    PCHK(dalloc(&d.inc_off, nv + 1));
-    PCHK(dalloc(&d.inc_ent, 3 * (size_t)nf));
-    PCHK(dalloc(&d.coef, 36 * (size_t)nf));
-    PCHK(dalloc(&d.rhs, 2 * (size_t)nv));
+    PCHK(dalloc(&d.inc_off, ns + 1));
+    PCHK(dalloc(&d.inc_ent, lower ? 1 : 3 * (size_t)nf));
+    PCHK(dalloc(&d.coef, lower ? 1 : 36 * (size_t)nf));
+    PCHK(dalloc(&d.rhs, 2 * (size_t)ns));
     PCHK(dalloc(&d.partial, d.partial_elems));
-    PCHK(dalloc(&pb->d_vperm, nv));
-    PCHK(dalloc(&pb->u_in, 2 * (size_t)nv));
-    PCHK(dalloc(&pb->y_out, 2 * (size_t)nv));
+    PCHK(dalloc(&pb->d_vperm, ns));
+    PCHK(dalloc(&pb->u_in, 2 * (size_t)ns));
+    PCHK(dalloc(&pb->y_out, 2 * (size_t)ns));
     PCHK(dalloc(&pb->phi_reac, nc));
     PCHK(dalloc(&pb->e_dev, 4));
     PCHK(hipHostMalloc((void**)&pb->host_pinned, 64));
@@ -601,29 +615,42 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
     for (int k = 0; k < d.nc_pad; ++k)
         for (int c = 0; c < 3; ++c) qs[(size_t)c * d.nc_pad + k] = qpos[3 * std::min(k, nc - 1) + c];
 
-    PCHK(hipMemcpyAsync(d.xyz, hx.data(), sizeof(double) * hx.size(), hipMemcpyHostToDevice, s));
-    PCHK(hipMemcpyAsync(d.nrm, hn.data(), sizeof(double) * hn.size(), hipMemcpyHostToDevice, s));
+    if (lower) {
+        // sites (centroids, face normals) are computed by the setup kernel from the vertices
+        PCHK(hipMemcpyAsync(d.vxyz, hx.data(), sizeof(double) * hx.size(), hipMemcpyHostToDevice, s));
+        off.assign(ns + 1, 0);   // no incident (singular) entries
+    } else {
+        PCHK(hipMemcpyAsync(d.xyz, hx.data(), sizeof(double) * hx.size(), hipMemcpyHostToDevice, s));
+        PCHK(hipMemcpyAsync(d.nrm, hn.data(), sizeof(double) * hn.size(), hipMemcpyHostToDevice, s));
+    }
     PCHK(hipMemcpyAsync(d.tri, ht.data(), sizeof(int) * ht.size(), hipMemcpyHostToDevice, s));
     PCHK(hipMemcpyAsync(d.qpos, qpos, sizeof(double) * 3 * nc, hipMemcpyHostToDevice, s));
     PCHK(hipMemcpyAsync(d.q, q, sizeof(double) * nc, hipMemcpyHostToDevice, s));
     PCHK(hipMemcpyAsync(d.qsoa, qs.data(), sizeof(double) * qs.size(), hipMemcpyHostToDevice, s));
     PCHK(hipMemcpyAsync(d.inc_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
-    PCHK(hipMemcpyAsync(d.inc_ent, ent.data(), sizeof(int) * ent.size(), hipMemcpyHostToDevice, s));
-    PCHK(hipMemcpyAsync(pb->d_vperm, vperm.data(), sizeof(int) * nv, hipMemcpyHostToDevice, s));
-    // vertex-id range of every 64-node block (16 consecutive triangles)
+    if (!lower) PCHK(hipMemcpyAsync(d.inc_ent, ent.data(), sizeof(int) * ent.size(), hipMemcpyHostToDevice, s));
+    PCHK(hipMemcpyAsync(pb->d_vperm, pb->vperm.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+    // masked-id range of every 64-node block: the vertices of its 16 consecutive triangles
+    // (higher-order), or its own 64 sites (lower-order: a node is masked for its own site)
     std::vector<int2> brange((d.nn + 63) / 64);
     for (size_t b = 0; b < brange.size(); ++b) {
-        int lo = nv, hi = -1;
-        for (int t = (int)(16 * b); t < std::min(nf, (int)(16 * b + 16)); ++t)
-            for (int k = 0; k < 3; ++k) {
-                lo = std::min(lo, ht[3 * t + k]);
-                hi = std::max(hi, ht[3 * t + k]);
-            }
+        int lo = ns, hi = -1;
+        if (lower) {
+            lo = (int)(64 * b);
+            hi = std::min(nf - 1, (int)(64 * b + 63));
+        } else {
+            for (int t = (int)(16 * b); t < std::min(nf, (int)(16 * b + 16)); ++t)
+                for (int k = 0; k < 3; ++k) {
+                    lo = std::min(lo, ht[3 * t + k]);
+                    hi = std::max(hi, ht[3 * t + k]);
+                }
+        }
         brange[b] = make_int2(lo, hi);
     }
     PCHK(hipMemcpyAsync(d.blk_range, brange.data(), sizeof(int2) * brange.size(), hipMemcpyHostToDevice, s));
     PCHK(hipMemsetAsync(d.node64, 0, sizeof(NodeD) * d.nn, s));
     PCHK(hipMemsetAsync(d.node32, 0, sizeof(NodeF) * d.nn, s));
+    PCHK(hipMemsetAsync(pb->d_err, 0, sizeof(int) * nf, s));
     PCHK(hipStreamSynchronize(s));
     float ms = 0.f;
     if ((st = run_device_setup(pb, &ms)) != HOBI_OK) return cleanup_fail(st);
@@ -648,7 +675,7 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
             return cleanup_fail(fail(ctx, HOBI_E_CHARGE_OUTSIDE, "charge %d is outside the surface", k));
     }
 #undef PCHK
-    pb->last.pairs_per_matvec = (int64_t)nv * d.nn;
+    pb->last.pairs_per_matvec = (int64_t)d.nv * d.nn;
     *out = pb;
     return HOBI_OK;
 }
@@ -798,14 +825,15 @@ hobi_status hobi_get_nodes(hobi_problem pb, double* y, double* ny, double* w) {
     HIPCHK(pb->ctx, hipMemcpyAsync(nd.data(), pb->d.node64, sizeof(NodeD) * nn, hipMemcpyDeviceToHost, s));
     HIPCHK(pb->ctx, hipMemcpyAsync(hw.data(), pb->d.w, sizeof(double) * nn, hipMemcpyDeviceToHost, s));
     HIPCHK(pb->ctx, hipStreamSynchronize(s));
+    const int per = nn / nf;   // nodes per triangle: 4 (higher-order) or 1 (lower-order)
     for (int t = 0; t < nf; ++t) {
         const int o = pb->tperm[t];
-        for (int m = 0; m < 4; ++m) {
-            const NodeD& a = nd[4 * t + m];
-            const size_t b = 4 * (size_t)o + m;
+        for (int m = 0; m < per; ++m) {
+            const NodeD& a = nd[per * t + m];
+            const size_t b = per * (size_t)o + m;
             if (y) y[3 * b] = a.x, y[3 * b + 1] = a.y, y[3 * b + 2] = a.z;
             if (ny) ny[3 * b] = a.nx, ny[3 * b + 1] = a.ny, ny[3 * b + 2] = a.nz;
-            if (w) w[b] = hw[4 * t + m];
+            if (w) w[b] = hw[per * t + m];
         }
     }
     return HOBI_OK;

@@ -24,13 +24,18 @@ struct PairPlan {
 };
 
 struct DeviceProblem {
-    int nv = 0, nf = 0, nc = 0, nn = 0;     // vertices, triangles, charges, regular nodes
+    // nv counts the collocation sites, which carry the unknowns: the vertices (higher-order
+    // method) or the triangles' centroids (lower-order method, then nv = nf and nn = nf)
+    int nv = 0, nf = 0, nc = 0, nn = 0;     // sites, triangles, charges, quadrature nodes
+    int method = HOBI_HIGHER_ORDER;
+    int nverts = 0;                         // mesh vertices
+    double* vxyz = nullptr;                 // [nverts][3] vertex positions (lower-order method only)
     double eps1 = 1, eps2 = 80, kappa = 0, eps = 80;
     double center[3] = {0, 0, 0};          // shift applied to the FP32 copies
     double s32 = 1;                         // scale of the FP32 positions: kappa log2(e) (1 if kappa = 0)
     // inputs in internal (spatially sorted) order
-    double* xyz = nullptr;                  // [nv][3]
-    double* nrm = nullptr;                  // [nv][3]
+    double* xyz = nullptr;                  // [nv][3] site positions
+    double* nrm = nullptr;                  // [nv][3] site normals
     int* tri = nullptr;                     // [nf][3]
     double* qpos = nullptr;                 // [nc][3]
     double* q = nullptr;                    // [nc]
@@ -62,6 +67,7 @@ hipError_t launch_regular_nodes(const DeviceProblem& p, hipStream_t s);
 hipError_t launch_targets(const DeviceProblem& p, hipStream_t s);
 hipError_t launch_singular(const DeviceProblem& p, hipStream_t s);
 hipError_t launch_sources(const DeviceProblem& p, hipStream_t s);
+hipError_t launch_lobi_nodes(const DeviceProblem& p, hipStream_t s);
 
 // ---- matvec kernels (pair_kernels.hip) ----
 PairPlan make_plan(int n_pad, int nn, int tpl);

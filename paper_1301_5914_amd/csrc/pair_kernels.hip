@@ -39,10 +39,13 @@ __device__ __forceinline__ void xcd_block(int* tb, int* ch) {
 
 __global__ void gather_kernel(const double* __restrict__ u, int nv, const int* __restrict__ tri,
                               const double* __restrict__ w, int nn, NodeD* __restrict__ node64,
-                              NodeF* __restrict__ node32, int mixed, double eps, double s32) {
+                              NodeF* __restrict__ node32, int mixed, double eps, double s32, int method) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nn) return;
-    gather_node(idx, u, nv, tri, w, node64, node32, mixed, eps, s32);
+    if (method == HOBI_LOWER_ORDER)
+        gather_site(idx, u, nv, w, node64, node32, mixed, eps, s32);
+    else
+        gather_node(idx, u, nv, tri, w, node64, node32, mixed, eps, s32);
 }
 
 template <int TPL, bool KAPPA0>
@@ -173,7 +176,7 @@ PairPlan make_plan(int n_pad, int nn, int tpl) {
 
 hipError_t launch_gather(const DeviceProblem& p, const double* u, bool mixed, hipStream_t s) {
     hipLaunchKernelGGL(gather_kernel, dim3(nblk(p.nn, 256)), dim3(256), 0, s, u, p.nv, p.tri, p.w, p.nn,
-                       p.node64, p.node32, mixed ? 1 : 0, p.eps, p.s32);
+                       p.node64, p.node32, mixed ? 1 : 0, p.eps, p.s32, p.method);
     return hipGetLastError();
 }
 

@@ -159,22 +159,12 @@ __device__ __forceinline__ void pair_f32_tile(
     }
 }
 
-// Strengths of regular node idx = 4 j + m from u (1/(4 pi) folded in), FP64 and FP32 records.
-// The FP32 record's positions are in units of 1/s32; its strengths carry the matching powers
-// of s32 (Gamma terms over r and (d.ny)/r^3 terms: s32, s32^2; the Phi term of K4: s32^3).
-__device__ __forceinline__ void gather_node(int idx, const double* __restrict__ u, int nv,
-                                            const int* __restrict__ tri, const double* __restrict__ w,
-                                            NodeD* __restrict__ node64, NodeF* __restrict__ node32,
-                                            int mixed, double eps, double s32) {
-    const int j = idx >> 2, m = idx & 3;
-    double r, s, wm;
-    gauss_radau4(m, &r, &s, &wm);
-    const double L0 = 1.0 - r - s, L1 = r, L2 = s;
-    const int v0 = tri[3 * j], v1 = tri[3 * j + 1], v2 = tri[3 * j + 2];
-    const double dp = L0 * u[nv + v0] + L1 * u[nv + v1] + L2 * u[nv + v2];
-    const double pp = L0 * u[v0] + L1 * u[v1] + L2 * u[v2];
-    const double sc = w[idx] * kInv4Pi;
-    const double g = sc * dp, p = sc * pp;
+// Node strengths Gamma = g, Phi = p (1/(4 pi) folded in) and the quantities derived from
+// them into the FP64 and FP32 records of node idx.  The FP32 record's positions are in
+// units of 1/s32; its strengths carry the matching powers of s32 (Gamma terms over r and
+// (d.ny)/r^3 terms: s32, s32^2; the Phi term of K4: s32^3).
+__device__ __forceinline__ void write_strengths(int idx, double g, double p, NodeD* __restrict__ node64,
+                                                NodeF* __restrict__ node32, int mixed, double eps, double s32) {
     {
         NodeD& n = node64[idx];
         n.g = g;
@@ -188,6 +178,7 @@ __device__ __forceinline__ void gather_node(int idx, const double* __restrict__ 
         n.qz = p * n.nz;
     }
     if (mixed) {
+        const NodeD& d = node64[idx];
         NodeF& n = node32[idx];
         const double s2 = s32 * s32, s3 = s2 * s32;
         n.g = (float)(s32 * g);
@@ -196,10 +187,35 @@ __device__ __forceinline__ void gather_node(int idx, const double* __restrict__ 
         n.gb = (float)(-s2 * g / eps);
         n.pa = (float)((eps - 1.0) * s2 * p);
         n.pb = (float)(-eps * s2 * p);
-        n.qx = (float)(s3 * p * node64[idx].nx);
-        n.qy = (float)(s3 * p * node64[idx].ny);
-        n.qz = (float)(s3 * p * node64[idx].nz);
+        n.qx = (float)(s3 * p * d.nx);
+        n.qy = (float)(s3 * p * d.ny);
+        n.qz = (float)(s3 * p * d.nz);
     }
+}
+
+// Higher-order method: regular node idx = 4 j + m of triangle j interpolates the vertex
+// unknowns linearly (W_{j,m,n} of eqdbef3/eqdbef4).
+__device__ __forceinline__ void gather_node(int idx, const double* __restrict__ u, int nv,
+                                            const int* __restrict__ tri, const double* __restrict__ w,
+                                            NodeD* __restrict__ node64, NodeF* __restrict__ node32,
+                                            int mixed, double eps, double s32) {
+    const int j = idx >> 2, m = idx & 3;
+    double r, s, wm;
+    gauss_radau4(m, &r, &s, &wm);
+    const double L0 = 1.0 - r - s, L1 = r, L2 = s;
+    const int v0 = tri[3 * j], v1 = tri[3 * j + 1], v2 = tri[3 * j + 2];
+    const double dp = L0 * u[nv + v0] + L1 * u[nv + v1] + L2 * u[nv + v2];
+    const double pp = L0 * u[v0] + L1 * u[v1] + L2 * u[v2];
+    const double sc = w[idx] * kInv4Pi;
+    write_strengths(idx, sc * dp, sc * pp, node64, node32, mixed, eps, s32);
+}
+
+// Lower-order method: node j is site j (eqdbef1/eqdbef2), weight = triangle area.
+__device__ __forceinline__ void gather_site(int j, const double* __restrict__ u, int nv,
+                                            const double* __restrict__ w, NodeD* __restrict__ node64,
+                                            NodeF* __restrict__ node32, int mixed, double eps, double s32) {
+    const double sc = w[j] * kInv4Pi;
+    write_strengths(j, sc * u[nv + j], sc * u[j], node64, node32, mixed, eps, s32);
 }
 
 // FP64 pairs of nodes [sb, se) with the lane's TPL targets.  Per pair (kappa > 0) about 62

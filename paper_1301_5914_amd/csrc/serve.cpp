@@ -32,6 +32,7 @@ namespace {
 struct Request {
     uint64_t ticket = 0;
     int nv = 0, nf = 0, nc = 0;
+    int nu = 0;             // unknown sites: vertices, or triangles (lower-order method)
     std::vector<double> xyz, nrm, qpos, q;
     std::vector<int32_t> tri;
     hobi_params prm{};
@@ -62,7 +63,9 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 // Device bytes of one admitted request (the allocations of hobi_problem_create plus the
 // server's Krylov basis), from its sizes alone.
-int64_t footprint_bytes(int nv, int nf, int nc, int m) {
+int64_t footprint_bytes(int nv, int nf, int nc, int m, int method) {
+    // the lower-order method has one site and one node per triangle (an upper bound below)
+    if (method == HOBI_LOWER_ORDER) nv = std::max(nv, nf);
     const int64_t nv_pad = round_up(nv, 2048), nc_pad = round_up(nc, 256), nn = 4LL * nf;
     const PairPlan p64 = make_plan((int)nv_pad, (int)nn, kTpl64), p32 = make_plan((int)nv_pad, (int)nn, nv_pad >= 16384 ? 8 : 4);
     const PairPlan pp = make_plan((int)nc_pad, (int)nn, 1);
@@ -145,7 +148,7 @@ hobi_status admit(hobi_server sv, Request& r) {
     const DeviceProblem& d = r.pb->d;
     r.plan = mixed ? d.plan32 : d.plan64;
     r.m = std::max(1, r.prm.max_iter);
-    const int n = 2 * r.nv, m = r.m;
+    const int n = 2 * r.nu, m = r.m;
     hipError_t e = hipSuccess;
 #define SA(expr)                                                                   \
     if ((e = (expr)) != hipSuccess) {                                              \
@@ -180,7 +183,7 @@ hobi_status admit(hobi_server sv, Request& r) {
     r.k = 0;
     r.est = r.bnorm > 0 ? 1.0 : 0.0;
     r.stats.ms_setup = r.pb->last.ms_setup;
-    r.stats.pairs_per_matvec = (int64_t)r.nv * d.nn;
+    r.stats.pairs_per_matvec = (int64_t)d.nv * d.nn;
     return HOBI_OK;
 }
 
@@ -188,7 +191,7 @@ hobi_status admit(hobi_server sv, Request& r) {
 void finish(hobi_server sv, Request& r, bool converged) {
     hobi_ctx c = sv->ctx;
     hipStream_t s = c->stream;
-    const int n = 2 * r.nv;
+    const int n = 2 * r.nu;
     hipError_t e = hipSuccess;
     if (r.k > 0) {
         if ((e = launch_trisolve(r.H, r.m + 1, r.k, r.g, r.yk, s)) == hipSuccess)
@@ -208,8 +211,8 @@ void finish(hobi_server sv, Request& r, bool converged) {
             fail_request(r, st, c->err);
         } else {
             const double scale = 4.0 * kPi * 332.0716;
-            r.phi.assign(hu.begin(), hu.begin() + r.nv);
-            r.dphi.assign(hu.begin() + r.nv, hu.end());
+            r.phi.assign(hu.begin(), hu.begin() + r.nu);
+            r.dphi.assign(hu.begin() + r.nu, hu.end());
             for (double& v : r.phi) v *= scale;
             for (double& v : r.dphi) v *= scale;
             bool finite = std::isfinite(r.energy);
@@ -281,7 +284,7 @@ hobi_status tick(hobi_server sv) {
     for (size_t q = 0; q < na; ++q) {
         Request& r = *sv->active[q];
         const DeviceProblem& d = r.pb->d;
-        const int n = 2 * r.nv;
+        const int n = 2 * r.nu;
         ServeDesc& sd = sv->h_desc[q];
         sd.u = r.V + (size_t)r.k * n;
         sd.y = r.V + (size_t)(r.k + 1) * n;
@@ -307,6 +310,8 @@ hobi_status tick(hobi_server sv) {
         sd.chunks = r.plan.chunks;
         sd.mixed = r.prm.precision == HOBI_MIXED ? 1 : 0;
         sd.tpl = r.plan.tpl;
+        sd.method = d.method;
+        sd.pad = 0;
         for (int blk = 0; blk < (d.nn + kServeBlock - 1) / kServeBlock; ++blk)
             hl[0][fill[0]++] = ServeItem{(int)q, blk, 0, 0};
         const int pl = sd.mixed ? 1 : 2;
@@ -348,7 +353,7 @@ hobi_status tick(hobi_server sv) {
     // per-request Gram-Schmidt (two passes), normalisation and Givens update
     for (size_t q = 0; q < na; ++q) {
         Request& r = *sv->active[q];
-        const int n = 2 * r.nv, j = r.k;
+        const int n = 2 * r.nu, j = r.k;
         double* w = r.V + (size_t)(j + 1) * n;
         for (int pass = 0; pass < 2; ++pass) {
             double* h = pass == 0 ? r.h1 : r.h2;
@@ -503,7 +508,8 @@ hobi_status hobi_server_submit(hobi_server sv, int32_t nv, const double* xyz, co
     hobi_params_default(&r->prm);
     if (params) r->prm = *params;
     r->prm.restart = r->prm.max_iter;
-    r->footprint = footprint_bytes(nv, nf, nc, std::max(1, r->prm.max_iter));
+    r->nu = r->prm.method == HOBI_LOWER_ORDER ? nf : nv;
+    r->footprint = footprint_bytes(nv, nf, nc, std::max(1, r->prm.max_iter), r->prm.method);
     std::lock_guard<std::mutex> lk(sv->mu);
     if (r->footprint > sv->budget) {
         sv->last_error = "request footprint exceeds the server budget";
@@ -535,8 +541,8 @@ hobi_status hobi_server_poll(hobi_server sv, uint64_t ticket, double* phi, doubl
         sv->done.erase(it);
         if (r->status != HOBI_OK) sv->last_error = r->message;
     }
-    if (phi && !r->phi.empty()) std::memcpy(phi, r->phi.data(), sizeof(double) * r->nv);
-    if (dphi && !r->dphi.empty()) std::memcpy(dphi, r->dphi.data(), sizeof(double) * r->nv);
+    if (phi && !r->phi.empty()) std::memcpy(phi, r->phi.data(), sizeof(double) * r->nu);
+    if (dphi && !r->dphi.empty()) std::memcpy(dphi, r->dphi.data(), sizeof(double) * r->nu);
     if (e_sol) *e_sol = r->energy;
     if (st) *st = r->stats;
     return r->status;

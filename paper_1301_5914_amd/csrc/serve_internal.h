@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "hobi.h"
 #include "hobi_device.h"
 
 namespace hobi {
@@ -34,6 +35,8 @@ struct ServeDesc {
     int chunk, chunks;
     int mixed;
     int tpl;                // targets per lane of the request's pair plan (the single-problem plan)
+    int method;             // HOBI_HIGHER_ORDER or HOBI_LOWER_ORDER
+    int pad;
 };
 
 // One unit of work: request `req`; (a, b) = (target block, chunk) for the pair kernel,

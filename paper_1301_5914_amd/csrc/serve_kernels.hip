@@ -26,7 +26,12 @@ __global__ __launch_bounds__(kPairBlock) void batched_gather_kernel(const ServeD
         const const_as<ServeItem>& item = as_constant(items)[uniform(it)];
         const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
         const int idx = item.a * kPairBlock + (int)threadIdx.x;
-        if (idx < d.nn) gather_node(idx, d.u, d.nv, d.tri, d.w, d.node64, d.node32, d.mixed, d.eps, d.s32);
+        if (idx < d.nn) {
+            if (d.method == HOBI_LOWER_ORDER)
+                gather_site(idx, d.u, d.nv, d.w, d.node64, d.node32, d.mixed, d.eps, d.s32);
+            else
+                gather_node(idx, d.u, d.nv, d.tri, d.w, d.node64, d.node32, d.mixed, d.eps, d.s32);
+        }
     }
 }
 

@@ -80,6 +80,37 @@ __global__ void regular_kernel(const double* __restrict__ patch, const int* __re
     w[idx] = wm * J;
 }
 
+// Lower-order method (eqdbef1/eqdbef2): triangle j is one site and one node, at its
+// centroid, with the flat triangle's unit normal and area; its node is masked for its own
+// site only (ids j, j, j).
+__global__ void lobi_nodes_kernel(const double* __restrict__ vxyz, const int* __restrict__ tri, int nf,
+                                  NodeD* __restrict__ node64, NodeF* __restrict__ node32,
+                                  int4* __restrict__ node_vid, double* __restrict__ w,
+                                  double* __restrict__ sxyz, double* __restrict__ snrm, double cx, double cy,
+                                  double cz, double s32) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nf) return;
+    const Vec3 A = load3(vxyz, tri[3 * j]), B = load3(vxyz, tri[3 * j + 1]), C = load3(vxyz, tri[3 * j + 2]);
+    const Vec3 c = (1.0 / 3.0) * (A + B + C);
+    const Vec3 cr = cross(B - A, C - A);
+    const double a2 = norm(cr);
+    const Vec3 n = (1.0 / a2) * cr;
+    NodeD d{};
+    d.x = c.x, d.y = c.y, d.z = c.z;
+    d.nx = n.x, d.ny = n.y, d.nz = n.z;
+    node64[j] = d;
+    NodeF f{};
+    f.x = (float)((c.x - cx) * s32);
+    f.y = (float)((c.y - cy) * s32);
+    f.z = (float)((c.z - cz) * s32);
+    f.nx = (float)n.x, f.ny = (float)n.y, f.nz = (float)n.z;
+    node32[j] = f;
+    node_vid[j] = make_int4(j, j, j, 0);
+    w[j] = 0.5 * a2;
+    sxyz[3 * j] = c.x, sxyz[3 * j + 1] = c.y, sxyz[3 * j + 2] = c.z;
+    snrm[3 * j] = n.x, snrm[3 * j + 1] = n.y, snrm[3 * j + 2] = n.z;
+}
+
 __global__ void targets_kernel(const double* __restrict__ xyz, const double* __restrict__ nrm, int nv,
                                int nv_pad, double* __restrict__ t64, float* __restrict__ t32,
                                double cx, double cy, double cz, double s32) {
@@ -185,6 +216,12 @@ hipError_t launch_patch(const DeviceProblem& p, int* d_err, hipStream_t s) {
 hipError_t launch_regular_nodes(const DeviceProblem& p, hipStream_t s) {
     hipLaunchKernelGGL(regular_kernel, dim3(nblk(4L * p.nf, 128)), dim3(128), 0, s, p.patch, p.tri, p.nf,
                        p.node64, p.node32, p.node_vid, p.w, p.center[0], p.center[1], p.center[2], p.s32);
+    return hipGetLastError();
+}
+
+hipError_t launch_lobi_nodes(const DeviceProblem& p, hipStream_t s) {
+    hipLaunchKernelGGL(lobi_nodes_kernel, dim3(nblk(p.nf, 128)), dim3(128), 0, s, p.vxyz, p.tri, p.nf, p.node64,
+                       p.node32, p.node_vid, p.w, p.xyz, p.nrm, p.center[0], p.center[1], p.center[2], p.s32);
     return hipGetLastError();
 }
 

@@ -21,6 +21,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "hobi.h")
 
 HOBI_FP64 = 0
 HOBI_MIXED = 1
+HOBI_HIGHER_ORDER = 0
+HOBI_LOWER_ORDER = 1
 
 STATUS = {0: "HOBI_OK", 1: "HOBI_E_ARG", 2: "HOBI_E_MESH", 3: "HOBI_E_CHARGE_OUTSIDE",
           4: "HOBI_E_NOCONV", 5: "HOBI_E_OOM", 6: "HOBI_E_HIP", 7: "HOBI_E_NUMERIC",
@@ -37,7 +39,7 @@ class HobiError(RuntimeError):
 class hobi_params(ctypes.Structure):
     _fields_ = [("eps1", ctypes.c_double), ("eps2", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class hobi_stats(ctypes.Structure):
@@ -180,7 +182,7 @@ class Problem:
     """One surface + charge set with its setup resident on the device."""
 
     def __init__(self, ctx: Context, xyz, nrm, tri, qpos, q, eps1=1.0, eps2=80.0, kappa=0.1257,
-                 rtol=1e-6, max_iter=200, restart=200, precision=HOBI_FP64):
+                 rtol=1e-6, max_iter=200, restart=200, precision=HOBI_FP64, method=HOBI_HIGHER_ORDER):
         self.ctx = ctx
         xyz = _f64(xyz).reshape(-1, 3)
         nrm = _f64(nrm).reshape(-1, 3)
@@ -188,9 +190,12 @@ class Problem:
         qpos = _f64(qpos).reshape(-1, 3)
         q = _f64(q).ravel()
         self.nv, self.nf, self.nc = xyz.shape[0], tri.shape[0], q.shape[0]
+        self.method = method
+        # unknowns per site: vertices (higher-order) or triangles (lower-order)
+        self.nu = self.nf if method == HOBI_LOWER_ORDER else self.nv
         p = hobi_params_default()
         p.eps1, p.eps2, p.kappa, p.rtol = eps1, eps2, kappa, rtol
-        p.max_iter, p.restart, p.precision = max_iter, restart, precision
+        p.max_iter, p.restart, p.precision, p.method = max_iter, restart, precision, method
         h = _P()
         st = lib().hobi_problem_create(ctx.handle, self.nv, _dptr(xyz), _dptr(nrm), self.nf,
                                        tri.ctypes.data_as(_I), self.nc, _dptr(qpos), _dptr(q),
@@ -225,8 +230,8 @@ class Problem:
             self._chk(lib().hobi_matvec(self.handle, _P(u.data_ptr()), _P(out.data_ptr()), 1))
             return out
         u = _f64(u).ravel()
-        if u.shape[0] != 2 * self.nv:
-            raise ValueError("u must have 2*nv entries")
+        if u.shape[0] != 2 * self.nu:
+            raise ValueError("u must have 2 entries per site")
         y = np.empty_like(u)
         self._chk(lib().hobi_matvec(self.handle, _P(u.ctypes.data), _P(y.ctypes.data), 0))
         return y
@@ -241,8 +246,8 @@ class Problem:
         return e.value
 
     def solve(self, allow_noconv: bool = False):
-        phi = np.empty(self.nv)
-        dphi = np.empty(self.nv)
+        phi = np.empty(self.nu)
+        dphi = np.empty(self.nu)
         e = ctypes.c_double()
         st = hobi_stats()
         code = lib().hobi_solve(self.handle, _dptr(phi), _dptr(dphi), ctypes.byref(e), ctypes.byref(st))
@@ -251,14 +256,15 @@ class Problem:
         return dict(phi=phi, dphi=dphi, energy=e.value, stats=st.as_dict(), status=STATUS[code])
 
     def nodes(self):
-        y = np.empty((self.nf, 4, 3))
-        ny = np.empty((self.nf, 4, 3))
-        w = np.empty((self.nf, 4))
+        per = 1 if self.method == HOBI_LOWER_ORDER else 4
+        y = np.empty((self.nf, per, 3))
+        ny = np.empty((self.nf, per, 3))
+        w = np.empty((self.nf, per))
         self._chk(lib().hobi_get_nodes(self.handle, _dptr(y), _dptr(ny), _dptr(w)))
         return y, ny, w
 
     def rhs(self):
-        b = np.empty(2 * self.nv)
+        b = np.empty(2 * self.nu)
         self._chk(lib().hobi_get_rhs(self.handle, _dptr(b)))
         return b
 
@@ -322,7 +328,7 @@ class Server:
         raise HobiError(st, msg.decode() if msg else "")
 
     def submit(self, prob, rtol=1e-6, max_iter=300, precision=HOBI_MIXED, eps1=None, eps2=None,
-               kappa=None) -> int:
+               kappa=None, method=HOBI_HIGHER_ORDER) -> int:
         xyz = _f64(prob.xyz).reshape(-1, 3)
         nrm = _f64(prob.nrm).reshape(-1, 3)
         tri = np.ascontiguousarray(np.asarray(prob.tri, dtype=np.int32).reshape(-1, 3))
@@ -332,14 +338,14 @@ class Server:
         p.eps1 = prob.eps1 if eps1 is None else eps1
         p.eps2 = prob.eps2 if eps2 is None else eps2
         p.kappa = prob.kappa if kappa is None else kappa
-        p.rtol, p.max_iter, p.restart, p.precision = rtol, max_iter, max_iter, precision
+        p.rtol, p.max_iter, p.restart, p.precision, p.method = rtol, max_iter, max_iter, precision, method
         t = ctypes.c_uint64()
         st = lib().hobi_server_submit(self.handle, xyz.shape[0], _dptr(xyz), _dptr(nrm), tri.shape[0],
                                       tri.ctypes.data_as(_I), q.shape[0], _dptr(qpos), _dptr(q),
                                       ctypes.byref(p), ctypes.byref(t))
         if st != 0:
             self._err(st)
-        self._nv[t.value] = xyz.shape[0]
+        self._nv[t.value] = tri.shape[0] if method == HOBI_LOWER_ORDER else xyz.shape[0]
         return t.value
 
     def poll(self, ticket: int, raise_errors: bool = True):
