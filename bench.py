@@ -57,27 +57,41 @@ def workload_name(args, prob):
     return f"off-centre Kirkwood sphere R=4 A, 8 charges, icosphere L{args.level}"
 
 
-def cpu_baseline(prob, seconds: float, workers: int):
+def cpu_baseline(prob, seconds: float, workers: int, lower: bool = False):
     """The FP64 oracle's matvec on a bounded sample of rows of the same workload."""
-    from oracle import operator as O
     from paper_1301_5914_amd import inputs
 
-    st = O.setup(prob.xyz, prob.nrm, prob.tri)
-    u = inputs.random_vector(2 * prob.nv, 1)
     eps = prob.eps2 / prob.eps1
+    if lower:
+        from oracle import lobi as LO
+        st = LO.setup(prob.xyz, prob.nrm, prob.tri)
+        n_sites, n_nodes = prob.nf, prob.nf
+
+        def rows_fn(u, rows):
+            return LO.matvec(st, u, prob.kappa, eps, rows=rows)
+        cores = 1   # the lower-order oracle runs in one process
+    else:
+        from oracle import operator as O
+        st = O.setup(prob.xyz, prob.nrm, prob.tri)
+        n_sites, n_nodes = prob.nv, 4 * prob.nf
+
+        def rows_fn(u, rows):
+            return O.matvec(st, u, prob.kappa, eps, rows=rows, workers=workers)
+        cores = workers
+    u = inputs.random_vector(2 * n_sites, 1)
     # per-row cost measured with all workers busy, then a sample sized to ~`seconds`
-    probe = np.arange(4 * workers)
+    probe = np.arange(4 * cores)
     t0 = time.perf_counter()
-    O.matvec(st, u, prob.kappa, eps, rows=probe, workers=workers)
+    rows_fn(u, probe)
     per_row = (time.perf_counter() - t0) / probe.size
-    nrows = int(min(prob.nv, max(probe.size, seconds / max(per_row, 1e-9))))
+    nrows = int(min(n_sites, max(probe.size, seconds / max(per_row, 1e-9))))
     rows = np.arange(nrows)
     t0 = time.perf_counter()
-    O.matvec(st, u, prob.kappa, eps, rows=rows, workers=workers)
+    rows_fn(u, rows)
     dt = time.perf_counter() - t0
-    pairs = nrows * 4 * prob.nf
-    return {"value": pairs / dt / 1e9, "unit": "G-pairs/s", "cores": workers, "kind": "oracle",
-            "sample": f"{nrows} of {prob.nv} matvec rows (x {4 * prob.nf} nodes), {dt:.1f} s"}
+    pairs = nrows * n_nodes
+    return {"value": pairs / dt / 1e9, "unit": "G-pairs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nrows} of {n_sites} matvec rows (x {n_nodes} nodes), {dt:.1f} s"}
 
 
 def _make_molecule(n_atoms, seed):
@@ -199,6 +213,8 @@ def main():
     ap.add_argument("--atoms", type=int, default=500, help="atom count (molecule)")
     ap.add_argument("--seed", type=int, default=3, help="packing seed (molecule)")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--method", choices=["higher", "lower"], default="higher",
+                    help="higher-order (curved, vertex unknowns) or lower-order (flat, centroid) scheme")
     ap.add_argument("--max-iter", type=int, default=400, help="GMRES iteration cap (unrestarted)")
     ap.add_argument("--mesh", default=None,
                     help="load the surface and charges from an .npz (xyz, nrm, tri, qpos, q) instead of generating")
@@ -230,7 +246,7 @@ def main():
     if not args.no_cpu_baseline:
         # before any GPU call: the oracle forks worker processes
         workers = max(1, min(16, len(os.sched_getaffinity(0))))
-        cpu = cpu_baseline(prob, args.cpu_seconds, workers)
+        cpu = cpu_baseline(prob, args.cpu_seconds, workers, lower=args.method == "lower")
 
     import torch
     from oracle import kirkwood as KW
@@ -239,7 +255,11 @@ def main():
     mixed = args.precision == "mixed"
     stream = torch.cuda.Stream()          # kernels and their timing events share this stream
     ctx = hobi.Context(0, stream=stream, profiling=True)
+    lower = args.method == "lower"
+    n_sites = prob.nf if lower else prob.nv
+    n_nodes = prob.nf if lower else 4 * prob.nf
     pb = hobi.Problem.from_inputs(ctx, prob, precision=hobi.HOBI_MIXED if mixed else hobi.HOBI_FP64,
+                                  method=hobi.HOBI_LOWER_ORDER if lower else hobi.HOBI_HIGHER_ORDER,
                                   max_iter=args.max_iter, restart=args.max_iter)
 
     def step():
@@ -256,7 +276,7 @@ def main():
     wall = time.perf_counter() - t0
     kst = pb.stats()
 
-    pairs_mv = prob.nv * 4 * prob.nf
+    pairs_mv = n_sites * n_nodes
     matvecs = sum(r["stats"]["iterations"] + 1 for r in results)   # + the true-residual matvec
     value = matvecs * pairs_mv / wall / 1e9
     avg_pair_ms = kst["ms_pair_kernel"] / max(1, kst["pair_launches"])
@@ -281,7 +301,8 @@ def main():
         "dtype": "f32-pairs/f64-accumulate" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": workload_name(args, prob),
-                   "nv": prob.nv, "nf": prob.nf, "nodes": 4 * prob.nf, "pairs_per_matvec": pairs_mv,
+                   "nv": prob.nv, "nf": prob.nf, "nodes": n_nodes, "pairs_per_matvec": pairs_mv,
+                   "method": args.method,
                    "kappa": prob.kappa, "eps1": prob.eps1, "eps2": prob.eps2, "rtol": 1e-6,
                    "precision": args.precision},
         "gmres_iterations": results[-1]["stats"]["iterations"],
@@ -295,7 +316,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": (PAIR_F32_L6_TRAFFIC_BYTES
-                                 if (mixed and args.workload == "kirkwood" and args.level == 6 and not args.mesh)
+                                 if (mixed and args.workload == "kirkwood" and args.level == 6 and not args.mesh and not lower)
                                  else None),
                      "frac_nonpacked_fp32": achieved / PEAK_NONPACKED_FP32 if mixed else None,
                      "kernel": "pair_f32_kernel" if mixed else "pair_f64_kernel",
@@ -303,7 +324,7 @@ def main():
     }
     # matvec alone (rows a1-a4, device vectors): median of 20 after 3 warm-ups, HIP events
     # on the library's stream around each call
-    uvec = torch.randn(2 * prob.nv, dtype=torch.float64, device="cuda")
+    uvec = torch.randn(2 * n_sites, dtype=torch.float64, device="cuda")
     yvec = torch.empty_like(uvec)
     torch.cuda.synchronize()
     mv_ms = []
