@@ -299,7 +299,7 @@ void free_problem(hobi_problem pb) {
     DeviceProblem& d = pb->d;
     void* ptrs[] = {d.xyz, d.nrm, d.vxyz, d.tri, d.qpos, d.q, d.qsoa, d.patch, d.node64, d.node32, d.node_vid,
                     d.blk_range, d.w,
-                    d.tgt64, d.tgt32, d.inc_off, d.inc_ent, d.coef, d.rhs, d.partial,
+                    d.tgt64, d.tgt32, d.inc_off, d.inc_ent, d.coef, d.rhs, d.partial, d.plan_tab,
                     pb->d_vperm, pb->u_in, pb->y_out, pb->phi_reac, pb->e_dev, pb->d_err};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -562,11 +562,7 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
     for (int k = 0; k < 3; ++k) d.center[k] = 0.5 * (lo[k] + hi[k]);
     d.nv_pad = round_up(d.nv, 2048);
     d.nc_pad = round_up(nc, 256);
-    d.plan64 = make_plan(d.nv_pad, d.nn, kTpl64);
-    d.plan32 = make_plan(d.nv_pad, d.nn, d.nv_pad >= 16384 ? 8 : 4);
-    d.plan_pts = make_plan(d.nc_pad, d.nn, 1);
-    d.partial_elems = std::max((size_t)2 * d.nv_pad * std::max(d.plan64.chunks, d.plan32.chunks),
-                               (size_t)d.nc_pad * d.plan_pts.chunks);
+    d.plan_pts = make_grid_plan(d.nc_pad, d.nn, 1);
 
     auto cleanup_fail = [&](hobi_status code) {
         free_problem(pb);
@@ -581,8 +577,28 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
                                      "%s: %s", #expr, hipGetErrorString(e_)));                  \
     } while (0)
 
+    // the pair plans: the split of the pair sum over the waves the device holds at once
+    std::vector<int> ptab;
+    {
+        const int tpl32 = tpl32_for(d.nv_pad);
+        const int r64 = pair_resident_waves(ctx->device, false, kTpl64);
+        const int r32 = pair_resident_waves(ctx->device, true, tpl32);
+        if (r64 < 1 || r32 < 1)
+            return cleanup_fail(fail(ctx, HOBI_E_HIP, "pair kernel occupancy query failed"));
+        if (!make_pair_plan(d.nv, d.nn, kTpl64, r64, &d.plan64, &ptab) ||
+            !make_pair_plan(d.nv, d.nn, tpl32, r32, &d.plan32, &ptab))
+            return cleanup_fail(fail(ctx, HOBI_E_ARG, "problem too large: %d sites x %d nodes", d.nv, d.nn));
+        d.partial_elems = std::max({(size_t)2 * d.plan64.slot * d.plan64.workers,
+                                    (size_t)2 * d.plan32.slot * d.plan32.workers,
+                                    (size_t)d.nc_pad * d.plan_pts.chunks});
+    }
+
     hipStream_t s = ctx->stream;
     const int ns = d.nv;   // sites
+    PCHK(dalloc(&d.plan_tab, ptab.size()));
+    PCHK(hipMemcpyAsync(d.plan_tab, ptab.data(), sizeof(int) * ptab.size(), hipMemcpyHostToDevice, s));
+    d.plan64.gstart = d.plan_tab;
+    d.plan32.gstart = d.plan_tab + (d.plan64.groups + 1);
     PCHK(dalloc(&d.xyz, 3 * (size_t)ns));
     PCHK(dalloc(&d.nrm, 3 * (size_t)ns));
     if (lower) PCHK(dalloc(&d.vxyz, 3 * (size_t)nv));

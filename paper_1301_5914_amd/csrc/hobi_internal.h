@@ -13,14 +13,36 @@
 
 namespace hobi {
 
-// Launch configuration of the dense pair sum, fixed per problem size only (so that the
-// reduction order -- and hence every bit of the result -- depends only on the problem).
-struct PairPlan {
+// Launch configuration of the point sums at the charges: blocks of targets by chunks of
+// nodes, fixed per problem size only.
+struct GridPlan {
     int tpl;            // targets per lane
     int block;          // threads per block
     int target_blocks;  // blocks along the targets
     int chunks;         // source chunks (split of the node range)
     int chunk;          // nodes per chunk
+};
+
+// Split of the dense pair sum over waves ("workers").  The targets are cut into slots of
+// 64 * tpl (one wave's targets), the nodes into `groups` contiguous ranges of equal length
+// (within one node); worker w takes slot w % slots against node group w / slots and writes
+// one row of partial sums (2 * slot doubles, row w).  groups is chosen so that the workers
+// make about kPairPasses passes of the waves the device holds at once: short workers let
+// the hardware's dispatch balance the load to the end of the launch (one long pass ends
+// with many SIMDs idle), while each worker's partial row is written once and read once by
+// the combine step, which bounds the useful number of passes.  The workers of a node group
+// run side by side on one XCD and read the same nodes from its L2 at about the same time.
+// The split depends on the problem and the device only, and so does the order of every
+// sum (results are reproducible bit for bit).
+constexpr int kPairPasses = 8;
+struct PairPlan {
+    int tpl;            // targets per lane
+    int slot;           // targets per slot: 64 * tpl
+    int slots;          // ceil(nv / slot)
+    int groups;         // node groups
+    int workers;        // slots * groups waves = partial rows
+    int blocks;         // workgroups of a launch: ceil(workers / waves per workgroup)
+    const int* gstart;  // device [groups + 1]: node range of group g is [gstart[g], gstart[g + 1])
 };
 
 struct DeviceProblem {
@@ -55,9 +77,11 @@ struct DeviceProblem {
     double* coef = nullptr;                 // [3 nf][12] singular (Duffy) coefficients
     double* rhs = nullptr;                  // [2 nv] (S1, S2)
     // per-matvec work space
-    double* partial = nullptr;              // [chunks][2][nv_pad]
+    double* partial = nullptr;              // pair sums: [workers][2][slot]; point sums: [chunks][nc_pad]
     int nv_pad = 0;
-    PairPlan plan64{}, plan32{}, plan_pts{};
+    PairPlan plan64{}, plan32{};
+    GridPlan plan_pts{};
+    int* plan_tab = nullptr;                // device group starts of plan64, then of plan32
     size_t partial_elems = 0;
 };
 
@@ -70,8 +94,15 @@ hipError_t launch_sources(const DeviceProblem& p, hipStream_t s);
 hipError_t launch_lobi_nodes(const DeviceProblem& p, hipStream_t s);
 
 // ---- matvec kernels (pair_kernels.hip) ----
-PairPlan make_plan(int n_pad, int nn, int tpl);
+GridPlan make_grid_plan(int n_pad, int nn, int tpl);
 constexpr int kTpl64 = 2;   // targets per lane of the FP64 pair kernel
+inline int tpl32_for(int nv_pad) { return nv_pad >= 16384 ? 8 : 4; }
+// Waves of the FP32 (mixed) or FP64 pair kernel with `tpl` targets per lane that device
+// `device` holds at once (occupancy of the kernel times the compute units); 0 on error.
+int pair_resident_waves(int device, bool mixed, int tpl);
+// The split of nv targets by nn nodes for a device holding resident_waves of the kernel at
+// once; the group starts are appended to `gstart` (the plan's device pointer is left null).
+bool make_pair_plan(int nv, int nn, int tpl, int resident_waves, PairPlan* plan, std::vector<int>* gstart);
 hipError_t launch_gather(const DeviceProblem& p, const double* u, bool mixed, hipStream_t s);
 hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s);
 hipError_t launch_combine(const DeviceProblem& p, const double* u, double* y, bool mixed,

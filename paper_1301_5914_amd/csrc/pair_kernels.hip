@@ -6,14 +6,17 @@
 //   pair_f64/f32    -- the dense regular sum over every (vertex, node) pair except the
 //                      nodes of the vertex's own triangles (those are singular):
 //                      R1_i = sum K1 Gamma + K2 Phi, R2_i = sum K3 Gamma + K4 Phi,
-//                      split over source chunks, one FP64 partial per (chunk, vertex)
-//   combine_kernel  -- sums the chunk partials in a fixed order, adds the singular
+//                      one wave per (target slot, node group), one FP64 partial row
+//                      per wave
+//   combine_kernel  -- sums a slot's partial rows in a fixed order, adds the singular
 //                      correction (FP64 coefficients) and the diagonal 1/2 (1 + eps).
 //
 // Pair-kernel layout: each lane owns TPL target vertices in registers; the wavefront
-// walks its chunk of source nodes in lock-step, so every node is one wave-uniform
-// scalar load (32 or 64 bytes) broadcast to all 64 lanes -- no LDS traffic, no
+// walks its range of source nodes in lock-step, so every node is one wave-uniform
+// scalar load (64 or 128 bytes) broadcast to all 64 lanes -- no LDS traffic, no
 // barriers, and each target's sum stays in its own lane (no cross-lane reduction).
+// The launch fills whole passes of the waves the device keeps resident, all with the same
+// work (the node groups differ by at most one node).
 // exp and rsqrt are VALU transcendental instructions in the FP32 kernel.
 #include "hobi_internal.h"
 #include "pair_tile.h"
@@ -23,19 +26,6 @@ namespace hobi {
 namespace {
 
 constexpr int kBlock = kPairBlock;
-
-// Workgroups are dispatched round-robin over the 8 XCDs by linear id.  Give each XCD a
-// contiguous range of logical blocks (target block fastest) so that the blocks sharing a
-// source chunk run on the same XCD and re-read the chunk from that XCD's L2.
-__device__ __forceinline__ void xcd_block(int* tb, int* ch) {
-    const int nx = gridDim.x, nb = gridDim.x * gridDim.y;
-    const int lin = blockIdx.x + nx * blockIdx.y;
-    const int x = lin & 7, slot = lin >> 3;
-    const int q = nb >> 3, rm = nb & 7;
-    const int logical = x * q + min(x, rm) + slot;
-    *tb = logical % nx;
-    *ch = logical / nx;
-}
 
 __global__ void gather_kernel(const double* __restrict__ u, int nv, const int* __restrict__ tri,
                               const double* __restrict__ w, int nn, NodeD* __restrict__ node64,
@@ -48,32 +38,45 @@ __global__ void gather_kernel(const double* __restrict__ u, int nv, const int* _
         gather_node(idx, u, nv, tri, w, node64, node32, mixed, eps, s32);
 }
 
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// Workgroups are dispatched round-robin over the 8 XCDs by linear id.  Give each XCD a
+// contiguous range of logical workgroups, so that the workers of a node group (consecutive
+// logical ids) share that XCD's L2 while they read the group's nodes.
+__device__ __forceinline__ int xcd_logical_block() {
+    const int nb = gridDim.x, p = blockIdx.x;
+    const int x = p & 7, q = nb >> 3, rm = nb & 7;
+    return x * q + min(x, rm) + (p >> 3);
+}
+
+// One wave per worker of the pair plan: logical workgroup b holds workers
+// kWavesPerBlock * b + (its waves); waves past the last worker return at once.
 template <int TPL, bool KAPPA0>
 __global__ __launch_bounds__(kBlock) void pair_f64_kernel(
-    const double* __restrict__ tgt, int nv_pad, const NodeD* __restrict__ nodes,
-    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int nn, int chunk, double kappa,
-    double eps, double* __restrict__ partial) {
-    int tb, ch;
-    xcd_block(&tb, &ch);
-    pair_f64_tile<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, nn, chunk, kappa, eps, partial, tb, ch);
+    const double* __restrict__ tgt, int nv, int nv_pad, const NodeD* __restrict__ nodes,
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa, double eps,
+    const int* __restrict__ gstart, int slots, int workers, double* __restrict__ partial) {
+    const int w = xcd_logical_block() * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    if (w >= workers) return;
+    pair_f64_worker<TPL, KAPPA0>(tgt, nv, nv_pad, nodes, node_vid, blk_range, kappa, eps, gstart, slots, partial, w);
 }
 
 template <int TPL, bool KAPPA0>
 __global__ __launch_bounds__(kBlock) void pair_f32_kernel(
-    const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes,
-    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int nn, int chunk,
-    double* __restrict__ partial) {
-    int tb, ch;
-    xcd_block(&tb, &ch);
-    pair_f32_tile<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, nn, chunk, partial, tb, ch);
+    const float* __restrict__ tgt, int nv, int nv_pad, const NodeF* __restrict__ nodes,
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, const int* __restrict__ gstart,
+    int slots, int workers, double* __restrict__ partial) {
+    const int w = xcd_logical_block() * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    if (w >= workers) return;
+    pair_f32_worker<TPL, KAPPA0>(tgt, nv, nv_pad, nodes, node_vid, blk_range, gstart, slots, partial, w);
 }
 
-__global__ void combine_kernel(const double* __restrict__ u, double* __restrict__ y, int nv, int nv_pad,
-                               const double* __restrict__ partial, int chunks,
+__global__ void combine_kernel(const double* __restrict__ u, double* __restrict__ y, int nv,
+                               const double* __restrict__ partial, int slot, int slots, int groups,
                                const int* __restrict__ inc_off, const int* __restrict__ inc_ent,
                                const int* __restrict__ tri, const double* __restrict__ coef,
                                double eps) {
-    combine_tile(blockIdx.x, u, y, nv, nv_pad, partial, chunks, inc_off, inc_ent, tri, coef, eps);
+    combine_tile(blockIdx.x, u, y, nv, partial, slot, slots, groups, inc_off, inc_ent, tri, coef, eps);
 }
 
 // Sums over every regular node at interior points (the charges):
@@ -155,23 +158,53 @@ inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
 
-PairPlan make_plan(int n_pad, int nn, int tpl) {
-    PairPlan pl{};
+GridPlan make_grid_plan(int n_pad, int nn, int tpl) {
+    GridPlan pl{};
     pl.tpl = tpl;
     pl.block = kBlock;
     pl.target_blocks = n_pad / (kBlock * tpl);
     if (pl.target_blocks < 1) pl.target_blocks = 1;
-    // about 16 blocks per compute unit on 256 CUs (a short tail when the last wave of blocks
-    // drains); at least 256 nodes per chunk
+    // about 16 blocks per compute unit on 256 CUs; at least 256 nodes per chunk
     const int want = 4096;
     int chunks = (want + pl.target_blocks - 1) / pl.target_blocks;
     const int max_chunks = nn / 256 > 1 ? nn / 256 : 1;
     if (chunks > max_chunks) chunks = max_chunks;
     if (chunks < 1) chunks = 1;
     pl.chunk = (nn + chunks - 1) / chunks;
-    pl.chunk = (pl.chunk + kFold - 1) / kFold * kFold;   // node sub-blocks start on kFold
     pl.chunks = (nn + pl.chunk - 1) / pl.chunk;
     return pl;
+}
+
+bool make_pair_plan(int nv, int nn, int tpl, int resident_waves, PairPlan* plan, std::vector<int>* gstart) {
+    if (nv < 1 || nn < 1 || resident_waves < 1) return false;
+    PairPlan pl{};
+    pl.tpl = tpl;
+    pl.slot = kWave * tpl;
+    pl.slots = (nv + pl.slot - 1) / pl.slot;
+    // about kPairPasses passes of the resident waves, with at least kFold nodes per group
+    const int max_groups = std::max(1, nn / kFold);
+    const int64_t want = (int64_t)kPairPasses * resident_waves / pl.slots;
+    pl.groups = (int)std::max<int64_t>(1, std::min<int64_t>(want, max_groups));
+    if ((int64_t)pl.groups * pl.slots >= ((int64_t)1 << 31) / kWavesPerBlock) return false;
+    pl.workers = pl.groups * pl.slots;
+    pl.blocks = (pl.workers + kWavesPerBlock - 1) / kWavesPerBlock;
+    for (int g = 0; g <= pl.groups; ++g) gstart->push_back((int)((int64_t)g * nn / pl.groups));
+    pl.gstart = nullptr;
+    *plan = pl;
+    return true;
+}
+
+int pair_resident_waves(int device, bool mixed, int tpl) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    hipError_t e;
+    if (mixed)
+        e = tpl == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pair_f32_kernel<8, false>, kBlock, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pair_f32_kernel<4, false>, kBlock, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pair_f64_kernel<kTpl64, false>, kBlock, 0);
+    if (e != hipSuccess || per_cu < 1) return 0;
+    return cus * per_cu * kWavesPerBlock;
 }
 
 hipError_t launch_gather(const DeviceProblem& p, const double* u, bool mixed, hipStream_t s) {
@@ -184,10 +217,9 @@ hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s) {
     const bool k0 = p.kappa == 0.0;
     if (mixed) {
         const PairPlan& pl = p.plan32;
-        dim3 grid(pl.target_blocks, pl.chunks);
-#define HOBI_PAIR32(T, K0)                                                                        \
-    hipLaunchKernelGGL((pair_f32_kernel<T, K0>), grid, dim3(kBlock), 0, s, p.tgt32, p.nv_pad, p.node32, \
-                       p.node_vid, p.blk_range, p.nn, pl.chunk, p.partial)
+#define HOBI_PAIR32(T, K0)                                                                                    \
+    hipLaunchKernelGGL((pair_f32_kernel<T, K0>), dim3(pl.blocks), dim3(kBlock), 0, s, p.tgt32, p.nv, p.nv_pad, \
+                       p.node32, p.node_vid, p.blk_range, pl.gstart, pl.slots, pl.workers, p.partial)
         if (pl.tpl == 8) {
             if (k0) HOBI_PAIR32(8, true); else HOBI_PAIR32(8, false);
         } else {
@@ -196,26 +228,24 @@ hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s) {
 #undef HOBI_PAIR32
     } else {
         const PairPlan& pl = p.plan64;
-        dim3 grid(pl.target_blocks, pl.chunks);
-        if (k0)
-            hipLaunchKernelGGL((pair_f64_kernel<kTpl64, true>), grid, dim3(kBlock), 0, s, p.tgt64, p.nv_pad,
-                               p.node64, p.node_vid, p.blk_range, p.nn, pl.chunk, p.kappa, p.eps, p.partial);
-        else
-            hipLaunchKernelGGL((pair_f64_kernel<kTpl64, false>), grid, dim3(kBlock), 0, s, p.tgt64, p.nv_pad,
-                               p.node64, p.node_vid, p.blk_range, p.nn, pl.chunk, p.kappa, p.eps, p.partial);
+#define HOBI_PAIR64(K0)                                                                                          \
+    hipLaunchKernelGGL((pair_f64_kernel<kTpl64, K0>), dim3(pl.blocks), dim3(kBlock), 0, s, p.tgt64, p.nv, p.nv_pad, \
+                       p.node64, p.node_vid, p.blk_range, p.kappa, p.eps, pl.gstart, pl.slots, pl.workers, p.partial)
+        if (k0) HOBI_PAIR64(true); else HOBI_PAIR64(false);
+#undef HOBI_PAIR64
     }
     return hipGetLastError();
 }
 
 hipError_t launch_combine(const DeviceProblem& p, const double* u, double* y, bool mixed, hipStream_t s) {
-    const int chunks = mixed ? p.plan32.chunks : p.plan64.chunks;
-    hipLaunchKernelGGL(combine_kernel, dim3(nblk(p.nv, kCombineVerts)), dim3(kPairBlock), 0, s, u, y, p.nv, p.nv_pad,
-                       p.partial, chunks, p.inc_off, p.inc_ent, p.tri, p.coef, p.eps);
+    const PairPlan& pl = mixed ? p.plan32 : p.plan64;
+    hipLaunchKernelGGL(combine_kernel, dim3(nblk(p.nv, kCombineVerts)), dim3(kPairBlock), 0, s, u, y, p.nv,
+                       p.partial, pl.slot, pl.slots, pl.groups, p.inc_off, p.inc_ent, p.tri, p.coef, p.eps);
     return hipGetLastError();
 }
 
 hipError_t launch_reaction_energy(const DeviceProblem& p, double* phi_reac, double* e_out, hipStream_t s) {
-    const PairPlan& pl = p.plan_pts;
+    const GridPlan& pl = p.plan_pts;
     hipLaunchKernelGGL((point_sum_kernel<0>), dim3(pl.target_blocks, pl.chunks), dim3(kBlock), 0, s, p.qsoa,
                        p.nc_pad, p.node64, p.w, p.nn, pl.chunk, p.kappa, p.eps, p.partial);
     hipError_t e = hipGetLastError();
@@ -226,7 +256,7 @@ hipError_t launch_reaction_energy(const DeviceProblem& p, double* phi_reac, doub
 }
 
 hipError_t launch_solid_angle(const DeviceProblem& p, double* frac, hipStream_t s) {
-    const PairPlan& pl = p.plan_pts;
+    const GridPlan& pl = p.plan_pts;
     hipLaunchKernelGGL((point_sum_kernel<1>), dim3(pl.target_blocks, pl.chunks), dim3(kBlock), 0, s, p.qsoa,
                        p.nc_pad, p.node64, p.w, p.nn, pl.chunk, p.kappa, p.eps, p.partial);
     hipError_t e = hipGetLastError();

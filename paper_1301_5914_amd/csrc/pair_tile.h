@@ -1,7 +1,7 @@
-// One tile of the FP32 dense pair sum: kPairBlock * TPL target vertices (one per lane
-// and per k < TPL) against the source nodes of chunk `ch`.  Shared by the single-problem
-// kernel and the batched kernel of the request server, so that a request's partial sums
-// are bit-for-bit the same whichever launch computes them.
+// The dense pair sum of one wave ("worker"): one slot of targets against one contiguous
+// range of source nodes.  Shared by the single-problem kernels and the batched
+// kernels of the request server, so that a request's partial sums are bit-for-bit the
+// same whichever launch computes them.
 #pragma once
 
 #include "hobi_device.h"
@@ -10,6 +10,13 @@ namespace hobi {
 
 constexpr int kPairBlock = 256;
 constexpr int kFold = 64;   // FP32 running sums are folded into FP64 every kFold nodes
+constexpr int kWave = 64;
+
+// Target slots.  Slot s holds the kWave * TPL targets from s * kWave * TPL, lane l holding
+// (slot start) + kWave * k + l for k < TPL.  The wave holding the last slot narrows TPL to
+// what that slot holds (halving while the real targets still fit), so the padding of the
+// target count costs at most 63 targets' work.  Partials of padding targets are neither
+// written nor read.
 
 // Source records are read-only for the whole launch and every wave reads them at
 // wave-uniform addresses: reading them through the constant address space makes each
@@ -36,6 +43,26 @@ __device__ __forceinline__ int4 load_vid(const const_as<int4>* p, int s) {
     return make_int4(p[s].x, p[s].y, p[s].z, 0);
 }
 
+// Lanes of target slot k (targets base + 64 k + lane) that are vertices of the node's
+// triangle, as a wave-wide lane mask: vid holds the vertex ids and base is wave-uniform,
+// so the mask is built with scalar instructions and applied with one conditional move per
+// slot (the mask is the move's lane condition).
+template <int K>
+__device__ __forceinline__ uint64_t vertex_lanes(int4 vid, int base) {
+    const unsigned ux = (unsigned)(vid.x - base), uy = (unsigned)(vid.y - base), uz = (unsigned)(vid.z - base);
+    uint64_t m = 0;
+    if ((ux >> 6) == (unsigned)K) m |= 1ull << (ux & 63);
+    if ((uy >> 6) == (unsigned)K) m |= 1ull << (uy & 63);
+    if ((uz >> 6) == (unsigned)K) m |= 1ull << (uz & 63);
+    return m;
+}
+
+template <int TPL, int K = 0>
+__device__ __forceinline__ void vertex_lane_masks(int4 vid, int base, uint64_t (&m)[TPL]) {
+    m[K] = vertex_lanes<K>(vid, base);
+    if constexpr (K + 1 < TPL) vertex_lane_masks<TPL, K + 1>(vid, base, m);
+}
+
 __device__ __forceinline__ NodeD load_node(const const_as<NodeD>* p, int s) {
     NodeD n;
     n.x = p[s].x, n.y = p[s].y, n.z = p[s].z, n.g = p[s].g;
@@ -56,7 +83,7 @@ __device__ __forceinline__ NodeD load_node(const const_as<NodeD>* p, int s) {
 // vertex with its own triangles' nodes (they belong to the singular rule) are skipped.
 template <int TPL, bool KAPPA0, bool MASK>
 __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, const const_as<int4>* cvid, int sb,
-                                             int se, int t0, const float (&tx)[TPL], const float (&ty)[TPL],
+                                             int se, int base, const float (&tx)[TPL], const float (&ty)[TPL],
                                              const float (&tz)[TPL], const float (&tnx)[TPL],
                                              const float (&tny)[TPL], const float (&tnz)[TPL],
                                              float (&a1)[TPL], float (&a2)[TPL]) {
@@ -65,17 +92,14 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, cons
     for (int s = sb; s < se; ++s) {
         // the next record's scalar load is in flight while this one is used
         const NodeF next = load_node(cnodes, min(s + 1, se - 1));
-        int4 vid = make_int4(-1, -1, -1, 0);
-        if (MASK) vid = load_vid(cvid, s);
+        uint64_t vmask[TPL];
+        if (MASK) vertex_lane_masks<TPL>(load_vid(cvid, s), base, vmask);
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
             const float dx = tx[k] - n.x, dy = ty[k] - n.y, dz = tz[k] - n.z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             float rinv = __builtin_amdgcn_rsqf(r2);
-            if (MASK) {
-                const int t = t0 + k * kPairBlock;
-                if ((t == vid.x) | (t == vid.y) | (t == vid.z)) rinv = 0.0f;
-            }
+            if (MASK && __builtin_amdgcn_inverse_ballot_w64(vmask[k])) rinv = 0.0f;
             const float rinv2 = rinv * rinv;
             const float dny = fmaf(dx, n.nx, fmaf(dy, n.ny, dz * n.nz));
             const float dnx = fmaf(dx, tnx[k], fmaf(dy, tny[k], dz * tnz[k]));
@@ -100,21 +124,24 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, cons
     }
 }
 
-// FP32 pairs, FP64 accumulation: running FP32 sums over kFold nodes are added into FP64
-// per-target accumulators.  blk_range[b] = (min, max) vertex id of the triangles of nodes
-// [64 b, 64 b + 64); a wave whose target ranges miss it runs the unmasked loop.
+// FP32 pairs, FP64 accumulation, of the kWave * TPL targets from `base` (wave-uniform) with
+// the nodes [n0, n1): running FP32 sums over the nodes of one kFold-aligned block are added
+// into FP64 per-target accumulators, stored to row `prow` of the partial sums (row 1 sums
+// at prow[t - base], row 2 sums at prow[slot + t - base]).  blk_range[b] = (min, max)
+// vertex id of the triangles of nodes [kFold b, kFold b + kFold); a wave whose targets miss
+// it runs the unmasked loop.
 template <int TPL, bool KAPPA0>
-__device__ __forceinline__ void pair_f32_tile(
+__device__ __forceinline__ void pair_f32_wave(
     const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes,
-    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int nn, int chunk,
-    double* __restrict__ partial, int tb, int ch) {
-    const int t0 = tb * (kPairBlock * TPL) + threadIdx.x;
-    const int wave0 = tb * (kPairBlock * TPL) + (__builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63);
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int base, int n0, int n1,
+    double* __restrict__ prow, int slot) {
+    const int lane = (int)(threadIdx.x % kWave);
+    const int t0 = base + lane;
     float tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL];
     double d1[TPL], d2[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
-        const int t = t0 + k * kPairBlock;
+        const int t = t0 + k * kWave;
         tx[k] = tgt[t];
         ty[k] = tgt[(size_t)nv_pad + t];
         tz[k] = tgt[2 * (size_t)nv_pad + t];
@@ -124,27 +151,20 @@ __device__ __forceinline__ void pair_f32_tile(
         d1[k] = 0.0;
         d2[k] = 0.0;
     }
-    const int s0 = ch * chunk;                 // chunk is a multiple of kFold
-    const int s1 = min(s0 + chunk, nn);
     const const_as<NodeF>* cnodes = as_constant(nodes);
     const const_as<int4>* cvid = as_constant(node_vid);
     const const_as<int2>* crange = as_constant(blk_range);
-    for (int sb = s0; sb < s1; sb += kFold) {
-        const int se = min(sb + kFold, s1);
+    for (int sb = n0, se; sb < n1; sb = se) {
+        se = min((sb / kFold + 1) * kFold, n1);
         const int vlo = crange[sb / kFold].x, vhi = crange[sb / kFold].y;
-        bool near = false;
-#pragma unroll
-        for (int k = 0; k < TPL; ++k) {
-            const int lo = wave0 + k * kPairBlock;
-            near |= (vhi >= lo) & (vlo <= lo + 63);
-        }
+        const bool near = (vhi >= base) & (vlo < base + kWave * TPL);
         float a1[TPL], a2[TPL];
 #pragma unroll
         for (int k = 0; k < TPL; ++k) a1[k] = a2[k] = 0.0f;
         if (near)
-            pair_f32_run<TPL, KAPPA0, true>(cnodes, cvid, sb, se, t0, tx, ty, tz, tnx, tny, tnz, a1, a2);
+            pair_f32_run<TPL, KAPPA0, true>(cnodes, cvid, sb, se, base, tx, ty, tz, tnx, tny, tnz, a1, a2);
         else
-            pair_f32_run<TPL, KAPPA0, false>(cnodes, cvid, sb, se, t0, tx, ty, tz, tnx, tny, tnz, a1, a2);
+            pair_f32_run<TPL, KAPPA0, false>(cnodes, cvid, sb, se, base, tx, ty, tz, tnx, tny, tnz, a1, a2);
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
             d1[k] += (double)a1[k];
@@ -153,10 +173,41 @@ __device__ __forceinline__ void pair_f32_tile(
     }
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
-        const int t = t0 + k * kPairBlock;
-        partial[(size_t)(2 * ch) * nv_pad + t] = d1[k];
-        partial[(size_t)(2 * ch + 1) * nv_pad + t] = d2[k];
+        prow[lane + k * kWave] = d1[k];
+        prow[slot + lane + k * kWave] = d2[k];
     }
+}
+
+// The slot from `base` with `live` = nv - base >= 1 real targets in it: the narrowest TPL
+// (halving) whose kWave * TPL targets still cover them.
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void pair_f32_narrow(
+    int live, const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes,
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int base, int n0, int n1,
+    double* __restrict__ prow, int slot) {
+    if constexpr (TPL > 1) {
+        if (live <= kWave * TPL / 2) {
+            pair_f32_narrow<TPL / 2, KAPPA0>(live, tgt, nv_pad, nodes, node_vid, blk_range, base, n0, n1, prow, slot);
+            return;
+        }
+    }
+    pair_f32_wave<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, base, n0, n1, prow, slot);
+}
+
+// Worker w of a pair plan with `slots` target slots and node groups [gstart[g],
+// gstart[g + 1]): slot w % slots against group w / slots, into partial row w.  w must be
+// wave-uniform and below slots * groups.
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void pair_f32_worker(
+    const float* __restrict__ tgt, int nv, int nv_pad, const NodeF* __restrict__ nodes,
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, const int* __restrict__ gstart,
+    int slots, double* __restrict__ partial, int w) {
+    constexpr int kSlot = kWave * TPL;
+    const int g = w / slots, s = w - g * slots;
+    const const_as<int>* cg = as_constant(gstart);
+    const int base = s * kSlot;
+    pair_f32_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, nodes, node_vid, blk_range, base, cg[g], cg[g + 1],
+                                 partial + (size_t)w * (2 * kSlot), kSlot);
 }
 
 // Node strengths Gamma = g, Phi = p (1/(4 pi) folded in) and the quantities derived from
@@ -226,23 +277,20 @@ __device__ __forceinline__ void gather_site(int j, const double* __restrict__ u,
 // skipped.
 template <int TPL, bool KAPPA0, bool MASK>
 __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, const const_as<int4>* cvid, int sb,
-                                             int se, int t0, const double (&tx)[TPL], const double (&ty)[TPL],
+                                             int se, int base, const double (&tx)[TPL], const double (&ty)[TPL],
                                              const double (&tz)[TPL], const double (&tnx)[TPL],
                                              const double (&tny)[TPL], const double (&tnz)[TPL], double kappa,
                                              double eps, double (&a1)[TPL], double (&a2)[TPL]) {
     for (int s = sb; s < se; ++s) {
         const NodeD nd = load_node(cnodes, s);   // (a prefetched FP64 record would not fit the scalar registers)
-        int4 vid = make_int4(-1, -1, -1, 0);
-        if (MASK) vid = load_vid(cvid, s);
+        uint64_t vmask[TPL];
+        if (MASK) vertex_lane_masks<TPL>(load_vid(cvid, s), base, vmask);
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
             const double dx = tx[k] - nd.x, dy = ty[k] - nd.y, dz = tz[k] - nd.z;
             const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
             double rinv = rsqrt_f64(r2);
-            if (MASK) {
-                const int t = t0 + k * kPairBlock;
-                if ((t == vid.x) | (t == vid.y) | (t == vid.z)) rinv = 0.0;
-            }
+            if (MASK && __builtin_amdgcn_inverse_ballot_w64(vmask[k])) rinv = 0.0;
             const double rinv2 = rinv * rinv;
             const double dny = fma(dx, nd.nx, fma(dy, nd.ny, dz * nd.nz));
             const double dnx = fma(dx, tnx[k], fma(dy, tny[k], dz * tnz[k]));
@@ -281,19 +329,19 @@ __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, cons
     }
 }
 
-// FP64 pairs of target block tb with the nodes of chunk ch (same block-range test as the
-// FP32 tile).
+// FP64 pairs of the kWave * TPL targets from `base` with the nodes [n0, n1), stored to row
+// `prow` as in the FP32 wave (same block-range test).
 template <int TPL, bool KAPPA0>
-__device__ __forceinline__ void pair_f64_tile(
+__device__ __forceinline__ void pair_f64_wave(
     const double* __restrict__ tgt, int nv_pad, const NodeD* __restrict__ nodes,
-    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int nn, int chunk, double kappa,
-    double eps, double* __restrict__ partial, int tb, int ch) {
-    const int t0 = tb * (kPairBlock * TPL) + threadIdx.x;
-    const int wave0 = tb * (kPairBlock * TPL) + (__builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63);
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa, double eps,
+    int base, int n0, int n1, double* __restrict__ prow, int slot) {
+    const int lane = (int)(threadIdx.x % kWave);
+    const int t0 = base + lane;
     double tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL], a1[TPL], a2[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
-        const int t = t0 + k * kPairBlock;
+        const int t = t0 + k * kWave;
         tx[k] = tgt[t];
         ty[k] = tgt[(size_t)nv_pad + t];
         tz[k] = tgt[2 * (size_t)nv_pad + t];
@@ -303,53 +351,79 @@ __device__ __forceinline__ void pair_f64_tile(
         a1[k] = 0.0;
         a2[k] = 0.0;
     }
-    const int s0 = ch * chunk;                 // chunk is a multiple of kFold
-    const int s1 = min(s0 + chunk, nn);
     const const_as<NodeD>* cnodes = as_constant(nodes);
     const const_as<int4>* cvid = as_constant(node_vid);
     const const_as<int2>* crange = as_constant(blk_range);
-    for (int sb = s0; sb < s1; sb += kFold) {
-        const int se = min(sb + kFold, s1);
+    for (int sb = n0, se; sb < n1; sb = se) {
+        se = min((sb / kFold + 1) * kFold, n1);
         const int vlo = crange[sb / kFold].x, vhi = crange[sb / kFold].y;
-        bool near = false;
-#pragma unroll
-        for (int k = 0; k < TPL; ++k) {
-            const int lo = wave0 + k * kPairBlock;
-            near |= (vhi >= lo) & (vlo <= lo + 63);
-        }
+        const bool near = (vhi >= base) & (vlo < base + kWave * TPL);
         if (near)
-            pair_f64_run<TPL, KAPPA0, true>(cnodes, cvid, sb, se, t0, tx, ty, tz, tnx, tny, tnz, kappa, eps, a1, a2);
+            pair_f64_run<TPL, KAPPA0, true>(cnodes, cvid, sb, se, base, tx, ty, tz, tnx, tny, tnz, kappa, eps, a1,
+                                            a2);
         else
-            pair_f64_run<TPL, KAPPA0, false>(cnodes, cvid, sb, se, t0, tx, ty, tz, tnx, tny, tnz, kappa, eps, a1, a2);
+            pair_f64_run<TPL, KAPPA0, false>(cnodes, cvid, sb, se, base, tx, ty, tz, tnx, tny, tnz, kappa, eps, a1,
+                                             a2);
     }
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
-        const int t = t0 + k * kPairBlock;
-        partial[(size_t)(2 * ch) * nv_pad + t] = a1[k];
-        partial[(size_t)(2 * ch + 1) * nv_pad + t] = a2[k];
+        prow[lane + k * kWave] = a1[k];
+        prow[slot + lane + k * kWave] = a2[k];
     }
+}
+
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void pair_f64_narrow(
+    int live, const double* __restrict__ tgt, int nv_pad, const NodeD* __restrict__ nodes,
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa, double eps,
+    int base, int n0, int n1, double* __restrict__ prow, int slot) {
+    if constexpr (TPL > 1) {
+        if (live <= kWave * TPL / 2) {
+            pair_f64_narrow<TPL / 2, KAPPA0>(live, tgt, nv_pad, nodes, node_vid, blk_range, kappa, eps, base, n0, n1,
+                                              prow, slot);
+            return;
+        }
+    }
+    pair_f64_wave<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, kappa, eps, base, n0, n1, prow, slot);
+}
+
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void pair_f64_worker(
+    const double* __restrict__ tgt, int nv, int nv_pad, const NodeD* __restrict__ nodes,
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa, double eps,
+    const int* __restrict__ gstart, int slots, double* __restrict__ partial, int w) {
+    constexpr int kSlot = kWave * TPL;
+    const int g = w / slots, s = w - g * slots;
+    const const_as<int>* cg = as_constant(gstart);
+    const int base = s * kSlot;
+    pair_f64_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, nodes, node_vid, blk_range, kappa, eps, base, cg[g],
+                                 cg[g + 1], partial + (size_t)w * (2 * kSlot), kSlot);
 }
 
 constexpr int kCombineWays = kPairBlock / kCombineVerts;  // waves splitting the chunk sum
 
-// Rows (i, i + nv) of y = A u for the kCombineVerts vertices of tile vb: the chunk partials
-// (wave s sums chunks s, s + 4, ...; the four sums are then added in a fixed order), the
-// singular correction and the diagonal.  Must be called by all kPairBlock threads of the
-// block (it synchronises them).
+// Rows (i, i + nv) of y = A u for the kCombineVerts vertices of tile vb: the partial rows of
+// their slot s (rows g * slots + s for the node groups g, each 2 * slot doubles; wave k of
+// the block sums groups k, k + 4, ... and the four sums are then added in a fixed order),
+// the singular correction and the diagonal.  slot is a multiple of kCombineVerts.  Must be called by all
+// kPairBlock threads of the block (it synchronises them).
 __device__ __forceinline__ void combine_tile(int vb, const double* __restrict__ u, double* __restrict__ y, int nv,
-                                             int nv_pad, const double* __restrict__ partial, int chunks,
-                                             const int* __restrict__ inc_off, const int* __restrict__ inc_ent,
+                                             const double* __restrict__ partial, int slot, int slots,
+                                             int groups, const int* __restrict__ inc_off, const int* __restrict__ inc_ent,
                                              const int* __restrict__ tri, const double* __restrict__ coef,
                                              double eps) {
     static_assert(kCombineWays == 4, "four partial sums per vertex");
     __shared__ double red[2][kCombineWays][kCombineVerts];
     const int lane = threadIdx.x % kCombineVerts, way = threadIdx.x / kCombineVerts;
     const int i = vb * kCombineVerts + lane;
+    const int s = vb * kCombineVerts / slot;
+    const int o = i - s * slot;
     double r1 = 0.0, r2 = 0.0;
     if (i < nv) {
-        for (int c = way; c < chunks; c += kCombineWays) {
-            r1 += partial[(size_t)(2 * c) * nv_pad + i];
-            r2 += partial[(size_t)(2 * c + 1) * nv_pad + i];
+        for (int g = way; g < groups; g += kCombineWays) {
+            const size_t r = (size_t)g * slots + s;
+            r1 += partial[(2 * r) * slot + o];
+            r2 += partial[(2 * r + 1) * slot + o];
         }
     }
     __syncthreads();                           // the previous tile's sums have been read

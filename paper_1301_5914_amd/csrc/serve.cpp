@@ -63,17 +63,27 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 // Device bytes of one admitted request (the allocations of hobi_problem_create plus the
 // server's Krylov basis), from its sizes alone.
-int64_t footprint_bytes(int nv, int nf, int nc, int m, int method) {
+int64_t footprint_bytes(int device, int nv, int nf, int nc, int m, int method) {
     // the lower-order method has one site and one node per triangle (an upper bound below)
     if (method == HOBI_LOWER_ORDER) nv = std::max(nv, nf);
     const int64_t nv_pad = round_up(nv, 2048), nc_pad = round_up(nc, 256), nn = 4LL * nf;
-    const PairPlan p64 = make_plan((int)nv_pad, (int)nn, kTpl64), p32 = make_plan((int)nv_pad, (int)nn, nv_pad >= 16384 ? 8 : 4);
-    const PairPlan pp = make_plan((int)nc_pad, (int)nn, 1);
+    const GridPlan pp = make_grid_plan((int)nc_pad, (int)nn, 1);
+    // pair plans: one partial row of 2 * slot doubles per worker, and the group starts
+    int64_t pair_rows_elems = 0, tab_ints = 0;
+    for (int mixed = 0; mixed < 2; ++mixed) {
+        const int tpl = mixed ? tpl32_for((int)nv_pad) : kTpl64;
+        PairPlan pl{};
+        std::vector<int> gs;
+        if (!make_pair_plan(nv, (int)nn, tpl, std::max(1, pair_resident_waves(device, mixed, tpl)), &pl, &gs))
+            return INT64_MAX;
+        pair_rows_elems = std::max<int64_t>(pair_rows_elems, 2LL * pl.slot * pl.workers);
+        tab_ints += (int64_t)gs.size();
+    }
     int64_t b = 0;
     b += 8 * (6LL * nv + 4LL * nc + 3 * nc_pad + 30LL * nf + 4 * nn + 12 * nv_pad + 36LL * nf + 2LL * nv + 4LL * nv);
     b += (int64_t)sizeof(NodeD) * nn + (int64_t)sizeof(NodeF) * nn + 16 * nn + 8 * (nn / 64 + 1);
     b += 4 * (3LL * nf + nv + 1 + 3LL * nf + nv + nf) + 2LL * 4 * nv_pad;
-    b += 8 * std::max<int64_t>(2 * nv_pad * std::max(p64.chunks, p32.chunks), nc_pad * pp.chunks);
+    b += 8 * std::max<int64_t>(pair_rows_elems, nc_pad * pp.chunks) + 4 * tab_ints;
     const int64_t n = 2LL * nv;
     b += 8 * ((int64_t)(m + 1) * n + (int64_t)(m + 1) * m + 6LL * (m + 1) + kDotBlocks * (int64_t)(m + 1) + n + 8);
     return b;
@@ -266,7 +276,7 @@ hobi_status tick(hobi_server sv) {
     for (auto& rp : sv->active) {
         const DeviceProblem& d = rp->pb->d;
         cnt[0] += (d.nn + kServeBlock - 1) / kServeBlock;
-        cnt[rp->prm.precision == HOBI_MIXED ? 1 : 2] += (size_t)rp->plan.target_blocks * rp->plan.chunks;
+        cnt[rp->prm.precision == HOBI_MIXED ? 1 : 2] += (size_t)rp->plan.blocks;
         cnt[3] += (d.nv + kCombineVerts - 1) / kCombineVerts;
     }
     // the four lists live at fixed offsets (quarters of the item buffer), so that the
@@ -306,8 +316,11 @@ hobi_status tick(hobi_server sv) {
         sd.nv = d.nv;
         sd.nv_pad = d.nv_pad;
         sd.nn = d.nn;
-        sd.chunk = r.plan.chunk;
-        sd.chunks = r.plan.chunks;
+        sd.gstart = r.plan.gstart;
+        sd.workers = r.plan.workers;
+        sd.slots = r.plan.slots;
+        sd.groups = r.plan.groups;
+        sd.slot = r.plan.slot;
         sd.mixed = r.prm.precision == HOBI_MIXED ? 1 : 0;
         sd.tpl = r.plan.tpl;
         sd.method = d.method;
@@ -315,8 +328,7 @@ hobi_status tick(hobi_server sv) {
         for (int blk = 0; blk < (d.nn + kServeBlock - 1) / kServeBlock; ++blk)
             hl[0][fill[0]++] = ServeItem{(int)q, blk, 0, 0};
         const int pl = sd.mixed ? 1 : 2;
-        for (int ch = 0; ch < r.plan.chunks; ++ch)
-            for (int tb = 0; tb < r.plan.target_blocks; ++tb) hl[pl][fill[pl]++] = ServeItem{(int)q, tb, ch, 0};
+        for (int b = 0; b < r.plan.blocks; ++b) hl[pl][fill[pl]++] = ServeItem{(int)q, b, 0, 0};
         for (int blk = 0; blk < (d.nv + kCombineVerts - 1) / kCombineVerts; ++blk)
             hl[3][fill[3]++] = ServeItem{(int)q, blk, 0, 0};
     }
@@ -509,7 +521,7 @@ hobi_status hobi_server_submit(hobi_server sv, int32_t nv, const double* xyz, co
     if (params) r->prm = *params;
     r->prm.restart = r->prm.max_iter;
     r->nu = r->prm.method == HOBI_LOWER_ORDER ? nf : nv;
-    r->footprint = footprint_bytes(nv, nf, nc, std::max(1, r->prm.max_iter), r->prm.method);
+    r->footprint = footprint_bytes(sv->device, nv, nf, nc, std::max(1, r->prm.max_iter), r->prm.method);
     std::lock_guard<std::mutex> lk(sv->mu);
     if (r->footprint > sv->budget) {
         sv->last_error = "request footprint exceeds the server budget";

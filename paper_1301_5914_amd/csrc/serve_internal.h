@@ -24,7 +24,8 @@ struct ServeDesc {
     const int2* blk_range;
     const float* tgt32;
     const double* tgt64;
-    double* partial;        // [chunks][2][nv_pad]
+    double* partial;        // [workers][2][slot] (the pair plan's rows)
+    const int* gstart;      // the pair plan's node-group starts
     const int* inc_off;
     const int* inc_ent;
     const double* coef;
@@ -32,15 +33,15 @@ struct ServeDesc {
     double eps;
     double s32;             // scale of the FP32 positions
     int nv, nv_pad, nn;
-    int chunk, chunks;
+    int workers, slots, groups, slot;   // the pair plan (the single-problem plan)
     int mixed;
     int tpl;                // targets per lane of the request's pair plan (the single-problem plan)
     int method;             // HOBI_HIGHER_ORDER or HOBI_LOWER_ORDER
     int pad;
 };
 
-// One unit of work: request `req`; (a, b) = (target block, chunk) for the pair kernel,
-// (node or vertex block, 0) for gather and combine.
+// One unit of work: request `req`; a = workgroup of the pair plan's workers (waves
+// 4a .. 4a + 3) for the pair kernels, node or vertex block for gather and combine.
 struct ServeItem {
     int req, a, b, pad;
 };

@@ -2,7 +2,8 @@
 // dense pair sum, combine) for every active request.  The launches walk device-side work
 // lists with a grid-stride loop, so their grids are fixed and the three launches can be
 // captured once in a HIP graph; the host only rewrites the descriptor and item arrays
-// between ticks.  Each item runs the same tile functions as the single-problem kernels,
+// between ticks.  Each item runs the same tile and worker functions as the single-problem
+// kernels (a pair item is one workgroup's worth of the problem's own pair plan),
 // and a request's items depend only on that request, so its result does not depend on
 // which other requests share the launch.
 #include "hobi_internal.h"
@@ -42,23 +43,26 @@ __global__ __launch_bounds__(kPairBlock) void batched_gather_kernel(const ServeD
 __global__ __launch_bounds__(kPairBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void batched_pair32_kernel(
     const ServeDesc* __restrict__ desc, const ServeItem* __restrict__ items, const int* __restrict__ count) {
     const int n = as_constant(count)[0];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const const_as<ServeItem>& item = as_constant(items)[uniform(it)];
         const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
+        const int w = item.a * (kPairBlock / kWave) + wave;
+        if (w >= d.workers) continue;
         if (d.tpl == 8) {
             if (d.kappa == 0.0)
-                pair_f32_tile<8, true>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk, d.partial,
-                                       item.a, item.b);
+                pair_f32_worker<8, true>(d.tgt32, d.nv, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.gstart, d.slots,
+                                         d.partial, w);
             else
-                pair_f32_tile<8, false>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk,
-                                        d.partial, item.a, item.b);
+                pair_f32_worker<8, false>(d.tgt32, d.nv, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.gstart, d.slots,
+                                          d.partial, w);
         } else {
             if (d.kappa == 0.0)
-                pair_f32_tile<4, true>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk, d.partial,
-                                       item.a, item.b);
+                pair_f32_worker<4, true>(d.tgt32, d.nv, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.gstart, d.slots,
+                                         d.partial, w);
             else
-                pair_f32_tile<4, false>(d.tgt32, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.nn, d.chunk,
-                                        d.partial, item.a, item.b);
+                pair_f32_worker<4, false>(d.tgt32, d.nv, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.gstart, d.slots,
+                                          d.partial, w);
         }
     }
 }
@@ -67,15 +71,18 @@ __global__ __launch_bounds__(kPairBlock) void batched_pair64_kernel(const ServeD
                                                                   const ServeItem* __restrict__ items,
                                                                   const int* __restrict__ count) {
     const int n = as_constant(count)[0];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const const_as<ServeItem>& item = as_constant(items)[uniform(it)];
         const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
+        const int w = item.a * (kPairBlock / kWave) + wave;
+        if (w >= d.workers) continue;
         if (d.kappa == 0.0)
-            pair_f64_tile<kTpl64, true>(d.tgt64, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.nn, d.chunk, d.kappa,
-                                        d.eps, d.partial, item.a, item.b);
+            pair_f64_worker<kTpl64, true>(d.tgt64, d.nv, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.kappa, d.eps,
+                                          d.gstart, d.slots, d.partial, w);
         else
-            pair_f64_tile<kTpl64, false>(d.tgt64, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.nn, d.chunk,
-                                         d.kappa, d.eps, d.partial, item.a, item.b);
+            pair_f64_worker<kTpl64, false>(d.tgt64, d.nv, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.kappa, d.eps,
+                                           d.gstart, d.slots, d.partial, w);
     }
 }
 
@@ -86,8 +93,8 @@ __global__ __launch_bounds__(kPairBlock) void batched_combine_kernel(const Serve
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const const_as<ServeItem>& item = as_constant(items)[uniform(it)];
         const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
-        combine_tile(item.a, d.u, d.y, d.nv, d.nv_pad, d.partial, d.chunks, d.inc_off, d.inc_ent, d.tri, d.coef,
-                     d.eps);
+        combine_tile(item.a, d.u, d.y, d.nv, d.partial, d.slot, d.slots, d.groups, d.inc_off, d.inc_ent, d.tri,
+                     d.coef, d.eps);
     }
 }
 
