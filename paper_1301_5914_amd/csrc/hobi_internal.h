@@ -30,11 +30,12 @@ struct GridPlan {
 // make about kPairPasses passes of the waves the device holds at once: short workers let
 // the hardware's dispatch balance the load to the end of the launch (one long pass ends
 // with many SIMDs idle), while each worker's partial row is written once and read once by
-// the combine step, which bounds the useful number of passes.  The workers of a node group
-// run side by side on one XCD and read the same nodes from its L2 at about the same time.
-// The split depends on the problem and the device only, and so does the order of every
-// sum (results are reproducible bit for bit).
-constexpr int kPairPasses = 8;
+// the combine step, so a group keeps at least kMinGroupNodes nodes.  The workers of a node
+// group run side by side on one XCD and read the same nodes from its L2 at about the same
+// time.  The split depends on the problem and the device only, and so does the order of
+// every sum (results are reproducible bit for bit).
+constexpr int kPairPasses = 16;
+constexpr int kMinGroupNodes = 256;
 struct PairPlan {
     int tpl;            // targets per lane
     int slot;           // targets per slot: 64 * tpl

@@ -181,8 +181,9 @@ bool make_pair_plan(int nv, int nn, int tpl, int resident_waves, PairPlan* plan,
     pl.tpl = tpl;
     pl.slot = kWave * tpl;
     pl.slots = (nv + pl.slot - 1) / pl.slot;
-    // about kPairPasses passes of the resident waves, with at least kFold nodes per group
-    const int max_groups = std::max(1, nn / kFold);
+    // about kPairPasses passes of the resident waves, with at least kMinGroupNodes nodes per
+    // group (a worker's partial row then costs the combine step little next to its pairs)
+    const int max_groups = std::max(1, nn / kMinGroupNodes);
     const int64_t want = (int64_t)kPairPasses * resident_waves / pl.slots;
     pl.groups = (int)std::max<int64_t>(1, std::min<int64_t>(want, max_groups));
     if ((int64_t)pl.groups * pl.slots >= ((int64_t)1 << 31) / kWavesPerBlock) return false;

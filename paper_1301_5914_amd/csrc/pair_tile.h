@@ -400,11 +400,13 @@ __device__ __forceinline__ void pair_f64_worker(
                                  cg[g + 1], partial + (size_t)w * (2 * kSlot), kSlot);
 }
 
-constexpr int kCombineWays = kPairBlock / kCombineVerts;  // waves splitting the chunk sum
+constexpr int kCombineWays = kPairBlock / kCombineVerts;  // waves splitting the sum over node groups
+constexpr int kCombineUnroll = 8;
 
 // Rows (i, i + nv) of y = A u for the kCombineVerts vertices of tile vb: the partial rows of
 // their slot s (rows g * slots + s for the node groups g, each 2 * slot doubles; wave k of
-// the block sums groups k, k + 4, ... and the four sums are then added in a fixed order),
+// the block sums groups k, k + 4, ... into eight running sums by turn, and the sums of
+// each wave and then of the four waves are added in a fixed order),
 // the singular correction and the diagonal.  slot is a multiple of kCombineVerts.  Must be called by all
 // kPairBlock threads of the block (it synchronises them).
 __device__ __forceinline__ void combine_tile(int vb, const double* __restrict__ u, double* __restrict__ y, int nv,
@@ -420,11 +422,29 @@ __device__ __forceinline__ void combine_tile(int vb, const double* __restrict__ 
     const int o = i - s * slot;
     double r1 = 0.0, r2 = 0.0;
     if (i < nv) {
-        for (int g = way; g < groups; g += kCombineWays) {
-            const size_t r = (size_t)g * slots + s;
-            r1 += partial[(2 * r) * slot + o];
-            r2 += partial[(2 * r + 1) * slot + o];
+        // kCombineUnroll rows in flight per wave, into separate sums added in a fixed order
+        double p1[kCombineUnroll], p2[kCombineUnroll];
+#pragma unroll
+        for (int j = 0; j < kCombineUnroll; ++j) p1[j] = p2[j] = 0.0;
+        const double* col = partial + o;
+        const size_t row_step = (size_t)kCombineWays * slots * 2 * slot;
+        const double* q = col + ((size_t)way * slots + s) * 2 * slot;
+        int g = way;
+        for (; g + (kCombineUnroll - 1) * kCombineWays < groups; g += kCombineUnroll * kCombineWays) {
+#pragma unroll
+            for (int j = 0; j < kCombineUnroll; ++j) {
+                p1[j] += q[j * row_step];
+                p2[j] += q[j * row_step + slot];
+            }
+            q += kCombineUnroll * row_step;
         }
+        for (; g < groups; g += kCombineWays, q += row_step) {
+            p1[0] += q[0];
+            p2[0] += q[slot];
+        }
+        static_assert(kCombineUnroll == 8, "fixed-order sum of eight");
+        r1 = ((p1[0] + p1[1]) + (p1[2] + p1[3])) + ((p1[4] + p1[5]) + (p1[6] + p1[7]));
+        r2 = ((p2[0] + p2[1]) + (p2[2] + p2[3])) + ((p2[4] + p2[5]) + (p2[6] + p2[7]));
     }
     __syncthreads();                           // the previous tile's sums have been read
     red[0][way][lane] = r1;
