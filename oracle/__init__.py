@@ -23,6 +23,11 @@ Modules, in the order of the method:
 * ``kirkwood``    -- Kirkwood's analytic sphere solutions (closed form and series), the
   error norm eqerror and the order eqeorder (Section 3.1).
 * ``solve``       -- the whole pipeline of the parallel pseudocode table, run serially.
+* ``lobi``        -- the lower-order scheme: flat triangles, centroid collocation and
+  one-point quadrature (Section 2.4, eqdbef1/eqdbef2).
+* ``field``       -- potential and field at points off the surface from the
+  representation formulas (Section 2.1, eqbim_1/eqbim_2) combined into the kernels of
+  eq. solvation_energy.
 
 Readings taken where the paper is silent or garbled are listed in each function's
 docstring.  The parity of the geometric construction (arc tangents, node normals, the

@@ -77,6 +77,35 @@ def surface_values(points, qpos, q, a, eps1, eps2, kappa, nmax=60):
     return phi, dphi
 
 
+def _kn_ratio(nmax, x, x0):
+    """k_n(x) / k_n(x0), n = 0..nmax, x >= x0 > 0: k_0 = (pi/2) e^-x / x and k_n = k_0 / prod_m R_m
+    with R_m = k_{m-1} / k_m from the recurrence of log_derivative_kn."""
+    def ratios(z):
+        R = np.empty(nmax + 1)
+        R[0] = 1.0
+        for k in range(1, nmax + 1):
+            R[k] = 1.0 / (R[k - 1] + (2 * k - 1) / z)
+        return R
+    out = (x0 / x) * np.exp(-(x - x0)) * np.cumprod(ratios(x0) / ratios(x))
+    return out
+
+
+def exterior_potential(points, qpos, q, a, eps1, eps2, kappa, nmax=60):
+    """Exact phi_2 (internal units) at points with |x| >= a: the surface series of
+    surface_values continued outwards by k_n(kappa r) / k_n(kappa a), or (a / r)^(n+1)
+    when kappa = 0 (the decaying solutions of the screened and plain Laplace equations)."""
+    n, rho, D, f = _coeffs(nmax, a, eps1, eps2, kappa)
+    rp, rq, cosg = _cos_and_radius(points, qpos)
+    P = _legendre(nmax, cosg)                        # [n, npts, nq]
+    radial = (rq[None, :] ** n[:, None]) / a ** (n[:, None] + 1)
+    S = np.einsum("nk,npk,k->np", radial, P, q)       # [n, npts]
+    if kappa == 0.0:
+        g = (a / rp[None, :]) ** (n[:, None] + 1)
+    else:
+        g = np.stack([_kn_ratio(nmax, kappa * r, kappa * a) for r in rp], axis=1)
+    return np.einsum("n,np,np->p", (2 * n + 1) / D, S, g) / FOUR_PI
+
+
 def reaction_potential(points, qpos, q, a, eps1, eps2, kappa, nmax=60):
     """Exact phi_reac (internal units) at interior points."""
     n, rho, D, f = _coeffs(nmax, a, eps1, eps2, kappa)
