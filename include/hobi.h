@@ -164,6 +164,34 @@ hobi_status hobi_matvec(hobi_problem pb, const double* u, double* y, int32_t on_
 hobi_status hobi_energy(hobi_problem pb, const double* u, int32_t on_device,
                         double* e_sol);
 
+/* ---- potential and field at points off the surface (Section 2.1: the representation
+ * formulas eqbim_1 in the solute and eqbim_2 in the solvent, combined with the jump
+ * conditions into the kernels of eq. solvation_energy).  With the reaction potential
+ *     R(x) = integral over the surface of K1 dphi/dnu + K2 phi
+ * (the quadrature of the energy: the 4-point rule on every triangle, or the centroid rule
+ * of the lower-order method) and S1(x) = sum_k q_k G0(x, x_k) / eps1:
+ *     x inside the surface:   phi(x) = S1(x) + R(x)
+ *     x outside (solvent):    phi(x) = (S1(x) + R(x)) / eps,      E = -grad phi.
+ * The side is read from the double layer of a unit density (solid-angle fraction of the
+ * surface seen from x, 1 inside and 0 outside): inside when it exceeds 1/2.  A charge
+ * within 1e-6 A of a point is left out of that point's S1 (so q_k times reac_field at x_k
+ * is the solvation force on charge k).
+ * u: [2 nv] internal units (as for hobi_energy), host or device per on_device.
+ * points: [np][3] host, A; np >= 0 (np = 0 is a no-op).
+ * Outputs: host arrays in the points' order, each may be NULL:
+ *   phi [np] total potential, kcal/(mol e);   field [np][3] E, kcal/(mol e A);
+ *   reac [np] R;   reac_field [np][3] -grad R;   inside [np] 1 inside, 0 outside.
+ * The pair sums run in the problem's precision (mixed: FP32 pairs, FP64 accumulation).
+ * There is no near-singular treatment: within about one edge length of the surface the
+ * rule's error grows, and a point on the surface is not a valid argument.
+ * Synchronous: returns when the outputs are written.  The work space it allocates on the
+ * first call (and on larger calls) stays with the problem until destroy.
+ * Errors: HOBI_E_ARG (NULL u, NULL points with np > 0, np < 0, too many points),
+ * HOBI_E_NUMERIC (non-finite point), HOBI_E_OOM, HOBI_E_HIP. */
+hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int32_t np,
+                       const double* points, double* phi, double* field, double* reac,
+                       double* reac_field, int32_t* inside);
+
 /* ---- inspection of the setup (for verification), caller's vertex/triangle order ---
  * y, ny: [nf][4][3] regular quadrature nodes and unit normals; w: [nf][4] weight times
  * Jacobian (Section 2.2); lower-order method: [nf][3], [nf][3], [nf] (centroid, face

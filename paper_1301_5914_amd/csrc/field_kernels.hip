@@ -1,0 +1,337 @@
+// Potential and field at points off the surface (Section 2.1: the representation formulas
+// eqbim_1 and eqbim_2 combined with the jump conditions into the kernels of eq.
+// solvation_energy).  With the surface strengths Gamma = w dphi/(4 pi), Phi = w phi/(4 pi)
+// at the quadrature nodes (written by the gather, as for the matrix-vector product):
+//
+//   R(x)      = sum_y K1 Gamma + K2 Phi                                  (reaction potential)
+//   grad R(x) = sum_y [(pa + pb f1) n_y - (f1 Gamma + (3 pa + pb f2) q) d] / r^3
+//   Omega(x)  = -sum_y w (d.n_y) / (4 pi r^3)                        (solid-angle fraction)
+//
+// with d = x - y, q = (d.n_y)/r^2, pa = (eps - 1) Phi, pb = -eps Phi (the gradient of
+// K1 = G0 - Gk and of K2 = eps dGk/dnu_y - dG0/dnu_y with the f-functions of the matvec).
+// Then x is inside when Omega > 1/2, and
+//   inside:   phi = S1 + R,          outside: phi = (S1 + R) / eps,     E = -grad phi,
+// S1 = sum_k q_k G0(x, x_k) / eps1 (a charge within kCoincident of x left out).
+//
+// Layout as the pair sum: one wave per (slot of points, node group) of a pair plan, each
+// writing a row of five partial sums per point (R, grad R, Omega); field_combine_kernel
+// adds a point's rows in a fixed order, then the Coulomb part in FP64.
+#include "hobi_internal.h"
+#include "pair_tile.h"
+
+namespace hobi {
+
+namespace {
+
+constexpr int kBlock = kPairBlock;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kParts = 5;                 // R, dR/dx, dR/dy, dR/dz, Omega
+constexpr double kCoincident = 1e-6;      // A
+
+__device__ __forceinline__ int xcd_logical_block() {
+    const int nb = gridDim.x, p = blockIdx.x;
+    const int x = p & 7, q = nb >> 3, rm = nb & 7;
+    return x * q + min(x, rm) + (p >> 3);
+}
+
+// FP32 sums over nodes [sb, se) for the lane's TPL points (positions in the scaled frame of
+// the FP32 records; the gradient comes out in scaled units, times 1/s32).
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void field_f32_run(const const_as<NodeF>* cnodes, int sb, int se,
+                                              const float (&tx)[TPL], const float (&ty)[TPL],
+                                              const float (&tz)[TPL], float (&a)[kParts][TPL]) {
+    constexpr float kLn2 = 0.693147180559945309f;
+    NodeF n = load_node(cnodes, sb);
+    for (int s = sb; s < se; ++s) {
+        const NodeF next = load_node(cnodes, min(s + 1, se - 1));
+        const float pa3 = 3.0f * n.pa;
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+            const float dx = tx[k] - n.x, dy = ty[k] - n.y, dz = tz[k] - n.z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const float rinv = __builtin_amdgcn_rsqf(r2);
+            const float rinv2 = rinv * rinv;
+            const float rinv3 = rinv2 * rinv;
+            const float dny = fmaf(dx, n.nx, fmaf(dy, n.ny, dz * n.nz));
+            const float q = dny * rinv2;
+            float c1, c2;
+            if (KAPPA0) {
+                a[0][k] = fmaf(dny * rinv3, n.pa, a[0][k]);
+                c2 = n.pa;
+                c1 = pa3 * q;
+            } else {
+                const float r = r2 * rinv;
+                const float e = __builtin_amdgcn_exp2f(-r);               // exp(-kappa r)
+                const float zp1 = fmaf(r, kLn2, 1.0f);                   // 1 + z
+                const float f1 = fmaf(-e, zp1, 1.0f);
+                const float f2 = fmaf(-e, fmaf(zp1, zp1 + 1.0f, 1.0f), 3.0f);
+                c2 = fmaf(n.pb, f1, n.pa);                               // pa + pb f1
+                a[0][k] = fmaf(rinv, fmaf(q, c2, fmaf(-e, n.g, n.g)), a[0][k]);
+                c1 = fmaf(f1, n.g, fmaf(n.pb, f2, pa3) * q);             // f1 Gamma + (3 pa + pb f2) q
+            }
+            const float gn = rinv3 * c2, gd = -rinv3 * c1;
+            a[1][k] = fmaf(gn, n.nx, fmaf(gd, dx, a[1][k]));
+            a[2][k] = fmaf(gn, n.ny, fmaf(gd, dy, a[2][k]));
+            a[3][k] = fmaf(gn, n.nz, fmaf(gd, dz, a[3][k]));
+            a[4][k] = fmaf(n.pad, dny * rinv3, a[4][k]);
+        }
+        n = next;
+    }
+}
+
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void field_f32_wave(const float* __restrict__ pts, int np_pad,
+                                               const NodeF* __restrict__ nodes, int base, int n0, int n1,
+                                               double* __restrict__ prow, int slot) {
+    const int lane = (int)(threadIdx.x % kWave);
+    float tx[TPL], ty[TPL], tz[TPL];
+    double acc[kParts][TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+        const int t = base + lane + k * kWave;
+        tx[k] = pts[t];
+        ty[k] = pts[(size_t)np_pad + t];
+        tz[k] = pts[2 * (size_t)np_pad + t];
+#pragma unroll
+        for (int c = 0; c < kParts; ++c) acc[c][k] = 0.0;
+    }
+    const const_as<NodeF>* cnodes = as_constant(nodes);
+    for (int sb = n0, se; sb < n1; sb = se) {
+        se = min((sb / kFold + 1) * kFold, n1);
+        float a[kParts][TPL];
+#pragma unroll
+        for (int c = 0; c < kParts; ++c)
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) a[c][k] = 0.0f;
+        field_f32_run<TPL, KAPPA0>(cnodes, sb, se, tx, ty, tz, a);
+#pragma unroll
+        for (int c = 0; c < kParts; ++c)
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) acc[c][k] += (double)a[c][k];
+    }
+#pragma unroll
+    for (int c = 0; c < kParts; ++c)
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) prow[(size_t)c * slot + lane + k * kWave] = acc[c][k];
+}
+
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void field_f32_narrow(int live, const float* __restrict__ pts, int np_pad,
+                                                 const NodeF* __restrict__ nodes, int base, int n0, int n1,
+                                                 double* __restrict__ prow, int slot) {
+    if constexpr (TPL > 1) {
+        if (live <= kWave * TPL / 2) {
+            field_f32_narrow<TPL / 2, KAPPA0>(live, pts, np_pad, nodes, base, n0, n1, prow, slot);
+            return;
+        }
+    }
+    field_f32_wave<TPL, KAPPA0>(pts, np_pad, nodes, base, n0, n1, prow, slot);
+}
+
+template <int TPL, bool KAPPA0>
+__global__ __launch_bounds__(kBlock) void field_f32_kernel(const float* __restrict__ pts, int np, int np_pad,
+                                                           const NodeF* __restrict__ nodes,
+                                                           const int* __restrict__ gstart, int slots, int workers,
+                                                           double* __restrict__ partial) {
+    const int w = xcd_logical_block() * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    if (w >= workers) return;
+    constexpr int kSlot = kWave * TPL;
+    const int g = w / slots, s = w - g * slots;
+    const const_as<int>* cg = as_constant(gstart);
+    const int base = s * kSlot;
+    field_f32_narrow<TPL, KAPPA0>(np - base, pts, np_pad, nodes, base, cg[g], cg[g + 1],
+                                  partial + (size_t)w * (kParts * kSlot), kSlot);
+}
+
+// FP64 sums (unscaled frame), the FP64 pair kernel's f-functions.
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void field_f64_wave(const double* __restrict__ pts, int np_pad,
+                                               const NodeD* __restrict__ nodes, double kappa, int base, int n0,
+                                               int n1, double* __restrict__ prow, int slot) {
+    const int lane = (int)(threadIdx.x % kWave);
+    double tx[TPL], ty[TPL], tz[TPL], a[kParts][TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+        const int t = base + lane + k * kWave;
+        tx[k] = pts[t];
+        ty[k] = pts[(size_t)np_pad + t];
+        tz[k] = pts[2 * (size_t)np_pad + t];
+#pragma unroll
+        for (int c = 0; c < kParts; ++c) a[c][k] = 0.0;
+    }
+    const const_as<NodeD>* cnodes = as_constant(nodes);
+    for (int s = n0; s < n1; ++s) {
+        const NodeD nd = load_node(cnodes, s);
+        const double pa3 = 3.0 * nd.pa;
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+            const double dx = tx[k] - nd.x, dy = ty[k] - nd.y, dz = tz[k] - nd.z;
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            const double rinv = rsqrt_f64(r2);
+            const double rinv2 = rinv * rinv;
+            const double rinv3 = rinv2 * rinv;
+            const double dny = fma(dx, nd.nx, fma(dy, nd.ny, dz * nd.nz));
+            const double q = dny * rinv2;
+            double c1, c2;
+            if (KAPPA0) {
+                a[0][k] = fma(dny * rinv3, nd.pa, a[0][k]);
+                c2 = nd.pa;
+                c1 = pa3 * q;
+            } else {
+                double f0, f1, f2;
+                f012_pair_f64(kappa * (r2 * rinv), f0, f1, f2);
+                c2 = fma(nd.pb, f1, nd.pa);
+                a[0][k] = fma(rinv, fma(q, c2, nd.g * f0), a[0][k]);
+                c1 = fma(f1, nd.g, fma(nd.pb, f2, pa3) * q);
+            }
+            const double gn = rinv3 * c2, gd = -rinv3 * c1;
+            a[1][k] = fma(gn, nd.nx, fma(gd, dx, a[1][k]));
+            a[2][k] = fma(gn, nd.ny, fma(gd, dy, a[2][k]));
+            a[3][k] = fma(gn, nd.nz, fma(gd, dz, a[3][k]));
+            a[4][k] = fma(nd.pad, dny * rinv3, a[4][k]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kParts; ++c)
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) prow[(size_t)c * slot + lane + k * kWave] = a[c][k];
+}
+
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void field_f64_narrow(int live, const double* __restrict__ pts, int np_pad,
+                                                 const NodeD* __restrict__ nodes, double kappa, int base, int n0,
+                                                 int n1, double* __restrict__ prow, int slot) {
+    if constexpr (TPL > 1) {
+        if (live <= kWave * TPL / 2) {
+            field_f64_narrow<TPL / 2, KAPPA0>(live, pts, np_pad, nodes, kappa, base, n0, n1, prow, slot);
+            return;
+        }
+    }
+    field_f64_wave<TPL, KAPPA0>(pts, np_pad, nodes, kappa, base, n0, n1, prow, slot);
+}
+
+template <int TPL, bool KAPPA0>
+__global__ __launch_bounds__(kBlock) void field_f64_kernel(const double* __restrict__ pts, int np, int np_pad,
+                                                           const NodeD* __restrict__ nodes, double kappa,
+                                                           const int* __restrict__ gstart, int slots, int workers,
+                                                           double* __restrict__ partial) {
+    const int w = xcd_logical_block() * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    if (w >= workers) return;
+    constexpr int kSlot = kWave * TPL;
+    const int g = w / slots, s = w - g * slots;
+    const const_as<int>* cg = as_constant(gstart);
+    const int base = s * kSlot;
+    field_f64_narrow<TPL, KAPPA0>(np - base, pts, np_pad, nodes, kappa, base, cg[g], cg[g + 1],
+                                  partial + (size_t)w * (kParts * kSlot), kSlot);
+}
+
+// One thread per point: the point's rows in group order (four running sums per part, added
+// in a fixed order), the frame scale of the gradient, the Coulomb part of the charges, the
+// side and the outputs in kcal/(mol e) [A^-1]: out[p] = {phi, Ex, Ey, Ez, R, -dR/dx,
+// -dR/dy, -dR/dz, Omega}, inside[p].
+__global__ __launch_bounds__(256) void field_combine_kernel(const double* __restrict__ partial, int np,
+                                                            int slot, int slots, int groups, double gscale,
+                                                            const double* __restrict__ pts, int np_pad,
+                                                            const double* __restrict__ qpos,
+                                                            const double* __restrict__ q, int nc, double eps1,
+                                                            double eps, double* __restrict__ out,
+                                                            int* __restrict__ inside) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int s = p / slot, o = p - s * slot;
+    double acc[kParts][4];
+#pragma unroll
+    for (int c = 0; c < kParts; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[c][j] = 0.0;
+    const size_t row_step = (size_t)slots * kParts * slot;   // next group, same slot
+    const double* col = partial + (size_t)s * kParts * slot + o;
+    int g = 0;
+    for (; g + 3 < groups; g += 4, col += 4 * row_step) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int c = 0; c < kParts; ++c) acc[c][j] += col[j * row_step + (size_t)c * slot];
+    }
+    for (; g < groups; ++g, col += row_step) {
+#pragma unroll
+        for (int c = 0; c < kParts; ++c) acc[c][0] += col[(size_t)c * slot];
+    }
+    double v[kParts];
+#pragma unroll
+    for (int c = 0; c < kParts; ++c) v[c] = (acc[c][0] + acc[c][1]) + (acc[c][2] + acc[c][3]);
+    const double R = v[0], gx = v[1] * gscale, gy = v[2] * gscale, gz = v[3] * gscale, om = v[4];
+    const double x = pts[p], y = pts[(size_t)np_pad + p], z = pts[2 * (size_t)np_pad + p];
+    double S = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int k = 0; k < nc; ++k) {
+        const double dx = x - qpos[3 * k], dy = y - qpos[3 * k + 1], dz = z - qpos[3 * k + 2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < kCoincident * kCoincident) continue;
+        const double rinv = 1.0 / sqrt(r2);
+        const double t = q[k] * rinv;
+        S += t;
+        const double t3 = t * rinv * rinv;
+        sx -= t3 * dx;
+        sy -= t3 * dy;
+        sz -= t3 * dz;
+    }
+    const double cs = kInv4Pi / eps1;
+    S *= cs, sx *= cs, sy *= cs, sz *= cs;
+    const bool in = om > 0.5;
+    const double side = in ? 1.0 : 1.0 / eps;
+    constexpr double kUnit = 4.0 * kPi * 332.0716;            // internal -> kcal/(mol e)
+    double* o9 = out + (size_t)9 * p;
+    o9[0] = kUnit * side * (S + R);
+    o9[1] = -kUnit * side * (sx + gx);
+    o9[2] = -kUnit * side * (sy + gy);
+    o9[3] = -kUnit * side * (sz + gz);
+    o9[4] = kUnit * R;
+    o9[5] = -kUnit * gx;
+    o9[6] = -kUnit * gy;
+    o9[7] = -kUnit * gz;
+    o9[8] = om;
+    inside[p] = in ? 1 : 0;
+}
+
+inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+int field_resident_waves(int device, bool mixed) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    const hipError_t e =
+        mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, field_f32_kernel<kFieldTpl32, false>, kBlock, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, field_f64_kernel<kFieldTpl64, false>, kBlock, 0);
+    if (e != hipSuccess || per_cu < 1) return 0;
+    return cus * per_cu * kWavesPerBlock;
+}
+
+hipError_t launch_field(const DeviceProblem& p, const FieldWork& f, const PairPlan& pl, bool mixed,
+                        hipStream_t s) {
+    const bool k0 = p.kappa == 0.0;
+    if (mixed) {
+        if (k0)
+            hipLaunchKernelGGL((field_f32_kernel<kFieldTpl32, true>), dim3(pl.blocks), dim3(kBlock), 0, s, f.pts32,
+                               f.np, f.np_pad, p.node32, pl.gstart, pl.slots, pl.workers, f.partial);
+        else
+            hipLaunchKernelGGL((field_f32_kernel<kFieldTpl32, false>), dim3(pl.blocks), dim3(kBlock), 0, s, f.pts32,
+                               f.np, f.np_pad, p.node32, pl.gstart, pl.slots, pl.workers, f.partial);
+    } else {
+        if (k0)
+            hipLaunchKernelGGL((field_f64_kernel<kFieldTpl64, true>), dim3(pl.blocks), dim3(kBlock), 0, s, f.pts64,
+                               f.np, f.np_pad, p.node64, p.kappa, pl.gstart, pl.slots, pl.workers, f.partial);
+        else
+            hipLaunchKernelGGL((field_f64_kernel<kFieldTpl64, false>), dim3(pl.blocks), dim3(kBlock), 0, s, f.pts64,
+                               f.np, f.np_pad, p.node64, p.kappa, pl.gstart, pl.slots, pl.workers, f.partial);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const double gscale = mixed ? p.s32 : 1.0;
+    hipLaunchKernelGGL(field_combine_kernel, dim3(nblk(f.np, 256)), dim3(256), 0, s, f.partial, f.np, pl.slot,
+                       pl.slots, pl.groups, gscale, f.pts64, f.np_pad, p.qpos, p.q, p.nc, p.eps1, p.eps, f.out,
+                       f.inside);
+    return hipGetLastError();
+}
+
+}  // namespace hobi

@@ -46,6 +46,19 @@ hipError_t dalloc(T** p, size_t n) {
     return hipMalloc((void**)p, (n ? n : 1) * sizeof(T));
 }
 
+// Grows a device buffer to hold at least n elements (contents are not kept).
+template <class T>
+hipError_t grow(T** p, size_t* cap, size_t n) {
+    if (*p && *cap >= n) return hipSuccess;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    const size_t m = std::max<size_t>(n, 1);
+    const hipError_t e = hipMalloc((void**)p, m * sizeof(T));
+    if (e == hipSuccess) *cap = m;
+    return e;
+}
+
 uint64_t spread3(uint64_t v) {   // 21 bits -> every third bit
     v &= 0x1fffff;
     v = (v | v << 32) & 0x1f00000000ffffULL;
@@ -304,6 +317,13 @@ void free_problem(hobi_problem pb) {
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     free_krylov(pb->kr);
+    {
+        FieldWork& f = pb->field;
+        void* fp[] = {f.pts64, f.pts32, f.partial, f.gstart, f.out, f.inside};
+        for (void* p : fp)
+            if (p) (void)hipFree(p);
+        f = FieldWork{};
+    }
     if (pb->host_pinned) (void)hipHostFree(pb->host_pinned);
     for (const Timer& t : pb->pending) {
         (void)hipEventDestroy(t.a);
@@ -764,6 +784,88 @@ hobi_status hobi_energy(hobi_problem pb, const double* u, int32_t on_device, dou
     HIPCHK(pb->ctx, launch_gather(pb->d, pb->u_in, false, s));
     HIPCHK(pb->ctx, launch_reaction_energy(pb->d, pb->phi_reac, pb->e_dev, s));
     return read_scalar(pb, pb->e_dev, e_sol);
+}
+
+hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int32_t np, const double* points,
+                       double* phi, double* field, double* reac, double* reac_field, int32_t* inside) {
+    if (!pb) return HOBI_E_ARG;
+    hobi_ctx c = pb->ctx;
+    if (!u) return fail(c, HOBI_E_ARG, "NULL u");
+    if (np < 0) return fail(c, HOBI_E_ARG, "np < 0");
+    if (np == 0) return HOBI_OK;
+    if (!points) return fail(c, HOBI_E_ARG, "NULL points");
+    for (size_t i = 0; i < 3 * (size_t)np; ++i)
+        if (!std::isfinite(points[i])) return fail(c, HOBI_E_NUMERIC, "non-finite point");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    DeviceProblem& d = pb->d;
+    const bool mixed = pb->prm.precision == HOBI_MIXED;
+    // node strengths of u
+    hobi_status st = to_internal(pb, u, on_device, pb->u_in);
+    if (st != HOBI_OK) return st;
+    HIPCHK(c, launch_gather(d, pb->u_in, mixed, s));
+    // the split over waves, points in Morton order
+    const int res = field_resident_waves(c->device, mixed);
+    if (res < 1) return fail(c, HOBI_E_HIP, "field kernel occupancy query failed");
+    PairPlan pl{};
+    std::vector<int> gs;
+    if (!make_pair_plan(np, d.nn, mixed ? kFieldTpl32 : kFieldTpl64, res, &pl, &gs))
+        return fail(c, HOBI_E_ARG, "too many points: %d", np);
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int i = 0; i < np; ++i)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], points[3 * i + k]);
+            hi[k] = std::max(hi[k], points[3 * i + k]);
+        }
+    const std::vector<double> pv(points, points + 3 * (size_t)np);
+    const std::vector<int> order = morton_order(pv, np, lo, hi);   // sorted position -> caller index
+    FieldWork& f = pb->field;
+    f.np = np;
+    f.np_pad = pl.slots * pl.slot;
+    std::vector<double> h64(3 * (size_t)f.np_pad);
+    std::vector<float> h32(3 * (size_t)f.np_pad);
+    for (int j = 0; j < f.np_pad; ++j) {
+        const int src = order[std::min(j, np - 1)];
+        for (int k = 0; k < 3; ++k) {
+            const double x = points[3 * (size_t)src + k];
+            h64[(size_t)k * f.np_pad + j] = x;
+            h32[(size_t)k * f.np_pad + j] = (float)((x - d.center[k]) * d.s32);
+        }
+    }
+    const size_t nparts = (size_t)pl.workers * 5 * pl.slot;
+    hipError_t e = hipSuccess;
+    if ((e = grow(&f.pts64, &f.cap_pts64, h64.size())) != hipSuccess ||
+        (e = grow(&f.pts32, &f.cap_pts32, h32.size())) != hipSuccess ||
+        (e = grow(&f.partial, &f.cap_partial, nparts)) != hipSuccess ||
+        (e = grow(&f.gstart, &f.cap_gstart, gs.size())) != hipSuccess ||
+        (e = grow(&f.out, &f.cap_out, 9 * (size_t)np)) != hipSuccess ||
+        (e = grow(&f.inside, &f.cap_inside, (size_t)np)) != hipSuccess)
+        return fail(c, e == hipErrorOutOfMemory ? HOBI_E_OOM : HOBI_E_HIP, "field work space: %s",
+                    hipGetErrorString(e));
+    HIPCHK(c, hipMemcpyAsync(f.pts64, h64.data(), sizeof(double) * h64.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(f.pts32, h32.data(), sizeof(float) * h32.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(f.gstart, gs.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
+    pl.gstart = f.gstart;
+    HIPCHK(c, launch_field(d, f, pl, mixed, s));
+    std::vector<double> ho(9 * (size_t)np);
+    std::vector<int> hin((size_t)np);
+    HIPCHK(c, hipMemcpyAsync(ho.data(), f.out, sizeof(double) * ho.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(hin.data(), f.inside, sizeof(int) * hin.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int j = 0; j < np; ++j) {
+        const int i = order[j];
+        const double* o = ho.data() + 9 * (size_t)j;
+        if (phi) phi[i] = o[0];
+        if (field)
+            for (int k = 0; k < 3; ++k) field[3 * (size_t)i + k] = o[1 + k];
+        if (reac) reac[i] = o[4];
+        if (reac_field)
+            for (int k = 0; k < 3; ++k) reac_field[3 * (size_t)i + k] = o[5 + k];
+        if (inside) inside[i] = hin[j];
+    }
+    for (size_t i = 0; i < ho.size(); ++i)
+        if (!std::isfinite(ho[i])) return fail(c, HOBI_E_NUMERIC, "non-finite field value (a point on the surface?)");
+    return HOBI_OK;
 }
 
 hobi_status hobi_solve(hobi_problem pb, double* phi, double* dphi, double* e_sol, hobi_stats* stats) {

@@ -15,17 +15,20 @@ namespace hobi {
 // so that K2 Phi = (d.ny)/r^3 (pa + pb f1) and K3 Gamma = (d.nx)/r^3 (ga + gb f1),
 // and the three vertex ids of the node's triangle (its pairs with those vertices belong
 // to the singular rule and are skipped by the dense sum).
+// `pad` holds the node's solid-angle weight -w J / (4 pi) (times s32^2 in the FP32 frame),
+// written by the setup: the double layer of a unit density at a point, which tells the
+// field evaluation on which side of the surface the point lies.
 // One node is one 64-byte record, i.e. one wave-uniform scalar load.
 struct alignas(64) NodeF {
     float x, y, z, nx, ny, nz, g, p;
     float ga, gb, pa, pb;
-    float qx, qy, qz, pad;   // p * (nx, ny, nz)
+    float qx, qy, qz, pad;   // p * (nx, ny, nz), solid-angle weight
 };
 struct alignas(128) NodeD {
     double x, y, z, g;
     double nx, ny, nz, p;
     double ga, gb, pa, pb;   // Gamma, Phi times the epsilon factors of K3, K2
-    double qx, qy, qz, pad;  // Phi * (nx, ny, nz)
+    double qx, qy, qz, pad;  // Phi * (nx, ny, nz), solid-angle weight
 };
 
 constexpr int kCombineVerts = 64;   // vertices per tile of the combine step

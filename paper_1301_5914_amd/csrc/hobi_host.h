@@ -49,6 +49,7 @@ struct hobi_problem_s {
     double* host_pinned = nullptr;   // small pinned buffer for scalar read-backs
     int* d_err = nullptr;            // [nf] per-triangle flags of the curved-edge construction
     hobi::Krylov kr;
+    hobi::FieldWork field;           // potential / field evaluation work space
     std::vector<hobi::Timer> pending;
     std::vector<hipEvent_t> event_pool;
     double ms[hobi::T_NKINDS] = {0, 0, 0, 0};

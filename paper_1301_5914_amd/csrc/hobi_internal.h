@@ -113,6 +113,27 @@ hipError_t launch_reaction_energy(const DeviceProblem& p, double* phi_reac, doub
                                   hipStream_t s);
 // solid-angle fraction seen from each charge (1 inside, 0 outside)
 hipError_t launch_solid_angle(const DeviceProblem& p, double* frac, hipStream_t s);
+
+// ---- potential and field at points off the surface (field_kernels.hip) ----
+constexpr int kFieldTpl32 = 4;   // points per lane of the FP32 field kernel
+constexpr int kFieldTpl64 = 2;   // and of the FP64 one
+// Work space of one field evaluation, kept by the problem and grown on demand.
+struct FieldWork {
+    int np = 0, np_pad = 0;       // points, points padded to whole slots
+    double* pts64 = nullptr;      // [3][np_pad] SoA, Morton order
+    float* pts32 = nullptr;       // [3][np_pad] in the frame of the FP32 node records
+    double* partial = nullptr;    // [workers][5][slot]
+    int* gstart = nullptr;        // [groups + 1]
+    double* out = nullptr;        // [np][9] phi, E, R, -grad R, solid-angle fraction
+    int* inside = nullptr;        // [np]
+    size_t cap_pts64 = 0, cap_pts32 = 0, cap_partial = 0, cap_gstart = 0, cap_out = 0, cap_inside = 0;
+};
+// Waves of the mixed or FP64 field kernel the device holds at once (0 on error).
+int field_resident_waves(int device, bool mixed);
+// Pair sums of the plan's workers, then the per-point combine (strengths of u must be in
+// the node records: launch_gather with the same precision).
+hipError_t launch_field(const DeviceProblem& p, const FieldWork& f, const PairPlan& plan, bool mixed,
+                        hipStream_t s);
 hipError_t launch_permute(const double* in, double* out, const int* perm, int nv, bool to_internal,
                           hipStream_t s);
 

@@ -35,7 +35,7 @@ __device__ __forceinline__ NodeF load_node(const const_as<NodeF>* p, int s) {
     n.x = p[s].x, n.y = p[s].y, n.z = p[s].z;
     n.nx = p[s].nx, n.ny = p[s].ny, n.nz = p[s].nz;
     n.g = p[s].g, n.p = p[s].p, n.ga = p[s].ga, n.gb = p[s].gb, n.pa = p[s].pa, n.pb = p[s].pb;
-    n.qx = p[s].qx, n.qy = p[s].qy, n.qz = p[s].qz, n.pad = 0.0f;
+    n.qx = p[s].qx, n.qy = p[s].qy, n.qz = p[s].qz, n.pad = p[s].pad;
     return n;
 }
 
@@ -68,7 +68,7 @@ __device__ __forceinline__ NodeD load_node(const const_as<NodeD>* p, int s) {
     n.x = p[s].x, n.y = p[s].y, n.z = p[s].z, n.g = p[s].g;
     n.nx = p[s].nx, n.ny = p[s].ny, n.nz = p[s].nz, n.p = p[s].p;
     n.ga = p[s].ga, n.gb = p[s].gb, n.pa = p[s].pa, n.pb = p[s].pb;
-    n.qx = p[s].qx, n.qy = p[s].qy, n.qz = p[s].qz, n.pad = 0.0;
+    n.qx = p[s].qx, n.qy = p[s].qy, n.qz = p[s].qz, n.pad = p[s].pad;
     return n;
 }
 
@@ -269,6 +269,29 @@ __device__ __forceinline__ void gather_site(int j, const double* __restrict__ u,
     write_strengths(j, sc * u[nv + j], sc * u[j], node64, node32, mixed, eps, s32);
 }
 
+// f0 = 1 - e^-z, f1 = 1 - e^-z (1 + z), f2 = 3 - e^-z (3 + 3z + z^2) in FP64: the closed forms
+// with the exponential of hobi_device.h, or their power series where z < kSeriesZ64 (Horner
+// in z, terms k = 1..12 of f0 and k = 2..12 of f1, f2; truncation below 1e-17 relative).
+__device__ __forceinline__ void f012_pair_f64(double z, double& f0, double& f1, double& f2) {
+    const double e = exp_neg_f64(z);
+    f0 = 1.0 - e;
+    f1 = fma(-e, 1.0 + z, 1.0);
+    f2 = fma(-e, fma(z, z + 3.0, 3.0), 3.0);
+    if (z < kSeriesZ64) {
+        constexpr SeriesTable T = series_table();
+        double s0 = T.f0[12], s1 = T.f1[12], s2 = T.f2[12];
+#pragma unroll
+        for (int j = 11; j >= 2; --j) {
+            s0 = fma(s0, z, T.f0[j]);
+            s1 = fma(s1, z, T.f1[j]);
+            s2 = fma(s2, z, T.f2[j]);
+        }
+        f0 = fma(s0, z, T.f0[1]) * z;
+        f1 = s1 * z * z;
+        f2 = s2 * z * z;
+    }
+}
+
 // FP64 pairs of nodes [sb, se) with the lane's TPL targets.  Per pair (kappa > 0) about 62
 // VALU operations: the exponential and reciprocal square root of hobi_device.h, the closed
 // forms of f0, f1, f2, and their power series where kappa r < kSeriesZ64 (rare: only nodes
@@ -301,24 +324,8 @@ __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, cons
             } else {
                 const double pnxy = fma(tnx[k], nd.qx, fma(tny[k], nd.qy, tnz[k] * nd.qz));
                 const double z = kappa * (r2 * rinv);
-                const double e = exp_neg_f64(z);
-                double f0 = 1.0 - e;
-                double f1 = fma(-e, 1.0 + z, 1.0);
-                double f2 = fma(-e, fma(z, z + 3.0, 3.0), 3.0);
-                if (z < kSeriesZ64) {
-                    // Horner in z, terms k = 1..12 (f0) and k = 2..12 (f1, f2); truncation < 1e-17 rel.
-                    constexpr SeriesTable T = series_table();
-                    double s0 = T.f0[12], s1 = T.f1[12], s2 = T.f2[12];
-#pragma unroll
-                    for (int j = 11; j >= 2; --j) {
-                        s0 = fma(s0, z, T.f0[j]);
-                        s1 = fma(s1, z, T.f1[j]);
-                        s2 = fma(s2, z, T.f2[j]);
-                    }
-                    f0 = fma(s0, z, T.f0[1]) * z;
-                    f1 = s1 * z * z;
-                    f2 = s2 * z * z;
-                }
+                double f0, f1, f2;
+                f012_pair_f64(z, f0, f1, f2);
                 // the FP32 tile's row algebra: q = (d.ny)/r^2, P = Phi ny
                 const double q = dny * rinv2;
                 a1[k] = fma(rinv, fma(q, fma(nd.pb, f1, nd.pa), nd.g * f0), a1[k]);

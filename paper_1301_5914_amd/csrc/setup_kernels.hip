@@ -67,6 +67,7 @@ __global__ void regular_kernel(const double* __restrict__ patch, const int* __re
     d.nx = n.x;
     d.ny = n.y;
     d.nz = n.z;
+    d.pad = -wm * J * kInv4Pi;                // solid-angle weight: -w / (4 pi)
     node64[idx] = d;
     NodeF f{};
     f.x = (float)((x.x - cx) * s32);
@@ -75,6 +76,7 @@ __global__ void regular_kernel(const double* __restrict__ patch, const int* __re
     f.nx = (float)n.x;
     f.ny = (float)n.y;
     f.nz = (float)n.z;
+    f.pad = (float)(d.pad * s32 * s32);       // in the FP32 frame
     node32[idx] = f;
     node_vid[idx] = make_int4(tri[3 * j], tri[3 * j + 1], tri[3 * j + 2], 0);
     w[idx] = wm * J;
@@ -98,12 +100,14 @@ __global__ void lobi_nodes_kernel(const double* __restrict__ vxyz, const int* __
     NodeD d{};
     d.x = c.x, d.y = c.y, d.z = c.z;
     d.nx = n.x, d.ny = n.y, d.nz = n.z;
+    d.pad = -0.5 * a2 * kInv4Pi;              // solid-angle weight: -area / (4 pi)
     node64[j] = d;
     NodeF f{};
     f.x = (float)((c.x - cx) * s32);
     f.y = (float)((c.y - cy) * s32);
     f.z = (float)((c.z - cz) * s32);
     f.nx = (float)n.x, f.ny = (float)n.y, f.nz = (float)n.z;
+    f.pad = (float)(d.pad * s32 * s32);
     node32[j] = f;
     node_vid[j] = make_int4(j, j, j, 0);
     w[j] = 0.5 * a2;

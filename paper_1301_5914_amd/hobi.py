@@ -75,6 +75,7 @@ _SIGS = {
     "hobi_solve": (ctypes.c_int, [_P, _D, _D, _D, ctypes.POINTER(hobi_stats)]),
     "hobi_matvec": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "hobi_energy": (ctypes.c_int, [_P, _P, ctypes.c_int32, _D]),
+    "hobi_field": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _D, _D, _D, _D, _D, _I]),
     "hobi_get_nodes": (ctypes.c_int, [_P, _D, _D, _D]),
     "hobi_get_rhs": (ctypes.c_int, [_P, _D]),
     "hobi_reset_stats": (ctypes.c_int, [_P]),
@@ -244,6 +245,26 @@ class Problem:
             u = _f64(u).ravel()
             self._chk(lib().hobi_energy(self.handle, _P(u.ctypes.data), 0, ctypes.byref(e)))
         return e.value
+
+    def field(self, u, points):
+        """Potential and field at points off the surface for the internal-unit solution u
+        (numpy or a device tensor): dict of phi [np], field [np,3], reac [np],
+        reac_field [np,3] (kcal/(mol e) [/A]) and inside [np] (int32)."""
+        pts = _f64(points).reshape(-1, 3)
+        n = pts.shape[0]
+        out = dict(phi=np.empty(n), field=np.empty((n, 3)), reac=np.empty(n), reac_field=np.empty((n, 3)),
+                   inside=np.empty(n, dtype=np.int32))
+        if hasattr(u, "data_ptr"):
+            uptr, dev = _P(u.data_ptr()), 1
+        else:
+            u = _f64(u).ravel()
+            if u.shape[0] != 2 * self.nu:
+                raise ValueError("u must have 2 entries per site")
+            uptr, dev = _P(u.ctypes.data), 0
+        self._chk(lib().hobi_field(self.handle, uptr, dev, n, _dptr(pts), _dptr(out["phi"]), _dptr(out["field"]),
+                                   _dptr(out["reac"]), _dptr(out["reac_field"]),
+                                   out["inside"].ctypes.data_as(_I)))
+        return out
 
     def solve(self, allow_noconv: bool = False):
         phi = np.empty(self.nu)

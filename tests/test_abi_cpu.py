@@ -30,6 +30,7 @@ def test_null_arguments_are_rejected_without_touching_a_device():
                                    ctypes.byref(out)) == 1
     assert lib.hobi_matvec(None, None, None, 0) == 1
     assert lib.hobi_solve(None, None, None, None, None) == 1
+    assert lib.hobi_field(None, None, 0, 0, None, None, None, None, None, None) == 1
     assert lib.hobi_last_error(None) == b"null context"
 
 
