@@ -94,6 +94,46 @@ def cpu_baseline(prob, seconds: float, workers: int, lower: bool = False):
             "sample": f"{nrows} of {n_sites} matvec rows (x {n_nodes} nodes), {dt:.1f} s"}
 
 
+FIELD_FLOPS_PER_PAIR = {True: 60, False: 41}   # R, grad R and the solid angle per (point, node)
+
+
+def field_bench(pb, prob, grid, res, mixed, n_nodes):
+    """Potential map: hobi_field on a grid^3 lattice over the surface's bounding box grown by
+    30% (points inside and outside), for the solved surface of the last timed step."""
+    from paper_1301_5914_amd import hobi
+    unit = 4.0 * np.pi * 332.0716
+    u = np.concatenate([res["phi"], res["dphi"]]) / unit
+    lo, hi = prob.xyz.min(axis=0), prob.xyz.max(axis=0)
+    c, h = 0.5 * (lo + hi), 0.65 * (hi - lo)
+    axes = [np.linspace(c[k] - h[k], c[k] + h[k], grid) for k in range(3)]
+    pts = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+    pb.field(u, pts[:1024])                       # work space and code warm-up
+    times, kern = [], []
+    out = None
+    for _ in range(3):
+        pb.reset_stats()
+        t0 = time.perf_counter()
+        out = pb.field(u, pts)
+        times.append((time.perf_counter() - t0) * 1e3)
+        st = pb.stats()
+        kern.append(st["ms_field_kernel"] / max(1, st["field_launches"]))
+    k_ms = float(np.median(kern))
+    pairs = pts.shape[0] * n_nodes
+    flops = FIELD_FLOPS_PER_PAIR[prob.kappa > 0]
+    achieved = flops * pairs / (k_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS["mixed" if mixed else "fp64"]
+    # end-to-end cross-check: the energy from the reaction potential at the charges
+    at_q = pb.field(u, prob.qpos)
+    e_field = 0.5 * float(np.sum(prob.q * at_q["reac"]))
+    return {"grid": grid, "points": int(pts.shape[0]), "pairs": int(pairs),
+            "kernel_ms": k_ms, "kernel_gpairs_per_s": pairs / (k_ms * 1e-3) / 1e9,
+            "call_ms_median": float(np.median(times)),
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                         "frac": achieved / peak, "flops_per_pair": flops},
+            "inside_fraction": float(np.mean(out["inside"])),
+            "energy_from_field_rel": abs(e_field / res["energy"] - 1)}
+
+
 def _make_molecule(n_atoms, seed):
     from paper_1301_5914_amd import inputs
     return inputs.molecule(int(n_atoms), seed=int(seed))
@@ -230,6 +270,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=0.7, help="arrival rate / saturated throughput")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--field-map", type=int, default=64,
+                    help="potential map of grid^3 points after the timed steps (hobi_field); 0 = off")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -339,6 +381,8 @@ def main():
             mv_ms.append(ev0.elapsed_time(ev1))
     out["matvec_ms_median"] = float(np.median(mv_ms))
     out["matvec_gpairs_per_s"] = pairs_mv / (out["matvec_ms_median"] * 1e-3) / 1e9
+    if args.field_map > 0:
+        out["field"] = field_bench(pb, prob, args.field_map, results[-1], mixed, n_nodes)
     if not args.no_compare:
         # the other precision on the same problem (outside the timed region)
         pb.set_precision(hobi.HOBI_FP64 if mixed else hobi.HOBI_MIXED)

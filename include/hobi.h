@@ -96,6 +96,8 @@ typedef struct hobi_stats {
     double ms_pair_kernel;
     int64_t pair_launches;
     double ms_gather, ms_combine, ms_krylov;
+    double ms_field_kernel;    /* pair sums of hobi_field (R, its gradient, solid angle)     */
+    int64_t field_launches;
 } hobi_stats;
 
 /* Fills p with the defaults listed in hobi_params. */

@@ -225,41 +225,51 @@ __global__ __launch_bounds__(kBlock) void field_f64_kernel(const double* __restr
                                   partial + (size_t)w * (kParts * kSlot), kSlot);
 }
 
-// One thread per point: the point's rows in group order (four running sums per part, added
-// in a fixed order), the frame scale of the gradient, the Coulomb part of the charges, the
-// side and the outputs in kcal/(mol e) [A^-1]: out[p] = {phi, Ex, Ey, Ez, R, -dR/dx,
-// -dR/dy, -dR/dz, Omega}, inside[p].
-__global__ __launch_bounds__(256) void field_combine_kernel(const double* __restrict__ partial, int np,
-                                                            int slot, int slots, int groups, double gscale,
-                                                            const double* __restrict__ pts, int np_pad,
-                                                            const double* __restrict__ qpos,
-                                                            const double* __restrict__ q, int nc, double eps1,
-                                                            double eps, double* __restrict__ out,
-                                                            int* __restrict__ inside) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    const int s = p / slot, o = p - s * slot;
-    double acc[kParts][4];
-#pragma unroll
-    for (int c = 0; c < kParts; ++c)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[c][j] = 0.0;
-    const size_t row_step = (size_t)slots * kParts * slot;   // next group, same slot
-    const double* col = partial + (size_t)s * kParts * slot + o;
-    int g = 0;
-    for (; g + 3 < groups; g += 4, col += 4 * row_step) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int c = 0; c < kParts; ++c) acc[c][j] += col[j * row_step + (size_t)c * slot];
-    }
-    for (; g < groups; ++g, col += row_step) {
-#pragma unroll
-        for (int c = 0; c < kParts; ++c) acc[c][0] += col[(size_t)c * slot];
-    }
+// 64 points per block of 256 threads: wave k sums the point's rows of node groups k, k + 4,
+// ... into two running sums by turn (fixed order), the four waves' sums are added in a
+// fixed order through LDS; then the frame scale of the gradient, the Coulomb part of the
+// charges, the side and the outputs in kcal/(mol e) [A^-1]: out[p] = {phi, Ex, Ey, Ez, R,
+// -dR/dx, -dR/dy, -dR/dz, Omega}, inside[p].
+constexpr int kCombPts = 64, kCombWays = 4;
+
+__global__ __launch_bounds__(kCombPts * kCombWays) void field_combine_kernel(
+    const double* __restrict__ partial, int np, int slot, int slots, int groups, double gscale,
+    const double* __restrict__ pts, int np_pad, const double* __restrict__ qpos, const double* __restrict__ q,
+    int nc, double eps1, double eps, double* __restrict__ out, int* __restrict__ inside) {
+    __shared__ double red[kCombWays][kParts][kCombPts];
+    const int lane = threadIdx.x % kCombPts, way = threadIdx.x / kCombPts;
+    const int p = blockIdx.x * kCombPts + lane;
     double v[kParts];
 #pragma unroll
-    for (int c = 0; c < kParts; ++c) v[c] = (acc[c][0] + acc[c][1]) + (acc[c][2] + acc[c][3]);
+    for (int c = 0; c < kParts; ++c) v[c] = 0.0;
+    if (p < np) {
+        const int s = p / slot, o = p - s * slot;
+        const size_t row_step = (size_t)slots * kParts * slot;   // next group, same slot
+        const double* col = partial + ((size_t)way * slots + s) * kParts * slot + o;
+        double a0[kParts], a1[kParts];
+#pragma unroll
+        for (int c = 0; c < kParts; ++c) a0[c] = a1[c] = 0.0;
+        int g = way;
+        for (; g + kCombWays < groups; g += 2 * kCombWays, col += 2 * kCombWays * row_step) {
+#pragma unroll
+            for (int c = 0; c < kParts; ++c) {
+                a0[c] += col[(size_t)c * slot];
+                a1[c] += col[kCombWays * row_step + (size_t)c * slot];
+            }
+        }
+        if (g < groups) {
+#pragma unroll
+            for (int c = 0; c < kParts; ++c) a0[c] += col[(size_t)c * slot];
+        }
+#pragma unroll
+        for (int c = 0; c < kParts; ++c) v[c] = a0[c] + a1[c];
+    }
+#pragma unroll
+    for (int c = 0; c < kParts; ++c) red[way][c][lane] = v[c];
+    __syncthreads();
+    if (way != 0 || p >= np) return;
+#pragma unroll
+    for (int c = 0; c < kParts; ++c) v[c] = (red[0][c][lane] + red[1][c][lane]) + (red[2][c][lane] + red[3][c][lane]);
     const double R = v[0], gx = v[1] * gscale, gy = v[2] * gscale, gz = v[3] * gscale, om = v[4];
     const double x = pts[p], y = pts[(size_t)np_pad + p], z = pts[2 * (size_t)np_pad + p];
     double S = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
@@ -307,8 +317,8 @@ int field_resident_waves(int device, bool mixed) {
     return cus * per_cu * kWavesPerBlock;
 }
 
-hipError_t launch_field(const DeviceProblem& p, const FieldWork& f, const PairPlan& pl, bool mixed,
-                        hipStream_t s) {
+hipError_t launch_field_pairs(const DeviceProblem& p, const FieldWork& f, const PairPlan& pl, bool mixed,
+                              hipStream_t s) {
     const bool k0 = p.kappa == 0.0;
     if (mixed) {
         if (k0)
@@ -325,12 +335,15 @@ hipError_t launch_field(const DeviceProblem& p, const FieldWork& f, const PairPl
             hipLaunchKernelGGL((field_f64_kernel<kFieldTpl64, false>), dim3(pl.blocks), dim3(kBlock), 0, s, f.pts64,
                                f.np, f.np_pad, p.node64, p.kappa, pl.gstart, pl.slots, pl.workers, f.partial);
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_field_combine(const DeviceProblem& p, const FieldWork& f, const PairPlan& pl, bool mixed,
+                                hipStream_t s) {
     const double gscale = mixed ? p.s32 : 1.0;
-    hipLaunchKernelGGL(field_combine_kernel, dim3(nblk(f.np, 256)), dim3(256), 0, s, f.partial, f.np, pl.slot,
-                       pl.slots, pl.groups, gscale, f.pts64, f.np_pad, p.qpos, p.q, p.nc, p.eps1, p.eps, f.out,
-                       f.inside);
+    hipLaunchKernelGGL(field_combine_kernel, dim3(nblk(f.np, kCombPts)), dim3(kCombPts * kCombWays), 0, s,
+                       f.partial, f.np, pl.slot, pl.slots, pl.groups, gscale, f.pts64, f.np_pad, p.qpos, p.q,
+                       p.nc, p.eps1, p.eps, f.out, f.inside);
     return hipGetLastError();
 }
 

@@ -846,7 +846,11 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
     HIPCHK(c, hipMemcpyAsync(f.pts32, h32.data(), sizeof(float) * h32.size(), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(f.gstart, gs.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
     pl.gstart = f.gstart;
-    HIPCHK(c, launch_field(d, f, pl, mixed, s));
+    {
+        ScopedTimer t(pb, T_FIELD);
+        HIPCHK(c, launch_field_pairs(d, f, pl, mixed, s));
+    }
+    HIPCHK(c, launch_field_combine(d, f, pl, mixed, s));
     std::vector<double> ho(9 * (size_t)np);
     std::vector<int> hin((size_t)np);
     HIPCHK(c, hipMemcpyAsync(ho.data(), f.out, sizeof(double) * ho.size(), hipMemcpyDeviceToHost, s));
@@ -925,6 +929,8 @@ hobi_status hobi_solve(hobi_problem pb, double* phi, double* dphi, double* e_sol
     L.ms_gather = pb->ms[T_GATHER];
     L.ms_combine = pb->ms[T_COMBINE];
     L.ms_krylov = pb->ms[T_KRYLOV];
+    L.ms_field_kernel = pb->ms[T_FIELD];
+    L.field_launches = pb->cnt[T_FIELD];
     if (stats) *stats = L;
     for (int i = 0; i < n; ++i)
         if (!std::isfinite(hu[i])) return fail(c, HOBI_E_NUMERIC, "non-finite solution");
@@ -978,6 +984,8 @@ hobi_status hobi_get_stats(hobi_problem pb, hobi_stats* out) {
     pb->last.ms_gather = pb->ms[T_GATHER];
     pb->last.ms_combine = pb->ms[T_COMBINE];
     pb->last.ms_krylov = pb->ms[T_KRYLOV];
+    pb->last.ms_field_kernel = pb->ms[T_FIELD];
+    pb->last.field_launches = pb->cnt[T_FIELD];
     *out = pb->last;
     return st;
 }

@@ -20,7 +20,7 @@ struct hobi_ctx_s {
 
 namespace hobi {
 
-enum TimerKind { T_GATHER = 0, T_PAIR, T_COMBINE, T_KRYLOV, T_NKINDS };
+enum TimerKind { T_GATHER = 0, T_PAIR, T_COMBINE, T_KRYLOV, T_FIELD, T_NKINDS };
 
 struct Timer {
     hipEvent_t a, b;
@@ -52,8 +52,8 @@ struct hobi_problem_s {
     hobi::FieldWork field;           // potential / field evaluation work space
     std::vector<hobi::Timer> pending;
     std::vector<hipEvent_t> event_pool;
-    double ms[hobi::T_NKINDS] = {0, 0, 0, 0};
-    int64_t cnt[hobi::T_NKINDS] = {0, 0, 0, 0};
+    double ms[hobi::T_NKINDS] = {};
+    int64_t cnt[hobi::T_NKINDS] = {};
     hobi_stats last{};
 };
 

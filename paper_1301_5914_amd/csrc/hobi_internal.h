@@ -130,10 +130,12 @@ struct FieldWork {
 };
 // Waves of the mixed or FP64 field kernel the device holds at once (0 on error).
 int field_resident_waves(int device, bool mixed);
-// Pair sums of the plan's workers, then the per-point combine (strengths of u must be in
-// the node records: launch_gather with the same precision).
-hipError_t launch_field(const DeviceProblem& p, const FieldWork& f, const PairPlan& plan, bool mixed,
-                        hipStream_t s);
+// Pair sums of the plan's workers (strengths of u must be in the node records: launch_gather
+// with the same precision), then the per-point combine.
+hipError_t launch_field_pairs(const DeviceProblem& p, const FieldWork& f, const PairPlan& plan, bool mixed,
+                              hipStream_t s);
+hipError_t launch_field_combine(const DeviceProblem& p, const FieldWork& f, const PairPlan& plan, bool mixed,
+                                hipStream_t s);
 hipError_t launch_permute(const double* in, double* out, const int* perm, int nv, bool to_internal,
                           hipStream_t s);
 

@@ -49,7 +49,8 @@ class hobi_stats(ctypes.Structure):
                 ("ms_energy", ctypes.c_double), ("pairs_per_matvec", ctypes.c_int64),
                 ("ms_pair_kernel", ctypes.c_double), ("pair_launches", ctypes.c_int64),
                 ("ms_gather", ctypes.c_double), ("ms_combine", ctypes.c_double),
-                ("ms_krylov", ctypes.c_double)]
+                ("ms_krylov", ctypes.c_double), ("ms_field_kernel", ctypes.c_double),
+                ("field_launches", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
