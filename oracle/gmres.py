@@ -74,3 +74,23 @@ def gmres(matvec, b, rtol=1e-6, restart=200, max_iter=200):
         x = x + V[:k_used].T @ yk
         if done:
             return x, total, rel, rel <= rtol
+
+
+def diagonal_scaling(nv, eps):
+    """1 / the diagonal coefficients of the two row blocks of eqdbef3/eqdbef4 (and of the
+    lower-order eqdbef1/eqdbef2): 1/(1/2 (1 + eps)) on the phi unknowns, 1/(1/2 (1 + 1/eps))
+    on the dphi unknowns."""
+    return np.concatenate([np.full(nv, 1.0 / (0.5 * (1.0 + eps))), np.full(nv, 1.0 / (0.5 * (1.0 + 1.0 / eps)))])
+
+
+def gmres_scaled(matvec, b, dinv, rtol=1e-6, restart=200, max_iter=200):
+    """GMRES on the second-kind form with both diagonal blocks the identity: the unknowns
+    are scaled, A D^-1 y = b with D the diagonal coefficients and u = D^-1 y (right
+    scaling, so the residual GMRES estimates is still ||b - A u|| / ||b||).  The discrete
+    solution is the same; only the Krylov iteration differs (reading: the paper names the
+    equations well-posed of the second kind and runs GMRES on them without giving their
+    scaling).  Returns (u, iterations, estimated relative residual, converged)."""
+    dinv = np.asarray(dinv, dtype=np.float64)
+    y, its, rel, conv = gmres(lambda v: matvec(dinv * v), b, rtol, restart, max_iter)
+    return dinv * y, its, rel, conv
+

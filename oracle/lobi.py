@@ -26,7 +26,7 @@ import dataclasses
 import numpy as np
 
 from . import COULOMB_KCAL, FOUR_PI
-from .gmres import gmres
+from .gmres import diagonal_scaling, gmres, gmres_scaled
 from .kernels import kernels, kernels_12
 from .operator import ChargeOutsideError, sources, validate_mesh
 
@@ -115,8 +115,9 @@ def solid_angle_fraction(st: LobiSetup, points):
 
 
 def solve(xyz, nrm, tri, qpos, q, eps1=1.0, eps2=80.0, kappa=0.1257, rtol=1e-6, restart=200,
-          max_iter=200, st=None):
-    """The whole lower-order solve: sources at the centroids, GMRES, energy."""
+          max_iter=200, st=None, diag_scaling=True):
+    """The whole lower-order solve: sources at the centroids, GMRES (on the diagonally
+    scaled system by default, as oracle.solve), energy."""
     eps = eps2 / eps1
     if st is None:
         st = setup(xyz, nrm, tri)
@@ -126,7 +127,11 @@ def solve(xyz, nrm, tri, qpos, q, eps1=1.0, eps2=80.0, kappa=0.1257, rtol=1e-6, 
         raise ChargeOutsideError("charge outside the surface")
     S1, S2 = sources(st.c, st.n, qpos, q, eps1)
     b = np.concatenate([S1, S2])
-    u, its, rel, conv = gmres(lambda v: matvec(st, v, kappa, eps), b, rtol, restart, max_iter)
+    A = lambda v: matvec(st, v, kappa, eps)
+    if diag_scaling:
+        u, its, rel, conv = gmres_scaled(A, b, diagonal_scaling(st.nf, eps), rtol, restart, max_iter)
+    else:
+        u, its, rel, conv = gmres(A, b, rtol, restart, max_iter)
     E = solvation_energy(st, u, qpos, q, kappa, eps)
     nf = st.nf
     scale = FOUR_PI * COULOMB_KCAL

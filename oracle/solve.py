@@ -10,12 +10,14 @@ from __future__ import annotations
 import numpy as np
 
 from . import COULOMB_KCAL, FOUR_PI
-from .gmres import gmres
+from .gmres import diagonal_scaling, gmres, gmres_scaled
 from .operator import check_charges_inside, matvec, setup, solvation_energy, sources
 
 
 def solve(xyz, nrm, tri, qpos, q, eps1=1.0, eps2=80.0, kappa=0.1257,
-          rtol=1e-6, restart=200, max_iter=200, st=None, workers=1):
+          rtol=1e-6, restart=200, max_iter=200, st=None, workers=1, diag_scaling=True):
+    """diag_scaling: GMRES on the system with both diagonal blocks scaled to the identity
+    (gmres_scaled, the default) or on A u = b as written."""
     eps = eps2 / eps1
     if st is None:
         st = setup(xyz, nrm, tri)
@@ -24,8 +26,11 @@ def solve(xyz, nrm, tri, qpos, q, eps1=1.0, eps2=80.0, kappa=0.1257,
     check_charges_inside(st, qpos)
     S1, S2 = sources(st.xyz, st.nrm, qpos, q, eps1)
     b = np.concatenate([S1, S2])
-    u, its, rel, conv = gmres(lambda v: matvec(st, v, kappa, eps, workers=workers), b, rtol, restart,
-                             max_iter)
+    A = lambda v: matvec(st, v, kappa, eps, workers=workers)
+    if diag_scaling:
+        u, its, rel, conv = gmres_scaled(A, b, diagonal_scaling(st.nv, eps), rtol, restart, max_iter)
+    else:
+        u, its, rel, conv = gmres(A, b, rtol, restart, max_iter)
     true_rel = float(np.linalg.norm(b - matvec(st, u, kappa, eps, workers=workers)) / np.linalg.norm(b))
     E = solvation_energy(st, u, qpos, q, kappa, eps)
     nv = st.nv
