@@ -79,6 +79,10 @@ typedef struct hobi_params {
     int32_t restart;    /* GMRES(m) restart length, default 200                             */
     int32_t precision;  /* HOBI_FP64 or HOBI_MIXED, default HOBI_FP64                       */
     int32_t method;     /* HOBI_HIGHER_ORDER (default) or HOBI_LOWER_ORDER                  */
+    int32_t diag_scaling; /* 1 (default): GMRES runs on the second-kind form with both       */
+                        /* diagonal blocks scaled to the identity (unknowns scaled by        */
+                        /* 1/(1/2 (1+eps)) and 1/(1/2 (1+1/eps)); same solution, the monitored */
+                        /* residual is still ||b - A u|| / ||b||); 0: on A u = b as written  */
 } hobi_params;
 
 typedef struct hobi_stats {

@@ -52,6 +52,24 @@ __global__ void multi_axpy_kernel(const double* __restrict__ V, size_t ld, int n
     w[i] += sign * acc;
 }
 
+__global__ void diag_scale_kernel(const double* __restrict__ in, double* __restrict__ out, int nv, double s1,
+                                  double s2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * nv) return;
+    out[i] = (i < nv ? s1 : s2) * in[i];
+}
+
+// x[i] += s(i) * sum_j coef[j] V[j][i]
+__global__ void multi_axpy_scaled_kernel(const double* __restrict__ V, size_t ld, int nvec,
+                                         const double* __restrict__ coef, double* __restrict__ x, int nv,
+                                         double s1, double s2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * nv) return;
+    double acc = 0.0;
+    for (int j = 0; j < nvec; ++j) acc += coef[j] * V[ld * j + i];
+    x[i] += (i < nv ? s1 : s2) * acc;
+}
+
 __global__ void scale_copy_kernel(const double* __restrict__ in, const double* __restrict__ denom,
                                   double* __restrict__ out, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -139,6 +157,18 @@ hipError_t launch_multi_axpy(const double* V, size_t ld, int nvec, const double*
 
 hipError_t launch_scale_copy(const double* in, const double* denom, double* out, int n, hipStream_t s) {
     hipLaunchKernelGGL(scale_copy_kernel, dim3(nblk(n, kT)), dim3(kT), 0, s, in, denom, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_scale(const double* in, double* out, int nv, double s1, double s2, hipStream_t s) {
+    hipLaunchKernelGGL(diag_scale_kernel, dim3(nblk(2 * nv, kT)), dim3(kT), 0, s, in, out, nv, s1, s2);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy_scaled(const double* V, size_t ld, int nvec, const double* coef, double* x, int nv,
+                                    double s1, double s2, hipStream_t s) {
+    hipLaunchKernelGGL(multi_axpy_scaled_kernel, dim3(nblk(2 * nv, kT)), dim3(kT), 0, s, V, ld, nvec, coef, x, nv,
+                       s1, s2);
     return hipGetLastError();
 }
 

@@ -200,7 +200,10 @@ hobi_status norm2(hobi_problem pb, const double* v, int n, double* dev_out) {
     return HOBI_OK;
 }
 
-// Restarted GMRES(m) from x0 = 0 on A x = rhs (internal order).  Classical Gram-Schmidt
+// Restarted GMRES(m) from x0 = 0 on A x = rhs (internal order); with diag_scaling the
+// Krylov space is that of A D^-1, D the diagonal coefficients 1/2 (1 + eps), 1/2 (1 + 1/eps)
+// of the two row blocks, and the iterate is x = D^-1 y (the residual it estimates is that
+// of A x = rhs).  Classical Gram-Schmidt
 // with a second pass, Givens rotations, stop when the estimate |g_{k+1}| / ||b|| <= rtol.
 hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
     const int n = 2 * pb->d.nv;
@@ -221,6 +224,10 @@ hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
     if (!(bnorm > 0.0)) return std::isfinite(bnorm) ? HOBI_OK : fail(c, HOBI_E_NUMERIC, "non-finite rhs");
     int total = 0;
     const double rtol = pb->prm.rtol;
+    // right scaling (diag_scaling): Krylov space of A D^-1, iterate x = D^-1 y
+    const bool scaled = pb->prm.diag_scaling != 0;
+    double s1 = 1.0, s2 = 1.0;
+    gmres_scales(pb->d.eps, &s1, &s2);
     while (true) {
         // r = b - A x
         const double* r = b;
@@ -241,7 +248,12 @@ hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
         bool stop = false;
         for (int j = 0; j < m; ++j) {
             double* w = k.V + (size_t)(j + 1) * n;
-            if ((st = matvec_internal(pb, k.V + (size_t)j * n, w)) != HOBI_OK) return st;
+            const double* vj = k.V + (size_t)j * n;
+            if (scaled) {
+                HIPCHK(c, launch_diag_scale(vj, k.tmp, n / 2, s1, s2, s));
+                vj = k.tmp;
+            }
+            if ((st = matvec_internal(pb, vj, w)) != HOBI_OK) return st;
             ++total;
             {
                 ScopedTimer t(pb, T_KRYLOV);
@@ -266,7 +278,10 @@ hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
             }
         }
         HIPCHK(c, launch_trisolve(k.H, m + 1, kk, k.g, k.yk, s));
-        HIPCHK(c, launch_multi_axpy(k.V, n, kk, k.yk, 1.0, k.x, n, s));
+        if (scaled)
+            HIPCHK(c, launch_multi_axpy_scaled(k.V, n, kk, k.yk, k.x, n / 2, s1, s2, s));
+        else
+            HIPCHK(c, launch_multi_axpy(k.V, n, kk, k.yk, 1.0, k.x, n, s));
         if (stop) break;
     }
     *iters = total;
@@ -376,6 +391,7 @@ hobi_status validate_params(hobi_ctx ctx, const hobi_params& p) {
         return fail(ctx, HOBI_E_ARG, "precision must be HOBI_FP64 or HOBI_MIXED");
     if (p.method != HOBI_HIGHER_ORDER && p.method != HOBI_LOWER_ORDER)
         return fail(ctx, HOBI_E_ARG, "method must be HOBI_HIGHER_ORDER or HOBI_LOWER_ORDER");
+    if (p.diag_scaling != 0 && p.diag_scaling != 1) return fail(ctx, HOBI_E_ARG, "diag_scaling must be 0 or 1");
     return HOBI_OK;
 }
 
@@ -463,6 +479,7 @@ void hobi_params_default(hobi_params* p) {
     p->restart = 200;
     p->precision = HOBI_FP64;
     p->method = HOBI_HIGHER_ORDER;
+    p->diag_scaling = 1;
 }
 
 hobi_status hobi_ctx_create(int device, void* stream, hobi_ctx* out) {

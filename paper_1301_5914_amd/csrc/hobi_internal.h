@@ -150,6 +150,16 @@ hipError_t launch_multi_axpy(const double* V, size_t ld, int nvec, const double*
 hipError_t launch_scale_copy(const double* in, const double* denom, double* out, int n,
                              hipStream_t s);
 hipError_t launch_sub(const double* a, const double* b, double* out, int n, hipStream_t s);
+// out[i] = s1 in[i] (i < nv), s2 in[i] (nv <= i < 2 nv)
+hipError_t launch_diag_scale(const double* in, double* out, int nv, double s1, double s2, hipStream_t s);
+// x[i] += s(i) sum_j coef[j] V[j][i], s(i) = s1 for i < nv, s2 for nv <= i < 2 nv
+hipError_t launch_multi_axpy_scaled(const double* V, size_t ld, int nvec, const double* coef, double* x, int nv,
+                                    double s1, double s2, hipStream_t s);
+// the right-scaling factors 1 / (1/2 (1 + eps)) and 1 / (1/2 (1 + 1/eps))
+inline void gmres_scales(double eps, double* s1, double* s2) {
+    *s1 = 1.0 / (0.5 * (1.0 + eps));
+    *s2 = 1.0 / (0.5 * (1.0 + 1.0 / eps));
+}
 hipError_t launch_givens(double* H, int ldh, int k, const double* h1, const double* h2,
                          const double* hnext, double* cs, double* sn, double* g,
                          double bnorm, double* res, hipStream_t s);

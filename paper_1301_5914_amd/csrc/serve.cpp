@@ -43,6 +43,7 @@ struct Request {
     double *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
     double *h1 = nullptr, *h2 = nullptr, *hn = nullptr, *yk = nullptr, *dpart = nullptr;
     double *x = nullptr, *scal = nullptr;
+    double* z = nullptr;    // D^-1 v_k, the matvec input under diag_scaling
     int m = 0, k = 0;
     double bnorm = 0, est = 1;
     Clock::time_point t_admit;
@@ -85,15 +86,15 @@ int64_t footprint_bytes(int device, int nv, int nf, int nc, int m, int method) {
     b += 4 * (3LL * nf + nv + 1 + 3LL * nf + nv + nf) + 2LL * 4 * nv_pad;
     b += 8 * std::max<int64_t>(pair_rows_elems, nc_pad * pp.chunks) + 4 * tab_ints;
     const int64_t n = 2LL * nv;
-    b += 8 * ((int64_t)(m + 1) * n + (int64_t)(m + 1) * m + 6LL * (m + 1) + kDotBlocks * (int64_t)(m + 1) + n + 8);
+    b += 8 * ((int64_t)(m + 1) * n + (int64_t)(m + 1) * m + 6LL * (m + 1) + kDotBlocks * (int64_t)(m + 1) + 2 * n + 8);
     return b;
 }
 
 void free_request_device(Request& r) {
-    double* ptrs[] = {r.V, r.H, r.cs, r.sn, r.g, r.h1, r.h2, r.hn, r.yk, r.dpart, r.x, r.scal};
+    double* ptrs[] = {r.V, r.H, r.cs, r.sn, r.g, r.h1, r.h2, r.hn, r.yk, r.dpart, r.x, r.scal, r.z};
     for (double* p : ptrs)
         if (p) (void)hipFree(p);
-    r.V = r.H = r.cs = r.sn = r.g = r.h1 = r.h2 = r.hn = r.yk = r.dpart = r.x = r.scal = nullptr;
+    r.V = r.H = r.cs = r.sn = r.g = r.h1 = r.h2 = r.hn = r.yk = r.dpart = r.x = r.scal = r.z = nullptr;
     if (r.pb) hobi_problem_destroy(r.pb);
     r.pb = nullptr;
 }
@@ -177,6 +178,7 @@ hobi_status admit(hobi_server sv, Request& r) {
     SA(dalloc(&r.dpart, (size_t)kDotBlocks * (m + 1)));
     SA(dalloc(&r.x, n));
     SA(dalloc(&r.scal, 4));
+    if (r.prm.diag_scaling) SA(dalloc(&r.z, n));
     SA(hipMemsetAsync(r.x, 0, sizeof(double) * n, s));
     SA(launch_dots(d.rhs, 0, 1, d.rhs, n, r.dpart, s));
     SA(launch_reduce(r.dpart, 1, r.scal, 1, s));
@@ -204,8 +206,15 @@ void finish(hobi_server sv, Request& r, bool converged) {
     const int n = 2 * r.nu;
     hipError_t e = hipSuccess;
     if (r.k > 0) {
-        if ((e = launch_trisolve(r.H, r.m + 1, r.k, r.g, r.yk, s)) == hipSuccess)
-            e = launch_multi_axpy(r.V, n, r.k, r.yk, 1.0, r.x, n, s);
+        if ((e = launch_trisolve(r.H, r.m + 1, r.k, r.g, r.yk, s)) == hipSuccess) {
+            if (r.prm.diag_scaling) {
+                double s1, s2;
+                gmres_scales(r.pb->d.eps, &s1, &s2);
+                e = launch_multi_axpy_scaled(r.V, n, r.k, r.yk, r.x, r.nu, s1, s2, s);
+            } else {
+                e = launch_multi_axpy(r.V, n, r.k, r.yk, 1.0, r.x, n, s);
+            }
+        }
     }
     if (e == hipSuccess) e = launch_gather(r.pb->d, r.x, false, s);
     if (e == hipSuccess) e = launch_reaction_energy(r.pb->d, r.pb->phi_reac, r.pb->e_dev, s);
@@ -298,6 +307,14 @@ hobi_status tick(hobi_server sv) {
         ServeDesc& sd = sv->h_desc[q];
         sd.u = r.V + (size_t)r.k * n;
         sd.y = r.V + (size_t)(r.k + 1) * n;
+        if (r.prm.diag_scaling) {
+            // the matvec of the scaled system takes D^-1 v_k (the single-problem path's kernel)
+            double s1, s2;
+            gmres_scales(d.eps, &s1, &s2);
+            if ((e = launch_diag_scale(sd.u, r.z, r.nu, s1, s2, s)) != hipSuccess)
+                return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
+            sd.u = r.z;
+        }
         sd.tri = d.tri;
         sd.w = d.w;
         sd.node64 = d.node64;

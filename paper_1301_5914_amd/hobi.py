@@ -39,7 +39,7 @@ class HobiError(RuntimeError):
 class hobi_params(ctypes.Structure):
     _fields_ = [("eps1", ctypes.c_double), ("eps2", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("method", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("method", ctypes.c_int32), ("diag_scaling", ctypes.c_int32)]
 
 
 class hobi_stats(ctypes.Structure):
@@ -184,7 +184,8 @@ class Problem:
     """One surface + charge set with its setup resident on the device."""
 
     def __init__(self, ctx: Context, xyz, nrm, tri, qpos, q, eps1=1.0, eps2=80.0, kappa=0.1257,
-                 rtol=1e-6, max_iter=200, restart=200, precision=HOBI_FP64, method=HOBI_HIGHER_ORDER):
+                 rtol=1e-6, max_iter=200, restart=200, precision=HOBI_FP64, method=HOBI_HIGHER_ORDER,
+                 diag_scaling=1):
         self.ctx = ctx
         xyz = _f64(xyz).reshape(-1, 3)
         nrm = _f64(nrm).reshape(-1, 3)
@@ -198,6 +199,7 @@ class Problem:
         p = hobi_params_default()
         p.eps1, p.eps2, p.kappa, p.rtol = eps1, eps2, kappa, rtol
         p.max_iter, p.restart, p.precision, p.method = max_iter, restart, precision, method
+        p.diag_scaling = diag_scaling
         h = _P()
         st = lib().hobi_problem_create(ctx.handle, self.nv, _dptr(xyz), _dptr(nrm), self.nf,
                                        tri.ctypes.data_as(_I), self.nc, _dptr(qpos), _dptr(q),
@@ -350,7 +352,7 @@ class Server:
         raise HobiError(st, msg.decode() if msg else "")
 
     def submit(self, prob, rtol=1e-6, max_iter=300, precision=HOBI_MIXED, eps1=None, eps2=None,
-               kappa=None, method=HOBI_HIGHER_ORDER) -> int:
+               kappa=None, method=HOBI_HIGHER_ORDER, diag_scaling=1) -> int:
         xyz = _f64(prob.xyz).reshape(-1, 3)
         nrm = _f64(prob.nrm).reshape(-1, 3)
         tri = np.ascontiguousarray(np.asarray(prob.tri, dtype=np.int32).reshape(-1, 3))
@@ -361,6 +363,7 @@ class Server:
         p.eps2 = prob.eps2 if eps2 is None else eps2
         p.kappa = prob.kappa if kappa is None else kappa
         p.rtol, p.max_iter, p.restart, p.precision, p.method = rtol, max_iter, max_iter, precision, method
+        p.diag_scaling = diag_scaling
         t = ctypes.c_uint64()
         st = lib().hobi_server_submit(self.handle, xyz.shape[0], _dptr(xyz), _dptr(nrm), tri.shape[0],
                                       tri.ctypes.data_as(_I), q.shape[0], _dptr(qpos), _dptr(q),
