@@ -210,17 +210,20 @@ hobi_status hobi_reset_stats(hobi_problem pb);
 hobi_status hobi_get_stats(hobi_problem pb, hobi_stats* st);
 
 /* ---- request server: continuous batching of many solves on one device -------------
- * A worker thread owns a stream of its own.  Submitted requests wait in FIFO order until
- * a slot is free and their device footprint (surface, quadrature data, Krylov basis of
- * max_iter + 1 vectors) fits in hbm_budget_bytes next to the active ones; admitted
- * requests run their setup and then advance one GMRES iteration per scheduler tick, all
- * active requests together: each tick does one batched gather, one batched pair-sum and
+ * Two threads, each with a stream of its own.  Submitted requests wait in FIFO order
+ * until a slot is free and their device footprint (surface, quadrature data, Krylov basis
+ * of max_iter + 1 vectors) fits in hbm_budget_bytes next to the admitted ones; the
+ * preparation thread then builds the request's problem (host checks and ordering, device
+ * setup) while the worker's ticks run, and the worker advances every built request one
+ * GMRES iteration per scheduler tick, all together: each tick does one batched gather,
+ * one batched pair-sum and
  * one batched combine launch for every request (captured once in a HIP graph when
  * use_graph is 1), then each request's Gram-Schmidt and Givens update.  Requests
  * arriving during a tick join at the next one; finished requests leave at the end of the
  * tick that finished them.  A request's arithmetic depends only on that request (its
- * chunking is fixed by its own size), so its results are bit-for-bit the same alone and
- * in any mix.  Served solves do not restart: max_iter bounds the Krylov basis.
+ * split over waves is fixed by its own size and the device), so its results are
+ * bit-for-bit the same alone, in any mix, and as hobi_solve with restart = max_iter.
+ * Served solves do not restart: max_iter bounds the Krylov basis.
  * Thread safety: submit, poll and get_stats may be called from any thread. */
 typedef struct hobi_server_stats {
     int64_t submitted, completed, failed;  /* requests                                      */
@@ -231,7 +234,7 @@ typedef struct hobi_server_stats {
     double busy_ms;                        /* wall time the worker spent with work in hand    */
 } hobi_server_stats;
 
-/* device: from ctx (the server creates its own stream and worker thread).
+/* device: from ctx (the server creates its own two streams and threads).
  * hbm_budget_bytes > 0; max_slots >= 1.  Errors: HOBI_E_ARG, HOBI_E_HIP. */
 hobi_status hobi_server_create(hobi_ctx ctx, int64_t hbm_budget_bytes, int32_t max_slots,
                                int32_t use_graph, hobi_server* out);

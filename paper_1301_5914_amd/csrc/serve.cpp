@@ -117,10 +117,19 @@ struct hobi_server_s {
     std::set<uint64_t> in_flight;     // submitted, not finished yet
     std::string last_error;
     hobi_server_stats st{};
+    // preparation: requests whose problem (host checks, ordering, device setup) is being
+    // built on the preparation thread's own context, and those built and waiting for the
+    // worker; their footprints are already counted in in_use
+    std::condition_variable prep_cv;
+    std::deque<std::unique_ptr<Request>> ready;
+    int preparing = 0;
+    int active_count = 0;             // the worker's active requests (guarded by mu)
+    int64_t in_use = 0;
+    hobi_ctx prep_ctx = nullptr;
+    std::thread prep;
 
     // worker-only state
     std::vector<std::unique_ptr<Request>> active;
-    int64_t in_use = 0;
     double batch_sum = 0;
     ServeDesc* d_desc = nullptr;
     ServeItem* d_items = nullptr;     // gather | pair | combine item arrays
@@ -144,17 +153,12 @@ void fail_request(Request& r, hobi_status code, const std::string& msg) {
     r.message = msg;
 }
 
-// Allocates the device state of a request and starts its GMRES (x0 = 0, v0 = b / |b|).
+// Allocates the Krylov state of a request whose problem the preparation thread created and
+// starts its GMRES (x0 = 0, v0 = b / |b|).
 hobi_status admit(hobi_server sv, Request& r) {
     hobi_ctx c = sv->ctx;
     hipStream_t s = c->stream;
     r.t_admit = Clock::now();
-    hobi_status st = hobi_problem_create(c, r.nv, r.xyz.data(), r.nrm.data(), r.nf, r.tri.data(), r.nc,
-                                         r.qpos.data(), r.q.data(), &r.prm, &r.pb);
-    if (st != HOBI_OK) {
-        fail_request(r, st, c->err);
-        return st;
-    }
     const bool mixed = r.prm.precision == HOBI_MIXED;
     const DeviceProblem& d = r.pb->d;
     r.plan = mixed ? d.plan32 : d.plan64;
@@ -410,24 +414,21 @@ void worker_main(hobi_server sv) {
         std::vector<std::unique_ptr<Request>> admitted;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            if (sv->active.empty())
-                sv->cv.wait(lk, [&] { return sv->stop || !sv->pending.empty(); });
+            if (sv->active.empty()) sv->cv.wait(lk, [&] { return sv->stop || !sv->ready.empty(); });
             if (sv->stop) break;
-            // FIFO admission while a slot is free and the head fits in the budget
-            while (!sv->pending.empty() && (int)(sv->active.size() + admitted.size()) < sv->max_slots &&
-                   sv->in_use + sv->pending.front()->footprint <= sv->budget) {
-                sv->in_use += sv->pending.front()->footprint;
-                admitted.push_back(std::move(sv->pending.front()));
-                sv->pending.pop_front();
+            // the requests the preparation thread has built, in FIFO order
+            while (!sv->ready.empty()) {
+                admitted.push_back(std::move(sv->ready.front()));
+                sv->ready.pop_front();
             }
-            sv->st.pending = (int32_t)sv->pending.size();
-            sv->st.bytes_in_use = sv->in_use;
-            sv->st.peak_bytes = std::max(sv->st.peak_bytes, sv->in_use);
+            sv->active_count = (int)(sv->active.size() + admitted.size());
         }
         const auto t0 = Clock::now();
         std::vector<std::unique_ptr<Request>> finished;
         for (auto& r : admitted) {
-            if (admit(sv, *r) != HOBI_OK || r->bnorm == 0.0) {
+            if (!r->pb) {                     // its problem could not be built
+                finished.push_back(std::move(r));
+            } else if (admit(sv, *r) != HOBI_OK || r->bnorm == 0.0) {
                 if (r->status == HOBI_OK) finish(sv, *r, true);   // b = 0: u = 0
                 else free_request_device(*r);
                 finished.push_back(std::move(r));
@@ -479,12 +480,58 @@ void worker_main(hobi_server sv) {
                 sv->done[r->ticket] = std::move(r);
             }
             sv->st.active = (int32_t)sv->active.size();
+            sv->active_count = (int)sv->active.size();
             sv->st.bytes_in_use = sv->in_use;
             sv->st.mean_batch = sv->st.ticks ? sv->batch_sum / (double)sv->st.ticks : 0.0;
         }
+        sv->prep_cv.notify_all();             // slots and budget may have been freed
     }
     for (auto& r : sv->active) free_request_device(*r);
     sv->active.clear();
+}
+
+// Preparation thread: FIFO over the pending requests while a slot is free (active, ready
+// and in preparation together below max_slots) and the head fits in the budget; builds
+// each request's problem on its own context and stream (host checks and ordering, device
+// setup), concurrently with the worker's ticks, then hands the problem to the worker's
+// context.
+void prep_main(hobi_server sv) {
+    (void)hipSetDevice(sv->device);
+    while (true) {
+        std::unique_ptr<Request> r;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->prep_cv.wait(lk, [&] {
+                return sv->stop ||
+                       (!sv->pending.empty() &&
+                        sv->active_count + (int)sv->ready.size() + sv->preparing < sv->max_slots &&
+                        sv->in_use + sv->pending.front()->footprint <= sv->budget);
+            });
+            if (sv->stop) break;
+            r = std::move(sv->pending.front());
+            sv->pending.pop_front();
+            sv->in_use += r->footprint;
+            sv->preparing += 1;
+            sv->st.pending = (int32_t)sv->pending.size();
+            sv->st.bytes_in_use = sv->in_use;
+            sv->st.peak_bytes = std::max(sv->st.peak_bytes, sv->in_use);
+        }
+        const hobi_status st = hobi_problem_create(sv->prep_ctx, r->nv, r->xyz.data(), r->nrm.data(), r->nf,
+                                                   r->tri.data(), r->nc, r->qpos.data(), r->q.data(), &r->prm,
+                                                   &r->pb);
+        if (st != HOBI_OK) {
+            fail_request(*r, st, sv->prep_ctx->err);
+            r->pb = nullptr;
+        } else {
+            r->pb->ctx = sv->ctx;             // built and synchronised: from now on the worker's
+        }
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->preparing -= 1;
+            sv->ready.push_back(std::move(r));
+        }
+        sv->cv.notify_all();
+    }
 }
 
 }  // namespace
@@ -501,9 +548,11 @@ hobi_status hobi_server_create(hobi_ctx ctx, int64_t hbm_budget_bytes, int32_t m
     sv->budget = hbm_budget_bytes;
     sv->max_slots = max_slots;
     sv->use_graph = use_graph != 0;
-    if (hobi_ctx_create(ctx->device, nullptr, &sv->ctx) != HOBI_OK) {
+    if (hobi_ctx_create(ctx->device, nullptr, &sv->ctx) != HOBI_OK ||
+        hobi_ctx_create(ctx->device, nullptr, &sv->prep_ctx) != HOBI_OK) {
+        if (sv->ctx) hobi_ctx_destroy(sv->ctx);
         delete sv;
-        return host_fail(ctx, HOBI_E_HIP, "could not create the server stream");
+        return host_fail(ctx, HOBI_E_HIP, "could not create the server streams");
     }
     if (hipMalloc((void**)&sv->d_counts, 4 * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void**)&sv->h_counts, 4 * sizeof(int)) != hipSuccess ||
@@ -512,6 +561,7 @@ hobi_status hobi_server_create(hobi_ctx ctx, int64_t hbm_budget_bytes, int32_t m
         return host_fail(ctx, HOBI_E_OOM, "server buffers");
     }
     sv->worker = std::thread(worker_main, sv);
+    sv->prep = std::thread(prep_main, sv);
     *out = sv;
     return HOBI_OK;
 }
@@ -550,7 +600,7 @@ hobi_status hobi_server_submit(hobi_server sv, int32_t nv, const double* xyz, co
     sv->pending.push_back(std::move(r));
     sv->st.submitted += 1;
     sv->st.pending = (int32_t)sv->pending.size();
-    sv->cv.notify_one();
+    sv->prep_cv.notify_all();
     return HOBI_OK;
 }
 
@@ -593,7 +643,11 @@ void hobi_server_destroy(hobi_server sv) {
         sv->stop = true;
     }
     sv->cv.notify_all();
+    sv->prep_cv.notify_all();
+    if (sv->prep.joinable()) sv->prep.join();
     if (sv->worker.joinable()) sv->worker.join();
+    for (auto& r : sv->ready) free_request_device(*r);
+    sv->ready.clear();
     if (sv->ctx) (void)hipStreamSynchronize(sv->ctx->stream);
     if (sv->graph_exec) (void)hipGraphExecDestroy(sv->graph_exec);
     if (sv->graph) (void)hipGraphDestroy(sv->graph);
@@ -606,6 +660,7 @@ void hobi_server_destroy(hobi_server sv) {
     if (sv->h_counts) (void)hipHostFree(sv->h_counts);
     if (sv->h_res) (void)hipHostFree(sv->h_res);
     if (sv->ctx) hobi_ctx_destroy(sv->ctx);
+    if (sv->prep_ctx) hobi_ctx_destroy(sv->prep_ctx);
     delete sv;
 }
 
