@@ -111,33 +111,37 @@ __global__ __launch_bounds__(kBlock) void point_sum_kernel(
     partial[(size_t)blockIdx.y * np_pad + p] = acc;
 }
 
-// MODE 0: phi_reac[p] = sum over chunks; E = 1/2 * 4 pi C * sum_p q_p phi_reac[p].
-// MODE 1: out[p] = -(sum over chunks) / (4 pi).  One block, fixed reduction order.
+// One block per point p: the sum over chunks (thread t takes chunks t, t + 256, ... in
+// order, then a fixed LDS tree).  MODE 0: out[p] = phi_reac[p]; MODE 1: out[p] = -sum / (4 pi).
 template <int MODE>
-__global__ __launch_bounds__(256) void point_reduce_kernel(const double* __restrict__ partial, int np,
-                                                           int np_pad, int chunks,
-                                                           const double* __restrict__ q,
-                                                           double* __restrict__ out,
-                                                           double* __restrict__ e_out) {
+__global__ __launch_bounds__(256) void point_reduce_kernel(const double* __restrict__ partial, int np_pad,
+                                                           int chunks, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int p = blockIdx.x;
+    double v = 0.0;
+    for (int c = threadIdx.x; c < chunks; c += 256) v += partial[(size_t)c * np_pad + p];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[p] = MODE == 0 ? red[0] : -red[0] * kInv4Pi;
+}
+
+// E = 1/2 * 4 pi C * sum_p q_p phi_reac[p]; one block, fixed order.
+__global__ __launch_bounds__(256) void energy_kernel(const double* __restrict__ phi_reac, const double* __restrict__ q,
+                                                     int np, double* __restrict__ e_out) {
     __shared__ double red[256];
     double local = 0.0;
-    for (int p = threadIdx.x; p < np; p += 256) {
-        double v = 0.0;
-        for (int c = 0; c < chunks; ++c) v += partial[(size_t)c * np_pad + p];
-        if (MODE == 0) {
-            out[p] = v;
-            local += q[p] * v;
-        } else {
-            out[p] = -v * kInv4Pi;
-        }
-    }
+    for (int p = threadIdx.x; p < np; p += 256) local += q[p] * phi_reac[p];
     red[threadIdx.x] = local;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
-    if (MODE == 0 && threadIdx.x == 0) e_out[0] = 0.5 * 4.0 * kPi * 332.0716 * red[0];
+    if (threadIdx.x == 0) e_out[0] = 0.5 * 4.0 * kPi * 332.0716 * red[0];
 }
 
 __global__ void permute_kernel(const double* __restrict__ in, double* __restrict__ out,
@@ -251,8 +255,11 @@ hipError_t launch_reaction_energy(const DeviceProblem& p, double* phi_reac, doub
                        p.nc_pad, p.node64, p.w, p.nn, pl.chunk, p.kappa, p.eps, p.partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((point_reduce_kernel<0>), dim3(1), dim3(256), 0, s, p.partial, p.nc, p.nc_pad,
-                       pl.chunks, p.q, phi_reac, e_out);
+    hipLaunchKernelGGL((point_reduce_kernel<0>), dim3(p.nc), dim3(256), 0, s, p.partial, p.nc_pad, pl.chunks,
+                       phi_reac);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(256), 0, s, phi_reac, p.q, p.nc, e_out);
     return hipGetLastError();
 }
 
@@ -262,8 +269,8 @@ hipError_t launch_solid_angle(const DeviceProblem& p, double* frac, hipStream_t 
                        p.nc_pad, p.node64, p.w, p.nn, pl.chunk, p.kappa, p.eps, p.partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((point_reduce_kernel<1>), dim3(1), dim3(256), 0, s, p.partial, p.nc, p.nc_pad,
-                       pl.chunks, p.q, frac, (double*)nullptr);
+    hipLaunchKernelGGL((point_reduce_kernel<1>), dim3(p.nc), dim3(256), 0, s, p.partial, p.nc_pad, pl.chunks,
+                       frac);
     return hipGetLastError();
 }
 

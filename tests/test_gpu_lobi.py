@@ -110,3 +110,25 @@ def test_lobi_served_equals_single_problem(ctx):
         np.testing.assert_array_equal(r["dphi"], ref["dphi"])
         assert r["energy"] == ref["energy"]
     sv.close()
+
+
+def test_lobi_bench_workload_L6_sampled_rows(ctx):
+    """The lower-order bench workload at full size (`bench.py --method lower`: 81920 sites
+    and nodes, 8 targets per lane, the same pair plan as the timed run): rows at both ends,
+    around slot boundaries and at random, against the oracle row by row, and the mixed
+    energy against FP64."""
+    p = inputs.kirkwood_offcenter(6)
+    st = LO.setup(p.xyz, p.nrm, p.tri)
+    u = inputs.random_vector(2 * p.nf, 32)
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.r_[0:4, p.nf - 4:p.nf, 510:514, 40958:40962, rng.integers(0, p.nf, 24)])
+    y_or = LO.matvec(st, u, p.kappa, p.eps2 / p.eps1, rows=rows)
+    E = {}
+    for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
+        g = hobi.Problem.from_inputs(ctx, p, precision=prec, method=LOWER, max_iter=400, restart=400)
+        y = g.matvec(u)
+        err = _rel_inf(np.stack([y[rows], y[p.nf + rows]]), y_or)
+        print(f"lobi L6 precision {prec} rel err {err:.3e}", flush=True)
+        assert err <= tol
+        E[prec] = g.solve()["energy"]
+    assert abs(E[hobi.HOBI_MIXED] / E[hobi.HOBI_FP64] - 1) <= 1e-5
