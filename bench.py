@@ -33,7 +33,7 @@ PEAK_NONPACKED_FP32 = 78.6                    # 256 CU x 4 SIMD x 16 lanes x 2 f
 # HBM bytes per launch of the FP32 pair kernel on the default workload (icosphere L6):
 # rocprofv3 FETCH_SIZE (x2.000) + WRITE_SIZE (x1.000), each scaled by a 256 MiB copy.
 # Only valid for the kernel build it was measured on; null for any other configuration.
-PAIR_F32_L6_TRAFFIC_BYTES = (29830.9 * 2.000 + 518569.0 * 1.000) * 1024
+PAIR_F32_L6_TRAFFIC_BYTES = (29821.0 * 2.000 + 518569.0 * 1.000) * 1024
 
 
 def workload(args):
