@@ -134,6 +134,46 @@ def field_bench(pb, prob, grid, res, mixed, n_nodes):
             "energy_from_field_rel": abs(e_field / res["energy"] - 1)}
 
 
+def tree_bench(ctx, stream, prob, theta, degree, leaf, mixed, dense_pb, dense_res, dense_mv_ms, pairs_mv):
+    """The treecode form of the matvec on the same problem: matvec time (HIP events, median
+    of 20), the dense pair count it replaces per second, its error against the dense matvec
+    on a random vector, and the solve with it against the dense solve."""
+    import torch
+    from paper_1301_5914_amd import hobi
+    pb = hobi.Problem.from_inputs(ctx, prob, precision=hobi.HOBI_MIXED if mixed else hobi.HOBI_FP64,
+                                  tree_theta=theta, tree_degree=degree, tree_leaf=leaf, max_iter=400, restart=400)
+    st = pb.stats()
+    u = torch.randn(2 * prob.nv, dtype=torch.float64, device="cuda")
+    yt = torch.empty_like(u)
+    yd = torch.empty_like(u)
+    ms = []
+    for i in range(23):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        pb.matvec(u, out=yt)
+        ev1.record(stream)
+        ev1.synchronize()
+        if i >= 3:
+            ms.append(ev0.elapsed_time(ev1))
+    dense_pb.matvec(u, out=yd)
+    torch.cuda.synchronize()
+    err = float((yt - yd).abs().max() / yd.abs().max())
+    pb.solve()                                        # warm-up
+    res = [pb.solve() for _ in range(2)]
+    mv = float(np.median(ms))
+    return {"theta": theta, "degree": degree, "leaf": leaf,
+            "far_pairs": st["tree_far_pairs"], "near_pairs": st["tree_near_pairs"],
+            "matvec_ms_median": mv, "dense_matvec_ms_median": dense_mv_ms,
+            "speedup_over_dense_matvec": dense_mv_ms / mv,
+            "equivalent_gpairs_per_s": pairs_mv / (mv * 1e-3) / 1e9,
+            "matvec_rel_err_vs_dense": err,
+            "gmres_iterations": res[-1]["stats"]["iterations"],
+            "solve_ms": float(np.mean([r["stats"]["ms_solve"] for r in res])),
+            "dense_solve_ms": dense_res["stats"]["ms_solve"],
+            "energy_rel_diff_vs_dense": abs(res[-1]["energy"] / dense_res["energy"] - 1)}
+
+
 def _make_molecule(n_atoms, seed):
     from paper_1301_5914_amd import inputs
     return inputs.molecule(int(n_atoms), seed=int(seed))
@@ -272,6 +312,10 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--field-map", type=int, default=64,
                     help="potential map of grid^3 points after the timed steps (hobi_field); 0 = off")
+    ap.add_argument("--tree-theta", type=float, default=0.5,
+                    help="also time the treecode matvec and solve with this opening parameter (0: skip)")
+    ap.add_argument("--tree-degree", type=int, default=5)
+    ap.add_argument("--tree-leaf", type=int, default=1024)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -383,6 +427,9 @@ def main():
     out["matvec_gpairs_per_s"] = pairs_mv / (out["matvec_ms_median"] * 1e-3) / 1e9
     if args.field_map > 0:
         out["field"] = field_bench(pb, prob, args.field_map, results[-1], mixed, n_nodes)
+    if args.tree_theta > 0 and not lower:
+        out["tree"] = tree_bench(ctx, stream, prob, args.tree_theta, args.tree_degree, args.tree_leaf, mixed, pb,
+                                 results[-1], out["matvec_ms_median"], pairs_mv)
     if not args.no_compare:
         # the other precision on the same problem (outside the timed region)
         pb.set_precision(hobi.HOBI_FP64 if mixed else hobi.HOBI_MIXED)

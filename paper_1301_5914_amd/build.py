@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhobi.so")
 
 SOURCES = ["hobi_api.cpp", "serve.cpp", "setup_kernels.hip", "pair_kernels.hip", "gmres_kernels.hip",
-           "serve_kernels.hip", "field_kernels.hip"]
+           "serve_kernels.hip", "field_kernels.hip", "tree_kernels.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

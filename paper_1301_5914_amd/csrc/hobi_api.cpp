@@ -143,6 +143,18 @@ hobi_status matvec_internal(hobi_problem pb, const double* u, double* y) {
         ScopedTimer t(pb, T_GATHER);
         HIPCHK(pb->ctx, launch_gather(pb->d, u, mixed, s));
     }
+    if (pb->d.tree.on) {
+        {
+            ScopedTimer t(pb, T_PAIR);
+            HIPCHK(pb->ctx, launch_tree_proxies(pb->d, mixed, s));
+            HIPCHK(pb->ctx, launch_tree_pairs(pb->d, mixed, s));
+        }
+        {
+            ScopedTimer t(pb, T_COMBINE);
+            HIPCHK(pb->ctx, launch_tree_combine(pb->d, u, y, mixed, s));
+        }
+        return HOBI_OK;
+    }
     {
         ScopedTimer t(pb, T_PAIR);
         HIPCHK(pb->ctx, launch_pair(pb->d, mixed, s));
@@ -333,6 +345,13 @@ void free_problem(hobi_problem pb) {
         if (p) (void)hipFree(p);
     free_krylov(pb->kr);
     {
+        TreePlan& t = d.tree;
+        void* tp[] = {t.clu_range, t.clu_box, t.prox64, t.prox32, t.items[0], t.items[1], t.partial};
+        for (void* p : tp)
+            if (p) (void)hipFree(p);
+        t = TreePlan{};
+    }
+    {
         FieldWork& f = pb->field;
         void* fp[] = {f.pts64, f.pts32, f.partial, f.gstart, f.out, f.inside};
         for (void* p : fp)
@@ -375,6 +394,119 @@ hobi_status run_device_setup(hobi_problem pb, float* ms_out) {
     return HOBI_OK;
 }
 
+// The treecode's partition (hobi_params.tree_theta > 0), from the node and target positions
+// in internal order: clusters of tree_leaf consecutive nodes, batches of kTreeBatch
+// consecutive targets, each with the bounding sphere of its box (centre, half diagonal); a
+// pair is far when r_b + r_c <= theta |c_b - c_c| and the vertex ids of the cluster's
+// triangles, taken as a range, miss the batch's.  Work items: every (slot, cluster) of each
+// precision's target slots, slot-major, marked far when its batch's pair is.
+hobi_status build_tree_plan(hobi_problem pb) {
+    DeviceProblem& d = pb->d;
+    TreePlan& t = d.tree;
+    const hobi_params& prm = pb->prm;
+    if (!(prm.tree_theta > 0)) return HOBI_OK;
+    hobi_ctx ctx = pb->ctx;
+    hipStream_t s = ctx->stream;
+    const int nn = d.nn, nv = d.nv, nf = d.nf;
+    std::vector<NodeD> nodes(nn);
+    std::vector<double> tg(3 * (size_t)d.nv_pad);
+    std::vector<int> tri(3 * (size_t)nf);
+    HIPCHK(ctx, hipMemcpyAsync(nodes.data(), d.node64, sizeof(NodeD) * nn, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(tg.data(), d.tgt64, sizeof(double) * tg.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(tri.data(), d.tri, sizeof(int) * tri.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    t.degree = prm.tree_degree;
+    t.nprox = (t.degree + 1) * (t.degree + 1) * (t.degree + 1);
+    t.leaf = prm.tree_leaf;
+    t.ncl = (nn + t.leaf - 1) / t.leaf;
+    t.nbatch = (nv + kTreeBatch - 1) / kTreeBatch;
+    // centre of the box [lo, hi] into c; returns its diagonal
+    auto box_centre = [](const double lo[3], const double hi[3], double c[3]) {
+        double q = 0;
+        for (int k = 0; k < 3; ++k) {
+            c[k] = 0.5 * (lo[k] + hi[k]);
+            q += (hi[k] - lo[k]) * (hi[k] - lo[k]);
+        }
+        return std::sqrt(q);
+    };
+    std::vector<int2> crange(t.ncl);
+    std::vector<double> cbox(6 * (size_t)t.ncl), ccen(3 * (size_t)t.ncl), crad(t.ncl);
+    std::vector<int> cvlo(t.ncl), cvhi(t.ncl);
+    for (int c = 0; c < t.ncl; ++c) {
+        const int a = c * t.leaf, b = std::min(a + t.leaf, nn);
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int j = a; j < b; ++j) {
+            const double pj[3] = {nodes[j].x, nodes[j].y, nodes[j].z};
+            for (int k = 0; k < 3; ++k) lo[k] = std::min(lo[k], pj[k]), hi[k] = std::max(hi[k], pj[k]);
+        }
+        const double diag = box_centre(lo, hi, &ccen[3 * (size_t)c]);
+        crad[c] = 0.5 * diag;
+        const double g = kTreeGrow * diag + 1e-12;
+        for (int k = 0; k < 3; ++k) cbox[6 * (size_t)c + k] = lo[k] - g, cbox[6 * (size_t)c + 3 + k] = hi[k] + g;
+        int vlo = nv, vhi = -1;
+        for (int f = a / 4; f < (b + 3) / 4; ++f)
+            for (int k = 0; k < 3; ++k) vlo = std::min(vlo, tri[3 * f + k]), vhi = std::max(vhi, tri[3 * f + k]);
+        cvlo[c] = vlo;
+        cvhi[c] = vhi;
+        crange[c] = make_int2(a, b);
+    }
+    std::vector<char> far((size_t)t.nbatch * t.ncl, 0);
+    t.nfar = 0;
+    for (int bi = 0; bi < t.nbatch; ++bi) {
+        const int a = bi * kTreeBatch, b = std::min(a + kTreeBatch, nv);
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int i = a; i < b; ++i)
+            for (int k = 0; k < 3; ++k) {
+                const double v = tg[(size_t)k * d.nv_pad + i];
+                lo[k] = std::min(lo[k], v), hi[k] = std::max(hi[k], v);
+            }
+        double cb[3];
+        const double rb = 0.5 * box_centre(lo, hi, cb);
+        for (int c = 0; c < t.ncl; ++c) {
+            const bool touches = cvhi[c] >= a && cvlo[c] <= b - 1;
+            const double* cc = &ccen[3 * (size_t)c];
+            const double dx = cb[0] - cc[0], dy = cb[1] - cc[1], dz = cb[2] - cc[2];
+            const bool f = !touches && rb + crad[c] <= prm.tree_theta * std::sqrt(dx * dx + dy * dy + dz * dz);
+            far[(size_t)bi * t.ncl + c] = f;
+            t.nfar += f;
+        }
+    }
+    std::vector<int4> items[2];
+    size_t partial_elems = 0;
+    for (int m = 0; m < 2; ++m) {
+        t.tpl[m] = m ? tpl32_for(d.nv_pad) : kTpl64;
+        t.slot[m] = 64 * t.tpl[m];
+        const int slots = (nv + t.slot[m] - 1) / t.slot[m];
+        const int64_t n_items = (int64_t)slots * t.ncl;
+        const size_t elems = (size_t)n_items * 2 * t.slot[m];
+        if (n_items > ((int64_t)1 << 30) || elems > ((size_t)1 << 31))
+            return fail(ctx, HOBI_E_ARG, "treecode plan too large (%lld work items): raise tree_leaf",
+                        (long long)n_items);
+        t.nitems[m] = (int)n_items;
+        partial_elems = std::max(partial_elems, elems);
+        items[m].reserve(n_items);
+        for (int sl = 0; sl < slots; ++sl) {
+            const int bi = sl * t.slot[m] / kTreeBatch;
+            for (int c = 0; c < t.ncl; ++c) items[m].push_back(make_int4(sl, far[(size_t)bi * t.ncl + c], c, 0));
+        }
+    }
+    HIPCHK(ctx, dalloc(&t.clu_range, t.ncl));
+    HIPCHK(ctx, dalloc(&t.clu_box, 6 * (size_t)t.ncl));
+    HIPCHK(ctx, dalloc(&t.prox64, (size_t)t.ncl * t.nprox));
+    HIPCHK(ctx, dalloc(&t.prox32, (size_t)t.ncl * t.nprox));
+    HIPCHK(ctx, dalloc(&t.items[0], items[0].size()));
+    HIPCHK(ctx, dalloc(&t.items[1], items[1].size()));
+    HIPCHK(ctx, dalloc(&t.partial, partial_elems));
+    HIPCHK(ctx, hipMemcpyAsync(t.clu_range, crange.data(), sizeof(int2) * crange.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(t.clu_box, cbox.data(), sizeof(double) * cbox.size(), hipMemcpyHostToDevice, s));
+    for (int m = 0; m < 2; ++m)
+        HIPCHK(ctx, hipMemcpyAsync(t.items[m], items[m].data(), sizeof(int4) * items[m].size(),
+                                   hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    t.on = 1;
+    return HOBI_OK;
+}
+
 bool finite_all(const double* a, size_t n) {
     for (size_t i = 0; i < n; ++i)
         if (!std::isfinite(a[i])) return false;
@@ -392,6 +524,13 @@ hobi_status validate_params(hobi_ctx ctx, const hobi_params& p) {
     if (p.method != HOBI_HIGHER_ORDER && p.method != HOBI_LOWER_ORDER)
         return fail(ctx, HOBI_E_ARG, "method must be HOBI_HIGHER_ORDER or HOBI_LOWER_ORDER");
     if (p.diag_scaling != 0 && p.diag_scaling != 1) return fail(ctx, HOBI_E_ARG, "diag_scaling must be 0 or 1");
+    if (!(p.tree_theta >= 0) || !std::isfinite(p.tree_theta)) return fail(ctx, HOBI_E_ARG, "tree_theta must be >= 0");
+    if (p.tree_degree < 1 || p.tree_degree > kTreeMaxDeg)
+        return fail(ctx, HOBI_E_ARG, "tree_degree must be in 1..%d", kTreeMaxDeg);
+    if (p.tree_leaf < 64 || p.tree_leaf > (1 << 24) || p.tree_leaf % 64 != 0)
+        return fail(ctx, HOBI_E_ARG, "tree_leaf must be a multiple of 64 in [64, 2^24]");
+    if (p.tree_theta > 0 && p.method != HOBI_HIGHER_ORDER)
+        return fail(ctx, HOBI_E_ARG, "the treecode serves the higher-order method only");
     return HOBI_OK;
 }
 
@@ -480,6 +619,9 @@ void hobi_params_default(hobi_params* p) {
     p->precision = HOBI_FP64;
     p->method = HOBI_HIGHER_ORDER;
     p->diag_scaling = 1;
+    p->tree_theta = 0.0;
+    p->tree_degree = 5;
+    p->tree_leaf = 1024;
 }
 
 hobi_status hobi_ctx_create(int device, void* stream, hobi_ctx* out) {
@@ -707,6 +849,7 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
     PCHK(hipStreamSynchronize(s));
     float ms = 0.f;
     if ((st = run_device_setup(pb, &ms)) != HOBI_OK) return cleanup_fail(st);
+    if ((st = build_tree_plan(pb)) != HOBI_OK) return cleanup_fail(st);
     std::vector<int> herr(nf);
     PCHK(hipMemcpyAsync(herr.data(), pb->d_err, sizeof(int) * nf, hipMemcpyDeviceToHost, s));
     PCHK(hipStreamSynchronize(s));
@@ -948,6 +1091,8 @@ hobi_status hobi_solve(hobi_problem pb, double* phi, double* dphi, double* e_sol
     L.ms_krylov = pb->ms[T_KRYLOV];
     L.ms_field_kernel = pb->ms[T_FIELD];
     L.field_launches = pb->cnt[T_FIELD];
+    L.tree_far_pairs = pb->d.tree.nfar;
+    L.tree_near_pairs = pb->d.tree.on ? (int64_t)pb->d.tree.nbatch * pb->d.tree.ncl - pb->d.tree.nfar : 0;
     if (stats) *stats = L;
     for (int i = 0; i < n; ++i)
         if (!std::isfinite(hu[i])) return fail(c, HOBI_E_NUMERIC, "non-finite solution");
@@ -1003,6 +1148,8 @@ hobi_status hobi_get_stats(hobi_problem pb, hobi_stats* out) {
     pb->last.ms_krylov = pb->ms[T_KRYLOV];
     pb->last.ms_field_kernel = pb->ms[T_FIELD];
     pb->last.field_launches = pb->cnt[T_FIELD];
+    pb->last.tree_far_pairs = pb->d.tree.nfar;
+    pb->last.tree_near_pairs = pb->d.tree.on ? (int64_t)pb->d.tree.nbatch * pb->d.tree.ncl - pb->d.tree.nfar : 0;
     *out = pb->last;
     return st;
 }

@@ -46,6 +46,36 @@ struct PairPlan {
     const int* gstart;  // device [groups + 1]: node range of group g is [gstart[g], gstart[g + 1])
 };
 
+// Treecode form of the regular sum (hobi_params.tree_theta > 0; higher-order method).  The
+// partition is geometric and built once at problem creation; the proxy charges depend on u
+// and are rebuilt by every matvec.
+constexpr int kTreeMaxDeg = 7;       // (n + 1)^3 <= 512 proxies per cluster
+constexpr int kTreeBatch = 512;      // targets per batch of the acceptance test
+constexpr double kTreeGrow = 1e-6;   // proxy box = node box grown by this fraction of its diagonal (+ 1e-12 A)
+struct ProxyD {                      // proxy point and its three charges (64 B)
+    double x, y, z, q0, qk, qk2, pad0, pad1;
+};
+struct ProxyF {                      // FP32 copy in the frame of the FP32 node records (32 B):
+    float x, y, z;                   // positions shifted and scaled like the targets
+    float q0a, qka;                  // s32 Q0, s32 Qk           (row 1)
+    float q0b, qk2b, pad;            // s32^2 Q0, s32^2 Qk2      (row 2)
+};
+struct TreePlan {
+    int on = 0;
+    int degree = 0, nprox = 0;       // n, (n + 1)^3
+    int leaf = 0, ncl = 0, nbatch = 0;
+    int64_t nfar = 0;                // far (batch, cluster) pairs
+    int2* clu_range = nullptr;       // [ncl] node range of each cluster
+    double* clu_box = nullptr;       // [ncl][6] grown box: lo[3], hi[3]
+    ProxyD* prox64 = nullptr;        // [ncl][nprox]
+    ProxyF* prox32 = nullptr;        // [ncl][nprox]
+    int4* items[2] = {nullptr, nullptr};   // [0] FP64, [1] mixed: {slot, far, cluster, 0}, slot-major
+    int nitems[2] = {0, 0};          // slots * ncl
+    int slot[2] = {0, 0};            // targets per slot
+    int tpl[2] = {0, 0};
+    double* partial = nullptr;       // [nitems][2][slot] (the larger of the two)
+};
+
 struct DeviceProblem {
     // nv counts the collocation sites, which carry the unknowns: the vertices (higher-order
     // method) or the triangles' centroids (lower-order method, then nv = nf and nn = nf)
@@ -84,6 +114,7 @@ struct DeviceProblem {
     GridPlan plan_pts{};
     int* plan_tab = nullptr;                // device group starts of plan64, then of plan32
     size_t partial_elems = 0;
+    TreePlan tree{};
 };
 
 // ---- setup kernels (setup_kernels.hip) ----
@@ -138,6 +169,14 @@ hipError_t launch_field_combine(const DeviceProblem& p, const FieldWork& f, cons
                                 hipStream_t s);
 hipError_t launch_permute(const double* in, double* out, const int* perm, int nv, bool to_internal,
                           hipStream_t s);
+
+// ---- treecode (tree_kernels.hip) ----
+// proxy charges of every cluster (node strengths of u must be gathered, FP64 records)
+hipError_t launch_tree_proxies(const DeviceProblem& p, bool mixed, hipStream_t s);
+// one partial row per work item: near items the masked pair sum, far items the proxies
+hipError_t launch_tree_pairs(const DeviceProblem& p, bool mixed, hipStream_t s);
+// rows of each slot in item order, singular correction and diagonal
+hipError_t launch_tree_combine(const DeviceProblem& p, const double* u, double* y, bool mixed, hipStream_t s);
 
 // ---- Krylov kernels (gmres_kernels.hip) ----
 constexpr int kDotBlocks = 64;

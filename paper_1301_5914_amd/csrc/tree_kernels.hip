@@ -1,0 +1,411 @@
+// Treecode matvec (optional, hobi_params.tree_theta > 0): the dense regular sum of the
+// pair kernels replaced by a single-level cluster-particle treecode.  The partition (built
+// on the host at problem creation): node clusters = consecutive runs of `leaf` nodes in
+// Morton order, target batches = consecutive runs of 512 targets; a (batch, cluster) pair
+// is far when (rb + rc) <= theta |cb - cc| and no target of the batch is a vertex of a
+// triangle of the cluster, else near.  Per matvec, after the gather:
+//
+//   proxy_kernel   -- per cluster, the (n+1)^3 Chebyshev points of its box (grown by
+//                     1e-6 of the diagonal) and three charges per point,
+//                       Q0  = sum_j  Gamma_j L_k(y_j) - Phi_j grad L_k(y_j).n_j
+//                       Qk  = sum_j -Gamma_j L_k(y_j) + eps Phi_j grad L_k(y_j).n_j
+//                       Qk2 = sum_j -Gamma_j L_k(y_j) / eps + Phi_j grad L_k(y_j).n_j
+//                     (L_k the tensor Lagrange basis, product form): the Green's functions
+//                     interpolated in the source point, so that a far cluster's two rows
+//                     are sum_k G0 Q0 + Gk Qk and sum_k dG0/dnu_x Q0 + dGk/dnu_x Qk2 at s_k
+//   tree_*_kernel  -- one wave per work item (slot of targets, cluster): near items run the
+//                     masked pair loop over the cluster's nodes, far items the proxies;
+//                     each item writes one partial row
+//   tree_combine   -- a slot's rows in item order, then the singular correction and the
+//                     diagonal (as combine_tile).
+#include "hobi_internal.h"
+#include "pair_tile.h"
+
+namespace hobi {
+
+namespace {
+
+constexpr int kBlock = kPairBlock;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kChunk = 16;          // nodes per LDS round of the proxy kernel
+
+__device__ __forceinline__ int xcd_logical_block() {
+    const int nb = gridDim.x, p = blockIdx.x;
+    const int x = p & 7, q = nb >> 3, rm = nb & 7;
+    return x * q + min(x, rm) + (p >> 3);
+}
+
+// One block per cluster.  Each round puts l_a(y_d) and l_a'(y_d) of kChunk nodes (every
+// dimension d and index a) into LDS; then thread k accumulates the charges of proxies k and
+// k + kBlock over the round's nodes in node order.
+__global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__ nodes,
+                                                       const int2* __restrict__ clu_range,
+                                                       const double* __restrict__ clu_box, int n, double eps,
+                                                       ProxyD* __restrict__ prox64, ProxyF* __restrict__ prox32,
+                                                       int mixed, double s32, double cx, double cy, double cz) {
+    __shared__ double pt[3][kTreeMaxDeg + 1];
+    __shared__ double lv[kChunk][3][kTreeMaxDeg + 1];
+    __shared__ double dv[kChunk][3][kTreeMaxDeg + 1];
+    __shared__ double ng[kChunk], np_[kChunk], nn3[kChunk][3];
+    const int c = blockIdx.x;
+    const int n1 = n + 1, P = n1 * n1 * n1;
+    const int2 rg = clu_range[c];
+    const double* box = clu_box + 6 * (size_t)c;
+    if (threadIdx.x < 3 * n1) {
+        const int d = threadIdx.x / n1, a = threadIdx.x % n1;
+        const double lo = box[d], hi = box[3 + d];
+        pt[d][a] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * cos(kPi * a / n);
+    }
+    __syncthreads();
+    double q0[2] = {0.0, 0.0}, qk[2] = {0.0, 0.0}, qk2[2] = {0.0, 0.0};
+    int ka[2], kb[2], kc[2];
+    for (int h = 0; h < 2; ++h) {
+        const int k = threadIdx.x + h * kBlock;
+        ka[h] = k / (n1 * n1);
+        kb[h] = (k / n1) % n1;
+        kc[h] = k % n1;
+    }
+    for (int j0 = rg.x; j0 < rg.y; j0 += kChunk) {
+        const int m = min(kChunk, rg.y - j0);
+        for (int e = threadIdx.x; e < 3 * n1 * m; e += kBlock) {
+            const int i = e / (3 * n1), d = (e / n1) % 3, a = e % n1;
+            const NodeD& nd = nodes[j0 + i];
+            const double t = d == 0 ? nd.x : (d == 1 ? nd.y : nd.z);
+            double l = 1.0, dl = 0.0;
+            for (int b = 0; b < n1; ++b) {
+                if (b == a) continue;
+                const double f = (t - pt[d][b]) / (pt[d][a] - pt[d][b]);
+                dl = dl * f + l / (pt[d][a] - pt[d][b]);   // product rule, running
+                l *= f;
+            }
+            lv[i][d][a] = l;
+            dv[i][d][a] = dl;
+        }
+        if ((int)threadIdx.x < m) {
+            const NodeD& nd = nodes[j0 + threadIdx.x];
+            ng[threadIdx.x] = nd.g;
+            np_[threadIdx.x] = nd.p;
+            nn3[threadIdx.x][0] = nd.nx;
+            nn3[threadIdx.x][1] = nd.ny;
+            nn3[threadIdx.x][2] = nd.nz;
+        }
+        __syncthreads();
+        for (int h = 0; h < 2; ++h) {
+            if ((int)threadIdx.x + h * kBlock >= P) continue;
+            for (int i = 0; i < m; ++i) {
+                const double la = lv[i][0][ka[h]], lb = lv[i][1][kb[h]], lc = lv[i][2][kc[h]];
+                const double L = la * lb * lc;
+                const double G = dv[i][0][ka[h]] * lb * lc * nn3[i][0] + la * dv[i][1][kb[h]] * lc * nn3[i][1] +
+                                 la * lb * dv[i][2][kc[h]] * nn3[i][2];
+                const double gL = ng[i] * L, pG = np_[i] * G;
+                q0[h] += gL - pG;
+                qk[h] += -gL + eps * pG;
+                qk2[h] += -gL / eps + pG;
+            }
+        }
+        __syncthreads();
+    }
+    for (int h = 0; h < 2; ++h) {
+        const int k = threadIdx.x + h * kBlock;
+        if (k >= P) continue;
+        ProxyD pd{};
+        pd.x = pt[0][ka[h]];
+        pd.y = pt[1][kb[h]];
+        pd.z = pt[2][kc[h]];
+        pd.q0 = q0[h];
+        pd.qk = qk[h];
+        pd.qk2 = qk2[h];
+        prox64[(size_t)c * P + k] = pd;
+        if (mixed) {
+            ProxyF pf{};
+            pf.x = (float)((pd.x - cx) * s32);
+            pf.y = (float)((pd.y - cy) * s32);
+            pf.z = (float)((pd.z - cz) * s32);
+            pf.q0a = (float)(s32 * q0[h]);
+            pf.qka = (float)(s32 * qk[h]);
+            pf.q0b = (float)(s32 * s32 * q0[h]);
+            pf.qk2b = (float)(s32 * s32 * qk2[h]);
+            prox32[(size_t)c * P + k] = pf;
+        }
+    }
+}
+
+__device__ __forceinline__ ProxyF load_proxy(const const_as<ProxyF>* p, int k) {
+    ProxyF r;
+    r.x = p[k].x, r.y = p[k].y, r.z = p[k].z, r.q0a = p[k].q0a;
+    r.qka = p[k].qka, r.q0b = p[k].q0b, r.qk2b = p[k].qk2b, r.pad = 0.0f;
+    return r;
+}
+
+__device__ __forceinline__ ProxyD load_proxy(const const_as<ProxyD>* p, int k) {
+    ProxyD r;
+    r.x = p[k].x, r.y = p[k].y, r.z = p[k].z, r.q0 = p[k].q0, r.qk = p[k].qk, r.qk2 = p[k].qk2;
+    r.pad0 = r.pad1 = 0.0;
+    return r;
+}
+
+// FP32 far item: the kWave * TPL targets from `base` (scaled frame) against the cluster's
+// proxies; FP32 running sums folded into FP64 every kFold proxies.
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void far_f32_wave(const float* __restrict__ tgt, int nv_pad,
+                                             const ProxyF* __restrict__ prox, int P, int base,
+                                             double* __restrict__ prow, int slot) {
+    constexpr float kLn2 = 0.693147180559945309f;
+    const int lane = (int)(threadIdx.x % kWave);
+    float tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL];
+    double d1[TPL], d2[TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+        const int t = base + lane + k * kWave;
+        tx[k] = tgt[t];
+        ty[k] = tgt[(size_t)nv_pad + t];
+        tz[k] = tgt[2 * (size_t)nv_pad + t];
+        tnx[k] = tgt[3 * (size_t)nv_pad + t];
+        tny[k] = tgt[4 * (size_t)nv_pad + t];
+        tnz[k] = tgt[5 * (size_t)nv_pad + t];
+        d1[k] = d2[k] = 0.0;
+    }
+    const const_as<ProxyF>* cp = as_constant(prox);
+    for (int k0 = 0; k0 < P; k0 += kFold) {
+        const int k1 = min(k0 + kFold, P);
+        float a1[TPL], a2[TPL];
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) a1[k] = a2[k] = 0.0f;
+        for (int q = k0; q < k1; ++q) {
+            const ProxyF pr = load_proxy(cp, q);
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) {
+                const float dx = tx[k] - pr.x, dy = ty[k] - pr.y, dz = tz[k] - pr.z;
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                const float dnx = fmaf(dx, tnx[k], fmaf(dy, tny[k], dz * tnz[k]));
+                const float rinv3 = rinv * rinv * rinv;
+                if (KAPPA0) {
+                    a1[k] = fmaf(rinv, pr.q0a + pr.qka, a1[k]);
+                    a2[k] = fmaf(-rinv3 * dnx, pr.q0b + pr.qk2b, a2[k]);
+                } else {
+                    const float r = r2 * rinv;
+                    const float e = __builtin_amdgcn_exp2f(-r);           // exp(-kappa r)
+                    const float zp1 = fmaf(r, kLn2, 1.0f);               // 1 + kappa r
+                    a1[k] = fmaf(rinv, fmaf(e, pr.qka, pr.q0a), a1[k]);
+                    a2[k] = fmaf(-rinv3 * dnx, fmaf(e * zp1, pr.qk2b, pr.q0b), a2[k]);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+            d1[k] += (double)a1[k];
+            d2[k] += (double)a2[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+        prow[lane + k * kWave] = d1[k];
+        prow[slot + lane + k * kWave] = d2[k];
+    }
+}
+
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void far_f32_narrow(int live, const float* __restrict__ tgt, int nv_pad,
+                                               const ProxyF* __restrict__ prox, int P, int base,
+                                               double* __restrict__ prow, int slot) {
+    if constexpr (TPL > 1) {
+        if (live <= kWave * TPL / 2) {
+            far_f32_narrow<TPL / 2, KAPPA0>(live, tgt, nv_pad, prox, P, base, prow, slot);
+            return;
+        }
+    }
+    far_f32_wave<TPL, KAPPA0>(tgt, nv_pad, prox, P, base, prow, slot);
+}
+
+// FP64 far item (unscaled frame).
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void far_f64_wave(const double* __restrict__ tgt, int nv_pad,
+                                             const ProxyD* __restrict__ prox, int P, double kappa, int base,
+                                             double* __restrict__ prow, int slot) {
+    const int lane = (int)(threadIdx.x % kWave);
+    double tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL], a1[TPL], a2[TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+        const int t = base + lane + k * kWave;
+        tx[k] = tgt[t];
+        ty[k] = tgt[(size_t)nv_pad + t];
+        tz[k] = tgt[2 * (size_t)nv_pad + t];
+        tnx[k] = tgt[3 * (size_t)nv_pad + t];
+        tny[k] = tgt[4 * (size_t)nv_pad + t];
+        tnz[k] = tgt[5 * (size_t)nv_pad + t];
+        a1[k] = a2[k] = 0.0;
+    }
+    const const_as<ProxyD>* cp = as_constant(prox);
+    for (int q = 0; q < P; ++q) {
+        const ProxyD pr = load_proxy(cp, q);
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+            const double dx = tx[k] - pr.x, dy = ty[k] - pr.y, dz = tz[k] - pr.z;
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            const double rinv = rsqrt_f64(r2);
+            const double dnx = fma(dx, tnx[k], fma(dy, tny[k], dz * tnz[k]));
+            const double rinv3 = rinv * rinv * rinv;
+            if (KAPPA0) {
+                a1[k] = fma(rinv, pr.q0 + pr.qk, a1[k]);
+                a2[k] = fma(-rinv3 * dnx, pr.q0 + pr.qk2, a2[k]);
+            } else {
+                const double z = kappa * (r2 * rinv);
+                const double e = exp_neg_f64(z);
+                a1[k] = fma(rinv, fma(e, pr.qk, pr.q0), a1[k]);
+                a2[k] = fma(-rinv3 * dnx, fma(e * (1.0 + z), pr.qk2, pr.q0), a2[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+        prow[lane + k * kWave] = a1[k];
+        prow[slot + lane + k * kWave] = a2[k];
+    }
+}
+
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void far_f64_narrow(int live, const double* __restrict__ tgt, int nv_pad,
+                                               const ProxyD* __restrict__ prox, int P, double kappa, int base,
+                                               double* __restrict__ prow, int slot) {
+    if constexpr (TPL > 1) {
+        if (live <= kWave * TPL / 2) {
+            far_f64_narrow<TPL / 2, KAPPA0>(live, tgt, nv_pad, prox, P, kappa, base, prow, slot);
+            return;
+        }
+    }
+    far_f64_wave<TPL, KAPPA0>(tgt, nv_pad, prox, P, kappa, base, prow, slot);
+}
+
+// One wave per work item {slot, kind, cluster, -}: the item's partial row is its index.
+template <int TPL, bool KAPPA0>
+__global__ __launch_bounds__(kBlock) void tree_f32_kernel(
+    const int4* __restrict__ items, int nitems, const float* __restrict__ tgt, int nv, int nv_pad,
+    const NodeF* __restrict__ nodes, const int4* __restrict__ node_vid, const int2* __restrict__ blk_range,
+    const int2* __restrict__ clu_range, const ProxyF* __restrict__ prox, int P, double* __restrict__ partial) {
+    const int w = xcd_logical_block() * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    if (w >= nitems) return;
+    constexpr int kSlot = kWave * TPL;
+    const int4 it = make_int4(as_constant(items)[w].x, as_constant(items)[w].y, as_constant(items)[w].z, 0);
+    const int base = it.x * kSlot;
+    double* prow = partial + (size_t)w * (2 * kSlot);
+    if (it.y == 0) {
+        const int n0 = as_constant(clu_range)[it.z].x, n1 = as_constant(clu_range)[it.z].y;
+        pair_f32_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, nodes, node_vid, blk_range, base, n0, n1, prow, kSlot);
+    } else {
+        far_f32_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, prox + (size_t)it.z * P, P, base, prow, kSlot);
+    }
+}
+
+template <int TPL, bool KAPPA0>
+__global__ __launch_bounds__(kBlock) void tree_f64_kernel(
+    const int4* __restrict__ items, int nitems, const double* __restrict__ tgt, int nv, int nv_pad,
+    const NodeD* __restrict__ nodes, const int4* __restrict__ node_vid, const int2* __restrict__ blk_range,
+    const int2* __restrict__ clu_range, const ProxyD* __restrict__ prox, int P, double kappa, double eps,
+    double* __restrict__ partial) {
+    const int w = xcd_logical_block() * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    if (w >= nitems) return;
+    constexpr int kSlot = kWave * TPL;
+    const int4 it = make_int4(as_constant(items)[w].x, as_constant(items)[w].y, as_constant(items)[w].z, 0);
+    const int base = it.x * kSlot;
+    double* prow = partial + (size_t)w * (2 * kSlot);
+    if (it.y == 0) {
+        const int n0 = as_constant(clu_range)[it.z].x, n1 = as_constant(clu_range)[it.z].y;
+        pair_f64_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, nodes, node_vid, blk_range, kappa, eps, base, n0, n1,
+                                     prow, kSlot);
+    } else {
+        far_f64_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, prox + (size_t)it.z * P, P, kappa, base, prow, kSlot);
+    }
+}
+
+// Rows (i, i + nv) for the kCombineVerts targets of tile vb: the ncl rows of their slot
+// s (items s ncl .. s ncl + ncl - 1; wave k sums rows k, k + 4, ..., the four sums added in
+// a fixed order), then the singular correction and the diagonal.
+__global__ __launch_bounds__(kBlock) void tree_combine_kernel(
+    const double* __restrict__ u, double* __restrict__ y, int nv, const double* __restrict__ partial, int slot,
+    int ncl, const int* __restrict__ inc_off, const int* __restrict__ inc_ent, const int* __restrict__ tri,
+    const double* __restrict__ coef, double eps) {
+    __shared__ double red[2][4][kCombineVerts];
+    const int vb = blockIdx.x;
+    const int lane = threadIdx.x % kCombineVerts, way = threadIdx.x / kCombineVerts;
+    const int i = vb * kCombineVerts + lane;
+    const int s = vb * kCombineVerts / slot, o = i - s * slot;
+    const int rb = s * ncl, re = rb + ncl;
+    double r1 = 0.0, r2 = 0.0;
+    if (i < nv) {
+        for (int r = rb + way; r < re; r += 4) {
+            r1 += partial[(size_t)(2 * r) * slot + o];
+            r2 += partial[(size_t)(2 * r + 1) * slot + o];
+        }
+    }
+    red[0][way][lane] = r1;
+    red[1][way][lane] = r2;
+    __syncthreads();
+    if (way != 0 || i >= nv) return;
+    r1 = (red[0][0][lane] + red[0][1][lane]) + (red[0][2][lane] + red[0][3][lane]);
+    r2 = (red[1][0][lane] + red[1][1][lane]) + (red[1][2][lane] + red[1][3][lane]);
+    double c1 = 0.0, c2 = 0.0;
+    for (int e = inc_off[i]; e < inc_off[i + 1]; ++e) {
+        const int ent = inc_ent[e];
+        const int j = ent / 3, k = ent - 3 * (ent / 3);
+        const double* co = coef + 12 * (size_t)ent;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const int v = tri[3 * j + (k + b) % 3];
+            const double ph = u[v], dp = u[nv + v];
+            c1 += co[b] * dp + co[3 + b] * ph;
+            c2 += co[6 + b] * dp + co[9 + b] * ph;
+        }
+    }
+    y[i] = 0.5 * (1.0 + eps) * u[i] - r1 - c1;
+    y[nv + i] = 0.5 * (1.0 + 1.0 / eps) * u[nv + i] - r2 - c2;
+}
+
+inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_tree_proxies(const DeviceProblem& p, bool mixed, hipStream_t s) {
+    const TreePlan& t = p.tree;
+    hipLaunchKernelGGL(proxy_kernel, dim3(t.ncl), dim3(kBlock), 0, s, p.node64, t.clu_range, t.clu_box, t.degree,
+                       p.eps, t.prox64, t.prox32, mixed ? 1 : 0, p.s32, p.center[0], p.center[1], p.center[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_pairs(const DeviceProblem& p, bool mixed, hipStream_t s) {
+    const TreePlan& t = p.tree;
+    const bool k0 = p.kappa == 0.0;
+    const int m = mixed ? 1 : 0;
+    const dim3 grid(nblk(t.nitems[m], kWavesPerBlock));
+    if (mixed) {
+#define HOBI_TREE32(T, K0)                                                                                       \
+    hipLaunchKernelGGL((tree_f32_kernel<T, K0>), grid, dim3(kBlock), 0, s, t.items[1], t.nitems[1], p.tgt32, p.nv, \
+                       p.nv_pad, p.node32, p.node_vid, p.blk_range, t.clu_range, t.prox32, t.nprox, t.partial)
+        if (t.tpl[1] == 8) {
+            if (k0) HOBI_TREE32(8, true); else HOBI_TREE32(8, false);
+        } else {
+            if (k0) HOBI_TREE32(4, true); else HOBI_TREE32(4, false);
+        }
+#undef HOBI_TREE32
+    } else {
+        if (k0)
+            hipLaunchKernelGGL((tree_f64_kernel<kTpl64, true>), grid, dim3(kBlock), 0, s, t.items[0], t.nitems[0],
+                               p.tgt64, p.nv, p.nv_pad, p.node64, p.node_vid, p.blk_range, t.clu_range, t.prox64,
+                               t.nprox, p.kappa, p.eps, t.partial);
+        else
+            hipLaunchKernelGGL((tree_f64_kernel<kTpl64, false>), grid, dim3(kBlock), 0, s, t.items[0], t.nitems[0],
+                               p.tgt64, p.nv, p.nv_pad, p.node64, p.node_vid, p.blk_range, t.clu_range, t.prox64,
+                               t.nprox, p.kappa, p.eps, t.partial);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_combine(const DeviceProblem& p, const double* u, double* y, bool mixed, hipStream_t s) {
+    const TreePlan& t = p.tree;
+    const int m = mixed ? 1 : 0;
+    hipLaunchKernelGGL(tree_combine_kernel, dim3(nblk(p.nv, kCombineVerts)), dim3(kBlock), 0, s, u, y, p.nv,
+                       t.partial, t.slot[m], t.ncl, p.inc_off, p.inc_ent, p.tri, p.coef, p.eps);
+    return hipGetLastError();
+}
+
+}  // namespace hobi

@@ -39,7 +39,8 @@ class HobiError(RuntimeError):
 class hobi_params(ctypes.Structure):
     _fields_ = [("eps1", ctypes.c_double), ("eps2", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("method", ctypes.c_int32), ("diag_scaling", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("method", ctypes.c_int32), ("diag_scaling", ctypes.c_int32),
+                ("tree_theta", ctypes.c_double), ("tree_degree", ctypes.c_int32), ("tree_leaf", ctypes.c_int32)]
 
 
 class hobi_stats(ctypes.Structure):
@@ -50,7 +51,8 @@ class hobi_stats(ctypes.Structure):
                 ("ms_pair_kernel", ctypes.c_double), ("pair_launches", ctypes.c_int64),
                 ("ms_gather", ctypes.c_double), ("ms_combine", ctypes.c_double),
                 ("ms_krylov", ctypes.c_double), ("ms_field_kernel", ctypes.c_double),
-                ("field_launches", ctypes.c_int64)]
+                ("field_launches", ctypes.c_int64), ("tree_far_pairs", ctypes.c_int64),
+                ("tree_near_pairs", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -185,7 +187,7 @@ class Problem:
 
     def __init__(self, ctx: Context, xyz, nrm, tri, qpos, q, eps1=1.0, eps2=80.0, kappa=0.1257,
                  rtol=1e-6, max_iter=200, restart=200, precision=HOBI_FP64, method=HOBI_HIGHER_ORDER,
-                 diag_scaling=1):
+                 diag_scaling=1, tree_theta=0.0, tree_degree=5, tree_leaf=1024):
         self.ctx = ctx
         xyz = _f64(xyz).reshape(-1, 3)
         nrm = _f64(nrm).reshape(-1, 3)
@@ -200,6 +202,7 @@ class Problem:
         p.eps1, p.eps2, p.kappa, p.rtol = eps1, eps2, kappa, rtol
         p.max_iter, p.restart, p.precision, p.method = max_iter, restart, precision, method
         p.diag_scaling = diag_scaling
+        p.tree_theta, p.tree_degree, p.tree_leaf = tree_theta, tree_degree, tree_leaf
         h = _P()
         st = lib().hobi_problem_create(ctx.handle, self.nv, _dptr(xyz), _dptr(nrm), self.nf,
                                        tri.ctypes.data_as(_I), self.nc, _dptr(qpos), _dptr(q),

@@ -1,0 +1,141 @@
+"""GPU parity of the treecode form of the matvec (hobi_params.tree_theta > 0) through the
+C ABI against the treecode oracle (oracle/treecode.py) on the same seeded inputs and the
+same partition: FP64 to 1e-12 and mixed to 1e-5 of the largest row, the far-pair count
+exactly.  With every pair near the treecode is the dense matvec; at full size it stays
+within its interpolation error of the dense matvec and solve.  Parameter errors."""
+import ctypes
+import importlib.util
+import os
+
+import numpy as np
+import pytest
+
+from oracle import operator as O
+from oracle import treecode as T
+from paper_1301_5914_amd import hobi, inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+_spec = importlib.util.spec_from_file_location("make_tree_golden", os.path.join(GOLDEN, "make_tree_golden.py"))
+G = importlib.util.module_from_spec(_spec)
+_spec.loader.exec_module(G)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return hobi.Context(0)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _check_case(ctx, p, theta, degree, leaf, u, ref, nfar, name):
+    print(f"tree case {name} nv={p.nv} far pairs {nfar}", flush=True)
+    assert nfar > 0
+    for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
+        g = hobi.Problem.from_inputs(ctx, p, precision=prec, tree_theta=theta, tree_degree=degree, tree_leaf=leaf)
+        s = g.stats()
+        assert s["tree_far_pairs"] == nfar
+        nb, nc = -(-p.nv // 512), -(-4 * p.nf // leaf)
+        assert s["tree_far_pairs"] + s["tree_near_pairs"] == nb * nc
+        err = _rel(g.matvec(u), ref)
+        print(f"  precision {prec} rel err {err:.3e}", flush=True)
+        assert err <= tol, (name, prec, err)
+
+
+@pytest.mark.parametrize("name", list(G.CASES))
+def test_tree_matvec_matches_stored_oracle_treecode(ctx, name):
+    """Several batches with a far/near mix and ragged last batch and cluster (kappa = 0
+    takes the Laplace branch); expected values written by tests/golden/make_tree_golden.py
+    from the oracle."""
+    recipe, theta, degree, leaf = G.CASES[name]
+    ref = np.load(os.path.join(GOLDEN, f"tree_{name}.npz"))
+    assert (float(ref["theta"]), int(ref["degree"]), int(ref["leaf"])) == (theta, degree, leaf)
+    p = G.surface(recipe)
+    u = inputs.random_vector(2 * p.nv, int(ref["seed"]))
+    _check_case(ctx, p, theta, degree, leaf, u, ref["y"], int(ref["nfar"]), name)
+
+
+def test_tree_matvec_matches_oracle_treecode_L3(ctx):
+    """Smallest clusters (64 nodes), degree 5, kappa = 1: the oracle run live."""
+    p = inputs.kirkwood_offcenter(3, kappa=1.0, eps1=4.0)
+    theta, degree, leaf = 0.9, 5, 64
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    u = inputs.random_vector(2 * p.nv, 25)
+    ref, nfar = T.matvec(st, u, p.kappa, p.eps2 / p.eps1, theta=theta, degree=degree, leaf=leaf, batch=512)
+    _check_case(ctx, p, theta, degree, leaf, u, ref, nfar, "L3_k1_n5_leaf64")
+
+
+def test_all_near_is_the_dense_matvec(ctx):
+    """An opening parameter so small that no pair is far: the dense sum, cluster by
+    cluster (FP64 to 1e-12 of the oracle's dense matvec, mixed to 1e-5)."""
+    p = inputs.kirkwood_offcenter(3)
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    u = inputs.random_vector(2 * p.nv, 22)
+    ref = O.matvec(st, u, p.kappa, p.eps2 / p.eps1)
+    for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
+        g = hobi.Problem.from_inputs(ctx, p, precision=prec, tree_theta=1e-9, tree_leaf=128)
+        assert g.stats()["tree_far_pairs"] == 0
+        assert _rel(g.matvec(u), ref) <= tol
+
+
+def test_tree_is_deterministic_and_precision_switch(ctx):
+    p = inputs.kirkwood_offcenter(4)
+    g = hobi.Problem.from_inputs(ctx, p, tree_theta=0.6, tree_degree=4, tree_leaf=256)
+    u = inputs.random_vector(2 * p.nv, 23)
+    y64 = g.matvec(u)
+    assert np.array_equal(y64, g.matvec(u))
+    g.set_precision(hobi.HOBI_MIXED)
+    y32 = g.matvec(u)
+    assert np.array_equal(y32, g.matvec(u))
+    assert _rel(y32, y64) <= 1e-5
+
+
+def test_bench_workload_L6_tree_against_dense(ctx):
+    """The default bench surface at full size (40962 targets, 327680 nodes): the treecode
+    matvec (theta 0.5, degree 5) within 1e-4 of the dense one, FP64 and mixed treecode
+    within 1e-5 of each other, and the solve's energy within 1e-4 of the dense solve's."""
+    p = inputs.kirkwood_offcenter(6)
+    u = inputs.random_vector(2 * p.nv, 24)
+    dense = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED)
+    tree = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED, tree_theta=0.5, tree_degree=5)
+    s = tree.stats()
+    print(f"L6 tree far {s['tree_far_pairs']} near {s['tree_near_pairs']}", flush=True)
+    assert s["tree_far_pairs"] > 0
+    yd = dense.matvec(u)
+    yt = tree.matvec(u)
+    err = _rel(yt, yd)
+    print(f"L6 tree vs dense rel err {err:.3e}", flush=True)
+    assert err <= 1e-4
+    tree.set_precision(hobi.HOBI_FP64)
+    assert _rel(tree.matvec(u), yt) <= 1e-5
+    tree.set_precision(hobi.HOBI_MIXED)
+    ed = dense.solve()["energy"]
+    et = tree.solve()["energy"]
+    print(f"L6 energy dense {ed:.8f} tree {et:.8f}", flush=True)
+    assert abs(et - ed) <= 1e-4 * abs(ed)
+
+
+def test_tree_parameter_errors(ctx):
+    p = inputs.kirkwood_offcenter(2)
+    bad = [dict(tree_theta=-0.1), dict(tree_theta=float("nan")), dict(tree_theta=0.5, tree_degree=0),
+           dict(tree_theta=0.5, tree_degree=8), dict(tree_theta=0.5, tree_leaf=100),
+           dict(tree_theta=0.5, tree_leaf=0), dict(tree_theta=0.5, method=hobi.HOBI_LOWER_ORDER)]
+    for kw in bad:
+        with pytest.raises(hobi.HobiError) as e:
+            hobi.Problem.from_inputs(ctx, p, **kw)
+        assert e.value.status == 1, kw
+    sv = hobi.Server(ctx, hbm_budget_bytes=1 << 30, max_slots=2)
+    params = hobi.hobi_params_default()
+    params.tree_theta = 0.5
+    tk = ctypes.c_uint64()
+    xyz, nrm = np.ascontiguousarray(p.xyz), np.ascontiguousarray(p.nrm)
+    tri = np.ascontiguousarray(p.tri.astype(np.int32))
+    qpos, q = np.ascontiguousarray(p.qpos), np.ascontiguousarray(p.q)
+    st = hobi.lib().hobi_server_submit(sv.handle, p.nv, hobi._dptr(xyz), hobi._dptr(nrm), p.nf,
+                                       tri.ctypes.data_as(hobi._I), len(q), hobi._dptr(qpos), hobi._dptr(q),
+                                       ctypes.byref(params), ctypes.byref(tk))
+    assert st == 1
+    sv.close()
