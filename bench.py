@@ -134,14 +134,15 @@ def field_bench(pb, prob, grid, res, mixed, n_nodes):
             "energy_from_field_rel": abs(e_field / res["energy"] - 1)}
 
 
-def tree_bench(ctx, stream, prob, theta, degree, leaf, mixed, dense_pb, dense_res, dense_mv_ms, pairs_mv):
+def tree_bench(ctx, stream, prob, theta, degree, leaf, batch, mixed, dense_pb, dense_res, dense_mv_ms, pairs_mv):
     """The treecode form of the matvec on the same problem: matvec time (HIP events, median
     of 20), the dense pair count it replaces per second, its error against the dense matvec
     on a random vector, and the solve with it against the dense solve."""
     import torch
     from paper_1301_5914_amd import hobi
     pb = hobi.Problem.from_inputs(ctx, prob, precision=hobi.HOBI_MIXED if mixed else hobi.HOBI_FP64,
-                                  tree_theta=theta, tree_degree=degree, tree_leaf=leaf, max_iter=400, restart=400)
+                                  tree_theta=theta, tree_degree=degree, tree_leaf=leaf, tree_batch=batch,
+                                  max_iter=400, restart=400)
     st = pb.stats()
     u = torch.randn(2 * prob.nv, dtype=torch.float64, device="cuda")
     yt = torch.empty_like(u)
@@ -162,7 +163,7 @@ def tree_bench(ctx, stream, prob, theta, degree, leaf, mixed, dense_pb, dense_re
     pb.solve()                                        # warm-up
     res = [pb.solve() for _ in range(2)]
     mv = float(np.median(ms))
-    return {"theta": theta, "degree": degree, "leaf": leaf,
+    return {"theta": theta, "degree": degree, "leaf": leaf, "batch": batch,
             "far_pairs": st["tree_far_pairs"], "near_pairs": st["tree_near_pairs"],
             "matvec_ms_median": mv, "dense_matvec_ms_median": dense_mv_ms,
             "speedup_over_dense_matvec": dense_mv_ms / mv,
@@ -312,10 +313,11 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--field-map", type=int, default=64,
                     help="potential map of grid^3 points after the timed steps (hobi_field); 0 = off")
-    ap.add_argument("--tree-theta", type=float, default=0.5,
+    ap.add_argument("--tree-theta", type=float, default=0.7,
                     help="also time the treecode matvec and solve with this opening parameter (0: skip)")
     ap.add_argument("--tree-degree", type=int, default=5)
-    ap.add_argument("--tree-leaf", type=int, default=1024)
+    ap.add_argument("--tree-leaf", type=int, default=256)
+    ap.add_argument("--tree-batch", type=int, default=128)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -428,7 +430,8 @@ def main():
     if args.field_map > 0:
         out["field"] = field_bench(pb, prob, args.field_map, results[-1], mixed, n_nodes)
     if args.tree_theta > 0 and not lower:
-        out["tree"] = tree_bench(ctx, stream, prob, args.tree_theta, args.tree_degree, args.tree_leaf, mixed, pb,
+        out["tree"] = tree_bench(ctx, stream, prob, args.tree_theta, args.tree_degree, args.tree_leaf,
+                                 args.tree_batch, mixed, pb,
                                  results[-1], out["matvec_ms_median"], pairs_mv)
     if not args.no_compare:
         # the other precision on the same problem (outside the timed region)

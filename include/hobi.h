@@ -84,16 +84,19 @@ typedef struct hobi_params {
                         /* 1/(1/2 (1+eps)) and 1/(1/2 (1+1/eps)); same solution, the monitored */
                         /* residual is still ||b - A u|| / ||b||); 0: on A u = b as written  */
     /* Treecode form of the regular (dense) sum, higher-order method only.  0 (default):
-     * the dense sum.  > 0: a single-level cluster-particle treecode with opening parameter
-     * tree_theta.  Quadrature nodes in order are cut into clusters of tree_leaf nodes, the
-     * target vertices into batches of 512; a (batch, cluster) pair whose bounding spheres
-     * satisfy r_b + r_c <= tree_theta |c_b - c_c| and whose cluster has no triangle incident
-     * to a target of the batch takes the Green's functions interpolated in the source point
-     * on the (tree_degree + 1)^3 Chebyshev points of the cluster's box; every other pair
-     * is summed directly.  The partition is fixed at problem creation.                   */
+     * the dense sum.  > 0: a cluster-particle treecode with opening parameter tree_theta.
+     * The quadrature nodes in order are cut into leaves of tree_leaf nodes, joined pairwise
+     * level by level into a binary cluster tree; the target vertices in order into batches
+     * of tree_batch.  Each batch walks the tree from the root: a cluster whose bounding
+     * sphere and the batch's satisfy r_b + r_c <= tree_theta |c_b - c_c|, and which has no
+     * triangle incident to a target of the batch, is taken by the Green's functions
+     * interpolated in the source point on the (tree_degree + 1)^3 Chebyshev points of its
+     * box; a leaf that fails is summed directly; a parent that fails is opened.  The
+     * partition is fixed at problem creation.                                            */
     double tree_theta;  /* >= 0, default 0                                                  */
     int32_t tree_degree; /* interpolation degree n, 1..7, default 5                        */
-    int32_t tree_leaf;  /* nodes per cluster, a multiple of 64 in [64, 2^24], default 1024  */
+    int32_t tree_leaf;  /* nodes per leaf, a multiple of 64 in [64, 2^24], default 256      */
+    int32_t tree_batch; /* targets per batch: 128, 256 or 512, default 128                  */
 } hobi_params;
 
 typedef struct hobi_stats {
@@ -114,7 +117,7 @@ typedef struct hobi_stats {
     double ms_field_kernel;    /* pair sums of hobi_field (R, its gradient, solid angle)     */
     int64_t field_launches;
     int64_t tree_far_pairs;    /* treecode: (batch, cluster) pairs taken by the proxies      */
-    int64_t tree_near_pairs;   /* and summed directly (both 0 without the treecode)          */
+    int64_t tree_near_pairs;   /* and (batch, leaf) pairs summed directly (0 without it)     */
 } hobi_stats;
 
 /* Fills p with the defaults listed in hobi_params. */

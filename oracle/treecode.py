@@ -4,22 +4,28 @@ Test infrastructure only: plain numpy FP64; nothing in the product path imports 
 
 The paper's CPU time grows as O(N^2) with the number of elements (Section 3, protein
 1ajj), and it names fast summation (treecode or fast multipole, its refs. on TABI-PB) as
-the way past that.  This module is one such scheme, a single-level cluster-particle
-treecode with polynomial interpolation of the Green's functions in the source point; it
-is the reference the GPU version is checked against, both taking the same partition and
-rules, written out here:
+the way past that.  This module is one such scheme, a cluster-particle treecode over a
+binary cluster tree with polynomial interpolation of the Green's functions in the source
+point; it is the reference the GPU version is checked against, both taking the same
+partition and rules, written out here:
 
 * Order: vertices and triangles in Morton order over the vertices' bounding box: each
   coordinate mapped to [0, 1] by (x - lo) / (hi - lo) (an extent of 0 read as 1), clamped,
   multiplied by 2097151 and truncated to 21 bits; the bits interleaved with x lowest; a
   stable sort (ties keep the input order).  A triangle's position is its vertex
   centroid (a + b + c) / 3; its 4 regular nodes stay together in the rule's order.
-* Clusters: consecutive runs of `leaf` nodes in that order; batches: consecutive runs of
-  `batch` target vertices in vertex order.  Each has the bounding box of its points, its
-  centre and its radius (half the box diagonal).
-* A (batch, cluster) pair is far when rb + rc <= theta |cb - cc| and no target of the
-  batch is a vertex of a triangle of the cluster (so an incident triangle, which belongs
-  to the singular rule, is never approximated); otherwise it is near.
+* Leaves: consecutive runs of `leaf` nodes in that order; batches: consecutive runs of
+  `batch` target vertices in vertex order.  Each cluster and batch has the bounding box of
+  its points, its centre and its radius (half the box diagonal).
+* Cluster tree: the leaves are level 0; level l + 1 joins neighbours 2i and 2i + 1 of level l
+  into one cluster over both node ranges, a last cluster without a neighbour moving up
+  unchanged; the single cluster left is the root.
+* A (batch, cluster) pair is accepted (far) when rb + rc <= theta |cb - cc| and no target of
+  the batch is a vertex of a triangle of the cluster (so an incident triangle, which
+  belongs to the singular rule, is never approximated).  Each batch walks the tree from
+  the root: an accepted cluster is taken by its proxies, a rejected leaf is summed
+  directly (near), a rejected parent is opened into its two children.  The accepted and
+  near clusters of a batch cover every node once.
 * Near pairs: the direct regular sum, incident triangles masked (as operator.matvec).
 * Far pairs: the Green's functions interpolated in the source point y by the tensor
   Lagrange basis L_k on the (n+1)^3 Chebyshev points of the second kind of the cluster's
@@ -33,7 +39,8 @@ rules, written out here:
   the two rows of a far pair are
       sum_k G0(x, s_k) Q0_k + Gk(x, s_k) Qk_k,   sum_k dG0/dnu_x(x, s_k) Q0_k + dGk/dnu_x(x, s_k) Qk2_k
   (K1 = G0 - Gk, K2 = eps dGk/dnu_y - dG0/dnu_y, K3 = dG0/dnu_x - dGk/dnu_x / eps,
-  K4 = d2Gk/dnu_x dnu_y - d2G0/dnu_x dnu_y, eq. Eq_Ls).
+  K4 = d2Gk/dnu_x dnu_y - d2G0/dnu_x dnu_y, eq. Eq_Ls).  The charges of every cluster,
+  parent or leaf, are these sums over its own nodes.
 The singular correction and the diagonal are those of operator.matvec.  theta = 0 makes
 every pair near, and the result is the dense matvec.
 """
@@ -70,9 +77,31 @@ def morton_order(pts, lo, hi):
 class Partition:
     vorder: np.ndarray     # [nv] targets in order (caller's vertex ids)
     torder: np.ndarray     # [nf] triangles in order
-    clusters: list         # (first, last + 1) in ordered node positions
+    clusters: list         # (first, last + 1) in ordered node positions; leaves first
+    children: list         # per cluster: None (leaf) or its two children's indices
+    nleaf: int
     batches: list          # (first, last + 1) in ordered target positions
-    far: np.ndarray        # [nbatch, ncluster] bool
+    far: list              # per batch: accepted cluster indices
+    near: list             # per batch: rejected leaf indices
+
+
+def cluster_tree(nn, leaf):
+    """Clusters (leaves first, then each level's parents) and their children."""
+    clusters = [(a, min(a + leaf, nn)) for a in range(0, nn, leaf)]
+    children = [None] * len(clusters)
+    level = list(range(len(clusters)))
+    while len(level) > 1:
+        up = []
+        for i in range(0, len(level), 2):
+            if i + 1 < len(level):
+                l, r = level[i], level[i + 1]
+                clusters.append((clusters[l][0], clusters[r][1]))
+                children.append((l, r))
+                up.append(len(clusters) - 1)
+            else:
+                up.append(level[i])
+        level = up
+    return clusters, children, level[0]
 
 
 def partition(st: Setup, theta, leaf, batch):
@@ -86,7 +115,8 @@ def partition(st: Setup, theta, leaf, batch):
     y = st.y[torder].reshape(-1, 3)
     tv = vrank[tri[torder]]                       # [nf,3] ordered vertex ranks
     nn = y.shape[0]
-    clusters = [(a, min(a + leaf, nn)) for a in range(0, nn, leaf)]
+    clusters, children, root = cluster_tree(nn, leaf)
+    nleaf = (nn + leaf - 1) // leaf
     batches = [(a, min(a + batch, st.nv)) for a in range(0, st.nv, batch)]
     tx = xyz[vorder]
 
@@ -95,14 +125,24 @@ def partition(st: Setup, theta, leaf, batch):
         return 0.5 * (blo + bhi), 0.5 * np.linalg.norm(bhi - blo)
 
     cs = [sphere(y[a:b]) for a, b in clusters]
-    bs = [sphere(tx[a:b]) for a, b in batches]
-    far = np.zeros((len(batches), len(clusters)), dtype=bool)
-    for i, (a, b) in enumerate(batches):
-        for c, (p, q) in enumerate(clusters):
-            vl, vh = tv[p // 4:(q + 3) // 4].min(), tv[p // 4:(q + 3) // 4].max()
-            touches = vh >= a and vl <= b - 1
-            far[i, c] = (not touches) and bs[i][1] + cs[c][1] <= theta * np.linalg.norm(bs[i][0] - cs[c][0])
-    return Partition(vorder, torder, clusters, batches, far)
+    cv = [(tv[a // 4:(b + 3) // 4].min(), tv[a // 4:(b + 3) // 4].max()) for a, b in clusters]
+    far, near = [], []
+    for a, b in batches:
+        cb, rb = sphere(tx[a:b])
+        fa, ne = [], []
+        stack = [root]
+        while stack:
+            c = stack.pop()
+            touches = cv[c][1] >= a and cv[c][0] <= b - 1
+            if not touches and rb + cs[c][1] <= theta * np.linalg.norm(cb - cs[c][0]):
+                fa.append(c)
+            elif children[c] is None:
+                ne.append(c)
+            else:
+                stack.extend(children[c][::-1])
+        far.append(fa)
+        near.append(ne)
+    return Partition(vorder, torder, clusters, children, nleaf, batches, far, near)
 
 
 def cheb_points(lo, hi, n):
@@ -149,9 +189,9 @@ def proxies(y, ny, gam, phi, eps, n):
     return s, Q0, Qk, Qk2
 
 
-def matvec(st: Setup, u, kappa, eps, theta=0.5, degree=5, leaf=1024, batch=512):
+def matvec(st: Setup, u, kappa, eps, theta=0.5, degree=5, leaf=256, batch=128):
     """y = A u with the regular sum taken by the treecode (singular part and diagonal as
-    operator.matvec), and the count of far (batch, cluster) pairs."""
+    operator.matvec), and the count of accepted (batch, cluster) pairs."""
     nv = st.nv
     u = np.asarray(u, dtype=np.float64)
     phi_v, dphi_v = u[:nv], u[nv:]
@@ -171,25 +211,26 @@ def matvec(st: Setup, u, kappa, eps, theta=0.5, degree=5, leaf=1024, batch=512):
     tree = np.zeros((nv, 2))                      # the treecode's regular sums
     cache = {}
     for i, (a, b) in enumerate(part.batches):
-        for c, (p, q) in enumerate(part.clusters):
-            if part.far[i, c]:
-                if c not in cache:
-                    cache[c] = proxies(y[p:q], ny[p:q], gam[p:q], phn[p:q], eps, degree)
-                s, Q0, Qk, Qk2 = cache[c]
-                for t in range(a, b):
-                    d = tx[t] - s
-                    r = np.linalg.norm(d, axis=1)
-                    e = np.exp(-kappa * r)
-                    dnx = d @ tn[t]
-                    g0 = 1.0 / (FOUR_PI * r)
-                    tree[t, 0] += np.sum(g0 * Q0 + e * g0 * Qk)
-                    tree[t, 1] += np.sum(-dnx / (FOUR_PI * r ** 3) * (Q0 + e * (1.0 + kappa * r) * Qk2))
-            else:
-                for t in range(a, b):
-                    keep = ~np.any(node_tri[p:q] == part.vorder[t], axis=1)
-                    K1, K2, K3, K4 = kernels(tx[t], tn[t], y[p:q][keep], ny[p:q][keep], kappa, eps)
-                    tree[t, 0] += np.sum(K1 * gam[p:q][keep] + K2 * phn[p:q][keep])
-                    tree[t, 1] += np.sum(K3 * gam[p:q][keep] + K4 * phn[p:q][keep])
+        for c in part.far[i]:
+            p, q = part.clusters[c]
+            if c not in cache:
+                cache[c] = proxies(y[p:q], ny[p:q], gam[p:q], phn[p:q], eps, degree)
+            s, Q0, Qk, Qk2 = cache[c]
+            for t in range(a, b):
+                d = tx[t] - s
+                r = np.linalg.norm(d, axis=1)
+                e = np.exp(-kappa * r)
+                dnx = d @ tn[t]
+                g0 = 1.0 / (FOUR_PI * r)
+                tree[t, 0] += np.sum(g0 * Q0 + e * g0 * Qk)
+                tree[t, 1] += np.sum(-dnx / (FOUR_PI * r ** 3) * (Q0 + e * (1.0 + kappa * r) * Qk2))
+        for c in part.near[i]:
+            p, q = part.clusters[c]
+            for t in range(a, b):
+                keep = ~np.any(node_tri[p:q] == part.vorder[t], axis=1)
+                K1, K2, K3, K4 = kernels(tx[t], tn[t], y[p:q][keep], ny[p:q][keep], kappa, eps)
+                tree[t, 0] += np.sum(K1 * gam[p:q][keep] + K2 * phn[p:q][keep])
+                tree[t, 1] += np.sum(K3 * gam[p:q][keep] + K4 * phn[p:q][keep])
     # the same dense regular sum, for swapping it out of y_dense
     for t in range(nv):
         keep = ~np.any(node_tri == part.vorder[t], axis=1)
@@ -200,4 +241,4 @@ def matvec(st: Setup, u, kappa, eps, theta=0.5, degree=5, leaf=1024, batch=512):
     idx = part.vorder
     out[idx] += reg[:, 0] - tree[:, 0]
     out[nv + idx] += reg[:, 1] - tree[:, 1]
-    return out, int(part.far.sum())
+    return out, int(sum(len(f) for f in part.far))

@@ -346,7 +346,8 @@ void free_problem(hobi_problem pb) {
     free_krylov(pb->kr);
     {
         TreePlan& t = d.tree;
-        void* tp[] = {t.clu_range, t.clu_box, t.prox64, t.prox32, t.items[0], t.items[1], t.partial};
+        void* tp[] = {t.clu_range, t.clu_child, t.clu_box, t.prox64, t.prox32, t.items[0], t.items[1],
+                      t.slot_row[0], t.slot_row[1], t.partial};
         for (void* p : tp)
             if (p) (void)hipFree(p);
         t = TreePlan{};
@@ -395,11 +396,15 @@ hobi_status run_device_setup(hobi_problem pb, float* ms_out) {
 }
 
 // The treecode's partition (hobi_params.tree_theta > 0), from the node and target positions
-// in internal order: clusters of tree_leaf consecutive nodes, batches of kTreeBatch
-// consecutive targets, each with the bounding sphere of its box (centre, half diagonal); a
-// pair is far when r_b + r_c <= theta |c_b - c_c| and the vertex ids of the cluster's
-// triangles, taken as a range, miss the batch's.  Work items: every (slot, cluster) of each
-// precision's target slots, slot-major, marked far when its batch's pair is.
+// in internal order.  Leaves: runs of tree_leaf consecutive nodes; parents: neighbours
+// joined pairwise level by level (a last cluster without a neighbour moves up unchanged),
+// stored after the leaves level by level.  Each cluster and batch (tree_batch consecutive
+// targets) has the bounding sphere of its box (centre, half diagonal); a cluster's
+// vertex-id range is that of its triangles.  Each batch walks the tree from the root:
+// accepted (far) when r_b + r_c <= theta |c_b - c_c| and the cluster's vertex-id range
+// misses the batch's targets, else a leaf is near and a parent is opened (left child
+// first).  Work items: for every target slot of each precision, its batch's far and near
+// clusters in walk order.
 hobi_status build_tree_plan(hobi_problem pb) {
     DeviceProblem& d = pb->d;
     TreePlan& t = d.tree;
@@ -418,8 +423,55 @@ hobi_status build_tree_plan(hobi_problem pb) {
     t.degree = prm.tree_degree;
     t.nprox = (t.degree + 1) * (t.degree + 1) * (t.degree + 1);
     t.leaf = prm.tree_leaf;
-    t.ncl = (nn + t.leaf - 1) / t.leaf;
-    t.nbatch = (nv + kTreeBatch - 1) / kTreeBatch;
+    t.batch = prm.tree_batch;
+    t.nleaf = (nn + t.leaf - 1) / t.leaf;
+    t.nbatch = (nv + t.batch - 1) / t.batch;
+    // clusters: node range, box (lo, hi, ungrown), vertex-id range, children
+    struct Clu {
+        int a, b, vlo, vhi, c0, c1;
+        double lo[3], hi[3];
+    };
+    std::vector<Clu> cl(t.nleaf);
+    for (int c = 0; c < t.nleaf; ++c) {
+        Clu& k = cl[c];
+        k.a = c * t.leaf;
+        k.b = std::min(k.a + t.leaf, nn);
+        k.c0 = k.c1 = -1;
+        for (int q = 0; q < 3; ++q) k.lo[q] = 1e300, k.hi[q] = -1e300;
+        for (int j = k.a; j < k.b; ++j) {
+            const double pj[3] = {nodes[j].x, nodes[j].y, nodes[j].z};
+            for (int q = 0; q < 3; ++q) k.lo[q] = std::min(k.lo[q], pj[q]), k.hi[q] = std::max(k.hi[q], pj[q]);
+        }
+        k.vlo = nv, k.vhi = -1;
+        for (int f = k.a / 4; f < (k.b + 3) / 4; ++f)
+            for (int q = 0; q < 3; ++q) k.vlo = std::min(k.vlo, tri[3 * f + q]), k.vhi = std::max(k.vhi, tri[3 * f + q]);
+    }
+    std::vector<int> level(t.nleaf);
+    std::iota(level.begin(), level.end(), 0);
+    t.nlev = 0;
+    while (level.size() > 1) {
+        if (t.nlev >= kTreeMaxLevels) return fail(ctx, HOBI_E_ARG, "cluster tree too deep");
+        t.lev_off[t.nlev] = (int)cl.size();
+        std::vector<int> up;
+        for (size_t i = 0; i < level.size(); i += 2) {
+            if (i + 1 == level.size()) {
+                up.push_back(level[i]);
+                continue;
+            }
+            const Clu &l = cl[level[i]], &r = cl[level[i + 1]];
+            Clu k;
+            k.a = l.a, k.b = r.b, k.c0 = level[i], k.c1 = level[i + 1];
+            k.vlo = std::min(l.vlo, r.vlo), k.vhi = std::max(l.vhi, r.vhi);
+            for (int q = 0; q < 3; ++q) k.lo[q] = std::min(l.lo[q], r.lo[q]), k.hi[q] = std::max(l.hi[q], r.hi[q]);
+            cl.push_back(k);
+            up.push_back((int)cl.size() - 1);
+        }
+        level.swap(up);
+        ++t.nlev;
+    }
+    t.lev_off[t.nlev] = (int)cl.size();
+    const int root = level[0];
+    t.nclu = (int)cl.size();
     // centre of the box [lo, hi] into c; returns its diagonal
     auto box_centre = [](const double lo[3], const double hi[3], double c[3]) {
         double q = 0;
@@ -429,79 +481,91 @@ hobi_status build_tree_plan(hobi_problem pb) {
         }
         return std::sqrt(q);
     };
-    std::vector<int2> crange(t.ncl);
-    std::vector<double> cbox(6 * (size_t)t.ncl), ccen(3 * (size_t)t.ncl), crad(t.ncl);
-    std::vector<int> cvlo(t.ncl), cvhi(t.ncl);
-    for (int c = 0; c < t.ncl; ++c) {
-        const int a = c * t.leaf, b = std::min(a + t.leaf, nn);
-        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-        for (int j = a; j < b; ++j) {
-            const double pj[3] = {nodes[j].x, nodes[j].y, nodes[j].z};
-            for (int k = 0; k < 3; ++k) lo[k] = std::min(lo[k], pj[k]), hi[k] = std::max(hi[k], pj[k]);
-        }
-        const double diag = box_centre(lo, hi, &ccen[3 * (size_t)c]);
+    std::vector<int2> crange(t.nclu), cchild(t.nclu);
+    std::vector<double> cbox(6 * (size_t)t.nclu), ccen(3 * (size_t)t.nclu), crad(t.nclu);
+    for (int c = 0; c < t.nclu; ++c) {
+        const Clu& k = cl[c];
+        const double diag = box_centre(k.lo, k.hi, &ccen[3 * (size_t)c]);
         crad[c] = 0.5 * diag;
         const double g = kTreeGrow * diag + 1e-12;
-        for (int k = 0; k < 3; ++k) cbox[6 * (size_t)c + k] = lo[k] - g, cbox[6 * (size_t)c + 3 + k] = hi[k] + g;
-        int vlo = nv, vhi = -1;
-        for (int f = a / 4; f < (b + 3) / 4; ++f)
-            for (int k = 0; k < 3; ++k) vlo = std::min(vlo, tri[3 * f + k]), vhi = std::max(vhi, tri[3 * f + k]);
-        cvlo[c] = vlo;
-        cvhi[c] = vhi;
-        crange[c] = make_int2(a, b);
+        for (int q = 0; q < 3; ++q) cbox[6 * (size_t)c + q] = k.lo[q] - g, cbox[6 * (size_t)c + 3 + q] = k.hi[q] + g;
+        crange[c] = make_int2(k.a, k.b);
+        cchild[c] = make_int2(k.c0, k.c1);
     }
-    std::vector<char> far((size_t)t.nbatch * t.ncl, 0);
-    t.nfar = 0;
+    // the walk of every batch: far (1) and near (0) clusters
+    std::vector<std::vector<std::pair<int, int>>> walk(t.nbatch);
+    t.nfar = t.nnear = 0;
+    std::vector<int> stack;
     for (int bi = 0; bi < t.nbatch; ++bi) {
-        const int a = bi * kTreeBatch, b = std::min(a + kTreeBatch, nv);
+        const int a = bi * t.batch, b = std::min(a + t.batch, nv);
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
         for (int i = a; i < b; ++i)
-            for (int k = 0; k < 3; ++k) {
-                const double v = tg[(size_t)k * d.nv_pad + i];
-                lo[k] = std::min(lo[k], v), hi[k] = std::max(hi[k], v);
+            for (int q = 0; q < 3; ++q) {
+                const double v = tg[(size_t)q * d.nv_pad + i];
+                lo[q] = std::min(lo[q], v), hi[q] = std::max(hi[q], v);
             }
         double cb[3];
         const double rb = 0.5 * box_centre(lo, hi, cb);
-        for (int c = 0; c < t.ncl; ++c) {
-            const bool touches = cvhi[c] >= a && cvlo[c] <= b - 1;
+        stack.assign(1, root);
+        while (!stack.empty()) {
+            const int c = stack.back();
+            stack.pop_back();
+            const bool touches = cl[c].vhi >= a && cl[c].vlo <= b - 1;
             const double* cc = &ccen[3 * (size_t)c];
             const double dx = cb[0] - cc[0], dy = cb[1] - cc[1], dz = cb[2] - cc[2];
-            const bool f = !touches && rb + crad[c] <= prm.tree_theta * std::sqrt(dx * dx + dy * dy + dz * dz);
-            far[(size_t)bi * t.ncl + c] = f;
-            t.nfar += f;
+            if (!touches && rb + crad[c] <= prm.tree_theta * std::sqrt(dx * dx + dy * dy + dz * dz)) {
+                walk[bi].emplace_back(c, 1);
+                ++t.nfar;
+            } else if (cl[c].c0 < 0) {
+                walk[bi].emplace_back(c, 0);
+                ++t.nnear;
+            } else {
+                stack.push_back(cl[c].c1);
+                stack.push_back(cl[c].c0);
+            }
         }
     }
     std::vector<int4> items[2];
+    std::vector<int> srow[2];
     size_t partial_elems = 0;
     for (int m = 0; m < 2; ++m) {
-        t.tpl[m] = m ? tpl32_for(d.nv_pad) : kTpl64;
+        t.tpl[m] = m ? t.batch / 64 : kTpl64;
         t.slot[m] = 64 * t.tpl[m];
         const int slots = (nv + t.slot[m] - 1) / t.slot[m];
-        const int64_t n_items = (int64_t)slots * t.ncl;
-        const size_t elems = (size_t)n_items * 2 * t.slot[m];
-        if (n_items > ((int64_t)1 << 30) || elems > ((size_t)1 << 31))
-            return fail(ctx, HOBI_E_ARG, "treecode plan too large (%lld work items): raise tree_leaf",
-                        (long long)n_items);
-        t.nitems[m] = (int)n_items;
-        partial_elems = std::max(partial_elems, elems);
-        items[m].reserve(n_items);
+        srow[m].assign(1, 0);
         for (int sl = 0; sl < slots; ++sl) {
-            const int bi = sl * t.slot[m] / kTreeBatch;
-            for (int c = 0; c < t.ncl; ++c) items[m].push_back(make_int4(sl, far[(size_t)bi * t.ncl + c], c, 0));
+            const int bi = sl * t.slot[m] / t.batch;
+            for (const auto& w : walk[bi]) items[m].push_back(make_int4(sl, w.second, w.first, 0));
+            if (items[m].size() > ((size_t)1 << 30))
+                return fail(ctx, HOBI_E_ARG, "treecode plan too large: raise tree_leaf or tree_theta");
+            srow[m].push_back((int)items[m].size());
         }
+        t.nitems[m] = (int)items[m].size();
+        const size_t elems = (size_t)t.nitems[m] * 2 * t.slot[m];
+        if (elems > ((size_t)1 << 31))
+            return fail(ctx, HOBI_E_ARG, "treecode plan too large (%d work items): raise tree_leaf or tree_theta",
+                        t.nitems[m]);
+        partial_elems = std::max(partial_elems, elems);
     }
-    HIPCHK(ctx, dalloc(&t.clu_range, t.ncl));
-    HIPCHK(ctx, dalloc(&t.clu_box, 6 * (size_t)t.ncl));
-    HIPCHK(ctx, dalloc(&t.prox64, (size_t)t.ncl * t.nprox));
-    HIPCHK(ctx, dalloc(&t.prox32, (size_t)t.ncl * t.nprox));
-    HIPCHK(ctx, dalloc(&t.items[0], items[0].size()));
-    HIPCHK(ctx, dalloc(&t.items[1], items[1].size()));
+    HIPCHK(ctx, dalloc(&t.clu_range, t.nclu));
+    HIPCHK(ctx, dalloc(&t.clu_child, t.nclu));
+    HIPCHK(ctx, dalloc(&t.clu_box, 6 * (size_t)t.nclu));
+    HIPCHK(ctx, dalloc(&t.prox64, (size_t)t.nclu * t.nprox));
+    HIPCHK(ctx, dalloc(&t.prox32, (size_t)t.nclu * t.nprox));
+    for (int m = 0; m < 2; ++m) {
+        HIPCHK(ctx, dalloc(&t.items[m], items[m].size()));
+        HIPCHK(ctx, dalloc(&t.slot_row[m], srow[m].size()));
+    }
     HIPCHK(ctx, dalloc(&t.partial, partial_elems));
     HIPCHK(ctx, hipMemcpyAsync(t.clu_range, crange.data(), sizeof(int2) * crange.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(t.clu_child, cchild.data(), sizeof(int2) * cchild.size(), hipMemcpyHostToDevice, s));
     HIPCHK(ctx, hipMemcpyAsync(t.clu_box, cbox.data(), sizeof(double) * cbox.size(), hipMemcpyHostToDevice, s));
-    for (int m = 0; m < 2; ++m)
+    for (int m = 0; m < 2; ++m) {
         HIPCHK(ctx, hipMemcpyAsync(t.items[m], items[m].data(), sizeof(int4) * items[m].size(),
                                    hipMemcpyHostToDevice, s));
+        HIPCHK(ctx, hipMemcpyAsync(t.slot_row[m], srow[m].data(), sizeof(int) * srow[m].size(),
+                                   hipMemcpyHostToDevice, s));
+    }
     HIPCHK(ctx, hipStreamSynchronize(s));
     t.on = 1;
     return HOBI_OK;
@@ -529,6 +593,8 @@ hobi_status validate_params(hobi_ctx ctx, const hobi_params& p) {
         return fail(ctx, HOBI_E_ARG, "tree_degree must be in 1..%d", kTreeMaxDeg);
     if (p.tree_leaf < 64 || p.tree_leaf > (1 << 24) || p.tree_leaf % 64 != 0)
         return fail(ctx, HOBI_E_ARG, "tree_leaf must be a multiple of 64 in [64, 2^24]");
+    if (p.tree_batch != 128 && p.tree_batch != 256 && p.tree_batch != 512)
+        return fail(ctx, HOBI_E_ARG, "tree_batch must be 128, 256 or 512");
     if (p.tree_theta > 0 && p.method != HOBI_HIGHER_ORDER)
         return fail(ctx, HOBI_E_ARG, "the treecode serves the higher-order method only");
     return HOBI_OK;
@@ -621,7 +687,8 @@ void hobi_params_default(hobi_params* p) {
     p->diag_scaling = 1;
     p->tree_theta = 0.0;
     p->tree_degree = 5;
-    p->tree_leaf = 1024;
+    p->tree_leaf = 256;
+    p->tree_batch = 128;
 }
 
 hobi_status hobi_ctx_create(int device, void* stream, hobi_ctx* out) {
@@ -1092,7 +1159,7 @@ hobi_status hobi_solve(hobi_problem pb, double* phi, double* dphi, double* e_sol
     L.ms_field_kernel = pb->ms[T_FIELD];
     L.field_launches = pb->cnt[T_FIELD];
     L.tree_far_pairs = pb->d.tree.nfar;
-    L.tree_near_pairs = pb->d.tree.on ? (int64_t)pb->d.tree.nbatch * pb->d.tree.ncl - pb->d.tree.nfar : 0;
+    L.tree_near_pairs = pb->d.tree.nnear;
     if (stats) *stats = L;
     for (int i = 0; i < n; ++i)
         if (!std::isfinite(hu[i])) return fail(c, HOBI_E_NUMERIC, "non-finite solution");
@@ -1149,7 +1216,7 @@ hobi_status hobi_get_stats(hobi_problem pb, hobi_stats* out) {
     pb->last.ms_field_kernel = pb->ms[T_FIELD];
     pb->last.field_launches = pb->cnt[T_FIELD];
     pb->last.tree_far_pairs = pb->d.tree.nfar;
-    pb->last.tree_near_pairs = pb->d.tree.on ? (int64_t)pb->d.tree.nbatch * pb->d.tree.ncl - pb->d.tree.nfar : 0;
+    pb->last.tree_near_pairs = pb->d.tree.nnear;
     *out = pb->last;
     return st;
 }

@@ -50,7 +50,7 @@ struct PairPlan {
 // partition is geometric and built once at problem creation; the proxy charges depend on u
 // and are rebuilt by every matvec.
 constexpr int kTreeMaxDeg = 7;       // (n + 1)^3 <= 512 proxies per cluster
-constexpr int kTreeBatch = 512;      // targets per batch of the acceptance test
+constexpr int kTreeMaxLevels = 40;
 constexpr double kTreeGrow = 1e-6;   // proxy box = node box grown by this fraction of its diagonal (+ 1e-12 A)
 struct ProxyD {                      // proxy point and its three charges (64 B)
     double x, y, z, q0, qk, qk2, pad0, pad1;
@@ -63,14 +63,19 @@ struct ProxyF {                      // FP32 copy in the frame of the FP32 node 
 struct TreePlan {
     int on = 0;
     int degree = 0, nprox = 0;       // n, (n + 1)^3
-    int leaf = 0, ncl = 0, nbatch = 0;
-    int64_t nfar = 0;                // far (batch, cluster) pairs
-    int2* clu_range = nullptr;       // [ncl] node range of each cluster
-    double* clu_box = nullptr;       // [ncl][6] grown box: lo[3], hi[3]
-    ProxyD* prox64 = nullptr;        // [ncl][nprox]
-    ProxyF* prox32 = nullptr;        // [ncl][nprox]
+    int leaf = 0, batch = 0;
+    int nleaf = 0, nclu = 0, nbatch = 0;   // leaves, all clusters (leaves first), batches
+    int nlev = 0;                    // parent levels
+    int lev_off[kTreeMaxLevels + 1] = {};  // parents of level l: clusters [lev_off[l], lev_off[l + 1])
+    int64_t nfar = 0, nnear = 0;     // accepted (batch, cluster) and near (batch, leaf) pairs
+    int2* clu_range = nullptr;       // [nclu] node range of each cluster
+    double* clu_box = nullptr;       // [nclu][6] grown box: lo[3], hi[3]
+    int2* clu_child = nullptr;       // [nclu] children of a parent ((-1, -1) for a leaf)
+    ProxyD* prox64 = nullptr;        // [nclu][nprox]
+    ProxyF* prox32 = nullptr;        // [nclu][nprox]
     int4* items[2] = {nullptr, nullptr};   // [0] FP64, [1] mixed: {slot, far, cluster, 0}, slot-major
-    int nitems[2] = {0, 0};          // slots * ncl
+    int* slot_row[2] = {nullptr, nullptr}; // [slots + 1]: items of slot s are [slot_row[s], slot_row[s + 1])
+    int nitems[2] = {0, 0};
     int slot[2] = {0, 0};            // targets per slot
     int tpl[2] = {0, 0};
     double* partial = nullptr;       // [nitems][2][slot] (the larger of the two)

@@ -1,20 +1,26 @@
 // Treecode matvec (optional, hobi_params.tree_theta > 0): the dense regular sum of the
-// pair kernels replaced by a single-level cluster-particle treecode.  The partition (built
-// on the host at problem creation): node clusters = consecutive runs of `leaf` nodes in
-// Morton order, target batches = consecutive runs of 512 targets; a (batch, cluster) pair
-// is far when (rb + rc) <= theta |cb - cc| and no target of the batch is a vertex of a
-// triangle of the cluster, else near.  Per matvec, after the gather:
+// pair kernels replaced by a cluster-particle treecode.  The partition (built on the host
+// at problem creation): leaves = consecutive runs of tree_leaf nodes in Morton order,
+// joined pairwise level by level into a binary cluster tree; batches = consecutive runs of
+// tree_batch targets.  Each batch walks the tree: a cluster with (r_b + r_c) <= theta
+// |c_b - c_c| and no triangle incident to a target of the batch is far, a leaf that fails
+// is near, a parent that fails is opened.  Per matvec, after the gather:
 //
-//   proxy_kernel   -- per cluster, the (n+1)^3 Chebyshev points of its box (grown by
-//                     1e-6 of the diagonal) and three charges per point,
+//   proxy_kernel   -- per leaf, the (n+1)^3 Chebyshev points of its box (grown by 1e-6 of
+//                     the diagonal) and three charges per point,
 //                       Q0  = sum_j  Gamma_j L_k(y_j) - Phi_j grad L_k(y_j).n_j
 //                       Qk  = sum_j -Gamma_j L_k(y_j) + eps Phi_j grad L_k(y_j).n_j
 //                       Qk2 = sum_j -Gamma_j L_k(y_j) / eps + Phi_j grad L_k(y_j).n_j
 //                     (L_k the tensor Lagrange basis, product form): the Green's functions
 //                     interpolated in the source point, so that a far cluster's two rows
 //                     are sum_k G0 Q0 + Gk Qk and sum_k dG0/dnu_x Q0 + dGk/dnu_x Qk2 at s_k
-//   tree_*_kernel  -- one wave per work item (slot of targets, cluster): near items run the
-//                     masked pair loop over the cluster's nodes, far items the proxies;
+//   upward_kernel  -- per parent of one level, its charges from its two children's:
+//                     Q_k = sum over the children's points s_j of L_k(s_j) Q_j, the same
+//                     value as the sums over its nodes (each L_k of the parent is a
+//                     tensor polynomial of degree n, which a child's degree-n
+//                     interpolation reproduces together with its gradient)
+//   tree_*_kernel  -- one wave per work item (slot of targets, cluster): near items run
+//                     the masked pair loop over the leaf's nodes, far items the proxies;
 //                     each item writes one partial row
 //   tree_combine   -- a slot's rows in item order, then the singular correction and the
 //                     diagonal (as combine_tile).
@@ -35,7 +41,46 @@ __device__ __forceinline__ int xcd_logical_block() {
     return x * q + min(x, rm) + (p >> 3);
 }
 
-// One block per cluster.  Each round puts l_a(y_d) and l_a'(y_d) of kChunk nodes (every
+// l_a(t) and l_a'(t) of the points p[0..n1) (product form, the derivative by the running
+// product rule).
+__device__ __forceinline__ double lagrange_1d(const double* p, int n1, int a, double t, double* dl) {
+    double l = 1.0, d = 0.0;
+    for (int b = 0; b < n1; ++b) {
+        if (b == a) continue;
+        const double h = 1.0 / (p[a] - p[b]);
+        d = d * ((t - p[b]) * h) + l * h;
+        l *= (t - p[b]) * h;
+    }
+    *dl = d;
+    return l;
+}
+
+// n1 Chebyshev points of the second kind on [lo, hi]
+__device__ __forceinline__ double cheb_point(double lo, double hi, int a, int n) {
+    return 0.5 * (lo + hi) + 0.5 * (hi - lo) * cos(kPi * a / n);
+}
+
+// The FP64 proxy record and its FP32 copy (positions in the frame of the FP32 targets).
+__device__ __forceinline__ void write_proxy(ProxyD* __restrict__ prox64, ProxyF* __restrict__ prox32, size_t at,
+                                            double x, double y, double z, double q0, double qk, double qk2,
+                                            int mixed, double s32, double cx, double cy, double cz) {
+    ProxyD pd{};
+    pd.x = x, pd.y = y, pd.z = z, pd.q0 = q0, pd.qk = qk, pd.qk2 = qk2;
+    prox64[at] = pd;
+    if (mixed) {
+        ProxyF pf{};
+        pf.x = (float)((x - cx) * s32);
+        pf.y = (float)((y - cy) * s32);
+        pf.z = (float)((z - cz) * s32);
+        pf.q0a = (float)(s32 * q0);
+        pf.qka = (float)(s32 * qk);
+        pf.q0b = (float)(s32 * s32 * q0);
+        pf.qk2b = (float)(s32 * s32 * qk2);
+        prox32[at] = pf;
+    }
+}
+
+// One block per leaf.  Each round puts l_a(y_d) and l_a'(y_d) of kChunk nodes (every
 // dimension d and index a) into LDS; then thread k accumulates the charges of proxies k and
 // k + kBlock over the round's nodes in node order.
 __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__ nodes,
@@ -54,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
     if (threadIdx.x < 3 * n1) {
         const int d = threadIdx.x / n1, a = threadIdx.x % n1;
         const double lo = box[d], hi = box[3 + d];
-        pt[d][a] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * cos(kPi * a / n);
+        pt[d][a] = cheb_point(lo, hi, a, n);
     }
     __syncthreads();
     double q0[2] = {0.0, 0.0}, qk[2] = {0.0, 0.0}, qk2[2] = {0.0, 0.0};
@@ -71,14 +116,8 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
             const int i = e / (3 * n1), d = (e / n1) % 3, a = e % n1;
             const NodeD& nd = nodes[j0 + i];
             const double t = d == 0 ? nd.x : (d == 1 ? nd.y : nd.z);
-            double l = 1.0, dl = 0.0;
-            for (int b = 0; b < n1; ++b) {
-                if (b == a) continue;
-                const double f = (t - pt[d][b]) / (pt[d][a] - pt[d][b]);
-                dl = dl * f + l / (pt[d][a] - pt[d][b]);   // product rule, running
-                l *= f;
-            }
-            lv[i][d][a] = l;
+            double dl;
+            lv[i][d][a] = lagrange_1d(pt[d], n1, a, t, &dl);
             dv[i][d][a] = dl;
         }
         if ((int)threadIdx.x < m) {
@@ -108,25 +147,70 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
     for (int h = 0; h < 2; ++h) {
         const int k = threadIdx.x + h * kBlock;
         if (k >= P) continue;
-        ProxyD pd{};
-        pd.x = pt[0][ka[h]];
-        pd.y = pt[1][kb[h]];
-        pd.z = pt[2][kc[h]];
-        pd.q0 = q0[h];
-        pd.qk = qk[h];
-        pd.qk2 = qk2[h];
-        prox64[(size_t)c * P + k] = pd;
-        if (mixed) {
-            ProxyF pf{};
-            pf.x = (float)((pd.x - cx) * s32);
-            pf.y = (float)((pd.y - cy) * s32);
-            pf.z = (float)((pd.z - cz) * s32);
-            pf.q0a = (float)(s32 * q0[h]);
-            pf.qka = (float)(s32 * qk[h]);
-            pf.q0b = (float)(s32 * s32 * q0[h]);
-            pf.qk2b = (float)(s32 * s32 * qk2[h]);
-            prox32[(size_t)c * P + k] = pf;
-        }
+        write_proxy(prox64, prox32, (size_t)c * P + k, pt[0][ka[h]], pt[1][kb[h]], pt[2][kc[h]], q0[h], qk[h], qk2[h],
+                    mixed, s32, cx, cy, cz);
+    }
+}
+
+// One block per parent c = first + blockIdx.x of one level: its proxy points from its box,
+// and its charges from its two children's (computed by earlier launches):
+//   Q_k = sum_{child} sum_{b} l_ka(s_b1) l_kb(s_b2) l_kc(s_b3) Q_b(child),
+// children in order, each child's points in record order.
+__global__ __launch_bounds__(kBlock) void upward_kernel(int first, const int2* __restrict__ clu_child,
+                                                        const double* __restrict__ clu_box, int n,
+                                                        ProxyD* __restrict__ prox64, ProxyF* __restrict__ prox32,
+                                                        int mixed, double s32, double cx, double cy, double cz) {
+    constexpr int M = kTreeMaxDeg + 1;
+    __shared__ double pt[3][M];
+    __shared__ double cp[2][3][M];          // children's 1D points
+    __shared__ double lt[2][3][M][M];       // l_a(parent) at the children's points b
+    __shared__ double qc[2][3][M * M * M];  // children's charges
+    const int c = first + blockIdx.x;
+    const int n1 = n + 1, P = n1 * n1 * n1;
+    const int2 ch = clu_child[c];
+    const double* box = clu_box + 6 * (size_t)c;
+    if (threadIdx.x < 3 * n1) {
+        const int d = threadIdx.x / n1, a = threadIdx.x % n1;
+        pt[d][a] = cheb_point(box[d], box[3 + d], a, n);
+    }
+    if (threadIdx.x < 2 * 3 * n1) {
+        const int h = threadIdx.x / (3 * n1), d = (threadIdx.x / n1) % 3, b = threadIdx.x % n1;
+        const ProxyD* q = prox64 + (size_t)(h ? ch.y : ch.x) * P;
+        cp[h][d][b] = d == 0 ? q[b * n1 * n1].x : (d == 1 ? q[b * n1].y : q[b].z);
+    }
+    for (int e = threadIdx.x; e < 2 * P; e += kBlock) {
+        const int h = e / P, k = e % P;
+        const ProxyD& q = prox64[(size_t)(h ? ch.y : ch.x) * P + k];
+        qc[h][0][k] = q.q0;
+        qc[h][1][k] = q.qk;
+        qc[h][2][k] = q.qk2;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * 3 * n1 * n1; e += kBlock) {
+        const int h = e / (3 * n1 * n1), d = (e / (n1 * n1)) % 3, a = (e / n1) % n1, b = e % n1;
+        double dl;
+        lt[h][d][a][b] = lagrange_1d(pt[d], n1, a, cp[h][d][b], &dl);
+    }
+    __syncthreads();
+    for (int h = 0; h < 2; ++h) {
+        const int k = threadIdx.x + h * kBlock;
+        if (k >= P) continue;
+        const int ka = k / (n1 * n1), kb = (k / n1) % n1, kc = k % n1;
+        double q0 = 0.0, qk = 0.0, qk2 = 0.0;
+        for (int g = 0; g < 2; ++g)
+            for (int b1 = 0; b1 < n1; ++b1)
+                for (int b2 = 0; b2 < n1; ++b2) {
+                    const double w12 = lt[g][0][ka][b1] * lt[g][1][kb][b2];
+                    const int j0 = (b1 * n1 + b2) * n1;
+                    for (int b3 = 0; b3 < n1; ++b3) {
+                        const double wgt = w12 * lt[g][2][kc][b3];
+                        q0 += wgt * qc[g][0][j0 + b3];
+                        qk += wgt * qc[g][1][j0 + b3];
+                        qk2 += wgt * qc[g][2][j0 + b3];
+                    }
+                }
+        write_proxy(prox64, prox32, (size_t)c * P + k, pt[0][ka], pt[1][kb], pt[2][kc], q0, qk, qk2, mixed, s32, cx,
+                    cy, cz);
     }
 }
 
@@ -318,19 +402,19 @@ __global__ __launch_bounds__(kBlock) void tree_f64_kernel(
     }
 }
 
-// Rows (i, i + nv) for the kCombineVerts targets of tile vb: the ncl rows of their slot
-// s (items s ncl .. s ncl + ncl - 1; wave k sums rows k, k + 4, ..., the four sums added in
-// a fixed order), then the singular correction and the diagonal.
+// Rows (i, i + nv) for the kCombineVerts targets of tile vb: the rows of their slot s
+// (items slot_row[s] .. slot_row[s + 1] - 1; wave k sums rows k, k + 4, ..., the four sums
+// added in a fixed order), then the singular correction and the diagonal.
 __global__ __launch_bounds__(kBlock) void tree_combine_kernel(
     const double* __restrict__ u, double* __restrict__ y, int nv, const double* __restrict__ partial, int slot,
-    int ncl, const int* __restrict__ inc_off, const int* __restrict__ inc_ent, const int* __restrict__ tri,
+    const int* __restrict__ slot_row, const int* __restrict__ inc_off, const int* __restrict__ inc_ent, const int* __restrict__ tri,
     const double* __restrict__ coef, double eps) {
     __shared__ double red[2][4][kCombineVerts];
     const int vb = blockIdx.x;
     const int lane = threadIdx.x % kCombineVerts, way = threadIdx.x / kCombineVerts;
     const int i = vb * kCombineVerts + lane;
     const int s = vb * kCombineVerts / slot, o = i - s * slot;
-    const int rb = s * ncl, re = rb + ncl;
+    const int rb = slot_row[s], re = slot_row[s + 1];
     double r1 = 0.0, r2 = 0.0;
     if (i < nv) {
         for (int r = rb + way; r < re; r += 4) {
@@ -367,8 +451,13 @@ inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
 hipError_t launch_tree_proxies(const DeviceProblem& p, bool mixed, hipStream_t s) {
     const TreePlan& t = p.tree;
-    hipLaunchKernelGGL(proxy_kernel, dim3(t.ncl), dim3(kBlock), 0, s, p.node64, t.clu_range, t.clu_box, t.degree,
+    hipLaunchKernelGGL(proxy_kernel, dim3(t.nleaf), dim3(kBlock), 0, s, p.node64, t.clu_range, t.clu_box, t.degree,
                        p.eps, t.prox64, t.prox32, mixed ? 1 : 0, p.s32, p.center[0], p.center[1], p.center[2]);
+    for (int l = 0; l < t.nlev; ++l) {
+        const int first = t.lev_off[l], count = t.lev_off[l + 1] - t.lev_off[l];
+        hipLaunchKernelGGL(upward_kernel, dim3(count), dim3(kBlock), 0, s, first, t.clu_child, t.clu_box, t.degree,
+                           t.prox64, t.prox32, mixed ? 1 : 0, p.s32, p.center[0], p.center[1], p.center[2]);
+    }
     return hipGetLastError();
 }
 
@@ -383,8 +472,10 @@ hipError_t launch_tree_pairs(const DeviceProblem& p, bool mixed, hipStream_t s) 
                        p.nv_pad, p.node32, p.node_vid, p.blk_range, t.clu_range, t.prox32, t.nprox, t.partial)
         if (t.tpl[1] == 8) {
             if (k0) HOBI_TREE32(8, true); else HOBI_TREE32(8, false);
-        } else {
+        } else if (t.tpl[1] == 4) {
             if (k0) HOBI_TREE32(4, true); else HOBI_TREE32(4, false);
+        } else {
+            if (k0) HOBI_TREE32(2, true); else HOBI_TREE32(2, false);
         }
 #undef HOBI_TREE32
     } else {
@@ -404,7 +495,7 @@ hipError_t launch_tree_combine(const DeviceProblem& p, const double* u, double* 
     const TreePlan& t = p.tree;
     const int m = mixed ? 1 : 0;
     hipLaunchKernelGGL(tree_combine_kernel, dim3(nblk(p.nv, kCombineVerts)), dim3(kBlock), 0, s, u, y, p.nv,
-                       t.partial, t.slot[m], t.ncl, p.inc_off, p.inc_ent, p.tri, p.coef, p.eps);
+                       t.partial, t.slot[m], t.slot_row[m], p.inc_off, p.inc_ent, p.tri, p.coef, p.eps);
     return hipGetLastError();
 }
 

@@ -40,7 +40,8 @@ class hobi_params(ctypes.Structure):
     _fields_ = [("eps1", ctypes.c_double), ("eps2", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("method", ctypes.c_int32), ("diag_scaling", ctypes.c_int32),
-                ("tree_theta", ctypes.c_double), ("tree_degree", ctypes.c_int32), ("tree_leaf", ctypes.c_int32)]
+                ("tree_theta", ctypes.c_double), ("tree_degree", ctypes.c_int32), ("tree_leaf", ctypes.c_int32),
+                ("tree_batch", ctypes.c_int32)]
 
 
 class hobi_stats(ctypes.Structure):
@@ -187,7 +188,7 @@ class Problem:
 
     def __init__(self, ctx: Context, xyz, nrm, tri, qpos, q, eps1=1.0, eps2=80.0, kappa=0.1257,
                  rtol=1e-6, max_iter=200, restart=200, precision=HOBI_FP64, method=HOBI_HIGHER_ORDER,
-                 diag_scaling=1, tree_theta=0.0, tree_degree=5, tree_leaf=1024):
+                 diag_scaling=1, tree_theta=0.0, tree_degree=5, tree_leaf=256, tree_batch=128):
         self.ctx = ctx
         xyz = _f64(xyz).reshape(-1, 3)
         nrm = _f64(nrm).reshape(-1, 3)
@@ -202,7 +203,7 @@ class Problem:
         p.eps1, p.eps2, p.kappa, p.rtol = eps1, eps2, kappa, rtol
         p.max_iter, p.restart, p.precision, p.method = max_iter, restart, precision, method
         p.diag_scaling = diag_scaling
-        p.tree_theta, p.tree_degree, p.tree_leaf = tree_theta, tree_degree, tree_leaf
+        p.tree_theta, p.tree_degree, p.tree_leaf, p.tree_batch = tree_theta, tree_degree, tree_leaf, tree_batch
         h = _P()
         st = lib().hobi_problem_create(ctx.handle, self.nv, _dptr(xyz), _dptr(nrm), self.nf,
                                        tri.ctypes.data_as(_I), self.nc, _dptr(qpos), _dptr(q),

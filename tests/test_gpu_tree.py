@@ -31,15 +31,14 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-def _check_case(ctx, p, theta, degree, leaf, u, ref, nfar, name):
-    print(f"tree case {name} nv={p.nv} far pairs {nfar}", flush=True)
-    assert nfar > 0
+def _check_case(ctx, p, theta, degree, leaf, batch, u, ref, nfar, nnear, name):
+    print(f"tree case {name} nv={p.nv} far pairs {nfar} near pairs {nnear}", flush=True)
+    assert nfar > 0 and nnear > 0
     for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
-        g = hobi.Problem.from_inputs(ctx, p, precision=prec, tree_theta=theta, tree_degree=degree, tree_leaf=leaf)
+        g = hobi.Problem.from_inputs(ctx, p, precision=prec, tree_theta=theta, tree_degree=degree, tree_leaf=leaf,
+                                     tree_batch=batch)
         s = g.stats()
-        assert s["tree_far_pairs"] == nfar
-        nb, nc = -(-p.nv // 512), -(-4 * p.nf // leaf)
-        assert s["tree_far_pairs"] + s["tree_near_pairs"] == nb * nc
+        assert (s["tree_far_pairs"], s["tree_near_pairs"]) == (nfar, nnear)
         err = _rel(g.matvec(u), ref)
         print(f"  precision {prec} rel err {err:.3e}", flush=True)
         assert err <= tol, (name, prec, err)
@@ -47,25 +46,27 @@ def _check_case(ctx, p, theta, degree, leaf, u, ref, nfar, name):
 
 @pytest.mark.parametrize("name", list(G.CASES))
 def test_tree_matvec_matches_stored_oracle_treecode(ctx, name):
-    """Several batches with a far/near mix and ragged last batch and cluster (kappa = 0
-    takes the Laplace branch); expected values written by tests/golden/make_tree_golden.py
-    from the oracle."""
-    recipe, theta, degree, leaf = G.CASES[name]
+    """Several batches of each size (128, 256, 512), leaves of 64 to 256 nodes, parents
+    accepted at several levels, ragged last batch and leaf (kappa = 0 takes the Laplace
+    branch); expected values written by tests/golden/make_tree_golden.py from the oracle."""
+    recipe, theta, degree, leaf, batch = G.CASES[name]
     ref = np.load(os.path.join(GOLDEN, f"tree_{name}.npz"))
-    assert (float(ref["theta"]), int(ref["degree"]), int(ref["leaf"])) == (theta, degree, leaf)
+    assert (float(ref["theta"]), int(ref["degree"]), int(ref["leaf"]), int(ref["batch"])) == (theta, degree, leaf,
+                                                                                               batch)
     p = G.surface(recipe)
     u = inputs.random_vector(2 * p.nv, int(ref["seed"]))
-    _check_case(ctx, p, theta, degree, leaf, u, ref["y"], int(ref["nfar"]), name)
+    _check_case(ctx, p, theta, degree, leaf, batch, u, ref["y"], int(ref["nfar"]), int(ref["nnear"]), name)
 
 
 def test_tree_matvec_matches_oracle_treecode_L3(ctx):
-    """Smallest clusters (64 nodes), degree 5, kappa = 1: the oracle run live."""
+    """Smallest leaves (64 nodes), degree 5, kappa = 1: the oracle run live."""
     p = inputs.kirkwood_offcenter(3, kappa=1.0, eps1=4.0)
-    theta, degree, leaf = 0.9, 5, 64
+    theta, degree, leaf, batch = 0.9, 5, 64, 128
     st = O.setup(p.xyz, p.nrm, p.tri)
     u = inputs.random_vector(2 * p.nv, 25)
-    ref, nfar = T.matvec(st, u, p.kappa, p.eps2 / p.eps1, theta=theta, degree=degree, leaf=leaf, batch=512)
-    _check_case(ctx, p, theta, degree, leaf, u, ref, nfar, "L3_k1_n5_leaf64")
+    ref, nfar = T.matvec(st, u, p.kappa, p.eps2 / p.eps1, theta=theta, degree=degree, leaf=leaf, batch=batch)
+    nnear = sum(len(n) for n in T.partition(st, theta, leaf, batch).near)
+    _check_case(ctx, p, theta, degree, leaf, batch, u, ref, nfar, nnear, "L3_k1_n5_leaf64_b128")
 
 
 def test_all_near_is_the_dense_matvec(ctx):
@@ -76,14 +77,14 @@ def test_all_near_is_the_dense_matvec(ctx):
     u = inputs.random_vector(2 * p.nv, 22)
     ref = O.matvec(st, u, p.kappa, p.eps2 / p.eps1)
     for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
-        g = hobi.Problem.from_inputs(ctx, p, precision=prec, tree_theta=1e-9, tree_leaf=128)
+        g = hobi.Problem.from_inputs(ctx, p, precision=prec, tree_theta=1e-9, tree_leaf=128, tree_batch=512)
         assert g.stats()["tree_far_pairs"] == 0
         assert _rel(g.matvec(u), ref) <= tol
 
 
 def test_tree_is_deterministic_and_precision_switch(ctx):
     p = inputs.kirkwood_offcenter(4)
-    g = hobi.Problem.from_inputs(ctx, p, tree_theta=0.6, tree_degree=4, tree_leaf=256)
+    g = hobi.Problem.from_inputs(ctx, p, tree_theta=0.6, tree_degree=4)
     u = inputs.random_vector(2 * p.nv, 23)
     y64 = g.matvec(u)
     assert np.array_equal(y64, g.matvec(u))
@@ -95,12 +96,13 @@ def test_tree_is_deterministic_and_precision_switch(ctx):
 
 def test_bench_workload_L6_tree_against_dense(ctx):
     """The default bench surface at full size (40962 targets, 327680 nodes): the treecode
-    matvec (theta 0.5, degree 5) within 1e-4 of the dense one, FP64 and mixed treecode
-    within 1e-5 of each other, and the solve's energy within 1e-4 of the dense solve's."""
+    matvec (theta 0.7, degree 5, 256-node leaves, 128-target batches) within 1e-4 of the
+    dense one, FP64 and mixed treecode within 1e-5 of each other, and the solve's energy
+    within 1e-4 of the dense solve's."""
     p = inputs.kirkwood_offcenter(6)
     u = inputs.random_vector(2 * p.nv, 24)
     dense = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED)
-    tree = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED, tree_theta=0.5, tree_degree=5)
+    tree = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED, tree_theta=0.7, tree_degree=5)
     s = tree.stats()
     print(f"L6 tree far {s['tree_far_pairs']} near {s['tree_near_pairs']}", flush=True)
     assert s["tree_far_pairs"] > 0
@@ -122,7 +124,8 @@ def test_tree_parameter_errors(ctx):
     p = inputs.kirkwood_offcenter(2)
     bad = [dict(tree_theta=-0.1), dict(tree_theta=float("nan")), dict(tree_theta=0.5, tree_degree=0),
            dict(tree_theta=0.5, tree_degree=8), dict(tree_theta=0.5, tree_leaf=100),
-           dict(tree_theta=0.5, tree_leaf=0), dict(tree_theta=0.5, method=hobi.HOBI_LOWER_ORDER)]
+           dict(tree_theta=0.5, tree_leaf=0), dict(tree_theta=0.5, tree_batch=64),
+           dict(tree_theta=0.5, tree_batch=1024), dict(tree_theta=0.5, method=hobi.HOBI_LOWER_ORDER)]
     for kw in bad:
         with pytest.raises(hobi.HobiError) as e:
             hobi.Problem.from_inputs(ctx, p, **kw)

@@ -64,16 +64,62 @@ def test_lagrange_basis_reproduces_polynomials():
 
 
 def test_partition_covers_and_far_pairs_hold_no_incident_triangle(sphere):
+    """Every batch's accepted and near clusters tile the node range exactly once; the
+    tree's parents join their children's ranges; no accepted cluster holds a triangle
+    incident to a target of its batch."""
     p, st = sphere
     part = T.partition(st, 0.6, 256, 128)
     nn = 4 * p.nf
-    assert part.clusters[0][0] == 0 and part.clusters[-1][1] == nn
-    assert all(part.clusters[i][1] == part.clusters[i + 1][0] for i in range(len(part.clusters) - 1))
+    assert part.clusters[0][0] == 0 and part.clusters[part.nleaf - 1][1] == nn
+    assert all(part.clusters[i][1] == part.clusters[i + 1][0] for i in range(part.nleaf - 1))
+    for c, ch in enumerate(part.children):
+        assert (ch is None) == (c < part.nleaf)
+        if ch is not None:
+            assert part.clusters[c] == (part.clusters[ch[0]][0], part.clusters[ch[1]][1])
+            assert part.clusters[ch[0]][1] == part.clusters[ch[1]][0]
     assert part.batches[-1][1] == p.nv and sorted(part.vorder) == list(range(p.nv))
     tri_o = st.tri[part.torder]
+    assert sum(len(f) for f in part.far) > 0
+    assert any(c >= part.nleaf for f in part.far for c in f)        # parents are accepted too
     for i, (a, b) in enumerate(part.batches):
+        assert all(c < part.nleaf for c in part.near[i])
+        spans = sorted(part.clusters[c] for c in part.far[i] + part.near[i])
+        assert spans[0][0] == 0 and spans[-1][1] == nn
+        assert all(spans[k][1] == spans[k + 1][0] for k in range(len(spans) - 1))
         targets = set(part.vorder[a:b].tolist())
-        for c, (q0, q1) in enumerate(part.clusters):
-            if part.far[i, c]:
-                verts = set(tri_o[q0 // 4:q1 // 4].ravel().tolist())
-                assert not (targets & verts)
+        for c in part.far[i]:
+            q0, q1 = part.clusters[c]
+            verts = set(tri_o[q0 // 4:q1 // 4].ravel().tolist())
+            assert not (targets & verts)
+
+
+def test_parent_charges_are_the_children_charges_interpolated(sphere):
+    """A parent's proxy charges (sums over its nodes) equal its children's charges carried
+    to the parent's points by the parent's basis: a degree-n tensor polynomial (each L_k of
+    the parent, and so its gradient) is reproduced exactly by the child's degree-n
+    interpolation.  (The GPU builds parent charges this way.)"""
+    p, st = sphere
+    part = T.partition(st, 0.6, 256, 128)
+    rng = np.random.default_rng(3)
+    tri_o = st.tri[part.torder]
+    y = st.y[part.torder].reshape(-1, 3)
+    ny = st.ny[part.torder].reshape(-1, 3)
+    gam, phn = rng.standard_normal(y.shape[0]), rng.standard_normal(y.shape[0])
+    n, eps = 4, 80.0
+    parent = next(c for c, ch in enumerate(part.children) if ch is not None and
+                  all(part.children[k] is not None for k in ch))
+    a, b = part.clusters[parent]
+    sp, *Qp = T.proxies(y[a:b], ny[a:b], gam[a:b], phn[a:b], eps, n)
+    lo, hi = y[a:b].min(axis=0), y[a:b].max(axis=0)
+    g = T.GROW * np.linalg.norm(hi - lo) + 1e-12
+    P = T.cheb_points(lo - g, hi + g, n)
+    carried = [np.zeros(sp.shape[0]) for _ in range(3)]
+    for ch in part.children[parent]:
+        ca, cb = part.clusters[ch]
+        sc, *Qc = T.proxies(y[ca:cb], ny[ca:cb], gam[ca:cb], phn[ca:cb], eps, n)
+        L = [T.lagrange_1d(P[d], sc[:, d])[0] for d in range(3)]
+        Lk = np.einsum("ja,jb,jc->jabc", L[0], L[1], L[2]).reshape(sc.shape[0], -1)
+        for m in range(3):
+            carried[m] += Qc[m] @ Lk
+    for m in range(3):
+        np.testing.assert_allclose(carried[m], Qp[m], rtol=1e-10, atol=1e-10 * np.max(np.abs(Qp[m])))
