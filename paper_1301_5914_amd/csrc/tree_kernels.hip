@@ -33,7 +33,7 @@ namespace {
 
 constexpr int kBlock = kPairBlock;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kChunk = 16;          // nodes per LDS round of the proxy kernel
+constexpr int kChunk = 32;          // nodes per LDS round of the proxy kernel
 
 __device__ __forceinline__ int xcd_logical_block() {
     const int nb = gridDim.x, p = blockIdx.x;
@@ -42,17 +42,27 @@ __device__ __forceinline__ int xcd_logical_block() {
 }
 
 // l_a(t) and l_a'(t) of the points p[0..n1) (product form, the derivative by the running
-// product rule).
-__device__ __forceinline__ double lagrange_1d(const double* p, int n1, int a, double t, double* dl) {
+// product rule); inv[b] = 1 / (p[a] - p[b]).
+__device__ __forceinline__ double lagrange_1d(const double* p, const double* inv, int n1, int a, double t,
+                                              double* dl) {
     double l = 1.0, d = 0.0;
     for (int b = 0; b < n1; ++b) {
         if (b == a) continue;
-        const double h = 1.0 / (p[a] - p[b]);
-        d = d * ((t - p[b]) * h) + l * h;
-        l *= (t - p[b]) * h;
+        const double f = (t - p[b]) * inv[b];
+        d = d * f + l * inv[b];
+        l *= f;
     }
     *dl = d;
     return l;
+}
+
+// inv[d][a][b] = 1 / (pt[d][a] - pt[d][b]) for a != b, by the first 3 (n + 1)^2 threads
+template <int M>
+__device__ __forceinline__ void inverse_differences(const double (&pt)[3][M], double (&inv)[3][M][M], int n1) {
+    if ((int)threadIdx.x < 3 * n1 * n1) {
+        const int d = threadIdx.x / (n1 * n1), a = (threadIdx.x / n1) % n1, b = threadIdx.x % n1;
+        inv[d][a][b] = a == b ? 0.0 : 1.0 / (pt[d][a] - pt[d][b]);
+    }
 }
 
 // n1 Chebyshev points of the second kind on [lo, hi]
@@ -89,6 +99,7 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
                                                        ProxyD* __restrict__ prox64, ProxyF* __restrict__ prox32,
                                                        int mixed, double s32, double cx, double cy, double cz) {
     __shared__ double pt[3][kTreeMaxDeg + 1];
+    __shared__ double inv[3][kTreeMaxDeg + 1][kTreeMaxDeg + 1];
     __shared__ double lv[kChunk][3][kTreeMaxDeg + 1];
     __shared__ double dv[kChunk][3][kTreeMaxDeg + 1];
     __shared__ double ng[kChunk], np_[kChunk], nn3[kChunk][3];
@@ -101,6 +112,8 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
         const double lo = box[d], hi = box[3 + d];
         pt[d][a] = cheb_point(lo, hi, a, n);
     }
+    __syncthreads();
+    inverse_differences(pt, inv, n1);
     __syncthreads();
     double q0[2] = {0.0, 0.0}, qk[2] = {0.0, 0.0}, qk2[2] = {0.0, 0.0};
     int ka[2], kb[2], kc[2];
@@ -117,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
             const NodeD& nd = nodes[j0 + i];
             const double t = d == 0 ? nd.x : (d == 1 ? nd.y : nd.z);
             double dl;
-            lv[i][d][a] = lagrange_1d(pt[d], n1, a, t, &dl);
+            lv[i][d][a] = lagrange_1d(pt[d], inv[d][a], n1, a, t, &dl);
             dv[i][d][a] = dl;
         }
         if ((int)threadIdx.x < m) {
@@ -154,19 +167,22 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
 
 // One block per parent c = first + blockIdx.x of one level: its proxy points from its box,
 // and its charges from its two children's (computed by earlier launches):
-//   Q_k = sum_{child} sum_{b} l_ka(s_b1) l_kb(s_b2) l_kc(s_b3) Q_b(child),
-// children in order, each child's points in record order.
+//   Q_a = sum_{child} sum_{b} l_a1(s_b1) l_a2(s_b2) l_a3(s_b3) Q_b(child),
+// as three one-dimensional contractions per child (over b3, then b2, then b1: n + 1 terms
+// per output each), children in order.
 __global__ __launch_bounds__(kBlock) void upward_kernel(int first, const int2* __restrict__ clu_child,
                                                         const double* __restrict__ clu_box, int n,
                                                         ProxyD* __restrict__ prox64, ProxyF* __restrict__ prox32,
                                                         int mixed, double s32, double cx, double cy, double cz) {
-    constexpr int M = kTreeMaxDeg + 1;
+    constexpr int M = kTreeMaxDeg + 1, MP = M * M * M;
     __shared__ double pt[3][M];
+    __shared__ double inv[3][M][M];
     __shared__ double cp[2][3][M];          // children's 1D points
     __shared__ double lt[2][3][M][M];       // l_a(parent) at the children's points b
-    __shared__ double qc[2][3][M * M * M];  // children's charges
+    __shared__ double qc[2][3][MP];         // children's charges
+    __shared__ double t1[3][MP], t2[3][MP]; // partial contractions
     const int c = first + blockIdx.x;
-    const int n1 = n + 1, P = n1 * n1 * n1;
+    const int n1 = n + 1, n2 = n1 * n1, P = n2 * n1;
     const int2 ch = clu_child[c];
     const double* box = clu_box + 6 * (size_t)c;
     if (threadIdx.x < 3 * n1) {
@@ -176,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void upward_kernel(int first, const int2* _
     if (threadIdx.x < 2 * 3 * n1) {
         const int h = threadIdx.x / (3 * n1), d = (threadIdx.x / n1) % 3, b = threadIdx.x % n1;
         const ProxyD* q = prox64 + (size_t)(h ? ch.y : ch.x) * P;
-        cp[h][d][b] = d == 0 ? q[b * n1 * n1].x : (d == 1 ? q[b * n1].y : q[b].z);
+        cp[h][d][b] = d == 0 ? q[b * n2].x : (d == 1 ? q[b * n1].y : q[b].z);
     }
     for (int e = threadIdx.x; e < 2 * P; e += kBlock) {
         const int h = e / P, k = e % P;
@@ -186,31 +202,64 @@ __global__ __launch_bounds__(kBlock) void upward_kernel(int first, const int2* _
         qc[h][2][k] = q.qk2;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 2 * 3 * n1 * n1; e += kBlock) {
-        const int h = e / (3 * n1 * n1), d = (e / (n1 * n1)) % 3, a = (e / n1) % n1, b = e % n1;
+    inverse_differences(pt, inv, n1);
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * 3 * n2; e += kBlock) {
+        const int h = e / (3 * n2), d = (e / n2) % 3, a = (e / n1) % n1, b = e % n1;
         double dl;
-        lt[h][d][a][b] = lagrange_1d(pt[d], n1, a, cp[h][d][b], &dl);
+        lt[h][d][a][b] = lagrange_1d(pt[d], inv[d][a], n1, a, cp[h][d][b], &dl);
     }
     __syncthreads();
+    double acc[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    for (int g = 0; g < 2; ++g) {
+        for (int h = 0; h < 2; ++h) {            // t1[b1 b2 a3] = sum_b3 l_a3(b3) Q[b1 b2 b3]
+            const int k = threadIdx.x + h * kBlock;
+            if (k >= P) continue;
+            const int j0 = k - k % n1, a3 = k % n1;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int b = 0; b < n1; ++b) {
+                const double w = lt[g][2][a3][b];
+                s0 += w * qc[g][0][j0 + b];
+                s1 += w * qc[g][1][j0 + b];
+                s2 += w * qc[g][2][j0 + b];
+            }
+            t1[0][k] = s0, t1[1][k] = s1, t1[2][k] = s2;
+        }
+        __syncthreads();
+        for (int h = 0; h < 2; ++h) {            // t2[b1 a2 a3] = sum_b2 l_a2(b2) t1[b1 b2 a3]
+            const int k = threadIdx.x + h * kBlock;
+            if (k >= P) continue;
+            const int b1 = k / n2, a2 = (k / n1) % n1, a3 = k % n1;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int b = 0; b < n1; ++b) {
+                const double w = lt[g][1][a2][b];
+                const int j = b1 * n2 + b * n1 + a3;
+                s0 += w * t1[0][j];
+                s1 += w * t1[1][j];
+                s2 += w * t1[2][j];
+            }
+            t2[0][k] = s0, t2[1][k] = s1, t2[2][k] = s2;
+        }
+        __syncthreads();
+        for (int h = 0; h < 2; ++h) {            // Q[a1 a2 a3] += sum_b1 l_a1(b1) t2[b1 a2 a3]
+            const int k = threadIdx.x + h * kBlock;
+            if (k >= P) continue;
+            const int a1 = k / n2, r = k % n2;
+            for (int b = 0; b < n1; ++b) {
+                const double w = lt[g][0][a1][b];
+                acc[h][0] += w * t2[0][b * n2 + r];
+                acc[h][1] += w * t2[1][b * n2 + r];
+                acc[h][2] += w * t2[2][b * n2 + r];
+            }
+        }
+        __syncthreads();                         // t1, t2 are rewritten for the next child
+    }
     for (int h = 0; h < 2; ++h) {
         const int k = threadIdx.x + h * kBlock;
         if (k >= P) continue;
-        const int ka = k / (n1 * n1), kb = (k / n1) % n1, kc = k % n1;
-        double q0 = 0.0, qk = 0.0, qk2 = 0.0;
-        for (int g = 0; g < 2; ++g)
-            for (int b1 = 0; b1 < n1; ++b1)
-                for (int b2 = 0; b2 < n1; ++b2) {
-                    const double w12 = lt[g][0][ka][b1] * lt[g][1][kb][b2];
-                    const int j0 = (b1 * n1 + b2) * n1;
-                    for (int b3 = 0; b3 < n1; ++b3) {
-                        const double wgt = w12 * lt[g][2][kc][b3];
-                        q0 += wgt * qc[g][0][j0 + b3];
-                        qk += wgt * qc[g][1][j0 + b3];
-                        qk2 += wgt * qc[g][2][j0 + b3];
-                    }
-                }
-        write_proxy(prox64, prox32, (size_t)c * P + k, pt[0][ka], pt[1][kb], pt[2][kc], q0, qk, qk2, mixed, s32, cx,
-                    cy, cz);
+        const int ka = k / n2, kb = (k / n1) % n1, kc = k % n1;
+        write_proxy(prox64, prox32, (size_t)c * P + k, pt[0][ka], pt[1][kb], pt[2][kc], acc[h][0], acc[h][1],
+                    acc[h][2], mixed, s32, cx, cy, cz);
     }
 }
 
