@@ -304,8 +304,10 @@ __device__ __forceinline__ void far_f32_wave(const float* __restrict__ tgt, int 
         float a1[TPL], a2[TPL];
 #pragma unroll
         for (int k = 0; k < TPL; ++k) a1[k] = a2[k] = 0.0f;
+        ProxyF pr = load_proxy(cp, k0);
         for (int q = k0; q < k1; ++q) {
-            const ProxyF pr = load_proxy(cp, q);
+            // the next record's scalar load is in flight while this one is used
+            const ProxyF next = load_proxy(cp, min(q + 1, k1 - 1));
 #pragma unroll
             for (int k = 0; k < TPL; ++k) {
                 const float dx = tx[k] - pr.x, dy = ty[k] - pr.y, dz = tz[k] - pr.z;
@@ -324,6 +326,7 @@ __device__ __forceinline__ void far_f32_wave(const float* __restrict__ tgt, int 
                     a2[k] = fmaf(-rinv3 * dnx, fmaf(e * zp1, pr.qk2b, pr.q0b), a2[k]);
                 }
             }
+            pr = next;
         }
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {

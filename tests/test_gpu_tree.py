@@ -69,6 +69,32 @@ def test_tree_matvec_matches_oracle_treecode_L3(ctx):
     _check_case(ctx, p, theta, degree, leaf, batch, u, ref, nfar, nnear, "L3_k1_n5_leaf64_b128")
 
 
+@pytest.mark.parametrize("degree", [1, 7])
+def test_tree_degree_extremes_match_oracle(ctx, degree):
+    """Degree 1 (8 proxies) and the largest degree 7 (512 proxies: two per thread in the
+    charge kernels), against the oracle run live on L3."""
+    p = inputs.kirkwood_offcenter(3)
+    theta, leaf, batch = 0.9, 64, 128
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    u = inputs.random_vector(2 * p.nv, 26 + degree)
+    ref, nfar = T.matvec(st, u, p.kappa, p.eps2 / p.eps1, theta=theta, degree=degree, leaf=leaf, batch=batch)
+    nnear = sum(len(n) for n in T.partition(st, theta, leaf, batch).near)
+    _check_case(ctx, p, theta, degree, leaf, batch, u, ref, nfar, nnear, f"L3_degree{degree}")
+
+
+def test_single_leaf_is_the_dense_matvec(ctx):
+    """A leaf larger than the node count: one cluster, no parent level, every pair near."""
+    p = inputs.kirkwood_offcenter(2)
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    u = inputs.random_vector(2 * p.nv, 33)
+    ref = O.matvec(st, u, p.kappa, p.eps2 / p.eps1)
+    for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
+        g = hobi.Problem.from_inputs(ctx, p, precision=prec, tree_theta=0.9, tree_leaf=1 << 24)
+        s = g.stats()
+        assert (s["tree_far_pairs"], s["tree_near_pairs"]) == (0, -(-p.nv // 128))   # one leaf per batch
+        assert _rel(g.matvec(u), ref) <= tol
+
+
 def test_all_near_is_the_dense_matvec(ctx):
     """An opening parameter so small that no pair is far: the dense sum, cluster by
     cluster (FP64 to 1e-12 of the oracle's dense matvec, mixed to 1e-5)."""
