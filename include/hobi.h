@@ -234,7 +234,11 @@ hobi_status hobi_get_stats(hobi_problem pb, hobi_stats* st);
  * GMRES iteration per scheduler tick, all together: each tick does one batched gather,
  * one batched pair-sum and
  * one batched combine launch for every request (captured once in a HIP graph when
- * use_graph is 1), then each request's Gram-Schmidt and Givens update.  Requests
+ * use_graph is 1), then each request's Gram-Schmidt and Givens update.  A request with
+ * tree_theta > 0 runs its own treecode matvec launches in the tick instead (the sequence of
+ * hobi_matvec); it is admitted on its dense footprint and charged its treecode buffers,
+ * which depend on the partition, once its problem is built, so bytes_in_use may then
+ * exceed the budget until it leaves.  Requests
  * arriving during a tick join at the next one; finished requests leave at the end of the
  * tick that finished them.  A request's arithmetic depends only on that request (its
  * split over waves is fixed by its own size and the device), so its results are

@@ -1,7 +1,8 @@
 // Request server: continuous batching of HOBI-PB solves on one device (hobi_server_* in
 // hobi.h).  One worker thread owns a stream; requests are admitted by device footprint,
-// advance one GMRES iteration per tick with their matvecs batched into three launches,
-// and retire as soon as they converge.
+// advance one GMRES iteration per tick with their matvecs batched into four launches
+// (requests with the treecode run their own matvec launches in the same tick), and
+// retire as soon as they converge.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -88,6 +89,22 @@ int64_t footprint_bytes(int device, int nv, int nf, int nc, int m, int method) {
     const int64_t n = 2LL * nv;
     b += 8 * ((int64_t)(m + 1) * n + (int64_t)(m + 1) * m + 6LL * (m + 1) + kDotBlocks * (int64_t)(m + 1) + 2 * n + 8);
     return b;
+}
+
+// Device bytes of a built problem's treecode buffers (0 without the treecode).  They depend
+// on the partition, so a request is admitted on its dense footprint and charged these bytes
+// once its problem is built.
+int64_t tree_bytes(const DeviceProblem& d) {
+    const TreePlan& t = d.tree;
+    if (!t.on) return 0;
+    int64_t b = (int64_t)t.nclu * (2 * sizeof(int2) + 6 * sizeof(double)) +
+                (int64_t)t.nclu * t.nprox * (sizeof(ProxyD) + sizeof(ProxyF));
+    int64_t part = 0;
+    for (int m = 0; m < 2; ++m) {
+        b += (int64_t)t.nitems[m] * sizeof(int4) + 4LL * ((d.nv + t.slot[m] - 1) / t.slot[m] + 1);
+        part = std::max<int64_t>(part, 2LL * t.nitems[m] * t.slot[m]);
+    }
+    return b + 8 * part;
 }
 
 void free_request_device(Request& r) {
@@ -288,13 +305,15 @@ hobi_status tick(hobi_server sv) {
     size_t cnt[4] = {0, 0, 0, 0};
     for (auto& rp : sv->active) {
         const DeviceProblem& d = rp->pb->d;
+        if (d.tree.on) continue;              // launched on its own below
         cnt[0] += (d.nn + kServeBlock - 1) / kServeBlock;
         cnt[rp->prm.precision == HOBI_MIXED ? 1 : 2] += (size_t)rp->plan.blocks;
         cnt[3] += (d.nv + kCombineVerts - 1) / kCombineVerts;
     }
     // the four lists live at fixed offsets (quarters of the item buffer), so that the
     // captured launches stay valid until the buffer has to grow
-    hipError_t e = ensure_capacity(sv, na, 4 * std::max(std::max(cnt[0], cnt[1]), std::max(cnt[2], cnt[3])));
+    hipError_t e =
+        ensure_capacity(sv, na, 4 * std::max<size_t>(1, std::max(std::max(cnt[0], cnt[1]), std::max(cnt[2], cnt[3]))));
     if (e != hipSuccess) return host_fail(sv->ctx, HOBI_E_OOM, "server work-list allocation failed");
     const size_t t4 = sv->cap_items / 4;
     ServeItem* hl[4];
@@ -346,6 +365,7 @@ hobi_status tick(hobi_server sv) {
         sd.tpl = r.plan.tpl;
         sd.method = d.method;
         sd.pad = 0;
+        if (d.tree.on) continue;
         for (int blk = 0; blk < (d.nn + kServeBlock - 1) / kServeBlock; ++blk)
             hl[0][fill[0]++] = ServeItem{(int)q, blk, 0, 0};
         const int pl = sd.mixed ? 1 : 2;
@@ -382,6 +402,18 @@ hobi_status tick(hobi_server sv) {
             return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
     } else if ((e = launch_batched_matvec(sv->d_desc, dl, sv->d_counts, s)) != hipSuccess) {
         return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
+    }
+    // treecode requests: the single-problem sequence (gather, proxy charges, items, combine)
+    for (size_t q = 0; q < na; ++q) {
+        Request& r = *sv->active[q];
+        const DeviceProblem& d = r.pb->d;
+        if (!d.tree.on) continue;
+        const ServeDesc& sd = sv->h_desc[q];
+        const bool mixed = r.prm.precision == HOBI_MIXED;
+        if ((e = launch_gather(d, sd.u, mixed, s)) != hipSuccess || (e = launch_tree_proxies(d, mixed, s)) != hipSuccess ||
+            (e = launch_tree_pairs(d, mixed, s)) != hipSuccess ||
+            (e = launch_tree_combine(d, sd.u, sd.y, mixed, s)) != hipSuccess)
+            return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
     }
     // per-request Gram-Schmidt (two passes), normalisation and Givens update
     for (size_t q = 0; q < na; ++q) {
@@ -525,8 +557,13 @@ void prep_main(hobi_server sv) {
         } else {
             r->pb->ctx = sv->ctx;             // built and synchronised: from now on the worker's
         }
+        const int64_t extra = r->pb ? tree_bytes(r->pb->d) : 0;
         {
             std::lock_guard<std::mutex> lk(sv->mu);
+            r->footprint += extra;
+            sv->in_use += extra;
+            sv->st.bytes_in_use = sv->in_use;
+            sv->st.peak_bytes = std::max(sv->st.peak_bytes, sv->in_use);
             sv->preparing -= 1;
             sv->ready.push_back(std::move(r));
         }
@@ -586,11 +623,6 @@ hobi_status hobi_server_submit(hobi_server sv, int32_t nv, const double* xyz, co
     r->q.assign(q, q + nc);
     hobi_params_default(&r->prm);
     if (params) r->prm = *params;
-    if (r->prm.tree_theta != 0.0) {
-        std::lock_guard<std::mutex> lk(sv->mu);
-        sv->last_error = "the server runs the dense sum only (tree_theta must be 0)";
-        return HOBI_E_ARG;
-    }
     r->prm.restart = r->prm.max_iter;
     r->nu = r->prm.method == HOBI_LOWER_ORDER ? nf : nv;
     r->footprint = footprint_bytes(sv->device, nv, nf, nc, std::max(1, r->prm.max_iter), r->prm.method);

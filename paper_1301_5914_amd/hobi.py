@@ -356,7 +356,8 @@ class Server:
         raise HobiError(st, msg.decode() if msg else "")
 
     def submit(self, prob, rtol=1e-6, max_iter=300, precision=HOBI_MIXED, eps1=None, eps2=None,
-               kappa=None, method=HOBI_HIGHER_ORDER, diag_scaling=1) -> int:
+               kappa=None, method=HOBI_HIGHER_ORDER, diag_scaling=1, tree_theta=0.0, tree_degree=5, tree_leaf=256,
+               tree_batch=128) -> int:
         xyz = _f64(prob.xyz).reshape(-1, 3)
         nrm = _f64(prob.nrm).reshape(-1, 3)
         tri = np.ascontiguousarray(np.asarray(prob.tri, dtype=np.int32).reshape(-1, 3))
@@ -368,6 +369,7 @@ class Server:
         p.kappa = prob.kappa if kappa is None else kappa
         p.rtol, p.max_iter, p.restart, p.precision, p.method = rtol, max_iter, max_iter, precision, method
         p.diag_scaling = diag_scaling
+        p.tree_theta, p.tree_degree, p.tree_leaf, p.tree_batch = tree_theta, tree_degree, tree_leaf, tree_batch
         t = ctypes.c_uint64()
         st = lib().hobi_server_submit(self.handle, xyz.shape[0], _dptr(xyz), _dptr(nrm), tri.shape[0],
                                       tri.ctypes.data_as(_I), q.shape[0], _dptr(qpos), _dptr(q),

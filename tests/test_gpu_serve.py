@@ -87,6 +87,37 @@ def test_alone_equals_in_the_mix(ctx, use_graph):
     sv.close()
 
 
+def test_treecode_requests_equal_the_single_problem_path(ctx):
+    """Treecode requests (their own matvec launches in each tick) give the bits of
+    hobi_solve with the same parameters, alone and next to dense requests; a request with
+    bad treecode parameters fails on its own."""
+    tree = dict(tree_theta=0.8, tree_degree=4, tree_leaf=128, tree_batch=128)
+    cases = [(inputs.kirkwood_offcenter(3), dict(precision=hobi.HOBI_MIXED, **tree)),
+             (inputs.kirkwood_offcenter(3, kappa=0.0, eps1=2.0), dict(precision=hobi.HOBI_FP64, **tree)),
+             (inputs.kirkwood_centered(3), dict(precision=hobi.HOBI_MIXED))]
+    refs = []
+    for p, kw in cases:
+        g = hobi.Problem.from_inputs(ctx, p, max_iter=200, restart=200, **kw)
+        assert kw.get("tree_theta", 0) == 0 or g.stats()["tree_far_pairs"] > 0
+        refs.append(g.solve())
+    for use_graph in (True, False):
+        sv = hobi.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=8, use_graph=use_graph)
+        alone = _wait(sv, [sv.submit(cases[0][0], max_iter=200, **cases[0][1])])
+        tickets = [sv.submit(p, max_iter=200, **kw) for p, kw in cases]
+        bad = sv.submit(cases[0][0], max_iter=200, tree_theta=0.5, tree_degree=9)
+        out = _wait(sv, tickets + [bad])
+        for r, ref in zip([next(iter(alone.values()))] + [out[t] for t in tickets], [refs[0]] + refs):
+            assert r["status"] == "HOBI_OK"
+            assert r["stats"]["iterations"] == ref["stats"]["iterations"]
+            np.testing.assert_array_equal(r["phi"], ref["phi"])
+            np.testing.assert_array_equal(r["dphi"], ref["dphi"])
+            assert r["energy"] == ref["energy"]
+        assert out[bad]["status"] == "HOBI_E_ARG"
+        st = sv.stats()
+        assert st["bytes_in_use"] == 0 and st["failed"] == 1
+        sv.close()
+
+
 def test_graph_replays_equal_eager_launches(ctx):
     mix = _mix()
     res = {}

@@ -3,7 +3,6 @@ C ABI against the treecode oracle (oracle/treecode.py) on the same seeded inputs
 same partition: FP64 to 1e-12 and mixed to 1e-5 of the largest row, the far-pair count
 exactly.  With every pair near the treecode is the dense matvec; at full size it stays
 within its interpolation error of the dense matvec and solve.  Parameter errors."""
-import ctypes
 import importlib.util
 import os
 
@@ -82,6 +81,27 @@ def test_tree_degree_extremes_match_oracle(ctx, degree):
     _check_case(ctx, p, theta, degree, leaf, batch, u, ref, nfar, nnear, f"L3_degree{degree}")
 
 
+def test_set_dielectric_on_a_tree_problem(ctx):
+    """New eps and kappa on an existing treecode problem (same partition): the FP32 frame
+    is rescaled and kappa = 0 switches to the Laplace kernels; both precisions against the
+    oracle treecode at the new parameters."""
+    p = inputs.kirkwood_offcenter(3)
+    theta, degree, leaf, batch = 0.9, 4, 64, 128
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    u = inputs.random_vector(2 * p.nv, 34)
+    gs = {prec: hobi.Problem.from_inputs(ctx, p, precision=prec, tree_theta=theta, tree_degree=degree,
+                                         tree_leaf=leaf, tree_batch=batch)
+          for prec in (hobi.HOBI_FP64, hobi.HOBI_MIXED)}
+    for eps1, eps2, kappa in ((2.0, 80.0, 0.5), (4.0, 40.0, 0.0)):
+        ref, nfar = T.matvec(st, u, kappa, eps2 / eps1, theta=theta, degree=degree, leaf=leaf, batch=batch)
+        assert nfar > 0
+        for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
+            gs[prec].set_dielectric(eps1, eps2, kappa)
+            err = _rel(gs[prec].matvec(u), ref)
+            print(f"  eps {eps2 / eps1} kappa {kappa} precision {prec} rel err {err:.3e}", flush=True)
+            assert err <= tol
+
+
 def test_single_leaf_is_the_dense_matvec(ctx):
     """A leaf larger than the node count: one cluster, no parent level, every pair near."""
     p = inputs.kirkwood_offcenter(2)
@@ -156,15 +176,4 @@ def test_tree_parameter_errors(ctx):
         with pytest.raises(hobi.HobiError) as e:
             hobi.Problem.from_inputs(ctx, p, **kw)
         assert e.value.status == 1, kw
-    sv = hobi.Server(ctx, hbm_budget_bytes=1 << 30, max_slots=2)
-    params = hobi.hobi_params_default()
-    params.tree_theta = 0.5
-    tk = ctypes.c_uint64()
-    xyz, nrm = np.ascontiguousarray(p.xyz), np.ascontiguousarray(p.nrm)
-    tri = np.ascontiguousarray(p.tri.astype(np.int32))
-    qpos, q = np.ascontiguousarray(p.qpos), np.ascontiguousarray(p.q)
-    st = hobi.lib().hobi_server_submit(sv.handle, p.nv, hobi._dptr(xyz), hobi._dptr(nrm), p.nf,
-                                       tri.ctypes.data_as(hobi._I), len(q), hobi._dptr(qpos), hobi._dptr(q),
-                                       ctypes.byref(params), ctypes.byref(tk))
-    assert st == 1
-    sv.close()
+    # the server takes treecode requests (tests/test_gpu_serve.py); its submit checks sizes only
