@@ -199,8 +199,10 @@ def _make_molecule_job(indexed_job):
     return k, _make_molecule(*job)
 
 
-def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slots, n_check):
-    """Poisson request stream through the continuous-batching server (mixed precision)."""
+def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slots, n_check, tree_theta=0.0):
+    """Poisson request stream through the continuous-batching server (mixed precision; with
+    tree_theta > 0 every request takes the treecode with the default degree, leaf and
+    batch, and the energy check is still against the dense FP64 solve)."""
     from paper_1301_5914_amd import hobi
 
     rng = np.random.default_rng(seed)
@@ -217,7 +219,7 @@ def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slot
 
     def submit(req):
         m, e1, kap = req
-        return sv.submit(m, precision=hobi.HOBI_MIXED, eps1=e1, kappa=kap, max_iter=400)
+        return sv.submit(m, precision=hobi.HOBI_MIXED, eps1=e1, kappa=kap, max_iter=400, tree_theta=tree_theta)
 
     # saturated throughput: a burst submitted at once
     burst = draw(min(16, n_requests))
@@ -271,7 +273,7 @@ def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slot
     lat_ms = np.array(lat) * 1e3
     sizes = [m.nf for m in pool_mols]
     return {
-        "requests": n_requests, "converged": ok, "arrival_rate_per_s": rate,
+        "requests": n_requests, "tree_theta": tree_theta, "converged": ok, "arrival_rate_per_s": rate,
         "saturated_rate_per_s": sat, "rate_factor": rate_factor,
         "throughput_requests_per_s": n_requests / wall, "throughput_gpairs_per_s": pairs / wall / 1e9,
         "latency_ms_p50": float(np.percentile(lat_ms, 50)), "latency_ms_p99": float(np.percentile(lat_ms, 99)),
@@ -311,6 +313,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=0.7, help="arrival rate / saturated throughput")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-tree-theta", type=float, default=0.0,
+                    help="serve the stream with the treecode at this opening parameter (0: dense)")
     ap.add_argument("--field-map", type=int, default=64,
                     help="potential map of grid^3 points after the timed steps (hobi_field); 0 = off")
     ap.add_argument("--tree-theta", type=float, default=0.7,
@@ -458,7 +462,8 @@ def main():
         out["calibration_copy_bytes"] = src.numel() * 4
     if pool_mols is not None:
         out["serving"] = serve_bench(pool_mols, args.serve_requests, 5, args.serve_rate,
-                                     int(args.serve_budget_gb * (1 << 30)), args.serve_slots, n_check=8)
+                                     int(args.serve_budget_gb * (1 << 30)), args.serve_slots, n_check=8,
+                                     tree_theta=args.serve_tree_theta)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
