@@ -67,10 +67,9 @@ def surface_nodes(st, u):
     raise TypeError("unknown setup type")
 
 
-def reaction_terms(st, u, points, kappa, eps):
-    """(R, grad R, solid-angle fraction) at each point, internal units."""
-    y, ny, w, dphi, phi = surface_nodes(st, u)
-    pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+def node_sums(pts, y, ny, w, dphi, phi, kappa, eps):
+    """(R, grad R, solid-angle fraction) at each point from the given quadrature nodes
+    (positions y, normals ny, weights w, interpolated dphi and phi)."""
     R = np.empty(pts.shape[0])
     gR = np.empty((pts.shape[0], 3))
     frac = np.empty(pts.shape[0])
@@ -98,6 +97,13 @@ def reaction_terms(st, u, points, kappa, eps):
         gR[k] = np.sum(w[:, None] * (gK1 * dphi[:, None] + gK2 * phi[:, None]), axis=0)
         frac[k] = -np.sum(w * dG0)
     return R, gR, frac
+
+
+def reaction_terms(st, u, points, kappa, eps):
+    """(R, grad R, solid-angle fraction) at each point, internal units."""
+    y, ny, w, dphi, phi = surface_nodes(st, u)
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    return node_sums(pts, y, ny, w, dphi, phi, kappa, eps)
 
 
 def coulomb_terms(points, qpos, q, eps1):

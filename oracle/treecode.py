@@ -169,8 +169,9 @@ def lagrange_1d(p, t):
     return L, D
 
 
-def proxies(y, ny, gam, phi, eps, n):
-    """(s [P,3], Q0, Qk, Qk2 [P]) of one cluster (nodes y, normals ny, strengths)."""
+def basis(y, ny, n):
+    """(s [P,3], L_k(y_j) [m,P], grad L_k(y_j).n_j [m,P]) of the cluster with nodes y,
+    normals ny: the proxy points of its grown box and the tensor basis at its nodes."""
     blo, bhi = y.min(axis=0), y.max(axis=0)
     g = GROW * np.linalg.norm(bhi - blo) + 1e-12
     p = cheb_points(blo - g, bhi + g, n)
@@ -182,10 +183,16 @@ def proxies(y, ny, gam, phi, eps, n):
     Gk = (np.einsum("ja,jb,jc->jabc", D[0], L[1], L[2]) * ny[:, 0, None, None, None]
           + np.einsum("ja,jb,jc->jabc", L[0], D[1], L[2]) * ny[:, 1, None, None, None]
           + np.einsum("ja,jb,jc->jabc", L[0], L[1], D[2]) * ny[:, 2, None, None, None]).reshape(y.shape[0], -1)
+    s = np.stack(np.meshgrid(p[0], p[1], p[2], indexing="ij"), axis=-1).reshape(-1, 3)
+    return s, Lk, Gk
+
+
+def proxies(y, ny, gam, phi, eps, n):
+    """(s [P,3], Q0, Qk, Qk2 [P]) of one cluster (nodes y, normals ny, strengths)."""
+    s, Lk, Gk = basis(y, ny, n)
     Q0 = gam @ Lk - phi @ Gk
     Qk = -(gam @ Lk) + eps * (phi @ Gk)
     Qk2 = -(gam @ Lk) / eps + phi @ Gk
-    s = np.stack(np.meshgrid(p[0], p[1], p[2], indexing="ij"), axis=-1).reshape(-1, 3)
     return s, Q0, Qk, Qk2
 
 
@@ -242,3 +249,75 @@ def matvec(st: Setup, u, kappa, eps, theta=0.5, degree=5, leaf=256, batch=128):
     out[idx] += reg[:, 0] - tree[:, 0]
     out[nv + idx] += reg[:, 1] - tree[:, 1]
     return out, int(sum(len(f) for f in part.far))
+
+
+def field_terms(st, u, points, kappa, eps, theta=0.5, degree=5, leaf=256, batch=256):
+    """(R, grad R, solid-angle fraction) at each point (as field.reaction_terms) with the
+    surface sum taken by the treecode, and the counts of accepted (batch, cluster) and near
+    (batch, leaf) pairs.  The points are ordered by the Morton rule over their own bounding
+    box and cut into batches of `batch`; each batch walks the cluster tree of the matvec's
+    partition with the acceptance test rb + rc <= theta |cb - cc| alone (the points are off
+    the surface).  Accepted clusters use, with d = x - s_k and a = exp(-kappa r),
+        R      ~ sum_k G0 Q0_k + Gk Qk_k,
+        grad R ~ -sum_k d/(4 pi r^3) (Q0_k + a (1 + kappa r) Qk_k),
+        frac   ~ sum_k G0 Qs_k,  Qs_k = -sum_j w_j grad L_k(y_j).n_j
+    (the solid angle is the double layer of the unit density, so its charge is the
+    normal-derivative part with weight -w); near leaves are summed directly."""
+    from .field import node_sums, surface_nodes
+
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    xyz, tri = st.xyz, st.tri
+    cen = (xyz[tri[:, 0]] + xyz[tri[:, 1]] + xyz[tri[:, 2]]) / 3.0
+    torder = morton_order(cen, xyz.min(axis=0), xyz.max(axis=0))   # the matvec's node order
+    y0, ny0, w0, dphi0, phi0 = surface_nodes(st, u)
+    idx = (4 * torder[:, None] + np.arange(4)[None, :]).ravel()
+    y, ny, w, dphi, phi = y0[idx], ny0[idx], w0[idx], dphi0[idx], phi0[idx]
+    gam, phn = w * dphi, w * phi
+    clusters, children, root = cluster_tree(y.shape[0], leaf)
+
+    def sphere(p):
+        blo, bhi = p.min(axis=0), p.max(axis=0)
+        return 0.5 * (blo + bhi), 0.5 * np.linalg.norm(bhi - blo)
+
+    cs = [sphere(y[a:b]) for a, b in clusters]
+    porder = morton_order(pts, pts.min(axis=0), pts.max(axis=0))
+    tp = pts[porder]
+    R = np.zeros(pts.shape[0])
+    gR = np.zeros((pts.shape[0], 3))
+    frac = np.zeros(pts.shape[0])
+    cache = {}
+    nfar = nnear = 0
+    for a0 in range(0, pts.shape[0], batch):
+        b0 = min(a0 + batch, pts.shape[0])
+        cb, rb = sphere(tp[a0:b0])
+        stack = [root]
+        while stack:
+            c = stack.pop()
+            a, b = clusters[c]
+            if rb + cs[c][1] <= theta * np.linalg.norm(cb - cs[c][0]):
+                nfar += 1
+                if c not in cache:
+                    s, Lk, Gk = basis(y[a:b], ny[a:b], degree)
+                    cache[c] = (s, gam[a:b] @ Lk - phn[a:b] @ Gk, -(gam[a:b] @ Lk) + eps * (phn[a:b] @ Gk),
+                                -(w[a:b] @ Gk))
+                s, Q0, Qk, Qs = cache[c]
+                for t in range(a0, b0):
+                    d = tp[t] - s
+                    r = np.linalg.norm(d, axis=1)
+                    e = np.exp(-kappa * r)
+                    g0 = 1.0 / (FOUR_PI * r)
+                    R[t] += np.sum(g0 * Q0 + e * g0 * Qk)
+                    gR[t] -= np.sum((d / (FOUR_PI * r ** 3)[:, None]) * (Q0 + e * (1.0 + kappa * r) * Qk)[:, None],
+                                    axis=0)
+                    frac[t] += np.sum(g0 * Qs)
+            elif children[c] is None:
+                nnear += 1
+                r_, g_, f_ = node_sums(tp[a0:b0], y[a:b], ny[a:b], w[a:b], dphi[a:b], phi[a:b], kappa, eps)
+                R[a0:b0] += r_
+                gR[a0:b0] += g_
+                frac[a0:b0] += f_
+            else:
+                stack.extend(children[c][::-1])
+    out_R, out_g, out_f = np.empty_like(R), np.empty_like(gR), np.empty_like(frac)
+    out_R[porder], out_g[porder], out_f[porder] = R, gR, frac
+    return out_R, out_g, out_f, nfar, nnear

@@ -5,6 +5,7 @@ holds a triangle incident to one of its targets; the partition covers everything
 import numpy as np
 import pytest
 
+from oracle import field as F
 from oracle import operator as O
 from oracle import treecode as T
 from paper_1301_5914_amd import inputs
@@ -123,3 +124,41 @@ def test_parent_charges_are_the_children_charges_interpolated(sphere):
             carried[m] += Qc[m] @ Lk
     for m in range(3):
         np.testing.assert_allclose(carried[m], Qp[m], rtol=1e-10, atol=1e-10 * np.max(np.abs(Qp[m])))
+
+
+def _field_points(n, seed):
+    """A potential-map lattice n^3 over [-8, 8]^3 A around the 4 A sphere, less the points
+    within 0.6 A of it, in a seeded order."""
+    ax = np.linspace(-8.0, 8.0, n)
+    pts = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), axis=-1).reshape(-1, 3)
+    pts = pts[np.abs(np.linalg.norm(pts, axis=1) - 4.0) > 0.6]
+    return pts[np.random.default_rng(seed).permutation(pts.shape[0])]
+
+
+def test_field_theta_zero_is_the_direct_sum(sphere):
+    p, st = sphere
+    u = inputs.random_vector(2 * p.nv, 5)
+    pts = _field_points(7, 6)
+    eps = p.eps2 / p.eps1
+    R, gR, fr, nfar, nnear = T.field_terms(st, u, pts, p.kappa, eps, theta=0.0, degree=3, leaf=256, batch=64)
+    assert nfar == 0 and nnear == -(-pts.shape[0] // 64) * 20
+    R0, g0, f0 = F.reaction_terms(st, u, pts, p.kappa, eps)
+    for a, b in ((R, R0), (gR, g0), (fr, f0)):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * np.max(np.abs(b)))
+
+
+def test_field_error_falls_with_degree(sphere):
+    """Against the direct sums: R, its gradient and the solid angle, inside and outside."""
+    p, st = sphere
+    u = inputs.random_vector(2 * p.nv, 7)
+    pts = _field_points(12, 8)
+    eps = p.eps2 / p.eps1
+    ref = F.reaction_terms(st, u, pts, p.kappa, eps)
+    errs = []
+    for n in (2, 4, 6):
+        *got, nfar, nnear = T.field_terms(st, u, pts, p.kappa, eps, theta=0.6, degree=n, leaf=128, batch=64)
+        assert nfar > 0 and nnear > 0
+        errs.append([_rel(g, r) for g, r in zip(got, ref)])
+    errs = np.array(errs)
+    assert np.all(errs[0] > errs[1]) and np.all(errs[1] > errs[2]), errs
+    assert np.all(errs[2] < 1e-6), errs
