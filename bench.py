@@ -97,27 +97,37 @@ def cpu_baseline(prob, seconds: float, workers: int, lower: bool = False):
 FIELD_FLOPS_PER_PAIR = {True: 60, False: 41}   # R, grad R and the solid angle per (point, node)
 
 
-def field_bench(pb, prob, grid, res, mixed, n_nodes):
-    """Potential map: hobi_field on a grid^3 lattice over the surface's bounding box grown by
-    30% (points inside and outside), for the solved surface of the last timed step."""
-    from paper_1301_5914_amd import hobi
-    unit = 4.0 * np.pi * 332.0716
-    u = np.concatenate([res["phi"], res["dphi"]]) / unit
+def map_points(prob, grid):
+    """A grid^3 lattice over the surface's bounding box grown by 30% (inside and outside)."""
     lo, hi = prob.xyz.min(axis=0), prob.xyz.max(axis=0)
     c, h = 0.5 * (lo + hi), 0.65 * (hi - lo)
     axes = [np.linspace(c[k] - h[k], c[k] + h[k], grid) for k in range(3)]
-    pts = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+    return np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+
+
+def timed_map(pb, u, pts, reps=3):
+    """hobi_field on pts: (outputs, median whole-call ms, median field-kernel ms)."""
     pb.field(u, pts[:1024])                       # work space and code warm-up
     times, kern = [], []
     out = None
-    for _ in range(3):
+    for _ in range(reps):
         pb.reset_stats()
         t0 = time.perf_counter()
         out = pb.field(u, pts)
         times.append((time.perf_counter() - t0) * 1e3)
         st = pb.stats()
         kern.append(st["ms_field_kernel"] / max(1, st["field_launches"]))
-    k_ms = float(np.median(kern))
+    return out, float(np.median(times)), float(np.median(kern))
+
+
+def field_bench(pb, prob, grid, res, mixed, n_nodes):
+    """Potential map: hobi_field on a grid^3 lattice over the surface's bounding box grown by
+    30% (points inside and outside), for the solved surface of the last timed step."""
+    from paper_1301_5914_amd import hobi
+    unit = 4.0 * np.pi * 332.0716
+    u = np.concatenate([res["phi"], res["dphi"]]) / unit
+    pts = map_points(prob, grid)
+    out, call_ms, k_ms = timed_map(pb, u, pts)
     pairs = pts.shape[0] * n_nodes
     flops = FIELD_FLOPS_PER_PAIR[prob.kappa > 0]
     achieved = flops * pairs / (k_ms * 1e-3) / 1e12
@@ -127,14 +137,15 @@ def field_bench(pb, prob, grid, res, mixed, n_nodes):
     e_field = 0.5 * float(np.sum(prob.q * at_q["reac"]))
     return {"grid": grid, "points": int(pts.shape[0]), "pairs": int(pairs),
             "kernel_ms": k_ms, "kernel_gpairs_per_s": pairs / (k_ms * 1e-3) / 1e9,
-            "call_ms_median": float(np.median(times)),
+            "call_ms_median": call_ms,
             "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                          "frac": achieved / peak, "flops_per_pair": flops},
             "inside_fraction": float(np.mean(out["inside"])),
             "energy_from_field_rel": abs(e_field / res["energy"] - 1)}
 
 
-def tree_bench(ctx, stream, prob, theta, degree, leaf, batch, mixed, dense_pb, dense_res, dense_mv_ms, pairs_mv):
+def tree_bench(ctx, stream, prob, theta, degree, leaf, batch, mixed, dense_pb, dense_res, dense_mv_ms, pairs_mv,
+               grid=0):
     """The treecode form of the matvec on the same problem: matvec time (HIP events, median
     of 20), the dense pair count it replaces per second, its error against the dense matvec
     on a random vector, and the solve with it against the dense solve."""
@@ -163,7 +174,23 @@ def tree_bench(ctx, stream, prob, theta, degree, leaf, batch, mixed, dense_pb, d
     pb.solve()                                        # warm-up
     res = [pb.solve() for _ in range(2)]
     mv = float(np.median(ms))
-    return {"theta": theta, "degree": degree, "leaf": leaf, "batch": batch,
+    fmap = None
+    if grid > 0:
+        # the potential map of the dense solution, with the treecode and with the dense sums
+        unit = 4.0 * np.pi * 332.0716
+        uu = np.concatenate([dense_res["phi"], dense_res["dphi"]]) / unit
+        pts = map_points(prob, grid)
+        od, d_call, d_kern = timed_map(dense_pb, uu, pts)
+        ot, t_call, t_kern = timed_map(pb, uu, pts)
+        fst = pb.stats()
+        rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+        fmap = {"grid": grid, "points": int(pts.shape[0]),
+                "far_pairs": fst["field_tree_far_pairs"], "near_pairs": fst["field_tree_near_pairs"],
+                "kernel_ms": t_kern, "call_ms_median": t_call, "dense_kernel_ms": d_kern,
+                "dense_call_ms_median": d_call, "speedup_kernel": d_kern / t_kern, "speedup_call": d_call / t_call,
+                "phi_rel_err_vs_dense": rel(ot["phi"], od["phi"]), "field_rel_err_vs_dense": rel(ot["field"], od["field"]),
+                "inside_mismatches": int(np.sum(ot["inside"] != od["inside"]))}
+    return {"theta": theta, "degree": degree, "leaf": leaf, "batch": batch, "map": fmap,
             "far_pairs": st["tree_far_pairs"], "near_pairs": st["tree_near_pairs"],
             "matvec_ms_median": mv, "dense_matvec_ms_median": dense_mv_ms,
             "speedup_over_dense_matvec": dense_mv_ms / mv,
@@ -436,7 +463,7 @@ def main():
     if args.tree_theta > 0 and not lower:
         out["tree"] = tree_bench(ctx, stream, prob, args.tree_theta, args.tree_degree, args.tree_leaf,
                                  args.tree_batch, mixed, pb,
-                                 results[-1], out["matvec_ms_median"], pairs_mv)
+                                 results[-1], out["matvec_ms_median"], pairs_mv, grid=args.field_map)
     if not args.no_compare:
         # the other precision on the same problem (outside the timed region)
         pb.set_precision(hobi.HOBI_FP64 if mixed else hobi.HOBI_MIXED)

@@ -118,6 +118,8 @@ typedef struct hobi_stats {
     int64_t field_launches;
     int64_t tree_far_pairs;    /* treecode: (batch, cluster) pairs taken by the proxies      */
     int64_t tree_near_pairs;   /* and (batch, leaf) pairs summed directly (0 without it)     */
+    int64_t field_tree_far_pairs;  /* the same for the last hobi_field call's point batches   */
+    int64_t field_tree_near_pairs;
 } hobi_stats;
 
 /* Fills p with the defaults listed in hobi_params. */
@@ -204,6 +206,11 @@ hobi_status hobi_energy(hobi_problem pb, const double* u, int32_t on_device,
  *   phi [np] total potential, kcal/(mol e);   field [np][3] E, kcal/(mol e A);
  *   reac [np] R;   reac_field [np][3] -grad R;   inside [np] 1 inside, 0 outside.
  * The pair sums run in the problem's precision (mixed: FP32 pairs, FP64 accumulation).
+ * With tree_theta > 0 the sums over the surface take the problem's treecode: the points
+ * in Morton order form batches of 256 that walk its cluster tree with the acceptance test
+ * alone (no incidence rule off the surface); accepted clusters add R, grad R and the
+ * solid angle from their proxy charges (the solid angle from the charge of the unit
+ * double layer), near leaves their nodes directly.
  * There is no near-singular treatment: within about one edge length of the surface the
  * rule's error grows, and a point on the surface is not a valid argument.
  * Synchronous: returns when the outputs are written.  The work space it allocates on the

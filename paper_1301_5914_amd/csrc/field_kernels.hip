@@ -225,15 +225,202 @@ __global__ __launch_bounds__(kBlock) void field_f64_kernel(const double* __restr
                                   partial + (size_t)w * (kParts * kSlot), kSlot);
 }
 
+// Treecode far items (hobi_params.tree_theta > 0): the kWave * TPL points from `base`
+// against one cluster's proxies s_k with the charges Q0, Qk, Qs (d = x - s_k, a = e^-kappa r):
+//   R += sum Q0/r + a Qk/r,   grad R -= sum (Q0 + a (1 + kappa r) Qk) d / r^3,   Omega += sum Qs/r,
+// rows as the direct waves'.  FP32: positions in the scaled frame, q0a = s32 Q0, qka = s32 Qk,
+// qs = s32 Qs, so that the gradient comes out times 1/s32 like the direct rows.
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void far_field_f32_wave(const float* __restrict__ pts, int np_pad,
+                                                   const ProxyF* __restrict__ prox, int P, int base,
+                                                   double* __restrict__ prow, int slot) {
+    constexpr float kLn2 = 0.693147180559945309f;
+    const int lane = (int)(threadIdx.x % kWave);
+    float tx[TPL], ty[TPL], tz[TPL];
+    double acc[kParts][TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+        const int t = base + lane + k * kWave;
+        tx[k] = pts[t];
+        ty[k] = pts[(size_t)np_pad + t];
+        tz[k] = pts[2 * (size_t)np_pad + t];
+#pragma unroll
+        for (int c = 0; c < kParts; ++c) acc[c][k] = 0.0;
+    }
+    const const_as<ProxyF>* cp = as_constant(prox);
+    for (int k0 = 0; k0 < P; k0 += kFold) {
+        const int k1 = min(k0 + kFold, P);
+        float a[kParts][TPL];
+#pragma unroll
+        for (int c = 0; c < kParts; ++c)
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) a[c][k] = 0.0f;
+        ProxyF pr = load_proxy(cp, k0);
+        for (int q = k0; q < k1; ++q) {
+            const ProxyF next = load_proxy(cp, min(q + 1, k1 - 1));
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) {
+                const float dx = tx[k] - pr.x, dy = ty[k] - pr.y, dz = tz[k] - pr.z;
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                const float rinv3 = rinv * rinv * rinv;
+                float c;
+                if (KAPPA0) {
+                    c = pr.q0a + pr.qka;
+                    a[0][k] = fmaf(rinv, c, a[0][k]);
+                } else {
+                    const float r = r2 * rinv;
+                    const float e = __builtin_amdgcn_exp2f(-r);           // exp(-kappa r)
+                    const float zp1 = fmaf(r, kLn2, 1.0f);               // 1 + kappa r
+                    a[0][k] = fmaf(rinv, fmaf(e, pr.qka, pr.q0a), a[0][k]);
+                    c = fmaf(e * zp1, pr.qka, pr.q0a);
+                }
+                const float g = -rinv3 * c;
+                a[1][k] = fmaf(g, dx, a[1][k]);
+                a[2][k] = fmaf(g, dy, a[2][k]);
+                a[3][k] = fmaf(g, dz, a[3][k]);
+                a[4][k] = fmaf(rinv, pr.qs, a[4][k]);
+            }
+            pr = next;
+        }
+#pragma unroll
+        for (int c = 0; c < kParts; ++c)
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) acc[c][k] += (double)a[c][k];
+    }
+#pragma unroll
+    for (int c = 0; c < kParts; ++c)
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) prow[(size_t)c * slot + lane + k * kWave] = acc[c][k];
+}
+
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void far_field_f32_narrow(int live, const float* __restrict__ pts, int np_pad,
+                                                     const ProxyF* __restrict__ prox, int P, int base,
+                                                     double* __restrict__ prow, int slot) {
+    if constexpr (TPL > 1) {
+        if (live <= kWave * TPL / 2) {
+            far_field_f32_narrow<TPL / 2, KAPPA0>(live, pts, np_pad, prox, P, base, prow, slot);
+            return;
+        }
+    }
+    far_field_f32_wave<TPL, KAPPA0>(pts, np_pad, prox, P, base, prow, slot);
+}
+
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void far_field_f64_wave(const double* __restrict__ pts, int np_pad,
+                                                   const ProxyD* __restrict__ prox, int P, double kappa, int base,
+                                                   double* __restrict__ prow, int slot) {
+    const int lane = (int)(threadIdx.x % kWave);
+    double tx[TPL], ty[TPL], tz[TPL], a[kParts][TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+        const int t = base + lane + k * kWave;
+        tx[k] = pts[t];
+        ty[k] = pts[(size_t)np_pad + t];
+        tz[k] = pts[2 * (size_t)np_pad + t];
+#pragma unroll
+        for (int c = 0; c < kParts; ++c) a[c][k] = 0.0;
+    }
+    const const_as<ProxyD>* cp = as_constant(prox);
+    for (int q = 0; q < P; ++q) {
+        const ProxyD pr = load_proxy(cp, q);
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+            const double dx = tx[k] - pr.x, dy = ty[k] - pr.y, dz = tz[k] - pr.z;
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            const double rinv = rsqrt_f64(r2);
+            const double rinv3 = rinv * rinv * rinv;
+            double c;
+            if (KAPPA0) {
+                c = pr.q0 + pr.qk;
+                a[0][k] = fma(rinv, c, a[0][k]);
+            } else {
+                const double z = kappa * (r2 * rinv);
+                const double e = exp_neg_f64(z);
+                a[0][k] = fma(rinv, fma(e, pr.qk, pr.q0), a[0][k]);
+                c = fma(e * (1.0 + z), pr.qk, pr.q0);
+            }
+            const double g = -rinv3 * c;
+            a[1][k] = fma(g, dx, a[1][k]);
+            a[2][k] = fma(g, dy, a[2][k]);
+            a[3][k] = fma(g, dz, a[3][k]);
+            a[4][k] = fma(rinv, pr.qs, a[4][k]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kParts; ++c)
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) prow[(size_t)c * slot + lane + k * kWave] = a[c][k];
+}
+
+template <int TPL, bool KAPPA0>
+__device__ __forceinline__ void far_field_f64_narrow(int live, const double* __restrict__ pts, int np_pad,
+                                                     const ProxyD* __restrict__ prox, int P, double kappa, int base,
+                                                     double* __restrict__ prow, int slot) {
+    if constexpr (TPL > 1) {
+        if (live <= kWave * TPL / 2) {
+            far_field_f64_narrow<TPL / 2, KAPPA0>(live, pts, np_pad, prox, P, kappa, base, prow, slot);
+            return;
+        }
+    }
+    far_field_f64_wave<TPL, KAPPA0>(pts, np_pad, prox, P, kappa, base, prow, slot);
+}
+
+// One wave per treecode work item {slot, far, cluster, -} of the points; the item's partial
+// rows are its index: near items sum the leaf's nodes directly, far items its proxies.
+template <int TPL, bool KAPPA0>
+__global__ __launch_bounds__(kBlock) void field_tree_f32_kernel(const int4* __restrict__ items, int nitems,
+                                                                const float* __restrict__ pts, int np, int np_pad,
+                                                                const NodeF* __restrict__ nodes,
+                                                                const int2* __restrict__ clu_range,
+                                                                const ProxyF* __restrict__ prox, int P,
+                                                                double* __restrict__ partial) {
+    const int w = xcd_logical_block() * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    if (w >= nitems) return;
+    constexpr int kSlot = kWave * TPL;
+    const int4 it = make_int4(as_constant(items)[w].x, as_constant(items)[w].y, as_constant(items)[w].z, 0);
+    const int base = it.x * kSlot;
+    double* prow = partial + (size_t)w * (kParts * kSlot);
+    if (it.y == 0)
+        field_f32_narrow<TPL, KAPPA0>(np - base, pts, np_pad, nodes, base, as_constant(clu_range)[it.z].x,
+                                      as_constant(clu_range)[it.z].y, prow, kSlot);
+    else
+        far_field_f32_narrow<TPL, KAPPA0>(np - base, pts, np_pad, prox + (size_t)it.z * P, P, base, prow, kSlot);
+}
+
+template <int TPL, bool KAPPA0>
+__global__ __launch_bounds__(kBlock) void field_tree_f64_kernel(const int4* __restrict__ items, int nitems,
+                                                                const double* __restrict__ pts, int np, int np_pad,
+                                                                const NodeD* __restrict__ nodes, double kappa,
+                                                                const int2* __restrict__ clu_range,
+                                                                const ProxyD* __restrict__ prox, int P,
+                                                                double* __restrict__ partial) {
+    const int w = xcd_logical_block() * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    if (w >= nitems) return;
+    constexpr int kSlot = kWave * TPL;
+    const int4 it = make_int4(as_constant(items)[w].x, as_constant(items)[w].y, as_constant(items)[w].z, 0);
+    const int base = it.x * kSlot;
+    double* prow = partial + (size_t)w * (kParts * kSlot);
+    if (it.y == 0)
+        field_f64_narrow<TPL, KAPPA0>(np - base, pts, np_pad, nodes, kappa, base, as_constant(clu_range)[it.z].x,
+                                      as_constant(clu_range)[it.z].y, prow, kSlot);
+    else
+        far_field_f64_narrow<TPL, KAPPA0>(np - base, pts, np_pad, prox + (size_t)it.z * P, P, kappa, base, prow,
+                                          kSlot);
+}
+
 // 64 points per block of 256 threads: wave k sums the point's rows of node groups k, k + 4,
-// ... into two running sums by turn (fixed order), the four waves' sums are added in a
-// fixed order through LDS; then the frame scale of the gradient, the Coulomb part of the
+// ... into two running sums by turn (fixed order), or, with slot_row, the rows of the
+// point's slot's treecode items k, k + 4, ... in item order; the four waves' sums are added
+// in a fixed order through LDS; then the frame scale of the gradient, the Coulomb part of the
 // charges, the side and the outputs in kcal/(mol e) [A^-1]: out[p] = {phi, Ex, Ey, Ez, R,
 // -dR/dx, -dR/dy, -dR/dz, Omega}, inside[p].
 constexpr int kCombPts = 64, kCombWays = 4;
 
 __global__ __launch_bounds__(kCombPts * kCombWays) void field_combine_kernel(
-    const double* __restrict__ partial, int np, int slot, int slots, int groups, double gscale,
+    const double* __restrict__ partial, const int* __restrict__ slot_row, int np, int slot, int slots, int groups,
+    double gscale,
     const double* __restrict__ pts, int np_pad, const double* __restrict__ qpos, const double* __restrict__ q,
     int nc, double eps1, double eps, double* __restrict__ out, int* __restrict__ inside) {
     __shared__ double red[kCombWays][kParts][kCombPts];
@@ -242,7 +429,14 @@ __global__ __launch_bounds__(kCombPts * kCombWays) void field_combine_kernel(
     double v[kParts];
 #pragma unroll
     for (int c = 0; c < kParts; ++c) v[c] = 0.0;
-    if (p < np) {
+    if (p < np && slot_row) {
+        const int s = p / slot, o = p - s * slot;
+        for (int r = slot_row[s] + way; r < slot_row[s + 1]; r += kCombWays) {
+            const double* col = partial + (size_t)r * kParts * slot + o;
+#pragma unroll
+            for (int c = 0; c < kParts; ++c) v[c] += col[(size_t)c * slot];
+        }
+    } else if (p < np) {
         const int s = p / slot, o = p - s * slot;
         const size_t row_step = (size_t)slots * kParts * slot;   // next group, same slot
         const double* col = partial + ((size_t)way * slots + s) * kParts * slot + o;
@@ -338,11 +532,34 @@ hipError_t launch_field_pairs(const DeviceProblem& p, const FieldWork& f, const 
     return hipGetLastError();
 }
 
+hipError_t launch_field_tree_pairs(const DeviceProblem& p, const FieldWork& f, int nitems, bool mixed,
+                                   hipStream_t s) {
+    const TreePlan& t = p.tree;
+    const bool k0 = p.kappa == 0.0;
+    const dim3 grid(nblk(nitems, kWavesPerBlock));
+    if (mixed) {
+        if (k0)
+            hipLaunchKernelGGL((field_tree_f32_kernel<kFieldTpl32, true>), grid, dim3(kBlock), 0, s, f.items, nitems,
+                               f.pts32, f.np, f.np_pad, p.node32, t.clu_range, t.prox32, t.nprox, f.partial);
+        else
+            hipLaunchKernelGGL((field_tree_f32_kernel<kFieldTpl32, false>), grid, dim3(kBlock), 0, s, f.items, nitems,
+                               f.pts32, f.np, f.np_pad, p.node32, t.clu_range, t.prox32, t.nprox, f.partial);
+    } else {
+        if (k0)
+            hipLaunchKernelGGL((field_tree_f64_kernel<kFieldTpl64, true>), grid, dim3(kBlock), 0, s, f.items, nitems,
+                               f.pts64, f.np, f.np_pad, p.node64, p.kappa, t.clu_range, t.prox64, t.nprox, f.partial);
+        else
+            hipLaunchKernelGGL((field_tree_f64_kernel<kFieldTpl64, false>), grid, dim3(kBlock), 0, s, f.items, nitems,
+                               f.pts64, f.np, f.np_pad, p.node64, p.kappa, t.clu_range, t.prox64, t.nprox, f.partial);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_field_combine(const DeviceProblem& p, const FieldWork& f, const PairPlan& pl, bool mixed,
-                                hipStream_t s) {
+                                hipStream_t s, const int* slot_row) {
     const double gscale = mixed ? p.s32 : 1.0;
     hipLaunchKernelGGL(field_combine_kernel, dim3(nblk(f.np, kCombPts)), dim3(kCombPts * kCombWays), 0, s,
-                       f.partial, f.np, pl.slot, pl.slots, pl.groups, gscale, f.pts64, f.np_pad, p.qpos, p.q,
+                       f.partial, slot_row, f.np, pl.slot, pl.slots, pl.groups, gscale, f.pts64, f.np_pad, p.qpos, p.q,
                        p.nc, p.eps1, p.eps, f.out, f.inside);
     return hipGetLastError();
 }

@@ -354,7 +354,7 @@ void free_problem(hobi_problem pb) {
     }
     {
         FieldWork& f = pb->field;
-        void* fp[] = {f.pts64, f.pts32, f.partial, f.gstart, f.out, f.inside};
+        void* fp[] = {f.pts64, f.pts32, f.partial, f.gstart, f.out, f.inside, f.items, f.slot_row};
         for (void* p : fp)
             if (p) (void)hipFree(p);
         f = FieldWork{};
@@ -471,6 +471,7 @@ hobi_status build_tree_plan(hobi_problem pb) {
     }
     t.lev_off[t.nlev] = (int)cl.size();
     const int root = level[0];
+    t.root = root;
     t.nclu = (int)cl.size();
     // centre of the box [lo, hi] into c; returns its diagonal
     auto box_centre = [](const double lo[3], const double hi[3], double c[3]) {
@@ -492,6 +493,9 @@ hobi_status build_tree_plan(hobi_problem pb) {
         crange[c] = make_int2(k.a, k.b);
         cchild[c] = make_int2(k.c0, k.c1);
     }
+    t.h_cen = ccen;
+    t.h_rad = crad;
+    t.h_child = cchild;
     // the walk of every batch: far (1) and near (0) clusters
     std::vector<std::vector<std::pair<int, int>>> walk(t.nbatch);
     t.nfar = t.nnear = 0;
@@ -1031,13 +1035,21 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
     hobi_status st = to_internal(pb, u, on_device, pb->u_in);
     if (st != HOBI_OK) return st;
     HIPCHK(c, launch_gather(d, pb->u_in, mixed, s));
-    // the split over waves, points in Morton order
-    const int res = field_resident_waves(c->device, mixed);
-    if (res < 1) return fail(c, HOBI_E_HIP, "field kernel occupancy query failed");
+    // the split over waves (dense sum) or the treecode's slots of points, points in Morton order
+    const bool tree = d.tree.on != 0;
     PairPlan pl{};
     std::vector<int> gs;
-    if (!make_pair_plan(np, d.nn, mixed ? kFieldTpl32 : kFieldTpl64, res, &pl, &gs))
-        return fail(c, HOBI_E_ARG, "too many points: %d", np);
+    if (tree) {
+        pl.tpl = mixed ? kFieldTpl32 : kFieldTpl64;
+        pl.slot = 64 * pl.tpl;
+        pl.slots = (np + pl.slot - 1) / pl.slot;
+        pl.groups = 1;
+    } else {
+        const int res = field_resident_waves(c->device, mixed);
+        if (res < 1) return fail(c, HOBI_E_HIP, "field kernel occupancy query failed");
+        if (!make_pair_plan(np, d.nn, mixed ? kFieldTpl32 : kFieldTpl64, res, &pl, &gs))
+            return fail(c, HOBI_E_ARG, "too many points: %d", np);
+    }
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int i = 0; i < np; ++i)
         for (int k = 0; k < 3; ++k) {
@@ -1048,7 +1060,7 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
     const std::vector<int> order = morton_order(pv, np, lo, hi);   // sorted position -> caller index
     FieldWork& f = pb->field;
     f.np = np;
-    f.np_pad = pl.slots * pl.slot;
+    f.np_pad = tree ? round_up(np, kFieldTreeBatch) : pl.slots * pl.slot;
     std::vector<double> h64(3 * (size_t)f.np_pad);
     std::vector<float> h32(3 * (size_t)f.np_pad);
     for (int j = 0; j < f.np_pad; ++j) {
@@ -1059,25 +1071,84 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
             h32[(size_t)k * f.np_pad + j] = (float)((x - d.center[k]) * d.s32);
         }
     }
-    const size_t nparts = (size_t)pl.workers * 5 * pl.slot;
+    // treecode: each batch of kFieldTreeBatch points walks the cluster tree (accepted when
+    // r_b + r_c <= theta |c_b - c_c|; the points are off the surface, so no incidence rule),
+    // work items per slot in walk order
+    std::vector<int4> items;
+    std::vector<int> srow(1, 0);
+    if (tree) {
+        const TreePlan& t = d.tree;
+        const int nb = (np + kFieldTreeBatch - 1) / kFieldTreeBatch;
+        std::vector<std::vector<std::pair<int, int>>> walk(nb);
+        f.tree_far = f.tree_near = 0;
+        std::vector<int> stack;
+        for (int bi = 0; bi < nb; ++bi) {
+            const int a = bi * kFieldTreeBatch, b = std::min(a + kFieldTreeBatch, np);
+            double blo[3] = {1e300, 1e300, 1e300}, bhi[3] = {-1e300, -1e300, -1e300};
+            for (int i = a; i < b; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    const double v = h64[(size_t)k * f.np_pad + i];
+                    blo[k] = std::min(blo[k], v), bhi[k] = std::max(bhi[k], v);
+                }
+            double cb[3], q = 0;
+            for (int k = 0; k < 3; ++k) cb[k] = 0.5 * (blo[k] + bhi[k]), q += (bhi[k] - blo[k]) * (bhi[k] - blo[k]);
+            const double rb = 0.5 * std::sqrt(q);
+            stack.assign(1, t.root);
+            while (!stack.empty()) {
+                const int cc = stack.back();
+                stack.pop_back();
+                const double* cen = &t.h_cen[3 * (size_t)cc];
+                const double dx = cb[0] - cen[0], dy = cb[1] - cen[1], dz = cb[2] - cen[2];
+                if (rb + t.h_rad[cc] <= pb->prm.tree_theta * std::sqrt(dx * dx + dy * dy + dz * dz)) {
+                    walk[bi].emplace_back(cc, 1);
+                    ++f.tree_far;
+                } else if (t.h_child[cc].x < 0) {
+                    walk[bi].emplace_back(cc, 0);
+                    ++f.tree_near;
+                } else {
+                    stack.push_back(t.h_child[cc].y);
+                    stack.push_back(t.h_child[cc].x);
+                }
+            }
+        }
+        for (int sl = 0; sl < pl.slots; ++sl) {
+            for (const auto& w : walk[sl * pl.slot / kFieldTreeBatch]) items.push_back(make_int4(sl, w.second, w.first, 0));
+            if (items.size() > ((size_t)1 << 30)) return fail(c, HOBI_E_ARG, "too many points for the treecode: %d", np);
+            srow.push_back((int)items.size());
+        }
+    }
+    const size_t nparts = (tree ? items.size() : (size_t)pl.workers) * 5 * pl.slot;
     hipError_t e = hipSuccess;
     if ((e = grow(&f.pts64, &f.cap_pts64, h64.size())) != hipSuccess ||
         (e = grow(&f.pts32, &f.cap_pts32, h32.size())) != hipSuccess ||
         (e = grow(&f.partial, &f.cap_partial, nparts)) != hipSuccess ||
         (e = grow(&f.gstart, &f.cap_gstart, gs.size())) != hipSuccess ||
         (e = grow(&f.out, &f.cap_out, 9 * (size_t)np)) != hipSuccess ||
-        (e = grow(&f.inside, &f.cap_inside, (size_t)np)) != hipSuccess)
+        (e = grow(&f.inside, &f.cap_inside, (size_t)np)) != hipSuccess ||
+        (tree && (e = grow(&f.items, &f.cap_items, items.size())) != hipSuccess) ||
+        (tree && (e = grow(&f.slot_row, &f.cap_slot_row, srow.size())) != hipSuccess))
         return fail(c, e == hipErrorOutOfMemory ? HOBI_E_OOM : HOBI_E_HIP, "field work space: %s",
                     hipGetErrorString(e));
     HIPCHK(c, hipMemcpyAsync(f.pts64, h64.data(), sizeof(double) * h64.size(), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(f.pts32, h32.data(), sizeof(float) * h32.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(f.gstart, gs.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
-    pl.gstart = f.gstart;
-    {
-        ScopedTimer t(pb, T_FIELD);
-        HIPCHK(c, launch_field_pairs(d, f, pl, mixed, s));
+    if (tree) {
+        HIPCHK(c, hipMemcpyAsync(f.items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(f.slot_row, srow.data(), sizeof(int) * srow.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(c, launch_tree_proxies(d, mixed, s));
+        {
+            ScopedTimer t(pb, T_FIELD);
+            HIPCHK(c, launch_field_tree_pairs(d, f, (int)items.size(), mixed, s));
+        }
+        HIPCHK(c, launch_field_combine(d, f, pl, mixed, s, f.slot_row));
+    } else {
+        HIPCHK(c, hipMemcpyAsync(f.gstart, gs.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
+        pl.gstart = f.gstart;
+        {
+            ScopedTimer t(pb, T_FIELD);
+            HIPCHK(c, launch_field_pairs(d, f, pl, mixed, s));
+        }
+        HIPCHK(c, launch_field_combine(d, f, pl, mixed, s));
     }
-    HIPCHK(c, launch_field_combine(d, f, pl, mixed, s));
     std::vector<double> ho(9 * (size_t)np);
     std::vector<int> hin((size_t)np);
     HIPCHK(c, hipMemcpyAsync(ho.data(), f.out, sizeof(double) * ho.size(), hipMemcpyDeviceToHost, s));
@@ -1159,6 +1230,8 @@ hobi_status hobi_solve(hobi_problem pb, double* phi, double* dphi, double* e_sol
     L.ms_field_kernel = pb->ms[T_FIELD];
     L.field_launches = pb->cnt[T_FIELD];
     L.tree_far_pairs = pb->d.tree.nfar;
+    L.field_tree_far_pairs = pb->field.tree_far;
+    L.field_tree_near_pairs = pb->field.tree_near;
     L.tree_near_pairs = pb->d.tree.nnear;
     if (stats) *stats = L;
     for (int i = 0; i < n; ++i)
@@ -1216,6 +1289,8 @@ hobi_status hobi_get_stats(hobi_problem pb, hobi_stats* out) {
     pb->last.ms_field_kernel = pb->ms[T_FIELD];
     pb->last.field_launches = pb->cnt[T_FIELD];
     pb->last.tree_far_pairs = pb->d.tree.nfar;
+    pb->last.field_tree_far_pairs = pb->field.tree_far;
+    pb->last.field_tree_near_pairs = pb->field.tree_near;
     pb->last.tree_near_pairs = pb->d.tree.nnear;
     *out = pb->last;
     return st;

@@ -201,6 +201,17 @@ constexpr SeriesTable series_table() {
     return t;
 }
 
+// Treecode proxy records: a point of a cluster's proxy grid with its charges (the sums over
+// the cluster's nodes of the strengths times the tensor basis and its normal derivative).
+struct ProxyD {                      // proxy point and its charges (64 B); qs: solid angle
+    double x, y, z, q0, qk, qk2, qs, pad;
+};
+struct ProxyF {                      // FP32 copy in the frame of the FP32 node records (32 B):
+    float x, y, z;                   // positions shifted and scaled like the targets
+    float q0a, qka;                  // s32 Q0, s32 Qk           (row 1)
+    float q0b, qk2b;                 // s32^2 Q0, s32^2 Qk2      (row 2)
+    float qs;                        // s32 Qs                   (solid angle)
+};
 constexpr double kSeriesZ64 = 0.1;
 
 __device__ __forceinline__ void f012_f64(double z, double* f0, double* f1, double* f2) {

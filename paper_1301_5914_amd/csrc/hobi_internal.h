@@ -52,14 +52,6 @@ struct PairPlan {
 constexpr int kTreeMaxDeg = 7;       // (n + 1)^3 <= 512 proxies per cluster
 constexpr int kTreeMaxLevels = 40;
 constexpr double kTreeGrow = 1e-6;   // proxy box = node box grown by this fraction of its diagonal (+ 1e-12 A)
-struct ProxyD {                      // proxy point and its three charges (64 B)
-    double x, y, z, q0, qk, qk2, pad0, pad1;
-};
-struct ProxyF {                      // FP32 copy in the frame of the FP32 node records (32 B):
-    float x, y, z;                   // positions shifted and scaled like the targets
-    float q0a, qka;                  // s32 Q0, s32 Qk           (row 1)
-    float q0b, qk2b, pad;            // s32^2 Q0, s32^2 Qk2      (row 2)
-};
 struct TreePlan {
     int on = 0;
     int degree = 0, nprox = 0;       // n, (n + 1)^3
@@ -71,6 +63,9 @@ struct TreePlan {
     int2* clu_range = nullptr;       // [nclu] node range of each cluster
     double* clu_box = nullptr;       // [nclu][6] grown box: lo[3], hi[3]
     int2* clu_child = nullptr;       // [nclu] children of a parent ((-1, -1) for a leaf)
+    int root = 0;                    // the root cluster
+    std::vector<double> h_cen, h_rad;  // host copies: centre [nclu][3] and radius of each cluster
+    std::vector<int2> h_child;         // and its children, for the walks of hobi_field
     ProxyD* prox64 = nullptr;        // [nclu][nprox]
     ProxyF* prox32 = nullptr;        // [nclu][nprox]
     int4* items[2] = {nullptr, nullptr};   // [0] FP64, [1] mixed: {slot, far, cluster, 0}, slot-major
@@ -162,7 +157,11 @@ struct FieldWork {
     int* gstart = nullptr;        // [groups + 1]
     double* out = nullptr;        // [np][9] phi, E, R, -grad R, solid-angle fraction
     int* inside = nullptr;        // [np]
+    int4* items = nullptr;        // treecode: work items {slot, far, cluster, 0}, slot-major
+    int* slot_row = nullptr;      // treecode: items of slot s are [slot_row[s], slot_row[s + 1])
     size_t cap_pts64 = 0, cap_pts32 = 0, cap_partial = 0, cap_gstart = 0, cap_out = 0, cap_inside = 0;
+    size_t cap_items = 0, cap_slot_row = 0;
+    int64_t tree_far = 0, tree_near = 0;   // accepted and near (batch, cluster) pairs of the last call
 };
 // Waves of the mixed or FP64 field kernel the device holds at once (0 on error).
 int field_resident_waves(int device, bool mixed);
@@ -170,8 +169,13 @@ int field_resident_waves(int device, bool mixed);
 // with the same precision), then the per-point combine.
 hipError_t launch_field_pairs(const DeviceProblem& p, const FieldWork& f, const PairPlan& plan, bool mixed,
                               hipStream_t s);
+// slot_row non-null: the rows of slot s are the treecode items slot_row[s] .. slot_row[s + 1] - 1
 hipError_t launch_field_combine(const DeviceProblem& p, const FieldWork& f, const PairPlan& plan, bool mixed,
-                                hipStream_t s);
+                                hipStream_t s, const int* slot_row = nullptr);
+// treecode field (proxy charges computed): one wave per item of f.items, nitems of them
+constexpr int kFieldTreeBatch = 64 * kFieldTpl32;   // points per batch: one FP32 field slot
+hipError_t launch_field_tree_pairs(const DeviceProblem& p, const FieldWork& f, int nitems, bool mixed,
+                                   hipStream_t s);
 hipError_t launch_permute(const double* in, double* out, const int* perm, int nv, bool to_internal,
                           hipStream_t s);
 

@@ -39,6 +39,20 @@ __device__ __forceinline__ NodeF load_node(const const_as<NodeF>* p, int s) {
     return n;
 }
 
+__device__ __forceinline__ ProxyF load_proxy(const const_as<ProxyF>* p, int k) {
+    ProxyF r;
+    r.x = p[k].x, r.y = p[k].y, r.z = p[k].z, r.q0a = p[k].q0a;
+    r.qka = p[k].qka, r.q0b = p[k].q0b, r.qk2b = p[k].qk2b, r.qs = p[k].qs;
+    return r;
+}
+
+__device__ __forceinline__ ProxyD load_proxy(const const_as<ProxyD>* p, int k) {
+    ProxyD r;
+    r.x = p[k].x, r.y = p[k].y, r.z = p[k].z, r.q0 = p[k].q0, r.qk = p[k].qk, r.qk2 = p[k].qk2;
+    r.qs = p[k].qs, r.pad = 0.0;
+    return r;
+}
+
 __device__ __forceinline__ int4 load_vid(const const_as<int4>* p, int s) {
     return make_int4(p[s].x, p[s].y, p[s].z, 0);
 }

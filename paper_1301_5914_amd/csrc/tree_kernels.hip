@@ -11,6 +11,8 @@
 //                       Q0  = sum_j  Gamma_j L_k(y_j) - Phi_j grad L_k(y_j).n_j
 //                       Qk  = sum_j -Gamma_j L_k(y_j) + eps Phi_j grad L_k(y_j).n_j
 //                       Qk2 = sum_j -Gamma_j L_k(y_j) / eps + Phi_j grad L_k(y_j).n_j
+//                       Qs  = sum_j pad_j grad L_k(y_j).n_j   (pad = -w/(4 pi): the unit
+//                                                              double layer of hobi_field)
 //                     (L_k the tensor Lagrange basis, product form): the Green's functions
 //                     interpolated in the source point, so that a far cluster's two rows
 //                     are sum_k G0 Q0 + Gk Qk and sum_k dG0/dnu_x Q0 + dGk/dnu_x Qk2 at s_k
@@ -73,9 +75,9 @@ __device__ __forceinline__ double cheb_point(double lo, double hi, int a, int n)
 // The FP64 proxy record and its FP32 copy (positions in the frame of the FP32 targets).
 __device__ __forceinline__ void write_proxy(ProxyD* __restrict__ prox64, ProxyF* __restrict__ prox32, size_t at,
                                             double x, double y, double z, double q0, double qk, double qk2,
-                                            int mixed, double s32, double cx, double cy, double cz) {
+                                            double qs, int mixed, double s32, double cx, double cy, double cz) {
     ProxyD pd{};
-    pd.x = x, pd.y = y, pd.z = z, pd.q0 = q0, pd.qk = qk, pd.qk2 = qk2;
+    pd.x = x, pd.y = y, pd.z = z, pd.q0 = q0, pd.qk = qk, pd.qk2 = qk2, pd.qs = qs;
     prox64[at] = pd;
     if (mixed) {
         ProxyF pf{};
@@ -86,6 +88,7 @@ __device__ __forceinline__ void write_proxy(ProxyD* __restrict__ prox64, ProxyF*
         pf.qka = (float)(s32 * qk);
         pf.q0b = (float)(s32 * s32 * q0);
         pf.qk2b = (float)(s32 * s32 * qk2);
+        pf.qs = (float)(s32 * qs);
         prox32[at] = pf;
     }
 }
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
     __shared__ double inv[3][kTreeMaxDeg + 1][kTreeMaxDeg + 1];
     __shared__ double lv[kChunk][3][kTreeMaxDeg + 1];
     __shared__ double dv[kChunk][3][kTreeMaxDeg + 1];
-    __shared__ double ng[kChunk], np_[kChunk], nn3[kChunk][3];
+    __shared__ double ng[kChunk], np_[kChunk], nw[kChunk], nn3[kChunk][3];
     const int c = blockIdx.x;
     const int n1 = n + 1, P = n1 * n1 * n1;
     const int2 rg = clu_range[c];
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
     __syncthreads();
     inverse_differences(pt, inv, n1);
     __syncthreads();
-    double q0[2] = {0.0, 0.0}, qk[2] = {0.0, 0.0}, qk2[2] = {0.0, 0.0};
+    double q0[2] = {0.0, 0.0}, qk[2] = {0.0, 0.0}, qk2[2] = {0.0, 0.0}, qs[2] = {0.0, 0.0};
     int ka[2], kb[2], kc[2];
     for (int h = 0; h < 2; ++h) {
         const int k = threadIdx.x + h * kBlock;
@@ -137,6 +140,7 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
             const NodeD& nd = nodes[j0 + threadIdx.x];
             ng[threadIdx.x] = nd.g;
             np_[threadIdx.x] = nd.p;
+            nw[threadIdx.x] = nd.pad;          // -w / (4 pi): the solid-angle weight
             nn3[threadIdx.x][0] = nd.nx;
             nn3[threadIdx.x][1] = nd.ny;
             nn3[threadIdx.x][2] = nd.nz;
@@ -153,6 +157,7 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
                 q0[h] += gL - pG;
                 qk[h] += -gL + eps * pG;
                 qk2[h] += -gL / eps + pG;
+                qs[h] += nw[i] * G;
             }
         }
         __syncthreads();
@@ -161,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
         const int k = threadIdx.x + h * kBlock;
         if (k >= P) continue;
         write_proxy(prox64, prox32, (size_t)c * P + k, pt[0][ka[h]], pt[1][kb[h]], pt[2][kc[h]], q0[h], qk[h], qk2[h],
-                    mixed, s32, cx, cy, cz);
+                    qs[h], mixed, s32, cx, cy, cz);
     }
 }
 
@@ -179,8 +184,9 @@ __global__ __launch_bounds__(kBlock) void upward_kernel(int first, const int2* _
     __shared__ double inv[3][M][M];
     __shared__ double cp[2][3][M];          // children's 1D points
     __shared__ double lt[2][3][M][M];       // l_a(parent) at the children's points b
-    __shared__ double qc[2][3][MP];         // children's charges
-    __shared__ double t1[3][MP], t2[3][MP]; // partial contractions
+    constexpr int NQ = 4;                   // charges: q0, qk, qk2, qs
+    __shared__ double qc[NQ][MP];           // one child's charges
+    __shared__ double t1[NQ][MP], t2[NQ][MP]; // partial contractions
     const int c = first + blockIdx.x;
     const int n1 = n + 1, n2 = n1 * n1, P = n2 * n1;
     const int2 ch = clu_child[c];
@@ -194,13 +200,6 @@ __global__ __launch_bounds__(kBlock) void upward_kernel(int first, const int2* _
         const ProxyD* q = prox64 + (size_t)(h ? ch.y : ch.x) * P;
         cp[h][d][b] = d == 0 ? q[b * n2].x : (d == 1 ? q[b * n1].y : q[b].z);
     }
-    for (int e = threadIdx.x; e < 2 * P; e += kBlock) {
-        const int h = e / P, k = e % P;
-        const ProxyD& q = prox64[(size_t)(h ? ch.y : ch.x) * P + k];
-        qc[h][0][k] = q.q0;
-        qc[h][1][k] = q.qk;
-        qc[h][2][k] = q.qk2;
-    }
     __syncthreads();
     inverse_differences(pt, inv, n1);
     __syncthreads();
@@ -210,35 +209,43 @@ __global__ __launch_bounds__(kBlock) void upward_kernel(int first, const int2* _
         lt[h][d][a][b] = lagrange_1d(pt[d], inv[d][a], n1, a, cp[h][d][b], &dl);
     }
     __syncthreads();
-    double acc[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    double acc[2][NQ] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
     for (int g = 0; g < 2; ++g) {
+        for (int k = threadIdx.x; k < P; k += kBlock) {
+            const ProxyD& q = prox64[(size_t)(g ? ch.y : ch.x) * P + k];
+            qc[0][k] = q.q0;
+            qc[1][k] = q.qk;
+            qc[2][k] = q.qk2;
+            qc[3][k] = q.qs;
+        }
+        __syncthreads();
         for (int h = 0; h < 2; ++h) {            // t1[b1 b2 a3] = sum_b3 l_a3(b3) Q[b1 b2 b3]
             const int k = threadIdx.x + h * kBlock;
             if (k >= P) continue;
             const int j0 = k - k % n1, a3 = k % n1;
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            double sq[NQ] = {0.0, 0.0, 0.0, 0.0};
             for (int b = 0; b < n1; ++b) {
                 const double w = lt[g][2][a3][b];
-                s0 += w * qc[g][0][j0 + b];
-                s1 += w * qc[g][1][j0 + b];
-                s2 += w * qc[g][2][j0 + b];
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) sq[m] += w * qc[m][j0 + b];
             }
-            t1[0][k] = s0, t1[1][k] = s1, t1[2][k] = s2;
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) t1[m][k] = sq[m];
         }
         __syncthreads();
         for (int h = 0; h < 2; ++h) {            // t2[b1 a2 a3] = sum_b2 l_a2(b2) t1[b1 b2 a3]
             const int k = threadIdx.x + h * kBlock;
             if (k >= P) continue;
             const int b1 = k / n2, a2 = (k / n1) % n1, a3 = k % n1;
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            double sq[NQ] = {0.0, 0.0, 0.0, 0.0};
             for (int b = 0; b < n1; ++b) {
                 const double w = lt[g][1][a2][b];
                 const int j = b1 * n2 + b * n1 + a3;
-                s0 += w * t1[0][j];
-                s1 += w * t1[1][j];
-                s2 += w * t1[2][j];
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) sq[m] += w * t1[m][j];
             }
-            t2[0][k] = s0, t2[1][k] = s1, t2[2][k] = s2;
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) t2[m][k] = sq[m];
         }
         __syncthreads();
         for (int h = 0; h < 2; ++h) {            // Q[a1 a2 a3] += sum_b1 l_a1(b1) t2[b1 a2 a3]
@@ -247,34 +254,19 @@ __global__ __launch_bounds__(kBlock) void upward_kernel(int first, const int2* _
             const int a1 = k / n2, r = k % n2;
             for (int b = 0; b < n1; ++b) {
                 const double w = lt[g][0][a1][b];
-                acc[h][0] += w * t2[0][b * n2 + r];
-                acc[h][1] += w * t2[1][b * n2 + r];
-                acc[h][2] += w * t2[2][b * n2 + r];
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) acc[h][m] += w * t2[m][b * n2 + r];
             }
         }
-        __syncthreads();                         // t1, t2 are rewritten for the next child
+        __syncthreads();                         // qc, t1, t2 are rewritten for the next child
     }
     for (int h = 0; h < 2; ++h) {
         const int k = threadIdx.x + h * kBlock;
         if (k >= P) continue;
         const int ka = k / n2, kb = (k / n1) % n1, kc = k % n1;
         write_proxy(prox64, prox32, (size_t)c * P + k, pt[0][ka], pt[1][kb], pt[2][kc], acc[h][0], acc[h][1],
-                    acc[h][2], mixed, s32, cx, cy, cz);
+                    acc[h][2], acc[h][3], mixed, s32, cx, cy, cz);
     }
-}
-
-__device__ __forceinline__ ProxyF load_proxy(const const_as<ProxyF>* p, int k) {
-    ProxyF r;
-    r.x = p[k].x, r.y = p[k].y, r.z = p[k].z, r.q0a = p[k].q0a;
-    r.qka = p[k].qka, r.q0b = p[k].q0b, r.qk2b = p[k].qk2b, r.pad = 0.0f;
-    return r;
-}
-
-__device__ __forceinline__ ProxyD load_proxy(const const_as<ProxyD>* p, int k) {
-    ProxyD r;
-    r.x = p[k].x, r.y = p[k].y, r.z = p[k].z, r.q0 = p[k].q0, r.qk = p[k].qk, r.qk2 = p[k].qk2;
-    r.pad0 = r.pad1 = 0.0;
-    return r;
 }
 
 // FP32 far item: the kWave * TPL targets from `base` (scaled frame) against the cluster's

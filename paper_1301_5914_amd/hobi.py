@@ -53,7 +53,8 @@ class hobi_stats(ctypes.Structure):
                 ("ms_gather", ctypes.c_double), ("ms_combine", ctypes.c_double),
                 ("ms_krylov", ctypes.c_double), ("ms_field_kernel", ctypes.c_double),
                 ("field_launches", ctypes.c_int64), ("tree_far_pairs", ctypes.c_int64),
-                ("tree_near_pairs", ctypes.c_int64)]
+                ("tree_near_pairs", ctypes.c_int64), ("field_tree_far_pairs", ctypes.c_int64),
+                ("field_tree_near_pairs", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

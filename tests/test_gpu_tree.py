@@ -9,6 +9,8 @@ import os
 import numpy as np
 import pytest
 
+from oracle import COULOMB_KCAL, FOUR_PI
+from oracle import field as F
 from oracle import operator as O
 from oracle import treecode as T
 from paper_1301_5914_amd import hobi, inputs
@@ -164,6 +166,67 @@ def test_bench_workload_L6_tree_against_dense(ctx):
     et = tree.solve()["energy"]
     print(f"L6 energy dense {ed:.8f} tree {et:.8f}", flush=True)
     assert abs(et - ed) <= 1e-4 * abs(ed)
+
+
+UNIT = FOUR_PI * COULOMB_KCAL
+
+
+def _lattice(n, radius=4.0, half=8.0):
+    """A potential-map lattice n^3 over [-half, half]^3 A less the points within 0.6 A of the
+    sphere."""
+    ax = np.linspace(-half, half, n)
+    pts = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), axis=-1).reshape(-1, 3)
+    return pts[np.abs(np.linalg.norm(pts, axis=1) - radius) > 0.6]
+
+
+@pytest.mark.parametrize("kappa,degree,leaf", [(0.1257, 4, 128), (0.0, 5, 64)])
+def test_tree_field_matches_oracle(ctx, kappa, degree, leaf):
+    """hobi_field with the treecode against oracle.treecode.field_terms (the same tree and
+    point batches): R, -grad R, phi and E to 1e-12 (FP64) and 1e-5 (mixed) of each output's
+    largest magnitude, the side flags and the far and near pair counts exactly."""
+    p = inputs.kirkwood_offcenter(3, kappa=kappa)
+    theta = 0.6
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    eps = p.eps2 / p.eps1
+    u = inputs.random_vector(2 * p.nv, 35)
+    pts = _lattice(13)
+    R, gR, fr, nfar, nnear = T.field_terms(st, u, pts, p.kappa, eps, theta=theta, degree=degree, leaf=leaf, batch=256)
+    print(f"tree field kappa {kappa}: {pts.shape[0]} points, far pairs {nfar}, near pairs {nnear}", flush=True)
+    assert nfar > 0 and nnear > 0
+    S, gS = F.coulomb_terms(pts, p.qpos, p.q, p.eps1)
+    inside = fr > 0.5
+    side = np.where(inside, 1.0, 1.0 / eps)
+    ref = {"reac": UNIT * R, "reac_field": -UNIT * gR, "phi": UNIT * side * (S + R),
+           "field": -UNIT * side[:, None] * (gS + gR)}
+    for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
+        g = hobi.Problem.from_inputs(ctx, p, precision=prec, tree_theta=theta, tree_degree=degree, tree_leaf=leaf)
+        out = g.field(u, pts)
+        s = g.stats()
+        assert (s["field_tree_far_pairs"], s["field_tree_near_pairs"]) == (nfar, nnear)
+        for key, val in ref.items():
+            err = _rel(out[key], val)
+            print(f"  precision {prec} {key} rel err {err:.3e}", flush=True)
+            assert err <= tol, (key, err)
+        np.testing.assert_array_equal(out["inside"], inside.astype(np.int32))
+
+
+def test_tree_field_bench_map_L6_against_dense(ctx):
+    """A 32^3 map through the L6 bench surface: the treecode (theta 0.7, degree 5) within
+    1e-4 of the dense field sums (relative to each output's largest magnitude), same sides."""
+    p = inputs.kirkwood_offcenter(6)
+    u = inputs.random_vector(2 * p.nv, 36)
+    pts = _lattice(32, half=7.9)
+    dense = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED).field(u, pts)
+    g = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED, tree_theta=0.7, tree_degree=5)
+    out = g.field(u, pts)
+    s = g.stats()
+    print(f"L6 tree map {pts.shape[0]} points: far {s['field_tree_far_pairs']} near {s['field_tree_near_pairs']}",
+          flush=True)
+    for key in ("phi", "field", "reac", "reac_field"):
+        err = _rel(out[key], dense[key])
+        print(f"  {key} rel err vs dense {err:.3e}", flush=True)
+        assert err <= 1e-4, (key, err)
+    np.testing.assert_array_equal(out["inside"], dense["inside"])
 
 
 def test_tree_parameter_errors(ctx):
