@@ -69,6 +69,41 @@ uint64_t spread3(uint64_t v) {   // 21 bits -> every third bit
     return v;
 }
 
+// Indices 0..n-1 ordered by key, ties in index order: a least-significant-digit radix sort
+// (each pass a stable counting sort on one digit; 16-bit digits for large inputs, 8-bit
+// for small ones, passes whose digit is the same for every key skipped).
+std::vector<int> stable_key_order(const std::vector<uint64_t>& key_in) {
+    const size_t n = key_in.size();
+    const int bits = n >= 65536 ? 16 : 8;
+    const size_t radix = (size_t)1 << bits;
+    const int passes = 64 / bits;
+    std::vector<uint64_t> k(key_in), k2(n);
+    std::vector<int> ord(n), o2(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::vector<uint32_t> hist((size_t)passes * radix, 0);
+    for (size_t i = 0; i < n; ++i)
+        for (int p = 0; p < passes; ++p) hist[p * radix + ((k[i] >> (bits * p)) & (radix - 1))]++;
+    for (int p = 0; p < passes; ++p) {
+        uint32_t* h = &hist[p * radix];
+        if (*std::max_element(h, h + radix) == n) continue;
+        uint32_t sum = 0;
+        for (size_t d = 0; d < radix; ++d) {
+            const uint32_t c = h[d];
+            h[d] = sum;
+            sum += c;
+        }
+        const int shift = bits * p;
+        for (size_t i = 0; i < n; ++i) {
+            const uint32_t at = h[(k[i] >> shift) & (radix - 1)]++;
+            k2[at] = k[i];
+            o2[at] = ord[i];
+        }
+        k.swap(k2);
+        ord.swap(o2);
+    }
+    return ord;
+}
+
 std::vector<int> morton_order(const std::vector<double>& pts, int n, const double lo[3], const double hi[3]) {
     std::vector<uint64_t> code(n);
     for (int i = 0; i < n; ++i) {
@@ -81,10 +116,7 @@ std::vector<int> morton_order(const std::vector<double>& pts, int n, const doubl
         }
         code[i] = c;
     }
-    std::vector<int> ord(n);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return code[a] < code[b]; });
-    return ord;
+    return stable_key_order(code);
 }
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
