@@ -321,3 +321,62 @@ def field_terms(st, u, points, kappa, eps, theta=0.5, degree=5, leaf=256, batch=
     out_R, out_g, out_f = np.empty_like(R), np.empty_like(gR), np.empty_like(frac)
     out_R[porder], out_g[porder], out_f[porder] = R, gR, frac
     return out_R, out_g, out_f, nfar, nnear
+
+
+def matvec_lobi(ls, xyz, tri, u, kappa, eps, theta=0.5, degree=5, leaf=256, batch=128):
+    """y = A u of the lower-order scheme (oracle.lobi.matvec, Section 2.4) with its regular
+    sum taken by the treecode, and the count of accepted (batch, cluster) pairs.  Sites and
+    nodes are the centroids, in the Morton order of the triangles (as `partition`); leaves,
+    tree and batches as for the higher-order scheme.  A centroid's own node is the only one
+    left out of its row, so a cluster is never accepted for a batch whose sites overlap its
+    nodes.  There is no singular part: y = diagonal - (tree sums)."""
+    nf = ls.nf
+    u = np.asarray(u, dtype=np.float64)
+    cen = (xyz[tri[:, 0]] + xyz[tri[:, 1]] + xyz[tri[:, 2]]) / 3.0
+    order = morton_order(cen, xyz.min(axis=0), xyz.max(axis=0))
+    y, ny, W = ls.c[order], ls.n[order], ls.W[order]
+    phi, dphi = u[:nf][order], u[nf:][order]
+    gam, phn = W * dphi, W * phi
+    clusters, children, root = cluster_tree(nf, leaf)
+
+    def sphere(p):
+        blo, bhi = p.min(axis=0), p.max(axis=0)
+        return 0.5 * (blo + bhi), 0.5 * np.linalg.norm(bhi - blo)
+
+    cs = [sphere(y[a:b]) for a, b in clusters]
+    tree = np.zeros((nf, 2))
+    cache = {}
+    nfar = 0
+    for a0 in range(0, nf, batch):
+        b0 = min(a0 + batch, nf)
+        cb, rb = sphere(y[a0:b0])
+        stack = [root]
+        while stack:
+            c = stack.pop()
+            p, q = clusters[c]
+            touches = q - 1 >= a0 and p <= b0 - 1
+            if not touches and rb + cs[c][1] <= theta * np.linalg.norm(cb - cs[c][0]):
+                nfar += 1
+                if c not in cache:
+                    cache[c] = proxies(y[p:q], ny[p:q], gam[p:q], phn[p:q], eps, degree)
+                s, Q0, Qk, Qk2 = cache[c]
+                for t in range(a0, b0):
+                    d = y[t] - s
+                    r = np.linalg.norm(d, axis=1)
+                    e = np.exp(-kappa * r)
+                    dnx = d @ ny[t]
+                    g0 = 1.0 / (FOUR_PI * r)
+                    tree[t, 0] += np.sum(g0 * Q0 + e * g0 * Qk)
+                    tree[t, 1] += np.sum(-dnx / (FOUR_PI * r ** 3) * (Q0 + e * (1.0 + kappa * r) * Qk2))
+            elif children[c] is None:
+                for t in range(a0, b0):
+                    keep = np.arange(p, q) != t
+                    K1, K2, K3, K4 = kernels(y[t], ny[t], y[p:q][keep], ny[p:q][keep], kappa, eps)
+                    tree[t, 0] += np.sum(K1 * gam[p:q][keep] + K2 * phn[p:q][keep])
+                    tree[t, 1] += np.sum(K3 * gam[p:q][keep] + K4 * phn[p:q][keep])
+            else:
+                stack.extend(children[c][::-1])
+    out = np.empty(2 * nf)
+    out[order] = 0.5 * (1.0 + eps) * phi - tree[:, 0]
+    out[nf + order] = 0.5 * (1.0 + 1.0 / eps) * dphi - tree[:, 1]
+    return out, nfar

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import field as F
+from oracle import lobi as LO
 from oracle import operator as O
 from oracle import treecode as T
 from paper_1301_5914_amd import inputs
@@ -162,3 +163,31 @@ def test_field_error_falls_with_degree(sphere):
     errs = np.array(errs)
     assert np.all(errs[0] > errs[1]) and np.all(errs[1] > errs[2]), errs
     assert np.all(errs[2] < 1e-6), errs
+
+
+def test_lower_order_theta_zero_is_the_matvec():
+    """The lower-order scheme's treecode at theta = 0 is oracle.lobi.matvec (1e-12)."""
+    p = inputs.kirkwood_offcenter(3)
+    ls = LO.setup(p.xyz, p.nrm, p.tri)
+    u = inputs.random_vector(2 * p.nf, 9)
+    eps = p.eps2 / p.eps1
+    ref = LO.matvec(ls, u, p.kappa, eps)
+    y, nfar = T.matvec_lobi(ls, p.xyz, p.tri, u, p.kappa, eps, theta=0.0, degree=3, leaf=128, batch=128)
+    assert nfar == 0
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * np.max(np.abs(ref)))
+
+
+def test_lower_order_error_falls_with_degree():
+    """On L3 with small leaves and batches (32 sites each, far pairs at every level) at
+    theta 0.7 the error against oracle.lobi.matvec falls with the degree, below 1e-6 at 6."""
+    p = inputs.kirkwood_offcenter(3)
+    ls = LO.setup(p.xyz, p.nrm, p.tri)
+    u = inputs.random_vector(2 * p.nf, 9)
+    eps = p.eps2 / p.eps1
+    ref = LO.matvec(ls, u, p.kappa, eps)
+    errs = []
+    for n in (2, 6):
+        y, nfar = T.matvec_lobi(ls, p.xyz, p.tri, u, p.kappa, eps, theta=0.7, degree=n, leaf=32, batch=32)
+        assert nfar > 0
+        errs.append(_rel(y, ref))
+    assert errs[0] > 10 * errs[1] and errs[1] < 1e-6, errs
