@@ -145,17 +145,18 @@ def field_bench(pb, prob, grid, res, mixed, n_nodes):
 
 
 def tree_bench(ctx, stream, prob, theta, degree, leaf, batch, mixed, dense_pb, dense_res, dense_mv_ms, pairs_mv,
-               grid=0):
+               grid=0, lower=False):
     """The treecode form of the matvec on the same problem: matvec time (HIP events, median
     of 20), the dense pair count it replaces per second, its error against the dense matvec
     on a random vector, and the solve with it against the dense solve."""
     import torch
     from paper_1301_5914_amd import hobi
     pb = hobi.Problem.from_inputs(ctx, prob, precision=hobi.HOBI_MIXED if mixed else hobi.HOBI_FP64,
+                                  method=hobi.HOBI_LOWER_ORDER if lower else hobi.HOBI_HIGHER_ORDER,
                                   tree_theta=theta, tree_degree=degree, tree_leaf=leaf, tree_batch=batch,
                                   max_iter=400, restart=400)
     st = pb.stats()
-    u = torch.randn(2 * prob.nv, dtype=torch.float64, device="cuda")
+    u = torch.randn(2 * (prob.nf if lower else prob.nv), dtype=torch.float64, device="cuda")
     yt = torch.empty_like(u)
     yd = torch.empty_like(u)
     ms = []
@@ -460,10 +461,11 @@ def main():
     out["matvec_gpairs_per_s"] = pairs_mv / (out["matvec_ms_median"] * 1e-3) / 1e9
     if args.field_map > 0:
         out["field"] = field_bench(pb, prob, args.field_map, results[-1], mixed, n_nodes)
-    if args.tree_theta > 0 and not lower:
+    if args.tree_theta > 0:
+        # (hobi_field takes the treecode with the higher-order method only: no map otherwise)
         out["tree"] = tree_bench(ctx, stream, prob, args.tree_theta, args.tree_degree, args.tree_leaf,
-                                 args.tree_batch, mixed, pb,
-                                 results[-1], out["matvec_ms_median"], pairs_mv, grid=args.field_map)
+                                 args.tree_batch, mixed, pb, results[-1], out["matvec_ms_median"], pairs_mv,
+                                 grid=0 if lower else args.field_map, lower=lower)
     if not args.no_compare:
         # the other precision on the same problem (outside the timed region)
         pb.set_precision(hobi.HOBI_FP64 if mixed else hobi.HOBI_MIXED)

@@ -83,7 +83,7 @@ typedef struct hobi_params {
                         /* diagonal blocks scaled to the identity (unknowns scaled by        */
                         /* 1/(1/2 (1+eps)) and 1/(1/2 (1+1/eps)); same solution, the monitored */
                         /* residual is still ||b - A u|| / ||b||); 0: on A u = b as written  */
-    /* Treecode form of the regular (dense) sum, higher-order method only.  0 (default):
+    /* Treecode form of the regular (dense) sum, either method.  0 (default):
      * the dense sum.  > 0: a cluster-particle treecode with opening parameter tree_theta.
      * The quadrature nodes in order are cut into leaves of tree_leaf nodes, joined pairwise
      * level by level into a binary cluster tree; the target vertices in order into batches
@@ -91,8 +91,10 @@ typedef struct hobi_params {
      * sphere and the batch's satisfy r_b + r_c <= tree_theta |c_b - c_c|, and which has no
      * triangle incident to a target of the batch, is taken by the Green's functions
      * interpolated in the source point on the (tree_degree + 1)^3 Chebyshev points of its
-     * box; a leaf that fails is summed directly; a parent that fails is opened.  The
-     * partition is fixed at problem creation.                                            */
+     * box; a leaf that fails is summed directly; a parent that fails is opened (with the
+     * lower-order method a cluster is rejected for a batch whose sites overlap its nodes).
+     * The partition is fixed at problem creation.  hobi_field takes the treecode with the
+     * higher-order method only.                                                          */
     double tree_theta;  /* >= 0, default 0                                                  */
     int32_t tree_degree; /* interpolation degree n, 1..7, default 5                        */
     int32_t tree_leaf;  /* nodes per leaf, a multiple of 64 in [64, 2^24], default 256      */
@@ -206,7 +208,8 @@ hobi_status hobi_energy(hobi_problem pb, const double* u, int32_t on_device,
  *   phi [np] total potential, kcal/(mol e);   field [np][3] E, kcal/(mol e A);
  *   reac [np] R;   reac_field [np][3] -grad R;   inside [np] 1 inside, 0 outside.
  * The pair sums run in the problem's precision (mixed: FP32 pairs, FP64 accumulation).
- * With tree_theta > 0 the sums over the surface take the problem's treecode: the points
+ * With tree_theta > 0 (higher-order method) the sums over the surface take the problem's
+ * treecode: the points
  * in Morton order form batches of 256 that walk its cluster tree with the acceptance test
  * alone (no incidence rule off the surface); accepted clusters add R, grad R and the
  * solid angle from their proxy charges (the solid angle from the charge of the unit

@@ -432,7 +432,8 @@ hobi_status run_device_setup(hobi_problem pb, float* ms_out) {
 // joined pairwise level by level (a last cluster without a neighbour moves up unchanged),
 // stored after the leaves level by level.  Each cluster and batch (tree_batch consecutive
 // targets) has the bounding sphere of its box (centre, half diagonal); a cluster's
-// vertex-id range is that of its triangles.  Each batch walks the tree from the root:
+// vertex-id range is that of its triangles (higher-order method) or its own node range
+// (lower-order method: a centroid's node is left out of its own row only).  Each batch walks the tree from the root:
 // accepted (far) when r_b + r_c <= theta |c_b - c_c| and the cluster's vertex-id range
 // misses the batch's targets, else a leaf is near and a parent is opened (left child
 // first).  Work items: for every target slot of each precision, its batch's far and near
@@ -474,9 +475,14 @@ hobi_status build_tree_plan(hobi_problem pb) {
             const double pj[3] = {nodes[j].x, nodes[j].y, nodes[j].z};
             for (int q = 0; q < 3; ++q) k.lo[q] = std::min(k.lo[q], pj[q]), k.hi[q] = std::max(k.hi[q], pj[q]);
         }
-        k.vlo = nv, k.vhi = -1;
-        for (int f = k.a / 4; f < (k.b + 3) / 4; ++f)
-            for (int q = 0; q < 3; ++q) k.vlo = std::min(k.vlo, tri[3 * f + q]), k.vhi = std::max(k.vhi, tri[3 * f + q]);
+        if (d.method == HOBI_LOWER_ORDER) {
+            k.vlo = k.a, k.vhi = k.b - 1;   // node j is site j, left out of its own row only
+        } else {
+            k.vlo = nv, k.vhi = -1;
+            for (int f = k.a / 4; f < (k.b + 3) / 4; ++f)
+                for (int q = 0; q < 3; ++q)
+                    k.vlo = std::min(k.vlo, tri[3 * f + q]), k.vhi = std::max(k.vhi, tri[3 * f + q]);
+        }
     }
     std::vector<int> level(t.nleaf);
     std::iota(level.begin(), level.end(), 0);
@@ -631,8 +637,6 @@ hobi_status validate_params(hobi_ctx ctx, const hobi_params& p) {
         return fail(ctx, HOBI_E_ARG, "tree_leaf must be a multiple of 64 in [64, 2^24]");
     if (p.tree_batch != 128 && p.tree_batch != 256 && p.tree_batch != 512)
         return fail(ctx, HOBI_E_ARG, "tree_batch must be 128, 256 or 512");
-    if (p.tree_theta > 0 && p.method != HOBI_HIGHER_ORDER)
-        return fail(ctx, HOBI_E_ARG, "the treecode serves the higher-order method only");
     return HOBI_OK;
 }
 
@@ -1068,7 +1072,8 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
     if (st != HOBI_OK) return st;
     HIPCHK(c, launch_gather(d, pb->u_in, mixed, s));
     // the split over waves (dense sum) or the treecode's slots of points, points in Morton order
-    const bool tree = d.tree.on != 0;
+    // (the treecode form of the field sums is defined for the higher-order method's nodes)
+    const bool tree = d.tree.on != 0 && d.method == HOBI_HIGHER_ORDER;
     PairPlan pl{};
     std::vector<int> gs;
     if (tree) {

@@ -59,6 +59,32 @@ def test_tree_matvec_matches_stored_oracle_treecode(ctx, name):
     _check_case(ctx, p, theta, degree, leaf, batch, u, ref["y"], int(ref["nfar"]), int(ref["nnear"]), name)
 
 
+@pytest.mark.parametrize("name", list(G.LOBI_CASES))
+def test_lower_order_tree_matches_stored_oracle(ctx, name):
+    """The lower-order scheme with the treecode (5120 sites in 128-site batches, 64-node
+    leaves) against oracle.treecode.matvec_lobi: FP64 to 1e-12, mixed to 1e-5, the far-pair
+    count exactly; hobi_field of such a problem takes the dense sums (bitwise those of the
+    problem without the treecode)."""
+    recipe, theta, degree, leaf, batch = G.LOBI_CASES[name]
+    ref = np.load(os.path.join(GOLDEN, f"tree_lobi_{name}.npz"))
+    p = G.surface(recipe)
+    u = inputs.random_vector(2 * p.nf, int(ref["seed"]))
+    print(f"lower-order tree case {name}: far pairs {int(ref['nfar'])}", flush=True)
+    assert int(ref["nfar"]) > 0
+    for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
+        g = hobi.Problem.from_inputs(ctx, p, precision=prec, method=hobi.HOBI_LOWER_ORDER, tree_theta=theta,
+                                     tree_degree=degree, tree_leaf=leaf, tree_batch=batch)
+        assert g.stats()["tree_far_pairs"] == int(ref["nfar"])
+        err = _rel(g.matvec(u), ref["y"])
+        print(f"  precision {prec} rel err {err:.3e}", flush=True)
+        assert err <= tol, (prec, err)
+    pts = _lattice(9)
+    dense = hobi.Problem.from_inputs(ctx, p, method=hobi.HOBI_LOWER_ORDER).field(u, pts)
+    out = hobi.Problem.from_inputs(ctx, p, method=hobi.HOBI_LOWER_ORDER, tree_theta=theta).field(u, pts)
+    for key in ("phi", "field", "reac", "reac_field", "inside"):
+        np.testing.assert_array_equal(out[key], dense[key])
+
+
 def test_tree_matvec_matches_oracle_treecode_L3(ctx):
     """Smallest leaves (64 nodes), degree 5, kappa = 1: the oracle run live."""
     p = inputs.kirkwood_offcenter(3, kappa=1.0, eps1=4.0)
@@ -234,7 +260,7 @@ def test_tree_parameter_errors(ctx):
     bad = [dict(tree_theta=-0.1), dict(tree_theta=float("nan")), dict(tree_theta=0.5, tree_degree=0),
            dict(tree_theta=0.5, tree_degree=8), dict(tree_theta=0.5, tree_leaf=100),
            dict(tree_theta=0.5, tree_leaf=0), dict(tree_theta=0.5, tree_batch=64),
-           dict(tree_theta=0.5, tree_batch=1024), dict(tree_theta=0.5, method=hobi.HOBI_LOWER_ORDER)]
+           dict(tree_theta=0.5, tree_batch=1024)]
     for kw in bad:
         with pytest.raises(hobi.HobiError) as e:
             hobi.Problem.from_inputs(ctx, p, **kw)
