@@ -497,9 +497,33 @@ __global__ __launch_bounds__(kCombPts * kCombWays) void field_combine_kernel(
     inside[p] = in ? 1 : 0;
 }
 
+// Sorted point p's outputs to the caller's index order[p], split into the ABI's arrays.
+__global__ void field_scatter_kernel(const double* __restrict__ out9, const int* __restrict__ ins, int np,
+                                     const int* __restrict__ order, double* __restrict__ outc, int* __restrict__ insc) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int i = order[p];
+    const double* o = out9 + 9 * (size_t)p;
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) finite = finite && isfinite(o[k]);
+    outc[i] = o[0];                                  // phi
+    for (int k = 0; k < 3; ++k) outc[(size_t)np + 3 * (size_t)i + k] = o[1 + k];       // E
+    outc[4 * (size_t)np + i] = o[4];                 // R
+    for (int k = 0; k < 3; ++k) outc[5 * (size_t)np + 3 * (size_t)i + k] = o[5 + k];   // -grad R
+    insc[i] = ins[p];
+    if (!finite) insc[np] = 1;
+}
+
 inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
+
+hipError_t launch_field_scatter(const FieldWork& f, hipStream_t s) {
+    hipLaunchKernelGGL(field_scatter_kernel, dim3(nblk(f.np, 256)), dim3(256), 0, s, f.out, f.inside, f.np, f.order,
+                       f.outc, f.insc);
+    return hipGetLastError();
+}
 
 int field_resident_waves(int device, bool mixed) {
     int cus = 0, per_cu = 0;

@@ -59,6 +59,18 @@ hipError_t grow(T** p, size_t* cap, size_t n) {
     return e;
 }
 
+template <class T>
+hipError_t grow_pinned(T** p, size_t* cap, size_t n) {
+    if (*p && *cap >= n) return hipSuccess;
+    if (*p) (void)hipHostFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    const size_t m = std::max<size_t>(n, 1);
+    const hipError_t e = hipHostMalloc((void**)p, m * sizeof(T));
+    if (e == hipSuccess) *cap = m;
+    return e;
+}
+
 uint64_t spread3(uint64_t v) {   // 21 bits -> every third bit
     v &= 0x1fffff;
     v = (v | v << 32) & 0x1f00000000ffffULL;
@@ -386,9 +398,11 @@ void free_problem(hobi_problem pb) {
     }
     {
         FieldWork& f = pb->field;
-        void* fp[] = {f.pts64, f.pts32, f.partial, f.gstart, f.out, f.inside, f.items, f.slot_row};
+        void* fp[] = {f.pts64, f.pts32, f.partial, f.gstart, f.out, f.inside, f.items, f.slot_row, f.order, f.outc, f.insc};
         for (void* p : fp)
             if (p) (void)hipFree(p);
+        if (f.hp64) (void)hipHostFree(f.hp64);
+        if (f.hp32) (void)hipHostFree(f.hp32);
         f = FieldWork{};
     }
     if (pb->host_pinned) (void)hipHostFree(pb->host_pinned);
@@ -1098,8 +1112,12 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
     FieldWork& f = pb->field;
     f.np = np;
     f.np_pad = tree ? round_up(np, kFieldTreeBatch) : pl.slots * pl.slot;
-    std::vector<double> h64(3 * (size_t)f.np_pad);
-    std::vector<float> h32(3 * (size_t)f.np_pad);
+    hipError_t e = hipSuccess;
+    if ((e = grow_pinned(&f.hp64, &f.cap_hp64, 3 * (size_t)f.np_pad)) != hipSuccess ||
+        (e = grow_pinned(&f.hp32, &f.cap_hp32, 3 * (size_t)f.np_pad)) != hipSuccess)
+        return fail(c, e == hipErrorOutOfMemory ? HOBI_E_OOM : HOBI_E_HIP, "field staging: %s", hipGetErrorString(e));
+    double* h64 = f.hp64;
+    float* h32 = f.hp32;
     for (int j = 0; j < f.np_pad; ++j) {
         const int src = order[std::min(j, np - 1)];
         for (int k = 0; k < 3; ++k) {
@@ -1155,19 +1173,22 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
         }
     }
     const size_t nparts = (tree ? items.size() : (size_t)pl.workers) * 5 * pl.slot;
-    hipError_t e = hipSuccess;
-    if ((e = grow(&f.pts64, &f.cap_pts64, h64.size())) != hipSuccess ||
-        (e = grow(&f.pts32, &f.cap_pts32, h32.size())) != hipSuccess ||
+    if ((e = grow(&f.pts64, &f.cap_pts64, 3 * (size_t)f.np_pad)) != hipSuccess ||
+        (e = grow(&f.pts32, &f.cap_pts32, 3 * (size_t)f.np_pad)) != hipSuccess ||
         (e = grow(&f.partial, &f.cap_partial, nparts)) != hipSuccess ||
         (e = grow(&f.gstart, &f.cap_gstart, gs.size())) != hipSuccess ||
         (e = grow(&f.out, &f.cap_out, 9 * (size_t)np)) != hipSuccess ||
         (e = grow(&f.inside, &f.cap_inside, (size_t)np)) != hipSuccess ||
+        (e = grow(&f.order, &f.cap_order, (size_t)np)) != hipSuccess ||
+        (e = grow(&f.outc, &f.cap_outc, 8 * (size_t)np)) != hipSuccess ||
+        (e = grow(&f.insc, &f.cap_insc, (size_t)np + 1)) != hipSuccess ||
         (tree && (e = grow(&f.items, &f.cap_items, items.size())) != hipSuccess) ||
         (tree && (e = grow(&f.slot_row, &f.cap_slot_row, srow.size())) != hipSuccess))
         return fail(c, e == hipErrorOutOfMemory ? HOBI_E_OOM : HOBI_E_HIP, "field work space: %s",
                     hipGetErrorString(e));
-    HIPCHK(c, hipMemcpyAsync(f.pts64, h64.data(), sizeof(double) * h64.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(f.pts32, h32.data(), sizeof(float) * h32.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(f.pts64, h64, sizeof(double) * 3 * (size_t)f.np_pad, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(f.pts32, h32, sizeof(float) * 3 * (size_t)f.np_pad, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(f.order, order.data(), sizeof(int) * (size_t)np, hipMemcpyHostToDevice, s));
     if (tree) {
         HIPCHK(c, hipMemcpyAsync(f.items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, s));
         HIPCHK(c, hipMemcpyAsync(f.slot_row, srow.data(), sizeof(int) * srow.size(), hipMemcpyHostToDevice, s));
@@ -1186,24 +1207,20 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
         }
         HIPCHK(c, launch_field_combine(d, f, pl, mixed, s));
     }
-    std::vector<double> ho(9 * (size_t)np);
-    std::vector<int> hin((size_t)np);
-    HIPCHK(c, hipMemcpyAsync(ho.data(), f.out, sizeof(double) * ho.size(), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(hin.data(), f.inside, sizeof(int) * hin.size(), hipMemcpyDeviceToHost, s));
+    // outputs in the caller's order on the device, then straight into the caller's arrays
+    HIPCHK(c, hipMemsetAsync(f.insc + np, 0, sizeof(int), s));
+    HIPCHK(c, launch_field_scatter(f, s));
+    const size_t n1 = (size_t)np;
+    if (phi) HIPCHK(c, hipMemcpyAsync(phi, f.outc, sizeof(double) * n1, hipMemcpyDeviceToHost, s));
+    if (field) HIPCHK(c, hipMemcpyAsync(field, f.outc + n1, sizeof(double) * 3 * n1, hipMemcpyDeviceToHost, s));
+    if (reac) HIPCHK(c, hipMemcpyAsync(reac, f.outc + 4 * n1, sizeof(double) * n1, hipMemcpyDeviceToHost, s));
+    if (reac_field)
+        HIPCHK(c, hipMemcpyAsync(reac_field, f.outc + 5 * n1, sizeof(double) * 3 * n1, hipMemcpyDeviceToHost, s));
+    if (inside) HIPCHK(c, hipMemcpyAsync(inside, f.insc, sizeof(int) * n1, hipMemcpyDeviceToHost, s));
+    int* flag = (int*)pb->host_pinned;
+    HIPCHK(c, hipMemcpyAsync(flag, f.insc + np, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    for (int j = 0; j < np; ++j) {
-        const int i = order[j];
-        const double* o = ho.data() + 9 * (size_t)j;
-        if (phi) phi[i] = o[0];
-        if (field)
-            for (int k = 0; k < 3; ++k) field[3 * (size_t)i + k] = o[1 + k];
-        if (reac) reac[i] = o[4];
-        if (reac_field)
-            for (int k = 0; k < 3; ++k) reac_field[3 * (size_t)i + k] = o[5 + k];
-        if (inside) inside[i] = hin[j];
-    }
-    for (size_t i = 0; i < ho.size(); ++i)
-        if (!std::isfinite(ho[i])) return fail(c, HOBI_E_NUMERIC, "non-finite field value (a point on the surface?)");
+    if (*flag) return fail(c, HOBI_E_NUMERIC, "non-finite field value (a point on the surface?)");
     return HOBI_OK;
 }
 

@@ -157,10 +157,15 @@ struct FieldWork {
     int* gstart = nullptr;        // [groups + 1]
     double* out = nullptr;        // [np][9] phi, E, R, -grad R, solid-angle fraction
     int* inside = nullptr;        // [np]
+    int* order = nullptr;         // [np] caller index of each sorted point
+    double* outc = nullptr;       // [8 np] outputs in caller order: phi, E (3), R, -grad R (3)
+    int* insc = nullptr;          // [np + 1] sides in caller order, then the non-finite flag
+    double* hp64 = nullptr;       // pinned host staging of pts64
+    float* hp32 = nullptr;        // and of pts32
     int4* items = nullptr;        // treecode: work items {slot, far, cluster, 0}, slot-major
     int* slot_row = nullptr;      // treecode: items of slot s are [slot_row[s], slot_row[s + 1])
     size_t cap_pts64 = 0, cap_pts32 = 0, cap_partial = 0, cap_gstart = 0, cap_out = 0, cap_inside = 0;
-    size_t cap_items = 0, cap_slot_row = 0;
+    size_t cap_items = 0, cap_slot_row = 0, cap_order = 0, cap_outc = 0, cap_insc = 0, cap_hp64 = 0, cap_hp32 = 0;
     int64_t tree_far = 0, tree_near = 0;   // accepted and near (batch, cluster) pairs of the last call
 };
 // Waves of the mixed or FP64 field kernel the device holds at once (0 on error).
@@ -178,6 +183,9 @@ hipError_t launch_field_tree_pairs(const DeviceProblem& p, const FieldWork& f, i
                                    hipStream_t s);
 hipError_t launch_permute(const double* in, double* out, const int* perm, int nv, bool to_internal,
                           hipStream_t s);
+// f.out / f.inside (sorted points) -> f.outc / f.insc in the caller's order (f.order), and
+// f.insc[np] = 1 if any output value is not finite (the caller clears it first)
+hipError_t launch_field_scatter(const FieldWork& f, hipStream_t s);
 
 // ---- treecode (tree_kernels.hip) ----
 // proxy charges of every cluster (node strengths of u must be gathered, FP64 records)

@@ -118,6 +118,7 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
     __syncthreads();
     inverse_differences(pt, inv, n1);
     __syncthreads();
+    const double ieps = 1.0 / eps;
     double q0[2] = {0.0, 0.0}, qk[2] = {0.0, 0.0}, qk2[2] = {0.0, 0.0}, qs[2] = {0.0, 0.0};
     int ka[2], kb[2], kc[2];
     for (int h = 0; h < 2; ++h) {
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void proxy_kernel(const NodeD* __restrict__
                 const double gL = ng[i] * L, pG = np_[i] * G;
                 q0[h] += gL - pG;
                 qk[h] += -gL + eps * pG;
-                qk2[h] += -gL / eps + pG;
+                qk2[h] += fma(-gL, ieps, pG);
                 qs[h] += nw[i] * G;
             }
         }

@@ -236,6 +236,26 @@ def test_tree_field_matches_oracle(ctx, kappa, degree, leaf):
         np.testing.assert_array_equal(out["inside"], inside.astype(np.int32))
 
 
+@pytest.mark.parametrize("npts", [1, 255, 257, 700])
+def test_tree_field_ragged_point_counts(ctx, npts):
+    """Point counts around the 256-point batch (one point; one short and one long of a
+    batch): R and -grad R against the oracle's treecode field, both precisions."""
+    p = inputs.kirkwood_offcenter(3)
+    theta, degree, leaf = 0.6, 4, 64
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    eps = p.eps2 / p.eps1
+    u = inputs.random_vector(2 * p.nv, 37)
+    pts = _lattice(13)[np.random.default_rng(npts).permutation(2107)[:npts]]
+    R, gR, fr, nfar, nnear = T.field_terms(st, u, pts, p.kappa, eps, theta=theta, degree=degree, leaf=leaf, batch=256)
+    for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
+        g = hobi.Problem.from_inputs(ctx, p, precision=prec, tree_theta=theta, tree_degree=degree, tree_leaf=leaf)
+        out = g.field(u, pts)
+        s = g.stats()
+        assert (s["field_tree_far_pairs"], s["field_tree_near_pairs"]) == (nfar, nnear)
+        assert _rel(out["reac"], UNIT * R) <= tol and _rel(out["reac_field"], -UNIT * gR) <= tol
+        np.testing.assert_array_equal(out["inside"], (fr > 0.5).astype(np.int32))
+
+
 def test_tree_field_bench_map_L6_against_dense(ctx):
     """A 32^3 map through the L6 bench surface: the treecode (theta 0.7, degree 5) within
     1e-4 of the dense field sums (relative to each output's largest magnitude), same sides."""
