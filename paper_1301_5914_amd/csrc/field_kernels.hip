@@ -16,6 +16,8 @@
 // Layout as the pair sum: one wave per (slot of points, node group) of a pair plan, each
 // writing a row of five partial sums per point (R, grad R, Omega); field_combine_kernel
 // adds a point's rows in a fixed order, then the Coulomb part in FP64.
+#include <hipcub/hipcub.hpp>
+
 #include "hobi_internal.h"
 #include "pair_tile.h"
 
@@ -497,6 +499,73 @@ __global__ __launch_bounds__(kCombPts * kCombWays) void field_combine_kernel(
     inside[p] = in ? 1 : 0;
 }
 
+__device__ __forceinline__ uint64_t spread3_bits(uint64_t v) {   // 21 bits -> every third bit
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+
+__global__ void morton_keys_kernel(const double* __restrict__ raw, int np, double lx, double ly, double lz, double ex,
+                                   double ey, double ez, uint64_t* __restrict__ keys, int* __restrict__ idx) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const double lo[3] = {lx, ly, lz}, ext[3] = {ex, ey, ez};
+    uint64_t c = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double f = fmin(fmax((raw[3 * (size_t)i + d] - lo[d]) / ext[d], 0.0), 1.0);
+        c |= spread3_bits((uint64_t)(f * 2097151.0)) << d;
+    }
+    keys[i] = c;
+    idx[i] = i;
+}
+
+__global__ void stage_points_kernel(const double* __restrict__ raw, const int* __restrict__ order, int np, int np_pad,
+                                    double cx, double cy, double cz, double s32, double* __restrict__ pts64,
+                                    float* __restrict__ pts32) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= np_pad) return;
+    const int src = order[min(j, np - 1)];
+    const double c[3] = {cx, cy, cz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double x = raw[3 * (size_t)src + k];
+        pts64[(size_t)k * np_pad + j] = x;
+        pts32[(size_t)k * np_pad + j] = (float)((x - c[k]) * s32);
+    }
+}
+
+// One block per batch of kFieldTreeBatch sorted points: the box of its points (exact min/max).
+static_assert(kFieldTreeBatch == 256, "one thread per point of a batch");
+__global__ __launch_bounds__(256) void batch_box_kernel(const double* __restrict__ pts64, int np, int np_pad,
+                                                        double* __restrict__ bbox) {
+    __shared__ double red[6][256];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int i = b * kFieldTreeBatch + t;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double v = i < np ? pts64[(size_t)k * np_pad + i] : pts64[(size_t)k * np_pad + b * kFieldTreeBatch];
+        red[k][t] = v;
+        red[3 + k][t] = v;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                red[k][t] = fmin(red[k][t], red[k][t + w]);
+                red[3 + k][t] = fmax(red[3 + k][t], red[3 + k][t + w]);
+            }
+        }
+        __syncthreads();
+    }
+    if (t < 6) bbox[6 * (size_t)b + t] = red[t][0];
+}
+
 // Sorted point p's outputs to the caller's index order[p], split into the ABI's arrays.
 __global__ void field_scatter_kernel(const double* __restrict__ out9, const int* __restrict__ ins, int np,
                                      const int* __restrict__ order, double* __restrict__ outc, int* __restrict__ insc) {
@@ -518,6 +587,33 @@ __global__ void field_scatter_kernel(const double* __restrict__ out9, const int*
 inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
+
+size_t point_sort_temp_bytes(int np) {
+    size_t bytes = 0;
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                           (const int*)nullptr, (int*)nullptr, np, 0, 64) != hipSuccess)
+        return 0;
+    return std::max<size_t>(bytes, 1);
+}
+
+hipError_t launch_point_order(const FieldWork& f, const double lo[3], const double hi[3], const double center[3],
+                              double s32, int nbatch, hipStream_t s) {
+    double ext[3];
+    for (int k = 0; k < 3; ++k) ext[k] = hi[k] - lo[k] > 0 ? hi[k] - lo[k] : 1.0;
+    hipLaunchKernelGGL(morton_keys_kernel, dim3(nblk(f.np, 256)), dim3(256), 0, s, f.raw, f.np, lo[0], lo[1], lo[2],
+                       ext[0], ext[1], ext[2], f.keys, f.idx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t bytes = f.cap_sort_tmp;
+    if ((e = hipcub::DeviceRadixSort::SortPairs(f.sort_tmp, bytes, f.keys, f.keys + f.np, f.idx, f.order, f.np, 0, 64,
+                                                s)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(stage_points_kernel, dim3(nblk(f.np_pad, 256)), dim3(256), 0, s, f.raw, f.order, f.np,
+                       f.np_pad, center[0], center[1], center[2], s32, f.pts64, f.pts32);
+    if (nbatch > 0)
+        hipLaunchKernelGGL(batch_box_kernel, dim3(nbatch), dim3(256), 0, s, f.pts64, f.np, f.np_pad, f.bbox);
+    return hipGetLastError();
+}
 
 hipError_t launch_field_scatter(const FieldWork& f, hipStream_t s) {
     hipLaunchKernelGGL(field_scatter_kernel, dim3(nblk(f.np, 256)), dim3(256), 0, s, f.out, f.inside, f.np, f.order,

@@ -398,11 +398,11 @@ void free_problem(hobi_problem pb) {
     }
     {
         FieldWork& f = pb->field;
-        void* fp[] = {f.pts64, f.pts32, f.partial, f.gstart, f.out, f.inside, f.items, f.slot_row, f.order, f.outc, f.insc};
+        void* fp[] = {f.pts64, f.pts32, f.partial, f.gstart, f.out, f.inside, f.items, f.slot_row, f.order, f.outc,
+                      f.insc, f.raw, f.keys, f.idx, f.sort_tmp, f.bbox};
         for (void* p : fp)
             if (p) (void)hipFree(p);
-        if (f.hp64) (void)hipHostFree(f.hp64);
-        if (f.hp32) (void)hipHostFree(f.hp32);
+        if (f.hbox) (void)hipHostFree(f.hbox);
         f = FieldWork{};
     }
     if (pb->host_pinned) (void)hipHostFree(pb->host_pinned);
@@ -1107,24 +1107,31 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
             lo[k] = std::min(lo[k], points[3 * i + k]);
             hi[k] = std::max(hi[k], points[3 * i + k]);
         }
-    const std::vector<double> pv(points, points + 3 * (size_t)np);
-    const std::vector<int> order = morton_order(pv, np, lo, hi);   // sorted position -> caller index
     FieldWork& f = pb->field;
     f.np = np;
     f.np_pad = tree ? round_up(np, kFieldTreeBatch) : pl.slots * pl.slot;
+    const int nb = (np + kFieldTreeBatch - 1) / kFieldTreeBatch;
+    const size_t sort_bytes = point_sort_temp_bytes(np);
+    if (sort_bytes == 0) return fail(c, HOBI_E_HIP, "radix-sort work space query failed");
     hipError_t e = hipSuccess;
-    if ((e = grow_pinned(&f.hp64, &f.cap_hp64, 3 * (size_t)f.np_pad)) != hipSuccess ||
-        (e = grow_pinned(&f.hp32, &f.cap_hp32, 3 * (size_t)f.np_pad)) != hipSuccess)
-        return fail(c, e == hipErrorOutOfMemory ? HOBI_E_OOM : HOBI_E_HIP, "field staging: %s", hipGetErrorString(e));
-    double* h64 = f.hp64;
-    float* h32 = f.hp32;
-    for (int j = 0; j < f.np_pad; ++j) {
-        const int src = order[std::min(j, np - 1)];
-        for (int k = 0; k < 3; ++k) {
-            const double x = points[3 * (size_t)src + k];
-            h64[(size_t)k * f.np_pad + j] = x;
-            h32[(size_t)k * f.np_pad + j] = (float)((x - d.center[k]) * d.s32);
-        }
+    if ((e = grow(&f.raw, &f.cap_raw, 3 * (size_t)np)) != hipSuccess ||
+        (e = grow(&f.keys, &f.cap_keys, 2 * (size_t)np)) != hipSuccess ||
+        (e = grow(&f.idx, &f.cap_idx, (size_t)np)) != hipSuccess ||
+        (e = grow(&f.order, &f.cap_order, (size_t)np)) != hipSuccess ||
+        (e = grow((char**)&f.sort_tmp, &f.cap_sort_tmp, sort_bytes)) != hipSuccess ||
+        (e = grow(&f.pts64, &f.cap_pts64, 3 * (size_t)f.np_pad)) != hipSuccess ||
+        (e = grow(&f.pts32, &f.cap_pts32, 3 * (size_t)f.np_pad)) != hipSuccess ||
+        (tree && (e = grow(&f.bbox, &f.cap_bbox, 6 * (size_t)nb)) != hipSuccess) ||
+        (tree && (e = grow_pinned(&f.hbox, &f.cap_hbox, 6 * (size_t)nb)) != hipSuccess))
+        return fail(c, e == hipErrorOutOfMemory ? HOBI_E_OOM : HOBI_E_HIP, "field work space: %s",
+                    hipGetErrorString(e));
+    // the points in Morton order over their box (sorted position -> caller index in f.order),
+    // staged on the device; with the treecode the box of each batch of sorted points
+    HIPCHK(c, hipMemcpyAsync(f.raw, points, sizeof(double) * 3 * (size_t)np, hipMemcpyHostToDevice, s));
+    HIPCHK(c, launch_point_order(f, lo, hi, d.center, d.s32, tree ? nb : 0, s));
+    if (tree) {
+        HIPCHK(c, hipMemcpyAsync(f.hbox, f.bbox, sizeof(double) * 6 * (size_t)nb, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
     }
     // treecode: each batch of kFieldTreeBatch points walks the cluster tree (accepted when
     // r_b + r_c <= theta |c_b - c_c|; the points are off the surface, so no incidence rule),
@@ -1133,18 +1140,12 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
     std::vector<int> srow(1, 0);
     if (tree) {
         const TreePlan& t = d.tree;
-        const int nb = (np + kFieldTreeBatch - 1) / kFieldTreeBatch;
         std::vector<std::vector<std::pair<int, int>>> walk(nb);
         f.tree_far = f.tree_near = 0;
         std::vector<int> stack;
         for (int bi = 0; bi < nb; ++bi) {
-            const int a = bi * kFieldTreeBatch, b = std::min(a + kFieldTreeBatch, np);
-            double blo[3] = {1e300, 1e300, 1e300}, bhi[3] = {-1e300, -1e300, -1e300};
-            for (int i = a; i < b; ++i)
-                for (int k = 0; k < 3; ++k) {
-                    const double v = h64[(size_t)k * f.np_pad + i];
-                    blo[k] = std::min(blo[k], v), bhi[k] = std::max(bhi[k], v);
-                }
+            const double* blo = f.hbox + 6 * (size_t)bi;
+            const double* bhi = blo + 3;
             double cb[3], q = 0;
             for (int k = 0; k < 3; ++k) cb[k] = 0.5 * (blo[k] + bhi[k]), q += (bhi[k] - blo[k]) * (bhi[k] - blo[k]);
             const double rb = 0.5 * std::sqrt(q);
@@ -1173,22 +1174,16 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
         }
     }
     const size_t nparts = (tree ? items.size() : (size_t)pl.workers) * 5 * pl.slot;
-    if ((e = grow(&f.pts64, &f.cap_pts64, 3 * (size_t)f.np_pad)) != hipSuccess ||
-        (e = grow(&f.pts32, &f.cap_pts32, 3 * (size_t)f.np_pad)) != hipSuccess ||
-        (e = grow(&f.partial, &f.cap_partial, nparts)) != hipSuccess ||
+    if ((e = grow(&f.partial, &f.cap_partial, nparts)) != hipSuccess ||
         (e = grow(&f.gstart, &f.cap_gstart, gs.size())) != hipSuccess ||
         (e = grow(&f.out, &f.cap_out, 9 * (size_t)np)) != hipSuccess ||
         (e = grow(&f.inside, &f.cap_inside, (size_t)np)) != hipSuccess ||
-        (e = grow(&f.order, &f.cap_order, (size_t)np)) != hipSuccess ||
         (e = grow(&f.outc, &f.cap_outc, 8 * (size_t)np)) != hipSuccess ||
         (e = grow(&f.insc, &f.cap_insc, (size_t)np + 1)) != hipSuccess ||
         (tree && (e = grow(&f.items, &f.cap_items, items.size())) != hipSuccess) ||
         (tree && (e = grow(&f.slot_row, &f.cap_slot_row, srow.size())) != hipSuccess))
         return fail(c, e == hipErrorOutOfMemory ? HOBI_E_OOM : HOBI_E_HIP, "field work space: %s",
                     hipGetErrorString(e));
-    HIPCHK(c, hipMemcpyAsync(f.pts64, h64, sizeof(double) * 3 * (size_t)f.np_pad, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(f.pts32, h32, sizeof(float) * 3 * (size_t)f.np_pad, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(f.order, order.data(), sizeof(int) * (size_t)np, hipMemcpyHostToDevice, s));
     if (tree) {
         HIPCHK(c, hipMemcpyAsync(f.items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, s));
         HIPCHK(c, hipMemcpyAsync(f.slot_row, srow.data(), sizeof(int) * srow.size(), hipMemcpyHostToDevice, s));

@@ -160,12 +160,17 @@ struct FieldWork {
     int* order = nullptr;         // [np] caller index of each sorted point
     double* outc = nullptr;       // [8 np] outputs in caller order: phi, E (3), R, -grad R (3)
     int* insc = nullptr;          // [np + 1] sides in caller order, then the non-finite flag
-    double* hp64 = nullptr;       // pinned host staging of pts64
-    float* hp32 = nullptr;        // and of pts32
+    double* raw = nullptr;        // [3 np] the caller's points
+    uint64_t* keys = nullptr;     // [2 np] Morton codes: unsorted, then sorted
+    int* idx = nullptr;           // [np] 0 .. np - 1
+    void* sort_tmp = nullptr;     // radix-sort work space
+    double* bbox = nullptr;       // [nbatch][6] lo, hi of each treecode batch of sorted points
+    double* hbox = nullptr;       // pinned host copy
     int4* items = nullptr;        // treecode: work items {slot, far, cluster, 0}, slot-major
     int* slot_row = nullptr;      // treecode: items of slot s are [slot_row[s], slot_row[s + 1])
     size_t cap_pts64 = 0, cap_pts32 = 0, cap_partial = 0, cap_gstart = 0, cap_out = 0, cap_inside = 0;
-    size_t cap_items = 0, cap_slot_row = 0, cap_order = 0, cap_outc = 0, cap_insc = 0, cap_hp64 = 0, cap_hp32 = 0;
+    size_t cap_items = 0, cap_slot_row = 0, cap_order = 0, cap_outc = 0, cap_insc = 0;
+    size_t cap_raw = 0, cap_keys = 0, cap_idx = 0, cap_sort_tmp = 0, cap_bbox = 0, cap_hbox = 0;
     int64_t tree_far = 0, tree_near = 0;   // accepted and near (batch, cluster) pairs of the last call
 };
 // Waves of the mixed or FP64 field kernel the device holds at once (0 on error).
@@ -183,6 +188,14 @@ hipError_t launch_field_tree_pairs(const DeviceProblem& p, const FieldWork& f, i
                                    hipStream_t s);
 hipError_t launch_permute(const double* in, double* out, const int* perm, int nv, bool to_internal,
                           hipStream_t s);
+// Bytes of radix-sort work space for np points (0 on error).
+size_t point_sort_temp_bytes(int np);
+// The points f.raw in Morton order over [lo, hi] (the rule of the problem's own ordering:
+// 21 bits per coordinate, x lowest, ties in input order): f.order, then f.pts64 / f.pts32
+// (SoA, padded to f.np_pad by repeating the last point; pts32 shifted by center, scaled by
+// s32), and with nbatch > 0 the box of each run of kFieldTreeBatch sorted points in f.bbox.
+hipError_t launch_point_order(const FieldWork& f, const double lo[3], const double hi[3], const double center[3],
+                              double s32, int nbatch, hipStream_t s);
 // f.out / f.inside (sorted points) -> f.outc / f.insc in the caller's order (f.order), and
 // f.insc[np] = 1 if any output value is not finite (the caller clears it first)
 hipError_t launch_field_scatter(const FieldWork& f, hipStream_t s);
