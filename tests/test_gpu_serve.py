@@ -94,11 +94,13 @@ def test_treecode_requests_equal_the_single_problem_path(ctx):
     tree = dict(tree_theta=0.8, tree_degree=4, tree_leaf=128, tree_batch=128)
     cases = [(inputs.kirkwood_offcenter(3), dict(precision=hobi.HOBI_MIXED, **tree)),
              (inputs.kirkwood_offcenter(3, kappa=0.0, eps1=2.0), dict(precision=hobi.HOBI_FP64, **tree)),
-             (inputs.kirkwood_centered(3), dict(precision=hobi.HOBI_MIXED))]
+             (inputs.kirkwood_centered(3), dict(precision=hobi.HOBI_MIXED)),
+             (inputs.kirkwood_offcenter(3), dict(precision=hobi.HOBI_MIXED, method=hobi.HOBI_LOWER_ORDER, **tree))]
     refs = []
     for p, kw in cases:
         g = hobi.Problem.from_inputs(ctx, p, max_iter=200, restart=200, **kw)
-        assert kw.get("tree_theta", 0) == 0 or g.stats()["tree_far_pairs"] > 0
+        assert kw.get("tree_theta", 0) == 0 or kw.get("method") == hobi.HOBI_LOWER_ORDER or \
+            g.stats()["tree_far_pairs"] > 0
         refs.append(g.solve())
     for use_graph in (True, False):
         sv = hobi.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=8, use_graph=use_graph)
