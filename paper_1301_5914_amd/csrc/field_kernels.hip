@@ -421,20 +421,20 @@ __global__ __launch_bounds__(kBlock) void field_tree_f64_kernel(const int4* __re
 constexpr int kCombPts = 64, kCombWays = 4;
 
 __global__ __launch_bounds__(kCombPts * kCombWays) void field_combine_kernel(
-    const double* __restrict__ partial, const int* __restrict__ slot_row, int np, int slot, int slots, int groups,
-    double gscale,
+    const double* __restrict__ partial, const int* __restrict__ slot_row, int row_base, int p0, int np, int slot,
+    int slots, int groups, double gscale,
     const double* __restrict__ pts, int np_pad, const double* __restrict__ qpos, const double* __restrict__ q,
     int nc, double eps1, double eps, double* __restrict__ out, int* __restrict__ inside) {
     __shared__ double red[kCombWays][kParts][kCombPts];
     const int lane = threadIdx.x % kCombPts, way = threadIdx.x / kCombPts;
-    const int p = blockIdx.x * kCombPts + lane;
+    const int p = p0 + blockIdx.x * kCombPts + lane;
     double v[kParts];
 #pragma unroll
     for (int c = 0; c < kParts; ++c) v[c] = 0.0;
     if (p < np && slot_row) {
         const int s = p / slot, o = p - s * slot;
         for (int r = slot_row[s] + way; r < slot_row[s + 1]; r += kCombWays) {
-            const double* col = partial + (size_t)r * kParts * slot + o;
+            const double* col = partial + (size_t)(r - row_base) * kParts * slot + o;
 #pragma unroll
             for (int c = 0; c < kParts; ++c) v[c] += col[(size_t)c * slot];
         }
@@ -676,10 +676,12 @@ hipError_t launch_field_tree_pairs(const DeviceProblem& p, const FieldWork& f, i
 }
 
 hipError_t launch_field_combine(const DeviceProblem& p, const FieldWork& f, const PairPlan& pl, bool mixed,
-                                hipStream_t s, const int* slot_row) {
+                                hipStream_t s, const int* slot_row, int row_base, int p0, int p1) {
     const double gscale = mixed ? p.s32 : 1.0;
-    hipLaunchKernelGGL(field_combine_kernel, dim3(nblk(f.np, kCombPts)), dim3(kCombPts * kCombWays), 0, s,
-                       f.partial, slot_row, f.np, pl.slot, pl.slots, pl.groups, gscale, f.pts64, f.np_pad, p.qpos, p.q,
+    if (p1 < 0) p1 = f.np;
+    if (p1 <= p0) return hipSuccess;
+    hipLaunchKernelGGL(field_combine_kernel, dim3(nblk(p1 - p0, kCombPts)), dim3(kCombPts * kCombWays), 0, s,
+                       f.partial, slot_row, row_base, p0, p1, pl.slot, pl.slots, pl.groups, gscale, f.pts64, f.np_pad, p.qpos, p.q,
                        p.nc, p.eps1, p.eps, f.out, f.inside);
     return hipGetLastError();
 }

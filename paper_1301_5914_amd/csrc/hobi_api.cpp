@@ -1173,26 +1173,44 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
             srow.push_back((int)items.size());
         }
     }
-    const size_t nparts = (tree ? items.size() : (size_t)pl.workers) * 5 * pl.slot;
+    // treecode: passes over runs of slots whose partial rows fit kFieldTreeRows doubles
+    std::vector<int> pass_start(1, 0);
+    size_t pass_rows = 0;
+    if (tree) {
+        const size_t row = 5 * (size_t)pl.slot;
+        for (int sl = 0; sl < pl.slots; ++sl) {
+            const size_t rows_now = (size_t)(srow[sl + 1] - srow[pass_start.back()]);
+            if (sl > pass_start.back() && rows_now * row > kFieldTreeRows) pass_start.push_back(sl);
+            pass_rows = std::max(pass_rows, (size_t)(srow[sl + 1] - srow[pass_start.back()]));
+        }
+        pass_start.push_back(pl.slots);
+    }
+    const size_t nparts = (tree ? pass_rows : (size_t)pl.workers) * 5 * pl.slot;
     if ((e = grow(&f.partial, &f.cap_partial, nparts)) != hipSuccess ||
         (e = grow(&f.gstart, &f.cap_gstart, gs.size())) != hipSuccess ||
         (e = grow(&f.out, &f.cap_out, 9 * (size_t)np)) != hipSuccess ||
         (e = grow(&f.inside, &f.cap_inside, (size_t)np)) != hipSuccess ||
         (e = grow(&f.outc, &f.cap_outc, 8 * (size_t)np)) != hipSuccess ||
         (e = grow(&f.insc, &f.cap_insc, (size_t)np + 1)) != hipSuccess ||
-        (tree && (e = grow(&f.items, &f.cap_items, items.size())) != hipSuccess) ||
+        (tree && (e = grow(&f.items, &f.cap_items, pass_rows)) != hipSuccess) ||
         (tree && (e = grow(&f.slot_row, &f.cap_slot_row, srow.size())) != hipSuccess))
         return fail(c, e == hipErrorOutOfMemory ? HOBI_E_OOM : HOBI_E_HIP, "field work space: %s",
                     hipGetErrorString(e));
     if (tree) {
-        HIPCHK(c, hipMemcpyAsync(f.items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, s));
         HIPCHK(c, hipMemcpyAsync(f.slot_row, srow.data(), sizeof(int) * srow.size(), hipMemcpyHostToDevice, s));
         HIPCHK(c, launch_tree_proxies(d, mixed, s));
-        {
-            ScopedTimer t(pb, T_FIELD);
-            HIPCHK(c, launch_field_tree_pairs(d, f, (int)items.size(), mixed, s));
+        for (size_t k = 0; k + 1 < pass_start.size(); ++k) {
+            const int s0 = pass_start[k], s1 = pass_start[k + 1];
+            const int r0 = srow[s0], nrow = srow[s1] - srow[s0];
+            if (k > 0) HIPCHK(c, hipStreamSynchronize(s));   // the previous pass is done with f.items
+            HIPCHK(c, hipMemcpyAsync(f.items, items.data() + r0, sizeof(int4) * (size_t)nrow, hipMemcpyHostToDevice, s));
+            {
+                ScopedTimer t(pb, T_FIELD);
+                HIPCHK(c, launch_field_tree_pairs(d, f, nrow, mixed, s));
+            }
+            HIPCHK(c, launch_field_combine(d, f, pl, mixed, s, f.slot_row, r0, s0 * pl.slot,
+                                           std::min(s1 * pl.slot, np)));
         }
-        HIPCHK(c, launch_field_combine(d, f, pl, mixed, s, f.slot_row));
     } else {
         HIPCHK(c, hipMemcpyAsync(f.gstart, gs.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
         pl.gstart = f.gstart;

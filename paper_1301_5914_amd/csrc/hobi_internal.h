@@ -179,11 +179,14 @@ int field_resident_waves(int device, bool mixed);
 // with the same precision), then the per-point combine.
 hipError_t launch_field_pairs(const DeviceProblem& p, const FieldWork& f, const PairPlan& plan, bool mixed,
                               hipStream_t s);
-// slot_row non-null: the rows of slot s are the treecode items slot_row[s] .. slot_row[s + 1] - 1
+// slot_row non-null: the rows of slot s are the treecode items slot_row[s] .. slot_row[s + 1] - 1,
+// stored from row_base on; the points [p0, p1) (p1 < 0: all)
 hipError_t launch_field_combine(const DeviceProblem& p, const FieldWork& f, const PairPlan& plan, bool mixed,
-                                hipStream_t s, const int* slot_row = nullptr);
+                                hipStream_t s, const int* slot_row = nullptr, int row_base = 0, int p0 = 0,
+                                int p1 = -1);
 // treecode field (proxy charges computed): one wave per item of f.items, nitems of them
 constexpr int kFieldTreeBatch = 64 * kFieldTpl32;   // points per batch: one FP32 field slot
+constexpr size_t kFieldTreeRows = (size_t)1 << 29;  // partial-row doubles of one pass (4 GiB)
 hipError_t launch_field_tree_pairs(const DeviceProblem& p, const FieldWork& f, int nitems, bool mixed,
                                    hipStream_t s);
 hipError_t launch_permute(const double* in, double* out, const int* perm, int nv, bool to_internal,

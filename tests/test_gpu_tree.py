@@ -275,6 +275,30 @@ def test_tree_field_bench_map_L6_against_dense(ctx):
     np.testing.assert_array_equal(out["inside"], dense["inside"])
 
 
+def test_tree_field_large_map_in_passes(ctx):
+    """A 150^3 lattice through the L6 surface (about 3 million points) at theta 0.5: the
+    treecode's partial rows (about 15 GiB) exceed one pass's 4 GiB, so the map runs in four
+    passes over runs of point slots; against the dense field sums within 1e-4 of each
+    output's largest magnitude (measured 7.7e-6 for phi, 2.0e-5 for R), same sides."""
+    p = inputs.kirkwood_offcenter(6)
+    u = inputs.random_vector(2 * p.nv, 38)
+    pts = _lattice(150, half=7.9)
+    print(f"large map: {pts.shape[0]} points", flush=True)
+    dense = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED).field(u, pts)
+    g = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED, tree_theta=0.5, tree_degree=5)
+    out = g.field(u, pts)
+    s = g.stats()
+    rows = (s["field_tree_far_pairs"] + s["field_tree_near_pairs"]) * 5 * 256 * 8
+    print(f"  far {s['field_tree_far_pairs']} near {s['field_tree_near_pairs']}: about {rows / 2**30:.1f} GiB "
+          f"of partial rows", flush=True)
+    assert rows > 2 ** 32              # more than one pass
+    for key in ("phi", "field", "reac", "reac_field"):
+        err = _rel(out[key], dense[key])
+        print(f"  {key} rel err vs dense {err:.3e}", flush=True)
+        assert err <= 1e-4, (key, err)
+    np.testing.assert_array_equal(out["inside"], dense["inside"])
+
+
 def test_tree_parameter_errors(ctx):
     p = inputs.kirkwood_offcenter(2)
     bad = [dict(tree_theta=-0.1), dict(tree_theta=float("nan")), dict(tree_theta=0.5, tree_degree=0),
