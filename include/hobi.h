@@ -213,9 +213,9 @@ hobi_status hobi_energy(hobi_problem pb, const double* u, int32_t on_device,
  * in Morton order form batches of 256 that walk its cluster tree with the acceptance test
  * alone (no incidence rule off the surface); accepted clusters add R, grad R and the
  * solid angle from their proxy charges (the solid angle from the charge of the unit
- * double layer), near leaves their nodes directly.  Its work space grows with the
- * points: one row of partial sums per (slot of points, cluster) pair, about 6 KB per
- * point at the default parameters (1.5 GB for a 64^3 map); HOBI_E_OOM if it does not fit.
+ * double layer), near leaves their nodes directly.  Its partial sums take one row per
+ * (slot of points, cluster) pair, about 6 KB per point at the default parameters; larger
+ * maps run in passes of at most 4 GiB of rows.
  * There is no near-singular treatment: within about one edge length of the surface the
  * rule's error grows, and a point on the surface is not a valid argument.
  * Synchronous: returns when the outputs are written.  The work space it allocates on the
