@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -746,6 +747,37 @@ def molecule(n_atoms: int = 500, seed: int = 3, grid: float = 0.5, ball_radius=N
     c, r, q = pack_atoms(n_atoms, R, seed)
     xyz, nrm, tri = molecule_surface(c, r, grid=grid)
     return Problem(xyz, nrm, tri, c, q, eps1, eps2, kappa, name=f"molecule_{n_atoms}_s{seed}")
+
+
+# Surfaces too slow to generate on the fly, stored by meshes/make_meshes.py (positions and
+# triangles; the atoms and normals are recomputed here from the same generator).
+MESH_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "meshes")
+STORED_MOLECULES = {
+    # 5000 atoms at protein density, marched at 0.4 A: 267,718 triangles, 133,859 vertices
+    "molecule_5000_s4_g0.4": {"n_atoms": 5000, "seed": 4, "grid": 0.4},
+}
+
+
+def stored_molecule(name: str = "molecule_5000_s4_g0.4", eps1: float = 1.0, eps2: float = 80.0,
+                    kappa: float = 0.1257) -> Problem:
+    """A protein-like molecule of STORED_MOLECULES: the stored surface positions and
+    triangles, the atoms and charges from pack_atoms with the same seed, and the vertex
+    normals as molecule_surface computes them (-grad rho / |grad rho|, face-averaged at the
+    vertices of remaining folds).  Raises if the stored vertices do not lie on the density
+    iso-surface of those atoms."""
+    spec = STORED_MOLECULES[name]
+    d = np.load(os.path.join(MESH_DIR, name + ".npz"))
+    xyz = np.ascontiguousarray(d["xyz"], dtype=np.float64)
+    tri = np.ascontiguousarray(d["tri"], dtype=np.int32)
+    n = spec["n_atoms"]
+    c, r, q = pack_atoms(n, protein_ball_radius(n), spec["seed"])
+    ag = _AtomGrid(c, r)
+    rho, g = ag.eval(xyz, grad=True)
+    if np.max(np.abs(rho - 1.0)) > 1e-8:
+        raise ValueError(f"{name}: stored vertices are not on the density iso-surface of its atoms")
+    nrm = -g / np.linalg.norm(g, axis=1, keepdims=True)
+    nrm = crease_normals(xyz, tri.astype(np.int64), nrm)
+    return Problem(xyz, nrm, tri, c, q, eps1, eps2, kappa, name=name)
 
 
 def mesh_quality(xyz, tri):
