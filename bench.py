@@ -5,14 +5,16 @@ regular nodes, singular coefficients, source terms), restarted GMRES to ||r||/||
 (every iteration one matvec: gather, dense pair kernel, singular correction + diagonal,
 then Gram-Schmidt/Givens on the device) and the solvation energy.
 
-Workload (default): the off-centre Kirkwood sphere -- radius 4 A, 8 seeded charges in
-r < 2.5 A, eps1 = 1, eps2 = 80, kappa = 0.1257 / A -- on the level-6 icosphere (40962
-vertices, 81920 curved triangles, 327680 quadrature nodes, 1.34e10 pairs per matvec),
-mixed precision (FP32 pair kernel, FP64 everywhere else).
+Workload (default): the large protein-like surface -- 5000 atoms packed at protein density
+(seed 4), partial charges N(0, 0.4) e at the atom centres, the Gaussian-density surface
+marched on a 0.4 A grid (267,718 curved triangles, 133,859 vertices, 1,070,872 quadrature
+nodes, 1.43e11 pairs per matvec), eps1 = 1, eps2 = 80, kappa = 0.1257 / A, mixed precision
+(FP32 pair kernel, FP64 everywhere else).  The off-centre Kirkwood sphere at icosphere
+level 6 is measured beside it (matvec and pair kernel, energy against the series).
 
 Prints one JSON line: value = matvec (vertex, node) pairs evaluated per second over the
-timed steps (G-pairs/s), with the dominant kernel's roofline and the FP64 oracle's rate on
-the host cores beside it.
+timed steps (G-pairs/s), with the dominant kernel's roofline, the FP64 oracle's rate on
+the host cores and the GPU rows' error against the oracle's rows beside it.
 """
 from __future__ import annotations
 
@@ -28,12 +30,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOPS_PER_PAIR = {True: 58, False: 28}      # kappa > 0 / kappa = 0 (algorithmic count)
-PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}  # published FP32 (packed) and FP64 vector peaks
-PEAK_NONPACKED_FP32 = 78.6                    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
-# HBM bytes per launch of the FP32 pair kernel on the default workload (icosphere L6):
-# rocprofv3 FETCH_SIZE (x2.000) + WRITE_SIZE (x1.000), each scaled by a 256 MiB copy.
-# Only valid for the kernel build it was measured on; null for any other configuration.
-PAIR_F32_L6_TRAFFIC_BYTES = (29821.0 * 2.000 + 518569.0 * 1.000) * 1024
+TRANS_PER_PAIR = {True: 2, False: 1}        # exp and rsqrt / rsqrt only
+PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}  # published FP32 and FP64 vector peaks
+CUS, CLOCK_HZ = 256, 2.4e9
+FLOPS_PER_CLK_CU = {"mixed": 256.0, "fp64": 128.0}   # the peaks above per clock per CU
+# HBM bytes per launch of the FP32 pair kernel on the default workload, from two rocprofv3
+# --pmc passes (FETCH_SIZE, WRITE_SIZE; each scaled by what it reads for a plain device copy
+# of known size), valid only for the kernel sources they were taken on: keyed by the
+# workload and a hash of those sources, else the bench reports null.
+PAIR_TRAFFIC = {}   # (workload, precision, sources sha16) -> (bytes per launch, profile file)
+KERNEL_SOURCES = ("paper_1301_5914_amd/csrc/pair_tile.h", "paper_1301_5914_amd/csrc/pair_kernels.hip",
+                  "paper_1301_5914_amd/csrc/hobi_device.h")
+
+# Cycles of one wave64 transcendental instruction on a SIMD at 2.4 GHz, measured by the
+# issue-rate probe (paper_1301_5914_amd/probes/issue_rate.hip, profiles/valu_issue_rate_probe.md);
+# results per clock per compute unit = 4 SIMDs x 64 lanes / cycles.
+TRANS_CYCLES_F32 = {"exp": 8.32, "rsq": 8.19}
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def workload(args):
@@ -43,6 +64,8 @@ def workload(args):
         d = np.load(args.mesh)
         return inputs.Problem(d["xyz"], d["nrm"], d["tri"].astype(np.int32), d["qpos"], d["q"],
                               name=os.path.basename(args.mesh))
+    if args.workload == "large":
+        return inputs.stored_molecule("molecule_5000_s4_g0.4")
     if args.workload == "molecule":
         return inputs.molecule(args.atoms, seed=args.seed)
     return inputs.kirkwood_offcenter(args.level)
@@ -51,17 +74,33 @@ def workload(args):
 def workload_name(args, prob):
     if args.mesh:
         return f"surface loaded from {prob.name} ({args.mesh_label or 'saved surface'}), {prob.nf} triangles"
+    if args.workload == "large":
+        return (f"large protein-like surface: 5000 atoms at protein density (seed 4), Gaussian density "
+                f"marched at 0.4 A, {prob.nf} triangles, {prob.nv} vertices")
     if args.workload == "molecule":
         return (f"protein-like surface, {args.atoms} atoms (seed {args.seed}) at protein density, "
                 f"Gaussian density marched at 0.5 A, {prob.nf} triangles")
     return f"off-centre Kirkwood sphere R=4 A, 8 charges, icosphere L{args.level}"
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(prob, seconds: float, workers: int, lower: bool = False):
-    """The FP64 oracle's matvec on a bounded sample of rows of the same workload."""
+    """The FP64 oracle's matvec on a bounded sample of rows of the same workload.  Returns
+    the baseline record and (u, rows, oracle rows) for the comparison with the GPU rows."""
     from paper_1301_5914_amd import inputs
 
     eps = prob.eps2 / prob.eps1
+    t_setup = time.perf_counter()
     if lower:
         from oracle import lobi as LO
         st = LO.setup(prob.xyz, prob.nrm, prob.tri)
@@ -78,20 +117,108 @@ def cpu_baseline(prob, seconds: float, workers: int, lower: bool = False):
         def rows_fn(u, rows):
             return O.matvec(st, u, prob.kappa, eps, rows=rows, workers=workers)
         cores = workers
+    t_setup = time.perf_counter() - t_setup
     u = inputs.random_vector(2 * n_sites, 1)
+    rng = np.random.default_rng(0)
     # per-row cost measured with all workers busy, then a sample sized to ~`seconds`
-    probe = np.arange(4 * cores)
+    probe = np.sort(rng.choice(n_sites, min(n_sites, 2 * cores), replace=False))
     t0 = time.perf_counter()
     rows_fn(u, probe)
     per_row = (time.perf_counter() - t0) / probe.size
     nrows = int(min(n_sites, max(probe.size, seconds / max(per_row, 1e-9))))
-    rows = np.arange(nrows)
+    rows = np.sort(rng.choice(n_sites, nrows, replace=False))
     t0 = time.perf_counter()
-    rows_fn(u, rows)
+    y_rows = rows_fn(u, rows)
     dt = time.perf_counter() - t0
     pairs = nrows * n_nodes
-    return {"value": pairs / dt / 1e9, "unit": "G-pairs/s", "cores": cores, "kind": "oracle",
-            "sample": f"{nrows} of {n_sites} matvec rows (x {n_nodes} nodes), {dt:.1f} s"}
+    rec = {"value": pairs / dt / 1e9, "unit": "G-pairs/s", "cores": cores, "kind": "oracle",
+           "sample": f"{nrows} random of {n_sites} matvec rows (x {n_nodes} nodes), {dt:.1f} s "
+                     f"(oracle setup {t_setup:.1f} s, not timed)",
+           "cpu_model": cpu_model(), "host_cpus_visible": len(os.sched_getaffinity(0))}
+    return rec, (u, rows, y_rows)
+
+
+def rows_rel_err(y_gpu, sample):
+    """max |GPU rows - oracle rows| / max |oracle rows| over the sampled row pairs."""
+    u, rows, y_or = sample
+    n = y_gpu.shape[0] // 2
+    got = np.stack([y_gpu[rows], y_gpu[n + rows]])
+    return float(np.max(np.abs(got - y_or)) / np.max(np.abs(y_or)))
+
+
+def pair_roofline(precision: str, kappa_pos: bool, pairs: int, avg_ms: float, workload_key: str):
+    """Roofline of the dominant kernel (the dense pair kernel): algorithmic flops per launch
+    over the HIP-event average launch time, against the published vector peak; the
+    mix-adjusted fraction charges each pair its transcendentals at the probed rate."""
+    flops = FLOPS_PER_PAIR[kappa_pos] * pairs
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[precision]
+    out = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+           "traffic": None, "kernel": "pair_f32_kernel" if precision == "mixed" else "pair_f64_kernel",
+           "flops_per_pair": FLOPS_PER_PAIR[kappa_pos]}
+    if precision == "mixed" and TRANS_CYCLES_F32["exp"]:
+        # clocks of one CU per pair: flops at 256 per clock, each transcendental at tau per clock
+        tau_exp = 4 * 64 / TRANS_CYCLES_F32["exp"]
+        tau_rsq = 4 * 64 / TRANS_CYCLES_F32["rsq"]
+        clk = FLOPS_PER_PAIR[kappa_pos] / FLOPS_PER_CLK_CU["mixed"] + 1.0 / tau_rsq + (1.0 / tau_exp if kappa_pos else 0.0)
+        pairs_max = CUS * CLOCK_HZ / clk
+        out["mix_adjusted"] = {"pairs_per_s_ceiling": pairs_max, "tau_exp": tau_exp, "tau_rsq": tau_rsq,
+                               "frac": pairs / (avg_ms * 1e-3) / pairs_max,
+                               "source": "profiles/valu_issue_rate_probe.md"}
+    key = (workload_key, precision, kernel_sources_hash())
+    if key in PAIR_TRAFFIC:
+        out["traffic"], out["traffic_source"] = PAIR_TRAFFIC[key]
+    out["kernel_sources_sha16"] = key[2]
+    return out
+
+
+def l6_leg(ctx, stream, mixed):
+    """The off-centre Kirkwood sphere at icosphere level 6 beside the headline workload: the
+    matvec (median of 20 after 3 warm-ups), the pair kernel (HIP events) and a solve's energy
+    against the Kirkwood series."""
+    import torch
+    from oracle import kirkwood as KW
+    from paper_1301_5914_amd import hobi, inputs
+    p = inputs.kirkwood_offcenter(6)
+    pb = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED if mixed else hobi.HOBI_FP64,
+                                  max_iter=400, restart=400)
+    res = pb.solve()
+    mv = matvec_median(pb, stream, 2 * p.nv)
+    pb.reset_stats()
+    u = torch.randn(2 * p.nv, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(u)
+    for _ in range(20):
+        pb.matvec(u, out=y)
+    torch.cuda.synchronize()
+    st = pb.stats()
+    avg = st["ms_pair_kernel"] / max(1, st["pair_launches"])
+    pairs = p.nv * 4 * p.nf
+    E = KW.solvation_energy(p.qpos, p.q, 4.0, p.eps1, p.eps2, p.kappa)
+    return {"workload": "off-centre Kirkwood sphere R=4 A, 8 charges, icosphere L6", "nv": p.nv, "nf": p.nf,
+            "pairs_per_matvec": pairs, "matvec_ms_median": mv, "matvec_gpairs_per_s": pairs / (mv * 1e-3) / 1e9,
+            "pair_kernel_ms": avg,
+            "roofline": pair_roofline("mixed" if mixed else "fp64", True, pairs, avg, "kirkwood_L6"),
+            "gmres_iterations": res["stats"]["iterations"], "solve_ms": res["stats"]["ms_solve"],
+            "energy_rel_err_vs_kirkwood": abs(res["energy"] / E - 1)}
+
+
+def matvec_median(pb, stream, n, reps=20, warm=3):
+    """Median ms of hobi_matvec on device vectors (HIP events on the library's stream)."""
+    import torch
+    u = torch.randn(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(u)
+    torch.cuda.synchronize()
+    ms = []
+    for i in range(reps + warm):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        pb.matvec(u, out=y)
+        ev1.record(stream)
+        ev1.synchronize()
+        if i >= warm:
+            ms.append(ev0.elapsed_time(ev1))
+    return float(np.median(ms))
 
 
 FIELD_FLOPS_PER_PAIR = {True: 60, False: 41}   # R, grad R and the solid angle per (point, node)
@@ -230,7 +357,7 @@ def _make_molecule_job(indexed_job):
 def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slots, n_check, tree_theta=0.0):
     """Poisson request stream through the continuous-batching server (mixed precision; with
     tree_theta > 0 every request takes the treecode with the default degree, leaf and
-    batch, and the energy check is still against the dense FP64 solve)."""
+    batch).  Served results are checked against the FP64 oracle."""
     from paper_1301_5914_amd import hobi
 
     rng = np.random.default_rng(seed)
@@ -285,19 +412,42 @@ def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slot
     sv.close()
     pairs = sum(r["stats"]["pairs_per_matvec"] * r["stats"]["iterations"] for r in results.values())
     ok = sum(1 for r in results.values() if r["status"] == "HOBI_OK")
-    # per-request energy error against the single-problem FP64 path (oracle-validated)
-    errs, checks = [], []
-    for t in list(results)[:n_check]:
+    # checks against the FP64 oracle: the served solution's energy recomputed by the oracle,
+    # and the oracle's residual rows b - A u of the served solution (random rows), on
+    # n_check requests with distinct (molecule, eps1, kappa), smallest molecules first
+    # (single process: the GPU is initialised, so the oracle forks no workers here)
+    from oracle import COULOMB_KCAL, FOUR_PI
+    from oracle import operator as O
+    seen, picks = set(), []
+    for t in sorted(results, key=lambda t: (reqs[sub_time[t][1]][0].nf, t)):
         m, e1, kap = reqs[sub_time[t][1]]
-        ref = hobi.Problem(ctx, m.xyz, m.nrm, m.tri, m.qpos, m.q, eps1=e1, eps2=m.eps2, kappa=kap,
-                           max_iter=400, restart=400).solve(allow_noconv=True)
-        errs.append(abs(results[t]["energy"] / ref["energy"] - 1))
-        print(f"[bench] check {len(errs)}/{n_check}: {m.nf} triangles, energy error {errs[-1]:.2e}",
-              file=sys.stderr, flush=True)
-        checks.append({"nf": m.nf, "eps1": e1, "kappa": kap, "err": errs[-1],
-                       "its": results[t]["stats"]["iterations"], "its_fp64": ref["stats"]["iterations"],
-                       "status": results[t]["status"], "status_fp64": ref["status"],
-                       "E": results[t]["energy"], "E_fp64": ref["energy"]})
+        if (id(m), e1, kap) in seen or results[t]["status"] != "HOBI_OK":
+            continue
+        seen.add((id(m), e1, kap))
+        picks.append(t)
+        if len(picks) == n_check:
+            break
+    setups, checks = {}, []
+    crng = np.random.default_rng(7)
+    for t in picks:
+        m, e1, kap = reqs[sub_time[t][1]]
+        if id(m) not in setups:
+            setups[id(m)] = O.setup(m.xyz, m.nrm, m.tri)
+        st_or = setups[id(m)]
+        eps = m.eps2 / e1
+        r = results[t]
+        u = np.concatenate([r["phi"], r["dphi"]]) / (FOUR_PI * COULOMB_KCAL)
+        E_or = O.solvation_energy(st_or, u, m.qpos, m.q, kap, eps)
+        S1, S2 = O.sources(st_or.xyz, st_or.nrm, m.qpos, m.q, e1)
+        rows = np.sort(crng.choice(m.nv, min(32, m.nv), replace=False))
+        Au = O.matvec(st_or, u, kap, eps, rows=rows)
+        b = np.stack([S1[rows], S2[rows]])
+        resid = float(np.max(np.abs(b - Au)) / max(np.max(np.abs(S1)), np.max(np.abs(S2))))
+        checks.append({"nf": m.nf, "nc": m.nc, "eps1": e1, "kappa": kap, "its": r["stats"]["iterations"],
+                       "E": r["energy"], "E_oracle_at_u": E_or, "energy_rel_err": abs(r["energy"] / E_or - 1),
+                       "oracle_residual_rows": resid})
+        print(f"[bench] oracle check {len(checks)}/{len(picks)}: {m.nf} triangles, energy {checks[-1]['energy_rel_err']:.1e}, "
+              f"residual rows {resid:.1e}", file=sys.stderr, flush=True)
     lat_ms = np.array(lat) * 1e3
     sizes = [m.nf for m in pool_mols]
     return {
@@ -309,8 +459,13 @@ def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slot
         "mean_active_per_tick": st["mean_batch"], "ticks": st["ticks"], "peak_hbm_bytes": st["peak_bytes"],
         "budget_bytes": budget_bytes,
         "pool": {"molecules": len(pool_mols), "triangles_min": int(min(sizes)), "triangles_max": int(max(sizes))},
-        "energy_rel_err_vs_fp64_max": float(max(errs)) if errs else None, "energy_checked": len(errs),
-        "checks": checks,
+        "oracle_checks": {
+            "requests": len(checks),
+            "energy_rel_err_max": max((c["energy_rel_err"] for c in checks), default=None),
+            "residual_rows_max": max((c["oracle_residual_rows"] for c in checks), default=None),
+            "what": "served solution u: |E_served / E_oracle(u) - 1| and max |b - A u| / max |b| over 32 "
+                    "random oracle rows (FP64 oracle), distinct (molecule, eps1, kappa), smallest first",
+            "checks": checks},
     }
 
 
@@ -319,7 +474,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["kirkwood", "molecule"], default="kirkwood")
+    ap.add_argument("--workload", choices=["large", "kirkwood", "molecule"], default="large",
+                    help="large: the stored 5000-atom surface (default); kirkwood: the off-centre sphere at "
+                         "--level; molecule: a generated protein-like surface of --atoms atoms")
     ap.add_argument("--level", type=int, default=6, help="icosphere level (kirkwood)")
     ap.add_argument("--atoms", type=int, default=500, help="atom count (molecule)")
     ap.add_argument("--seed", type=int, default=3, help="packing seed (molecule)")
@@ -332,7 +489,8 @@ def main():
     ap.add_argument("--mesh-label", default=None, help="description of the loaded surface for the JSON line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--no-compare", action="store_true", help="skip the comparison solve in the other precision")
+    ap.add_argument("--no-l6", action="store_true", help="skip the icosphere-L6 leg beside the workload")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests in the served stream (0: skip the serving measurement)")
     ap.add_argument("--serve-pool", type=int, default=8, help="distinct molecules the stream draws from")
@@ -341,6 +499,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=0.7, help="arrival rate / saturated throughput")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-checks", type=int, default=16, help="served requests checked against the oracle")
     ap.add_argument("--serve-tree-theta", type=float, default=0.0,
                     help="serve the stream with the treecode at this opening parameter (0: dense)")
     ap.add_argument("--field-map", type=int, default=64,
@@ -357,16 +516,21 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     prob = workload(args)
+    progress(f"workload: {prob.nv} sites, {prob.nf} triangles")
     pool_mols = None
+    # the box gives one GPU's job a share of 16 host cores
+    host_workers = max(1, min(16, len(os.sched_getaffinity(0))))
     if args.serve_requests > 0:
-        pool_mols = build_pool(args.serve_pool, args.serve_min_atoms, args.serve_max_atoms, 5,
-                               max(1, min(16, len(os.sched_getaffinity(0)))))
-    cpu = None
+        pool_mols = build_pool(args.serve_pool, args.serve_min_atoms, args.serve_max_atoms, 5, host_workers)
+    cpu, sample = None, None
     if not args.no_cpu_baseline:
         # before any GPU call: the oracle forks worker processes
-        workers = max(1, min(16, len(os.sched_getaffinity(0))))
-        cpu = cpu_baseline(prob, args.cpu_seconds, workers, lower=args.method == "lower")
+        cpu, sample = cpu_baseline(prob, args.cpu_seconds, host_workers, lower=args.method == "lower")
+        progress(f"oracle baseline: {cpu['sample']}")
 
     import torch
     from oracle import kirkwood as KW
@@ -381,6 +545,7 @@ def main():
     pb = hobi.Problem.from_inputs(ctx, prob, precision=hobi.HOBI_MIXED if mixed else hobi.HOBI_FP64,
                                   method=hobi.HOBI_LOWER_ORDER if lower else hobi.HOBI_HIGHER_ORDER,
                                   max_iter=args.max_iter, restart=args.max_iter)
+    progress("problem created")
 
     def step():
         pb.set_dielectric(prob.eps1, prob.eps2, prob.kappa)
@@ -388,6 +553,7 @@ def main():
 
     for _ in range(args.warmup):
         step()
+    progress("warm-up done")
     pb.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -395,18 +561,18 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kst = pb.stats()
+    progress(f"timed steps done: {wall:.1f} s")
 
     pairs_mv = n_sites * n_nodes
     matvecs = sum(r["stats"]["iterations"] + 1 for r in results)   # + the true-residual matvec
     value = matvecs * pairs_mv / wall / 1e9
     avg_pair_ms = kst["ms_pair_kernel"] / max(1, kst["pair_launches"])
-    flops = FLOPS_PER_PAIR[prob.kappa > 0] * pairs_mv
-    achieved = flops / (avg_pair_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.precision]
     E = results[-1]["energy"]
     E_exact = None
     if args.workload == "kirkwood" and not args.mesh:
         E_exact = KW.solvation_energy(prob.qpos, prob.q, 4.0, prob.eps1, prob.eps2, prob.kappa)
+    wkey = ("large" if args.workload == "large" and not args.mesh else
+            f"{args.workload}_{args.level if args.workload == 'kirkwood' else args.atoms}") + ("_lower" if lower else "")
     out = {
         "metric": "matvec G-pairs/s + GMRES solve time to 1e-6; serving p50/p99 latency",
         "value": value,
@@ -421,11 +587,13 @@ def main():
         "dtype": "f32-pairs/f64-accumulate" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": workload_name(args, prob),
-                   "nv": prob.nv, "nf": prob.nf, "nodes": n_nodes, "pairs_per_matvec": pairs_mv,
+                   "nv": prob.nv, "nf": prob.nf, "nc": prob.nc, "nodes": n_nodes, "pairs_per_matvec": pairs_mv,
                    "method": args.method,
                    "kappa": prob.kappa, "eps1": prob.eps1, "eps2": prob.eps2, "rtol": 1e-6,
                    "precision": args.precision},
         "gmres_iterations": results[-1]["stats"]["iterations"],
+        "gmres_converged": bool(results[-1]["stats"]["converged"]),
+        "true_residual": results[-1]["stats"]["true_residual"],
         "solve_ms": float(np.mean([r["stats"]["ms_solve"] for r in results])),
         "setup_ms": results[-1]["stats"]["ms_setup"],
         "energy_ms": results[-1]["stats"]["ms_energy"],
@@ -433,39 +601,27 @@ def main():
         "pair_kernel_gpairs_per_s": pairs_mv / (avg_pair_ms * 1e-3) / 1e9,
         "energy_kcal_mol": E,
         "energy_rel_err_vs_kirkwood": abs(E / E_exact - 1) if E_exact else None,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "traffic": (PAIR_F32_L6_TRAFFIC_BYTES
-                                 if (mixed and args.workload == "kirkwood" and args.level == 6 and not args.mesh and not lower)
-                                 else None),
-                     "frac_nonpacked_fp32": achieved / PEAK_NONPACKED_FP32 if mixed else None,
-                     "kernel": "pair_f32_kernel" if mixed else "pair_f64_kernel",
-                     "flops_per_pair": FLOPS_PER_PAIR[prob.kappa > 0]},
+        "roofline": pair_roofline(args.precision, prob.kappa > 0, pairs_mv, avg_pair_ms, wkey),
     }
     # matvec alone (rows a1-a4, device vectors): median of 20 after 3 warm-ups, HIP events
     # on the library's stream around each call
-    uvec = torch.randn(2 * n_sites, dtype=torch.float64, device="cuda")
-    yvec = torch.empty_like(uvec)
-    torch.cuda.synchronize()
-    mv_ms = []
-    for i in range(23):
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        pb.matvec(uvec, out=yvec)
-        ev1.record(stream)
-        ev1.synchronize()
-        if i >= 3:
-            mv_ms.append(ev0.elapsed_time(ev1))
-    out["matvec_ms_median"] = float(np.median(mv_ms))
+    out["matvec_ms_median"] = matvec_median(pb, stream, 2 * n_sites)
     out["matvec_gpairs_per_s"] = pairs_mv / (out["matvec_ms_median"] * 1e-3) / 1e9
+    if sample is not None:
+        # the GPU's rows of the same matvec against the oracle's rows of cpu_baseline
+        y = pb.matvec(sample[0])
+        out["oracle_rows"] = {"rows": int(sample[1].size), "rel_err": rows_rel_err(y, sample),
+                              "what": "max |y_gpu - y_oracle| / max |y_oracle| over the cpu_baseline rows, same u"}
+    progress("matvec timed")
     if args.field_map > 0:
         out["field"] = field_bench(pb, prob, args.field_map, results[-1], mixed, n_nodes)
+        progress("field map done")
     if args.tree_theta > 0:
         # (hobi_field takes the treecode with the higher-order method only: no map otherwise)
         out["tree"] = tree_bench(ctx, stream, prob, args.tree_theta, args.tree_degree, args.tree_leaf,
                                  args.tree_batch, mixed, pb, results[-1], out["matvec_ms_median"], pairs_mv,
                                  grid=0 if lower else args.field_map, lower=lower)
+        progress("treecode leg done")
     if not args.no_compare:
         # the other precision on the same problem (outside the timed region)
         pb.set_precision(hobi.HOBI_FP64 if mixed else hobi.HOBI_MIXED)
@@ -479,10 +635,19 @@ def main():
             "other_precision": "fp64" if mixed else "mixed",
             "other_solve_ms": other["stats"]["ms_solve"],
             "other_iterations": other["stats"]["iterations"],
+            "other_converged": bool(other["stats"]["converged"]),
             "other_pair_kernel_ms": o_pair,
+            "other_roofline": pair_roofline("fp64" if mixed else "mixed", prob.kappa > 0, pairs_mv, o_pair, wkey),
             "mixed_vs_fp64_energy_rel": abs(mixed_E / fp64_E - 1),
             "speedup_mixed_over_fp64_pair_kernel": (o_pair / avg_pair_ms) if mixed else (avg_pair_ms / o_pair),
         }
+        if sample is not None:
+            out["compare"]["other_oracle_rows_rel_err"] = rows_rel_err(pb.matvec(sample[0]), sample)
+        pb.set_precision(hobi.HOBI_MIXED if mixed else hobi.HOBI_FP64)
+        progress("comparison solve done")
+    if not args.no_l6 and not (args.workload == "kirkwood" and args.level == 6) and not lower:
+        out["l6"] = l6_leg(ctx, stream, mixed)
+        progress("L6 leg done")
     if args.calibrate_copy:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -491,8 +656,13 @@ def main():
         out["calibration_copy_bytes"] = src.numel() * 4
     if pool_mols is not None:
         out["serving"] = serve_bench(pool_mols, args.serve_requests, 5, args.serve_rate,
-                                     int(args.serve_budget_gb * (1 << 30)), args.serve_slots, n_check=8,
+                                     int(args.serve_budget_gb * (1 << 30)), args.serve_slots, args.serve_checks,
                                      tree_theta=args.serve_tree_theta)
+        full = (args.serve_requests >= 512 and args.serve_pool >= 16 and args.serve_max_atoms >= 3000)
+        out["serving"]["reduced"] = not full
+        if not full:
+            out["serving"]["full_stream"] = ("512 requests, 16 molecules of 50-3000 atoms: "
+                                             "profiles/serving_stream_512_requests.md")
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -339,3 +339,40 @@ def test_molecule500_sampled_rows_and_energy(ctx, mol500):
           flush=True)
     assert r64["stats"]["converged"] == 1 and r32["stats"]["converged"] == 1
     assert abs(r32["energy"] / r64["energy"] - 1) <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def large():
+    print("loading the stored 5000-atom surface", flush=True)
+    return inputs.stored_molecule("molecule_5000_s4_g0.4")
+
+
+def test_large_molecule_sampled_rows_and_energy(ctx, large):
+    """The default bench workload at full size: 5000 atoms, 267,718 triangles, 133,859
+    vertices, 1.43e11 pairs per matvec, in the launch configuration bench.py times (FP32
+    kernel with 8 targets per lane, ~16 passes of node groups).  FP64 rows to 1e-12 and
+    mixed rows to 1e-5 against the oracle computed row by row (first and last target
+    slots, random rows), then full solves: the mixed energy within 1e-5 of the FP64 one."""
+    p = large
+    print(f"large molecule nv={p.nv} nf={p.nf}", flush=True)
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    u = inputs.random_vector(2 * p.nv, 51)
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.r_[0:2, p.nv - 2:p.nv, rng.integers(0, p.nv, 8)])
+    y_or = O.matvec(st, u, p.kappa, p.eps2 / p.eps1, rows=rows)
+    print("oracle rows done", flush=True)
+    res = {}
+    for prec, tol in ((hobi.HOBI_FP64, 1e-12), (hobi.HOBI_MIXED, 1e-5)):
+        g = hobi.Problem.from_inputs(ctx, p, precision=prec, max_iter=400, restart=400)
+        y = g.matvec(u)
+        got = np.stack([y[rows], y[p.nv + rows]])
+        err = _rel_inf(got, y_or)
+        print(f"large precision {prec} rows rel err {err:.3e}", flush=True)
+        assert err <= tol
+        res[prec] = g.solve()
+        print(f"large precision {prec}: E {res[prec]['energy']:.10f} its {res[prec]['stats']['iterations']} "
+              f"true residual {res[prec]['stats']['true_residual']:.2e}", flush=True)
+        assert res[prec]["stats"]["converged"] == 1
+        del g
+    r64, r32 = res[hobi.HOBI_FP64], res[hobi.HOBI_MIXED]
+    assert abs(r32["energy"] / r64["energy"] - 1) <= 1e-5
