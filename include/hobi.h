@@ -185,6 +185,25 @@ hobi_status hobi_solve(hobi_problem pb, double* phi, double* dphi, double* e_sol
  * call is asynchronous with respect to the host in that case). */
 hobi_status hobi_matvec(hobi_problem pb, const double* u, double* y, int32_t on_device);
 
+/* ---- allocation-free variant of hobi_matvec, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid it).
+ * Computes the same y = A u as hobi_matvec for a dense-sum problem (tree_theta = 0), with
+ * the pair sum's partial rows in a static work space of the library (64 MiB per device,
+ * a 64 KiB table of node-group starts and the rows; it lives in the library's code object
+ * and each device that runs the library holds it until the process ends) instead of the
+ * problem's own buffer.  The node groups are cut down to what fits (fewer groups than
+ * hobi_matvec on large problems), so the sum runs in a different order and the result
+ * equals hobi_matvec's up to rounding, not bit for bit.  Allocates nothing and calls no
+ * hipMalloc or hipFree; launches only kernels on the context's stream (asynchronous).
+ * u, y: [2 nv] FP64 device pointers valid on the context's stream, internal units, the
+ * caller's order (as hobi_matvec with on_device = 1); they may not alias.
+ * Every call on a device shares that device's work space and overwrites it (the group
+ * table is rewritten by each call): calls that overlap on one device -- on different
+ * streams, contexts or host threads -- race and give wrong results.
+ * Errors: HOBI_E_ARG (NULL vector; a treecode problem; a problem whose slots' partial rows
+ * for a single node group exceed the work space, about nv > 4 million), HOBI_E_HIP. */
+hobi_status hobi_matvec_noalloc(hobi_problem pb, const double* u, double* y);
+
 /* ---- solvation energy of a given u (eq. solvation_energy, 4-point rule on every
  * triangle; Section 2.6 routine (6)).  u: [2 nv] internal units; e_sol: kcal/mol. */
 hobi_status hobi_energy(hobi_problem pb, const double* u, int32_t on_device,

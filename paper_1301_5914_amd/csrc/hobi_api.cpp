@@ -752,8 +752,11 @@ hobi_status hobi_ctx_create(int device, void* stream, hobi_ctx* out) {
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return HOBI_E_HIP;
     if (device < 0 || device >= ndev) return HOBI_E_ARG;
     if (hipSetDevice(device) != hipSuccess) return HOBI_E_HIP;
+    void* scratch = nullptr;
+    if (hobi::static_scratch_address(device, &scratch) != hipSuccess) return HOBI_E_HIP;
     hobi_ctx c = new hobi_ctx_s();
     c->device = device;
+    c->scratch = scratch;
     if (stream) {
         c->stream = (hipStream_t)stream;
     } else {
@@ -1053,6 +1056,33 @@ hobi_status hobi_matvec(hobi_problem pb, const double* u, double* y, int32_t on_
     if (st != HOBI_OK) return st;
     if ((st = matvec_internal(pb, pb->u_in, pb->y_out)) != HOBI_OK) return st;
     return from_internal(pb, pb->y_out, on_device, y);
+}
+
+hobi_status hobi_matvec_noalloc(hobi_problem pb, const double* u, double* y) {
+    if (!pb) return HOBI_E_ARG;
+    hobi_ctx c = pb->ctx;
+    if (!u || !y) return fail(c, HOBI_E_ARG, "NULL vector");
+    if (pb->d.tree.on) return fail(c, HOBI_E_ARG, "hobi_matvec_noalloc takes the dense sum only (tree_theta = 0)");
+    if (!c->scratch) return fail(c, HOBI_E_HIP, "static work space not resolved");
+    const bool mixed = pb->prm.precision == HOBI_MIXED;
+    PairPlan pl{};
+    size_t row_bytes = 0;
+    if (!make_static_pair_plan(mixed ? pb->d.plan32 : pb->d.plan64, pb->d.nn, &pl, &row_bytes))
+        return fail(c, HOBI_E_ARG, "problem too large for the static work space: one node group needs %zu bytes "
+                    "of partial rows, %zu are available", row_bytes, kStaticScratchBytes - kStaticTableBytes);
+    int* tab = (int*)c->scratch;
+    double* part = (double*)((char*)c->scratch + kStaticTableBytes);
+    pl.gstart = tab;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const DeviceProblem& d = pb->d;
+    HIPCHK(c, launch_permute(u, pb->u_in, pb->d_vperm, d.nv, true, s));
+    HIPCHK(c, launch_group_starts(tab, pl.groups, d.nn, s));
+    HIPCHK(c, launch_gather(d, pb->u_in, mixed, s));
+    HIPCHK(c, launch_pair_plan(d, pl, part, mixed, s));
+    HIPCHK(c, launch_combine_plan(d, pl, part, pb->u_in, pb->y_out, s));
+    HIPCHK(c, launch_permute(pb->y_out, y, pb->d_vperm, d.nv, false, s));
+    return HOBI_OK;
 }
 
 hobi_status hobi_energy(hobi_problem pb, const double* u, int32_t on_device, double* e_sol) {

@@ -15,6 +15,7 @@ struct hobi_ctx_s {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool profile = false;
+    void* scratch = nullptr;   // this device's static work space (hobi_matvec_noalloc)
     std::string err;
 };
 

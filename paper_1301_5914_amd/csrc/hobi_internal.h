@@ -139,6 +139,28 @@ hipError_t launch_gather(const DeviceProblem& p, const double* u, bool mixed, hi
 hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s);
 hipError_t launch_combine(const DeviceProblem& p, const double* u, double* y, bool mixed,
                           hipStream_t s);
+// The same two launches on an explicit plan and partial-row buffer (the plan's gstart must
+// be a device table of groups + 1 node starts).
+hipError_t launch_pair_plan(const DeviceProblem& p, const PairPlan& pl, double* partial, bool mixed,
+                            hipStream_t s);
+hipError_t launch_combine_plan(const DeviceProblem& p, const PairPlan& pl, const double* partial,
+                               const double* u, double* y, hipStream_t s);
+
+// Static work space of the allocation-free matvec (hobi_matvec_noalloc): one array per
+// device in the library's code object, holding a table of node-group starts
+// (kStaticTableBytes) followed by the partial rows of the pair sum.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr size_t kStaticTableBytes = (size_t)64 << 10;
+// The array's device address on `device`, which must be the current device.  Looked up
+// once per device (hipGetSymbolAddress) and cached.
+hipError_t static_scratch_address(int device, void** out);
+// The dense-sum split of `base` (same slots) with its node groups cut down so that the
+// partial rows and the group-start table fit in the static work space; false if not even
+// one group fits (*row_bytes: bytes of one group's rows).  out->gstart is left null.
+bool make_static_pair_plan(const PairPlan& base, int nn, PairPlan* out, size_t* row_bytes);
+// tab[g] = g * nn / groups for g = 0 .. groups (the group starts of make_pair_plan).
+hipError_t launch_group_starts(int* tab, int groups, int nn, hipStream_t s);
+
 // reaction potential at the charges (nodes must hold Gamma/Phi of u) and the energy
 hipError_t launch_reaction_energy(const DeviceProblem& p, double* phi_reac, double* e_out,
                                   hipStream_t s);

@@ -21,7 +21,15 @@
 #include "hobi_internal.h"
 #include "pair_tile.h"
 
+#include <algorithm>
+#include <mutex>
+
 namespace hobi {
+
+// The allocation-free matvec's work space: one copy per device, alive until the process
+// ends.  Host code refers to it only through the address hipGetSymbolAddress returns.
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
 
 namespace {
 
@@ -158,6 +166,12 @@ __global__ void permute_kernel(const double* __restrict__ in, double* __restrict
     }
 }
 
+// Group starts of a pair plan: tab[g] = g * nn / groups (as make_pair_plan computes them).
+__global__ void group_starts_kernel(int* __restrict__ tab, int groups, int nn) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g <= groups) tab[g] = (int)((int64_t)g * nn / groups);
+}
+
 inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
@@ -218,13 +232,13 @@ hipError_t launch_gather(const DeviceProblem& p, const double* u, bool mixed, hi
     return hipGetLastError();
 }
 
-hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s) {
+hipError_t launch_pair_plan(const DeviceProblem& p, const PairPlan& pl, double* partial, bool mixed,
+                            hipStream_t s) {
     const bool k0 = p.kappa == 0.0;
     if (mixed) {
-        const PairPlan& pl = p.plan32;
 #define HOBI_PAIR32(T, K0)                                                                                    \
     hipLaunchKernelGGL((pair_f32_kernel<T, K0>), dim3(pl.blocks), dim3(kBlock), 0, s, p.tgt32, p.nv, p.nv_pad, \
-                       p.node32, p.node_vid, p.blk_range, pl.gstart, pl.slots, pl.workers, p.partial)
+                       p.node32, p.node_vid, p.blk_range, pl.gstart, pl.slots, pl.workers, partial)
         if (pl.tpl == 8) {
             if (k0) HOBI_PAIR32(8, true); else HOBI_PAIR32(8, false);
         } else {
@@ -232,21 +246,66 @@ hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s) {
         }
 #undef HOBI_PAIR32
     } else {
-        const PairPlan& pl = p.plan64;
 #define HOBI_PAIR64(K0)                                                                                          \
     hipLaunchKernelGGL((pair_f64_kernel<kTpl64, K0>), dim3(pl.blocks), dim3(kBlock), 0, s, p.tgt64, p.nv, p.nv_pad, \
-                       p.node64, p.node_vid, p.blk_range, p.kappa, p.eps, pl.gstart, pl.slots, pl.workers, p.partial)
+                       p.node64, p.node_vid, p.blk_range, p.kappa, p.eps, pl.gstart, pl.slots, pl.workers, partial)
         if (k0) HOBI_PAIR64(true); else HOBI_PAIR64(false);
 #undef HOBI_PAIR64
     }
     return hipGetLastError();
 }
 
-hipError_t launch_combine(const DeviceProblem& p, const double* u, double* y, bool mixed, hipStream_t s) {
-    const PairPlan& pl = mixed ? p.plan32 : p.plan64;
+hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s) {
+    return launch_pair_plan(p, mixed ? p.plan32 : p.plan64, p.partial, mixed, s);
+}
+
+hipError_t launch_combine_plan(const DeviceProblem& p, const PairPlan& pl, const double* partial,
+                               const double* u, double* y, hipStream_t s) {
     hipLaunchKernelGGL(combine_kernel, dim3(nblk(p.nv, kCombineVerts)), dim3(kPairBlock), 0, s, u, y, p.nv,
-                       p.partial, pl.slot, pl.slots, pl.groups, p.inc_off, p.inc_ent, p.tri, p.coef, p.eps);
+                       partial, pl.slot, pl.slots, pl.groups, p.inc_off, p.inc_ent, p.tri, p.coef, p.eps);
     return hipGetLastError();
+}
+
+hipError_t launch_combine(const DeviceProblem& p, const double* u, double* y, bool mixed, hipStream_t s) {
+    return launch_combine_plan(p, mixed ? p.plan32 : p.plan64, p.partial, u, y, s);
+}
+
+// ---- static work space of the allocation-free matvec ----
+
+bool make_static_pair_plan(const PairPlan& base, int nn, PairPlan* out, size_t* row_bytes) {
+    PairPlan pl = base;
+    const size_t per_group = (size_t)base.slots * 2 * base.slot * sizeof(double);
+    *row_bytes = per_group;
+    const size_t fit = (kStaticScratchBytes - kStaticTableBytes) / per_group;
+    const size_t table_max = kStaticTableBytes / sizeof(int) - 1;
+    if (fit < 1 || nn < 1) return false;
+    pl.groups = (int)std::min<size_t>({(size_t)base.groups, fit, table_max, (size_t)nn});
+    pl.workers = pl.groups * pl.slots;
+    pl.blocks = (pl.workers + kWavesPerBlock - 1) / kWavesPerBlock;
+    pl.gstart = nullptr;
+    *out = pl;
+    return true;
+}
+
+hipError_t launch_group_starts(int* tab, int groups, int nn, hipStream_t s) {
+    hipLaunchKernelGGL(group_starts_kernel, dim3(nblk(groups + 1, 256)), dim3(256), 0, s, tab, groups, nn);
+    return hipGetLastError();
+}
+
+hipError_t static_scratch_address(int device, void** out) {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_reaction_energy(const DeviceProblem& p, double* phi_reac, double* e_out, hipStream_t s) {

@@ -79,6 +79,7 @@ _SIGS = {
     "hobi_problem_set_dielectric": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "hobi_solve": (ctypes.c_int, [_P, _D, _D, _D, ctypes.POINTER(hobi_stats)]),
     "hobi_matvec": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "hobi_matvec_noalloc": (ctypes.c_int, [_P, _P, _P]),
     "hobi_energy": (ctypes.c_int, [_P, _P, ctypes.c_int32, _D]),
     "hobi_field": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _D, _D, _D, _D, _D, _I]),
     "hobi_get_nodes": (ctypes.c_int, [_P, _D, _D, _D]),
@@ -244,6 +245,16 @@ class Problem:
         y = np.empty_like(u)
         self._chk(lib().hobi_matvec(self.handle, _P(u.ctypes.data), _P(y.ctypes.data), 0))
         return y
+
+    def matvec_noalloc(self, u, out):
+        """y = A u from device tensors into ``out`` through the allocation-free entry point
+        (partial sums in the library's static work space; dense sum only)."""
+        if not (hasattr(u, "data_ptr") and hasattr(out, "data_ptr")):
+            raise ValueError("hobi_matvec_noalloc takes device tensors")
+        if u.numel() != 2 * self.nu or out.numel() != 2 * self.nu:
+            raise ValueError("u and out must have 2 entries per site")
+        self._chk(lib().hobi_matvec_noalloc(self.handle, _P(u.data_ptr()), _P(out.data_ptr())))
+        return out
 
     def energy(self, u) -> float:
         e = ctypes.c_double()
