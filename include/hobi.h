@@ -40,8 +40,8 @@ typedef enum hobi_status {
     HOBI_OK = 0,
     HOBI_E_ARG = 1,             /* bad argument (null pointer, size, parameter range)      */
     HOBI_E_MESH = 2,            /* not a closed oriented 2-manifold, degenerate triangle,   */
-                                /* normals disagreeing with the orientation on more than  */
-                                /* 1 % of the triangles, or a normal along an edge        */
+                                /* a triangle whose orientation disagrees with the sum of */
+                                /* its vertex normals, or a normal along an edge          */
     HOBI_E_CHARGE_OUTSIDE = 3,  /* a charge is not enclosed by the surface                  */
     HOBI_E_NOCONV = 4,          /* GMRES hit max_iter; outputs hold the last iterate        */
     HOBI_E_OOM = 5,             /* device allocation failed / over the serving budget      */

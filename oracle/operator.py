@@ -48,9 +48,9 @@ def validate_mesh(xyz, nrm, tri):
     """Closed, consistently oriented 2-manifold with unit normals; returns normals.
 
     Every directed edge must occur exactly once and its reverse exactly once; every
-    triangle must be non-degenerate; triangles must be counter-clockwise with respect to
-    the sum of their vertex normals, except on at most 1 % of them (a coarse mesh across a
-    sharp crease); normals must be unit to 1e-6 (they are then renormalised).
+    triangle must be non-degenerate; every triangle must be counter-clockwise with respect
+    to the sum of its vertex normals (the outward normals of the surface statement, Section
+    2.2); normals must be unit to 1e-6 (they are then renormalised).
     """
     xyz = np.asarray(xyz, dtype=np.float64)
     nrm = np.asarray(nrm, dtype=np.float64)
@@ -91,8 +91,8 @@ def validate_mesh(xyz, nrm, tri):
         raise MeshError("degenerate triangle")
     ns = nrm[tri[:, 0]] + nrm[tri[:, 1]] + nrm[tri[:, 2]]
     disagree = int(np.count_nonzero(np.einsum("ij,ij->i", cr, ns) <= 0.0))
-    if disagree > 0.01 * tri.shape[0]:
-        raise MeshError("triangle orientation disagrees with vertex normals")
+    if disagree > 0:
+        raise MeshError(f"orientation of {disagree} triangles disagrees with their vertex normals")
     return nrm
 
 

@@ -655,7 +655,7 @@ hobi_status validate_params(hobi_ctx ctx, const hobi_params& p) {
 }
 
 // Closed, consistently oriented 2-manifold, non-degenerate triangles, unit normals, and
-// triangles counter-clockwise w.r.t. their vertex normals except on at most 1 % of them.
+// every triangle counter-clockwise w.r.t. the sum of its vertex normals.
 hobi_status validate_mesh(hobi_ctx ctx, int nv, const double* xyz, std::vector<double>& nrm, int nf,
                           const int32_t* tri) {
     for (int i = 0; i < nv; ++i) {
@@ -692,9 +692,9 @@ hobi_status validate_mesh(hobi_ctx ctx, int nv, const double* xyz, std::vector<d
         if (!(area2 > 1e-12 * std::max(l1, l2))) return fail(ctx, HOBI_E_MESH, "triangle %d is degenerate", t);
         if (!(cr[0] * ns[0] + cr[1] * ns[1] + cr[2] * ns[2] > 0.0)) ++disagree;
     }
-    // a coarse mesh across a sharp crease may tilt a few triangles against their vertex
-    // normals; a misoriented surface or inverted normals tilts most of them
-    if (disagree > 0.01 * nf)
+    // every triangle, counter-clockwise seen from outside, must agree with the outward
+    // normals at its vertices (the curved element is built from them)
+    if (disagree > 0)
         return fail(ctx, HOBI_E_MESH, "%lld of %d triangles disagree with their vertex normals",
                     (long long)disagree, nf);
     for (int i = 0; i < nv; ++i)

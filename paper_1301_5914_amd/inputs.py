@@ -681,6 +681,58 @@ def crease_normals(verts, tri, nrm, cos_min: float = 0.3, passes: int = 3):
     return nrm
 
 
+def orientation_flips(verts, tri, nrm, passes: int = 4):
+    """Flips an edge of each triangle still oriented against the sum of its vertex normals
+    (a fold in a pinch of the density narrower than the grid, where neighbouring normals
+    point apart), choosing among its three edges the flip whose two new triangles both
+    agree with their vertex normals, with the larger of the smaller agreement; a flip that
+    would duplicate an edge is skipped.  Surfaces without such triangles are unchanged."""
+    tri = np.array(tri, dtype=np.int64)
+
+    def agree(a, b, c):
+        n = np.cross(verts[b] - verts[a], verts[c] - verts[a])
+        return float(np.dot(n, nrm[a] + nrm[b] + nrm[c]) / max(np.linalg.norm(n), 1e-300))
+
+    for _ in range(passes):
+        A, B, C = verts[tri[:, 0]], verts[tri[:, 1]], verts[tri[:, 2]]
+        bad = np.nonzero(np.einsum("ij,ij->i", np.cross(B - A, C - A), nrm[tri].sum(axis=1)) <= 0.0)[0]
+        if bad.size == 0:
+            break
+        edge_of = {}
+        for t, (a, b, c) in enumerate(tri):
+            edge_of[(a, b)] = t
+            edge_of[(b, c)] = t
+            edge_of[(c, a)] = t
+        for t1 in bad:
+            if agree(*tri[t1]) > 0.0:      # fixed by an earlier flip of this pass
+                continue
+            best = None
+            for k in range(3):
+                a, b, c = tri[t1][k], tri[t1][(k + 1) % 3], tri[t1][(k + 2) % 3]
+                t2 = edge_of.get((b, a))
+                if t2 is None:
+                    continue
+                d = [w for w in tri[t2] if w != a and w != b][0]
+                if c == d or (c, d) in edge_of or (d, c) in edge_of:
+                    continue
+                new = min(agree(a, d, c), agree(d, b, c))
+                if new > 0.0 and (best is None or new > best[0]):
+                    best = (new, a, b, c, d, t2)
+            if best is None:
+                continue
+            _, a, b, c, d, t2 = best
+            for e in ((a, b), (b, c), (c, a), (b, a), (a, d), (d, b)):
+                edge_of.pop(e, None)
+            tri[t1] = (a, d, c)
+            tri[t2] = (d, b, c)
+            for t in (t1, t2):
+                x, y, z = tri[t]
+                edge_of[(x, y)] = t
+                edge_of[(y, z)] = t
+                edge_of[(z, x)] = t
+    return tri
+
+
 def molecule_surface(centers, radii, grid: float = 0.5, pad: float = 3.0, decay=DENSITY_DECAY,
                      refine_steps: int = 30, collapse: float = 0.25, smooth: int = 2, flips: bool = True,
                      folds: bool = True, cavities: bool = False):
@@ -692,7 +744,8 @@ def molecule_surface(centers, radii, grid: float = 0.5, pad: float = 3.0, decay=
     back onto the surface; ``smooth`` rounds of tangential smoothing and Delaunay flips
     then remove the thin triangles left over, and ``folds`` removes triangles folded across
     creases; normals are -grad rho / |grad rho|, except at the vertices of folds that
-    remain (face-averaged there).  Buried cavities (closed components enclosing negative
+    remain (face-averaged there), and a last edge flip turns each triangle still against
+    the sum of its vertex normals.  Buried cavities (closed components enclosing negative
     volume) are filled unless ``cavities``."""
     ag = _AtomGrid(centers, radii, decay)
     lo = centers.min(axis=0) - radii.max() - pad
@@ -727,6 +780,7 @@ def molecule_surface(centers, radii, grid: float = 0.5, pad: float = 3.0, decay=
         tris = delaunay_flips(verts, tris, nrm)
     if folds:
         nrm = crease_normals(verts, np.asarray(tris), nrm)
+        tris = orientation_flips(verts, tris, nrm)
     return verts, nrm, tris.astype(np.int32)
 
 

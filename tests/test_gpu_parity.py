@@ -376,3 +376,35 @@ def test_large_molecule_sampled_rows_and_energy(ctx, large):
         del g
     r64, r32 = res[hobi.HOBI_FP64], res[hobi.HOBI_MIXED]
     assert abs(r32["energy"] / r64["energy"] - 1) <= 1e-5
+
+
+def test_library_and_oracle_reject_the_same_meshes(ctx):
+    """Mesh validation of hobi_problem_create against the oracle's on the same inputs: a
+    valid icosphere, two vertex normals turned inward (two triangles against their vertex
+    normals), one reversed triangle, an open surface, normals of length 2, all normals
+    inward; accepted or rejected alike, rejections with HOBI_E_MESH."""
+    xyz, nrm, tri = inputs.icosphere(2, 2.0)
+    a, b = int(tri[0, 0]), int(tri[0, 1])
+    fold = nrm.copy()
+    fold[[a, b]] *= -1.0
+    rev = tri.copy()
+    rev[5] = rev[5][::-1]
+    cases = {"valid": (xyz, nrm, tri), "fold": (xyz, fold, tri), "reversed": (xyz, nrm, rev),
+             "open": (xyz, nrm, tri[1:]), "long_normals": (xyz, 2.0 * nrm, tri), "inward": (xyz, -nrm, tri)}
+    qpos, q = np.zeros((1, 3)), np.ones(1)
+    for name, (x, n, t) in cases.items():
+        try:
+            O.validate_mesh(x, n, t)
+            oracle_ok = True
+        except O.MeshError:
+            oracle_ok = False
+        try:
+            hobi.Problem(ctx, x, n, t, qpos, q)
+            lib_ok = True
+        except hobi.HobiError as e:
+            assert e.name == "HOBI_E_MESH", (name, str(e))
+            lib_ok = False
+        print(f"mesh case {name}: oracle {'accepts' if oracle_ok else 'rejects'}, "
+              f"library {'accepts' if lib_ok else 'rejects'}", flush=True)
+        assert oracle_ok == lib_ok, name
+        assert oracle_ok == (name == "valid")

@@ -195,11 +195,27 @@ def test_offcenter_converges_to_the_kirkwood_series(offcenter_runs):
     assert errs_phi[2] < errs_phi[1] < errs_phi[0]
     assert errs_dphi[2] < errs_dphi[1] < errs_dphi[0]
     assert errs_E[2] < errs_E[1] < errs_E[0]
-    # second order in h (h halves per level) for the energy, better than 1.5 for phi, dphi
-    assert KW.order(2, 1, errs_E[1], errs_E[2]) > 1.8
-    assert KW.order(2, 1, errs_phi[1], errs_phi[2]) > 1.5
-    assert KW.order(2, 1, errs_dphi[1], errs_dphi[2]) > 1.5
+    # second order in h (h halves per level) for the energy, close to it for phi and dphi
+    # (measured L2 -> L3: 1.97, 1.72, 1.64; L3 -> L4: 2.00, 1.93, 1.84)
+    assert KW.order(2, 1, errs_E[1], errs_E[2]) > 1.9
+    assert KW.order(2, 1, errs_phi[1], errs_phi[2]) > 1.6
+    assert KW.order(2, 1, errs_dphi[1], errs_dphi[2]) > 1.6
     assert errs_phi[2] < 2e-3 and errs_E[2] < 5e-3
+
+
+def test_singular_rule_does_not_limit_the_centred_error():
+    """The centred charge's e_phi, about O(h) with the specified rules, is not the singular
+    rule's doing: 12 x 12 Duffy points instead of 4 x 4 change it by under 5% (the 4-point
+    rule on the non-incident neighbours of the target is what leaves it)."""
+    p = inputs.kirkwood_centered(3)
+    _, phi, _ = KW.centered_closed_form(1.0, 2.0, 1.0, 80.0, 0.1257)
+    errs = []
+    for ngl in (4, 12):
+        st = O.setup(p.xyz, p.nrm, p.tri, ngl=ngl)
+        r = _solve(p, rtol=1e-10, st=st, workers=8)
+        errs.append(KW.rel_max_error(r["phi"], SCALE * phi))
+    assert 1e-5 < errs[0] < 3e-5
+    assert abs(errs[1] / errs[0] - 1) < 0.05
 
 
 def test_consistency_residual_of_the_exact_solution(offcenter_runs):
@@ -285,3 +301,19 @@ def test_validation_rejects_bad_meshes_and_charges():
     st = O.setup(xyz, nrm, tri)
     with pytest.raises(O.ChargeOutsideError):
         O.check_charges_inside(st, np.array([[0.0, 0.0, 2.5]]))
+
+
+def test_validation_rejects_a_single_fold():
+    """Two neighbouring vertex normals turned inward turn exactly the two triangles that
+    share their edge against their vertex normals (0.6 % of the level-2 icosphere): the
+    mesh is rejected (every triangle must agree with the outward normals)."""
+    xyz, nrm, tri = inputs.icosphere(2, 2.0)
+    a, b = int(tri[0, 0]), int(tri[0, 1])
+    bad = nrm.copy()
+    bad[[a, b]] *= -1.0
+    A, B, C = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
+    agree = np.einsum("ij,ij->i", np.cross(B - A, C - A), bad[tri].sum(axis=1)) > 0.0
+    assert np.count_nonzero(~agree) == 2
+    with pytest.raises(O.MeshError, match="orientation"):
+        O.validate_mesh(xyz, bad, tri)
+    O.validate_mesh(xyz, nrm, tri)
