@@ -73,7 +73,8 @@ typedef struct hobi_server_s* hobi_server;
 typedef struct hobi_params {
     double eps1;        /* solute dielectric (> 0), default 1                               */
     double eps2;        /* solvent dielectric (> 0), default 80                             */
-    double kappa;       /* inverse Debye length in 1/A (>= 0), default 0.1257               */
+    double kappa;       /* inverse Debye length in 1/A (>= 0), default 0.1257; kappa times  */
+                        /* the surface's bounding-box diagonal must stay below 2.5e6       */
     double rtol;        /* GMRES stop: ||b - A u|| / ||b|| <= rtol (estimated), default 1e-6*/
     int32_t max_iter;   /* total matvecs allowed, default 200                               */
     int32_t restart;    /* GMRES(m) restart length, default 200                             */
@@ -245,6 +246,15 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
                        const double* points, double* phi, double* field, double* reac,
                        double* reac_field, int32_t* inside);
 
+/* ---- the FP64 pair sums' own arithmetic, for checking it against a reference -------
+ * y[i] = f(x[i]) on the context's device, with the routines the FP64 pair kernel uses:
+ *   HOBI_MATH_EXP_NEG: exp(-x), 0 <= x < 5e6 (Tang's table-driven method, 256 table values);
+ *   HOBI_MATH_RSQRT:   1 / sqrt(x), x > 0 (hardware estimate and one third-order step).
+ * x, y: [n] host arrays, n >= 0.  Synchronous.
+ * Errors: HOBI_E_ARG (unknown fn, NULL array, an argument outside the domain), HOBI_E_HIP. */
+enum { HOBI_MATH_EXP_NEG = 0, HOBI_MATH_RSQRT = 1 };
+hobi_status hobi_device_math(hobi_ctx ctx, int32_t fn, int32_t n, const double* x, double* y);
+
 /* ---- inspection of the setup (for verification), caller's vertex/triangle order ---
  * y, ny: [nf][4][3] regular quadrature nodes and unit normals; w: [nf][4] weight times
  * Jacobian (Section 2.2); lower-order method: [nf][3], [nf][3], [nf] (centroid, face
@@ -262,14 +272,16 @@ hobi_status hobi_get_stats(hobi_problem pb, hobi_stats* st);
  * of max_iter + 1 vectors) fits in hbm_budget_bytes next to the admitted ones; the
  * preparation thread then builds the request's problem (host checks and ordering, device
  * setup) while the worker's ticks run, and the worker advances every built request one
- * GMRES iteration per scheduler tick, all together: each tick does one batched gather,
- * one batched pair-sum and
- * one batched combine launch for every request (captured once in a HIP graph when
- * use_graph is 1), then each request's Gram-Schmidt and Givens update.  A request with
+ * GMRES iteration per scheduler tick, all together: each tick does one batched diagonal
+ * scaling, gather, pair-sum and combine launch for every request, then one batched launch
+ * per Gram-Schmidt, normalisation and Givens phase for every request (two launch sequences,
+ * each captured once in a HIP graph when use_graph is 1).  A request with
  * tree_theta > 0 runs its own treecode matvec launches in the tick instead (the sequence of
- * hobi_matvec); it is admitted on its dense footprint and charged its treecode buffers,
- * which depend on the partition, once its problem is built, so bytes_in_use may then
- * exceed the budget until it leaves.  Requests
+ * hobi_matvec); it is admitted on its dense footprint, and its treecode buffers, which
+ * depend on the partition, are charged when its problem is built with the budget's rest as
+ * their limit: if they do not fit, the request returns to the head of the queue charged
+ * their size and waits until they do, so bytes_in_use never exceeds the budget (a request
+ * that cannot fit even alone fails with HOBI_E_OOM).  Requests
  * arriving during a tick join at the next one; finished requests leave at the end of the
  * tick that finished them.  A request's arithmetic depends only on that request (its
  * split over waves is fixed by its own size and the device), so its results are

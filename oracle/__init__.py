@@ -25,7 +25,7 @@ Modules, in the order of the method:
 * ``solve``       -- the whole pipeline of the parallel pseudocode table, run serially.
 * ``lobi``        -- the lower-order scheme: flat triangles, centroid collocation and
   one-point quadrature (Section 2.4, eqdbef1/eqdbef2).
-* ``treecode``    -- a single-level cluster-particle treecode for the regular sum
+* ``treecode``    -- a cluster-particle treecode over a binary cluster tree for the regular sum
   (polynomial interpolation of the Green's functions in the source point), the
   reference of the GPU's optional fast matvec.
 * ``field``       -- potential and field at points off the surface from the

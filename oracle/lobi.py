@@ -14,8 +14,9 @@ Readings (the subsection is brief):
 * W_j is the area of flat triangle j; the unknowns and the kernels are taken constant on it;
 * the normal at centroid c_j is the flat triangle's unit normal (its orientation is the
   stored, counter-clockwise-from-outside vertex order);
-* "the contribution of a triangle is removed when the kernel is singular": only the
-  self term j = i, where the collocation point and the quadrature point coincide;
+* the subsection drops a triangle's contribution where the kernel is singular; read as the
+  self term j = i only, where the collocation point and the quadrature point coincide
+  (Section 2.4);
 * the source terms are those of the higher-order scheme, evaluated at the centroids with
   the face normals; the energy uses the same one-point rule at the charges.
 """

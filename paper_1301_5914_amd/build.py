@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhobi.so")
 
-SOURCES = ["hobi_api.cpp", "serve.cpp", "setup_kernels.hip", "pair_kernels.hip", "gmres_kernels.hip",
+SOURCES = ["hobi_api.cpp", "host_logic.cpp", "trace.cpp", "serve.cpp", "setup_kernels.hip", "pair_kernels.hip", "gmres_kernels.hip",
            "serve_kernels.hip", "field_kernels.hip", "tree_kernels.hip"]
 
 HIPCC_FLAGS = [
@@ -47,7 +47,7 @@ def build(verbose: bool = False, extra_flags=()) -> str:
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-ldl", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -3,42 +3,31 @@
 // Gram-Schmidt with one re-orthogonalisation pass, and the small Hessenberg work
 // (Givens rotations, back substitution) in single-lane kernels.
 #include "hobi_internal.h"
+#include "krylov_tile.h"
 
 namespace hobi {
 
 namespace {
 
-constexpr int kT = 256;
+constexpr int kT = kKrylovBlock;
+static_assert(kDotSlices == kDotBlocks, "one dot-product split");
 
-// partial[j * kDotBlocks + b] = sum over block b's slice of V[j] . w
+// partial[j * kDotBlocks + b] = slice b of V[j] . w
 __global__ __launch_bounds__(kT) void dots_kernel(const double* __restrict__ V, size_t ld,
                                                  const double* __restrict__ w, int n,
                                                  double* __restrict__ partial) {
     __shared__ double red[kT];
     const int j = blockIdx.y;
-    const double* v = V + ld * j;
-    double acc = 0.0;
-    for (int i = blockIdx.x * kT + threadIdx.x; i < n; i += kT * kDotBlocks) acc += v[i] * w[i];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = kT / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(size_t)j * kDotBlocks + blockIdx.x] = red[0];
+    const double d = dot_slice(V + ld * j, w, n, blockIdx.x, red);
+    if (threadIdx.x == 0) partial[(size_t)j * kDotBlocks + blockIdx.x] = d;
 }
 
 __global__ __launch_bounds__(kDotBlocks) void reduce_kernel(const double* __restrict__ partial,
                                                            double* __restrict__ out, int sqrt_out) {
     __shared__ double red[kDotBlocks];
     const int j = blockIdx.x;
-    red[threadIdx.x] = partial[(size_t)j * kDotBlocks + threadIdx.x];
-    __syncthreads();
-    for (int off = kDotBlocks / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[j] = sqrt_out ? sqrt(red[0]) : red[0];
+    const double d = sum_slices(partial + (size_t)j * kDotBlocks, red, sqrt_out != 0);
+    if (threadIdx.x == 0) out[j] = d;
 }
 
 // w[i] += sign * sum_j coef[j] V[j][i]
@@ -47,16 +36,14 @@ __global__ void multi_axpy_kernel(const double* __restrict__ V, size_t ld, int n
                                   int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double acc = 0.0;
-    for (int j = 0; j < nvec; ++j) acc += coef[j] * V[ld * j + i];
-    w[i] += sign * acc;
+    multi_axpy_elem(V, ld, nvec, coef, sign, w, i);
 }
 
 __global__ void diag_scale_kernel(const double* __restrict__ in, double* __restrict__ out, int nv, double s1,
                                   double s2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 2 * nv) return;
-    out[i] = (i < nv ? s1 : s2) * in[i];
+    diag_scale_elem(in, out, nv, s1, s2, i);
 }
 
 // x[i] += s(i) * sum_j coef[j] V[j][i]
@@ -66,16 +53,15 @@ __global__ void multi_axpy_scaled_kernel(const double* __restrict__ V, size_t ld
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 2 * nv) return;
     double acc = 0.0;
-    for (int j = 0; j < nvec; ++j) acc += coef[j] * V[ld * j + i];
-    x[i] += (i < nv ? s1 : s2) * acc;
+    for (int j = 0; j < nvec; ++j) acc = fma(coef[j], V[ld * j + i], acc);
+    x[i] = fma(i < nv ? s1 : s2, acc, x[i]);
 }
 
 __global__ void scale_copy_kernel(const double* __restrict__ in, const double* __restrict__ denom,
                                   double* __restrict__ out, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double d = denom[0];
-    out[i] = d != 0.0 ? in[i] / d : 0.0;
+    scale_copy_elem(in, denom[0], out, i);
 }
 
 __global__ void sub_kernel(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out,
@@ -84,37 +70,13 @@ __global__ void sub_kernel(const double* __restrict__ a, const double* __restric
     if (i < n) out[i] = a[i] - b[i];
 }
 
-// Column k of the Hessenberg matrix (column-major, leading dimension ldh = m + 1):
-// H[0..k][k] = h1 + h2 (two Gram-Schmidt passes), H[k+1][k] = hnext.  Applies the k
-// previous rotations, forms rotation k, updates g and writes |g[k+1]| / bnorm.
+// Column k of the Hessenberg matrix and rotation k (givens_step), one thread.
 __global__ void givens_kernel(double* __restrict__ H, int ldh, int k, const double* __restrict__ h1,
                               const double* __restrict__ h2, const double* __restrict__ hnext,
                               double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
                               double bnorm, double* __restrict__ res) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double* col = H + (size_t)k * ldh;
-    for (int i = 0; i <= k; ++i) col[i] = h1[i] + h2[i];
-    col[k + 1] = hnext[0];
-    for (int i = 0; i < k; ++i) {
-        const double a = col[i], b = col[i + 1];
-        col[i] = cs[i] * a + sn[i] * b;
-        col[i + 1] = -sn[i] * a + cs[i] * b;
-    }
-    const double a = col[k], b = col[k + 1];
-    const double den = hypot(a, b);
-    double c = 1.0, s = 0.0;
-    if (den > 0.0) {
-        c = a / den;
-        s = b / den;
-    }
-    cs[k] = c;
-    sn[k] = s;
-    col[k] = den;
-    col[k + 1] = 0.0;
-    const double gk = g[k];
-    g[k + 1] = -s * gk;
-    g[k] = c * gk;
-    res[0] = fabs(g[k + 1]) / bnorm;
+    givens_step(H, ldh, k, h1, h2, hnext, cs, sn, g, bnorm, res);
 }
 
 __global__ void init_g_kernel(const double* __restrict__ beta, double* __restrict__ g, int m) {

@@ -17,6 +17,7 @@
 
 #include "hobi.h"
 #include "hobi_host.h"
+#include "trace.h"
 #include "hobi_internal.h"
 
 using namespace hobi;
@@ -69,66 +70,6 @@ hipError_t grow_pinned(T** p, size_t* cap, size_t n) {
     const hipError_t e = hipHostMalloc((void**)p, m * sizeof(T));
     if (e == hipSuccess) *cap = m;
     return e;
-}
-
-uint64_t spread3(uint64_t v) {   // 21 bits -> every third bit
-    v &= 0x1fffff;
-    v = (v | v << 32) & 0x1f00000000ffffULL;
-    v = (v | v << 16) & 0x1f0000ff0000ffULL;
-    v = (v | v << 8) & 0x100f00f00f00f00fULL;
-    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
-    v = (v | v << 2) & 0x1249249249249249ULL;
-    return v;
-}
-
-// Indices 0..n-1 ordered by key, ties in index order: a least-significant-digit radix sort
-// (each pass a stable counting sort on one digit; 16-bit digits for large inputs, 8-bit
-// for small ones, passes whose digit is the same for every key skipped).
-std::vector<int> stable_key_order(const std::vector<uint64_t>& key_in) {
-    const size_t n = key_in.size();
-    const int bits = n >= 65536 ? 16 : 8;
-    const size_t radix = (size_t)1 << bits;
-    const int passes = 64 / bits;
-    std::vector<uint64_t> k(key_in), k2(n);
-    std::vector<int> ord(n), o2(n);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::vector<uint32_t> hist((size_t)passes * radix, 0);
-    for (size_t i = 0; i < n; ++i)
-        for (int p = 0; p < passes; ++p) hist[p * radix + ((k[i] >> (bits * p)) & (radix - 1))]++;
-    for (int p = 0; p < passes; ++p) {
-        uint32_t* h = &hist[p * radix];
-        if (*std::max_element(h, h + radix) == n) continue;
-        uint32_t sum = 0;
-        for (size_t d = 0; d < radix; ++d) {
-            const uint32_t c = h[d];
-            h[d] = sum;
-            sum += c;
-        }
-        const int shift = bits * p;
-        for (size_t i = 0; i < n; ++i) {
-            const uint32_t at = h[(k[i] >> shift) & (radix - 1)]++;
-            k2[at] = k[i];
-            o2[at] = ord[i];
-        }
-        k.swap(k2);
-        ord.swap(o2);
-    }
-    return ord;
-}
-
-std::vector<int> morton_order(const std::vector<double>& pts, int n, const double lo[3], const double hi[3]) {
-    std::vector<uint64_t> code(n);
-    for (int i = 0; i < n; ++i) {
-        uint64_t c = 0;
-        for (int d = 0; d < 3; ++d) {
-            const double ext = hi[d] - lo[d] > 0 ? hi[d] - lo[d] : 1.0;
-            double f = (pts[3 * i + d] - lo[d]) / ext;
-            f = std::min(std::max(f, 0.0), 1.0);
-            c |= spread3((uint64_t)(f * 2097151.0)) << d;
-        }
-        code[i] = c;
-    }
-    return stable_key_order(code);
 }
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
@@ -262,6 +203,7 @@ hobi_status norm2(hobi_problem pb, const double* v, int n, double* dev_out) {
 // of A x = rhs).  Classical Gram-Schmidt
 // with a second pass, Givens rotations, stop when the estimate |g_{k+1}| / ||b|| <= rtol.
 hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
+    TraceRange trace_range("gmres");
     const int n = 2 * pb->d.nv;
     const int m = std::max(1, std::min(pb->prm.restart, pb->prm.max_iter));
     hobi_status st = ensure_krylov(pb, n, m);
@@ -452,7 +394,19 @@ hobi_status run_device_setup(hobi_problem pb, float* ms_out) {
 // misses the batch's targets, else a leaf is near and a parent is opened (left child
 // first).  Work items: for every target slot of each precision, its batch's far and near
 // clusters in walk order.
-hobi_status build_tree_plan(hobi_problem pb) {
+// Device bytes of a treecode plan's buffers (the allocations below).
+int64_t tree_plan_bytes(const TreeHostPlan& hp, int nprox, int nv) {
+    int64_t b = (int64_t)hp.nclu * (2 * (int64_t)sizeof(int2) + 6 * (int64_t)sizeof(double)) +
+                (int64_t)hp.nclu * nprox * (int64_t)(sizeof(ProxyD) + sizeof(ProxyF));
+    for (int m = 0; m < 2; ++m)
+        b += (int64_t)hp.nitems[m] * (int64_t)sizeof(int4) + 4LL * ((nv + hp.slot[m] - 1) / hp.slot[m] + 1);
+    return b + 8 * (int64_t)hp.partial_elems;
+}
+
+// The treecode partition and its device buffers.  Fails with HOBI_E_OOM, and the buffers'
+// size in *need, when they would take more than `limit` bytes.
+hobi_status build_tree_plan(hobi_problem pb, int64_t limit, int64_t* need) {
+    TraceRange trace_range("treecode plan");
     DeviceProblem& d = pb->d;
     TreePlan& t = d.tree;
     const hobi_params& prm = pb->prm;
@@ -471,153 +425,59 @@ hobi_status build_tree_plan(hobi_problem pb) {
     t.nprox = (t.degree + 1) * (t.degree + 1) * (t.degree + 1);
     t.leaf = prm.tree_leaf;
     t.batch = prm.tree_batch;
-    t.nleaf = (nn + t.leaf - 1) / t.leaf;
-    t.nbatch = (nv + t.batch - 1) / t.batch;
-    // clusters: node range, box (lo, hi, ungrown), vertex-id range, children
-    struct Clu {
-        int a, b, vlo, vhi, c0, c1;
-        double lo[3], hi[3];
-    };
-    std::vector<Clu> cl(t.nleaf);
-    for (int c = 0; c < t.nleaf; ++c) {
-        Clu& k = cl[c];
-        k.a = c * t.leaf;
-        k.b = std::min(k.a + t.leaf, nn);
-        k.c0 = k.c1 = -1;
-        for (int q = 0; q < 3; ++q) k.lo[q] = 1e300, k.hi[q] = -1e300;
-        for (int j = k.a; j < k.b; ++j) {
-            const double pj[3] = {nodes[j].x, nodes[j].y, nodes[j].z};
-            for (int q = 0; q < 3; ++q) k.lo[q] = std::min(k.lo[q], pj[q]), k.hi[q] = std::max(k.hi[q], pj[q]);
-        }
-        if (d.method == HOBI_LOWER_ORDER) {
-            k.vlo = k.a, k.vhi = k.b - 1;   // node j is site j, left out of its own row only
-        } else {
-            k.vlo = nv, k.vhi = -1;
-            for (int f = k.a / 4; f < (k.b + 3) / 4; ++f)
-                for (int q = 0; q < 3; ++q)
-                    k.vlo = std::min(k.vlo, tri[3 * f + q]), k.vhi = std::max(k.vhi, tri[3 * f + q]);
-        }
+    std::vector<double> nxyz(3 * (size_t)nn);
+    for (int j = 0; j < nn; ++j) nxyz[3 * (size_t)j] = nodes[j].x, nxyz[3 * (size_t)j + 1] = nodes[j].y,
+                                 nxyz[3 * (size_t)j + 2] = nodes[j].z;
+    TreeHostPlan hp;
+    std::string msg;
+    if (!plan_tree(nn, nxyz.data(), nv, tg.data(), (size_t)d.nv_pad, nf, tri.data(),
+                   d.method == HOBI_LOWER_ORDER ? 1 : 0, prm.tree_theta, t.leaf, t.batch, kTpl64, &hp, &msg))
+        return fail(ctx, HOBI_E_ARG, "%s", msg.c_str());
+    const int64_t bytes = tree_plan_bytes(hp, t.nprox, nv);
+    if (bytes > limit) {
+        if (need) *need = bytes;
+        return fail(ctx, HOBI_E_OOM, "treecode buffers (%lld bytes) exceed the %lld bytes allowed", (long long)bytes,
+                    (long long)limit);
     }
-    std::vector<int> level(t.nleaf);
-    std::iota(level.begin(), level.end(), 0);
-    t.nlev = 0;
-    while (level.size() > 1) {
-        if (t.nlev >= kTreeMaxLevels) return fail(ctx, HOBI_E_ARG, "cluster tree too deep");
-        t.lev_off[t.nlev] = (int)cl.size();
-        std::vector<int> up;
-        for (size_t i = 0; i < level.size(); i += 2) {
-            if (i + 1 == level.size()) {
-                up.push_back(level[i]);
-                continue;
-            }
-            const Clu &l = cl[level[i]], &r = cl[level[i + 1]];
-            Clu k;
-            k.a = l.a, k.b = r.b, k.c0 = level[i], k.c1 = level[i + 1];
-            k.vlo = std::min(l.vlo, r.vlo), k.vhi = std::max(l.vhi, r.vhi);
-            for (int q = 0; q < 3; ++q) k.lo[q] = std::min(l.lo[q], r.lo[q]), k.hi[q] = std::max(l.hi[q], r.hi[q]);
-            cl.push_back(k);
-            up.push_back((int)cl.size() - 1);
-        }
-        level.swap(up);
-        ++t.nlev;
-    }
-    t.lev_off[t.nlev] = (int)cl.size();
-    const int root = level[0];
-    t.root = root;
-    t.nclu = (int)cl.size();
-    // centre of the box [lo, hi] into c; returns its diagonal
-    auto box_centre = [](const double lo[3], const double hi[3], double c[3]) {
-        double q = 0;
-        for (int k = 0; k < 3; ++k) {
-            c[k] = 0.5 * (lo[k] + hi[k]);
-            q += (hi[k] - lo[k]) * (hi[k] - lo[k]);
-        }
-        return std::sqrt(q);
-    };
-    std::vector<int2> crange(t.nclu), cchild(t.nclu);
-    std::vector<double> cbox(6 * (size_t)t.nclu), ccen(3 * (size_t)t.nclu), crad(t.nclu);
-    for (int c = 0; c < t.nclu; ++c) {
-        const Clu& k = cl[c];
-        const double diag = box_centre(k.lo, k.hi, &ccen[3 * (size_t)c]);
-        crad[c] = 0.5 * diag;
-        const double g = kTreeGrow * diag + 1e-12;
-        for (int q = 0; q < 3; ++q) cbox[6 * (size_t)c + q] = k.lo[q] - g, cbox[6 * (size_t)c + 3 + q] = k.hi[q] + g;
-        crange[c] = make_int2(k.a, k.b);
-        cchild[c] = make_int2(k.c0, k.c1);
-    }
-    t.h_cen = ccen;
-    t.h_rad = crad;
-    t.h_child = cchild;
-    // the walk of every batch: far (1) and near (0) clusters
-    std::vector<std::vector<std::pair<int, int>>> walk(t.nbatch);
-    t.nfar = t.nnear = 0;
-    std::vector<int> stack;
-    for (int bi = 0; bi < t.nbatch; ++bi) {
-        const int a = bi * t.batch, b = std::min(a + t.batch, nv);
-        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-        for (int i = a; i < b; ++i)
-            for (int q = 0; q < 3; ++q) {
-                const double v = tg[(size_t)q * d.nv_pad + i];
-                lo[q] = std::min(lo[q], v), hi[q] = std::max(hi[q], v);
-            }
-        double cb[3];
-        const double rb = 0.5 * box_centre(lo, hi, cb);
-        stack.assign(1, root);
-        while (!stack.empty()) {
-            const int c = stack.back();
-            stack.pop_back();
-            const bool touches = cl[c].vhi >= a && cl[c].vlo <= b - 1;
-            const double* cc = &ccen[3 * (size_t)c];
-            const double dx = cb[0] - cc[0], dy = cb[1] - cc[1], dz = cb[2] - cc[2];
-            if (!touches && rb + crad[c] <= prm.tree_theta * std::sqrt(dx * dx + dy * dy + dz * dz)) {
-                walk[bi].emplace_back(c, 1);
-                ++t.nfar;
-            } else if (cl[c].c0 < 0) {
-                walk[bi].emplace_back(c, 0);
-                ++t.nnear;
-            } else {
-                stack.push_back(cl[c].c1);
-                stack.push_back(cl[c].c0);
-            }
-        }
-    }
-    std::vector<int4> items[2];
-    std::vector<int> srow[2];
-    size_t partial_elems = 0;
+    t.nleaf = hp.nleaf;
+    t.nbatch = hp.nbatch;
+    t.nlev = hp.nlev;
+    std::copy(hp.lev_off, hp.lev_off + kTreeMaxLevels + 1, t.lev_off);
+    t.root = hp.root;
+    t.nclu = hp.nclu;
+    t.nfar = hp.nfar;
+    t.nnear = hp.nnear;
+    t.h_cen = hp.ccen;
+    t.h_rad = hp.crad;
+    t.h_child.resize(t.nclu);
+    for (int c = 0; c < t.nclu; ++c) t.h_child[c] = make_int2(hp.cchild[2 * (size_t)c], hp.cchild[2 * (size_t)c + 1]);
     for (int m = 0; m < 2; ++m) {
-        t.tpl[m] = m ? t.batch / 64 : kTpl64;
-        t.slot[m] = 64 * t.tpl[m];
-        const int slots = (nv + t.slot[m] - 1) / t.slot[m];
-        srow[m].assign(1, 0);
-        for (int sl = 0; sl < slots; ++sl) {
-            const int bi = sl * t.slot[m] / t.batch;
-            for (const auto& w : walk[bi]) items[m].push_back(make_int4(sl, w.second, w.first, 0));
-            if (items[m].size() > ((size_t)1 << 30))
-                return fail(ctx, HOBI_E_ARG, "treecode plan too large: raise tree_leaf or tree_theta");
-            srow[m].push_back((int)items[m].size());
-        }
-        t.nitems[m] = (int)items[m].size();
-        const size_t elems = (size_t)t.nitems[m] * 2 * t.slot[m];
-        if (elems > ((size_t)1 << 31))
-            return fail(ctx, HOBI_E_ARG, "treecode plan too large (%d work items): raise tree_leaf or tree_theta",
-                        t.nitems[m]);
-        partial_elems = std::max(partial_elems, elems);
+        t.tpl[m] = hp.tpl[m];
+        t.slot[m] = hp.slot[m];
+        t.nitems[m] = hp.nitems[m];
     }
+    static_assert(sizeof(int2) == 2 * sizeof(int) && sizeof(int4) == 4 * sizeof(int), "packed index records");
+    const std::vector<int>* items = hp.items;
+    const std::vector<int>* srow = hp.slot_row;
+    const size_t partial_elems = hp.partial_elems;
+    const std::vector<int>& crange = hp.crange;
+    const std::vector<int>& cchild = hp.cchild;
+    const std::vector<double>& cbox = hp.cbox;
     HIPCHK(ctx, dalloc(&t.clu_range, t.nclu));
     HIPCHK(ctx, dalloc(&t.clu_child, t.nclu));
     HIPCHK(ctx, dalloc(&t.clu_box, 6 * (size_t)t.nclu));
     HIPCHK(ctx, dalloc(&t.prox64, (size_t)t.nclu * t.nprox));
     HIPCHK(ctx, dalloc(&t.prox32, (size_t)t.nclu * t.nprox));
     for (int m = 0; m < 2; ++m) {
-        HIPCHK(ctx, dalloc(&t.items[m], items[m].size()));
+        HIPCHK(ctx, dalloc(&t.items[m], items[m].size() / 4));
         HIPCHK(ctx, dalloc(&t.slot_row[m], srow[m].size()));
     }
     HIPCHK(ctx, dalloc(&t.partial, partial_elems));
-    HIPCHK(ctx, hipMemcpyAsync(t.clu_range, crange.data(), sizeof(int2) * crange.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(ctx, hipMemcpyAsync(t.clu_child, cchild.data(), sizeof(int2) * cchild.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(t.clu_range, crange.data(), sizeof(int) * crange.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(t.clu_child, cchild.data(), sizeof(int) * cchild.size(), hipMemcpyHostToDevice, s));
     HIPCHK(ctx, hipMemcpyAsync(t.clu_box, cbox.data(), sizeof(double) * cbox.size(), hipMemcpyHostToDevice, s));
     for (int m = 0; m < 2; ++m) {
-        HIPCHK(ctx, hipMemcpyAsync(t.items[m], items[m].data(), sizeof(int4) * items[m].size(),
+        HIPCHK(ctx, hipMemcpyAsync(t.items[m], items[m].data(), sizeof(int) * items[m].size(),
                                    hipMemcpyHostToDevice, s));
         HIPCHK(ctx, hipMemcpyAsync(t.slot_row[m], srow[m].data(), sizeof(int) * srow[m].size(),
                                    hipMemcpyHostToDevice, s));
@@ -654,61 +514,11 @@ hobi_status validate_params(hobi_ctx ctx, const hobi_params& p) {
     return HOBI_OK;
 }
 
-// Closed, consistently oriented 2-manifold, non-degenerate triangles, unit normals, and
-// every triangle counter-clockwise w.r.t. the sum of its vertex normals.
+// Mesh validation (check_mesh of host_logic.cpp) with its message on the context.
 hobi_status validate_mesh(hobi_ctx ctx, int nv, const double* xyz, std::vector<double>& nrm, int nf,
                           const int32_t* tri) {
-    for (int i = 0; i < nv; ++i) {
-        double* n = &nrm[3 * i];
-        const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        if (std::fabs(l - 1.0) > 1e-6) return fail(ctx, HOBI_E_MESH, "normal %d is not unit length", i);
-        n[0] /= l, n[1] /= l, n[2] /= l;
-    }
-    std::vector<uint64_t> keys;
-    keys.reserve(3 * (size_t)nf);
-    std::vector<char> used(nv, 0);
-    int64_t disagree = 0;
-    for (int t = 0; t < nf; ++t) {
-        const int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
-        if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv)
-            return fail(ctx, HOBI_E_MESH, "triangle %d: vertex id out of range", t);
-        if (a == b || b == c || a == c) return fail(ctx, HOBI_E_MESH, "triangle %d repeats a vertex", t);
-        used[a] = used[b] = used[c] = 1;
-        keys.push_back((uint64_t)a * nv + b);
-        keys.push_back((uint64_t)b * nv + c);
-        keys.push_back((uint64_t)c * nv + a);
-        double e1[3], e2[3], cr[3], ns[3];
-        for (int d = 0; d < 3; ++d) {
-            e1[d] = xyz[3 * b + d] - xyz[3 * a + d];
-            e2[d] = xyz[3 * c + d] - xyz[3 * a + d];
-            ns[d] = nrm[3 * a + d] + nrm[3 * b + d] + nrm[3 * c + d];
-        }
-        cr[0] = e1[1] * e2[2] - e1[2] * e2[1];
-        cr[1] = e1[2] * e2[0] - e1[0] * e2[2];
-        cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
-        const double area2 = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
-        const double l1 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
-        const double l2 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
-        if (!(area2 > 1e-12 * std::max(l1, l2))) return fail(ctx, HOBI_E_MESH, "triangle %d is degenerate", t);
-        if (!(cr[0] * ns[0] + cr[1] * ns[1] + cr[2] * ns[2] > 0.0)) ++disagree;
-    }
-    // every triangle, counter-clockwise seen from outside, must agree with the outward
-    // normals at its vertices (the curved element is built from them)
-    if (disagree > 0)
-        return fail(ctx, HOBI_E_MESH, "%lld of %d triangles disagree with their vertex normals",
-                    (long long)disagree, nf);
-    for (int i = 0; i < nv; ++i)
-        if (!used[i]) return fail(ctx, HOBI_E_MESH, "vertex %d is not used by any triangle", i);
-    std::vector<uint64_t> sorted(keys);
-    std::sort(sorted.begin(), sorted.end());
-    for (size_t i = 1; i < sorted.size(); ++i)
-        if (sorted[i] == sorted[i - 1])
-            return fail(ctx, HOBI_E_MESH, "directed edge used twice (non-manifold or misoriented)");
-    for (uint64_t k : sorted) {
-        const uint64_t a = k / nv, b = k % nv;
-        if (!std::binary_search(sorted.begin(), sorted.end(), b * nv + a))
-            return fail(ctx, HOBI_E_MESH, "open edge (%d, %d)", (int)a, (int)b);
-    }
+    std::string msg;
+    if (!check_mesh(nv, xyz, nrm, nf, tri, &msg)) return fail(ctx, HOBI_E_MESH, "%s", msg.c_str());
     return HOBI_OK;
 }
 
@@ -792,6 +602,20 @@ void* hobi_ctx_stream(hobi_ctx ctx) { return ctx ? (void*)ctx->stream : nullptr;
 hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, const double* nrm_in,
                                 int32_t nf, const int32_t* tri_in, int32_t nc, const double* qpos,
                                 const double* q, const hobi_params* params, hobi_problem* out) {
+    return hobi::problem_create_limited(ctx, nv, xyz, nrm_in, nf, tri_in, nc, qpos, q, params, out, INT64_MAX,
+                                        nullptr);
+}
+
+}  // extern "C"
+
+namespace hobi {
+
+hobi_status problem_create_limited(hobi_ctx ctx, int32_t nv, const double* xyz, const double* nrm_in, int32_t nf,
+                                   const int32_t* tri_in, int32_t nc, const double* qpos, const double* q,
+                                   const hobi_params* params, hobi_problem* out, int64_t tree_limit,
+                                   int64_t* tree_need) {
+    TraceRange trace_range("hobi_problem_create");
+    if (tree_need) *tree_need = 0;
     if (!ctx) return HOBI_E_ARG;
     if (!out) return fail(ctx, HOBI_E_ARG, "out is NULL");
     *out = nullptr;
@@ -817,6 +641,10 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
             lo[d] = std::min(lo[d], xyz[3 * i + d]);
             hi[d] = std::max(hi[d], xyz[3 * i + d]);
         }
+    const double extent = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                    (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    if (!(prm.kappa * 2.0 * extent < kExpTabMaxZ))
+        return fail(ctx, HOBI_E_ARG, "kappa times the surface's extent must stay below %g", kExpTabMaxZ / 2);
     std::vector<double> xv(xyz, xyz + 3 * (size_t)nv);
     std::vector<int> vperm = morton_order(xv, nv, lo, hi);
     std::vector<int> vinv(nv);
@@ -863,6 +691,7 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
     d.kappa = prm.kappa;
     d.eps = prm.eps2 / prm.eps1;
     for (int k = 0; k < 3; ++k) d.center[k] = 0.5 * (lo[k] + hi[k]);
+    d.extent = extent;
     d.nv_pad = round_up(d.nv, 2048);
     d.nc_pad = round_up(nc, 256);
     d.plan_pts = make_grid_plan(d.nc_pad, d.nn, 1);
@@ -973,7 +802,7 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
     PCHK(hipStreamSynchronize(s));
     float ms = 0.f;
     if ((st = run_device_setup(pb, &ms)) != HOBI_OK) return cleanup_fail(st);
-    if ((st = build_tree_plan(pb)) != HOBI_OK) return cleanup_fail(st);
+    if ((st = build_tree_plan(pb, tree_limit, tree_need)) != HOBI_OK) return cleanup_fail(st);
     std::vector<int> herr(nf);
     PCHK(hipMemcpyAsync(herr.data(), pb->d_err, sizeof(int) * nf, hipMemcpyDeviceToHost, s));
     PCHK(hipStreamSynchronize(s));
@@ -1000,6 +829,10 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz, con
     return HOBI_OK;
 }
 
+}  // namespace hobi
+
+extern "C" {
+
 void hobi_problem_destroy(hobi_problem pb) {
     if (!pb) return;
     if (pb->ctx && pb->ctx->stream) (void)hipStreamSynchronize(pb->ctx->stream);
@@ -1016,6 +849,7 @@ hobi_status hobi_problem_set_precision(hobi_problem pb, int32_t precision) {
 }
 
 hobi_status hobi_problem_set_dielectric(hobi_problem pb, double eps1, double eps2, double kappa) {
+    TraceRange trace_range("hobi_problem_set_dielectric");
     if (!pb) return HOBI_E_ARG;
     hobi_params p = pb->prm;
     p.eps1 = eps1;
@@ -1023,6 +857,8 @@ hobi_status hobi_problem_set_dielectric(hobi_problem pb, double eps1, double eps
     p.kappa = kappa;
     hobi_status st = validate_params(pb->ctx, p);
     if (st != HOBI_OK) return st;
+    if (!(kappa * 2.0 * pb->d.extent < kExpTabMaxZ))
+        return fail(pb->ctx, HOBI_E_ARG, "kappa times the surface's extent must stay below %g", kExpTabMaxZ / 2);
     HIPCHK(pb->ctx, hipSetDevice(pb->ctx->device));
     pb->prm = p;
     DeviceProblem& d = pb->d;
@@ -1049,6 +885,7 @@ hobi_status hobi_problem_set_solver(hobi_problem pb, double rtol, int32_t max_it
 }
 
 hobi_status hobi_matvec(hobi_problem pb, const double* u, double* y, int32_t on_device) {
+    TraceRange trace_range("hobi_matvec");
     if (!pb) return HOBI_E_ARG;
     if (!u || !y) return fail(pb->ctx, HOBI_E_ARG, "NULL vector");
     HIPCHK(pb->ctx, hipSetDevice(pb->ctx->device));
@@ -1085,7 +922,30 @@ hobi_status hobi_matvec_noalloc(hobi_problem pb, const double* u, double* y) {
     return HOBI_OK;
 }
 
+hobi_status hobi_device_math(hobi_ctx ctx, int32_t fn, int32_t n, const double* x, double* y) {
+    if (!ctx) return HOBI_E_ARG;
+    if (fn != HOBI_MATH_EXP_NEG && fn != HOBI_MATH_RSQRT) return fail(ctx, HOBI_E_ARG, "unknown function %d", fn);
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(ctx, HOBI_E_ARG, "need n >= 0 and non-NULL arrays");
+    if (n == 0) return HOBI_OK;
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(x[i]) || (fn == HOBI_MATH_EXP_NEG ? !(x[i] >= 0.0 && x[i] < kExpTabMaxZ) : !(x[i] > 0.0)))
+            return fail(ctx, HOBI_E_ARG, "argument %d out of the function's domain", i);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    double* d = nullptr;
+    HIPCHK(ctx, hipMallocAsync((void**)&d, sizeof(double) * 2 * (size_t)n, s));
+    hipError_t e = hipMemcpyAsync(d, x, sizeof(double) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_device_math(fn, d, d + n, n, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(y, d + n, sizeof(double) * n, hipMemcpyDeviceToHost, s);
+    const hipError_t f = hipFreeAsync(d, s);
+    if (e == hipSuccess) e = f;
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(ctx, HOBI_E_HIP, "device math: %s", hipGetErrorString(e));
+    return HOBI_OK;
+}
+
 hobi_status hobi_energy(hobi_problem pb, const double* u, int32_t on_device, double* e_sol) {
+    TraceRange trace_range("hobi_energy");
     if (!pb) return HOBI_E_ARG;
     if (!u || !e_sol) return fail(pb->ctx, HOBI_E_ARG, "NULL argument");
     HIPCHK(pb->ctx, hipSetDevice(pb->ctx->device));
@@ -1099,6 +959,7 @@ hobi_status hobi_energy(hobi_problem pb, const double* u, int32_t on_device, dou
 
 hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int32_t np, const double* points,
                        double* phi, double* field, double* reac, double* reac_field, int32_t* inside) {
+    TraceRange trace_range("hobi_field");
     if (!pb) return HOBI_E_ARG;
     hobi_ctx c = pb->ctx;
     if (!u) return fail(c, HOBI_E_ARG, "NULL u");
@@ -1268,6 +1129,7 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
 }
 
 hobi_status hobi_solve(hobi_problem pb, double* phi, double* dphi, double* e_sol, hobi_stats* stats) {
+    TraceRange trace_range("hobi_solve");
     if (!pb) return HOBI_E_ARG;
     hobi_ctx c = pb->ctx;
     HIPCHK(c, hipSetDevice(c->device));

@@ -35,6 +35,9 @@ constexpr int kCombineVerts = 64;   // vertices per tile of the combine step
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kInv4Pi = 1.0 / (4.0 * kPi);
+// Largest kappa r the FP64 pair kernels' exponential takes (its table index stays an int);
+// a problem's kappa times twice its bounding-box diagonal must stay below it.
+constexpr double kExpTabMaxZ = 5.0e6;
 
 struct Vec3 {
     double x, y, z;

@@ -64,4 +64,11 @@ namespace hobi {
 hobi_status host_from_internal(hobi_problem pb, const double* src, int on_device, double* y);
 // records a message on the context and returns code
 hobi_status host_fail(hobi_ctx ctx, hobi_status code, const char* msg);
+// hobi_problem_create whose treecode buffers may take at most tree_limit bytes: beyond it
+// the call fails with HOBI_E_OOM and *tree_need (nullable) holds their size (0 on any other
+// outcome).
+hobi_status problem_create_limited(hobi_ctx ctx, int32_t nv, const double* xyz, const double* nrm, int32_t nf,
+                                   const int32_t* tri, int32_t nc, const double* qpos, const double* q,
+                                   const hobi_params* params, hobi_problem* out, int64_t tree_limit,
+                                   int64_t* tree_need);
 }  // namespace hobi

@@ -10,6 +10,7 @@
 
 #include "hobi.h"
 #include "hobi_device.h"
+#include "host_logic.h"
 
 namespace hobi {
 
@@ -49,9 +50,6 @@ struct PairPlan {
 // Treecode form of the regular sum (hobi_params.tree_theta > 0; higher-order method).  The
 // partition is geometric and built once at problem creation; the proxy charges depend on u
 // and are rebuilt by every matvec.
-constexpr int kTreeMaxDeg = 7;       // (n + 1)^3 <= 512 proxies per cluster
-constexpr int kTreeMaxLevels = 40;
-constexpr double kTreeGrow = 1e-6;   // proxy box = node box grown by this fraction of its diagonal (+ 1e-12 A)
 struct TreePlan {
     int on = 0;
     int degree = 0, nprox = 0;       // n, (n + 1)^3
@@ -85,6 +83,7 @@ struct DeviceProblem {
     double* vxyz = nullptr;                 // [nverts][3] vertex positions (lower-order method only)
     double eps1 = 1, eps2 = 80, kappa = 0, eps = 80;
     double center[3] = {0, 0, 0};          // shift applied to the FP32 copies
+    double extent = 0;                      // diagonal of the vertices' bounding box
     double s32 = 1;                         // scale of the FP32 positions: kappa log2(e) (1 if kappa = 0)
     // inputs in internal (spatially sorted) order
     double* xyz = nullptr;                  // [nv][3] site positions
@@ -164,6 +163,8 @@ hipError_t launch_group_starts(int* tab, int groups, int nn, hipStream_t s);
 // reaction potential at the charges (nodes must hold Gamma/Phi of u) and the energy
 hipError_t launch_reaction_energy(const DeviceProblem& p, double* phi_reac, double* e_out,
                                   hipStream_t s);
+// y[i] = the FP64 pair kernel's exp(-x[i]) (fn 0) or 1 / sqrt(x[i]) (fn 1), device arrays
+hipError_t launch_device_math(int fn, const double* x, double* y, int n, hipStream_t s);
 // solid-angle fraction seen from each charge (1 inside, 0 outside)
 hipError_t launch_solid_angle(const DeviceProblem& p, double* frac, hipStream_t s);
 

@@ -62,11 +62,13 @@ __device__ __forceinline__ int xcd_logical_block() {
 template <int TPL, bool KAPPA0>
 __global__ __launch_bounds__(kBlock) void pair_f64_kernel(
     const double* __restrict__ tgt, int nv, int nv_pad, const NodeD* __restrict__ nodes,
-    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa, double eps,
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa,
     const int* __restrict__ gstart, int slots, int workers, double* __restrict__ partial) {
+    __shared__ double etab[kExpTab];
+    if constexpr (!KAPPA0) fill_exp_table(etab);
     const int w = xcd_logical_block() * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     if (w >= workers) return;
-    pair_f64_worker<TPL, KAPPA0>(tgt, nv, nv_pad, nodes, node_vid, blk_range, kappa, eps, gstart, slots, partial, w);
+    pair_f64_worker<TPL, KAPPA0>(tgt, nv, nv_pad, nodes, node_vid, blk_range, kappa, etab, gstart, slots, partial, w);
 }
 
 template <int TPL, bool KAPPA0>
@@ -172,6 +174,17 @@ __global__ void group_starts_kernel(int* __restrict__ tab, int groups, int nn) {
     if (g <= groups) tab[g] = (int)((int64_t)g * nn / groups);
 }
 
+// The FP64 pair kernel's arithmetic on given arguments: fn 0 = exp(-x) (table-driven,
+// x >= 0), fn 1 = 1 / sqrt(x) (x > 0).
+__global__ __launch_bounds__(kBlock) void device_math_kernel(int fn, const double* __restrict__ x,
+                                                             double* __restrict__ y, int n) {
+    __shared__ double etab[kExpTab];
+    fill_exp_table(etab);
+    const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+    if (i >= n) return;
+    y[i] = fn == 0 ? exp_neg_tab_f64(x[i], etab) : rsqrt_f64(x[i]);
+}
+
 inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
@@ -248,7 +261,7 @@ hipError_t launch_pair_plan(const DeviceProblem& p, const PairPlan& pl, double* 
     } else {
 #define HOBI_PAIR64(K0)                                                                                          \
     hipLaunchKernelGGL((pair_f64_kernel<kTpl64, K0>), dim3(pl.blocks), dim3(kBlock), 0, s, p.tgt64, p.nv, p.nv_pad, \
-                       p.node64, p.node_vid, p.blk_range, p.kappa, p.eps, pl.gstart, pl.slots, pl.workers, partial)
+                       p.node64, p.node_vid, p.blk_range, p.kappa, pl.gstart, pl.slots, pl.workers, partial)
         if (k0) HOBI_PAIR64(true); else HOBI_PAIR64(false);
 #undef HOBI_PAIR64
     }
@@ -330,6 +343,11 @@ hipError_t launch_solid_angle(const DeviceProblem& p, double* frac, hipStream_t 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((point_reduce_kernel<1>), dim3(p.nc), dim3(256), 0, s, p.partial, p.nc_pad, pl.chunks,
                        frac);
+    return hipGetLastError();
+}
+
+hipError_t launch_device_math(int fn, const double* x, double* y, int n, hipStream_t s) {
+    hipLaunchKernelGGL(device_math_kernel, dim3(nblk(n, kBlock)), dim3(kBlock), 0, s, fn, x, y, n);
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 // same whichever launch computes them.
 #pragma once
 
+#include "exp2_table.h"
 #include "hobi_device.h"
 
 namespace hobi {
@@ -306,18 +307,55 @@ __device__ __forceinline__ void f012_pair_f64(double z, double& f0, double& f1, 
     }
 }
 
-// FP64 pairs of nodes [sb, se) with the lane's TPL targets.  Per pair (kappa > 0) about 62
-// VALU operations: the exponential and reciprocal square root of hobi_device.h, the closed
-// forms of f0, f1, f2, and their power series where kappa r < kSeriesZ64 (rare: only nodes
-// near the wave's targets); the rows as in the FP32 tile, with the strengths pre-multiplied
-// by the epsilon factors.  With MASK, pairs of a vertex with its own triangles' nodes are
-// skipped.
+// exp(-z) for 0 <= z < kExpTabMaxZ in FP64 by Tang's table-driven method (P. T. P. Tang, ACM
+// TOMS 15, 1989): n = rint(256 z log2(e)) = 256 k + j (0 <= j < 256), r = z - n ln2/256 with
+// |r| <= ln2/512 (Cody-Waite: ln2/256 split into a 32-bit head, so n * head is exact, and a
+// tail), and exp(-z) = 2^-k * 2^(-j/256) * exp(-r).  n comes from adding 1.5 * 2^52 to
+// 256 z log2(e) in one fused multiply-add: the sum's rounding is the rounding to an integer,
+// its low 32 bits are n, and subtracting the constant again gives n exactly.  The 256
+// values 2^(-j/256), each the nearest double (exp2_table.h), sit in LDS (fill_exp_table, once
+// per workgroup); exp(-r) - 1 is its Taylor polynomial to degree 4 (truncation below 4e-17),
+// added as T + T (exp(-r) - 1) by one fused multiply-add.  Measured against an
+// extended-precision reference: within 1.3 units in the last place.  Past z = 745 the result
+// underflows to 0; the problem checks (kappa times its extent) keep z below kExpTabMaxZ,
+// where n fits an int.
+constexpr int kExpTab = 256;
+
+// Must be called by every thread of the workgroup (it synchronises them).
+__device__ __forceinline__ void fill_exp_table(double* __restrict__ tab) {
+    for (int j = (int)threadIdx.x; j < kExpTab; j += (int)blockDim.x) tab[j] = kExp2NegTab256[j];
+    __syncthreads();
+}
+
+__device__ __forceinline__ double exp_neg_tab_f64(double z, const double* __restrict__ tab) {
+    constexpr double kC = kExpTab * 1.44269504088896340735992468100189214;   // 256 log2(e)
+    constexpr double kShift = 0x1.8p52;                                        // 1.5 * 2^52
+    const double y = fma(z, kC, kShift);
+    const double n = y - kShift;
+    const int ni = (int)(unsigned)__builtin_bit_cast(unsigned long long, y);
+    double r = fma(-n, kLn2Step256Hi, z);
+    r = fma(-n, kLn2Step256Lo, r);
+    double p = fma(r, 1.0 / 24.0, -1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, -1.0);
+    const double q = p * r;                       // exp(-r) - 1
+    const double t = tab[ni & (kExpTab - 1)];
+    return __builtin_amdgcn_ldexp(fma(t, q, t), -(ni >> 8));
+}
+
+// FP64 pairs of nodes [sb, se) with the lane's TPL targets.  Per pair (kappa > 0) about 50
+// FP64 operations: the reciprocal square root of hobi_device.h, the table-driven exponential
+// above (etab: its LDS table), and the closed forms of f1, f2 and 1 - e, whose cancellation
+// for small z = kappa r costs an absolute error of a few units of 1e-16, the size of the
+// rows' other rounding errors; the rows as in the FP32 tile, with the strengths
+// pre-multiplied by the epsilon factors.  With MASK, pairs of a vertex with its own
+// triangles' nodes are skipped.
 template <int TPL, bool KAPPA0, bool MASK>
 __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, const const_as<int4>* cvid, int sb,
                                              int se, int base, const double (&tx)[TPL], const double (&ty)[TPL],
                                              const double (&tz)[TPL], const double (&tnx)[TPL],
                                              const double (&tny)[TPL], const double (&tnz)[TPL], double kappa,
-                                             double eps, double (&a1)[TPL], double (&a2)[TPL]) {
+                                             const double* __restrict__ etab, double (&a1)[TPL], double (&a2)[TPL]) {
     for (int s = sb; s < se; ++s) {
         const NodeD nd = load_node(cnodes, s);   // (a prefetched FP64 record would not fit the scalar registers)
         uint64_t vmask[TPL];
@@ -338,11 +376,13 @@ __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, cons
             } else {
                 const double pnxy = fma(tnx[k], nd.qx, fma(tny[k], nd.qy, tnz[k] * nd.qz));
                 const double z = kappa * (r2 * rinv);
-                double f0, f1, f2;
-                f012_pair_f64(z, f0, f1, f2);
+                const double e = exp_neg_tab_f64(z, etab);
+                const double zp1 = z + 1.0;
+                const double f1 = fma(-e, zp1, 1.0);                          // 1 - e (1 + z)
+                const double f2 = fma(-e, fma(zp1, zp1 + 1.0, 1.0), 3.0);     // 3 - e (3 + 3z + z^2)
                 // the FP32 tile's row algebra: q = (d.ny)/r^2, P = Phi ny
                 const double q = dny * rinv2;
-                a1[k] = fma(rinv, fma(q, fma(nd.pb, f1, nd.pa), nd.g * f0), a1[k]);
+                a1[k] = fma(rinv, fma(q, fma(nd.pb, f1, nd.pa), fma(-e, nd.g, nd.g)), a1[k]);
                 const double t = fma(nd.p, q * f2, fma(nd.gb, f1, nd.ga));
                 a2[k] = fma(rinv2 * rinv, fma(-pnxy, f1, dnx * t), a2[k]);
             }
@@ -355,8 +395,8 @@ __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, cons
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void pair_f64_wave(
     const double* __restrict__ tgt, int nv_pad, const NodeD* __restrict__ nodes,
-    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa, double eps,
-    int base, int n0, int n1, double* __restrict__ prow, int slot) {
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa,
+    const double* __restrict__ etab, int base, int n0, int n1, double* __restrict__ prow, int slot) {
     const int lane = (int)(threadIdx.x % kWave);
     const int t0 = base + lane;
     double tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL], a1[TPL], a2[TPL];
@@ -380,10 +420,10 @@ __device__ __forceinline__ void pair_f64_wave(
         const int vlo = crange[sb / kFold].x, vhi = crange[sb / kFold].y;
         const bool near = (vhi >= base) & (vlo < base + kWave * TPL);
         if (near)
-            pair_f64_run<TPL, KAPPA0, true>(cnodes, cvid, sb, se, base, tx, ty, tz, tnx, tny, tnz, kappa, eps, a1,
+            pair_f64_run<TPL, KAPPA0, true>(cnodes, cvid, sb, se, base, tx, ty, tz, tnx, tny, tnz, kappa, etab, a1,
                                             a2);
         else
-            pair_f64_run<TPL, KAPPA0, false>(cnodes, cvid, sb, se, base, tx, ty, tz, tnx, tny, tnz, kappa, eps, a1,
+            pair_f64_run<TPL, KAPPA0, false>(cnodes, cvid, sb, se, base, tx, ty, tz, tnx, tny, tnz, kappa, etab, a1,
                                              a2);
     }
 #pragma unroll
@@ -396,28 +436,30 @@ __device__ __forceinline__ void pair_f64_wave(
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void pair_f64_narrow(
     int live, const double* __restrict__ tgt, int nv_pad, const NodeD* __restrict__ nodes,
-    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa, double eps,
-    int base, int n0, int n1, double* __restrict__ prow, int slot) {
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa,
+    const double* __restrict__ etab, int base, int n0, int n1, double* __restrict__ prow, int slot) {
     if constexpr (TPL > 1) {
         if (live <= kWave * TPL / 2) {
-            pair_f64_narrow<TPL / 2, KAPPA0>(live, tgt, nv_pad, nodes, node_vid, blk_range, kappa, eps, base, n0, n1,
+            pair_f64_narrow<TPL / 2, KAPPA0>(live, tgt, nv_pad, nodes, node_vid, blk_range, kappa, etab, base, n0, n1,
                                               prow, slot);
             return;
         }
     }
-    pair_f64_wave<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, kappa, eps, base, n0, n1, prow, slot);
+    pair_f64_wave<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, kappa, etab, base, n0, n1, prow, slot);
 }
 
+// etab: the workgroup's exponential table (fill_exp_table; not read when KAPPA0).
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void pair_f64_worker(
     const double* __restrict__ tgt, int nv, int nv_pad, const NodeD* __restrict__ nodes,
-    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa, double eps,
-    const int* __restrict__ gstart, int slots, double* __restrict__ partial, int w) {
+    const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa,
+    const double* __restrict__ etab, const int* __restrict__ gstart, int slots, double* __restrict__ partial,
+    int w) {
     constexpr int kSlot = kWave * TPL;
     const int g = w / slots, s = w - g * slots;
     const const_as<int>* cg = as_constant(gstart);
     const int base = s * kSlot;
-    pair_f64_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, nodes, node_vid, blk_range, kappa, eps, base, cg[g],
+    pair_f64_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, nodes, node_vid, blk_range, kappa, etab, base, cg[g],
                                  cg[g + 1], partial + (size_t)w * (2 * kSlot), kSlot);
 }
 

@@ -24,6 +24,7 @@
 #include "hobi_host.h"
 #include "hobi_internal.h"
 #include "serve_internal.h"
+#include "trace.h"
 
 using namespace hobi;
 using Clock = std::chrono::steady_clock;
@@ -37,7 +38,8 @@ struct Request {
     std::vector<double> xyz, nrm, qpos, q;
     std::vector<int32_t> tri;
     hobi_params prm{};
-    int64_t footprint = 0;
+    int64_t footprint = 0;  // bytes charged to the budget
+    int64_t tree_charged = 0;   // of which the treecode buffers, once measured
     // device state while active
     hobi_problem pb = nullptr;
     PairPlan plan{};        // the problem's own pair plan (its partial-sum buffer is reused)
@@ -92,8 +94,10 @@ int64_t footprint_bytes(int device, int nv, int nf, int nc, int m, int method) {
 }
 
 // Device bytes of a built problem's treecode buffers (0 without the treecode).  They depend
-// on the partition, so a request is admitted on its dense footprint and charged these bytes
-// once its problem is built.
+// on the partition, so a request is admitted on its dense footprint and its problem is built
+// with the rest of the budget as the limit for them; a request whose buffers do not fit
+// waits at the head of the queue, charged their size, until they do (alone in the server, it
+// fails with HOBI_E_OOM).
 int64_t tree_bytes(const DeviceProblem& d) {
     const TreePlan& t = d.tree;
     if (!t.on) return 0;
@@ -150,15 +154,19 @@ struct hobi_server_s {
     double batch_sum = 0;
     ServeDesc* d_desc = nullptr;
     ServeItem* d_items = nullptr;     // gather | pair | combine item arrays
-    int* d_counts = nullptr;
+    int* d_counts = nullptr;          // [4] matvec item counts, then [kKrylovPhases + 1] Krylov counts
     ServeDesc* h_desc = nullptr;      // pinned staging
     ServeItem* h_items = nullptr;
     int* h_counts = nullptr;
+    KrylovDesc* d_kdesc = nullptr;    // one Arnoldi step per active request
+    KrylovDesc* h_kdesc = nullptr;
     double* d_res = nullptr;          // one residual per active request
     double* h_res = nullptr;
     size_t cap_desc = 0, cap_items = 0;
-    hipGraph_t graph = nullptr;
+    hipGraph_t graph = nullptr;       // diagonal scaling and the batched matvec
     hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t kgraph = nullptr;      // the batched Gram-Schmidt and Givens phases
+    hipGraphExec_t kgraph_exec = nullptr;
     bool graph_dirty = true;
     std::thread worker;
 };
@@ -173,6 +181,7 @@ void fail_request(Request& r, hobi_status code, const std::string& msg) {
 // Allocates the Krylov state of a request whose problem the preparation thread created and
 // starts its GMRES (x0 = 0, v0 = b / |b|).
 hobi_status admit(hobi_server sv, Request& r) {
+    TraceRange trace_range("server admit");
     hobi_ctx c = sv->ctx;
     hipStream_t s = c->stream;
     r.t_admit = Clock::now();
@@ -222,6 +231,7 @@ hobi_status admit(hobi_server sv, Request& r) {
 
 // Forms x = V y, the energy and the caller-order outputs; frees the device state.
 void finish(hobi_server sv, Request& r, bool converged) {
+    TraceRange trace_range("server finish");
     hobi_ctx c = sv->ctx;
     hipStream_t s = c->stream;
     const int n = 2 * r.nu;
@@ -276,10 +286,14 @@ hipError_t ensure_capacity(hobi_server sv, size_t ndesc, size_t nitems) {
         size_t cap = std::max<size_t>(ndesc, 2 * sv->cap_desc);
         if (sv->d_desc) (void)hipFree(sv->d_desc);
         if (sv->h_desc) (void)hipHostFree(sv->h_desc);
+        if (sv->d_kdesc) (void)hipFree(sv->d_kdesc);
+        if (sv->h_kdesc) (void)hipHostFree(sv->h_kdesc);
         if (sv->d_res) (void)hipFree(sv->d_res);
         if (sv->h_res) (void)hipHostFree(sv->h_res);
         if ((e = hipMalloc((void**)&sv->d_desc, cap * sizeof(ServeDesc))) != hipSuccess) return e;
         if ((e = hipHostMalloc((void**)&sv->h_desc, cap * sizeof(ServeDesc))) != hipSuccess) return e;
+        if ((e = hipMalloc((void**)&sv->d_kdesc, cap * sizeof(KrylovDesc))) != hipSuccess) return e;
+        if ((e = hipHostMalloc((void**)&sv->h_kdesc, cap * sizeof(KrylovDesc))) != hipSuccess) return e;
         if ((e = hipMalloc((void**)&sv->d_res, (cap + 1) * sizeof(double))) != hipSuccess) return e;
         if ((e = hipHostMalloc((void**)&sv->h_res, (cap + 1) * sizeof(double))) != hipSuccess) return e;
         sv->cap_desc = cap;
@@ -297,8 +311,11 @@ hipError_t ensure_capacity(hobi_server sv, size_t ndesc, size_t nitems) {
     return e;
 }
 
-// One tick: every active request advances one Arnoldi step.
+// One tick: every active request advances one Arnoldi step: the batched diagonal scaling
+// and matvec (phase A), the treecode requests' own matvec launches, then the batched
+// Gram-Schmidt passes, normalisation and Givens updates (phase B).
 hobi_status tick(hobi_server sv) {
+    TraceRange trace_range("server tick");
     hipStream_t s = sv->ctx->stream;
     const size_t na = sv->active.size();
     // work lists: gather items, FP32 pair items, FP64 pair items, combine items
@@ -323,6 +340,7 @@ hobi_status tick(hobi_server sv) {
         dl[l] = sv->d_items + l * t4;
     }
     size_t fill[4] = {0, 0, 0, 0};
+    int kcnt[kKrylovPhases] = {0, 0, 0, 0, 0, 0};
     for (size_t q = 0; q < na; ++q) {
         Request& r = *sv->active[q];
         const DeviceProblem& d = r.pb->d;
@@ -330,12 +348,39 @@ hobi_status tick(hobi_server sv) {
         ServeDesc& sd = sv->h_desc[q];
         sd.u = r.V + (size_t)r.k * n;
         sd.y = r.V + (size_t)(r.k + 1) * n;
+        KrylovDesc& kd = sv->h_kdesc[q];
+        kd.vk = sd.u;
+        kd.z = r.prm.diag_scaling ? r.z : nullptr;
+        kd.V = r.V;
+        kd.w = sd.y;
+        kd.dpart = r.dpart;
+        kd.h1 = r.h1;
+        kd.h2 = r.h2;
+        kd.hn = r.hn;
+        kd.H = r.H;
+        kd.cs = r.cs;
+        kd.sn = r.sn;
+        kd.g = r.g;
+        kd.res = sv->d_res + q;
+        kd.s1 = kd.s2 = 1.0;
+        kd.bnorm = r.bnorm;
+        kd.n = n;
+        kd.nu = r.nu;
+        kd.k = r.k;
+        kd.ldh = r.m + 1;
+        {
+            // item counts of each phase (the implicit lists of serve_internal.h)
+            const int blocks = (n + kServeBlock - 1) / kServeBlock;
+            const int per[kKrylovPhases] = {r.prm.diag_scaling ? blocks : 0, kDotBlocks * (r.k + 1), r.k + 1, blocks,
+                                            kDotBlocks, 1};
+            for (int ph = 0; ph < kKrylovPhases; ++ph) {
+                kd.off[ph] = kcnt[ph];
+                kcnt[ph] += per[ph];
+            }
+        }
         if (r.prm.diag_scaling) {
-            // the matvec of the scaled system takes D^-1 v_k (the single-problem path's kernel)
-            double s1, s2;
-            gmres_scales(d.eps, &s1, &s2);
-            if ((e = launch_diag_scale(sd.u, r.z, r.nu, s1, s2, s)) != hipSuccess)
-                return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
+            // the matvec of the scaled system takes D^-1 v_k (the single-problem path's scaling)
+            gmres_scales(d.eps, &kd.s1, &kd.s2);
             sd.u = r.z;
         }
         sd.tri = d.tri;
@@ -374,35 +419,53 @@ hobi_status tick(hobi_server sv) {
             hl[3][fill[3]++] = ServeItem{(int)q, blk, 0, 0};
     }
     for (int l = 0; l < 4; ++l) sv->h_counts[l] = (int)cnt[l];
-    if ((e = hipMemcpyAsync(sv->d_desc, sv->h_desc, na * sizeof(ServeDesc), hipMemcpyHostToDevice, s)) != hipSuccess)
+    for (int ph = 0; ph < kKrylovPhases; ++ph) sv->h_counts[4 + ph] = kcnt[ph];
+    sv->h_counts[4 + kKrylovPhases] = (int)na;
+    const int* d_kcounts = sv->d_counts + 4;
+    if ((e = hipMemcpyAsync(sv->d_desc, sv->h_desc, na * sizeof(ServeDesc), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(sv->d_kdesc, sv->h_kdesc, na * sizeof(KrylovDesc), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
         return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
     for (int l = 0; l < 4; ++l)
         if (cnt[l] && (e = hipMemcpyAsync((void*)dl[l], hl[l], cnt[l] * sizeof(ServeItem), hipMemcpyHostToDevice,
                                           s)) != hipSuccess)
             return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
-    if ((e = hipMemcpyAsync(sv->d_counts, sv->h_counts, 4 * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess)
+    if ((e = hipMemcpyAsync(sv->d_counts, sv->h_counts, kServeCounts * sizeof(int), hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
         return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
-    if (sv->use_graph) {
-        if (sv->graph_dirty || !sv->graph_exec) {
-            if (sv->graph_exec) (void)hipGraphExecDestroy(sv->graph_exec);
-            if (sv->graph) (void)hipGraphDestroy(sv->graph);
-            sv->graph_exec = nullptr;
-            sv->graph = nullptr;
+    // phase A: diagonal scaling of v_k and the batched matvec; phase B: the Gram-Schmidt passes,
+    // normalisation and Givens updates of every request.  Each is one launch sequence over the
+    // device-side lists, captured once into a graph and replayed while the buffers keep their
+    // addresses (the host rewrites only the lists and counts).
+    auto phase_a = [&]() -> hipError_t {
+        hipError_t le = launch_batched_diag(sv->d_kdesc, d_kcounts, s);
+        if (le == hipSuccess) le = launch_batched_matvec(sv->d_desc, dl, sv->d_counts, s);
+        return le;
+    };
+    auto phase_b = [&]() -> hipError_t { return launch_batched_krylov(sv->d_kdesc, d_kcounts, s); };
+    if (sv->use_graph && (sv->graph_dirty || !sv->graph_exec || !sv->kgraph_exec)) {
+        if (sv->graph_exec) (void)hipGraphExecDestroy(sv->graph_exec);
+        if (sv->graph) (void)hipGraphDestroy(sv->graph);
+        if (sv->kgraph_exec) (void)hipGraphExecDestroy(sv->kgraph_exec);
+        if (sv->kgraph) (void)hipGraphDestroy(sv->kgraph);
+        sv->graph_exec = sv->kgraph_exec = nullptr;
+        sv->graph = sv->kgraph = nullptr;
+        for (int which = 0; which < 2; ++which) {
+            hipGraph_t* g = which == 0 ? &sv->graph : &sv->kgraph;
+            hipGraphExec_t* x = which == 0 ? &sv->graph_exec : &sv->kgraph_exec;
             if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                 return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
-            const hipError_t le = launch_batched_matvec(sv->d_desc, dl, sv->d_counts, s);
-            e = hipStreamEndCapture(s, &sv->graph);
+            const hipError_t le = which == 0 ? phase_a() : phase_b();
+            e = hipStreamEndCapture(s, g);
             if (le != hipSuccess || e != hipSuccess)
-                return host_fail(sv->ctx, HOBI_E_HIP, "graph capture of the batched matvec failed");
-            if ((e = hipGraphInstantiate(&sv->graph_exec, sv->graph, nullptr, nullptr, 0)) != hipSuccess)
+                return host_fail(sv->ctx, HOBI_E_HIP, "graph capture of the batched tick failed");
+            if ((e = hipGraphInstantiate(x, *g, nullptr, nullptr, 0)) != hipSuccess)
                 return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
-            sv->graph_dirty = false;
         }
-        if ((e = hipGraphLaunch(sv->graph_exec, s)) != hipSuccess)
-            return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
-    } else if ((e = launch_batched_matvec(sv->d_desc, dl, sv->d_counts, s)) != hipSuccess) {
-        return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
+        sv->graph_dirty = false;
     }
+    e = sv->use_graph ? hipGraphLaunch(sv->graph_exec, s) : phase_a();
+    if (e != hipSuccess) return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
     // treecode requests: the single-problem sequence (gather, proxy charges, items, combine)
     for (size_t q = 0; q < na; ++q) {
         Request& r = *sv->active[q];
@@ -415,25 +478,8 @@ hobi_status tick(hobi_server sv) {
             (e = launch_tree_combine(d, sd.u, sd.y, mixed, s)) != hipSuccess)
             return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
     }
-    // per-request Gram-Schmidt (two passes), normalisation and Givens update
-    for (size_t q = 0; q < na; ++q) {
-        Request& r = *sv->active[q];
-        const int n = 2 * r.nu, j = r.k;
-        double* w = r.V + (size_t)(j + 1) * n;
-        for (int pass = 0; pass < 2; ++pass) {
-            double* h = pass == 0 ? r.h1 : r.h2;
-            if ((e = launch_dots(r.V, n, j + 1, w, n, r.dpart, s)) != hipSuccess ||
-                (e = launch_reduce(r.dpart, j + 1, h, 0, s)) != hipSuccess ||
-                (e = launch_multi_axpy(r.V, n, j + 1, h, -1.0, w, n, s)) != hipSuccess)
-                return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
-        }
-        if ((e = launch_dots(w, 0, 1, w, n, r.dpart, s)) != hipSuccess ||
-            (e = launch_reduce(r.dpart, 1, r.hn, 1, s)) != hipSuccess ||
-            (e = launch_scale_copy(w, r.hn, w, n, s)) != hipSuccess ||
-            (e = launch_givens(r.H, r.m + 1, j, r.h1, r.h2, r.hn, r.cs, r.sn, r.g, r.bnorm, sv->d_res + q, s)) !=
-                hipSuccess)
-            return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
-    }
+    e = sv->use_graph ? hipGraphLaunch(sv->kgraph_exec, s) : phase_b();
+    if (e != hipSuccess) return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
     if ((e = hipMemcpyAsync(sv->h_res, sv->d_res, na * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return host_fail(sv->ctx, HOBI_E_HIP, hipGetErrorString(e));
@@ -531,6 +577,8 @@ void prep_main(hobi_server sv) {
     (void)hipSetDevice(sv->device);
     while (true) {
         std::unique_ptr<Request> r;
+        int64_t tree_limit = 0;
+        bool alone = false;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
             sv->prep_cv.wait(lk, [&] {
@@ -542,22 +590,40 @@ void prep_main(hobi_server sv) {
             if (sv->stop) break;
             r = std::move(sv->pending.front());
             sv->pending.pop_front();
+            alone = sv->in_use == 0;
             sv->in_use += r->footprint;
+            // what the budget leaves for the treecode buffers beyond the footprint charged
+            // so far (the dense footprint, or that and the buffers' size measured before)
+            tree_limit = sv->budget - sv->in_use + r->tree_charged;
             sv->preparing += 1;
             sv->st.pending = (int32_t)sv->pending.size();
             sv->st.bytes_in_use = sv->in_use;
             sv->st.peak_bytes = std::max(sv->st.peak_bytes, sv->in_use);
         }
-        const hobi_status st = hobi_problem_create(sv->prep_ctx, r->nv, r->xyz.data(), r->nrm.data(), r->nf,
-                                                   r->tri.data(), r->nc, r->qpos.data(), r->q.data(), &r->prm,
-                                                   &r->pb);
+        int64_t need = 0;
+        const hobi_status st = problem_create_limited(sv->prep_ctx, r->nv, r->xyz.data(), r->nrm.data(), r->nf,
+                                                      r->tri.data(), r->nc, r->qpos.data(), r->q.data(), &r->prm,
+                                                      &r->pb, tree_limit, &need);
+        if (st == HOBI_E_OOM && need > 0 && !alone && r->tree_charged == 0) {
+            // its treecode buffers do not fit next to the admitted requests: back to the head
+            // of the queue, charged their size, until enough of the budget is free
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->in_use -= r->footprint;
+            r->footprint += need;
+            r->tree_charged = need;
+            sv->preparing -= 1;
+            sv->st.bytes_in_use = sv->in_use;
+            sv->pending.push_front(std::move(r));
+            sv->st.pending = (int32_t)sv->pending.size();
+            continue;
+        }
         if (st != HOBI_OK) {
             fail_request(*r, st, sv->prep_ctx->err);
             r->pb = nullptr;
         } else {
             r->pb->ctx = sv->ctx;             // built and synchronised: from now on the worker's
         }
-        const int64_t extra = r->pb ? tree_bytes(r->pb->d) : 0;
+        const int64_t extra = r->pb ? tree_bytes(r->pb->d) - r->tree_charged : 0;
         {
             std::lock_guard<std::mutex> lk(sv->mu);
             r->footprint += extra;
@@ -591,8 +657,8 @@ hobi_status hobi_server_create(hobi_ctx ctx, int64_t hbm_budget_bytes, int32_t m
         delete sv;
         return host_fail(ctx, HOBI_E_HIP, "could not create the server streams");
     }
-    if (hipMalloc((void**)&sv->d_counts, 4 * sizeof(int)) != hipSuccess ||
-        hipHostMalloc((void**)&sv->h_counts, 4 * sizeof(int)) != hipSuccess ||
+    if (hipMalloc((void**)&sv->d_counts, kServeCounts * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void**)&sv->h_counts, kServeCounts * sizeof(int)) != hipSuccess ||
         ensure_capacity(sv, 16, 3 * 4096) != hipSuccess) {
         hobi_server_destroy(sv);
         return host_fail(ctx, HOBI_E_OOM, "server buffers");
@@ -688,7 +754,11 @@ void hobi_server_destroy(hobi_server sv) {
     if (sv->ctx) (void)hipStreamSynchronize(sv->ctx->stream);
     if (sv->graph_exec) (void)hipGraphExecDestroy(sv->graph_exec);
     if (sv->graph) (void)hipGraphDestroy(sv->graph);
+    if (sv->kgraph_exec) (void)hipGraphExecDestroy(sv->kgraph_exec);
+    if (sv->kgraph) (void)hipGraphDestroy(sv->kgraph);
     if (sv->d_desc) (void)hipFree(sv->d_desc);
+    if (sv->d_kdesc) (void)hipFree(sv->d_kdesc);
+    if (sv->h_kdesc) (void)hipHostFree(sv->h_kdesc);
     if (sv->d_items) (void)hipFree(sv->d_items);
     if (sv->d_counts) (void)hipFree(sv->d_counts);
     if (sv->d_res) (void)hipFree(sv->d_res);

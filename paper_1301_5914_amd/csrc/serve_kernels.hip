@@ -7,6 +7,7 @@
 // and a request's items depend only on that request, so its result does not depend on
 // which other requests share the launch.
 #include "hobi_internal.h"
+#include "krylov_tile.h"
 #include "pair_tile.h"
 #include "serve_internal.h"
 
@@ -70,6 +71,8 @@ __global__ __launch_bounds__(kPairBlock) __attribute__((amdgpu_waves_per_eu(4, 8
 __global__ __launch_bounds__(kPairBlock) void batched_pair64_kernel(const ServeDesc* __restrict__ desc,
                                                                   const ServeItem* __restrict__ items,
                                                                   const int* __restrict__ count) {
+    __shared__ double etab[kExpTab];
+    fill_exp_table(etab);
     const int n = as_constant(count)[0];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
@@ -78,10 +81,10 @@ __global__ __launch_bounds__(kPairBlock) void batched_pair64_kernel(const ServeD
         const int w = item.a * (kPairBlock / kWave) + wave;
         if (w >= d.workers) continue;
         if (d.kappa == 0.0)
-            pair_f64_worker<kTpl64, true>(d.tgt64, d.nv, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.kappa, d.eps,
+            pair_f64_worker<kTpl64, true>(d.tgt64, d.nv, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.kappa, etab,
                                           d.gstart, d.slots, d.partial, w);
         else
-            pair_f64_worker<kTpl64, false>(d.tgt64, d.nv, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.kappa, d.eps,
+            pair_f64_worker<kTpl64, false>(d.tgt64, d.nv, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.kappa, etab,
                                            d.gstart, d.slots, d.partial, w);
     }
 }
@@ -95,6 +98,93 @@ __global__ __launch_bounds__(kPairBlock) void batched_combine_kernel(const Serve
         const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
         combine_tile(item.a, d.u, d.y, d.nv, d.partial, d.slot, d.slots, d.groups, d.inc_off, d.inc_ent, d.tri,
                      d.coef, d.eps);
+    }
+}
+
+// ---- batched Arnoldi steps ----
+
+enum KrylovPhase { K_DIAG = 0, K_DOTS, K_REDUCE, K_AXPY, K_NORM_DOTS, K_SINGLE };
+
+// The request holding item `it` of `phase` (block-uniform): the last one whose first item is
+// at most it.
+__device__ __forceinline__ int krylov_owner(const KrylovDesc* __restrict__ kd, int nreq, int phase, int it) {
+    const const_as<KrylovDesc>* c = as_constant(kd);
+    int lo = 0, hi = nreq;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (c[mid].off[phase] <= it) lo = mid;
+        else hi = mid;
+    }
+    return uniform(lo);
+}
+
+__global__ __launch_bounds__(kKrylovBlock) void batched_diag_kernel(const KrylovDesc* __restrict__ kd,
+                                                                    const int* __restrict__ counts) {
+    const int n_items = as_constant(counts)[K_DIAG], nreq = as_constant(counts)[kKrylovPhases];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int q = krylov_owner(kd, nreq, K_DIAG, it);
+        const KrylovDesc& d = kd[q];
+        const int i = (it - d.off[K_DIAG]) * kKrylovBlock + (int)threadIdx.x;
+        if (d.z && i < d.n) diag_scale_elem(d.vk, d.z, d.nu, d.s1, d.s2, i);
+    }
+}
+
+// Slice partials of the Gram-Schmidt dot products (norm = 0: V[j] . w for j <= k) or of w . w.
+__global__ __launch_bounds__(kKrylovBlock) void batched_dots_kernel(const KrylovDesc* __restrict__ kd,
+                                                                    const int* __restrict__ counts, int norm) {
+    __shared__ double red[kKrylovBlock];
+    const int phase = norm ? K_NORM_DOTS : K_DOTS;
+    const int n_items = as_constant(counts)[phase], nreq = as_constant(counts)[kKrylovPhases];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int q = krylov_owner(kd, nreq, phase, it);
+        const KrylovDesc& d = kd[q];
+        const int local = it - d.off[phase];
+        const int j = local / kDotSlices, b = local % kDotSlices;
+        const double* v = norm ? d.w : d.V + (size_t)d.n * j;
+        const double s = dot_slice(v, d.w, d.n, b, red);
+        if (threadIdx.x == 0) d.dpart[(size_t)j * kDotSlices + b] = s;
+    }
+}
+
+// norm = 0: h_pass[j] = sum of the slices of dot product j; norm = 1: hn = its square root.
+__global__ __launch_bounds__(kDotSlices) void batched_reduce_kernel(const KrylovDesc* __restrict__ kd,
+                                                                   const int* __restrict__ counts, int pass,
+                                                                   int norm) {
+    __shared__ double red[kDotSlices];
+    const int phase = norm ? K_SINGLE : K_REDUCE;
+    const int n_items = as_constant(counts)[phase], nreq = as_constant(counts)[kKrylovPhases];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int q = krylov_owner(kd, nreq, phase, it);
+        const KrylovDesc& d = kd[q];
+        const int j = it - d.off[phase];
+        const double s = sum_slices(d.dpart + (size_t)j * kDotSlices, red, norm != 0);
+        if (threadIdx.x == 0) (norm ? d.hn : pass == 0 ? d.h1 : d.h2)[j] = s;
+    }
+}
+
+// scale = 0: w -= V h_pass (one Gram-Schmidt pass); scale = 1: w = w / hn.
+__global__ __launch_bounds__(kKrylovBlock) void batched_axpy_kernel(const KrylovDesc* __restrict__ kd,
+                                                                    const int* __restrict__ counts, int pass,
+                                                                    int scale) {
+    const int n_items = as_constant(counts)[K_AXPY], nreq = as_constant(counts)[kKrylovPhases];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int q = krylov_owner(kd, nreq, K_AXPY, it);
+        const KrylovDesc& d = kd[q];
+        const int i = (it - d.off[K_AXPY]) * kKrylovBlock + (int)threadIdx.x;
+        if (i >= d.n) continue;
+        if (scale)
+            scale_copy_elem(d.w, d.hn[0], d.w, i);
+        else
+            multi_axpy_elem(d.V, d.n, d.k + 1, pass == 0 ? d.h1 : d.h2, -1.0, d.w, i);
+    }
+}
+
+// One thread per request: column k of its Hessenberg matrix and rotation k.
+__global__ void batched_givens_kernel(const KrylovDesc* __restrict__ kd, const int* __restrict__ counts) {
+    const int nreq = as_constant(counts)[kKrylovPhases];
+    for (int q = blockIdx.x * blockDim.x + (int)threadIdx.x; q < nreq; q += gridDim.x * blockDim.x) {
+        const KrylovDesc& d = kd[q];
+        givens_step(d.H, d.ldh, d.k, d.h1, d.h2, d.hn, d.cs, d.sn, d.g, d.bnorm, d.res);
     }
 }
 
@@ -113,6 +203,31 @@ hipError_t launch_batched_matvec(const ServeDesc* desc, const ServeItem* const i
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(batched_combine_kernel, dim3(kServeGridSmall), dim3(kPairBlock), 0, s, desc, items[3],
                        counts + 3);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_diag(const KrylovDesc* kd, const int* counts, hipStream_t s) {
+    hipLaunchKernelGGL(batched_diag_kernel, dim3(kServeGridSmall), dim3(kKrylovBlock), 0, s, kd, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_krylov(const KrylovDesc* kd, const int* counts, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(batched_dots_kernel, dim3(kServeGridSmall), dim3(kKrylovBlock), 0, s, kd, counts, 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(batched_reduce_kernel, dim3(kServeGridSmall), dim3(kDotSlices), 0, s, kd, counts, pass, 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(batched_axpy_kernel, dim3(kServeGridSmall), dim3(kKrylovBlock), 0, s, kd, counts, pass, 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(batched_dots_kernel, dim3(kServeGridSmall), dim3(kKrylovBlock), 0, s, kd, counts, 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(batched_reduce_kernel, dim3(kServeGridSmall), dim3(kDotSlices), 0, s, kd, counts, 0, 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(batched_axpy_kernel, dim3(kServeGridSmall), dim3(kKrylovBlock), 0, s, kd, counts, 0, 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(batched_givens_kernel, dim3(1), dim3(64), 0, s, kd, counts);
     return hipGetLastError();
 }
 

@@ -350,8 +350,9 @@ __device__ __forceinline__ void far_f32_narrow(int live, const float* __restrict
 // FP64 far item (unscaled frame).
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void far_f64_wave(const double* __restrict__ tgt, int nv_pad,
-                                             const ProxyD* __restrict__ prox, int P, double kappa, int base,
-                                             double* __restrict__ prow, int slot) {
+                                             const ProxyD* __restrict__ prox, int P, double kappa,
+                                             const double* __restrict__ etab, int base, double* __restrict__ prow,
+                                             int slot) {
     const int lane = (int)(threadIdx.x % kWave);
     double tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL], a1[TPL], a2[TPL];
 #pragma unroll
@@ -380,7 +381,7 @@ __device__ __forceinline__ void far_f64_wave(const double* __restrict__ tgt, int
                 a2[k] = fma(-rinv3 * dnx, pr.q0 + pr.qk2, a2[k]);
             } else {
                 const double z = kappa * (r2 * rinv);
-                const double e = exp_neg_f64(z);
+                const double e = exp_neg_tab_f64(z, etab);
                 a1[k] = fma(rinv, fma(e, pr.qk, pr.q0), a1[k]);
                 a2[k] = fma(-rinv3 * dnx, fma(e * (1.0 + z), pr.qk2, pr.q0), a2[k]);
             }
@@ -395,15 +396,16 @@ __device__ __forceinline__ void far_f64_wave(const double* __restrict__ tgt, int
 
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void far_f64_narrow(int live, const double* __restrict__ tgt, int nv_pad,
-                                               const ProxyD* __restrict__ prox, int P, double kappa, int base,
-                                               double* __restrict__ prow, int slot) {
+                                               const ProxyD* __restrict__ prox, int P, double kappa,
+                                               const double* __restrict__ etab, int base, double* __restrict__ prow,
+                                               int slot) {
     if constexpr (TPL > 1) {
         if (live <= kWave * TPL / 2) {
-            far_f64_narrow<TPL / 2, KAPPA0>(live, tgt, nv_pad, prox, P, kappa, base, prow, slot);
+            far_f64_narrow<TPL / 2, KAPPA0>(live, tgt, nv_pad, prox, P, kappa, etab, base, prow, slot);
             return;
         }
     }
-    far_f64_wave<TPL, KAPPA0>(tgt, nv_pad, prox, P, kappa, base, prow, slot);
+    far_f64_wave<TPL, KAPPA0>(tgt, nv_pad, prox, P, kappa, etab, base, prow, slot);
 }
 
 // One wave per work item {slot, kind, cluster, -}: the item's partial row is its index.
@@ -430,8 +432,10 @@ template <int TPL, bool KAPPA0>
 __global__ __launch_bounds__(kBlock) void tree_f64_kernel(
     const int4* __restrict__ items, int nitems, const double* __restrict__ tgt, int nv, int nv_pad,
     const NodeD* __restrict__ nodes, const int4* __restrict__ node_vid, const int2* __restrict__ blk_range,
-    const int2* __restrict__ clu_range, const ProxyD* __restrict__ prox, int P, double kappa, double eps,
+    const int2* __restrict__ clu_range, const ProxyD* __restrict__ prox, int P, double kappa,
     double* __restrict__ partial) {
+    __shared__ double etab[kExpTab];
+    if constexpr (!KAPPA0) fill_exp_table(etab);
     const int w = xcd_logical_block() * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     if (w >= nitems) return;
     constexpr int kSlot = kWave * TPL;
@@ -440,10 +444,11 @@ __global__ __launch_bounds__(kBlock) void tree_f64_kernel(
     double* prow = partial + (size_t)w * (2 * kSlot);
     if (it.y == 0) {
         const int n0 = as_constant(clu_range)[it.z].x, n1 = as_constant(clu_range)[it.z].y;
-        pair_f64_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, nodes, node_vid, blk_range, kappa, eps, base, n0, n1,
+        pair_f64_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, nodes, node_vid, blk_range, kappa, etab, base, n0, n1,
                                      prow, kSlot);
     } else {
-        far_f64_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, prox + (size_t)it.z * P, P, kappa, base, prow, kSlot);
+        far_f64_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, prox + (size_t)it.z * P, P, kappa, etab, base, prow,
+                                    kSlot);
     }
 }
 
@@ -527,11 +532,11 @@ hipError_t launch_tree_pairs(const DeviceProblem& p, bool mixed, hipStream_t s) 
         if (k0)
             hipLaunchKernelGGL((tree_f64_kernel<kTpl64, true>), grid, dim3(kBlock), 0, s, t.items[0], t.nitems[0],
                                p.tgt64, p.nv, p.nv_pad, p.node64, p.node_vid, p.blk_range, t.clu_range, t.prox64,
-                               t.nprox, p.kappa, p.eps, t.partial);
+                               t.nprox, p.kappa, t.partial);
         else
             hipLaunchKernelGGL((tree_f64_kernel<kTpl64, false>), grid, dim3(kBlock), 0, s, t.items[0], t.nitems[0],
                                p.tgt64, p.nv, p.nv_pad, p.node64, p.node_vid, p.blk_range, t.clu_range, t.prox64,
-                               t.nprox, p.kappa, p.eps, t.partial);
+                               t.nprox, p.kappa, t.partial);
     }
     return hipGetLastError();
 }

@@ -80,6 +80,7 @@ _SIGS = {
     "hobi_solve": (ctypes.c_int, [_P, _D, _D, _D, ctypes.POINTER(hobi_stats)]),
     "hobi_matvec": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "hobi_matvec_noalloc": (ctypes.c_int, [_P, _P, _P]),
+    "hobi_device_math": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _D, _D]),
     "hobi_energy": (ctypes.c_int, [_P, _P, ctypes.c_int32, _D]),
     "hobi_field": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _D, _D, _D, _D, _D, _I]),
     "hobi_get_nodes": (ctypes.c_int, [_P, _D, _D, _D]),
@@ -141,6 +142,17 @@ def hobi_ctx_create(device: int = 0, stream: int | None = None):
     if st != 0:
         raise HobiError(st, "hobi_ctx_create failed")
     return h
+
+
+HOBI_MATH_EXP_NEG, HOBI_MATH_RSQRT = 0, 1
+
+
+def hobi_device_math(ctx, fn: int, x) -> np.ndarray:
+    """The FP64 pair kernel's exp(-x) (fn 0) or 1/sqrt(x) (fn 1) on the device, host arrays."""
+    x = _f64(x).ravel()
+    y = np.empty_like(x)
+    _check(ctx.handle, lib().hobi_device_math(ctx.handle, fn, x.shape[0], _dptr(x), _dptr(y)))
+    return y
 
 
 def hobi_last_error(ctx) -> str:

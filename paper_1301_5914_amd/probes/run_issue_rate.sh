@@ -8,3 +8,6 @@ mkdir -p "$out"
 /opt/rocm/bin/hipcc -O3 -std=c++17 --offload-arch=gfx950 -Xclang -target-feature -Xclang -packed-fp32-ops \
     -Wno-unused-command-line-argument "$here/issue_rate.hip" -o "$out/issue_rate"
 "$out/issue_rate"
+/opt/rocm/bin/hipcc -O3 -std=c++17 --offload-arch=gfx950 -Xclang -target-feature -Xclang -packed-fp32-ops \
+    -Wno-unused-command-line-argument "$here/rsq_f64_accuracy.hip" -o "$out/rsq_f64_accuracy"
+"$out/rsq_f64_accuracy"

@@ -27,6 +27,8 @@ def _cases():
         "offcenter_L2_k0_eps1_2": inputs.kirkwood_offcenter(2, kappa=0.0, eps1=2.0),
         "offcenter_L2_k1": inputs.kirkwood_offcenter(2, kappa=1.0, eps1=4.0),
         "ico_L0": inputs.kirkwood_centered(0, radius=2.0),
+        # small kappa: kappa r < 0.01 on every pair, where 1 - e, f1 and f2 cancel
+        "offcenter_L3_k0.001": inputs.kirkwood_offcenter(3, kappa=0.001),
     }
 
 
@@ -75,7 +77,7 @@ def test_matvec_fp64_matches_oracle(ctx, oracle_setups, name):
     assert _rel_inf(g.matvec(u), O.matvec(st, u, p.kappa, eps)) <= 1e-12
 
 
-@pytest.mark.parametrize("name", ["centered_L3", "offcenter_L3", "offcenter_L2_k0_eps1_2"])
+@pytest.mark.parametrize("name", list(CASES))
 def test_matvec_mixed_close_to_oracle(ctx, oracle_setups, name):
     p = CASES[name]
     g = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED)

@@ -168,3 +168,71 @@ def test_errors_are_reported_per_request(ctx):
     with pytest.raises(hobi.HobiError):
         sv.poll(ts[0])   # already collected
     sv.close()
+
+
+def test_served_energies_match_the_oracle(ctx):
+    """Served solves against the FP64 oracle's solve of the same problem (rtol 1e-10 on the
+    oracle's side): small protein-like molecules and spheres, mixed and FP64, several eps1
+    and kappa, submitted together; energies within 1e-5 (the mixed-mode bar)."""
+    from oracle.solve import solve as oracle_solve
+    m3, m4 = inputs.molecule(3, seed=1), inputs.molecule(4, seed=2)
+    cases = [(m3, dict(precision=hobi.HOBI_MIXED, eps1=1.0, kappa=0.1257)),
+             (m4, dict(precision=hobi.HOBI_MIXED, eps1=4.0, kappa=0.0)),
+             (m3, dict(precision=hobi.HOBI_FP64, eps1=2.0, kappa=0.1257)),
+             (inputs.kirkwood_offcenter(3), dict(precision=hobi.HOBI_MIXED)),
+             (inputs.kirkwood_offcenter(2), dict(precision=hobi.HOBI_MIXED, eps1=4.0, kappa=1.0)),
+             (inputs.kirkwood_centered(2), dict(precision=hobi.HOBI_FP64, kappa=0.0))]
+    sv = hobi.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=8)
+    ts = [sv.submit(p, max_iter=300, **kw) for p, kw in cases]
+    out = _wait(sv, ts)
+    sv.close()
+    for (p, kw), t in zip(cases, ts):
+        r = out[t]
+        assert r["status"] == "HOBI_OK"
+        o = oracle_solve(p.xyz, p.nrm, p.tri, p.qpos, p.q, kw.get("eps1", p.eps1), p.eps2, kw.get("kappa", p.kappa),
+                         rtol=1e-10, max_iter=300, restart=300)
+        err = abs(r["energy"] / o["energy"] - 1)
+        print(f"served nv={p.nv} {kw}: E {r['energy']:.8f} oracle {o['energy']:.8f} rel {err:.2e}, "
+              f"iterations {r['stats']['iterations']} / {o['iterations']}", flush=True)
+        assert err <= 1e-5
+
+
+def test_admission_respects_the_budget_with_treecode_requests(ctx):
+    """Treecode requests are charged their treecode buffers before they run: with room for
+    one and a half requests, four run one after another and the peak stays within the
+    budget; a budget below one request's needs fails it with HOBI_E_OOM."""
+    p = inputs.kirkwood_offcenter(3)
+    tree = dict(tree_theta=0.7, tree_degree=4, tree_leaf=128, tree_batch=128)
+    probe = hobi.Server(ctx, hbm_budget_bytes=1 << 40, max_slots=1)
+    t = probe.submit(p, **tree)
+    ref = _wait(probe, [t])[t]
+    one = probe.stats()["peak_bytes"]
+    probe.close()
+    budget = int(1.5 * one)
+    sv = hobi.Server(ctx, hbm_budget_bytes=budget, max_slots=8)
+    ts = [sv.submit(p, **tree) for _ in range(4)]
+    out = _wait(sv, ts)
+    st = sv.stats()
+    print("treecode budget test:", one, st, flush=True)
+    assert st["peak_bytes"] <= budget and st["completed"] == 4 and st["bytes_in_use"] == 0
+    for r in out.values():
+        assert r["status"] == "HOBI_OK"
+        np.testing.assert_array_equal(r["phi"], ref["phi"])
+    sv.close()
+    # room for the dense footprint but not the treecode buffers: fails alone
+    probe2 = hobi.Server(ctx, hbm_budget_bytes=1 << 40, max_slots=1)
+    t2 = probe2.submit(p)
+    _wait(probe2, [t2])
+    dense = probe2.stats()["peak_bytes"]
+    probe2.close()
+    assert dense < one
+    small = hobi.Server(ctx, hbm_budget_bytes=dense, max_slots=2)
+    try:
+        tt = small.submit(p, **tree)
+    except hobi.HobiError as e:        # refused at once: the dense footprint alone is over
+        assert e.name == "HOBI_E_OOM"
+    else:
+        r = _wait(small, [tt])[tt]
+        assert r["status"] == "HOBI_E_OOM"
+        assert small.stats()["peak_bytes"] <= dense
+    small.close()
