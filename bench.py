@@ -38,7 +38,9 @@ FLOPS_PER_CLK_CU = {"mixed": 256.0, "fp64": 128.0}   # the peaks above per clock
 # --pmc passes (FETCH_SIZE, WRITE_SIZE; each scaled by what it reads for a plain device copy
 # of known size), valid only for the kernel sources they were taken on: keyed by the
 # workload and a hash of those sources, else the bench reports null.
-PAIR_TRAFFIC = {}   # (workload, precision, sources sha16) -> (bytes per launch, profile file)
+PAIR_TRAFFIC = {    # (workload, precision, sources sha16) -> (bytes per launch, profile file)
+    ("large", "mixed", "4fba666d219e24fd"): (1479540065, "profiles/pair_f32_kernel_molecule5000_hbm_counters.md"),
+}
 KERNEL_SOURCES = ("paper_1301_5914_amd/csrc/pair_tile.h", "paper_1301_5914_amd/csrc/pair_kernels.hip",
                   "paper_1301_5914_amd/csrc/hobi_device.h")
 
@@ -120,19 +122,26 @@ def cpu_baseline(prob, seconds: float, workers: int, lower: bool = False):
     t_setup = time.perf_counter() - t_setup
     u = inputs.random_vector(2 * n_sites, 1)
     rng = np.random.default_rng(0)
+
+    def block(n):
+        # a contiguous run of rows at a seeded offset (the oracle spreads a contiguous run
+        # of rows over its worker processes)
+        n = min(n, n_sites)
+        a = int(rng.integers(0, n_sites - n + 1))
+        return np.arange(a, a + n)
     # per-row cost measured with all workers busy, then a sample sized to ~`seconds`
-    probe = np.sort(rng.choice(n_sites, min(n_sites, 2 * cores), replace=False))
+    probe = block(4 * cores if cores > 1 else 4)
     t0 = time.perf_counter()
     rows_fn(u, probe)
     per_row = (time.perf_counter() - t0) / probe.size
     nrows = int(min(n_sites, max(probe.size, seconds / max(per_row, 1e-9))))
-    rows = np.sort(rng.choice(n_sites, nrows, replace=False))
+    rows = block(nrows)
     t0 = time.perf_counter()
     y_rows = rows_fn(u, rows)
     dt = time.perf_counter() - t0
     pairs = nrows * n_nodes
     rec = {"value": pairs / dt / 1e9, "unit": "G-pairs/s", "cores": cores, "kind": "oracle",
-           "sample": f"{nrows} random of {n_sites} matvec rows (x {n_nodes} nodes), {dt:.1f} s "
+           "sample": f"{nrows} consecutive of {n_sites} matvec rows (x {n_nodes} nodes), {dt:.1f} s "
                      f"(oracle setup {t_setup:.1f} s, not timed)",
            "cpu_model": cpu_model(), "host_cpus_visible": len(os.sched_getaffinity(0))}
     return rec, (u, rows, y_rows)
@@ -349,6 +358,25 @@ def build_pool(n_mol, min_atoms, max_atoms, seed, workers):
     return out
 
 
+def load_or_build_pool(path, n_mol, min_atoms, max_atoms, seed, workers):
+    """build_pool, or its molecules from `path` when that file holds the same pool (written
+    there by an earlier run with the same arguments)."""
+    from paper_1301_5914_amd import inputs
+    key = np.array([n_mol, min_atoms, max_atoms, seed])
+    if path and os.path.exists(path):
+        d = np.load(path)
+        if np.array_equal(d["key"], key):
+            return [inputs.Problem(d[f"xyz{i}"], d[f"nrm{i}"], d[f"tri{i}"], d[f"qpos{i}"], d[f"q{i}"],
+                                   name=f"pool{i}") for i in range(n_mol)]
+    mols = build_pool(n_mol, min_atoms, max_atoms, seed, workers)
+    if path:
+        arrs = {"key": key}
+        for i, m in enumerate(mols):
+            arrs.update({f"xyz{i}": m.xyz, f"nrm{i}": m.nrm, f"tri{i}": m.tri, f"qpos{i}": m.qpos, f"q{i}": m.q})
+        np.savez(path, **arrs)
+    return mols
+
+
 def _make_molecule_job(indexed_job):
     k, job = indexed_job
     return k, _make_molecule(*job)
@@ -500,6 +528,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-checks", type=int, default=16, help="served requests checked against the oracle")
+    ap.add_argument("--serve-pool-cache", default=None,
+                    help=".npz to load the molecule pool from (written there if absent or different)")
     ap.add_argument("--serve-tree-theta", type=float, default=0.0,
                     help="serve the stream with the treecode at this opening parameter (0: dense)")
     ap.add_argument("--field-map", type=int, default=64,
@@ -525,7 +555,8 @@ def main():
     # the box gives one GPU's job a share of 16 host cores
     host_workers = max(1, min(16, len(os.sched_getaffinity(0))))
     if args.serve_requests > 0:
-        pool_mols = build_pool(args.serve_pool, args.serve_min_atoms, args.serve_max_atoms, 5, host_workers)
+        pool_mols = load_or_build_pool(args.serve_pool_cache, args.serve_pool, args.serve_min_atoms,
+                                       args.serve_max_atoms, 5, host_workers)
     cpu, sample = None, None
     if not args.no_cpu_baseline:
         # before any GPU call: the oracle forks worker processes
