@@ -42,7 +42,6 @@ template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void field_f32_run(const const_as<NodeF>* cnodes, int sb, int se,
                                               const float (&tx)[TPL], const float (&ty)[TPL],
                                               const float (&tz)[TPL], float (&a)[kParts][TPL]) {
-    constexpr float kLn2 = 0.693147180559945309f;
     NodeF n = load_node(cnodes, sb);
     for (int s = sb; s < se; ++s) {
         const NodeF next = load_node(cnodes, min(s + 1, se - 1));
@@ -62,11 +61,10 @@ __device__ __forceinline__ void field_f32_run(const const_as<NodeF>* cnodes, int
                 c2 = n.pa;
                 c1 = pa3 * q;
             } else {
-                const float r = r2 * rinv;
-                const float e = __builtin_amdgcn_exp2f(-r);               // exp(-kappa r)
-                const float zp1 = fmaf(r, kLn2, 1.0f);                   // 1 + z
+                const float zp1 = fmaf(r2, rinv, 1.0f);                  // 1 + z
+                const float e = __builtin_amdgcn_exp2f(fmaf(zp1, -kLog2E, kLog2E));   // exp(-z)
                 const float f1 = fmaf(-e, zp1, 1.0f);
-                const float f2 = fmaf(-e, fmaf(zp1, zp1 + 1.0f, 1.0f), 3.0f);
+                const float f2 = fmaf(-e, fmaf(zp1, 3.0f, r2), 3.0f);
                 c2 = fmaf(n.pb, f1, n.pa);                               // pa + pb f1
                 a[0][k] = fmaf(rinv, fmaf(q, c2, fmaf(-e, n.g, n.g)), a[0][k]);
                 c1 = fmaf(f1, n.g, fmaf(n.pb, f2, pa3) * q);             // f1 Gamma + (3 pa + pb f2) q
@@ -236,7 +234,6 @@ template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void far_field_f32_wave(const float* __restrict__ pts, int np_pad,
                                                    const ProxyF* __restrict__ prox, int P, int base,
                                                    double* __restrict__ prow, int slot) {
-    constexpr float kLn2 = 0.693147180559945309f;
     const int lane = (int)(threadIdx.x % kWave);
     float tx[TPL], ty[TPL], tz[TPL];
     double acc[kParts][TPL];
@@ -271,9 +268,8 @@ __device__ __forceinline__ void far_field_f32_wave(const float* __restrict__ pts
                     c = pr.q0a + pr.qka;
                     a[0][k] = fmaf(rinv, c, a[0][k]);
                 } else {
-                    const float r = r2 * rinv;
-                    const float e = __builtin_amdgcn_exp2f(-r);           // exp(-kappa r)
-                    const float zp1 = fmaf(r, kLn2, 1.0f);               // 1 + kappa r
+                    const float zp1 = fmaf(r2, rinv, 1.0f);              // 1 + kappa r
+                    const float e = __builtin_amdgcn_exp2f(fmaf(zp1, -kLog2E, kLog2E));   // exp(-kappa r)
                     a[0][k] = fmaf(rinv, fmaf(e, pr.qka, pr.q0a), a[0][k]);
                     c = fmaf(e * zp1, pr.qka, pr.q0a);
                 }

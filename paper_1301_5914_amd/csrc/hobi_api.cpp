@@ -360,7 +360,7 @@ hobi_status run_device_setup(hobi_problem pb, float* ms_out) {
     hipStream_t s = pb->ctx->stream;
     DeviceProblem& d = pb->d;
     hipEvent_t e0 = take_event(pb), e1 = take_event(pb);
-    d.s32 = d.kappa > 0 ? d.kappa * 1.4426950408889634074 : 1.0;
+    d.s32 = d.kappa > 0 ? d.kappa : 1.0;
     if (e0) (void)hipEventRecord(e0, s);
     if (d.method == HOBI_LOWER_ORDER) {
         HIPCHK(pb->ctx, launch_lobi_nodes(d, s));

@@ -84,7 +84,7 @@ struct DeviceProblem {
     double eps1 = 1, eps2 = 80, kappa = 0, eps = 80;
     double center[3] = {0, 0, 0};          // shift applied to the FP32 copies
     double extent = 0;                      // diagonal of the vertices' bounding box
-    double s32 = 1;                         // scale of the FP32 positions: kappa log2(e) (1 if kappa = 0)
+    double s32 = 1;                         // scale of the FP32 positions: kappa (1 if kappa = 0)
     // inputs in internal (spatially sorted) order
     double* xyz = nullptr;                  // [nv][3] site positions
     double* nrm = nullptr;                  // [nv][3] site normals

@@ -12,6 +12,7 @@ namespace hobi {
 constexpr int kPairBlock = 256;
 constexpr int kFold = 64;   // FP32 running sums are folded into FP64 every kFold nodes
 constexpr int kWave = 64;
+constexpr float kLog2E = 1.44269504088896340736f;   // exp(-z) = exp2(-z log2 e)
 
 // Target slots.  Slot s holds the kWave * TPL targets from s * kWave * TPL, lane l holding
 // (slot start) + kWave * k + l for k < TPL.  The wave holding the last slot narrows TPL to
@@ -88,9 +89,10 @@ __device__ __forceinline__ NodeD load_node(const const_as<NodeD>* p, int s) {
 }
 
 // FP32 pairs of nodes [sb, se) with the lane's TPL targets, added to FP32 running sums.
-// Positions are in units of 1 / (kappa log2 e) when kappa > 0, so that exp(-kappa r) is
-// exp2(-r) and kappa r = r ln 2 (the strengths carry the matching powers of the unit).
-// Per pair (kappa > 0): 34 VALU operations plus one rsqrt and one exp2.  With
+// Positions are in units of 1 / kappa when kappa > 0, so that z = kappa r = r: with
+// zp1 = 1 + z = r^2 / r + 1, exp(-z) = exp2(log2 e (1 - zp1)) and 3 + 3z + z^2 = 3 zp1 + r^2
+// (the strengths carry the matching powers of the unit).  Per pair (kappa > 0): 33 VALU
+// operations plus one rsqrt and one exp2.  With
 // q = (d.ny)/r^2, the two rows are
 //   row 1: K1 Gamma + K2 Phi = [Gamma (1 - e) + q (pa + pb f1)] / r
 //   row 2: K3 Gamma + K4 Phi = [(d.nx)(ga + gb f1 + p q f2) - (nx.P) f1] / r^3,  P = p ny,
@@ -102,7 +104,6 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, cons
                                              const float (&tz)[TPL], const float (&tnx)[TPL],
                                              const float (&tny)[TPL], const float (&tnz)[TPL],
                                              float (&a1)[TPL], float (&a2)[TPL]) {
-    constexpr float kLn2 = 0.693147180559945309f;
     NodeF n = load_node(cnodes, sb);
     for (int s = sb; s < se; ++s) {
         // the next record's scalar load is in flight while this one is used
@@ -124,11 +125,10 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, cons
                 a2[k] = fmaf(dnx * rinv3, n.ga, a2[k]);
             } else {
                 const float pnxy = fmaf(tnx[k], n.qx, fmaf(tny[k], n.qy, tnz[k] * n.qz));
-                const float r = r2 * rinv;
-                const float e = __builtin_amdgcn_exp2f(-r);               // exp(-kappa r)
-                const float zp1 = fmaf(r, kLn2, 1.0f);                   // 1 + z
+                const float zp1 = fmaf(r2, rinv, 1.0f);                  // 1 + z
+                const float e = __builtin_amdgcn_exp2f(fmaf(zp1, -kLog2E, kLog2E));   // exp(-z)
                 const float f1 = fmaf(-e, zp1, 1.0f);                    // 1 - e (1 + z)
-                const float f2 = fmaf(-e, fmaf(zp1, zp1 + 1.0f, 1.0f), 3.0f);   // 3 - e (3 + 3z + z^2)
+                const float f2 = fmaf(-e, fmaf(zp1, 3.0f, r2), 3.0f);    // 3 - e (3 + 3z + z^2)
                 const float q = dny * rinv2;
                 a1[k] = fmaf(rinv, fmaf(q, fmaf(n.pb, f1, n.pa), fmaf(-e, n.g, n.g)), a1[k]);
                 const float t = fmaf(n.p, q * f2, fmaf(n.gb, f1, n.ga));

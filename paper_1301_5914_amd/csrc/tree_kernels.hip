@@ -276,7 +276,6 @@ template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void far_f32_wave(const float* __restrict__ tgt, int nv_pad,
                                              const ProxyF* __restrict__ prox, int P, int base,
                                              double* __restrict__ prow, int slot) {
-    constexpr float kLn2 = 0.693147180559945309f;
     const int lane = (int)(threadIdx.x % kWave);
     float tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL];
     double d1[TPL], d2[TPL];
@@ -312,9 +311,8 @@ __device__ __forceinline__ void far_f32_wave(const float* __restrict__ tgt, int 
                     a1[k] = fmaf(rinv, pr.q0a + pr.qka, a1[k]);
                     a2[k] = fmaf(-rinv3 * dnx, pr.q0b + pr.qk2b, a2[k]);
                 } else {
-                    const float r = r2 * rinv;
-                    const float e = __builtin_amdgcn_exp2f(-r);           // exp(-kappa r)
-                    const float zp1 = fmaf(r, kLn2, 1.0f);               // 1 + kappa r
+                    const float zp1 = fmaf(r2, rinv, 1.0f);              // 1 + kappa r
+                    const float e = __builtin_amdgcn_exp2f(fmaf(zp1, -kLog2E, kLog2E));   // exp(-kappa r)
                     a1[k] = fmaf(rinv, fmaf(e, pr.qka, pr.q0a), a1[k]);
                     a2[k] = fmaf(-rinv3 * dnx, fmaf(e * zp1, pr.qk2b, pr.q0b), a2[k]);
                 }
