@@ -202,7 +202,8 @@ hobi_status hobi_matvec(hobi_problem pb, const double* u, double* y, int32_t on_
  * table is rewritten by each call): calls that overlap on one device -- on different
  * streams, contexts or host threads -- race and give wrong results.
  * Errors: HOBI_E_ARG (NULL vector; a treecode problem; a problem whose slots' partial rows
- * for a single node group exceed the work space, about nv > 4 million), HOBI_E_HIP. */
+ * for a single row of node groups (one group in FP64, four in mixed precision) exceed the
+ * work space, about nv > 4 million), HOBI_E_HIP. */
 hobi_status hobi_matvec_noalloc(hobi_problem pb, const double* u, double* y);
 
 /* ---- solvation energy of a given u (eq. solvation_energy, 4-point rule on every

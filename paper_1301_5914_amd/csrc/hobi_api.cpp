@@ -717,11 +717,11 @@ hobi_status problem_create_limited(hobi_ctx ctx, int32_t nv, const double* xyz, 
         const int r32 = pair_resident_waves(ctx->device, true, tpl32);
         if (r64 < 1 || r32 < 1)
             return cleanup_fail(fail(ctx, HOBI_E_HIP, "pair kernel occupancy query failed"));
-        if (!make_pair_plan(d.nv, d.nn, kTpl64, r64, &d.plan64, &ptab) ||
-            !make_pair_plan(d.nv, d.nn, tpl32, r32, &d.plan32, &ptab))
+        if (!make_pair_plan(d.nv, d.nn, kTpl64, r64, 1, &d.plan64, &ptab) ||
+            !make_pair_plan(d.nv, d.nn, tpl32, r32, kPairWaves, &d.plan32, &ptab))
             return cleanup_fail(fail(ctx, HOBI_E_ARG, "problem too large: %d sites x %d nodes", d.nv, d.nn));
-        d.partial_elems = std::max({(size_t)2 * d.plan64.slot * d.plan64.workers,
-                                    (size_t)2 * d.plan32.slot * d.plan32.workers,
+        d.partial_elems = std::max({(size_t)2 * d.plan64.slot * d.plan64.slots * d.plan64.rows,
+                                    (size_t)2 * d.plan32.slot * d.plan32.slots * d.plan32.rows,
                                     (size_t)d.nc_pad * d.plan_pts.chunks});
     }
 
@@ -989,7 +989,7 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
     } else {
         const int res = field_resident_waves(c->device, mixed);
         if (res < 1) return fail(c, HOBI_E_HIP, "field kernel occupancy query failed");
-        if (!make_pair_plan(np, d.nn, mixed ? kFieldTpl32 : kFieldTpl64, res, &pl, &gs))
+        if (!make_pair_plan(np, d.nn, mixed ? kFieldTpl32 : kFieldTpl64, res, 1, &pl, &gs))
             return fail(c, HOBI_E_ARG, "too many points: %d", np);
     }
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};

@@ -32,6 +32,7 @@ struct alignas(128) NodeD {
 };
 
 constexpr int kCombineVerts = 64;   // vertices per tile of the combine step
+constexpr int kPairWaves = 4;       // waves of a pair-kernel workgroup (an FP32 block: one slot, four node groups)
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kInv4Pi = 1.0 / (4.0 * kPi);

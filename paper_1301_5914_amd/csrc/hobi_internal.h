@@ -26,14 +26,19 @@ struct GridPlan {
 
 // Split of the dense pair sum over waves ("workers").  The targets are cut into slots of
 // 64 * tpl (one wave's targets), the nodes into `groups` contiguous ranges of equal length
-// (within one node); worker w takes slot w % slots against node group w / slots and writes
-// one row of partial sums (2 * slot doubles, row w).  groups is chosen so that the workers
-// make about kPairPasses passes of the waves the device holds at once: short workers let
-// the hardware's dispatch balance the load to the end of the launch (one long pass ends
-// with many SIMDs idle), while each worker's partial row is written once and read once by
-// the combine step, so a group keeps at least kMinGroupNodes nodes.  The workers of a node
-// group run side by side on one XCD and read the same nodes from its L2 at about the same
-// time.  The split depends on the problem and the device only, and so does the order of
+// (within one node; a multiple of per_row of them, some empty on tiny problems).  With
+// per_row = 4 (the FP32 pair kernels) one workgroup of 4 waves takes block b: slot
+// b % slots against groups 4 (b / slots) .. 4 (b / slots) + 3, the waves sharing out their
+// 64-node blocks, and sums the waves' rows in LDS in wave order into one row of partial sums
+// (2 * slot doubles, row b).  With per_row = 1 (the FP64 pair kernels and the off-surface
+// field kernels) worker w takes slot w % slots against group w / slots into row w.  Either
+// way there are `rows` = groups / per_row rows per slot.  groups is chosen so
+// that the workers make about kPairPasses passes of the waves the device holds at once:
+// short workers let the hardware's dispatch balance the load to the end of the launch (one
+// long pass ends with many SIMDs idle), while each partial row is written once and read once
+// by the combine step, so a group keeps at least kMinGroupNodes nodes.  The blocks of one
+// row index run side by side on one XCD and read the same nodes from its L2 at about the
+// same time.  The split depends on the problem and the device only, and so does the order of
 // every sum (results are reproducible bit for bit).
 constexpr int kPairPasses = 16;
 constexpr int kMinGroupNodes = 256;
@@ -41,9 +46,11 @@ struct PairPlan {
     int tpl;            // targets per lane
     int slot;           // targets per slot: 64 * tpl
     int slots;          // ceil(nv / slot)
-    int groups;         // node groups
-    int workers;        // slots * groups waves = partial rows
-    int blocks;         // workgroups of a launch: ceil(workers / waves per workgroup)
+    int groups;         // node groups, a multiple of per_row
+    int per_row;        // node groups summed into one partial row: 4 or 1
+    int rows;           // partial rows per slot: groups / per_row
+    int workers;        // slots * groups waves
+    int blocks;         // workgroups of a launch: ceil(workers / 4)
     const int* gstart;  // device [groups + 1]: node range of group g is [gstart[g], gstart[g + 1])
 };
 
@@ -133,7 +140,8 @@ inline int tpl32_for(int nv_pad) { return nv_pad >= 16384 ? 8 : 4; }
 int pair_resident_waves(int device, bool mixed, int tpl);
 // The split of nv targets by nn nodes for a device holding resident_waves of the kernel at
 // once; the group starts are appended to `gstart` (the plan's device pointer is left null).
-bool make_pair_plan(int nv, int nn, int tpl, int resident_waves, PairPlan* plan, std::vector<int>* gstart);
+bool make_pair_plan(int nv, int nn, int tpl, int resident_waves, int per_row, PairPlan* plan,
+                    std::vector<int>* gstart);
 hipError_t launch_gather(const DeviceProblem& p, const double* u, bool mixed, hipStream_t s);
 hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s);
 hipError_t launch_combine(const DeviceProblem& p, const double* u, double* y, bool mixed,

@@ -47,6 +47,7 @@ __global__ void gather_kernel(const double* __restrict__ u, int nv, const int* _
 }
 
 constexpr int kWavesPerBlock = kBlock / kWave;
+static_assert(kWavesPerBlock == kPairWaves, "a pair-kernel workgroup holds one block of the plan");
 
 // Workgroups are dispatched round-robin over the 8 XCDs by linear id.  Give each XCD a
 // contiguous range of logical workgroups, so that the workers of a node group (consecutive
@@ -57,7 +58,7 @@ __device__ __forceinline__ int xcd_logical_block() {
     return x * q + min(x, rm) + (p >> 3);
 }
 
-// One wave per worker of the pair plan: logical workgroup b holds workers
+// FP64: one wave per worker of the pair plan (per_row 1): logical workgroup b holds workers
 // kWavesPerBlock * b + (its waves); waves past the last worker return at once.
 template <int TPL, bool KAPPA0>
 __global__ __launch_bounds__(kBlock) void pair_f64_kernel(
@@ -71,22 +72,24 @@ __global__ __launch_bounds__(kBlock) void pair_f64_kernel(
     pair_f64_worker<TPL, KAPPA0>(tgt, nv, nv_pad, nodes, node_vid, blk_range, kappa, etab, gstart, slots, partial, w);
 }
 
+// FP32: one workgroup per block of the pair plan (per_row 4; logical workgroup b is block b);
+// every block of the grid is a block of the plan.
 template <int TPL, bool KAPPA0>
 __global__ __launch_bounds__(kBlock) void pair_f32_kernel(
     const float* __restrict__ tgt, int nv, int nv_pad, const NodeF* __restrict__ nodes,
     const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, const int* __restrict__ gstart,
-    int slots, int workers, double* __restrict__ partial) {
-    const int w = xcd_logical_block() * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    if (w >= workers) return;
-    pair_f32_worker<TPL, KAPPA0>(tgt, nv, nv_pad, nodes, node_vid, blk_range, gstart, slots, partial, w);
+    int slots, double* __restrict__ partial) {
+    __shared__ double red[kPairWaves * 2 * kWave * TPL];
+    pair_f32_block<TPL, KAPPA0>(tgt, nv, nv_pad, nodes, node_vid, blk_range, gstart, slots, partial,
+                                xcd_logical_block(), red);
 }
 
 __global__ void combine_kernel(const double* __restrict__ u, double* __restrict__ y, int nv,
-                               const double* __restrict__ partial, int slot, int slots, int groups,
+                               const double* __restrict__ partial, int slot, int slots, int rows,
                                const int* __restrict__ inc_off, const int* __restrict__ inc_ent,
                                const int* __restrict__ tri, const double* __restrict__ coef,
                                double eps) {
-    combine_tile(blockIdx.x, u, y, nv, partial, slot, slots, groups, inc_off, inc_ent, tri, coef, eps);
+    combine_tile(blockIdx.x, u, y, nv, partial, slot, slots, rows, inc_off, inc_ent, tri, coef, eps);
 }
 
 // Sums over every regular node at interior points (the charges):
@@ -206,8 +209,9 @@ GridPlan make_grid_plan(int n_pad, int nn, int tpl) {
     return pl;
 }
 
-bool make_pair_plan(int nv, int nn, int tpl, int resident_waves, PairPlan* plan, std::vector<int>* gstart) {
-    if (nv < 1 || nn < 1 || resident_waves < 1) return false;
+bool make_pair_plan(int nv, int nn, int tpl, int resident_waves, int per_row, PairPlan* plan,
+                    std::vector<int>* gstart) {
+    if (nv < 1 || nn < 1 || resident_waves < 1 || (per_row != 1 && per_row != kPairWaves)) return false;
     PairPlan pl{};
     pl.tpl = tpl;
     pl.slot = kWave * tpl;
@@ -216,8 +220,11 @@ bool make_pair_plan(int nv, int nn, int tpl, int resident_waves, PairPlan* plan,
     // group (a worker's partial row then costs the combine step little next to its pairs)
     const int max_groups = std::max(1, nn / kMinGroupNodes);
     const int64_t want = (int64_t)kPairPasses * resident_waves / pl.slots;
-    pl.groups = (int)std::max<int64_t>(1, std::min<int64_t>(want, max_groups));
-    if ((int64_t)pl.groups * pl.slots >= ((int64_t)1 << 31) / kWavesPerBlock) return false;
+    const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(want, max_groups));
+    pl.per_row = per_row;
+    pl.rows = (int)((groups + per_row - 1) / per_row);
+    pl.groups = pl.rows * per_row;
+    if ((int64_t)pl.groups * pl.slots >= ((int64_t)1 << 31) / kPairWaves) return false;
     pl.workers = pl.groups * pl.slots;
     pl.blocks = (pl.workers + kWavesPerBlock - 1) / kWavesPerBlock;
     for (int g = 0; g <= pl.groups; ++g) gstart->push_back((int)((int64_t)g * nn / pl.groups));
@@ -251,7 +258,7 @@ hipError_t launch_pair_plan(const DeviceProblem& p, const PairPlan& pl, double* 
     if (mixed) {
 #define HOBI_PAIR32(T, K0)                                                                                    \
     hipLaunchKernelGGL((pair_f32_kernel<T, K0>), dim3(pl.blocks), dim3(kBlock), 0, s, p.tgt32, p.nv, p.nv_pad, \
-                       p.node32, p.node_vid, p.blk_range, pl.gstart, pl.slots, pl.workers, partial)
+                       p.node32, p.node_vid, p.blk_range, pl.gstart, pl.slots, partial)
         if (pl.tpl == 8) {
             if (k0) HOBI_PAIR32(8, true); else HOBI_PAIR32(8, false);
         } else {
@@ -275,7 +282,7 @@ hipError_t launch_pair(const DeviceProblem& p, bool mixed, hipStream_t s) {
 hipError_t launch_combine_plan(const DeviceProblem& p, const PairPlan& pl, const double* partial,
                                const double* u, double* y, hipStream_t s) {
     hipLaunchKernelGGL(combine_kernel, dim3(nblk(p.nv, kCombineVerts)), dim3(kPairBlock), 0, s, u, y, p.nv,
-                       partial, pl.slot, pl.slots, pl.groups, p.inc_off, p.inc_ent, p.tri, p.coef, p.eps);
+                       partial, pl.slot, pl.slots, pl.rows, p.inc_off, p.inc_ent, p.tri, p.coef, p.eps);
     return hipGetLastError();
 }
 
@@ -287,12 +294,14 @@ hipError_t launch_combine(const DeviceProblem& p, const double* u, double* y, bo
 
 bool make_static_pair_plan(const PairPlan& base, int nn, PairPlan* out, size_t* row_bytes) {
     PairPlan pl = base;
-    const size_t per_group = (size_t)base.slots * 2 * base.slot * sizeof(double);
-    *row_bytes = per_group;
-    const size_t fit = (kStaticScratchBytes - kStaticTableBytes) / per_group;
-    const size_t table_max = kStaticTableBytes / sizeof(int) - 1;
+    // one partial row per slot for every per_row node groups
+    const size_t row_set = (size_t)base.slots * 2 * base.slot * sizeof(double);
+    *row_bytes = row_set;
+    const size_t fit = (kStaticScratchBytes - kStaticTableBytes) / row_set;
+    const size_t table_max = (kStaticTableBytes / sizeof(int) - 1) / base.per_row;
     if (fit < 1 || nn < 1) return false;
-    pl.groups = (int)std::min<size_t>({(size_t)base.groups, fit, table_max, (size_t)nn});
+    pl.rows = (int)std::min<size_t>({(size_t)base.rows, fit, table_max});
+    pl.groups = pl.rows * base.per_row;
     pl.workers = pl.groups * pl.slots;
     pl.blocks = (pl.workers + kWavesPerBlock - 1) / kWavesPerBlock;
     pl.gstart = nullptr;

@@ -140,7 +140,8 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, cons
 }
 
 // FP32 pairs, FP64 accumulation, of the kWave * TPL targets from `base` (wave-uniform) with
-// the nodes [n0, n1): running FP32 sums over the nodes of one kFold-aligned block are added
+// the kFold-aligned node blocks part, part + step, ... of the nodes [n0, n1) (all of them for
+// part 0, step 1): running FP32 sums over the nodes of one kFold-aligned block are added
 // into FP64 per-target accumulators, stored to row `prow` of the partial sums (row 1 sums
 // at prow[t - base], row 2 sums at prow[slot + t - base]).  blk_range[b] = (min, max)
 // vertex id of the triangles of nodes [kFold b, kFold b + kFold); a wave whose targets miss
@@ -149,7 +150,7 @@ template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void pair_f32_wave(
     const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes,
     const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int base, int n0, int n1,
-    double* __restrict__ prow, int slot) {
+    double* __restrict__ prow, int slot, int part, int step) {
     const int lane = (int)(threadIdx.x % kWave);
     const int t0 = base + lane;
     float tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL];
@@ -169,9 +170,10 @@ __device__ __forceinline__ void pair_f32_wave(
     const const_as<NodeF>* cnodes = as_constant(nodes);
     const const_as<int4>* cvid = as_constant(node_vid);
     const const_as<int2>* crange = as_constant(blk_range);
-    for (int sb = n0, se; sb < n1; sb = se) {
-        se = min((sb / kFold + 1) * kFold, n1);
-        const int vlo = crange[sb / kFold].x, vhi = crange[sb / kFold].y;
+    // the kFold-aligned node blocks part, part + step, part + 2 step, ... of [n0, n1)
+    for (int f = n0 / kFold + part; f * kFold < n1; f += step) {
+        const int sb = max(f * kFold, n0), se = min(f * kFold + kFold, n1);
+        const int vlo = crange[f].x, vhi = crange[f].y;
         const bool near = (vhi >= base) & (vlo < base + kWave * TPL);
         float a1[TPL], a2[TPL];
 #pragma unroll
@@ -199,30 +201,54 @@ template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void pair_f32_narrow(
     int live, const float* __restrict__ tgt, int nv_pad, const NodeF* __restrict__ nodes,
     const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, int base, int n0, int n1,
-    double* __restrict__ prow, int slot) {
+    double* __restrict__ prow, int slot, int part = 0, int step = 1) {
     if constexpr (TPL > 1) {
         if (live <= kWave * TPL / 2) {
-            pair_f32_narrow<TPL / 2, KAPPA0>(live, tgt, nv_pad, nodes, node_vid, blk_range, base, n0, n1, prow, slot);
+            pair_f32_narrow<TPL / 2, KAPPA0>(live, tgt, nv_pad, nodes, node_vid, blk_range, base, n0, n1, prow, slot,
+                                             part, step);
             return;
         }
     }
-    pair_f32_wave<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, base, n0, n1, prow, slot);
+    pair_f32_wave<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, base, n0, n1, prow, slot, part, step);
 }
 
-// Worker w of a pair plan with `slots` target slots and node groups [gstart[g],
-// gstart[g + 1]): slot w % slots against group w / slots, into partial row w.  w must be
-// wave-uniform and below slots * groups.
+// The kPairWaves rows of a block (row w at red + w * 2 * kSlot, in LDS) summed in wave order
+// into the block's partial row, for the `live` real targets of the slot.  All threads of the
+// block call it, after a barrier that follows the waves' writes.
+template <int kSlot>
+__device__ __forceinline__ void sum_wave_rows(const double* red, int live, double* __restrict__ row) {
+    for (int j = (int)threadIdx.x; j < 2 * kSlot; j += kPairBlock) {
+        if ((j < kSlot ? j : j - kSlot) < live) {
+            double v = red[j];
+#pragma unroll
+            for (int w = 1; w < kPairWaves; ++w) v += red[w * 2 * kSlot + j];
+            row[j] = v;
+        }
+    }
+}
+
+// Block b of a pair plan with per_row = kPairWaves, `slots` target slots and node groups
+// [gstart[g], gstart[g + 1]): slot b % slots against the nodes of groups
+// kPairWaves (b / slots) .. kPairWaves (b / slots) + kPairWaves - 1.  Wave w takes the
+// kFold-aligned node blocks w, w + kPairWaves, ... of that range (so the waves meet the
+// costlier masked blocks near the slot's own vertices in equal shares) into its LDS row, and
+// the block writes the rows' sum to partial row b.  red: kPairWaves * 2 * kWave * TPL doubles of LDS.  b must be block-uniform and
+// below slots * groups / kPairWaves; all threads of the block call it.
 template <int TPL, bool KAPPA0>
-__device__ __forceinline__ void pair_f32_worker(
+__device__ __forceinline__ void pair_f32_block(
     const float* __restrict__ tgt, int nv, int nv_pad, const NodeF* __restrict__ nodes,
     const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, const int* __restrict__ gstart,
-    int slots, double* __restrict__ partial, int w) {
+    int slots, double* __restrict__ partial, int b, double* red) {
     constexpr int kSlot = kWave * TPL;
-    const int g = w / slots, s = w - g * slots;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int q = b / slots, s = b - q * slots;
     const const_as<int>* cg = as_constant(gstart);
     const int base = s * kSlot;
-    pair_f32_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, nodes, node_vid, blk_range, base, cg[g], cg[g + 1],
-                                 partial + (size_t)w * (2 * kSlot), kSlot);
+    pair_f32_narrow<TPL, KAPPA0>(nv - base, tgt, nv_pad, nodes, node_vid, blk_range, base, cg[q * kPairWaves],
+                                 cg[q * kPairWaves + kPairWaves], red + wave * (2 * kSlot), kSlot, wave, kPairWaves);
+    __syncthreads();
+    sum_wave_rows<kSlot>(red, nv - base, partial + (size_t)b * (2 * kSlot));
+    __syncthreads();   // red may be reused at once
 }
 
 // Node strengths Gamma = g, Phi = p (1/(4 pi) folded in) and the quantities derived from
@@ -390,13 +416,14 @@ __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, cons
     }
 }
 
-// FP64 pairs of the kWave * TPL targets from `base` with the nodes [n0, n1), stored to row
-// `prow` as in the FP32 wave (same block-range test).
+// FP64 pairs of the kWave * TPL targets from `base` with the node blocks part, part + step,
+// ... of [n0, n1), stored to row `prow` as in the FP32 wave (same block-range test).
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void pair_f64_wave(
     const double* __restrict__ tgt, int nv_pad, const NodeD* __restrict__ nodes,
     const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa,
-    const double* __restrict__ etab, int base, int n0, int n1, double* __restrict__ prow, int slot) {
+    const double* __restrict__ etab, int base, int n0, int n1, double* __restrict__ prow, int slot, int part,
+    int step) {
     const int lane = (int)(threadIdx.x % kWave);
     const int t0 = base + lane;
     double tx[TPL], ty[TPL], tz[TPL], tnx[TPL], tny[TPL], tnz[TPL], a1[TPL], a2[TPL];
@@ -415,9 +442,10 @@ __device__ __forceinline__ void pair_f64_wave(
     const const_as<NodeD>* cnodes = as_constant(nodes);
     const const_as<int4>* cvid = as_constant(node_vid);
     const const_as<int2>* crange = as_constant(blk_range);
-    for (int sb = n0, se; sb < n1; sb = se) {
-        se = min((sb / kFold + 1) * kFold, n1);
-        const int vlo = crange[sb / kFold].x, vhi = crange[sb / kFold].y;
+    // the kFold-aligned node blocks part, part + step, part + 2 step, ... of [n0, n1)
+    for (int f = n0 / kFold + part; f * kFold < n1; f += step) {
+        const int sb = max(f * kFold, n0), se = min(f * kFold + kFold, n1);
+        const int vlo = crange[f].x, vhi = crange[f].y;
         const bool near = (vhi >= base) & (vlo < base + kWave * TPL);
         if (near)
             pair_f64_run<TPL, KAPPA0, true>(cnodes, cvid, sb, se, base, tx, ty, tz, tnx, tny, tnz, kappa, etab, a1,
@@ -437,18 +465,22 @@ template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void pair_f64_narrow(
     int live, const double* __restrict__ tgt, int nv_pad, const NodeD* __restrict__ nodes,
     const int4* __restrict__ node_vid, const int2* __restrict__ blk_range, double kappa,
-    const double* __restrict__ etab, int base, int n0, int n1, double* __restrict__ prow, int slot) {
+    const double* __restrict__ etab, int base, int n0, int n1, double* __restrict__ prow, int slot, int part = 0,
+    int step = 1) {
     if constexpr (TPL > 1) {
         if (live <= kWave * TPL / 2) {
             pair_f64_narrow<TPL / 2, KAPPA0>(live, tgt, nv_pad, nodes, node_vid, blk_range, kappa, etab, base, n0, n1,
-                                              prow, slot);
+                                              prow, slot, part, step);
             return;
         }
     }
-    pair_f64_wave<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, kappa, etab, base, n0, n1, prow, slot);
+    pair_f64_wave<TPL, KAPPA0>(tgt, nv_pad, nodes, node_vid, blk_range, kappa, etab, base, n0, n1, prow, slot, part,
+                               step);
 }
 
-// etab: the workgroup's exponential table (fill_exp_table; not read when KAPPA0).
+// Worker w of a pair plan with one row per node group (per_row 1): slot w % slots against
+// group w / slots, into partial row w.  etab: the workgroup's exponential table
+// (fill_exp_table; not read when KAPPA0).  w must be wave-uniform and below slots * groups.
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void pair_f64_worker(
     const double* __restrict__ tgt, int nv, int nv_pad, const NodeD* __restrict__ nodes,
@@ -467,14 +499,14 @@ constexpr int kCombineWays = kPairBlock / kCombineVerts;  // waves splitting the
 constexpr int kCombineUnroll = 8;
 
 // Rows (i, i + nv) of y = A u for the kCombineVerts vertices of tile vb: the partial rows of
-// their slot s (rows g * slots + s for the node groups g, each 2 * slot doubles; wave k of
-// the block sums groups k, k + 4, ... into eight running sums by turn, and the sums of
-// each wave and then of the four waves are added in a fixed order),
+// their slot s (rows r * slots + s for r < rows, each 2 * slot doubles; wave k of the block
+// sums rows k, k + 4, ... into eight running sums by turn, and the sums of each wave and
+// then of the four waves are added in a fixed order),
 // the singular correction and the diagonal.  slot is a multiple of kCombineVerts.  Must be called by all
 // kPairBlock threads of the block (it synchronises them).
 __device__ __forceinline__ void combine_tile(int vb, const double* __restrict__ u, double* __restrict__ y, int nv,
                                              const double* __restrict__ partial, int slot, int slots,
-                                             int groups, const int* __restrict__ inc_off, const int* __restrict__ inc_ent,
+                                             int rows, const int* __restrict__ inc_off, const int* __restrict__ inc_ent,
                                              const int* __restrict__ tri, const double* __restrict__ coef,
                                              double eps) {
     static_assert(kCombineWays == 4, "four partial sums per vertex");
@@ -493,7 +525,7 @@ __device__ __forceinline__ void combine_tile(int vb, const double* __restrict__ 
         const size_t row_step = (size_t)kCombineWays * slots * 2 * slot;
         const double* q = col + ((size_t)way * slots + s) * 2 * slot;
         int g = way;
-        for (; g + (kCombineUnroll - 1) * kCombineWays < groups; g += kCombineUnroll * kCombineWays) {
+        for (; g + (kCombineUnroll - 1) * kCombineWays < rows; g += kCombineUnroll * kCombineWays) {
 #pragma unroll
             for (int j = 0; j < kCombineUnroll; ++j) {
                 p1[j] += q[j * row_step];
@@ -501,7 +533,7 @@ __device__ __forceinline__ void combine_tile(int vb, const double* __restrict__ 
             }
             q += kCombineUnroll * row_step;
         }
-        for (; g < groups; g += kCombineWays, q += row_step) {
+        for (; g < rows; g += kCombineWays, q += row_step) {
             p1[0] += q[0];
             p2[0] += q[slot];
         }

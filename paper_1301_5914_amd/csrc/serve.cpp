@@ -78,9 +78,10 @@ int64_t footprint_bytes(int device, int nv, int nf, int nc, int m, int method) {
         const int tpl = mixed ? tpl32_for((int)nv_pad) : kTpl64;
         PairPlan pl{};
         std::vector<int> gs;
-        if (!make_pair_plan(nv, (int)nn, tpl, std::max(1, pair_resident_waves(device, mixed, tpl)), &pl, &gs))
+        if (!make_pair_plan(nv, (int)nn, tpl, std::max(1, pair_resident_waves(device, mixed, tpl)),
+                            mixed ? kPairWaves : 1, &pl, &gs))
             return INT64_MAX;
-        pair_rows_elems = std::max<int64_t>(pair_rows_elems, 2LL * pl.slot * pl.workers);
+        pair_rows_elems = std::max<int64_t>(pair_rows_elems, 2LL * pl.slot * pl.slots * pl.rows);
         tab_ints += (int64_t)gs.size();
     }
     int64_t b = 0;
@@ -402,9 +403,9 @@ hobi_status tick(hobi_server sv) {
         sd.nv_pad = d.nv_pad;
         sd.nn = d.nn;
         sd.gstart = r.plan.gstart;
-        sd.workers = r.plan.workers;
+        sd.blocks = r.plan.blocks;
         sd.slots = r.plan.slots;
-        sd.groups = r.plan.groups;
+        sd.rows = r.plan.rows;
         sd.slot = r.plan.slot;
         sd.mixed = r.prm.precision == HOBI_MIXED ? 1 : 0;
         sd.tpl = r.plan.tpl;

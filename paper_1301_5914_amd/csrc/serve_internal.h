@@ -34,15 +34,15 @@ struct ServeDesc {
     double eps;
     double s32;             // scale of the FP32 positions
     int nv, nv_pad, nn;
-    int workers, slots, groups, slot;   // the pair plan (the single-problem plan)
+    int blocks, slots, rows, slot;      // the pair plan (the single-problem plan)
     int mixed;
     int tpl;                // targets per lane of the request's pair plan (the single-problem plan)
     int method;             // HOBI_HIGHER_ORDER or HOBI_LOWER_ORDER
     int pad;
 };
 
-// One unit of work: request `req`; a = workgroup of the pair plan's workers (waves
-// 4a .. 4a + 3) for the pair kernels, node or vertex block for gather and combine.
+// One unit of work: request `req`; a = block of the pair plan for the pair kernels, node or
+// vertex block for gather and combine.
 struct ServeItem {
     int req, a, b, pad;
 };

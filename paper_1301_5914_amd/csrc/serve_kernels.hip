@@ -14,6 +14,7 @@
 namespace hobi {
 
 static_assert(kServeBlock == kPairBlock, "served work items are pair-kernel blocks");
+static_assert(kPairBlock == kPairWaves * kWave, "a pair block is kPairWaves waves");
 static_assert(kTpl64 == 2, "served FP64 tiles use the single-problem plan");
 
 namespace {
@@ -43,27 +44,26 @@ __global__ __launch_bounds__(kPairBlock) void batched_gather_kernel(const ServeD
 // more registers than the largest of them and lose a wave per SIMD.
 __global__ __launch_bounds__(kPairBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void batched_pair32_kernel(
     const ServeDesc* __restrict__ desc, const ServeItem* __restrict__ items, const int* __restrict__ count) {
+    __shared__ double red[kPairWaves * 2 * kWave * 8];
     const int n = as_constant(count)[0];
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const const_as<ServeItem>& item = as_constant(items)[uniform(it)];
         const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
-        const int w = item.a * (kPairBlock / kWave) + wave;
-        if (w >= d.workers) continue;
+        const int b = uniform(item.a);
         if (d.tpl == 8) {
             if (d.kappa == 0.0)
-                pair_f32_worker<8, true>(d.tgt32, d.nv, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.gstart, d.slots,
-                                         d.partial, w);
+                pair_f32_block<8, true>(d.tgt32, d.nv, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.gstart, d.slots,
+                                        d.partial, b, red);
             else
-                pair_f32_worker<8, false>(d.tgt32, d.nv, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.gstart, d.slots,
-                                          d.partial, w);
+                pair_f32_block<8, false>(d.tgt32, d.nv, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.gstart, d.slots,
+                                         d.partial, b, red);
         } else {
             if (d.kappa == 0.0)
-                pair_f32_worker<4, true>(d.tgt32, d.nv, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.gstart, d.slots,
-                                         d.partial, w);
+                pair_f32_block<4, true>(d.tgt32, d.nv, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.gstart, d.slots,
+                                        d.partial, b, red);
             else
-                pair_f32_worker<4, false>(d.tgt32, d.nv, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.gstart, d.slots,
-                                          d.partial, w);
+                pair_f32_block<4, false>(d.tgt32, d.nv, d.nv_pad, d.node32, d.node_vid, d.blk_range, d.gstart, d.slots,
+                                         d.partial, b, red);
         }
     }
 }
@@ -78,8 +78,8 @@ __global__ __launch_bounds__(kPairBlock) void batched_pair64_kernel(const ServeD
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const const_as<ServeItem>& item = as_constant(items)[uniform(it)];
         const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
-        const int w = item.a * (kPairBlock / kWave) + wave;
-        if (w >= d.workers) continue;
+        const int w = item.a * kPairWaves + wave;   // one row per worker (per_row 1)
+        if (w >= d.rows * d.slots) continue;
         if (d.kappa == 0.0)
             pair_f64_worker<kTpl64, true>(d.tgt64, d.nv, d.nv_pad, d.node64, d.node_vid, d.blk_range, d.kappa, etab,
                                           d.gstart, d.slots, d.partial, w);
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kPairBlock) void batched_combine_kernel(const Serve
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const const_as<ServeItem>& item = as_constant(items)[uniform(it)];
         const const_as<ServeDesc>& d = as_constant(desc)[uniform(item.req)];
-        combine_tile(item.a, d.u, d.y, d.nv, d.partial, d.slot, d.slots, d.groups, d.inc_off, d.inc_ent, d.tri,
+        combine_tile(item.a, d.u, d.y, d.nv, d.partial, d.slot, d.slots, d.rows, d.inc_off, d.inc_ent, d.tri,
                      d.coef, d.eps);
     }
 }
