@@ -33,9 +33,11 @@ Modules, in the order of the method:
   eq. solvation_energy.
 
 Readings taken where the paper is silent or garbled are listed in each function's
-docstring.  The parity of the geometric construction (arc tangents, node normals, the
-choice of Gauss-Radau rule) is pinned only indirectly (sphere area/volume, consistency,
-Kirkwood convergence): parity unpinned for those constructive choices themselves.
+docstring.  The geometric construction (arc tangents, node normals, the centroid node, the
+choice of Gauss-Radau rule) is a reading of a garbled passage with no worked example; it is
+pinned by closed forms (exactness of the rule, the error orders of the arcs on a circle and
+of the elements on spheres, area and volume, watertightness, Kirkwood convergence), not by
+values the paper prints.
 """
 
 FOUR_PI = 12.566370614359172953850573533118

@@ -2,10 +2,12 @@
 
 The construction itself (tangent lengths, node normals, centroid node) is a reading of
 an underdetermined passage, so it is pinned through what any correct construction must
-satisfy: the P3 basis interpolates cubics exactly; the arcs interpolate their end data;
-curved icospheres reproduce the sphere's area and volume at high order; shared edges
-are watertight; the patch is tangent to the vertex normals; the double-layer identity
-holds to rounding once the quadrature is refined.
+satisfy and through the closed-form error orders of this one: the P3 basis interpolates
+cubics exactly; the arcs interpolate their end data and approach a circle as theta^6
+(normals theta^5); on spheres the edge and centroid nodes converge as h^6, interior points
+as h^4 and normals as h^3, and area and volume at high order; shared edges are watertight;
+the patch is tangent to the vertex normals; the double-layer identity holds to rounding
+once the quadrature is refined.
 """
 import math
 
@@ -79,6 +81,52 @@ def test_arc_on_a_circle():
         x, n = G.arc_point(P, P / R, Q_, Q_ / R, t)
         assert abs(np.linalg.norm(x) - R) < 2e-5 * R
         assert np.allclose(n, x / np.linalg.norm(x), atol=1e-4)
+
+
+def test_arc_error_orders_on_a_circle():
+    """Against the circle through both ends (closed form): the arc's radial error falls as
+    theta^6 and its normal's error as theta^5 when the angle halves (reading of the arc
+    construction, Section 2.2: a chord-length tangent would give theta^4, an unprojected
+    normal blend theta^2)."""
+    R = 2.0
+    prev = None
+    for th in (0.4, 0.2, 0.1):
+        P = np.array([R, 0.0, 0.0])
+        Q_ = np.array([R * math.cos(th), R * math.sin(th), 0.0])
+        ep = en = 0.0
+        for t in np.linspace(0, 1, 41):
+            x, n = G.arc_point(P, P / R, Q_, Q_ / R, t)
+            ep = max(ep, abs(np.linalg.norm(x) - R))
+            en = max(en, np.linalg.norm(n - x / np.linalg.norm(x)))
+        if prev is not None:
+            assert prev[0] / ep > 60 and prev[1] / en > 30, (th, prev[0] / ep, prev[1] / en)
+        prev = (ep, en)
+
+
+def test_sphere_patch_error_orders():
+    """Curved elements of icospheres against the sphere (closed form), h halving per level:
+    the edge and centroid nodes (on arcs) converge as h^6, points inside the element (P3
+    interpolation of the 10 nodes) as h^4, the element normal there as h^3."""
+    R = 2.0
+    prev = None
+    for lvl in (2, 3, 4):
+        xyz, nrm, tri = inputs.icosphere(lvl, R)
+        patch = G.patch_nodes(xyz[tri], nrm[tri])
+        edge = np.abs(np.linalg.norm(patch[:, 3:9], axis=-1) - R).max()
+        cen = np.abs(np.linalg.norm(patch[:, 9], axis=-1) - R).max()
+        pos = nor = 0.0
+        for r, s in [(0.2, 0.2), (0.5, 0.25), (0.1, 0.6), (1 / 3, 1 / 3), (0.7, 0.1)]:
+            x, _, n = G.eval_patch(patch, r, s)
+            rad = np.linalg.norm(x, axis=-1, keepdims=True)
+            pos = max(pos, np.abs(rad[:, 0] - R).max())
+            nor = max(nor, np.linalg.norm(n - x / rad, axis=-1).max())
+        cur = (edge, cen, pos, nor)
+        if prev is not None:
+            ratios = [a / b for a, b in zip(prev, cur)]
+            assert ratios[0] > 45 and ratios[1] > 45, ratios
+            assert ratios[2] > 13 and ratios[3] > 7, ratios
+        prev = cur
+    assert cur[0] < 1e-11 and cur[1] < 1e-11 and cur[2] < 3e-7 and cur[3] < 1e-5
 
 
 def test_normal_parallel_to_edge_is_rejected():
