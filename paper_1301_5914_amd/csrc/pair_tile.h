@@ -334,14 +334,15 @@ __device__ __forceinline__ void f012_pair_f64(double z, double& f0, double& f1, 
 }
 
 // exp(-z) for 0 <= z < kExpTabMaxZ in FP64 by Tang's table-driven method (P. T. P. Tang, ACM
-// TOMS 15, 1989): n = rint(256 z log2(e)) = 256 k + j (0 <= j < 256), r = z - n ln2/256 with
-// |r| <= ln2/512 (Cody-Waite: ln2/256 split into a 32-bit head, so n * head is exact, and a
-// tail), and exp(-z) = 2^-k * 2^(-j/256) * exp(-r).  n comes from adding 1.5 * 2^52 to
-// 256 z log2(e) in one fused multiply-add: the sum's rounding is the rounding to an integer,
-// its low 32 bits are n, and subtracting the constant again gives n exactly.  The 256
-// values 2^(-j/256), each the nearest double (exp2_table.h), sit in LDS (fill_exp_table, once
-// per workgroup); exp(-r) - 1 is its Taylor polynomial to degree 4 (truncation below 4e-17),
-// added as T + T (exp(-r) - 1) by one fused multiply-add.  Measured against an
+// TOMS 15, 1989), in the negated reduction: m = rint(-256 z log2(e)) = 256 k + j
+// (0 <= j < 256, k <= 0), r = z + m ln2/256 with |r| <= ln2/512 (Cody-Waite: ln2/256 split
+// into a 32-bit head, so m * head is exact, and a tail), and exp(-z) = 2^k * 2^(j/256) *
+// exp(-r), so that j and k are the low byte and the arithmetic shift of m as it stands.  m
+// comes from adding 1.5 * 2^52 to -256 z log2(e) in one fused multiply-add: the sum's rounding
+// is the rounding to an integer, its low 32 bits are m, and subtracting the constant again
+// gives m exactly.  The 256 values 2^(j/256), each the nearest double (exp2_table.h), sit in
+// LDS (fill_exp_table, once per workgroup); exp(-r) - 1 is its Taylor polynomial to degree 4
+// (truncation below 4e-17), added as T + T (exp(-r) - 1) by one fused multiply-add.  Measured against an
 // extended-precision reference: within 1.3 units in the last place.  Past z = 745 the result
 // underflows to 0; the problem checks (kappa times its extent) keep z below kExpTabMaxZ,
 // where n fits an int.
@@ -349,24 +350,24 @@ constexpr int kExpTab = 256;
 
 // Must be called by every thread of the workgroup (it synchronises them).
 __device__ __forceinline__ void fill_exp_table(double* __restrict__ tab) {
-    for (int j = (int)threadIdx.x; j < kExpTab; j += (int)blockDim.x) tab[j] = kExp2NegTab256[j];
+    for (int j = (int)threadIdx.x; j < kExpTab; j += (int)blockDim.x) tab[j] = kExp2Tab256[j];
     __syncthreads();
 }
 
 __device__ __forceinline__ double exp_neg_tab_f64(double z, const double* __restrict__ tab) {
     constexpr double kC = kExpTab * 1.44269504088896340735992468100189214;   // 256 log2(e)
     constexpr double kShift = 0x1.8p52;                                        // 1.5 * 2^52
-    const double y = fma(z, kC, kShift);
-    const double n = y - kShift;
-    const int ni = (int)(unsigned)__builtin_bit_cast(unsigned long long, y);
-    double r = fma(-n, kLn2Step256Hi, z);
-    r = fma(-n, kLn2Step256Lo, r);
+    const double y = fma(z, -kC, kShift);
+    const double m = y - kShift;
+    const int mi = (int)(unsigned)__builtin_bit_cast(unsigned long long, y);
+    double r = fma(m, kLn2Step256Hi, z);
+    r = fma(m, kLn2Step256Lo, r);
     double p = fma(r, 1.0 / 24.0, -1.0 / 6.0);
     p = fma(p, r, 0.5);
     p = fma(p, r, -1.0);
     const double q = p * r;                       // exp(-r) - 1
-    const double t = tab[ni & (kExpTab - 1)];
-    return __builtin_amdgcn_ldexp(fma(t, q, t), -(ni >> 8));
+    const double t = tab[mi & (kExpTab - 1)];
+    return __builtin_amdgcn_ldexp(fma(t, q, t), mi >> 8);
 }
 
 // FP64 pairs of nodes [sb, se) with the lane's TPL targets.  Per pair (kappa > 0) about 50
