@@ -543,7 +543,7 @@ def main():
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU (the path runs on one device); --gpus must be 1"}))
         sys.exit(2)
 
     def progress(msg):
@@ -552,7 +552,7 @@ def main():
     prob = workload(args)
     progress(f"workload: {prob.nv} sites, {prob.nf} triangles")
     pool_mols = None
-    # the box gives one GPU's job a share of 16 host cores
+    # a one-GPU job gets a share of 16 host cores
     host_workers = max(1, min(16, len(os.sched_getaffinity(0))))
     if args.serve_requests > 0:
         pool_mols = load_or_build_pool(args.serve_pool_cache, args.serve_pool, args.serve_min_atoms,
