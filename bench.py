@@ -382,10 +382,14 @@ def _make_molecule_job(indexed_job):
     return k, _make_molecule(*job)
 
 
-def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slots, n_check, tree_theta=0.0):
-    """Poisson request stream through the continuous-batching server (mixed precision; with
+def serve_bench(pool_mols, n_requests, seed, rate_factors, budget_bytes, max_slots, n_check, tree_theta=0.0,
+                fp64_all=False):
+    """Poisson request streams through the continuous-batching server (mixed precision; with
     tree_theta > 0 every request takes the treecode with the default degree, leaf and
-    batch).  Served results are checked against the FP64 oracle."""
+    batch): one stream per arrival-rate factor (the same requests, arrivals at that factor
+    times the saturated rate of a 16-request burst).  The first factor's results are checked
+    against the FP64 oracle (n_check requests) and, with fp64_all, every request's energy
+    against a GPU FP64 solve of its (molecule, eps1, kappa)."""
     from paper_1301_5914_amd import hobi
 
     rng = np.random.default_rng(seed)
@@ -398,16 +402,16 @@ def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slot
         return out
 
     ctx = hobi.Context(0)
-    sv = hobi.Server(ctx, hbm_budget_bytes=budget_bytes, max_slots=max_slots)
 
-    def submit(req):
+    def submit(sv, req):
         m, e1, kap = req
         return sv.submit(m, precision=hobi.HOBI_MIXED, eps1=e1, kappa=kap, max_iter=400, tree_theta=tree_theta)
 
     # saturated throughput: a burst submitted at once
+    sv = hobi.Server(ctx, hbm_budget_bytes=budget_bytes, max_slots=max_slots)
     burst = draw(min(16, n_requests))
     t0 = time.perf_counter()
-    ts = [submit(r) for r in burst]
+    ts = [submit(sv, r) for r in burst]
     left = set(ts)
     while left:
         for t in list(left):
@@ -415,31 +419,49 @@ def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slot
                 left.discard(t)
         time.sleep(0.0005)
     sat = len(burst) / (time.perf_counter() - t0)
-    rate = rate_factor * sat
-    reqs = draw(n_requests)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_requests))
-    sub_time, lat, results = {}, [], {}
-    i = 0
-    start = time.perf_counter()
-    while len(results) < n_requests:
-        now = time.perf_counter() - start
-        while i < n_requests and arrivals[i] <= now:
-            t = submit(reqs[i])
-            sub_time[t] = (time.perf_counter(), i)
-            i += 1
-        for t in [t for t in sub_time if t not in results]:
-            r = sv.poll(t, raise_errors=False)
-            if r is not None:
-                results[t] = r
-                lat.append(time.perf_counter() - sub_time[t][0])
-                if len(results) % 32 == 0:
-                    print(f"[bench] served {len(results)}/{n_requests}", file=sys.stderr, flush=True)
-        time.sleep(0.0002)
-    wall = time.perf_counter() - start
-    st = sv.stats()
     sv.close()
-    pairs = sum(r["stats"]["pairs_per_matvec"] * r["stats"]["iterations"] for r in results.values())
-    ok = sum(1 for r in results.values() if r["status"] == "HOBI_OK")
+    reqs = draw(n_requests)
+
+    def stream(rate_factor):
+        sv = hobi.Server(ctx, hbm_budget_bytes=budget_bytes, max_slots=max_slots)
+        rate = rate_factor * sat
+        arrivals = np.cumsum(np.random.default_rng([seed, int(round(rate_factor * 1000))]).exponential(
+            1.0 / rate, n_requests))
+        sub_time, lat, results = {}, [], {}
+        i = 0
+        start = time.perf_counter()
+        while len(results) < n_requests:
+            now = time.perf_counter() - start
+            while i < n_requests and arrivals[i] <= now:
+                t = submit(sv, reqs[i])
+                sub_time[t] = (time.perf_counter(), i)
+                i += 1
+            for t in [t for t in sub_time if t not in results]:
+                r = sv.poll(t, raise_errors=False)
+                if r is not None:
+                    results[t] = r
+                    lat.append(time.perf_counter() - sub_time[t][0])
+                    if len(results) % 32 == 0:
+                        print(f"[bench] rate {rate_factor}: served {len(results)}/{n_requests}", file=sys.stderr,
+                              flush=True)
+            time.sleep(0.0002)
+        wall = time.perf_counter() - start
+        st = sv.stats()
+        sv.close()
+        pairs = sum(r["stats"]["pairs_per_matvec"] * r["stats"]["iterations"] for r in results.values())
+        lat_ms = np.array(lat) * 1e3
+        summary = {
+            "rate_factor": rate_factor, "arrival_rate_per_s": rate,
+            "converged": sum(1 for r in results.values() if r["status"] == "HOBI_OK"),
+            "throughput_requests_per_s": n_requests / wall, "throughput_gpairs_per_s": pairs / wall / 1e9,
+            "latency_ms_p50": float(np.percentile(lat_ms, 50)), "latency_ms_p99": float(np.percentile(lat_ms, 99)),
+            "latency_ms_mean": float(lat_ms.mean()),
+            "mean_active_per_tick": st["mean_batch"], "ticks": st["ticks"], "peak_hbm_bytes": st["peak_bytes"]}
+        return summary, results, sub_time
+
+    first, results, sub_time = stream(rate_factors[0])
+    others = [stream(f)[0] for f in rate_factors[1:]]
+    ok = first["converged"]
     # checks against the FP64 oracle: the served solution's energy recomputed by the oracle,
     # and the oracle's residual rows b - A u of the served solution (random rows), on
     # n_check requests with distinct (molecule, eps1, kappa), smallest molecules first
@@ -476,16 +498,40 @@ def serve_bench(pool_mols, n_requests, seed, rate_factor, budget_bytes, max_slot
                        "oracle_residual_rows": resid})
         print(f"[bench] oracle check {len(checks)}/{len(picks)}: {m.nf} triangles, energy {checks[-1]['energy_rel_err']:.1e}, "
               f"residual rows {resid:.1e}", file=sys.stderr, flush=True)
-    lat_ms = np.array(lat) * 1e3
+    # every request's energy against a GPU FP64 solve of its (molecule, eps1, kappa)
+    fp64 = None
+    if fp64_all:
+        ref = {}
+        for t in sorted(results, key=lambda t: sub_time[t][1]):
+            m, e1, kap = reqs[sub_time[t][1]]
+            key = (id(m), e1, kap)
+            if key not in ref:
+                pb = hobi.Problem(ctx, m.xyz, m.nrm, m.tri, m.qpos, m.q, e1, m.eps2, kap, precision=hobi.HOBI_FP64,
+                                  max_iter=400, restart=400)
+                res = pb.solve(allow_noconv=True)
+                ref[key] = (res["energy"], res["status"] == "HOBI_OK")
+                pb.close()
+        errs = [abs(results[t]["energy"] / ref[(id(reqs[sub_time[t][1]][0]),) + reqs[sub_time[t][1]][1:]][0] - 1)
+                for t in results if results[t]["status"] == "HOBI_OK"]
+        fp64 = {"requests": len(errs), "combinations": len(ref),
+                "fp64_converged": sum(1 for v in ref.values() if v[1]),
+                "energy_rel_err_max": float(max(errs)), "energy_rel_err_median": float(np.median(errs)),
+                "what": "|E_served / E_fp64 - 1| for every served request, E_fp64 a GPU FP64 solve (rtol 1e-6) "
+                        "of the request's (molecule, eps1, kappa)"}
     sizes = [m.nf for m in pool_mols]
     return {
-        "requests": n_requests, "tree_theta": tree_theta, "converged": ok, "arrival_rate_per_s": rate,
-        "saturated_rate_per_s": sat, "rate_factor": rate_factor,
-        "throughput_requests_per_s": n_requests / wall, "throughput_gpairs_per_s": pairs / wall / 1e9,
-        "latency_ms_p50": float(np.percentile(lat_ms, 50)), "latency_ms_p99": float(np.percentile(lat_ms, 99)),
-        "latency_ms_mean": float(lat_ms.mean()),
-        "mean_active_per_tick": st["mean_batch"], "ticks": st["ticks"], "peak_hbm_bytes": st["peak_bytes"],
+        "requests": n_requests, "tree_theta": tree_theta, "converged": ok,
+        "arrival_rate_per_s": first["arrival_rate_per_s"],
+        "saturated_rate_per_s": sat, "rate_factor": first["rate_factor"],
+        "throughput_requests_per_s": first["throughput_requests_per_s"],
+        "throughput_gpairs_per_s": first["throughput_gpairs_per_s"],
+        "latency_ms_p50": first["latency_ms_p50"], "latency_ms_p99": first["latency_ms_p99"],
+        "latency_ms_mean": first["latency_ms_mean"],
+        "mean_active_per_tick": first["mean_active_per_tick"], "ticks": first["ticks"],
+        "peak_hbm_bytes": first["peak_hbm_bytes"],
         "budget_bytes": budget_bytes,
+        "other_rates": others,
+        "fp64_all": fp64,
         "pool": {"molecules": len(pool_mols), "triangles_min": int(min(sizes)), "triangles_max": int(max(sizes))},
         "oracle_checks": {
             "requests": len(checks),
@@ -524,7 +570,11 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=8, help="distinct molecules the stream draws from")
     ap.add_argument("--serve-min-atoms", type=int, default=50)
     ap.add_argument("--serve-max-atoms", type=int, default=1000)
-    ap.add_argument("--serve-rate", type=float, default=0.7, help="arrival rate / saturated throughput")
+    ap.add_argument("--serve-rate", default="0.7",
+                    help="arrival rate / saturated throughput; a comma-separated list runs one stream per factor "
+                         "(the first is the reported one, the others go to serving.other_rates)")
+    ap.add_argument("--serve-fp64-all", action="store_true",
+                    help="check every served request's energy against a GPU FP64 solve of its problem")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-checks", type=int, default=16, help="served requests checked against the oracle")
@@ -686,9 +736,10 @@ def main():
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = src.numel() * 4
     if pool_mols is not None:
-        out["serving"] = serve_bench(pool_mols, args.serve_requests, 5, args.serve_rate,
+        out["serving"] = serve_bench(pool_mols, args.serve_requests, 5,
+                                     [float(f) for f in args.serve_rate.split(",")],
                                      int(args.serve_budget_gb * (1 << 30)), args.serve_slots, args.serve_checks,
-                                     tree_theta=args.serve_tree_theta)
+                                     tree_theta=args.serve_tree_theta, fp64_all=args.serve_fp64_all)
         full = (args.serve_requests >= 512 and args.serve_pool >= 16 and args.serve_max_atoms >= 3000)
         out["serving"]["reduced"] = not full
         if not full:
