@@ -311,6 +311,39 @@ def test_bench_workload_L6_energy(ctx, l6):
     assert abs(r64["energy"] / E - 1) <= 2e-4
 
 
+def test_config2_convergence_levels(ctx):
+    """Config 2 on the GPU, icosphere L3-L6 in FP64 and mixed precision, solved to rtol 1e-9
+    (FP64) and 1e-7 (mixed): e_phi, e_dphi (max error at the vertices over the max of the
+    exact values, Section 3.1) and the energy error against the Kirkwood series, and their
+    orders in h (h halves per level).  The orders stay near 2 (the oracle's L1-L4 run gives
+    1.93 / 1.84 / 2.00 from L3 to L4); mixed precision follows FP64 until its matvec noise
+    (about 1e-7 of a row) is reached."""
+    a = 4.0
+    errs = {}
+    for lvl in (3, 4, 5, 6):
+        p = inputs.kirkwood_offcenter(lvl)
+        phi, dphi = KW.surface_values(p.xyz, p.qpos, p.q, a, p.eps1, p.eps2, p.kappa)
+        E = KW.solvation_energy(p.qpos, p.q, a, p.eps1, p.eps2, p.kappa)
+        for prec, rtol in ((hobi.HOBI_FP64, 1e-9), (hobi.HOBI_MIXED, 1e-7)):
+            r = hobi.Problem.from_inputs(ctx, p, precision=prec, rtol=rtol, max_iter=400, restart=400).solve(
+                allow_noconv=prec == hobi.HOBI_MIXED)
+            errs[(lvl, prec)] = (KW.rel_max_error(r["phi"], SCALE * phi), KW.rel_max_error(r["dphi"], SCALE * dphi),
+                                 abs(r["energy"] / E - 1), r["stats"]["iterations"])
+    print("\n| level | precision | iterations | e_phi | e_dphi | energy | order phi | order dphi | order E |", flush=True)
+    for prec, name in ((hobi.HOBI_FP64, "FP64"), (hobi.HOBI_MIXED, "mixed")):
+        for lvl in (3, 4, 5, 6):
+            e = errs[(lvl, prec)]
+            o = ["", "", ""] if lvl == 3 else [f"{KW.order(2, 1, errs[(lvl - 1, prec)][k], e[k]):.2f}" for k in range(3)]
+            print(f"| L{lvl} | {name} | {e[3]} | {e[0]:.3e} | {e[1]:.3e} | {e[2]:.3e} | {o[0]} | {o[1]} | {o[2]} |",
+                  flush=True)
+    for lvl in (4, 5, 6):
+        f, c = errs[(lvl, hobi.HOBI_FP64)], errs[(lvl - 1, hobi.HOBI_FP64)]
+        assert KW.order(2, 1, c[0], f[0]) > 1.6 and KW.order(2, 1, c[1], f[1]) > 1.6, lvl
+        assert KW.order(2, 1, c[2], f[2]) > 1.8, lvl
+        m = errs[(lvl, hobi.HOBI_MIXED)]
+        assert abs(m[0] / f[0] - 1) < 0.05 and abs(m[2] / f[2] - 1) < 0.05, lvl
+
+
 @pytest.fixture(scope="module")
 def mol500():
     print("generating the 500-atom surface", flush=True)
