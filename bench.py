@@ -73,6 +73,14 @@ def workload(args):
     return inputs.kirkwood_offcenter(args.level)
 
 
+def surface_quality(prob):
+    """The surface's smallest triangle angle, connected components and Euler characteristic
+    (V - E + F: 2 per sphere-like component, 0 for a torus-like one)."""
+    from paper_1301_5914_amd import inputs
+    amin, comps, euler = inputs.mesh_quality(prob.xyz, prob.tri)
+    return {"min_angle_deg": round(amin, 2), "components": comps, "euler_characteristic": euler}
+
+
 def workload_name(args, prob):
     if args.mesh:
         return f"surface loaded from {prob.name} ({args.mesh_label or 'saved surface'}), {prob.nf} triangles"
@@ -671,7 +679,8 @@ def main():
                    "nv": prob.nv, "nf": prob.nf, "nc": prob.nc, "nodes": n_nodes, "pairs_per_matvec": pairs_mv,
                    "method": args.method,
                    "kappa": prob.kappa, "eps1": prob.eps1, "eps2": prob.eps2, "rtol": 1e-6,
-                   "precision": args.precision},
+                   "precision": args.precision,
+                   "surface": surface_quality(prob)},
         "gmres_iterations": results[-1]["stats"]["iterations"],
         "gmres_converged": bool(results[-1]["stats"]["converged"]),
         "true_residual": results[-1]["stats"]["true_residual"],
