@@ -241,7 +241,8 @@ hobi_status hobi_energy(hobi_problem pb, const double* u, int32_t on_device,
  * rule's error grows, and a point on the surface is not a valid argument.
  * Synchronous: returns when the outputs are written.  The work space it allocates on the
  * first call (and on larger calls) stays with the problem until destroy.
- * Errors: HOBI_E_ARG (NULL u, NULL points with np > 0, np < 0, too many points),
+ * Errors: HOBI_E_ARG (NULL u, NULL points with np > 0, np < 0, too many points, points so
+ * far from the surface that kappa times their distance from it could reach 2.5e6),
  * HOBI_E_NUMERIC (non-finite point), HOBI_E_OOM, HOBI_E_HIP. */
 hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int32_t np,
                        const double* points, double* phi, double* field, double* reac,

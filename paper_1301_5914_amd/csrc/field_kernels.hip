@@ -143,11 +143,13 @@ __global__ __launch_bounds__(kBlock) void field_f32_kernel(const float* __restri
                                   partial + (size_t)w * (kParts * kSlot), kSlot);
 }
 
-// FP64 sums (unscaled frame), the FP64 pair kernel's f-functions.
+// FP64 sums (unscaled frame) with the FP64 pair kernel's exponential (etab: the workgroup's
+// table, fill_exp_table; not read when KAPPA0) and closed-form f-functions.
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void field_f64_wave(const double* __restrict__ pts, int np_pad,
-                                               const NodeD* __restrict__ nodes, double kappa, int base, int n0,
-                                               int n1, double* __restrict__ prow, int slot) {
+                                               const NodeD* __restrict__ nodes, double kappa,
+                                               const double* __restrict__ etab, int base, int n0, int n1,
+                                               double* __restrict__ prow, int slot) {
     const int lane = (int)(threadIdx.x % kWave);
     double tx[TPL], ty[TPL], tz[TPL], a[kParts][TPL];
 #pragma unroll
@@ -178,10 +180,13 @@ __device__ __forceinline__ void field_f64_wave(const double* __restrict__ pts, i
                 c2 = nd.pa;
                 c1 = pa3 * q;
             } else {
-                double f0, f1, f2;
-                f012_pair_f64(kappa * (r2 * rinv), f0, f1, f2);
+                const double z = kappa * (r2 * rinv);
+                const double e = exp_neg_tab_f64(z, etab);
+                const double zp1 = z + 1.0;
+                const double f1 = fma(-e, zp1, 1.0);                          // 1 - e (1 + z)
+                const double f2 = fma(-e, fma(zp1, zp1 + 1.0, 1.0), 3.0);     // 3 - e (3 + 3z + z^2)
                 c2 = fma(nd.pb, f1, nd.pa);
-                a[0][k] = fma(rinv, fma(q, c2, nd.g * f0), a[0][k]);
+                a[0][k] = fma(rinv, fma(q, c2, fma(-e, nd.g, nd.g)), a[0][k]);   // Gamma (1 - e) = Gamma f0
                 c1 = fma(f1, nd.g, fma(nd.pb, f2, pa3) * q);
             }
             const double gn = rinv3 * c2, gd = -rinv3 * c1;
@@ -199,15 +204,16 @@ __device__ __forceinline__ void field_f64_wave(const double* __restrict__ pts, i
 
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void field_f64_narrow(int live, const double* __restrict__ pts, int np_pad,
-                                                 const NodeD* __restrict__ nodes, double kappa, int base, int n0,
-                                                 int n1, double* __restrict__ prow, int slot) {
+                                                 const NodeD* __restrict__ nodes, double kappa,
+                                                 const double* __restrict__ etab, int base, int n0, int n1,
+                                                 double* __restrict__ prow, int slot) {
     if constexpr (TPL > 1) {
         if (live <= kWave * TPL / 2) {
-            field_f64_narrow<TPL / 2, KAPPA0>(live, pts, np_pad, nodes, kappa, base, n0, n1, prow, slot);
+            field_f64_narrow<TPL / 2, KAPPA0>(live, pts, np_pad, nodes, kappa, etab, base, n0, n1, prow, slot);
             return;
         }
     }
-    field_f64_wave<TPL, KAPPA0>(pts, np_pad, nodes, kappa, base, n0, n1, prow, slot);
+    field_f64_wave<TPL, KAPPA0>(pts, np_pad, nodes, kappa, etab, base, n0, n1, prow, slot);
 }
 
 template <int TPL, bool KAPPA0>
@@ -215,13 +221,15 @@ __global__ __launch_bounds__(kBlock) void field_f64_kernel(const double* __restr
                                                            const NodeD* __restrict__ nodes, double kappa,
                                                            const int* __restrict__ gstart, int slots, int workers,
                                                            double* __restrict__ partial) {
+    __shared__ double etab[kExpTab];
+    if constexpr (!KAPPA0) fill_exp_table(etab);
     const int w = xcd_logical_block() * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     if (w >= workers) return;
     constexpr int kSlot = kWave * TPL;
     const int g = w / slots, s = w - g * slots;
     const const_as<int>* cg = as_constant(gstart);
     const int base = s * kSlot;
-    field_f64_narrow<TPL, KAPPA0>(np - base, pts, np_pad, nodes, kappa, base, cg[g], cg[g + 1],
+    field_f64_narrow<TPL, KAPPA0>(np - base, pts, np_pad, nodes, kappa, etab, base, cg[g], cg[g + 1],
                                   partial + (size_t)w * (kParts * kSlot), kSlot);
 }
 
@@ -307,7 +315,8 @@ __device__ __forceinline__ void far_field_f32_narrow(int live, const float* __re
 
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void far_field_f64_wave(const double* __restrict__ pts, int np_pad,
-                                                   const ProxyD* __restrict__ prox, int P, double kappa, int base,
+                                                   const ProxyD* __restrict__ prox, int P, double kappa,
+                                                   const double* __restrict__ etab, int base,
                                                    double* __restrict__ prow, int slot) {
     const int lane = (int)(threadIdx.x % kWave);
     double tx[TPL], ty[TPL], tz[TPL], a[kParts][TPL];
@@ -335,7 +344,7 @@ __device__ __forceinline__ void far_field_f64_wave(const double* __restrict__ pt
                 a[0][k] = fma(rinv, c, a[0][k]);
             } else {
                 const double z = kappa * (r2 * rinv);
-                const double e = exp_neg_f64(z);
+                const double e = exp_neg_tab_f64(z, etab);
                 a[0][k] = fma(rinv, fma(e, pr.qk, pr.q0), a[0][k]);
                 c = fma(e * (1.0 + z), pr.qk, pr.q0);
             }
@@ -354,15 +363,16 @@ __device__ __forceinline__ void far_field_f64_wave(const double* __restrict__ pt
 
 template <int TPL, bool KAPPA0>
 __device__ __forceinline__ void far_field_f64_narrow(int live, const double* __restrict__ pts, int np_pad,
-                                                     const ProxyD* __restrict__ prox, int P, double kappa, int base,
+                                                     const ProxyD* __restrict__ prox, int P, double kappa,
+                                                     const double* __restrict__ etab, int base,
                                                      double* __restrict__ prow, int slot) {
     if constexpr (TPL > 1) {
         if (live <= kWave * TPL / 2) {
-            far_field_f64_narrow<TPL / 2, KAPPA0>(live, pts, np_pad, prox, P, kappa, base, prow, slot);
+            far_field_f64_narrow<TPL / 2, KAPPA0>(live, pts, np_pad, prox, P, kappa, etab, base, prow, slot);
             return;
         }
     }
-    far_field_f64_wave<TPL, KAPPA0>(pts, np_pad, prox, P, kappa, base, prow, slot);
+    far_field_f64_wave<TPL, KAPPA0>(pts, np_pad, prox, P, kappa, etab, base, prow, slot);
 }
 
 // One wave per treecode work item {slot, far, cluster, -} of the points; the item's partial
@@ -394,6 +404,8 @@ __global__ __launch_bounds__(kBlock) void field_tree_f64_kernel(const int4* __re
                                                                 const int2* __restrict__ clu_range,
                                                                 const ProxyD* __restrict__ prox, int P,
                                                                 double* __restrict__ partial) {
+    __shared__ double etab[kExpTab];
+    if constexpr (!KAPPA0) fill_exp_table(etab);
     const int w = xcd_logical_block() * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     if (w >= nitems) return;
     constexpr int kSlot = kWave * TPL;
@@ -401,11 +413,11 @@ __global__ __launch_bounds__(kBlock) void field_tree_f64_kernel(const int4* __re
     const int base = it.x * kSlot;
     double* prow = partial + (size_t)w * (kParts * kSlot);
     if (it.y == 0)
-        field_f64_narrow<TPL, KAPPA0>(np - base, pts, np_pad, nodes, kappa, base, as_constant(clu_range)[it.z].x,
-                                      as_constant(clu_range)[it.z].y, prow, kSlot);
+        field_f64_narrow<TPL, KAPPA0>(np - base, pts, np_pad, nodes, kappa, etab, base,
+                                      as_constant(clu_range)[it.z].x, as_constant(clu_range)[it.z].y, prow, kSlot);
     else
-        far_field_f64_narrow<TPL, KAPPA0>(np - base, pts, np_pad, prox + (size_t)it.z * P, P, kappa, base, prow,
-                                          kSlot);
+        far_field_f64_narrow<TPL, KAPPA0>(np - base, pts, np_pad, prox + (size_t)it.z * P, P, kappa, etab, base,
+                                          prow, kSlot);
 }
 
 // 64 points per block of 256 threads: wave k sums the point's rows of node groups k, k + 4,

@@ -998,6 +998,19 @@ hobi_status hobi_field(hobi_problem pb, const double* u, int32_t on_device, int3
             lo[k] = std::min(lo[k], points[3 * i + k]);
             hi[k] = std::max(hi[k], points[3 * i + k]);
         }
+    if (d.kappa > 0.0) {
+        // kappa r must stay below kExpTabMaxZ for every (point, node) pair (the FP64 sums'
+        // table-driven exponential): r is at most the distance from the surface's box centre
+        // to the points' box's farthest corner plus half the surface's box diagonal
+        double far2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double a = std::max(std::fabs(hi[k] - d.center[k]), std::fabs(lo[k] - d.center[k]));
+            far2 += a * a;
+        }
+        if (!(d.kappa * (std::sqrt(far2) + 0.5 * d.extent) < 0.5 * kExpTabMaxZ))
+            return fail(c, HOBI_E_ARG, "kappa times the points' distance from the surface must stay below %g",
+                        0.5 * kExpTabMaxZ);
+    }
     FieldWork& f = pb->field;
     f.np = np;
     f.np_pad = tree ? round_up(np, kFieldTreeBatch) : pl.slots * pl.slot;

@@ -310,29 +310,6 @@ __device__ __forceinline__ void gather_site(int j, const double* __restrict__ u,
     write_strengths(j, sc * u[nv + j], sc * u[j], node64, node32, mixed, eps, s32);
 }
 
-// f0 = 1 - e^-z, f1 = 1 - e^-z (1 + z), f2 = 3 - e^-z (3 + 3z + z^2) in FP64: the closed forms
-// with the exponential of hobi_device.h, or their power series where z < kSeriesZ64 (Horner
-// in z, terms k = 1..12 of f0 and k = 2..12 of f1, f2; truncation below 1e-17 relative).
-__device__ __forceinline__ void f012_pair_f64(double z, double& f0, double& f1, double& f2) {
-    const double e = exp_neg_f64(z);
-    f0 = 1.0 - e;
-    f1 = fma(-e, 1.0 + z, 1.0);
-    f2 = fma(-e, fma(z, z + 3.0, 3.0), 3.0);
-    if (z < kSeriesZ64) {
-        constexpr SeriesTable T = series_table();
-        double s0 = T.f0[12], s1 = T.f1[12], s2 = T.f2[12];
-#pragma unroll
-        for (int j = 11; j >= 2; --j) {
-            s0 = fma(s0, z, T.f0[j]);
-            s1 = fma(s1, z, T.f1[j]);
-            s2 = fma(s2, z, T.f2[j]);
-        }
-        f0 = fma(s0, z, T.f0[1]) * z;
-        f1 = s1 * z * z;
-        f2 = s2 * z * z;
-    }
-}
-
 // exp(-z) for 0 <= z < kExpTabMaxZ in FP64 by Tang's table-driven method (P. T. P. Tang, ACM
 // TOMS 15, 1989), in the negated reduction: m = rint(-256 z log2(e)) = 256 k + j
 // (0 <= j < 256, k <= 0), r = z + m ln2/256 with |r| <= ln2/512 (Cody-Waite: ln2/256 split

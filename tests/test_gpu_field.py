@@ -166,3 +166,14 @@ def test_field_errors_and_empty(ctx):
     # all outputs NULL is allowed
     assert L.hobi_field(g.handle, hobi._P(u.ctypes.data), 0, 2, hobi._dptr(pts), None, None, None, None,
                         None) == 0
+    # points so far away that kappa r could leave the FP64 exponential's range (2.5e6 here is
+    # 2e7 A at kappa = 0.1257): rejected before any field sum; at kappa = 0 they are fine
+    far = np.array([[0.0, 0.0, 0.0], [2.1e7, 0.0, 0.0]])
+    assert L.hobi_field(g.handle, hobi._P(u.ctypes.data), 0, 2, hobi._dptr(far), None, None, None, None,
+                        None) == 1
+    near = np.array([[0.0, 0.0, 0.0], [1.9e7, 0.0, 0.0]])
+    assert L.hobi_field(g.handle, hobi._P(u.ctypes.data), 0, 2, hobi._dptr(near), None, None, None, None,
+                        None) == 0
+    g0 = hobi.Problem(ctx, p.xyz, p.nrm, p.tri, p.qpos, p.q, p.eps1, p.eps2, 0.0)
+    assert L.hobi_field(g0.handle, hobi._P(u.ctypes.data), 0, 2, hobi._dptr(far), None, None, None, None,
+                        None) == 0
