@@ -36,12 +36,13 @@ struct GridPlan {
 // that the workers make about kPairPasses passes of the waves the device holds at once:
 // short workers let the hardware's dispatch balance the load to the end of the launch (one
 // long pass ends with many SIMDs idle), while each partial row is written once and read once
-// by the combine step, so a group keeps at least kMinGroupNodes nodes.  The blocks of one
+// by the combine step, so a group keeps at least kMinGroupNodes nodes (one 64-node block: a
+// wave then always has a whole block to walk).  The blocks of one
 // row index run side by side on one XCD and read the same nodes from its L2 at about the
 // same time.  The split depends on the problem and the device only, and so does the order of
 // every sum (results are reproducible bit for bit).
 constexpr int kPairPasses = 16;
-constexpr int kMinGroupNodes = 256;
+constexpr int kMinGroupNodes = 64;
 struct PairPlan {
     int tpl;            // targets per lane
     int slot;           // targets per slot: 64 * tpl
