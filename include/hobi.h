@@ -80,10 +80,13 @@ typedef struct hobi_params {
     int32_t restart;    /* GMRES(m) restart length, default 200                             */
     int32_t precision;  /* HOBI_FP64 or HOBI_MIXED, default HOBI_FP64                       */
     int32_t method;     /* HOBI_HIGHER_ORDER (default) or HOBI_LOWER_ORDER                  */
-    int32_t diag_scaling; /* 1 (default): GMRES runs on the second-kind form with both       */
-                        /* diagonal blocks scaled to the identity (unknowns scaled by        */
-                        /* 1/(1/2 (1+eps)) and 1/(1/2 (1+1/eps)); same solution, the monitored */
-                        /* residual is still ||b - A u|| / ||b||); 0: on A u = b as written  */
+    int32_t diag_scaling; /* right preconditioner of GMRES (same solution; the monitored     */
+                        /* residual is still ||b - A u|| / ||b||).  2 (default): Jacobi, the  */
+                        /* inverse of A's own diagonal (1/2 (1+eps) and 1/2 (1+1/eps) minus  */
+                        /* each vertex's singular terms on its own unknowns; for the lower-  */
+                        /* order method, which has none, as 1).  1: the two row blocks'      */
+                        /* constants 1/(1/2 (1+eps)) and 1/(1/2 (1+1/eps)).  0: A u = b as   */
+                        /* written                                                           */
     /* Treecode form of the regular (dense) sum, either method.  0 (default):
      * the dense sum.  > 0: a cluster-particle treecode with opening parameter tree_theta.
      * The quadrature nodes in order are cut into leaves of tree_leaf nodes, joined pairwise

@@ -225,6 +225,26 @@ def _integral_rows(st, phi, dphi, kappa, eps, rows, workers):
     return [v for p in parts for v in p]
 
 
+def diagonal(st: Setup, kappa, eps):
+    """The diagonal of A (eqdbef3/eqdbef4): 1/2 (1 + eps) and 1/2 (1 + 1/eps) minus each vertex's
+    singular terms on its own unknowns (K2 on phi_i in row i, K3 on dphi_i in row i + Nv, over
+    its incident triangles with the Duffy rule).  The regular sum does not touch a vertex's
+    own unknowns: they enter only the nodes of its incident triangles, which are singular."""
+    nv = st.nv
+    d = np.concatenate([np.full(nv, 0.5 * (1.0 + eps)), np.full(nv, 0.5 * (1.0 + 1.0 / eps))])
+    for i in range(nv):
+        x, nx = st.xyz[i], st.nrm[i]
+        for j in st.incident[i]:
+            k = int(np.nonzero(st.tri[j] == i)[0][0])
+            _, K2, K3, _ = kernels(x, nx, st.ys[j, k], st.nys[j, k], kappa, eps)
+            W = st.ws[j, k] * st.Ls[:, 0]           # weight of the target's own (local 0) unknown
+            d[i] -= np.sum(W * K2)
+            d[nv + i] -= np.sum(W * K3)
+    # a non-positive entry (not met on the surfaces tried) is replaced by the row block's constant
+    const = np.concatenate([np.full(nv, 0.5 * (1.0 + eps)), np.full(nv, 0.5 * (1.0 + 1.0 / eps))])
+    return np.where(np.isfinite(d) & (d > 0.0), d, const)
+
+
 def matvec(st: Setup, u, kappa, eps, rows=None, workers: int = 1):
     """y = A u (all 2Nv rows), or the pair (rows i, i+Nv) for each i in ``rows``."""
     nv = st.nv

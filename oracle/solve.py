@@ -11,13 +11,14 @@ import numpy as np
 
 from . import COULOMB_KCAL, FOUR_PI
 from .gmres import diagonal_scaling, gmres, gmres_scaled
-from .operator import check_charges_inside, matvec, setup, solvation_energy, sources
+from .operator import check_charges_inside, diagonal, matvec, setup, solvation_energy, sources
 
 
 def solve(xyz, nrm, tri, qpos, q, eps1=1.0, eps2=80.0, kappa=0.1257,
-          rtol=1e-6, restart=200, max_iter=200, st=None, workers=1, diag_scaling=True):
-    """diag_scaling: GMRES on the system with both diagonal blocks scaled to the identity
-    (gmres_scaled, the default) or on A u = b as written."""
+          rtol=1e-6, restart=200, max_iter=200, st=None, workers=1, diag_scaling=2):
+    """diag_scaling, the right preconditioner of GMRES: 2 (default) Jacobi, the inverse of A's
+    own diagonal (operator.diagonal); 1 (or True) the two row blocks' constants; 0 (or False)
+    none, A u = b as written."""
     eps = eps2 / eps1
     if st is None:
         st = setup(xyz, nrm, tri)
@@ -28,7 +29,8 @@ def solve(xyz, nrm, tri, qpos, q, eps1=1.0, eps2=80.0, kappa=0.1257,
     b = np.concatenate([S1, S2])
     A = lambda v: matvec(st, v, kappa, eps, workers=workers)
     if diag_scaling:
-        u, its, rel, conv = gmres_scaled(A, b, diagonal_scaling(st.nv, eps), rtol, restart, max_iter)
+        dinv = 1.0 / diagonal(st, kappa, eps) if int(diag_scaling) == 2 else diagonal_scaling(st.nv, eps)
+        u, its, rel, conv = gmres_scaled(A, b, dinv, rtol, restart, max_iter)
     else:
         u, its, rel, conv = gmres(A, b, rtol, restart, max_iter)
     true_rel = float(np.linalg.norm(b - matvec(st, u, kappa, eps, workers=workers)) / np.linalg.norm(b))

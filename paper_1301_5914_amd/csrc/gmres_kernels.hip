@@ -39,22 +39,48 @@ __global__ void multi_axpy_kernel(const double* __restrict__ V, size_t ld, int n
     multi_axpy_elem(V, ld, nvec, coef, sign, w, i);
 }
 
-__global__ void diag_scale_kernel(const double* __restrict__ in, double* __restrict__ out, int nv, double s1,
-                                  double s2) {
+__global__ void diag_scale_kernel(const double* __restrict__ in, double* __restrict__ out, int n,
+                                  const double* __restrict__ dinv) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 2 * nv) return;
-    diag_scale_elem(in, out, nv, s1, s2, i);
+    if (i >= n) return;
+    diag_scale_elem(in, out, dinv, i);
 }
 
-// x[i] += s(i) * sum_j coef[j] V[j][i]
+// x[i] += dinv[i] * sum_j coef[j] V[j][i]
 __global__ void multi_axpy_scaled_kernel(const double* __restrict__ V, size_t ld, int nvec,
-                                         const double* __restrict__ coef, double* __restrict__ x, int nv,
-                                         double s1, double s2) {
+                                         const double* __restrict__ coef, double* __restrict__ x, int n,
+                                         const double* __restrict__ dinv) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 2 * nv) return;
+    if (i >= n) return;
     double acc = 0.0;
     for (int j = 0; j < nvec; ++j) acc = fma(coef[j], V[ld * j + i], acc);
-    x[i] = fma(i < nv ? s1 : s2, acc, x[i]);
+    x[i] = fma(dinv[i], acc, x[i]);
+}
+
+// The inverse diagonal of the right preconditioner.  mode 1: the constants 1 / (1/2 (1 + eps))
+// and 1 / (1/2 (1 + 1/eps)) of the two row blocks.  mode 2 (Jacobi): the inverse of A's own
+// diagonal, those constants' inverses minus the vertex's singular terms on its own unknowns
+// (entry b = 0 of each incident entry's coefficients: K2 on phi_i in row i, K3 on dphi_i in row
+// nv + i), summed in the combine step's order; a non-positive or non-finite value (not met on
+// the surfaces tried) falls back to the constant.  The lower-order method has no singular
+// terms, so its mode 2 is mode 1.
+__global__ void scaling_kernel(int nv, const int* __restrict__ inc_off, const int* __restrict__ inc_ent,
+                               const double* __restrict__ coef, double eps, int jacobi, double* __restrict__ dinv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    const double a0 = 0.5 * (1.0 + eps), b0 = 0.5 * (1.0 + 1.0 / eps);
+    double a = a0, b = b0;
+    if (jacobi) {
+        for (int e = inc_off[i]; e < inc_off[i + 1]; ++e) {
+            const double* co = coef + 12 * (size_t)inc_ent[e];
+            a -= co[3];
+            b -= co[6];
+        }
+        if (!(a > 0.0) || !isfinite(a)) a = a0;
+        if (!(b > 0.0) || !isfinite(b)) b = b0;
+    }
+    dinv[i] = 1.0 / a;
+    dinv[nv + i] = 1.0 / b;
 }
 
 __global__ void scale_copy_kernel(const double* __restrict__ in, const double* __restrict__ denom,
@@ -122,15 +148,21 @@ hipError_t launch_scale_copy(const double* in, const double* denom, double* out,
     return hipGetLastError();
 }
 
-hipError_t launch_diag_scale(const double* in, double* out, int nv, double s1, double s2, hipStream_t s) {
-    hipLaunchKernelGGL(diag_scale_kernel, dim3(nblk(2 * nv, kT)), dim3(kT), 0, s, in, out, nv, s1, s2);
+hipError_t launch_diag_scale(const double* in, double* out, int n, const double* dinv, hipStream_t s) {
+    hipLaunchKernelGGL(diag_scale_kernel, dim3(nblk(n, kT)), dim3(kT), 0, s, in, out, n, dinv);
     return hipGetLastError();
 }
 
-hipError_t launch_multi_axpy_scaled(const double* V, size_t ld, int nvec, const double* coef, double* x, int nv,
-                                    double s1, double s2, hipStream_t s) {
-    hipLaunchKernelGGL(multi_axpy_scaled_kernel, dim3(nblk(2 * nv, kT)), dim3(kT), 0, s, V, ld, nvec, coef, x, nv,
-                       s1, s2);
+hipError_t launch_multi_axpy_scaled(const double* V, size_t ld, int nvec, const double* coef, double* x, int n,
+                                    const double* dinv, hipStream_t s) {
+    hipLaunchKernelGGL(multi_axpy_scaled_kernel, dim3(nblk(n, kT)), dim3(kT), 0, s, V, ld, nvec, coef, x, n, dinv);
+    return hipGetLastError();
+}
+
+hipError_t launch_scaling(const DeviceProblem& p, int mode, double* dinv, hipStream_t s) {
+    const bool jacobi = mode == 2 && p.method == HOBI_HIGHER_ORDER;
+    hipLaunchKernelGGL(scaling_kernel, dim3(nblk(p.nv, kT)), dim3(kT), 0, s, p.nv, p.inc_off, p.inc_ent, p.coef, p.eps,
+                       jacobi ? 1 : 0, dinv);
     return hipGetLastError();
 }
 

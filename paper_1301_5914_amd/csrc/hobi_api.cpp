@@ -222,10 +222,10 @@ hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
     if (!(bnorm > 0.0)) return std::isfinite(bnorm) ? HOBI_OK : fail(c, HOBI_E_NUMERIC, "non-finite rhs");
     int total = 0;
     const double rtol = pb->prm.rtol;
-    // right scaling (diag_scaling): Krylov space of A D^-1, iterate x = D^-1 y
+    // right scaling (diag_scaling): Krylov space of A D^-1, iterate x = D^-1 y, D the row
+    // blocks' constants (mode 1) or A's own diagonal (mode 2)
     const bool scaled = pb->prm.diag_scaling != 0;
-    double s1 = 1.0, s2 = 1.0;
-    gmres_scales(pb->d.eps, &s1, &s2);
+    if (scaled) HIPCHK(c, launch_scaling(pb->d, pb->prm.diag_scaling, pb->d.dinv, s));
     while (true) {
         // r = b - A x
         const double* r = b;
@@ -248,7 +248,7 @@ hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
             double* w = k.V + (size_t)(j + 1) * n;
             const double* vj = k.V + (size_t)j * n;
             if (scaled) {
-                HIPCHK(c, launch_diag_scale(vj, k.tmp, n / 2, s1, s2, s));
+                HIPCHK(c, launch_diag_scale(vj, k.tmp, n, pb->d.dinv, s));
                 vj = k.tmp;
             }
             if ((st = matvec_internal(pb, vj, w)) != HOBI_OK) return st;
@@ -277,7 +277,7 @@ hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
         }
         HIPCHK(c, launch_trisolve(k.H, m + 1, kk, k.g, k.yk, s));
         if (scaled)
-            HIPCHK(c, launch_multi_axpy_scaled(k.V, n, kk, k.yk, k.x, n / 2, s1, s2, s));
+            HIPCHK(c, launch_multi_axpy_scaled(k.V, n, kk, k.yk, k.x, n, pb->d.dinv, s));
         else
             HIPCHK(c, launch_multi_axpy(k.V, n, kk, k.yk, 1.0, k.x, n, s));
         if (stop) break;
@@ -325,7 +325,7 @@ void free_problem(hobi_problem pb) {
     DeviceProblem& d = pb->d;
     void* ptrs[] = {d.xyz, d.nrm, d.vxyz, d.tri, d.qpos, d.q, d.qsoa, d.patch, d.node64, d.node32, d.node_vid,
                     d.blk_range, d.w,
-                    d.tgt64, d.tgt32, d.inc_off, d.inc_ent, d.coef, d.rhs, d.partial, d.plan_tab,
+                    d.tgt64, d.tgt32, d.inc_off, d.inc_ent, d.coef, d.rhs, d.dinv, d.partial, d.plan_tab,
                     pb->d_vperm, pb->u_in, pb->y_out, pb->phi_reac, pb->e_dev, pb->d_err};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -503,7 +503,7 @@ hobi_status validate_params(hobi_ctx ctx, const hobi_params& p) {
         return fail(ctx, HOBI_E_ARG, "precision must be HOBI_FP64 or HOBI_MIXED");
     if (p.method != HOBI_HIGHER_ORDER && p.method != HOBI_LOWER_ORDER)
         return fail(ctx, HOBI_E_ARG, "method must be HOBI_HIGHER_ORDER or HOBI_LOWER_ORDER");
-    if (p.diag_scaling != 0 && p.diag_scaling != 1) return fail(ctx, HOBI_E_ARG, "diag_scaling must be 0 or 1");
+    if (p.diag_scaling < 0 || p.diag_scaling > 2) return fail(ctx, HOBI_E_ARG, "diag_scaling must be 0, 1 or 2");
     if (!(p.tree_theta >= 0) || !std::isfinite(p.tree_theta)) return fail(ctx, HOBI_E_ARG, "tree_theta must be >= 0");
     if (p.tree_degree < 1 || p.tree_degree > kTreeMaxDeg)
         return fail(ctx, HOBI_E_ARG, "tree_degree must be in 1..%d", kTreeMaxDeg);
@@ -548,7 +548,7 @@ void hobi_params_default(hobi_params* p) {
     p->restart = 200;
     p->precision = HOBI_FP64;
     p->method = HOBI_HIGHER_ORDER;
-    p->diag_scaling = 1;
+    p->diag_scaling = 2;
     p->tree_theta = 0.0;
     p->tree_degree = 5;
     p->tree_leaf = 256;
@@ -750,6 +750,7 @@ hobi_status problem_create_limited(hobi_ctx ctx, int32_t nv, const double* xyz, 
     PCHK(dalloc(&d.inc_ent, lower ? 1 : 3 * (size_t)nf));
     PCHK(dalloc(&d.coef, lower ? 1 : 36 * (size_t)nf));
     PCHK(dalloc(&d.rhs, 2 * (size_t)ns));
+    PCHK(dalloc(&d.dinv, 2 * (size_t)ns));
     PCHK(dalloc(&d.partial, d.partial_elems));
     PCHK(dalloc(&pb->d_vperm, ns));
     PCHK(dalloc(&pb->u_in, 2 * (size_t)ns));

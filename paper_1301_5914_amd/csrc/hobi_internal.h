@@ -114,6 +114,7 @@ struct DeviceProblem {
     int* inc_ent = nullptr;                 // [3 nf] entry = tri * 3 + local vertex
     double* coef = nullptr;                 // [3 nf][12] singular (Duffy) coefficients
     double* rhs = nullptr;                  // [2 nv] (S1, S2)
+    double* dinv = nullptr;                 // [2 nv] the right preconditioner's inverse diagonal
     // per-matvec work space
     double* partial = nullptr;              // pair sums: [workers][2][slot]; point sums: [chunks][nc_pad]
     int nv_pad = 0;
@@ -254,16 +255,14 @@ hipError_t launch_multi_axpy(const double* V, size_t ld, int nvec, const double*
 hipError_t launch_scale_copy(const double* in, const double* denom, double* out, int n,
                              hipStream_t s);
 hipError_t launch_sub(const double* a, const double* b, double* out, int n, hipStream_t s);
-// out[i] = s1 in[i] (i < nv), s2 in[i] (nv <= i < 2 nv)
-hipError_t launch_diag_scale(const double* in, double* out, int nv, double s1, double s2, hipStream_t s);
-// x[i] += s(i) sum_j coef[j] V[j][i], s(i) = s1 for i < nv, s2 for nv <= i < 2 nv
-hipError_t launch_multi_axpy_scaled(const double* V, size_t ld, int nvec, const double* coef, double* x, int nv,
-                                    double s1, double s2, hipStream_t s);
-// the right-scaling factors 1 / (1/2 (1 + eps)) and 1 / (1/2 (1 + 1/eps))
-inline void gmres_scales(double eps, double* s1, double* s2) {
-    *s1 = 1.0 / (0.5 * (1.0 + eps));
-    *s2 = 1.0 / (0.5 * (1.0 + 1.0 / eps));
-}
+// out[i] = dinv[i] in[i], i < n
+hipError_t launch_diag_scale(const double* in, double* out, int n, const double* dinv, hipStream_t s);
+// x[i] += dinv[i] sum_j coef[j] V[j][i], i < n
+hipError_t launch_multi_axpy_scaled(const double* V, size_t ld, int nvec, const double* coef, double* x, int n,
+                                    const double* dinv, hipStream_t s);
+// dinv [2 nv]: the inverse diagonal of the right preconditioner of diag_scaling mode 1 (the two
+// row blocks' constants) or 2 (A's own diagonal; mode 1 for the lower-order method)
+hipError_t launch_scaling(const DeviceProblem& p, int mode, double* dinv, hipStream_t s);
 hipError_t launch_givens(double* H, int ldh, int k, const double* h1, const double* h2,
                          const double* hnext, double* cs, double* sn, double* g,
                          double bnorm, double* res, hipStream_t s);

@@ -55,10 +55,10 @@ __device__ __forceinline__ void multi_axpy_elem(const double* __restrict__ V, si
     w[i] = fma(sign, acc, w[i]);
 }
 
-// out[i] = s(i) in[i], s = s1 on the first nv entries and s2 on the next nv
-__device__ __forceinline__ void diag_scale_elem(const double* __restrict__ in, double* __restrict__ out, int nv,
-                                                double s1, double s2, int i) {
-    out[i] = (i < nv ? s1 : s2) * in[i];
+// out[i] = dinv[i] in[i] (the inverse diagonal of the right preconditioner)
+__device__ __forceinline__ void diag_scale_elem(const double* __restrict__ in, double* __restrict__ out,
+                                                const double* __restrict__ dinv, int i) {
+    out[i] = dinv[i] * in[i];
 }
 
 __device__ __forceinline__ void scale_copy_elem(const double* __restrict__ in, double d, double* __restrict__ out,

@@ -209,7 +209,10 @@ hobi_status admit(hobi_server sv, Request& r) {
     SA(dalloc(&r.dpart, (size_t)kDotBlocks * (m + 1)));
     SA(dalloc(&r.x, n));
     SA(dalloc(&r.scal, 4));
-    if (r.prm.diag_scaling) SA(dalloc(&r.z, n));
+    if (r.prm.diag_scaling) {
+        SA(dalloc(&r.z, n));
+        SA(launch_scaling(d, r.prm.diag_scaling, d.dinv, s));
+    }
     SA(hipMemsetAsync(r.x, 0, sizeof(double) * n, s));
     SA(launch_dots(d.rhs, 0, 1, d.rhs, n, r.dpart, s));
     SA(launch_reduce(r.dpart, 1, r.scal, 1, s));
@@ -240,9 +243,7 @@ void finish(hobi_server sv, Request& r, bool converged) {
     if (r.k > 0) {
         if ((e = launch_trisolve(r.H, r.m + 1, r.k, r.g, r.yk, s)) == hipSuccess) {
             if (r.prm.diag_scaling) {
-                double s1, s2;
-                gmres_scales(r.pb->d.eps, &s1, &s2);
-                e = launch_multi_axpy_scaled(r.V, n, r.k, r.yk, r.x, r.nu, s1, s2, s);
+                e = launch_multi_axpy_scaled(r.V, n, r.k, r.yk, r.x, n, r.pb->d.dinv, s);
             } else {
                 e = launch_multi_axpy(r.V, n, r.k, r.yk, 1.0, r.x, n, s);
             }
@@ -363,7 +364,7 @@ hobi_status tick(hobi_server sv) {
         kd.sn = r.sn;
         kd.g = r.g;
         kd.res = sv->d_res + q;
-        kd.s1 = kd.s2 = 1.0;
+        kd.dinv = nullptr;
         kd.bnorm = r.bnorm;
         kd.n = n;
         kd.nu = r.nu;
@@ -381,7 +382,7 @@ hobi_status tick(hobi_server sv) {
         }
         if (r.prm.diag_scaling) {
             // the matvec of the scaled system takes D^-1 v_k (the single-problem path's scaling)
-            gmres_scales(d.eps, &kd.s1, &kd.s2);
+            kd.dinv = d.dinv;
             sd.u = r.z;
         }
         sd.tri = d.tri;

@@ -69,7 +69,8 @@ struct KrylovDesc {
     double *h1, *h2, *hn;   // the two passes' coefficients and the norm
     double *H, *cs, *sn, *g;
     double* res;            // the request's residual estimate |g[k+1]| / ||b||
-    double s1, s2, bnorm;
+    const double* dinv;     // the preconditioner's inverse diagonal (diag_scaling), else null
+    double bnorm;
     int n, nu, k, ldh;
     int off[kKrylovPhases];
 };

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kKrylovBlock) void batched_diag_kernel(const Krylov
         const int q = krylov_owner(kd, nreq, K_DIAG, it);
         const KrylovDesc& d = kd[q];
         const int i = (it - d.off[K_DIAG]) * kKrylovBlock + (int)threadIdx.x;
-        if (d.z && i < d.n) diag_scale_elem(d.vk, d.z, d.nu, d.s1, d.s2, i);
+        if (d.z && i < d.n) diag_scale_elem(d.vk, d.z, d.dinv, i);
     }
 }
 

@@ -202,7 +202,7 @@ class Problem:
 
     def __init__(self, ctx: Context, xyz, nrm, tri, qpos, q, eps1=1.0, eps2=80.0, kappa=0.1257,
                  rtol=1e-6, max_iter=200, restart=200, precision=HOBI_FP64, method=HOBI_HIGHER_ORDER,
-                 diag_scaling=1, tree_theta=0.0, tree_degree=5, tree_leaf=256, tree_batch=128):
+                 diag_scaling=2, tree_theta=0.0, tree_degree=5, tree_leaf=256, tree_batch=128):
         self.ctx = ctx
         xyz = _f64(xyz).reshape(-1, 3)
         nrm = _f64(nrm).reshape(-1, 3)
@@ -380,7 +380,7 @@ class Server:
         raise HobiError(st, msg.decode() if msg else "")
 
     def submit(self, prob, rtol=1e-6, max_iter=300, precision=HOBI_MIXED, eps1=None, eps2=None,
-               kappa=None, method=HOBI_HIGHER_ORDER, diag_scaling=1, tree_theta=0.0, tree_degree=5, tree_leaf=256,
+               kappa=None, method=HOBI_HIGHER_ORDER, diag_scaling=2, tree_theta=0.0, tree_degree=5, tree_leaf=256,
                tree_batch=128) -> int:
         xyz = _f64(prob.xyz).reshape(-1, 3)
         nrm = _f64(prob.nrm).reshape(-1, 3)

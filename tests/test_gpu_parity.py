@@ -110,17 +110,18 @@ def test_identity_when_dielectrics_match(ctx):
         np.testing.assert_array_equal(g.matvec(u), u)
 
 
-@pytest.mark.parametrize("scaled", [1, 0])
+@pytest.mark.parametrize("scaled", [2, 1, 0])
 def test_solve_fp64_fixed_iterations_matches_oracle(ctx, scaled):
-    """Same number of GMRES iterations on both sides: same Krylov iterate to 1e-12, on the
-    diagonally scaled system (default) and on A u = b as written."""
+    """Same number of GMRES iterations on both sides: same Krylov iterate to 1e-12, with the
+    Jacobi preconditioner (default: A's own diagonal, the singular self terms included), with
+    the row blocks' constant scaling and on A u = b as written."""
     p = inputs.kirkwood_offcenter(3)
     its = 4 if scaled else 6
     g = hobi.Problem.from_inputs(ctx, p, rtol=0.0, max_iter=its, restart=200, diag_scaling=scaled)
     r = g.solve(allow_noconv=True)
     assert r["status"] == "HOBI_E_NOCONV" and r["stats"]["iterations"] == its
     o = oracle_solve(p.xyz, p.nrm, p.tri, p.qpos, p.q, p.eps1, p.eps2, p.kappa, rtol=0.0,
-                     max_iter=its, diag_scaling=bool(scaled))
+                     max_iter=its, diag_scaling=scaled)
     assert o["iterations"] == its
     assert _rel_inf(r["phi"], o["phi"]) <= 1e-12
     assert _rel_inf(r["dphi"], o["dphi"]) <= 1e-12
@@ -132,12 +133,15 @@ def test_scaled_and_unscaled_gmres_reach_the_same_solution(ctx):
     tolerance, true residuals below it, the scaled form in fewer matvecs."""
     p = inputs.kirkwood_offcenter(3)
     r = {}
-    for scaled in (1, 0):
+    for scaled in (2, 1, 0):
         r[scaled] = hobi.Problem.from_inputs(ctx, p, rtol=1e-10, diag_scaling=scaled).solve()
         assert r[scaled]["stats"]["true_residual"] < 1e-10
-    print("iterations scaled / unscaled", r[1]["stats"]["iterations"], r[0]["stats"]["iterations"], flush=True)
+    print("iterations Jacobi / scaled / unscaled", r[2]["stats"]["iterations"], r[1]["stats"]["iterations"],
+          r[0]["stats"]["iterations"], flush=True)
     assert r[1]["stats"]["iterations"] < r[0]["stats"]["iterations"]
+    assert r[2]["stats"]["iterations"] < r[0]["stats"]["iterations"]
     assert _rel_inf(r[1]["phi"], r[0]["phi"]) <= 1e-8
+    assert _rel_inf(r[2]["phi"], r[0]["phi"]) <= 1e-8
     assert abs(r[1]["energy"] / r[0]["energy"] - 1) <= 1e-9
 
 
@@ -231,7 +235,7 @@ def test_error_statuses(ctx):
         hobi.Problem(ctx, xyz, nrm, tri, np.zeros((1, 3)), q, eps1=-1.0)
     assert e.value.name == "HOBI_E_ARG"
     with pytest.raises(hobi.HobiError) as e:
-        hobi.Problem(ctx, xyz, nrm, tri, np.zeros((1, 3)), q, diag_scaling=2)
+        hobi.Problem(ctx, xyz, nrm, tri, np.zeros((1, 3)), q, diag_scaling=3)
     assert e.value.name == "HOBI_E_ARG"
     g = hobi.Problem(ctx, xyz, nrm, tri, np.zeros((1, 3)), q, max_iter=1, rtol=1e-12)
     with pytest.raises(hobi.HobiError) as e:

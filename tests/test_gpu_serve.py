@@ -46,7 +46,7 @@ def test_served_equals_single_problem_path(ctx):
     """Alone in the server, a small request (same tile shape as the single-problem path)
     gives the single-problem solve's bits."""
     sv = hobi.Server(ctx, hbm_budget_bytes=2 << 30, max_slots=8)
-    for prec, scaled in ((hobi.HOBI_FP64, 1), (hobi.HOBI_MIXED, 1), (hobi.HOBI_MIXED, 0)):
+    for prec, scaled in ((hobi.HOBI_FP64, 2), (hobi.HOBI_MIXED, 2), (hobi.HOBI_MIXED, 1), (hobi.HOBI_MIXED, 0)):
         p = inputs.kirkwood_offcenter(2)
         t = sv.submit(p, precision=prec, max_iter=200, diag_scaling=scaled)
         r = _wait(sv, [t])[t]
