@@ -91,13 +91,16 @@ __device__ __forceinline__ NodeD load_node(const const_as<NodeD>* p, int s) {
 // FP32 pairs of nodes [sb, se) with the lane's TPL targets, added to FP32 running sums.
 // Positions are in units of 1 / kappa when kappa > 0, so that z = kappa r = r: with
 // zp1 = 1 + z = r^2 / r + 1, exp(-z) = exp2(log2 e (1 - zp1)) and 3 + 3z + z^2 = 3 zp1 + r^2
-// (the strengths carry the matching powers of the unit).  Per pair (kappa > 0): 33 VALU
+// (the strengths carry the matching powers of the unit).  Per pair (kappa > 0): 32 VALU
 // operations plus one rsqrt and one exp2.  With
 // q = (d.ny)/r^2, the two rows are
 //   row 1: K1 Gamma + K2 Phi = [Gamma (1 - e) + q (pa + pb f1)] / r
 //   row 2: K3 Gamma + K4 Phi = [(d.nx)(ga + gb f1 + p q f2) - (nx.P) f1] / r^3,  P = p ny,
-// which is the kernel algebra with the node strengths folded in.  With MASK, pairs of a
-// vertex with its own triangles' nodes (they belong to the singular rule) are skipped.
+// which is the kernel algebra with the node strengths folded in.  f2 is never formed: since
+// f2 = 3 f1 - z^2 e and q z^2 = (d.ny) (z = r in this frame), the strength of row 2 is
+// ga + f1 (gb + 3p q) - p (d.ny) e, where 3p is taken once per node for the lane's TPL
+// targets.  With MASK, pairs of a vertex with its own triangles' nodes (they belong to the
+// singular rule) are skipped.
 template <int TPL, bool KAPPA0, bool MASK>
 __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, const const_as<int4>* cvid, int sb,
                                              int se, int base, const float (&tx)[TPL], const float (&ty)[TPL],
@@ -110,6 +113,7 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, cons
         const NodeF next = load_node(cnodes, min(s + 1, se - 1));
         uint64_t vmask[TPL];
         if (MASK) vertex_lane_masks<TPL>(load_vid(cvid, s), base, vmask);
+        const float p3 = 3.0f * n.p;
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
             const float dx = tx[k] - n.x, dy = ty[k] - n.y, dz = tz[k] - n.z;
@@ -128,10 +132,9 @@ __device__ __forceinline__ void pair_f32_run(const const_as<NodeF>* cnodes, cons
                 const float zp1 = fmaf(r2, rinv, 1.0f);                  // 1 + z
                 const float e = __builtin_amdgcn_exp2f(fmaf(zp1, -kLog2E, kLog2E));   // exp(-z)
                 const float f1 = fmaf(-e, zp1, 1.0f);                    // 1 - e (1 + z)
-                const float f2 = fmaf(-e, fmaf(zp1, 3.0f, r2), 3.0f);    // 3 - e (3 + 3z + z^2)
                 const float q = dny * rinv2;
                 a1[k] = fmaf(rinv, fmaf(q, fmaf(n.pb, f1, n.pa), fmaf(-e, n.g, n.g)), a1[k]);
-                const float t = fmaf(n.p, q * f2, fmaf(n.gb, f1, n.ga));
+                const float t = fmaf(-(n.p * dny), e, fmaf(f1, fmaf(p3, q, n.gb), n.ga));
                 a2[k] = fmaf(rinv2 * rinv, fmaf(-pnxy, f1, dnx * t), a2[k]);
             }
         }
@@ -352,7 +355,8 @@ __device__ __forceinline__ double exp_neg_tab_f64(double z, const double* __rest
 // above (etab: its LDS table), and the closed forms of f1, f2 and 1 - e, whose cancellation
 // for small z = kappa r costs an absolute error of a few units of 1e-16, the size of the
 // rows' other rounding errors; the rows as in the FP32 tile, with the strengths
-// pre-multiplied by the epsilon factors.  With MASK, pairs of a vertex with its own
+// pre-multiplied by the epsilon factors (f2 itself is formed here: with two targets per
+// lane, the per-node factors that fold it away cost what they save).  With MASK, pairs of a vertex with its own
 // triangles' nodes are skipped.
 template <int TPL, bool KAPPA0, bool MASK>
 __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, const const_as<int4>* cvid, int sb,
