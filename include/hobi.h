@@ -103,6 +103,19 @@ typedef struct hobi_params {
     int32_t tree_degree; /* interpolation degree n, 1..7, default 5                        */
     int32_t tree_leaf;  /* nodes per leaf, a multiple of 64 in [64, 2^24], default 256      */
     int32_t tree_batch; /* targets per batch: 128, 256 or 512, default 128                  */
+    /* With tree_theta > 0, what hobi_solve solves.  0 (default): the treecode's own system
+     * (GMRES with the treecode matvec; its residuals are the treecode operator's).  1: the
+     * dense system A u = b of tree_theta = 0, by defect correction (iterative refinement
+     * with an approximate operator): from u = 0, each outer step solves T d = r by GMRES
+     * with the treecode matvec T (same preconditioner, restart and precision), to the
+     * relative tolerance max(rtol/2 ||b|| / ||r||, rtol/2) capped at 1/2, adds d to u and
+     * recomputes r = b - A u with the dense matvec.  It stops when ||r|| / ||b|| <= rtol
+     * (converged: a dense residual, not an estimate), when the inner matvecs reach
+     * max_iter, after 16 outer steps, or when an outer step shrinks ||r|| by less than
+     * half (HOBI_E_NOCONV for the last three).  hobi_stats.iterations counts the treecode
+     * matvecs, refine_steps the outer steps and dense_matvecs the dense ones; the true
+     * residual is the last outer residual (no extra matvec).  Not taken by the server. */
+    int32_t tree_refine; /* 0 or 1, default 0; 1 needs tree_theta > 0                       */
 } hobi_params;
 
 typedef struct hobi_stats {
@@ -126,6 +139,8 @@ typedef struct hobi_stats {
     int64_t tree_near_pairs;   /* and (batch, leaf) pairs summed directly (0 without it)     */
     int64_t field_tree_far_pairs;  /* the same for the last hobi_field call's point batches   */
     int64_t field_tree_near_pairs;
+    int32_t refine_steps;      /* tree_refine: outer steps of the last solve (else 0)       */
+    int32_t dense_matvecs;     /* tree_refine: dense matvecs of the last solve (else 0)      */
 } hobi_stats;
 
 /* Fills p with the defaults listed in hobi_params. */

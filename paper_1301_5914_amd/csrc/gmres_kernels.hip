@@ -96,6 +96,12 @@ __global__ void sub_kernel(const double* __restrict__ a, const double* __restric
     if (i < n) out[i] = a[i] - b[i];
 }
 
+__global__ void add_kernel(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out,
+                           int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] + b[i];
+}
+
 // Column k of the Hessenberg matrix and rotation k (givens_step), one thread.
 __global__ void givens_kernel(double* __restrict__ H, int ldh, int k, const double* __restrict__ h1,
                               const double* __restrict__ h2, const double* __restrict__ hnext,
@@ -168,6 +174,11 @@ hipError_t launch_scaling(const DeviceProblem& p, int mode, double* dinv, hipStr
 
 hipError_t launch_sub(const double* a, const double* b, double* out, int n, hipStream_t s) {
     hipLaunchKernelGGL(sub_kernel, dim3(nblk(n, kT)), dim3(kT), 0, s, a, b, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(const double* a, const double* b, double* out, int n, hipStream_t s) {
+    hipLaunchKernelGGL(add_kernel, dim3(nblk(n, kT)), dim3(kT), 0, s, a, b, out, n);
     return hipGetLastError();
 }
 

@@ -120,15 +120,16 @@ hobi_status resolve_timers(hobi_problem pb) {
     return HOBI_OK;
 }
 
-// y = A u, both in internal order on the device.
-hobi_status matvec_internal(hobi_problem pb, const double* u, double* y) {
+// y = A u, both in internal order on the device: the treecode's operator when the problem
+// has one, unless `dense`.
+hobi_status matvec_internal(hobi_problem pb, const double* u, double* y, bool dense = false) {
     hipStream_t s = pb->ctx->stream;
     const bool mixed = pb->prm.precision == HOBI_MIXED;
     {
         ScopedTimer t(pb, T_GATHER);
         HIPCHK(pb->ctx, launch_gather(pb->d, u, mixed, s));
     }
-    if (pb->d.tree.on) {
+    if (pb->d.tree.on && !dense) {
         {
             ScopedTimer t(pb, T_PAIR);
             HIPCHK(pb->ctx, launch_tree_proxies(pb->d, mixed, s));
@@ -152,7 +153,7 @@ hobi_status matvec_internal(hobi_problem pb, const double* u, double* y) {
 }
 
 void free_krylov(Krylov& k) {
-    double* ptrs[] = {k.V, k.H, k.cs, k.sn, k.g, k.h1, k.h2, k.hn, k.yk, k.res, k.dpart, k.x, k.tmp, k.scal};
+    double* ptrs[] = {k.V, k.H, k.cs, k.sn, k.g, k.h1, k.h2, k.hn, k.yk, k.res, k.dpart, k.x, k.tmp, k.scal, k.xo, k.ro};
     for (double* p : ptrs)
         if (p) (void)hipFree(p);
     k = Krylov{};
@@ -177,6 +178,10 @@ hobi_status ensure_krylov(hobi_problem pb, int n, int m) {
     HIPCHK(c, dalloc(&k.x, n));
     HIPCHK(c, dalloc(&k.tmp, n));
     HIPCHK(c, dalloc(&k.scal, 4));
+    if (pb->prm.tree_refine) {
+        HIPCHK(c, dalloc(&k.xo, n));
+        HIPCHK(c, dalloc(&k.ro, n));
+    }
     k.n = n;
     k.m = m;
     return HOBI_OK;
@@ -197,21 +202,22 @@ hobi_status norm2(hobi_problem pb, const double* v, int n, double* dev_out) {
     return HOBI_OK;
 }
 
-// Restarted GMRES(m) from x0 = 0 on A x = rhs (internal order); with diag_scaling the
-// Krylov space is that of A D^-1, D the diagonal coefficients 1/2 (1 + eps), 1/2 (1 + 1/eps)
-// of the two row blocks, and the iterate is x = D^-1 y (the residual it estimates is that
-// of A x = rhs).  Classical Gram-Schmidt
-// with a second pass, Givens rotations, stop when the estimate |g_{k+1}| / ||b|| <= rtol.
-hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
-    TraceRange trace_range("gmres");
+// Restarted GMRES(m) from x0 = 0 on A x = rhs (internal order), A the problem's operator
+// (the treecode's when it has one), at most max_iter matvecs.  With `scaled` it is
+// right-preconditioned by the diagonal D whose inverse launch_scaling left in d.dinv (the
+// row blocks' constants, diag_scaling 1, or A's own diagonal, 2): the Krylov space is that
+// of A D^-1 and the iterate is x = D^-1 y, so the residual it estimates is that of
+// A x = rhs.  Classical Gram-Schmidt with a second pass, Givens rotations; stops when the
+// estimate |g_{k+1}| / ||rhs|| <= rtol.  The iterate is left in k.x (ensure_krylov first).
+hobi_status gmres_run(hobi_problem pb, const double* rhs, double rtol, int max_iter, bool scaled, int* iters,
+                      double* est, bool* converged) {
     const int n = 2 * pb->d.nv;
-    const int m = std::max(1, std::min(pb->prm.restart, pb->prm.max_iter));
-    hobi_status st = ensure_krylov(pb, n, m);
-    if (st != HOBI_OK) return st;
+    const int m = pb->kr.m;
+    hobi_status st = HOBI_OK;
     Krylov& k = pb->kr;
     hipStream_t s = pb->ctx->stream;
     hobi_ctx c = pb->ctx;
-    const double* b = pb->d.rhs;
+    const double* b = rhs;
     HIPCHK(c, hipMemsetAsync(k.x, 0, sizeof(double) * n, s));
     if ((st = norm2(pb, b, n, k.scal)) != HOBI_OK) return st;
     double bnorm = 0;
@@ -221,11 +227,6 @@ hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
     *converged = true;
     if (!(bnorm > 0.0)) return std::isfinite(bnorm) ? HOBI_OK : fail(c, HOBI_E_NUMERIC, "non-finite rhs");
     int total = 0;
-    const double rtol = pb->prm.rtol;
-    // right scaling (diag_scaling): Krylov space of A D^-1, iterate x = D^-1 y, D the row
-    // blocks' constants (mode 1) or A's own diagonal (mode 2)
-    const bool scaled = pb->prm.diag_scaling != 0;
-    if (scaled) HIPCHK(c, launch_scaling(pb->d, pb->prm.diag_scaling, pb->d.dinv, s));
     while (true) {
         // r = b - A x
         const double* r = b;
@@ -239,7 +240,7 @@ hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
         if ((st = read_scalar(pb, k.scal + 1, &beta)) != HOBI_OK) return st;
         if (!std::isfinite(beta)) return fail(c, HOBI_E_NUMERIC, "GMRES residual is not finite");
         *est = beta / bnorm;
-        if (*est <= rtol || total >= pb->prm.max_iter) break;
+        if (*est <= rtol || total >= max_iter) break;
         HIPCHK(c, launch_scale_copy(r, k.scal + 1, k.V, n, s));
         HIPCHK(c, launch_init_g(k.scal + 1, k.g, m, s));
         int kk = 0;
@@ -270,7 +271,7 @@ hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
             if (!std::isfinite(res)) return fail(c, HOBI_E_NUMERIC, "GMRES residual is not finite");
             *est = res;
             kk = j + 1;
-            if (res <= rtol || total >= pb->prm.max_iter) {
+            if (res <= rtol || total >= max_iter) {
                 stop = true;
                 break;
             }
@@ -285,6 +286,81 @@ hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged) {
     *iters = total;
     *converged = *est <= rtol;
     return HOBI_OK;
+}
+
+constexpr int kMaxRefineSteps = 16;
+
+// tree_refine: the dense system A x = b by defect correction with the treecode operator T
+// (iterative refinement with an approximate operator): from x = 0, each outer step solves
+// T d = r by gmres_run to the relative tolerance max(rtol/2 ||b|| / ||r||, rtol/2), capped at
+// 1/2, so that with T = A the next residual would be at most rtol/2 ||b||; then x += d and
+// r = b - A x with the dense matvec.  Stops as the ABI states; x is left in k.x and the
+// last dense residual b - A x in k.ro.
+hobi_status gmres_refined(hobi_problem pb, bool scaled, int* iters, double* est, bool* converged, int* steps,
+                          int* dense_mv) {
+    const int n = 2 * pb->d.nv;
+    Krylov& k = pb->kr;
+    hipStream_t s = pb->ctx->stream;
+    hobi_ctx c = pb->ctx;
+    const double* b = pb->d.rhs;
+    const double rtol = pb->prm.rtol;
+    const int max_iter = pb->prm.max_iter;
+    hobi_status st = HOBI_OK;
+    *iters = 0;
+    *est = 0.0;
+    *converged = true;
+    *steps = 0;
+    *dense_mv = 0;
+    HIPCHK(c, hipMemsetAsync(k.xo, 0, sizeof(double) * n, s));
+    HIPCHK(c, hipMemcpyAsync(k.ro, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if ((st = norm2(pb, b, n, k.scal + 2)) != HOBI_OK) return st;
+    double bnorm = 0;
+    if ((st = read_scalar(pb, k.scal + 2, &bnorm)) != HOBI_OK) return st;
+    if (!std::isfinite(bnorm)) return fail(c, HOBI_E_NUMERIC, "non-finite rhs");
+    if (bnorm > 0.0) {
+        double rnorm = bnorm;
+        int total = 0;
+        while (true) {
+            const double tol = std::min(0.5, std::max(0.5 * rtol * bnorm / rnorm, 0.5 * rtol));
+            int it = 0;
+            double e_in = 0;
+            bool c_in = false;
+            if ((st = gmres_run(pb, k.ro, tol, max_iter - total, scaled, &it, &e_in, &c_in)) != HOBI_OK) return st;
+            total += it;
+            HIPCHK(c, launch_add(k.xo, k.x, k.xo, n, s));
+            if ((st = matvec_internal(pb, k.xo, k.tmp, true)) != HOBI_OK) return st;
+            HIPCHK(c, launch_sub(b, k.tmp, k.ro, n, s));
+            ++*steps;
+            ++*dense_mv;
+            if ((st = norm2(pb, k.ro, n, k.scal + 2)) != HOBI_OK) return st;
+            double rn = 0;
+            if ((st = read_scalar(pb, k.scal + 2, &rn)) != HOBI_OK) return st;
+            if (!std::isfinite(rn)) return fail(c, HOBI_E_NUMERIC, "refinement residual is not finite");
+            *est = rn / bnorm;
+            *iters = total;
+            if (*est <= rtol || total >= max_iter || *steps >= kMaxRefineSteps || rn > 0.5 * rnorm) break;
+            rnorm = rn;
+        }
+    }
+    HIPCHK(c, hipMemcpyAsync(k.x, k.xo, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    *converged = *est <= rtol;
+    return HOBI_OK;
+}
+
+// The solve's Krylov driver: GMRES on the problem's operator, or the defect correction of
+// tree_refine.  refine_steps and dense_mv are 0 without it.
+hobi_status gmres(hobi_problem pb, int* iters, double* est, bool* converged, int* refine_steps, int* dense_mv) {
+    TraceRange trace_range("gmres");
+    const int n = 2 * pb->d.nv;
+    const int m = std::max(1, std::min(pb->prm.restart, pb->prm.max_iter));
+    hobi_status st = ensure_krylov(pb, n, m);
+    if (st != HOBI_OK) return st;
+    const bool scaled = pb->prm.diag_scaling != 0;
+    if (scaled) HIPCHK(pb->ctx, launch_scaling(pb->d, pb->prm.diag_scaling, pb->d.dinv, pb->ctx->stream));
+    *refine_steps = 0;
+    *dense_mv = 0;
+    if (pb->prm.tree_refine && pb->d.tree.on) return gmres_refined(pb, scaled, iters, est, converged, refine_steps, dense_mv);
+    return gmres_run(pb, pb->d.rhs, pb->prm.rtol, pb->prm.max_iter, scaled, iters, est, converged);
 }
 
 hobi_status to_internal(hobi_problem pb, const double* u, int on_device, double* dst) {
@@ -511,6 +587,9 @@ hobi_status validate_params(hobi_ctx ctx, const hobi_params& p) {
         return fail(ctx, HOBI_E_ARG, "tree_leaf must be a multiple of 64 in [64, 2^24]");
     if (p.tree_batch != 128 && p.tree_batch != 256 && p.tree_batch != 512)
         return fail(ctx, HOBI_E_ARG, "tree_batch must be 128, 256 or 512");
+    if (p.tree_refine != 0 && p.tree_refine != 1) return fail(ctx, HOBI_E_ARG, "tree_refine must be 0 or 1");
+    if (p.tree_refine == 1 && !(p.tree_theta > 0))
+        return fail(ctx, HOBI_E_ARG, "tree_refine needs the treecode (tree_theta > 0)");
     return HOBI_OK;
 }
 
@@ -553,6 +632,7 @@ void hobi_params_default(hobi_params* p) {
     p->tree_degree = 5;
     p->tree_leaf = 256;
     p->tree_batch = 128;
+    p->tree_refine = 0;
 }
 
 hobi_status hobi_ctx_create(int device, void* stream, hobi_ctx* out) {
@@ -1154,17 +1234,21 @@ hobi_status hobi_solve(hobi_problem pb, double* phi, double* dphi, double* e_sol
     for (auto& e : ev)
         if (!e) return fail(c, HOBI_E_HIP, "hipEventCreate failed");
     HIPCHK(c, hipEventRecord(ev[0], s));
-    int iters = 0;
+    int iters = 0, refine_steps = 0, dense_mv = 0;
     double est = 0;
     bool conv = false;
-    hobi_status st = gmres(pb, &iters, &est, &conv);
+    hobi_status st = gmres(pb, &iters, &est, &conv, &refine_steps, &dense_mv);
     if (st != HOBI_OK) return st;
     HIPCHK(c, hipEventRecord(ev[1], s));
     Krylov& k = pb->kr;
-    // true residual
-    if ((st = matvec_internal(pb, k.x, k.tmp)) != HOBI_OK) return st;
-    HIPCHK(c, launch_sub(pb->d.rhs, k.tmp, k.tmp, n, s));
-    if ((st = norm2(pb, k.tmp, n, k.scal + 2)) != HOBI_OK) return st;
+    // true residual (tree_refine: its last outer step's dense residual, already in k.ro)
+    const double* rres = k.ro;
+    if (refine_steps == 0) {
+        if ((st = matvec_internal(pb, k.x, k.tmp)) != HOBI_OK) return st;
+        HIPCHK(c, launch_sub(pb->d.rhs, k.tmp, k.tmp, n, s));
+        rres = k.tmp;
+    }
+    if ((st = norm2(pb, rres, n, k.scal + 2)) != HOBI_OK) return st;
     if ((st = norm2(pb, pb->d.rhs, n, k.scal + 3)) != HOBI_OK) return st;
     // energy (FP64 nodes, FP64 reduction)
     HIPCHK(c, hipEventRecord(ev[2], s));
@@ -1206,11 +1290,18 @@ hobi_status hobi_solve(hobi_problem pb, double* phi, double* dphi, double* e_sol
     L.field_tree_far_pairs = pb->field.tree_far;
     L.field_tree_near_pairs = pb->field.tree_near;
     L.tree_near_pairs = pb->d.tree.nnear;
+    L.refine_steps = refine_steps;
+    L.dense_matvecs = dense_mv;
     if (stats) *stats = L;
     for (int i = 0; i < n; ++i)
         if (!std::isfinite(hu[i])) return fail(c, HOBI_E_NUMERIC, "non-finite solution");
     if (!std::isfinite(E)) return fail(c, HOBI_E_NUMERIC, "non-finite energy");
-    if (!conv) return fail(c, HOBI_E_NOCONV, "GMRES stopped at %d matvecs, residual %.3e", iters, est);
+    if (!conv) {
+        if (refine_steps > 0)
+            return fail(c, HOBI_E_NOCONV, "defect correction stopped after %d outer steps (%d treecode matvecs), "
+                        "dense residual %.3e", refine_steps, iters, est);
+        return fail(c, HOBI_E_NOCONV, "GMRES stopped at %d matvecs, residual %.3e", iters, est);
+    }
     return HOBI_OK;
 }
 

@@ -33,6 +33,7 @@ struct Krylov {
     double *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
     double *h1 = nullptr, *h2 = nullptr, *hn = nullptr, *yk = nullptr, *res = nullptr;
     double *dpart = nullptr, *x = nullptr, *tmp = nullptr, *scal = nullptr;
+    double *xo = nullptr, *ro = nullptr;   // defect correction: outer iterate and dense residual
 };
 
 }  // namespace hobi

@@ -255,6 +255,8 @@ hipError_t launch_multi_axpy(const double* V, size_t ld, int nvec, const double*
 hipError_t launch_scale_copy(const double* in, const double* denom, double* out, int n,
                              hipStream_t s);
 hipError_t launch_sub(const double* a, const double* b, double* out, int n, hipStream_t s);
+// out = a + b
+hipError_t launch_add(const double* a, const double* b, double* out, int n, hipStream_t s);
 // out[i] = dinv[i] in[i], i < n
 hipError_t launch_diag_scale(const double* in, double* out, int n, const double* dinv, hipStream_t s);
 // x[i] += dinv[i] sum_j coef[j] V[j][i], i < n

@@ -691,6 +691,11 @@ hobi_status hobi_server_submit(hobi_server sv, int32_t nv, const double* xyz, co
     r->q.assign(q, q + nc);
     hobi_params_default(&r->prm);
     if (params) r->prm = *params;
+    if (r->prm.tree_refine != 0) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->last_error = "tree_refine is a hobi_solve option: the server solves each request's own operator";
+        return HOBI_E_ARG;
+    }
     r->prm.restart = r->prm.max_iter;
     r->nu = r->prm.method == HOBI_LOWER_ORDER ? nf : nv;
     r->footprint = footprint_bytes(sv->device, nv, nf, nc, std::max(1, r->prm.max_iter), r->prm.method);

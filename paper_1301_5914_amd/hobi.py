@@ -41,7 +41,7 @@ class hobi_params(ctypes.Structure):
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("method", ctypes.c_int32), ("diag_scaling", ctypes.c_int32),
                 ("tree_theta", ctypes.c_double), ("tree_degree", ctypes.c_int32), ("tree_leaf", ctypes.c_int32),
-                ("tree_batch", ctypes.c_int32)]
+                ("tree_batch", ctypes.c_int32), ("tree_refine", ctypes.c_int32)]
 
 
 class hobi_stats(ctypes.Structure):
@@ -54,7 +54,8 @@ class hobi_stats(ctypes.Structure):
                 ("ms_krylov", ctypes.c_double), ("ms_field_kernel", ctypes.c_double),
                 ("field_launches", ctypes.c_int64), ("tree_far_pairs", ctypes.c_int64),
                 ("tree_near_pairs", ctypes.c_int64), ("field_tree_far_pairs", ctypes.c_int64),
-                ("field_tree_near_pairs", ctypes.c_int64)]
+                ("field_tree_near_pairs", ctypes.c_int64), ("refine_steps", ctypes.c_int32),
+                ("dense_matvecs", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -202,7 +203,7 @@ class Problem:
 
     def __init__(self, ctx: Context, xyz, nrm, tri, qpos, q, eps1=1.0, eps2=80.0, kappa=0.1257,
                  rtol=1e-6, max_iter=200, restart=200, precision=HOBI_FP64, method=HOBI_HIGHER_ORDER,
-                 diag_scaling=2, tree_theta=0.0, tree_degree=5, tree_leaf=256, tree_batch=128):
+                 diag_scaling=2, tree_theta=0.0, tree_degree=5, tree_leaf=256, tree_batch=128, tree_refine=0):
         self.ctx = ctx
         xyz = _f64(xyz).reshape(-1, 3)
         nrm = _f64(nrm).reshape(-1, 3)
@@ -218,6 +219,7 @@ class Problem:
         p.max_iter, p.restart, p.precision, p.method = max_iter, restart, precision, method
         p.diag_scaling = diag_scaling
         p.tree_theta, p.tree_degree, p.tree_leaf, p.tree_batch = tree_theta, tree_degree, tree_leaf, tree_batch
+        p.tree_refine = tree_refine
         h = _P()
         st = lib().hobi_problem_create(ctx.handle, self.nv, _dptr(xyz), _dptr(nrm), self.nf,
                                        tri.ctypes.data_as(_I), self.nc, _dptr(qpos), _dptr(q),
@@ -381,7 +383,7 @@ class Server:
 
     def submit(self, prob, rtol=1e-6, max_iter=300, precision=HOBI_MIXED, eps1=None, eps2=None,
                kappa=None, method=HOBI_HIGHER_ORDER, diag_scaling=2, tree_theta=0.0, tree_degree=5, tree_leaf=256,
-               tree_batch=128) -> int:
+               tree_batch=128, tree_refine=0) -> int:
         xyz = _f64(prob.xyz).reshape(-1, 3)
         nrm = _f64(prob.nrm).reshape(-1, 3)
         tri = np.ascontiguousarray(np.asarray(prob.tri, dtype=np.int32).reshape(-1, 3))
@@ -394,6 +396,7 @@ class Server:
         p.rtol, p.max_iter, p.restart, p.precision, p.method = rtol, max_iter, max_iter, precision, method
         p.diag_scaling = diag_scaling
         p.tree_theta, p.tree_degree, p.tree_leaf, p.tree_batch = tree_theta, tree_degree, tree_leaf, tree_batch
+        p.tree_refine = tree_refine
         t = ctypes.c_uint64()
         st = lib().hobi_server_submit(self.handle, xyz.shape[0], _dptr(xyz), _dptr(nrm), tri.shape[0],
                                       tri.ctypes.data_as(_I), q.shape[0], _dptr(qpos), _dptr(q),

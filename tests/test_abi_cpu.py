@@ -20,6 +20,7 @@ def test_params_default():
     p = hobi.hobi_params_default()
     assert (p.eps1, p.eps2, p.kappa, p.rtol) == (1.0, 80.0, 0.1257, 1e-6)
     assert (p.max_iter, p.restart, p.precision, p.method, p.diag_scaling) == (200, 200, hobi.HOBI_FP64, 0, 2)
+    assert p.tree_refine == 0
     assert (p.tree_theta, p.tree_degree, p.tree_leaf, p.tree_batch) == (0.0, 5, 256, 128)
 
 

@@ -107,6 +107,9 @@ def test_treecode_requests_equal_the_single_problem_path(ctx):
         alone = _wait(sv, [sv.submit(cases[0][0], max_iter=200, **cases[0][1])])
         tickets = [sv.submit(p, max_iter=200, **kw) for p, kw in cases]
         bad = sv.submit(cases[0][0], max_iter=200, tree_theta=0.5, tree_degree=9)
+        with pytest.raises(hobi.HobiError) as e:   # the defect correction is hobi_solve's only
+            sv.submit(cases[0][0], max_iter=200, tree_theta=0.5, tree_refine=1)
+        assert e.value.status == 1
         out = _wait(sv, tickets + [bad])
         for r, ref in zip([next(iter(alone.values()))] + [out[t] for t in tickets], [refs[0]] + refs):
             assert r["status"] == "HOBI_OK"

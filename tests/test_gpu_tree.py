@@ -304,9 +304,85 @@ def test_tree_parameter_errors(ctx):
     bad = [dict(tree_theta=-0.1), dict(tree_theta=float("nan")), dict(tree_theta=0.5, tree_degree=0),
            dict(tree_theta=0.5, tree_degree=8), dict(tree_theta=0.5, tree_leaf=100),
            dict(tree_theta=0.5, tree_leaf=0), dict(tree_theta=0.5, tree_batch=64),
-           dict(tree_theta=0.5, tree_batch=1024)]
+           dict(tree_theta=0.5, tree_batch=1024), dict(tree_refine=1), dict(tree_theta=0.5, tree_refine=2),
+           dict(tree_theta=0.5, tree_refine=-1)]
     for kw in bad:
         with pytest.raises(hobi.HobiError) as e:
             hobi.Problem.from_inputs(ctx, p, **kw)
         assert e.value.status == 1, kw
     # the server takes treecode requests (tests/test_gpu_serve.py); its submit checks sizes only
+
+
+def _oracle_dense_residual(p, res):
+    """||b - A u|| / ||b|| of a solve's returned (phi, dphi) under the oracle's dense operator
+    and sources (FP64)."""
+    st = O.setup(p.xyz, p.nrm, p.tri)
+    S1, S2 = O.sources(st.xyz, st.nrm, p.qpos, p.q, p.eps1)
+    b = np.concatenate([S1, S2])
+    u = np.concatenate([res["phi"], res["dphi"]]) / UNIT
+    r = b - O.matvec(st, u, p.kappa, p.eps2 / p.eps1)
+    return float(np.linalg.norm(r) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("degree", [2, 5])
+def test_tree_refine_solves_the_dense_system(ctx, degree):
+    """tree_refine = 1 (defect correction, the treecode as the approximate operator) stops on
+    the dense system's residual: the returned solution's residual under the oracle's dense
+    operator is within rtol (1e-10), where the treecode's own solution is not, and its energy
+    is the dense solve's.  Degree 2 (a coarse treecode) takes more outer steps than 5."""
+    p = inputs.kirkwood_offcenter(3)
+    kw = dict(tree_theta=0.9, tree_degree=degree, tree_leaf=64, tree_batch=128, rtol=1e-10, max_iter=400,
+              restart=400)
+    own = hobi.Problem.from_inputs(ctx, p, **kw).solve()
+    dense = hobi.Problem.from_inputs(ctx, p, rtol=1e-10, max_iter=400, restart=400).solve()
+    r = hobi.Problem.from_inputs(ctx, p, tree_refine=1, **kw).solve()
+    s = r["stats"]
+    res_own, res_ref = _oracle_dense_residual(p, own), _oracle_dense_residual(p, r)
+    print(f"degree {degree}: outer {s['refine_steps']} tree matvecs {s['iterations']} dense {s['dense_matvecs']}"
+          f" true residual {s['true_residual']:.3e} oracle residual {res_ref:.3e} (treecode's own solution "
+          f"{res_own:.3e}); dense solve {dense['stats']['iterations']} iterations", flush=True)
+    assert s["converged"] == 1 and s["refine_steps"] >= 2 and s["dense_matvecs"] == s["refine_steps"]
+    assert s["true_residual"] <= 1e-10 and s["est_residual"] == s["true_residual"]
+    assert res_ref <= 1.2e-10
+    assert res_own > 1e-9
+    assert abs(r["energy"] - dense["energy"]) <= 1e-9 * abs(dense["energy"])
+    assert own["stats"]["refine_steps"] == 0 and own["stats"]["dense_matvecs"] == 0
+
+
+def test_tree_refine_mixed_and_lower_order(ctx):
+    """Mixed precision: the refined solve meets rtol 1e-6 on the dense mixed operator, and on
+    the oracle's FP64 one within the mixed matvec's own error; the lower-order method's
+    refined energy is its dense solve's."""
+    p = inputs.kirkwood_offcenter(3)
+    tree = dict(tree_theta=0.9, tree_degree=4, tree_leaf=64, tree_batch=128)
+    r = hobi.Problem.from_inputs(ctx, p, precision=hobi.HOBI_MIXED, tree_refine=1, **tree).solve()
+    d64 = hobi.Problem.from_inputs(ctx, p, rtol=1e-10).solve()
+    res = _oracle_dense_residual(p, r)
+    print(f"mixed refine: outer {r['stats']['refine_steps']} true residual {r['stats']['true_residual']:.3e} "
+          f"oracle residual {res:.3e}", flush=True)
+    assert r["stats"]["converged"] == 1 and r["stats"]["true_residual"] <= 1e-6
+    assert res <= 2e-6
+    assert abs(r["energy"] - d64["energy"]) <= 1e-5 * abs(d64["energy"])
+    lo = dict(method=hobi.HOBI_LOWER_ORDER, rtol=1e-10, max_iter=400, restart=400)
+    rl = hobi.Problem.from_inputs(ctx, p, tree_refine=1, **tree, **lo).solve()
+    dl = hobi.Problem.from_inputs(ctx, p, **lo).solve()
+    print(f"lower-order refine: outer {rl['stats']['refine_steps']} energy {rl['energy']:.10f} "
+          f"dense {dl['energy']:.10f}", flush=True)
+    assert rl["stats"]["converged"] == 1 and rl["stats"]["true_residual"] <= 1e-10
+    assert abs(rl["energy"] - dl["energy"]) <= 1e-9 * abs(dl["energy"])
+
+
+def test_tree_refine_stops_at_max_iter(ctx):
+    """The matvec budget binds the treecode matvecs of all outer steps together: at 3 the
+    solve ends unconverged with HOBI_E_NOCONV, its dense residual reported."""
+    p = inputs.kirkwood_offcenter(3)
+    g = hobi.Problem.from_inputs(ctx, p, tree_theta=0.9, tree_degree=5, tree_leaf=64, tree_batch=128,
+                                 tree_refine=1, max_iter=3, restart=3)
+    r = g.solve(allow_noconv=True)
+    s = r["stats"]
+    print(f"budget 3: status {r['status']} iterations {s['iterations']} outer {s['refine_steps']} "
+          f"residual {s['true_residual']:.3e}", flush=True)
+    assert r["status"] == "HOBI_E_NOCONV"
+    assert s["converged"] == 0 and s["iterations"] <= 3 and s["refine_steps"] >= 1
+    assert 0 < s["true_residual"] == s["est_residual"]
+
