@@ -507,7 +507,7 @@ hobi_status build_tree_plan(hobi_problem pb, int64_t limit, int64_t* need) {
     TreeHostPlan hp;
     std::string msg;
     if (!plan_tree(nn, nxyz.data(), nv, tg.data(), (size_t)d.nv_pad, nf, tri.data(),
-                   d.method == HOBI_LOWER_ORDER ? 1 : 0, prm.tree_theta, t.leaf, t.batch, kTpl64, &hp, &msg))
+                   d.method == HOBI_LOWER_ORDER ? 1 : 0, prm.tree_theta, t.leaf, t.batch, kTreeTpl64, &hp, &msg))
         return fail(ctx, HOBI_E_ARG, "%s", msg.c_str());
     const int64_t bytes = tree_plan_bytes(hp, t.nprox, nv);
     if (bytes > limit) {

@@ -350,13 +350,14 @@ __device__ __forceinline__ double exp_neg_tab_f64(double z, const double* __rest
     return __builtin_amdgcn_ldexp(fma(t, q, t), mi >> 8);
 }
 
-// FP64 pairs of nodes [sb, se) with the lane's TPL targets.  Per pair (kappa > 0) about 50
+// FP64 pairs of nodes [sb, se) with the lane's TPL targets.  Per pair (kappa > 0) about 48
 // FP64 operations: the reciprocal square root of hobi_device.h, the table-driven exponential
-// above (etab: its LDS table), and the closed forms of f1, f2 and 1 - e, whose cancellation
+// above (etab: its LDS table), and the closed forms of f1 and 1 - e, whose cancellation
 // for small z = kappa r costs an absolute error of a few units of 1e-16, the size of the
 // rows' other rounding errors; the rows as in the FP32 tile, with the strengths
-// pre-multiplied by the epsilon factors (f2 itself is formed here: with two targets per
-// lane, the per-node factors that fold it away cost what they save).  With MASK, pairs of a vertex with its own
+// pre-multiplied by the epsilon factors and f2 folded into the strength of row 2 as there:
+// f2 = 3 f1 - z^2 e with q z^2 = kappa^2 (d.ny), the node factors 3 Phi and kappa^2 Phi
+// taken once per node for the lane's TPL targets.  With MASK, pairs of a vertex with its own
 // triangles' nodes are skipped.
 template <int TPL, bool KAPPA0, bool MASK>
 __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, const const_as<int4>* cvid, int sb,
@@ -364,10 +365,12 @@ __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, cons
                                              const double (&tz)[TPL], const double (&tnx)[TPL],
                                              const double (&tny)[TPL], const double (&tnz)[TPL], double kappa,
                                              const double* __restrict__ etab, double (&a1)[TPL], double (&a2)[TPL]) {
+    const double kappa2 = kappa * kappa;
     for (int s = sb; s < se; ++s) {
         const NodeD nd = load_node(cnodes, s);   // (a prefetched FP64 record would not fit the scalar registers)
         uint64_t vmask[TPL];
         if (MASK) vertex_lane_masks<TPL>(load_vid(cvid, s), base, vmask);
+        const double p3 = 3.0 * nd.p, pk2 = nd.p * kappa2;
 #pragma unroll
         for (int k = 0; k < TPL; ++k) {
             const double dx = tx[k] - nd.x, dy = ty[k] - nd.y, dz = tz[k] - nd.z;
@@ -387,11 +390,10 @@ __device__ __forceinline__ void pair_f64_run(const const_as<NodeD>* cnodes, cons
                 const double e = exp_neg_tab_f64(z, etab);
                 const double zp1 = z + 1.0;
                 const double f1 = fma(-e, zp1, 1.0);                          // 1 - e (1 + z)
-                const double f2 = fma(-e, fma(zp1, zp1 + 1.0, 1.0), 3.0);     // 3 - e (3 + 3z + z^2)
                 // the FP32 tile's row algebra: q = (d.ny)/r^2, P = Phi ny
                 const double q = dny * rinv2;
                 a1[k] = fma(rinv, fma(q, fma(nd.pb, f1, nd.pa), fma(-e, nd.g, nd.g)), a1[k]);
-                const double t = fma(nd.p, q * f2, fma(nd.gb, f1, nd.ga));
+                const double t = fma(-(pk2 * dny), e, fma(f1, fma(p3, q, nd.gb), nd.ga));
                 a2[k] = fma(rinv2 * rinv, fma(-pnxy, f1, dnx * t), a2[k]);
             }
         }

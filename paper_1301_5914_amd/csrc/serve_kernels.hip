@@ -15,7 +15,6 @@ namespace hobi {
 
 static_assert(kServeBlock == kPairBlock, "served work items are pair-kernel blocks");
 static_assert(kPairBlock == kPairWaves * kWave, "a pair block is kPairWaves waves");
-static_assert(kTpl64 == 2, "served FP64 tiles use the single-problem plan");
 
 namespace {
 

@@ -528,11 +528,11 @@ hipError_t launch_tree_pairs(const DeviceProblem& p, bool mixed, hipStream_t s) 
 #undef HOBI_TREE32
     } else {
         if (k0)
-            hipLaunchKernelGGL((tree_f64_kernel<kTpl64, true>), grid, dim3(kBlock), 0, s, t.items[0], t.nitems[0],
+            hipLaunchKernelGGL((tree_f64_kernel<kTreeTpl64, true>), grid, dim3(kBlock), 0, s, t.items[0], t.nitems[0],
                                p.tgt64, p.nv, p.nv_pad, p.node64, p.node_vid, p.blk_range, t.clu_range, t.prox64,
                                t.nprox, p.kappa, t.partial);
         else
-            hipLaunchKernelGGL((tree_f64_kernel<kTpl64, false>), grid, dim3(kBlock), 0, s, t.items[0], t.nitems[0],
+            hipLaunchKernelGGL((tree_f64_kernel<kTreeTpl64, false>), grid, dim3(kBlock), 0, s, t.items[0], t.nitems[0],
                                p.tgt64, p.nv, p.nv_pad, p.node64, p.node_vid, p.blk_range, t.clu_range, t.prox64,
                                t.nprox, p.kappa, t.partial);
     }
