@@ -289,10 +289,12 @@ def field_bench(pb, prob, grid, res, mixed, n_nodes):
 
 
 def tree_bench(ctx, stream, prob, theta, degree, leaf, batch, mixed, dense_pb, dense_res, dense_mv_ms, pairs_mv,
-               grid=0, lower=False):
+               grid=0, lower=False, refine=(0.8, 3, 128, 128)):
     """The treecode form of the matvec on the same problem: matvec time (HIP events, median
     of 20), the dense pair count it replaces per second, its error against the dense matvec
-    on a random vector, and the solve with it against the dense solve."""
+    on a random vector, and the solve with it against the dense solve; then the dense system
+    solved through a treecode of parameters `refine` (theta, degree, leaf, batch) by defect
+    correction."""
     import torch
     from paper_1301_5914_amd import hobi
     pb = hobi.Problem.from_inputs(ctx, prob, precision=hobi.HOBI_MIXED if mixed else hobi.HOBI_FP64,
@@ -319,10 +321,12 @@ def tree_bench(ctx, stream, prob, theta, degree, leaf, batch, mixed, dense_pb, d
     pb.solve()                                        # warm-up
     res = [pb.solve() for _ in range(2)]
     mv = float(np.median(ms))
-    # the dense system to the same rtol by defect correction with this treecode (tree_refine)
+    # the dense system to the same rtol by defect correction with a treecode (tree_refine): its
+    # accuracy only sets how many outer steps it takes, so a cheaper one than above serves
+    r_theta, r_degree, r_leaf, r_batch = refine
     rp = hobi.Problem.from_inputs(ctx, prob, precision=hobi.HOBI_MIXED if mixed else hobi.HOBI_FP64,
                                   method=hobi.HOBI_LOWER_ORDER if lower else hobi.HOBI_HIGHER_ORDER,
-                                  tree_theta=theta, tree_degree=degree, tree_leaf=leaf, tree_batch=batch,
+                                  tree_theta=r_theta, tree_degree=r_degree, tree_leaf=r_leaf, tree_batch=r_batch,
                                   max_iter=400, restart=400, tree_refine=1)
     rp.solve()                                        # warm-up
     rr = [rp.solve() for _ in range(2)]
@@ -331,6 +335,7 @@ def tree_bench(ctx, stream, prob, theta, degree, leaf, batch, mixed, dense_pb, d
     r_ms = float(np.mean([r["stats"]["ms_solve"] for r in rr]))
     refined = {"what": "the dense system A u = b by defect correction: treecode GMRES for each correction, "
                        "the dense matvec for each outer residual; it stops on the dense residual",
+               "theta": r_theta, "degree": r_degree, "leaf": r_leaf, "batch": r_batch,
                "solve_ms": r_ms, "treecode_matvecs": rs["iterations"], "outer_steps": rs["refine_steps"],
                "dense_matvecs": rs["dense_matvecs"], "dense_true_residual": rs["true_residual"],
                "dense_solve_ms": dense_res["stats"]["ms_solve"],
@@ -616,6 +621,11 @@ def main():
     ap.add_argument("--tree-degree", type=int, default=5)
     ap.add_argument("--tree-leaf", type=int, default=256)
     ap.add_argument("--tree-batch", type=int, default=128)
+    ap.add_argument("--refine-theta", type=float, default=0.8,
+                    help="treecode of the defect-correction solve in the treecode leg (tree_refine)")
+    ap.add_argument("--refine-degree", type=int, default=3)
+    ap.add_argument("--refine-leaf", type=int, default=128)
+    ap.add_argument("--refine-batch", type=int, default=128)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -729,7 +739,8 @@ def main():
         # (hobi_field takes the treecode with the higher-order method only: no map otherwise)
         out["tree"] = tree_bench(ctx, stream, prob, args.tree_theta, args.tree_degree, args.tree_leaf,
                                  args.tree_batch, mixed, pb, results[-1], out["matvec_ms_median"], pairs_mv,
-                                 grid=0 if lower else args.field_map, lower=lower)
+                                 grid=0 if lower else args.field_map, lower=lower,
+                                 refine=(args.refine_theta, args.refine_degree, args.refine_leaf, args.refine_batch))
         progress("treecode leg done")
     if not args.no_compare:
         # the other precision on the same problem (outside the timed region)
