@@ -152,7 +152,8 @@ def cpu_baseline(prob, seconds: float, workers: int, lower: bool = False):
            "sample": f"{nrows} consecutive of {n_sites} matvec rows (x {n_nodes} nodes), {dt:.1f} s "
                      f"(oracle setup {t_setup:.1f} s, not timed)",
            "cpu_model": cpu_model(), "host_cpus_visible": len(os.sched_getaffinity(0)),
-           "gpairs_per_s_per_core": pairs / dt / 1e9 / max(1, cores)}
+           "gpairs_per_s_per_core": pairs / dt / 1e9 / max(1, cores),
+           "full_matvec_s_extrapolated": dt * n_sites / nrows}
     return rec, (u, rows, y_rows)
 
 
