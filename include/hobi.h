@@ -108,12 +108,12 @@ typedef struct hobi_params {
      * dense system A u = b of tree_theta = 0, by defect correction (iterative refinement
      * with an approximate operator): from u = 0, each outer step solves T d = r by GMRES
      * with the treecode matvec T (same preconditioner, restart and precision), to the
-     * relative tolerance 100 rtol in the first step and max(rtol/2 ||b|| / ||r||, rtol/2)
-     * after it (each capped at 1/2), adds d to u and recomputes r = b - A u with the dense
-     * matvec.  It stops when ||r|| / ||b|| <= rtol
-     * (converged: a dense residual, not an estimate), when the inner matvecs reach
-     * max_iter, after 16 outer steps, or when an outer step shrinks ||r|| by less than
-     * half (HOBI_E_NOCONV for the last three).  hobi_stats.iterations counts the treecode
+     * relative tolerance min(100 rtol, 1/10) in the first step and
+     * max(rtol/2 ||b|| / ||r||, rtol/2), at most 1/2, after it, adds d to u and recomputes
+     * r = b - A u with the dense matvec.  It stops when ||r|| / ||b|| <= rtol (converged:
+     * a dense residual, not an estimate), when the inner matvecs reach max_iter, after 16
+     * outer steps, or when an outer step shrinks ||r|| by less than a tenth
+     * (HOBI_E_NOCONV for the last three).  hobi_stats.iterations counts the treecode
      * matvecs, refine_steps the outer steps and dense_matvecs the dense ones; the true
      * residual is the last outer residual (no extra matvec).  Not taken by the server. */
     int32_t tree_refine; /* 0 or 1, default 0; 1 needs tree_theta > 0                       */

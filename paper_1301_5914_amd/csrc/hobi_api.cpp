@@ -293,12 +293,13 @@ constexpr int kMaxRefineSteps = 16;
 // tree_refine: the dense system A x = b by defect correction with the treecode operator T
 // (iterative refinement with an approximate operator): from x = 0, each outer step solves
 // T d = r by gmres_run, then x += d and r = b - A x with the dense matvec.  The first step
-// solves to 100 rtol: the dense residual after it is bounded by the treecode's own error
-// anyway, and GMRES converges about linearly, so solving further there only moves
-// iterations from the second step to the first.  Later steps solve to
-// max(rtol/2 ||b|| / ||r||, rtol/2), so that with T = A the next residual would be at most
-// rtol/2 ||b||.  Every tolerance is capped at 1/2.  Stops as the ABI states; x is left in
-// k.x and the last dense residual b - A x in k.ro.
+// solves to 100 rtol (at most 1/10): the dense residual after it is bounded by the
+// treecode's own error anyway, and GMRES converges about linearly, so solving further there
+// only moves iterations from the second step to the first.  Later steps solve to
+// max(rtol/2 ||b|| / ||r||, rtol/2), at most 1/2, so that with T = A the next residual would
+// be at most rtol/2 ||b||.  A step that shrinks ||r|| by less than a tenth ends the solve
+// (the treecode is too far from A).  Stops as the ABI states; x is left in k.x and the last
+// dense residual b - A x in k.ro.
 hobi_status gmres_refined(hobi_problem pb, bool scaled, int* iters, double* est, bool* converged, int* steps,
                           int* dense_mv) {
     const int n = 2 * pb->d.nv;
@@ -324,8 +325,8 @@ hobi_status gmres_refined(hobi_problem pb, bool scaled, int* iters, double* est,
         double rnorm = bnorm;
         int total = 0;
         while (true) {
-            const double tol = std::min(0.5, *steps == 0 ? std::max(100.0 * rtol, 0.5 * rtol)
-                                                         : std::max(0.5 * rtol * bnorm / rnorm, 0.5 * rtol));
+            const double tol = *steps == 0 ? std::min(0.1, std::max(100.0 * rtol, 0.5 * rtol))
+                                           : std::min(0.5, std::max(0.5 * rtol * bnorm / rnorm, 0.5 * rtol));
             int it = 0;
             double e_in = 0;
             bool c_in = false;
@@ -342,7 +343,7 @@ hobi_status gmres_refined(hobi_problem pb, bool scaled, int* iters, double* est,
             if (!std::isfinite(rn)) return fail(c, HOBI_E_NUMERIC, "refinement residual is not finite");
             *est = rn / bnorm;
             *iters = total;
-            if (*est <= rtol || total >= max_iter || *steps >= kMaxRefineSteps || rn > 0.5 * rnorm) break;
+            if (*est <= rtol || total >= max_iter || *steps >= kMaxRefineSteps || rn > 0.9 * rnorm) break;
             rnorm = rn;
         }
     }

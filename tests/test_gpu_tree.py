@@ -386,3 +386,18 @@ def test_tree_refine_stops_at_max_iter(ctx):
     assert s["converged"] == 0 and s["iterations"] <= 3 and s["refine_steps"] >= 1
     assert 0 < s["true_residual"] == s["est_residual"]
 
+
+@pytest.mark.parametrize("rtol", [1e-2, 1e-4])
+def test_tree_refine_loose_tolerances(ctx, rtol):
+    """Loose rtol: the first correction's tolerance is capped at 1/10, and the refined solve
+    still stops on the dense residual (checked with the oracle's dense operator)."""
+    p = inputs.kirkwood_offcenter(3)
+    r = hobi.Problem.from_inputs(ctx, p, tree_theta=0.9, tree_degree=3, tree_leaf=64, tree_batch=128,
+                                 tree_refine=1, rtol=rtol).solve()
+    s = r["stats"]
+    res = _oracle_dense_residual(p, r)
+    print(f"rtol {rtol:g}: outer {s['refine_steps']} treecode matvecs {s['iterations']} "
+          f"true residual {s['true_residual']:.3e} oracle residual {res:.3e}", flush=True)
+    assert s["converged"] == 1 and s["true_residual"] <= rtol
+    assert res <= 1.01 * rtol
+
