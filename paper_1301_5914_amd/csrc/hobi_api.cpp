@@ -288,8 +288,6 @@ hobi_status gmres_run(hobi_problem pb, const double* rhs, double rtol, int max_i
     return HOBI_OK;
 }
 
-constexpr int kMaxRefineSteps = 16;
-
 // tree_refine: the dense system A x = b by defect correction with the treecode operator T
 // (iterative refinement with an approximate operator): from x = 0, each outer step solves
 // T d = r by gmres_run, then x += d and r = b - A x with the dense matvec.  The first step

@@ -137,6 +137,7 @@ hipError_t launch_lobi_nodes(const DeviceProblem& p, hipStream_t s);
 GridPlan make_grid_plan(int n_pad, int nn, int tpl);
 constexpr int kTpl64 = 4;      // targets per lane of the FP64 pair kernel (dense sum, single and served)
 constexpr int kTreeTpl64 = 2;  // targets per lane of the treecode's FP64 tiles
+constexpr int kMaxRefineSteps = 16;   // outer steps of the tree_refine defect correction
 inline int tpl32_for(int nv_pad) { return nv_pad >= 16384 ? 8 : 4; }
 // Waves of the FP32 (mixed) or FP64 pair kernel with `tpl` targets per lane that device
 // `device` holds at once (occupancy of the kernel times the compute units); 0 on error.

@@ -49,6 +49,12 @@ struct Request {
     double* z = nullptr;    // D^-1 v_k, the matvec input under diag_scaling
     int m = 0, k = 0;
     double bnorm = 0, est = 1;
+    // tree_refine: the single-problem defect correction's state (outer iterate, dense
+    // residual, dense matvec output), the right-hand side's norm, the last outer residual's
+    // norm, the current correction's tolerance, treecode matvecs and outer steps so far
+    double *xo = nullptr, *ro = nullptr, *tmp = nullptr;
+    double bnorm_b = 0, rnorm = 0, tol_in = 0;
+    int total = 0, steps = 0;
     Clock::time_point t_admit;
     // outcome
     hobi_status status = HOBI_OK;
@@ -113,10 +119,11 @@ int64_t tree_bytes(const DeviceProblem& d) {
 }
 
 void free_request_device(Request& r) {
-    double* ptrs[] = {r.V, r.H, r.cs, r.sn, r.g, r.h1, r.h2, r.hn, r.yk, r.dpart, r.x, r.scal, r.z};
+    double* ptrs[] = {r.V, r.H, r.cs, r.sn, r.g, r.h1, r.h2, r.hn, r.yk, r.dpart, r.x, r.scal, r.z, r.xo, r.ro, r.tmp};
     for (double* p : ptrs)
         if (p) (void)hipFree(p);
     r.V = r.H = r.cs = r.sn = r.g = r.h1 = r.h2 = r.hn = r.yk = r.dpart = r.x = r.scal = r.z = nullptr;
+    r.xo = r.ro = r.tmp = nullptr;
     if (r.pb) hobi_problem_destroy(r.pb);
     r.pb = nullptr;
 }
@@ -225,6 +232,16 @@ hobi_status admit(hobi_server sv, Request& r) {
     }
     SA(launch_scale_copy(d.rhs, r.scal, r.V, n, s));
     SA(launch_init_g(r.scal, r.g, m, s));
+    if (r.prm.tree_refine) {
+        // the first correction solves T d = b from d = 0: the Krylov start above
+        SA(dalloc(&r.xo, n));
+        SA(dalloc(&r.ro, n));
+        SA(dalloc(&r.tmp, n));
+        SA(hipMemsetAsync(r.xo, 0, sizeof(double) * n, s));
+        r.bnorm_b = r.rnorm = r.bnorm;
+        r.tol_in = std::min(0.1, std::max(100.0 * r.prm.rtol, 0.5 * r.prm.rtol));
+        r.total = r.steps = 0;
+    }
 #undef SA
     r.k = 0;
     r.est = r.bnorm > 0 ? 1.0 : 0.0;
@@ -280,6 +297,83 @@ void finish(hobi_server sv, Request& r, bool converged) {
     r.stats.est_residual = r.est;
     r.stats.ms_solve = std::chrono::duration<double, std::milli>(Clock::now() - r.t_admit).count();
     free_request_device(r);
+}
+
+// tree_refine: the end of one correction (the request's inner GMRES met its tolerance or the
+// matvec budget).  The single-problem driver's outer step, with its kernels in its order:
+// d = D^-1 V y, x += d, r = b - A x by the dense matvec, ||r||.  Then either the request
+// finishes (as the driver stops) or the next correction starts from d = 0 on T d = r.
+// Returns true when the request is finished (finish() has run).
+bool refine_step(hobi_server sv, Request& r) {
+    TraceRange trace_range("server refine step");
+    hobi_ctx c = sv->ctx;
+    hipStream_t s = c->stream;
+    const DeviceProblem& d = r.pb->d;
+    const bool mixed = r.prm.precision == HOBI_MIXED;
+    const int n = 2 * r.nu;
+    r.total += r.k;
+    hipError_t e = hipSuccess;
+    if (r.k > 0) {
+        e = launch_trisolve(r.H, r.m + 1, r.k, r.g, r.yk, s);
+        if (e == hipSuccess)
+            e = r.prm.diag_scaling ? launch_multi_axpy_scaled(r.V, n, r.k, r.yk, r.x, n, d.dinv, s)
+                                   : launch_multi_axpy(r.V, n, r.k, r.yk, 1.0, r.x, n, s);
+    }
+    if (e == hipSuccess) e = launch_add(r.xo, r.x, r.xo, n, s);
+    if (e == hipSuccess) e = launch_gather(d, r.xo, mixed, s);
+    if (e == hipSuccess) e = launch_pair(d, mixed, s);
+    if (e == hipSuccess) e = launch_combine(d, r.xo, r.tmp, mixed, s);
+    if (e == hipSuccess) e = launch_sub(d.rhs, r.tmp, r.ro, n, s);
+    if (e == hipSuccess) e = launch_dots(r.ro, 0, 1, r.ro, n, r.dpart, s);
+    if (e == hipSuccess) e = launch_reduce(r.dpart, 1, r.scal, 1, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(sv->h_res, r.scal, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        fail_request(r, HOBI_E_HIP, hipGetErrorString(e));
+        free_request_device(r);
+        return true;
+    }
+    const double rn = sv->h_res[0];
+    r.steps += 1;
+    if (!std::isfinite(rn)) {
+        fail_request(r, HOBI_E_NUMERIC, "refinement residual is not finite");
+        free_request_device(r);
+        return true;
+    }
+    const double est = rn / r.bnorm_b;
+    if (est <= r.prm.rtol || r.total >= r.m || r.steps >= kMaxRefineSteps || rn > 0.9 * r.rnorm) {
+        const bool conv = est <= r.prm.rtol;
+        e = hipMemcpyAsync(r.x, r.xo, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) {
+            fail_request(r, HOBI_E_HIP, hipGetErrorString(e));
+            free_request_device(r);
+            return true;
+        }
+        r.k = 0;                          // the solution is in x already
+        r.est = est;
+        finish(sv, r, conv);
+        r.stats.iterations = r.total;
+        r.stats.est_residual = r.stats.true_residual = est;
+        r.stats.refine_steps = r.steps;
+        r.stats.dense_matvecs = r.steps;
+        if (!conv && r.status == HOBI_E_NOCONV)
+            r.message = "defect correction stopped after " + std::to_string(r.steps) + " outer steps";
+        return true;
+    }
+    // the next correction: T d = r from d = 0, to max(rtol/2 ||b|| / ||r||, rtol/2), at most 1/2
+    r.rnorm = rn;
+    r.bnorm = rn;
+    r.tol_in = std::min(0.5, std::max(0.5 * r.prm.rtol * r.bnorm_b / rn, 0.5 * r.prm.rtol));
+    r.k = 0;
+    r.est = 1.0;
+    if ((e = hipMemsetAsync(r.x, 0, sizeof(double) * n, s)) != hipSuccess ||
+        (e = launch_scale_copy(r.ro, r.scal, r.V, n, s)) != hipSuccess ||
+        (e = launch_init_g(r.scal, r.g, r.m, s)) != hipSuccess) {
+        fail_request(r, HOBI_E_HIP, hipGetErrorString(e));
+        free_request_device(r);
+        return true;
+    }
+    return false;
 }
 
 hipError_t ensure_capacity(hobi_server sv, size_t ndesc, size_t nitems) {
@@ -539,7 +633,10 @@ void worker_main(hobi_server sv) {
                     fail_request(*r, HOBI_E_NUMERIC, "GMRES residual is not finite");
                     free_request_device(*r);
                     finished.push_back(std::move(r));
-                } else if (res <= r->prm.rtol || r->k >= r->m) {
+                } else if (r->prm.tree_refine && (res <= r->tol_in || r->total + r->k >= r->m)) {
+                    if (refine_step(sv, *r)) finished.push_back(std::move(r));
+                    else still.push_back(std::move(r));
+                } else if (!r->prm.tree_refine && (res <= r->prm.rtol || r->k >= r->m)) {
                     finish(sv, *r, res <= r->prm.rtol);
                     finished.push_back(std::move(r));
                 } else {
@@ -691,14 +788,15 @@ hobi_status hobi_server_submit(hobi_server sv, int32_t nv, const double* xyz, co
     r->q.assign(q, q + nc);
     hobi_params_default(&r->prm);
     if (params) r->prm = *params;
-    if (r->prm.tree_refine != 0) {
+    if (r->prm.tree_refine != 0 && (r->prm.tree_refine != 1 || !(r->prm.tree_theta > 0))) {
         std::lock_guard<std::mutex> lk(sv->mu);
-        sv->last_error = "tree_refine is a hobi_solve option: the server solves each request's own operator";
+        sv->last_error = "tree_refine must be 0, or 1 with tree_theta > 0";
         return HOBI_E_ARG;
     }
     r->prm.restart = r->prm.max_iter;
     r->nu = r->prm.method == HOBI_LOWER_ORDER ? nf : nv;
     r->footprint = footprint_bytes(sv->device, nv, nf, nc, std::max(1, r->prm.max_iter), r->prm.method);
+    if (r->prm.tree_refine) r->footprint += 3LL * 2 * r->nu * (int64_t)sizeof(double);   // xo, ro, tmp
     std::lock_guard<std::mutex> lk(sv->mu);
     if (r->footprint > sv->budget) {
         sv->last_error = "request footprint exceeds the server budget";

@@ -107,8 +107,8 @@ def test_treecode_requests_equal_the_single_problem_path(ctx):
         alone = _wait(sv, [sv.submit(cases[0][0], max_iter=200, **cases[0][1])])
         tickets = [sv.submit(p, max_iter=200, **kw) for p, kw in cases]
         bad = sv.submit(cases[0][0], max_iter=200, tree_theta=0.5, tree_degree=9)
-        with pytest.raises(hobi.HobiError) as e:   # the defect correction is hobi_solve's only
-            sv.submit(cases[0][0], max_iter=200, tree_theta=0.5, tree_refine=1)
+        with pytest.raises(hobi.HobiError) as e:   # the defect correction needs a treecode
+            sv.submit(cases[0][0], max_iter=200, tree_refine=1)
         assert e.value.status == 1
         out = _wait(sv, tickets + [bad])
         for r, ref in zip([next(iter(alone.values()))] + [out[t] for t in tickets], [refs[0]] + refs):
@@ -239,3 +239,42 @@ def test_admission_respects_the_budget_with_treecode_requests(ctx):
         assert r["status"] == "HOBI_E_OOM"
         assert small.stats()["peak_bytes"] <= dense
     small.close()
+
+
+def test_served_defect_correction_equals_hobi_solve(ctx):
+    """tree_refine requests: each request's outer steps run between its ticks with the
+    single-problem driver's arithmetic, so a served result is hobi_solve's bit for bit (the
+    solution, the energy, the treecode matvecs, the outer steps and the dense residual),
+    alone and in a mix with dense and plain treecode requests, with and without graphs."""
+    tree = dict(tree_theta=0.9, tree_degree=3, tree_leaf=64, tree_batch=128)
+    cases = [(inputs.kirkwood_offcenter(3), dict(precision=hobi.HOBI_MIXED, tree_refine=1, **tree)),
+             (inputs.kirkwood_offcenter(3, kappa=0.0, eps1=2.0),
+              dict(precision=hobi.HOBI_FP64, tree_refine=1, rtol=1e-9, **tree)),
+             (inputs.kirkwood_offcenter(3), dict(precision=hobi.HOBI_MIXED, method=hobi.HOBI_LOWER_ORDER,
+                                                 tree_refine=1, **tree)),
+             (inputs.kirkwood_offcenter(2), dict(precision=hobi.HOBI_MIXED)),
+             (inputs.kirkwood_offcenter(3), dict(precision=hobi.HOBI_MIXED, **tree))]
+    refs = [hobi.Problem.from_inputs(ctx, p, max_iter=200, restart=200, **kw).solve() for p, kw in cases]
+    for ref, (_, kw) in zip(refs, cases):
+        steps = ref["stats"]["refine_steps"]
+        print(f"single path: refine {kw.get('tree_refine', 0)} outer {steps} iterations {ref['stats']['iterations']} "
+              f"residual {ref['stats']['true_residual']:.3e}", flush=True)
+        assert steps >= 2 if kw.get("tree_refine") else steps == 0
+    for use_graph in (True, False):
+        sv = hobi.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=8, use_graph=use_graph)
+        alone = _wait(sv, [sv.submit(cases[0][0], max_iter=200, **cases[0][1])])
+        tickets = [sv.submit(p, max_iter=200, **kw) for p, kw in cases]
+        out = _wait(sv, tickets)
+        for r, ref in zip([next(iter(alone.values()))] + [out[t] for t in tickets], [refs[0]] + refs):
+            assert r["status"] == "HOBI_OK"
+            for key in ("iterations", "refine_steps", "dense_matvecs"):
+                assert r["stats"][key] == ref["stats"][key], key
+            np.testing.assert_array_equal(r["phi"], ref["phi"])
+            np.testing.assert_array_equal(r["dphi"], ref["dphi"])
+            assert r["energy"] == ref["energy"]
+            if ref["stats"]["refine_steps"]:
+                assert r["stats"]["true_residual"] == ref["stats"]["true_residual"]
+        st = sv.stats()
+        assert st["bytes_in_use"] == 0 and st["failed"] == 0
+        sv.close()
+
