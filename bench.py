@@ -417,10 +417,11 @@ def _make_molecule_job(indexed_job):
 
 
 def serve_bench(pool_mols, n_requests, seed, rate_factors, budget_bytes, max_slots, n_check, tree_theta=0.0,
-                fp64_all=False):
+                fp64_all=False, tree_degree=5, tree_leaf=256, tree_refine=0):
     """Poisson request streams through the continuous-batching server (mixed precision; with
-    tree_theta > 0 every request takes the treecode with the default degree, leaf and
-    batch): one stream per arrival-rate factor (the same requests, arrivals at that factor
+    tree_theta > 0 every request takes the treecode of that theta, degree and leaf, and with
+    tree_refine solves the dense system through it by defect correction): one stream per
+    arrival-rate factor (the same requests, arrivals at that factor
     times the saturated rate of a 16-request burst).  The first factor's results are checked
     against the FP64 oracle (n_check requests) and, with fp64_all, every request's energy
     against a GPU FP64 solve of its (molecule, eps1, kappa)."""
@@ -439,7 +440,8 @@ def serve_bench(pool_mols, n_requests, seed, rate_factors, budget_bytes, max_slo
 
     def submit(sv, req):
         m, e1, kap = req
-        return sv.submit(m, precision=hobi.HOBI_MIXED, eps1=e1, kappa=kap, max_iter=400, tree_theta=tree_theta)
+        return sv.submit(m, precision=hobi.HOBI_MIXED, eps1=e1, kappa=kap, max_iter=400, tree_theta=tree_theta,
+                         tree_degree=tree_degree, tree_leaf=tree_leaf, tree_refine=tree_refine)
 
     # saturated throughput: a burst submitted at once
     sv = hobi.Server(ctx, hbm_budget_bytes=budget_bytes, max_slots=max_slots)
@@ -554,7 +556,9 @@ def serve_bench(pool_mols, n_requests, seed, rate_factors, budget_bytes, max_slo
                         "of the request's (molecule, eps1, kappa)"}
     sizes = [m.nf for m in pool_mols]
     return {
-        "requests": n_requests, "tree_theta": tree_theta, "converged": ok,
+        "requests": n_requests, "tree_theta": tree_theta,
+        "tree": ({"degree": tree_degree, "leaf": tree_leaf, "refine": tree_refine} if tree_theta > 0 else None),
+        "converged": ok,
         "arrival_rate_per_s": first["arrival_rate_per_s"],
         "saturated_rate_per_s": sat, "rate_factor": first["rate_factor"],
         "throughput_requests_per_s": first["throughput_requests_per_s"],
@@ -616,6 +620,10 @@ def main():
                     help=".npz to load the molecule pool from (written there if absent or different)")
     ap.add_argument("--serve-tree-theta", type=float, default=0.0,
                     help="serve the stream with the treecode at this opening parameter (0: dense)")
+    ap.add_argument("--serve-tree-degree", type=int, default=5)
+    ap.add_argument("--serve-tree-leaf", type=int, default=256)
+    ap.add_argument("--serve-tree-refine", action="store_true",
+                    help="served treecode requests solve the dense system by defect correction (tree_refine)")
     ap.add_argument("--field-map", type=int, default=64,
                     help="potential map of grid^3 points after the timed steps (hobi_field); 0 = off")
     ap.add_argument("--tree-theta", type=float, default=0.7,
@@ -780,7 +788,9 @@ def main():
         out["serving"] = serve_bench(pool_mols, args.serve_requests, 5,
                                      [float(f) for f in args.serve_rate.split(",")],
                                      int(args.serve_budget_gb * (1 << 30)), args.serve_slots, args.serve_checks,
-                                     tree_theta=args.serve_tree_theta, fp64_all=args.serve_fp64_all)
+                                     tree_theta=args.serve_tree_theta, fp64_all=args.serve_fp64_all,
+                                     tree_degree=args.serve_tree_degree, tree_leaf=args.serve_tree_leaf,
+                                     tree_refine=1 if args.serve_tree_refine else 0)
         full = (args.serve_requests >= 512 and args.serve_pool >= 16 and args.serve_max_atoms >= 3000)
         out["serving"]["reduced"] = not full
         if not full:
