@@ -465,7 +465,24 @@ __global__ __launch_bounds__(kBlock) void tree_combine_kernel(
     const int rb = slot_row[s], re = slot_row[s + 1];
     double r1 = 0.0, r2 = 0.0;
     if (i < nv) {
-        for (int r = rb + way; r < re; r += 4) {
+        // rows rb + way, rb + way + 4, ... summed in that order; the loads of kAhead rows are
+        // issued before their sums, so that they are in flight together
+        constexpr int kAhead = 8;
+        int r = rb + way;
+        for (; r + 4 * (kAhead - 1) < re; r += 4 * kAhead) {
+            double a[kAhead], b[kAhead];
+#pragma unroll
+            for (int q = 0; q < kAhead; ++q) {
+                a[q] = partial[(size_t)(2 * (r + 4 * q)) * slot + o];
+                b[q] = partial[(size_t)(2 * (r + 4 * q) + 1) * slot + o];
+            }
+#pragma unroll
+            for (int q = 0; q < kAhead; ++q) {
+                r1 += a[q];
+                r2 += b[q];
+            }
+        }
+        for (; r < re; r += 4) {
             r1 += partial[(size_t)(2 * r) * slot + o];
             r2 += partial[(size_t)(2 * r + 1) * slot + o];
         }
