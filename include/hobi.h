@@ -115,7 +115,9 @@ typedef struct hobi_params {
      * outer steps, or when an outer step shrinks ||r|| by less than a tenth
      * (HOBI_E_NOCONV for the last three).  hobi_stats.iterations counts the treecode
      * matvecs, refine_steps the outer steps and dense_matvecs the dense ones; the true
-     * residual is the last outer residual (no extra matvec).  The server takes it too:
+     * residual is the last outer residual (no extra matvec).  hobi_matvec and hobi_field
+     * keep the treecode (a dense matvec of such a problem is hobi_solve's business only).
+     * The server takes it too:
      * each request's outer steps run between its ticks, with the same arithmetic, so a
      * served result equals hobi_solve's. */
     int32_t tree_refine; /* 0 or 1, default 0; 1 needs tree_theta > 0                       */
