@@ -116,8 +116,7 @@ typedef struct hobi_params {
      * (HOBI_E_NOCONV for the last three).  hobi_stats.iterations counts the treecode
      * matvecs, refine_steps the outer steps and dense_matvecs the dense ones; the true
      * residual is the last outer residual (no extra matvec).  hobi_matvec and hobi_field
-     * keep the treecode (a dense matvec of such a problem is hobi_solve's business only).
-     * The server takes it too:
+     * of such a problem still use the treecode.  The server takes it too:
      * each request's outer steps run between its ticks, with the same arithmetic, so a
      * served result equals hobi_solve's. */
     int32_t tree_refine; /* 0 or 1, default 0; 1 needs tree_theta > 0                       */
