@@ -752,6 +752,12 @@ def main():
                                  grid=0 if lower else args.field_map, lower=lower,
                                  refine=(args.refine_theta, args.refine_degree, args.refine_leaf, args.refine_batch))
         progress("treecode leg done")
+        ref = out["tree"].get("refined") or {}
+        if "solve_ms" in ref:
+            # the time to the dense system's solution at rtol: GMRES on it, and defect correction
+            out["time_to_dense_solution_ms"] = {"gmres": out["solve_ms"], "defect_correction": ref["solve_ms"],
+                                                "defect_correction_treecode": [ref["theta"], ref["degree"],
+                                                                               ref["leaf"], ref["batch"]]}
     if not args.no_compare:
         # the other precision on the same problem (outside the timed region)
         pb.set_precision(hobi.HOBI_FP64 if mixed else hobi.HOBI_MIXED)
