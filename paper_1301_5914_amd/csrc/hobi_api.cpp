@@ -803,9 +803,12 @@ hobi_status problem_create_limited(hobi_ctx ctx, int32_t nv, const double* xyz, 
         if (!make_pair_plan(d.nv, d.nn, kTpl64, r64, 1, &d.plan64, &ptab) ||
             !make_pair_plan(d.nv, d.nn, tpl32, r32, kPairWaves, &d.plan32, &ptab))
             return cleanup_fail(fail(ctx, HOBI_E_ARG, "problem too large: %d sites x %d nodes", d.nv, d.nn));
-        d.partial_elems = std::max({(size_t)2 * d.plan64.slot * d.plan64.slots * d.plan64.rows,
-                                    (size_t)2 * d.plan32.slot * d.plan32.slots * d.plan32.rows,
-                                    (size_t)d.nc_pad * d.plan_pts.chunks});
+        // the partial rows of the current precision's plan (hobi_problem_set_precision grows
+        // the buffer for the other one when it needs more), and the point sums of the energy
+        const size_t pts = (size_t)d.nc_pad * d.plan_pts.chunks;
+        d.partial_need[0] = std::max((size_t)2 * d.plan64.slot * d.plan64.slots * d.plan64.rows, pts);
+        d.partial_need[1] = std::max((size_t)2 * d.plan32.slot * d.plan32.slots * d.plan32.rows, pts);
+        d.partial_elems = d.partial_need[prm.precision == HOBI_MIXED ? 1 : 0];
     }
 
     hipStream_t s = ctx->stream;
@@ -926,8 +929,25 @@ void hobi_problem_destroy(hobi_problem pb) {
 
 hobi_status hobi_problem_set_precision(hobi_problem pb, int32_t precision) {
     if (!pb) return HOBI_E_ARG;
+    hobi_ctx c = pb->ctx;
     if (precision != HOBI_FP64 && precision != HOBI_MIXED)
-        return fail(pb->ctx, HOBI_E_ARG, "precision must be HOBI_FP64 or HOBI_MIXED");
+        return fail(c, HOBI_E_ARG, "precision must be HOBI_FP64 or HOBI_MIXED");
+    DeviceProblem& d = pb->d;
+    const size_t need = d.partial_need[precision == HOBI_MIXED ? 1 : 0];
+    if (need > d.partial_elems) {
+        // the other plan's partial rows do not fit: a larger buffer, once the work queued on
+        // the old one is done
+        HIPCHK(c, hipSetDevice(c->device));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        double* grown = nullptr;
+        const hipError_t e = dalloc(&grown, need);
+        if (e != hipSuccess)
+            return fail(c, e == hipErrorOutOfMemory ? HOBI_E_OOM : HOBI_E_HIP, "partial-row buffer: %s",
+                        hipGetErrorString(e));
+        (void)hipFree(d.partial);
+        d.partial = grown;
+        d.partial_elems = need;
+    }
     pb->prm.precision = precision;
     return HOBI_OK;
 }

@@ -121,7 +121,8 @@ struct DeviceProblem {
     PairPlan plan64{}, plan32{};
     GridPlan plan_pts{};
     int* plan_tab = nullptr;                // device group starts of plan64, then of plan32
-    size_t partial_elems = 0;
+    size_t partial_elems = 0;               // allocated: what the current precision's plan needs
+    size_t partial_need[2] = {0, 0};        // what the FP64 [0] and FP32 [1] plans need (with the point sums)
     TreePlan tree{};
 };
 

@@ -73,21 +73,22 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 // Device bytes of one admitted request (the allocations of hobi_problem_create plus the
 // server's Krylov basis), from its sizes alone.
-int64_t footprint_bytes(int device, int nv, int nf, int nc, int m, int method) {
+int64_t footprint_bytes(int device, int nv, int nf, int nc, int m, int method, bool mixed) {
     // the lower-order method has one site and one node per triangle (an upper bound below)
     if (method == HOBI_LOWER_ORDER) nv = std::max(nv, nf);
     const int64_t nv_pad = round_up(nv, 2048), nc_pad = round_up(nc, 256), nn = 4LL * nf;
     const GridPlan pp = make_grid_plan((int)nc_pad, (int)nn, 1);
-    // pair plans: one partial row of 2 * slot doubles per worker, and the group starts
+    // pair plans: the group starts of both, and one partial row of 2 * slot doubles per
+    // worker of the request's own precision (a served problem keeps its precision)
     int64_t pair_rows_elems = 0, tab_ints = 0;
-    for (int mixed = 0; mixed < 2; ++mixed) {
-        const int tpl = mixed ? tpl32_for((int)nv_pad) : kTpl64;
+    for (int mx = 0; mx < 2; ++mx) {
+        const int tpl = mx ? tpl32_for((int)nv_pad) : kTpl64;
         PairPlan pl{};
         std::vector<int> gs;
-        if (!make_pair_plan(nv, (int)nn, tpl, std::max(1, pair_resident_waves(device, mixed, tpl)),
-                            mixed ? kPairWaves : 1, &pl, &gs))
+        if (!make_pair_plan(nv, (int)nn, tpl, std::max(1, pair_resident_waves(device, mx != 0, tpl)),
+                            mx ? kPairWaves : 1, &pl, &gs))
             return INT64_MAX;
-        pair_rows_elems = std::max<int64_t>(pair_rows_elems, 2LL * pl.slot * pl.slots * pl.rows);
+        if (mx == (mixed ? 1 : 0)) pair_rows_elems = 2LL * pl.slot * pl.slots * pl.rows;
         tab_ints += (int64_t)gs.size();
     }
     int64_t b = 0;
@@ -795,7 +796,8 @@ hobi_status hobi_server_submit(hobi_server sv, int32_t nv, const double* xyz, co
     }
     r->prm.restart = r->prm.max_iter;
     r->nu = r->prm.method == HOBI_LOWER_ORDER ? nf : nv;
-    r->footprint = footprint_bytes(sv->device, nv, nf, nc, std::max(1, r->prm.max_iter), r->prm.method);
+    r->footprint = footprint_bytes(sv->device, nv, nf, nc, std::max(1, r->prm.max_iter), r->prm.method,
+                                   r->prm.precision == HOBI_MIXED);
     if (r->prm.tree_refine) r->footprint += 3LL * 2 * r->nu * (int64_t)sizeof(double);   // xo, ro, tmp
     std::lock_guard<std::mutex> lk(sv->mu);
     if (r->footprint > sv->budget) {
