@@ -184,7 +184,10 @@ hobi_status hobi_problem_create(hobi_ctx ctx, int32_t nv, const double* xyz,
                                 int32_t nc, const double* qpos, const double* q,
                                 const hobi_params* params, hobi_problem* out);
 void hobi_problem_destroy(hobi_problem pb);
-/* Switches the pair-kernel arithmetic (HOBI_FP64 / HOBI_MIXED) of an existing problem. */
+/* Switches the pair-kernel arithmetic (HOBI_FP64 / HOBI_MIXED) of an existing problem.  The
+ * problem holds the partial-sum rows of its current precision's pair plan; a switch to a
+ * plan that needs more waits for the problem's queued work and reallocates them (HOBI_E_OOM
+ * if that fails; the problem then keeps its precision).  HOBI_E_ARG for another value. */
 hobi_status hobi_problem_set_precision(hobi_problem pb, int32_t precision);
 /* Replaces eps1, eps2 and kappa and re-runs the whole device part of the setup (curved
  * elements, regular nodes, singular coefficients, source terms) on the resident surface
